@@ -1,0 +1,884 @@
+/*
+ * mbd_oracle.c -- plain FP64 CPU oracle for the MBD energy and gradients.
+ *
+ * TEST INFRASTRUCTURE ONLY: called by tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py.  No product code may link or call it, and it
+ * shares no code with the HIP path.
+ *
+ * Written from the paper (Hermann et al., arXiv:2308.03140):
+ *   Sec. 2.1  eq:mbd-hamiltonian, eq:osc-param, eq:dipole, eq:q-matrix,
+ *             eq:diagonalization, eq:mbd-energy
+ *   Sec. 2.2  eq:brillouin-int, the Bloch sum of T, eq:ewald, eq:terfc
+ *   Sec. 2.4  eq:mbd-gradient
+ *   Sec. 2.5  eq:log-formula (frequency route), eq:dyn-pol
+ *   Sec. 2.7  eq:fermi-damping, eq:mbd-lr-dipole (T^lr = g T, a = 6)
+ *   Sec. 3.3  frequency grid map and Ewald defaults
+ *
+ * Readings where the paper is ambiguous (all documented in the design doc):
+ *   - T_ab = (delta_ab r^2 - 3 r_a r_b)/r^5, the explicit form of eq:dipole.
+ *   - eq:terfc: T^erfc_ab = (delta_ab r^2 B - r_a r_b C)/r^5 (the printed 3 in
+ *     front of r_a r_b C is already inside C; without it T^erfc -> T as
+ *     gamma -> 0).
+ *   - reciprocal phase exp(+i G.(R_j - R_i)) with k = G + q, consistent with
+ *     the real-space phase exp(-i q.R_nij), R_nij = R_j + R_n - R_i.
+ *   - the damped periodic tensor is the exact lattice sum of g T: the Ewald
+ *     split of the bare T plus the real-space correction -(1-g) T, the latter
+ *     summed over every image with (1-g) > 1e-18.
+ *   - surface term and k = 0 omitted.
+ *   - gradients as (1/4) Re Tr(Q^{-1/2} dQ/dX) - (3/2) d(sum omega)/dX.
+ *
+ * Eigenvalues come from the oracle's own cyclic Jacobi method (threshold
+ * strategy, round-robin ordering so that disjoint rotations of one round can
+ * be applied in parallel with OpenMP).  Hermitian matrices are handled by the
+ * real embedding [[A, -B], [B, A]].
+ */
+#include "mbd_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846264338327950288
+#define DAMP_TAIL 1e-18
+
+/* ------------------------------------------------------------------------- */
+/* Pair tensors                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* eq:dipole, explicit form; dT[c*9 + a*3 + b] = d T_ab / d r_c */
+void orc_dipole(const double *r, double *T, double *dT)
+{
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double d = sqrt(r2);
+    double r3 = r2 * d, r5 = r3 * r2, r7 = r5 * r2;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+            T[a * 3 + b] = (a == b ? 1.0 / r3 : 0.0) - 3.0 * r[a] * r[b] / r5;
+    if (!dT) return;
+    for (int c = 0; c < 3; c++)
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double v = 15.0 * r[a] * r[b] * r[c] / r7;
+                if (a == b) v -= 3.0 * r[c] / r5;
+                if (a == c) v -= 3.0 * r[b] / r5;
+                if (b == c) v -= 3.0 * r[a] / r5;
+                dT[c * 9 + a * 3 + b] = v;
+            }
+}
+
+/* eq:terfc (coefficient reading above). */
+void orc_dipole_erfc(const double *r, double gamma, double *T, double *dT)
+{
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double d = sqrt(r2);
+    double x = gamma * d;
+    double ex = exp(-x * x);
+    double B = erfc(x) + 2.0 * x / sqrt(PI) * ex;
+    double C = 3.0 * erfc(x) + 2.0 * x / sqrt(PI) * (3.0 + 2.0 * x * x) * ex;
+    double r3 = r2 * d, r5 = r3 * r2;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+            T[a * 3 + b] = (a == b ? B / r3 : 0.0) - C * r[a] * r[b] / r5;
+    if (!dT) return;
+    /* dB/dd = -(4 gamma^3 d^2/sqrt(pi)) e^{-x^2};  dC/dd = -(8 gamma x^4/sqrt(pi)) e^{-x^2} */
+    double dB = -4.0 * gamma * gamma * gamma * r2 / sqrt(PI) * ex;
+    double dC = -8.0 * gamma * x * x * x * x / sqrt(PI) * ex;
+    double db = dB / r3 - 3.0 * B / (r3 * d);     /* d(B/d^3)/dd */
+    double dc = dC / r5 - 5.0 * C / (r5 * d);     /* d(C/d^5)/dd */
+    for (int c = 0; c < 3; c++)
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double v = -dc * (r[c] / d) * r[a] * r[b];
+                if (a == b) v += db * r[c] / d;
+                if (a == c) v -= C * r[b] / r5;
+                if (b == c) v -= C * r[a] / r5;
+                dT[c * 9 + a * 3 + b] = v;
+            }
+}
+
+/* eq:fermi-damping with s_R = beta (MBD: a = 6).  Returns g, 1-g (computed
+ * without cancellation), dg/dd and dg/dR0 where R0 = beta (Rv_i + Rv_j). */
+static void fermi(double d, double R0, double a, double *g, double *omg,
+                  double *dg_dd, double *dg_dR0)
+{
+    if (R0 <= 0.0) { *g = 1.0; *omg = 0.0; *dg_dd = 0.0; *dg_dR0 = 0.0; return; }
+    double x = a * (d / R0 - 1.0);
+    if (x >= 0.0) { double e = exp(-x); *g = 1.0 / (1.0 + e); *omg = e / (1.0 + e); }
+    else          { double e = exp(x);  *g = e / (1.0 + e);   *omg = 1.0 / (1.0 + e); }
+    double gg = (*g) * (*omg);
+    *dg_dd = a / R0 * gg;
+    *dg_dR0 = -a * d / (R0 * R0) * gg;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Finite assembly, eq:q-matrix                                               */
+/* ------------------------------------------------------------------------- */
+
+void orc_assemble_finite(int N, const double *R, const double *alpha0,
+                         const double *omega, const double *rvdw,
+                         double beta, double a, double *Q)
+{
+    int n = 3 * N;
+    memset(Q, 0, sizeof(double) * (size_t)n * n);
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < N; i++) {
+        double ci = omega[i] * sqrt(alpha0[i]);
+        for (int j = 0; j < N; j++) {
+            if (i == j) {
+                for (int c = 0; c < 3; c++)
+                    Q[(size_t)(3 * i + c) * n + 3 * i + c] = omega[i] * omega[i];
+                continue;
+            }
+            double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1],
+                           R[3 * j + 2] - R[3 * i + 2]};
+            double d = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+            double T[9], g, omg, gd, gR;
+            orc_dipole(r, T, NULL);
+            fermi(d, beta * (rvdw[i] + rvdw[j]), a, &g, &omg, &gd, &gR);
+            double cc = ci * omega[j] * sqrt(alpha0[j]) * g;
+            for (int p = 0; p < 3; p++)
+                for (int s = 0; s < 3; s++)
+                    Q[(size_t)(3 * i + p) * n + 3 * j + s] = cc * T[p * 3 + s];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cyclic Jacobi (round-robin ordering)                                       */
+/* ------------------------------------------------------------------------- */
+
+int orc_jacobi(int n, double *A, double *w, double *V)
+{
+    if (n <= 0) return 0;
+    if (V) {
+        memset(V, 0, sizeof(double) * (size_t)n * n);
+        for (int i = 0; i < n; i++) V[(size_t)i * n + i] = 1.0;
+    }
+    if (n == 1) { w[0] = A[0]; return 0; }
+    int m = n + (n & 1);          /* players, one dummy if n is odd */
+    int np = m / 2;
+    int *pp = (int *)malloc(sizeof(int) * np), *qq = (int *)malloc(sizeof(int) * np);
+    double *cs = (double *)malloc(sizeof(double) * np), *sn = (double *)malloc(sizeof(double) * np);
+    int *slot = (int *)malloc(sizeof(int) * m);
+    int sweeps = -1;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        int rotated = 0;
+        for (int rnd = 0; rnd < m - 1; rnd++) {
+            slot[0] = 0;
+            for (int s = 1; s < m; s++) slot[s] = 1 + (s - 1 + rnd) % (m - 1);
+            int nact = 0;
+            for (int k = 0; k < np; k++) {
+                int p = slot[k], q = slot[m - 1 - k];
+                if (p >= n || q >= n) continue;
+                if (p > q) { int t = p; p = q; q = t; }
+                double apq = A[(size_t)p * n + q];
+                double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                if (fabs(apq) <= 1e-15 * sqrt(fabs(app * aqq)) || fabs(apq) < 1e-300)
+                    continue;
+                double theta = (aqq - app) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0);
+                pp[nact] = p; qq[nact] = q; cs[nact] = c; sn[nact] = t * c; nact++;
+            }
+            if (!nact) continue;
+            rotated = 1;
+            /* A <- A J (columns), V <- V J, row by row */
+#pragma omp parallel for schedule(static)
+            for (int r = 0; r < n; r++) {
+                double *ar = A + (size_t)r * n;
+                double *vr = V ? V + (size_t)r * n : NULL;
+                for (int k = 0; k < nact; k++) {
+                    int p = pp[k], q = qq[k];
+                    double c = cs[k], s = sn[k];
+                    double x = ar[p], y = ar[q];
+                    ar[p] = c * x - s * y; ar[q] = s * x + c * y;
+                    if (vr) { x = vr[p]; y = vr[q]; vr[p] = c * x - s * y; vr[q] = s * x + c * y; }
+                }
+            }
+            /* A <- J^T A (rows), one pair per iteration */
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nact; k++) {
+                int p = pp[k], q = qq[k];
+                double c = cs[k], s = sn[k];
+                double *ap = A + (size_t)p * n, *aq = A + (size_t)q * n;
+                for (int col = 0; col < n; col++) {
+                    double x = ap[col], y = aq[col];
+                    ap[col] = c * x - s * y; aq[col] = s * x + c * y;
+                }
+                ap[q] = 0.0; aq[p] = 0.0;
+            }
+        }
+        if (!rotated) { sweeps = sweep; break; }
+    }
+    for (int i = 0; i < n; i++) w[i] = A[(size_t)i * n + i];
+    /* sort ascending (selection sort keeps it plain), permuting V columns */
+    for (int i = 0; i < n - 1; i++) {
+        int k = i;
+        for (int j = i + 1; j < n; j++) if (w[j] < w[k]) k = j;
+        if (k != i) {
+            double t = w[i]; w[i] = w[k]; w[k] = t;
+            if (V) for (int r = 0; r < n; r++) {
+                double *vr = V + (size_t)r * n;
+                t = vr[i]; vr[i] = vr[k]; vr[k] = t;
+            }
+        }
+    }
+    free(pp); free(qq); free(cs); free(sn); free(slot);
+    return sweeps;
+}
+
+int orc_jacobi_hermitian(int n, const double *Are, const double *Aim,
+                         double *w, double *V)
+{
+    int m = 2 * n;
+    double *E = (double *)malloc(sizeof(double) * (size_t)m * m);
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            double re = Are[(size_t)i * n + j], im = Aim[(size_t)i * n + j];
+            E[(size_t)i * m + j] = re;
+            E[(size_t)(i + n) * m + j + n] = re;
+            E[(size_t)i * m + j + n] = -im;
+            E[(size_t)(i + n) * m + j] = im;
+        }
+    int s = orc_jacobi(m, E, w, V);
+    free(E);
+    return s;
+}
+
+/* M = V diag(lam^{-1/2}) V^T, plain triple loop */
+static void inv_sqrt_from_eig(int n, const double *V, const double *lam, double *M)
+{
+    double *s = (double *)malloc(sizeof(double) * n);
+    for (int k = 0; k < n; k++) s[k] = 1.0 / sqrt(lam[k]);
+#pragma omp parallel for schedule(dynamic)
+    for (int p = 0; p < n; p++)
+        for (int q = 0; q < n; q++) {
+            double acc = 0.0;
+            const double *vp = V + (size_t)p * n, *vq = V + (size_t)q * n;
+            for (int k = 0; k < n; k++) acc += vp[k] * s[k] * vq[k];
+            M[(size_t)p * n + q] = acc;
+        }
+    free(s);
+}
+
+/* Neumaier-compensated sum of sqrt(lam) */
+static double sum_sqrt(int n, const double *lam)
+{
+    double s = 0.0, c = 0.0;
+    for (int k = 0; k < n; k++) {
+        double x = sqrt(lam[k]);
+        double t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Finite energy and gradients                                                */
+/* ------------------------------------------------------------------------- */
+
+int orc_mbd_finite(int N, const double *R, const double *alpha0,
+                   const double *omega, const double *rvdw, double beta,
+                   double a, double *energy, double *grad_R,
+                   double *grad_alpha0, double *grad_omega, double *grad_rvdw,
+                   double *eigs)
+{
+    if (N < 1) return 1;
+    int n = 3 * N;
+    int want_grad = grad_R || grad_alpha0 || grad_omega || grad_rvdw;
+    double *Q = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *lam = (double *)malloc(sizeof(double) * n);
+    double *V = want_grad ? (double *)malloc(sizeof(double) * (size_t)n * n) : NULL;
+    orc_assemble_finite(N, R, alpha0, omega, rvdw, beta, a, Q);
+    int sw = orc_jacobi(n, Q, lam, V);
+    if (eigs) memcpy(eigs, lam, sizeof(double) * n);
+    int rc = 0;
+    if (sw < 0) rc = 3;
+    else if (lam[0] <= 0.0) rc = 2;
+    if (rc) {
+        if (energy) *energy = NAN;
+        free(Q); free(lam); free(V);
+        return rc;
+    }
+    double som = 0.0;
+    for (int i = 0; i < N; i++) som += omega[i];
+    if (energy) *energy = 0.5 * sum_sqrt(n, lam) - 1.5 * som;
+    if (want_grad) {
+        double *M = Q; /* reuse storage */
+        inv_sqrt_from_eig(n, V, lam, M);
+        double *gR = (double *)calloc((size_t)3 * N, sizeof(double));
+        double *S = (double *)calloc(N, sizeof(double));
+        double *U = (double *)calloc(N, sizeof(double));
+        for (int i = 0; i < N; i++) {
+            double ci = omega[i] * sqrt(alpha0[i]);
+            for (int j = i + 1; j < N; j++) {
+                double cj = omega[j] * sqrt(alpha0[j]);
+                double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1],
+                               R[3 * j + 2] - R[3 * i + 2]};
+                double d = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                double T[9], dT[27], g, omg, gd, gR0;
+                orc_dipole(r, T, dT);
+                fermi(d, beta * (rvdw[i] + rvdw[j]), a, &g, &omg, &gd, &gR0);
+                double f[3] = {0, 0, 0}, s = 0.0, u = 0.0;
+                for (int p = 0; p < 3; p++)
+                    for (int q = 0; q < 3; q++) {
+                        double m = M[(size_t)(3 * i + p) * n + 3 * j + q];
+                        s += m * g * T[p * 3 + q];
+                        u += m * T[p * 3 + q];
+                        for (int c = 0; c < 3; c++)
+                            f[c] += m * (gd * r[c] / d * T[p * 3 + q] + g * dT[c * 9 + p * 3 + q]);
+                    }
+                for (int c = 0; c < 3; c++) {
+                    double fc = 0.5 * ci * cj * f[c];
+                    gR[3 * i + c] -= fc;
+                    gR[3 * j + c] += fc;
+                }
+                S[i] += ci * cj * s; S[j] += ci * cj * s;
+                double uu = 0.5 * ci * cj * beta * gR0 * u;
+                U[i] += uu; U[j] += uu;
+            }
+        }
+        for (int i = 0; i < N; i++) {
+            double tr = 0.0;
+            for (int c = 0; c < 3; c++) tr += M[(size_t)(3 * i + c) * n + 3 * i + c];
+            if (grad_alpha0) grad_alpha0[i] = S[i] / (4.0 * alpha0[i]);
+            if (grad_omega) grad_omega[i] = S[i] / (2.0 * omega[i]) + 0.5 * omega[i] * tr - 1.5;
+            if (grad_rvdw) grad_rvdw[i] = U[i];
+            if (grad_R) for (int c = 0; c < 3; c++) grad_R[3 * i + c] = gR[3 * i + c];
+        }
+        free(gR); free(S); free(U);
+    }
+    free(Q); free(lam); free(V);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Periodic: lattice helpers and Bloch sums                                  */
+/* ------------------------------------------------------------------------- */
+
+static double det3(const double *A)
+{
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* Ainv[d*3+u] = (A^{-1})_{du} */
+static void inv3(const double *A, double *Ainv)
+{
+    double dt = det3(A);
+    Ainv[0] = (A[4] * A[8] - A[5] * A[7]) / dt;
+    Ainv[1] = (A[2] * A[7] - A[1] * A[8]) / dt;
+    Ainv[2] = (A[1] * A[5] - A[2] * A[4]) / dt;
+    Ainv[3] = (A[5] * A[6] - A[3] * A[8]) / dt;
+    Ainv[4] = (A[0] * A[8] - A[2] * A[6]) / dt;
+    Ainv[5] = (A[2] * A[3] - A[0] * A[5]) / dt;
+    Ainv[6] = (A[3] * A[7] - A[4] * A[6]) / dt;
+    Ainv[7] = (A[1] * A[6] - A[0] * A[7]) / dt;
+    Ainv[8] = (A[0] * A[4] - A[1] * A[3]) / dt;
+}
+
+void orc_ewald_defaults(const double *lattice, double *gamma, double *rc, double *kc)
+{
+    double vol = fabs(det3(lattice));
+    *gamma = 2.5 / cbrt(vol);
+    *rc = 6.0 / *gamma;
+    *kc = 10.0 * *gamma;
+}
+
+typedef struct {
+    double A[9], Ainv[9], B[9]; /* B rows = reciprocal vectors b_u, B_ud = 2 pi Ainv_du */
+    double vol;
+    int nimg; int *img;         /* integer triplets n */
+    int nrec; int *rec;         /* integer triplets m */
+    double gamma, rc, kc;
+} lattice_t;
+
+static double norm3(const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+static void lattice_setup(lattice_t *L, const double *lattice, double gamma,
+                          double rc, double kc, double rreal, double rmaxpair,
+                          double qmax)
+{
+    memcpy(L->A, lattice, sizeof(double) * 9);
+    inv3(L->A, L->Ainv);
+    for (int u = 0; u < 3; u++)
+        for (int d = 0; d < 3; d++) L->B[u * 3 + d] = 2.0 * PI * L->Ainv[d * 3 + u];
+    L->vol = fabs(det3(L->A));
+    L->gamma = gamma; L->rc = rc; L->kc = kc;
+    int nv[3], mv[3];
+    for (int v = 0; v < 3; v++) {
+        nv[v] = (int)ceil((rreal + rmaxpair) * norm3(L->B + 3 * v) / (2.0 * PI)) + 1;
+        mv[v] = (int)ceil((kc + qmax) * norm3(L->A + 3 * v) / (2.0 * PI)) + 1;
+    }
+    L->nimg = (2 * nv[0] + 1) * (2 * nv[1] + 1) * (2 * nv[2] + 1);
+    L->img = (int *)malloc(sizeof(int) * 3 * L->nimg);
+    int t = 0;
+    for (int x = -nv[0]; x <= nv[0]; x++)
+        for (int y = -nv[1]; y <= nv[1]; y++)
+            for (int z = -nv[2]; z <= nv[2]; z++) {
+                L->img[3 * t] = x; L->img[3 * t + 1] = y; L->img[3 * t + 2] = z; t++;
+            }
+    L->nrec = (2 * mv[0] + 1) * (2 * mv[1] + 1) * (2 * mv[2] + 1);
+    L->rec = (int *)malloc(sizeof(int) * 3 * L->nrec);
+    t = 0;
+    for (int x = -mv[0]; x <= mv[0]; x++)
+        for (int y = -mv[1]; y <= mv[1]; y++)
+            for (int z = -mv[2]; z <= mv[2]; z++) {
+                L->rec[3 * t] = x; L->rec[3 * t + 1] = y; L->rec[3 * t + 2] = z; t++;
+            }
+}
+
+static void lattice_free(lattice_t *L) { free(L->img); free(L->rec); }
+
+/* Bloch-summed damped tensor for one ordered pair, r = R_j - R_i.
+ * Outputs (each 9 complex = re/im arrays):
+ *   T[ab]            T_ij(q)
+ *   dR[c][ab]        d/dr_c
+ *   dA[v][c][ab]     d/dA_vc (Cartesian positions, fractional q fixed)
+ * dR, dA may be NULL. */
+static void bloch_pair(const lattice_t *L, const double *r, int self,
+                       const double *q, double R0, double a,
+                       double *Tre, double *Tim, double *dRre, double *dRim,
+                       double *dAre, double *dAim)
+{
+    const double gamma = L->gamma;
+    memset(Tre, 0, 9 * sizeof(double)); memset(Tim, 0, 9 * sizeof(double));
+    if (dRre) { memset(dRre, 0, 27 * sizeof(double)); memset(dRim, 0, 27 * sizeof(double)); }
+    if (dAre) { memset(dAre, 0, 81 * sizeof(double)); memset(dAim, 0, 81 * sizeof(double)); }
+    double rho[3];
+    for (int v = 0; v < 3; v++) {
+        rho[v] = 0.0;
+        for (int d = 0; d < 3; d++) rho[v] += L->Ainv[d * 3 + v] * r[d];
+    }
+    /* real space */
+    for (int t = 0; t < L->nimg; t++) {
+        const int *nn = L->img + 3 * t;
+        double x[3];
+        for (int d = 0; d < 3; d++)
+            x[d] = r[d] + nn[0] * L->A[d] + nn[1] * L->A[3 + d] + nn[2] * L->A[6 + d];
+        double dist = norm3(x);
+        if (dist == 0.0) continue;  /* n = 0, i = j */
+        double F[9] = {0}, dF[27] = {0};
+        int any = 0;
+        if (dist < L->rc) {
+            double Te[9], dTe[27];
+            orc_dipole_erfc(x, gamma, Te, dTe);
+            for (int k = 0; k < 9; k++) F[k] += Te[k];
+            for (int k = 0; k < 27; k++) dF[k] += dTe[k];
+            any = 1;
+        }
+        double g, omg, gd, gR0;
+        fermi(dist, R0, a, &g, &omg, &gd, &gR0);
+        if (omg > DAMP_TAIL) {
+            double T0[9], dT0[27];
+            orc_dipole(x, T0, dT0);
+            for (int k = 0; k < 9; k++) F[k] -= omg * T0[k];
+            for (int c = 0; c < 3; c++)
+                for (int k = 0; k < 9; k++)
+                    dF[c * 9 + k] -= omg * dT0[c * 9 + k] - gd * x[c] / dist * T0[k];
+            any = 1;
+        }
+        if (!any) continue;
+        double ph = -(q[0] * x[0] + q[1] * x[1] + q[2] * x[2]);
+        double cph = cos(ph), sph = sin(ph);
+        for (int k = 0; k < 9; k++) { Tre[k] += F[k] * cph; Tim[k] += F[k] * sph; }
+        if (dRre)
+            for (int c = 0; c < 3; c++)
+                for (int k = 0; k < 9; k++) {
+                    /* (dF_c - i q_c F) e^{i ph} */
+                    double are = dF[c * 9 + k], aim = -q[c] * F[k];
+                    dRre[c * 9 + k] += are * cph - aim * sph;
+                    dRim[c * 9 + k] += are * sph + aim * cph;
+                }
+        if (dAre)
+            for (int v = 0; v < 3; v++)
+                for (int c = 0; c < 3; c++)
+                    for (int k = 0; k < 9; k++) {
+                        /* (dF_c n_v + i q_c rho_v F) e^{i ph} */
+                        double are = dF[c * 9 + k] * nn[v], aim = q[c] * rho[v] * F[k];
+                        dAre[(v * 3 + c) * 9 + k] += are * cph - aim * sph;
+                        dAim[(v * 3 + c) * 9 + k] += are * sph + aim * cph;
+                    }
+    }
+    /* reciprocal space */
+    double pref = 4.0 * PI / L->vol;
+    for (int t = 0; t < L->nrec; t++) {
+        const int *mm = L->rec + 3 * t;
+        double G[3], k[3];
+        for (int d = 0; d < 3; d++) {
+            G[d] = mm[0] * L->B[d] + mm[1] * L->B[3 + d] + mm[2] * L->B[6 + d];
+            k[d] = G[d] + q[d];
+        }
+        double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        double kn = sqrt(k2);
+        if (kn == 0.0 || kn >= L->kc) continue;
+        double E = exp(-k2 / (4.0 * gamma * gamma));
+        double h[9];
+        for (int aa = 0; aa < 3; aa++)
+            for (int bb = 0; bb < 3; bb++) h[aa * 3 + bb] = k[aa] * k[bb] / k2 * E;
+        double ph = G[0] * r[0] + G[1] * r[1] + G[2] * r[2];
+        double cph = cos(ph), sph = sin(ph);
+        for (int kk = 0; kk < 9; kk++) { Tre[kk] += pref * h[kk] * cph; Tim[kk] += pref * h[kk] * sph; }
+        if (dRre)
+            for (int c = 0; c < 3; c++)
+                for (int kk = 0; kk < 9; kk++) {
+                    /* pref h (i G_c) e^{i ph} */
+                    dRre[c * 9 + kk] += -pref * h[kk] * G[c] * sph;
+                    dRim[c * 9 + kk] += pref * h[kk] * G[c] * cph;
+                }
+        if (dAre) {
+            /* dh_ab/dk_d */
+            double dh[27];
+            for (int d = 0; d < 3; d++)
+                for (int aa = 0; aa < 3; aa++)
+                    for (int bb = 0; bb < 3; bb++) {
+                        double v = -2.0 * k[aa] * k[bb] * k[d] / (k2 * k2) * E
+                                   - k[aa] * k[bb] / k2 * E * k[d] / (2.0 * gamma * gamma);
+                        if (aa == d) v += k[bb] / k2 * E;
+                        if (bb == d) v += k[aa] / k2 * E;
+                        dh[d * 9 + aa * 3 + bb] = v;
+                    }
+            for (int v = 0; v < 3; v++)
+                for (int c = 0; c < 3; c++)
+                    for (int kk = 0; kk < 9; kk++) {
+                        double dhv = 0.0;
+                        for (int d = 0; d < 3; d++) dhv += dh[d * 9 + kk] * L->Ainv[d * 3 + v];
+                        /* d(pref)/dA_vc = -pref Ainv_cv ; dk_d/dA_vc = -Ainv_dv k_c ;
+                           d(G.r)/dA_vc = -G_c rho_v */
+                        double re = -L->Ainv[c * 3 + v] * h[kk] - k[c] * dhv;
+                        double im = -h[kk] * G[c] * rho[v];
+                        dAre[(v * 3 + c) * 9 + kk] += pref * (re * cph - im * sph);
+                        dAim[(v * 3 + c) * 9 + kk] += pref * (re * sph + im * cph);
+                    }
+        }
+    }
+    if (self) {
+        double s = 4.0 * gamma * gamma * gamma / (3.0 * sqrt(PI));
+        Tre[0] -= s; Tre[4] -= s; Tre[8] -= s;
+    }
+}
+
+static void pair_extent(int N, const double *R, double *maxd)
+{
+    double m = 0.0;
+    for (int i = 0; i < N; i++)
+        for (int j = 0; j < N; j++) {
+            double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
+            double d = norm3(r);
+            if (d > m) m = d;
+        }
+    *maxd = m;
+}
+
+static double damp_range(int N, const double *rvdw, double beta, double a)
+{
+    if (beta <= 0.0) return 0.0;
+    double mx = 0.0;
+    for (int i = 0; i < N; i++) if (rvdw[i] > mx) mx = rvdw[i];
+    /* (1-g) > DAMP_TAIL  <=>  eta < 1 + ln(1/DAMP_TAIL - 1)/a */
+    return (1.0 + log(1.0 / DAMP_TAIL - 1.0) / a) * beta * 2.0 * mx * 1.0000001;
+}
+
+int orc_assemble_periodic(int N, const double *R, const double *lattice,
+                          const double *q, double gamma, double rc, double kc,
+                          const double *alpha0, const double *omega,
+                          const double *rvdw, double beta, double a,
+                          double *Qre, double *Qim)
+{
+    if (N < 1 || det3(lattice) <= 0.0) return 1;
+    int n = 3 * N;
+    double maxd;
+    pair_extent(N, R, &maxd);
+    double rreal = rc > damp_range(N, rvdw, beta, a) ? rc : damp_range(N, rvdw, beta, a);
+    lattice_t L;
+    lattice_setup(&L, lattice, gamma, rc, kc, rreal, maxd, norm3(q));
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < N; i++) {
+        double ci = omega[i] * sqrt(alpha0[i]);
+        for (int j = 0; j < N; j++) {
+            double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
+            double Tre[9], Tim[9];
+            bloch_pair(&L, r, i == j, q, beta * (rvdw[i] + rvdw[j]), a, Tre, Tim,
+                       NULL, NULL, NULL, NULL);
+            double cc = ci * omega[j] * sqrt(alpha0[j]);
+            for (int p = 0; p < 3; p++)
+                for (int s = 0; s < 3; s++) {
+                    Qre[(size_t)(3 * i + p) * n + 3 * j + s] =
+                        cc * Tre[p * 3 + s] + (i == j && p == s ? omega[i] * omega[i] : 0.0);
+                    Qim[(size_t)(3 * i + p) * n + 3 * j + s] = cc * Tim[p * 3 + s];
+                }
+        }
+    }
+    lattice_free(&L);
+    return 0;
+}
+
+int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
+                     const double *q_frac, double gamma, double rc, double kc,
+                     const double *alpha0, const double *omega,
+                     const double *rvdw, double beta, double a,
+                     double *energy, double *grad_R, double *grad_alpha0,
+                     double *grad_lattice, double *eigs)
+{
+    if (N < 1 || nq < 1 || det3(lattice) <= 0.0) return 1;
+    int n = 3 * N, m = 2 * n;
+    int want_grad = grad_R || grad_alpha0 || grad_lattice;
+    double Ainv[9], B[9];
+    inv3(lattice, Ainv);
+    for (int u = 0; u < 3; u++)
+        for (int d = 0; d < 3; d++) B[u * 3 + d] = 2.0 * PI * Ainv[d * 3 + u];
+    double maxd;
+    pair_extent(N, R, &maxd);
+    double dr = damp_range(N, rvdw, beta, a);
+    double rreal = rc > dr ? rc : dr;
+    double qmax = 0.0;
+    for (int t = 0; t < nq; t++) {
+        double qq[3];
+        for (int d = 0; d < 3; d++)
+            qq[d] = q_frac[3 * t] * B[d] + q_frac[3 * t + 1] * B[3 + d] + q_frac[3 * t + 2] * B[6 + d];
+        if (norm3(qq) > qmax) qmax = norm3(qq);
+    }
+    lattice_t L;
+    lattice_setup(&L, lattice, gamma, rc, kc, rreal, maxd, qmax);
+    double *Qre = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *Qim = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *lam = (double *)malloc(sizeof(double) * m);
+    double *V = want_grad ? (double *)malloc(sizeof(double) * (size_t)m * m) : NULL;
+    double *ME = want_grad ? (double *)malloc(sizeof(double) * (size_t)m * m) : NULL;
+    double som = 0.0;
+    for (int i = 0; i < N; i++) som += omega[i];
+    double esum = 0.0;
+    if (grad_R) memset(grad_R, 0, sizeof(double) * 3 * N);
+    if (grad_alpha0) memset(grad_alpha0, 0, sizeof(double) * N);
+    if (grad_lattice) memset(grad_lattice, 0, sizeof(double) * 9);
+    int rc_out = 0;
+    for (int t = 0; t < nq; t++) {
+        double q[3];
+        for (int d = 0; d < 3; d++)
+            q[d] = q_frac[3 * t] * B[d] + q_frac[3 * t + 1] * B[3 + d] + q_frac[3 * t + 2] * B[6 + d];
+        orc_assemble_periodic(N, R, lattice, q, gamma, rc, kc, alpha0, omega, rvdw,
+                              beta, a, Qre, Qim);
+        int sw = orc_jacobi_hermitian(n, Qre, Qim, lam, V);
+        if (sw < 0) { rc_out = 3; break; }
+        if (lam[0] <= 0.0) { rc_out = 2; break; }
+        if (eigs) for (int k = 0; k < n; k++) eigs[(size_t)t * n + k] = lam[2 * k];
+        esum += 0.25 * sum_sqrt(m, lam) - 1.5 * som;
+        if (!want_grad) continue;
+        inv_sqrt_from_eig(m, V, lam, ME);
+        /* M = ME[0:n,0:n] + i ME[n:2n, 0:n] */
+        double wq = 1.0 / nq;
+        double *gRloc = (double *)calloc((size_t)3 * N, sizeof(double));
+        double *galoc = (double *)calloc(N, sizeof(double));
+        double gl[9] = {0};
+#pragma omp parallel
+        {
+            double *gRt = (double *)calloc((size_t)3 * N, sizeof(double));
+            double *gat = (double *)calloc(N, sizeof(double));
+            double glt[9] = {0};
+#pragma omp for schedule(dynamic)
+            for (int i = 0; i < N; i++) {
+                double ci = omega[i] * sqrt(alpha0[i]);
+                for (int j = 0; j < N; j++) {
+                    double cj = omega[j] * sqrt(alpha0[j]);
+                    double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
+                    double Tre[9], Tim[9], dRre[27], dRim[27], dAre[81], dAim[81];
+                    bloch_pair(&L, r, i == j, q, beta * (rvdw[i] + rvdw[j]), a, Tre, Tim,
+                               dRre, dRim, dAre, dAim);
+                    double cc = ci * cj;
+                    /* M_{jb,ia} */
+                    double Mre[9], Mim[9];
+                    for (int aa = 0; aa < 3; aa++)
+                        for (int bb = 0; bb < 3; bb++) {
+                            Mre[aa * 3 + bb] = ME[(size_t)(3 * j + bb) * m + 3 * i + aa];
+                            Mim[aa * 3 + bb] = ME[(size_t)(n + 3 * j + bb) * m + 3 * i + aa];
+                        }
+                    double P = 0.0;
+                    for (int k = 0; k < 9; k++) P += Mre[k] * Tre[k] - Mim[k] * Tim[k];
+                    gat[i] += 0.25 * wq * cc * P / (2.0 * alpha0[i]);
+                    gat[j] += 0.25 * wq * cc * P / (2.0 * alpha0[j]);
+                    if (i != j)
+                        for (int c = 0; c < 3; c++) {
+                            double X = 0.0;
+                            for (int k = 0; k < 9; k++)
+                                X += Mre[k] * dRre[c * 9 + k] - Mim[k] * dRim[c * 9 + k];
+                            gRt[3 * j + c] += 0.25 * wq * cc * X;
+                            gRt[3 * i + c] -= 0.25 * wq * cc * X;
+                        }
+                    for (int vc = 0; vc < 9; vc++) {
+                        double X = 0.0;
+                        for (int k = 0; k < 9; k++)
+                            X += Mre[k] * dAre[vc * 9 + k] - Mim[k] * dAim[vc * 9 + k];
+                        glt[vc] += 0.25 * wq * cc * X;
+                    }
+                }
+            }
+#pragma omp critical
+            {
+                for (int k = 0; k < 3 * N; k++) gRloc[k] += gRt[k];
+                for (int k = 0; k < N; k++) galoc[k] += gat[k];
+                for (int k = 0; k < 9; k++) gl[k] += glt[k];
+            }
+            free(gRt); free(gat);
+        }
+        if (grad_R) for (int k = 0; k < 3 * N; k++) grad_R[k] += gRloc[k];
+        if (grad_alpha0) for (int k = 0; k < N; k++) grad_alpha0[k] += galoc[k];
+        if (grad_lattice) for (int k = 0; k < 9; k++) grad_lattice[k] += gl[k];
+        free(gRloc); free(galoc);
+    }
+    if (energy) *energy = rc_out ? NAN : esum / nq;
+    lattice_free(&L);
+    free(Qre); free(Qim); free(lam); free(V); free(ME);
+    return rc_out;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Frequency route (eq:log-formula) with the oracle's own Cholesky            */
+/* ------------------------------------------------------------------------- */
+
+void orc_gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; i++) {
+        double z = cos(PI * (i + 0.75) / (n + 0.5)), pp = 0.0;
+        for (int it = 0; it < 100; it++) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int k = 1; k <= n; k++) {
+                double p3 = p2; p2 = p1;
+                p1 = ((2.0 * k - 1.0) * z * p2 - (k - 1.0) * p3) / k;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            double z1 = z;
+            z = z1 - p1 / pp;
+            if (fabs(z - z1) < 1e-16) break;
+        }
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+/* In-place lower Cholesky of a row-major SPD matrix; returns 0 or 2 if not PD. */
+static int cholesky(int n, double *A)
+{
+    for (int j = 0; j < n; j++) {
+        double *aj = A + (size_t)j * n;
+        double s = aj[j];
+        for (int k = 0; k < j; k++) s -= aj[k] * aj[k];
+        if (!(s > 0.0)) return 2;
+        double l = sqrt(s);
+        aj[j] = l;
+#pragma omp parallel for schedule(static)
+        for (int i = j + 1; i < n; i++) {
+            double *ai = A + (size_t)i * n;
+            double t = ai[j];
+            for (int k = 0; k < j; k++) t -= ai[k] * aj[k];
+            ai[j] = t / l;
+        }
+    }
+    return 0;
+}
+
+int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
+                        const double *omega, const double *rvdw, double beta,
+                        double a, int npts, double *energy, int nsample,
+                        const int *atoms, double *grad_R_sample)
+{
+    if (N < 1 || npts < 1) return 1;
+    int n = 3 * N;
+    double *Q = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *S = (double *)malloc(sizeof(double) * (size_t)n * n);
+    orc_assemble_finite(N, R, alpha0, omega, rvdw, beta, a, Q);
+    double *x = (double *)malloc(sizeof(double) * npts), *w = (double *)malloc(sizeof(double) * npts);
+    orc_gauss_legendre(npts, x, w);
+    double *Mrows = nsample > 0 ? (double *)calloc((size_t)nsample * 3 * n, sizeof(double)) : NULL;
+    double *y = (double *)malloc(sizeof(double) * n);
+    double *dsc = (double *)malloc(sizeof(double) * n);
+    double etot = 0.0;
+    int rc = 0;
+    for (int t = 0; t < npts && !rc; t++) {
+        double u = 0.6 * (1.0 + x[t]) / (1.0 - x[t]);
+        double du = 0.6 * 2.0 / ((1.0 - x[t]) * (1.0 - x[t])) * w[t];
+        /* I + alpha(iu)^{1/2} T alpha(iu)^{1/2} = D^{-1}(Q + u^2)D^{-1}, D = (Omega^2 + u^2)^{1/2} */
+        for (int p = 0; p < n; p++) {
+            double om = omega[p / 3];
+            dsc[p] = 1.0 / sqrt(om * om + u * u);
+        }
+#pragma omp parallel for schedule(static)
+        for (int p = 0; p < n; p++)
+            for (int s = 0; s < n; s++)
+                S[(size_t)p * n + s] = Q[(size_t)p * n + s] * dsc[p] * dsc[s] +
+                                       (p == s ? u * u * dsc[p] * dsc[p] : 0.0);
+        if (cholesky(n, S)) { rc = 2; break; }
+        double ld = 0.0;
+        for (int p = 0; p < n; p++) ld += 2.0 * log(S[(size_t)p * n + p]);
+        etot += du * ld / (2.0 * PI);
+        /* rows of (Q + u^2)^{-1} = D^{-1} S^{-1} D^{-1} for the sampled atoms */
+        for (int sa = 0; sa < nsample; sa++)
+            for (int c = 0; c < 3; c++) {
+                int col = 3 * atoms[sa] + c;
+                for (int p = 0; p < n; p++) y[p] = (p == col) ? dsc[p] : 0.0;
+                for (int p = 0; p < n; p++) {         /* L y = b */
+                    double acc = y[p];
+                    const double *sp = S + (size_t)p * n;
+                    for (int k = 0; k < p; k++) acc -= sp[k] * y[k];
+                    y[p] = acc / sp[p];
+                }
+                for (int p = n - 1; p >= 0; p--) {    /* L^T z = y */
+                    double acc = y[p];
+                    for (int k = p + 1; k < n; k++) acc -= S[(size_t)k * n + p] * y[k];
+                    y[p] = acc / S[(size_t)p * n + p];
+                }
+                double *mr = Mrows + ((size_t)sa * 3 + c) * n;
+                for (int p = 0; p < n; p++) mr[p] += (2.0 / PI) * du * y[p] * dsc[p];
+            }
+    }
+    if (energy) *energy = rc ? NAN : etot;
+    if (!rc && nsample > 0) {
+        for (int sa = 0; sa < nsample; sa++) {
+            int k = atoms[sa];
+            double ck = omega[k] * sqrt(alpha0[k]);
+            double gk[3] = {0, 0, 0};
+            for (int j = 0; j < N; j++) {
+                if (j == k) continue;
+                double cj = omega[j] * sqrt(alpha0[j]);
+                double r[3] = {R[3 * j] - R[3 * k], R[3 * j + 1] - R[3 * k + 1], R[3 * j + 2] - R[3 * k + 2]};
+                double d = norm3(r);
+                double T[9], dT[27], g, omg, gd, gR0;
+                orc_dipole(r, T, dT);
+                fermi(d, beta * (rvdw[k] + rvdw[j]), a, &g, &omg, &gd, &gR0);
+                for (int c = 0; c < 3; c++) {
+                    double acc = 0.0;
+                    for (int p = 0; p < 3; p++)
+                        for (int s = 0; s < 3; s++) {
+                            double mm = Mrows[((size_t)sa * 3 + p) * n + 3 * j + s];
+                            acc += mm * (gd * r[c] / d * T[p * 3 + s] + g * dT[c * 9 + p * 3 + s]);
+                        }
+                    gk[c] -= 0.5 * ck * cj * acc;
+                }
+            }
+            for (int c = 0; c < 3; c++) grad_R_sample[3 * sa + c] = gk[c];
+        }
+    }
+    free(Q); free(S); free(x); free(w); free(Mrows); free(y); free(dsc);
+    return rc;
+}
+
+int orc_min_coupling_eig(int N, const double *R, const double *alpha0,
+                         const double *rvdw, double beta, double a,
+                         double *mu_min)
+{
+    int n = 3 * N;
+    double *om = (double *)malloc(sizeof(double) * N);
+    for (int i = 0; i < N; i++) om[i] = 1.0;
+    double *Q = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *lam = (double *)malloc(sizeof(double) * n);
+    /* with omega = 1: Q = I + alpha^{1/2} T alpha^{1/2} */
+    orc_assemble_finite(N, R, alpha0, om, rvdw, beta, a, Q);
+    for (int p = 0; p < n; p++) Q[(size_t)p * n + p] -= 1.0;
+    int sw = orc_jacobi(n, Q, lam, NULL);
+    *mu_min = lam[0];
+    free(om); free(Q); free(lam);
+    return sw < 0 ? 3 : 0;
+}

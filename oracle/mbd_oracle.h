@@ -1,0 +1,102 @@
+/*
+ * mbd_oracle.h -- plain FP64 CPU oracle for the MBD energy and its gradients.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may call into this library.  It shares no code
+ * with the HIP path (paper_2308_03140_amd/) and never imports it.
+ *
+ * Everything is in Hartree atomic units (bohr, Ha).  Arrays are row-major.
+ * The paper is Hermann et al., "libMBD: A general-purpose package for scalable
+ * quantum many-body dispersion calculations" (arXiv:2308.03140); citations
+ * name its sections and equation labels.
+ *
+ * Return codes: 0 ok, 1 invalid argument, 2 negative eigenvalue of Q
+ * (dipole collapse, Sec. 2.1 after eq:mbd-energy), 3 Jacobi not converged.
+ */
+#ifndef MBD_ORACLE_H
+#define MBD_ORACLE_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Q of eq:q-matrix for a finite system, T^lr = g T (eq:mbd-lr-dipole with the
+ * bare tensor of eq:dipole, Fermi damping eq:fermi-damping with s_R = beta).
+ * beta == 0 means no damping (g == 1).  Q is n x n, n = 3N, row-major,
+ * index p = 3*i + a. */
+void orc_assemble_finite(int N, const double *R, const double *alpha0,
+                         const double *omega, const double *rvdw,
+                         double beta, double a, double *Q);
+
+/* Cyclic Jacobi for a real symmetric n x n matrix (row-major, destroyed).
+ * w: eigenvalues ascending; V (may be NULL): V[i*n + k] = component i of
+ * eigenvector k.  Returns number of sweeps used, or -1 if not converged. */
+int orc_jacobi(int n, double *A, double *w, double *V);
+
+/* Hermitian eigenvalues (and optionally eigenvectors) via the real embedding
+ * [[Re, -Im], [Im, Re]] of size 2n; w gets the 2n embedded eigenvalues
+ * (each Hermitian eigenvalue twice), V the 2n x 2n embedded eigenvectors. */
+int orc_jacobi_hermitian(int n, const double *Are, const double *Aim,
+                         double *w, double *V);
+
+/* Finite MBD: energy eq:mbd-energy, gradients as (1/4) Re Tr(Q^{-1/2} dQ)
+ * (eq:mbd-gradient read with the full derivative of Q).  Any output pointer
+ * may be NULL.  eigs: 3N eigenvalues of Q ascending. */
+int orc_mbd_finite(int N, const double *R, const double *alpha0,
+                   const double *omega, const double *rvdw, double beta,
+                   double a, double *energy, double *grad_R,
+                   double *grad_alpha0, double *grad_omega, double *grad_rvdw,
+                   double *eigs);
+
+/* Ewald defaults of Sec. 3.3: gamma = 2.5/Omega^(1/3), Rc = 6/gamma,
+ * kc = 10 gamma.  lattice rows are the lattice vectors (bohr). */
+void orc_ewald_defaults(const double *lattice, double *gamma, double *rc,
+                        double *kc);
+
+/* Periodic Q(q) of eq:q-matrix with T^lr(q) the Bloch sum of g T evaluated
+ * with the Ewald split of eq:ewald/eq:terfc plus the damping correction
+ * -(1-g) T summed in real space.  q is Cartesian (1/bohr).  Qre/Qim n x n. */
+int orc_assemble_periodic(int N, const double *R, const double *lattice,
+                          const double *q, double gamma, double rc, double kc,
+                          const double *alpha0, const double *omega,
+                          const double *rvdw, double beta, double a,
+                          double *Qre, double *Qim);
+
+/* Periodic MBD per unit cell: E = mean over the q list of E(q)
+ * (eq:brillouin-int).  q_frac [nq][3] fractional in the reciprocal basis.
+ * grad_lattice [3][3] = dE/dA_{vc} with Cartesian positions, fractional q,
+ * gamma and the term sets fixed.  eigs: nq x 3N Hermitian eigenvalues. */
+int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
+                     const double *q_frac, double gamma, double rc, double kc,
+                     const double *alpha0, const double *omega,
+                     const double *rvdw, double beta, double a,
+                     double *energy, double *grad_R, double *grad_alpha0,
+                     double *grad_lattice, double *eigs);
+
+/* Gauss-Legendre nodes/weights on [-1, 1] (Newton on P_n). */
+void orc_gauss_legendre(int n, double *x, double *w);
+
+/* Finite MBD energy by the imaginary-frequency route eq:log-formula, with the
+ * Hermitian form alpha^{1/2} T alpha^{1/2}, eq:dyn-pol and the grid map
+ * u = 0.6 (1+x)/(1-x) of Sec. 3.3; ln det by the oracle's own Cholesky.
+ * Optionally (nsample > 0) the gradient dE/dR of the listed atoms from
+ * Q^{-1/2} = (2/pi) int_0^inf (Q + u^2)^{-1} du, reusing the same factors.
+ * Returns 2 if a Cholesky factorisation fails (collapse). */
+int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
+                        const double *omega, const double *rvdw, double beta,
+                        double a, int npts, double *energy, int nsample,
+                        const int *atoms, double *grad_R_sample);
+
+/* Smallest eigenvalue of alpha0^{1/2} T^lr alpha0^{1/2} (finite). */
+int orc_min_coupling_eig(int N, const double *R, const double *alpha0,
+                         const double *rvdw, double beta, double a,
+                         double *mu_min);
+
+/* Pairwise tensors for tests: bare T (eq:dipole), T^erfc (eq:terfc, with the
+ * coefficient reading -r_a r_b C), and their first derivatives dT[c][a][b]. */
+void orc_dipole(const double *r, double *T, double *dT);
+void orc_dipole_erfc(const double *r, double gamma, double *T, double *dT);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
