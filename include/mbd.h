@@ -1,0 +1,174 @@
+/*
+ * mbd.h -- C ABI of libmbd_hip.so: many-body dispersion (MBD) energy and
+ * analytic gradients on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Hermann et al., "libMBD: A general-purpose package
+ * for scalable quantum many-body dispersion calculations" (arXiv:2308.03140):
+ *
+ *   Q_ij = delta_ij omega_i^2 I + omega_i omega_j sqrt(alpha0_i alpha0_j) T^lr_ij
+ *                                                        (Sec. 2.1, eq:q-matrix)
+ *   Q = C Lambda C^T                                     (eq:diagonalization)
+ *   E = sum_k sqrt(lambda_k)/2 - 3 sum_i omega_i/2        (eq:mbd-energy)
+ *   T^lr = g T, g the Fermi function with a and beta     (Sec. 2.7,
+ *                                eq:mbd-lr-dipole, eq:fermi-damping, a = 6)
+ *   periodic: E = mean over the q mesh of E(q), T^lr(q) by Ewald summation
+ *                                (Sec. 2.2, eq:brillouin-int, eq:ewald, eq:terfc;
+ *                                 defaults of Sec. 3.3)
+ *   gradients: dE/dX = (1/4) Re Tr(Q^{-1/2} dQ/dX) - (3/2) d(sum omega)/dX
+ *                                (Sec. 2.4, eq:mbd-gradient)
+ *
+ * Conventions
+ *   - Hartree atomic units: lengths in bohr, energies in Ha, alpha0 in bohr^3,
+ *     omega in Ha, C6 in Ha bohr^6.
+ *   - Every array argument is FP64, contiguous, and a DEVICE pointer on the
+ *     context's device, unless marked (host).  Coordinates are [N][3]
+ *     row-major; the lattice is [3][3] with row v = lattice vector v.
+ *   - Ownership: the caller owns all input and output buffers.  The library
+ *     never frees them and does not keep them past the call.  The context owns
+ *     its device workspaces (grown to the largest problem seen, reused).
+ *   - Streams: all device work is enqueued on the context's stream.  A call
+ *     returns after one synchronisation of that stream (it reads one status
+ *     word back).  A context is not thread-safe; use one per host thread.
+ *   - Errors: every call returns an mbd_status; no exceptions cross the ABI
+ *     and the library never exits.  mbd_last_error() gives (code, origin,
+ *     message) of the last failure on the context, like get_exception of the
+ *     paper's Fortran API (Sec. 3.1).  On any error the outputs are undefined
+ *     except where stated.
+ */
+#ifndef MBD_H
+#define MBD_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbd_ctx mbd_ctx;
+
+typedef enum {
+    MBD_OK = 0,
+    MBD_ERR_INVALID_ARGUMENT = 1,   /* bad pointer, size, flag or input value */
+    MBD_ERR_NEGATIVE_EIGENVALUE = 2,/* Q not positive definite: the "dipole
+                                       collapse" of Sec. 2.1 (complex energy) */
+    MBD_ERR_NOT_CONVERGED = 3,      /* refinement did not reach its target    */
+    MBD_ERR_OUT_OF_MEMORY = 4,      /* device allocation failed or exceeded
+                                       MBD_WORKSPACE_LIMIT (bytes, env var)   */
+    MBD_ERR_DEVICE = 5,             /* HIP runtime error                      */
+    MBD_ERR_UNSUPPORTED = 6         /* valid request this build does not do  */
+} mbd_status;
+
+/* Arithmetic of the diagonalisation.  MBD_FP64: everything in FP64.
+ * MBD_FP32_REFINED: Householder reduction, tridiagonal solve and
+ * back-transform in FP32 on matrix cores with FP32 accumulation, then one
+ * Ogita-Aishima refinement step of the eigenpairs in FP64 against the FP64 Q;
+ * the sqrt(lambda) energy sum, the gradients and the Ewald sums stay FP64. */
+typedef enum { MBD_FP64 = 0, MBD_FP32_REFINED = 1 } mbd_precision;
+
+/* Second oscillator parameter: omega (Ha) or C6 (Ha bohr^6), related by
+ * 4 C6 = 3 omega alpha0^2 (Sec. 2.1, eq:osc-param). */
+typedef enum { MBD_PARAM_OMEGA = 0, MBD_PARAM_C6 = 1 } mbd_param_kind;
+
+enum {
+    MBD_WANT_ENERGY = 1,
+    MBD_WANT_GRAD_COORDS = 2,
+    MBD_WANT_GRAD_ALPHA0 = 4,
+    MBD_WANT_GRAD_OMEGA = 8,       /* gradient w.r.t. omega or C6 (param_kind) */
+    MBD_WANT_GRAD_RVDW = 16,       /* finite systems only                      */
+    MBD_WANT_GRAD_LATTICE = 32,    /* periodic systems only                    */
+    MBD_WANT_EIGVALS = 64,
+    MBD_WANT_ERRORS = 128
+};
+
+typedef struct {
+    int32_t n_atoms;              /* N >= 1                                      */
+    const double *coords;         /* [N][3] bohr                                 */
+    const double *lattice;        /* [3][3] bohr, rows = lattice vectors, or NULL
+                                     for a finite system (HOST pointer)          */
+    int32_t n_q;                  /* periodic: number of q points in q_frac, or 0
+                                     to use the Monkhorst-Pack mesh kgrid/kshift */
+    const double *q_frac;         /* [n_q][3] fractional coordinates in the
+                                     reciprocal basis (HOST pointer)             */
+    int32_t kgrid[3];             /* periodic mesh size when n_q == 0 (each >= 1) */
+    double kshift[3];             /* added to the Monkhorst-Pack fractions
+                                     (2r - n - 1)/(2n), r = 1..n                 */
+    const double *alpha0;         /* [N] static polarisabilities, > 0           */
+    const double *omega_or_c6;    /* [N] omega (Ha) or C6, > 0                  */
+    mbd_param_kind param_kind;
+    const double *rvdw;           /* [N] vdW radii, > 0                          */
+    double beta;                  /* damping s_R >= 0 (0: undamped, g == 1)      */
+    double a;                     /* damping steepness > 0 (MBD: 6)              */
+    double ewald_gamma, ewald_rc, ewald_kc; /* <= 0: gamma = 2.5/Omega^(1/3),
+                                     Rc = 6/gamma, kc = 10 gamma (Sec. 3.3)      */
+} mbd_system;
+
+typedef struct {
+    double *energy;               /* [1] Ha (per unit cell if periodic)          */
+    double *grad_coords;          /* [N][3] dE/dR, Ha/bohr                        */
+    double *grad_alpha0;          /* [N]                                          */
+    double *grad_omega_or_c6;     /* [N] w.r.t. the given parameter kind          */
+    double *grad_rvdw;            /* [N]                                          */
+    double *grad_lattice;         /* [3][3] dE/dA_vc, Cartesian positions and
+                                     fractional q fixed                           */
+    double *eigvals;              /* [n_q or 1][3N] eigenvalues of Q ascending    */
+    double *errors;               /* [4]: lambda_min, refinement orthogonality
+                                     residual max|X^T X - I| (0 for FP64), number
+                                     of refinement steps, refinement threshold    */
+} mbd_result;
+
+/* Create a context on HIP device `device` with the given precision.
+ * hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream),
+ * or NULL for the default stream.  Returns MBD_ERR_DEVICE if the device
+ * cannot be used. */
+mbd_status mbd_create(mbd_ctx **ctx, int device, mbd_precision prec, void *hip_stream);
+
+/* Release the context and all its device workspaces. */
+mbd_status mbd_destroy(mbd_ctx *ctx);
+
+/* Change the stream of an existing context (same device). */
+mbd_status mbd_set_stream(mbd_ctx *ctx, void *hip_stream);
+
+/* Energy and the requested gradients of one system (finite or periodic).
+ * `want` is a bit set of MBD_WANT_*; an output pointer must be non-NULL when
+ * its bit is set.  Collapse (some eigenvalue <= 0, Sec. 2.1) returns
+ * MBD_ERR_NEGATIVE_EIGENVALUE with energy = NaN and, if MBD_WANT_ERRORS,
+ * errors[0] = lambda_min; gradients are then not written.  Coincident atoms
+ * (distance < 1e-8 bohr) and non-finite or non-positive per-atom inputs give
+ * MBD_ERR_INVALID_ARGUMENT. */
+mbd_status mbd_evaluate(mbd_ctx *ctx, const mbd_system *sys, unsigned want, mbd_result *out);
+
+/* Many independent finite systems (molecules of uneven size) in one batched
+ * launch sequence.  sys and out are HOST arrays of n_sys entries whose device
+ * pointers follow mbd_evaluate; status (HOST, [n_sys]) receives each system's
+ * mbd_status.  Periodic systems are not accepted here (MBD_ERR_UNSUPPORTED).
+ * The launch sequence is captured once per batch signature (sizes, want,
+ * precision) in a HIP graph and replayed on later calls with the same
+ * signature.  Returns MBD_OK if every system succeeded, else the first
+ * failing code. */
+mbd_status mbd_evaluate_batch(mbd_ctx *ctx, int32_t n_sys, const mbd_system *sys, unsigned want,
+                              mbd_result *out, int32_t *status);
+
+/* Dense symmetric eigensolver of the MBD path, exposed for testing and reuse:
+ * the Householder reduction, divide-and-conquer tridiagonal solve and
+ * back-transform used for Q.  A: [nbatch] matrices of order n, column-major
+ * with leading dimension lda, consecutive matrices `stride` elements apart,
+ * lower triangle read and DESTROYED.  w: [nbatch][n] eigenvalues ascending.
+ * Z (may be NULL): [nbatch] n x n eigenvector matrices, leading dimension ldz,
+ * stride `zstride`.  dtype: 0 = FP64, 1 = FP32 (then A, w, Z are float). */
+mbd_status mbd_eigh(mbd_ctx *ctx, int32_t dtype, int32_t n, int32_t nbatch, void *A, int32_t lda,
+                    int64_t stride, void *w, void *Z, int32_t ldz, int64_t zstride);
+
+/* Measure the launch-shape choices of the path for the problem sizes given
+ * (HOST array sizes[nsizes] of matrix orders) and store the fastest in the
+ * context; if table_json_path is non-NULL the table is written there.  An
+ * existing table can be loaded with mbd_load_tuning. */
+mbd_status mbd_autotune(mbd_ctx *ctx, const int32_t *sizes, int32_t nsizes, const char *table_json_path);
+mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
+
+/* (code, origin, message) of the last error on the context; returns code.
+ * origin and message stay valid until the next call on the context. */
+int mbd_last_error(const mbd_ctx *ctx, const char **origin, const char **message);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,486 @@
+// Host runtime and C ABI of libmbd_hip.so (declared in include/mbd.h):
+// context, device workspaces, validation, and the orchestration of the MBD
+// stages on one stream.
+#include "mbd.h"
+#include "mbd_internal.h"
+#include "mbd_kernels.h"
+#include "mbd_sys.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+struct mbd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mbd_precision prec = MBD_FP64;
+    std::map<std::string, std::pair<void*, size_t>> bufs;
+    size_t total = 0, limit = 0;
+    int err_code = 0;
+    std::string err_origin, err_msg;
+};
+
+namespace {
+
+mbd_status fail(mbd_ctx* c, mbd_status code, const char* origin, const std::string& msg) {
+    if (c) {
+        c->err_code = (int)code;
+        c->err_origin = origin;
+        c->err_msg = msg;
+    }
+    return code;
+}
+
+#define HIPCHK(expr, origin)                                                         \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) return fail(c, MBD_ERR_DEVICE, origin, hipGetErrorString(e_)); \
+    } while (0)
+
+// Named, growable device buffer.  Returns nullptr (and records the error) on
+// allocation failure or when MBD_WORKSPACE_LIMIT would be exceeded.
+void* ws(mbd_ctx* c, const char* name, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    auto it = c->bufs.find(name);
+    if (it != c->bufs.end() && it->second.second >= bytes) return it->second.first;
+    size_t old = it != c->bufs.end() ? it->second.second : 0;
+    if (c->limit && c->total - old + bytes > c->limit) {
+        fail(c, MBD_ERR_OUT_OF_MEMORY, "workspace", std::string("workspace limit exceeded for ") + name);
+        return nullptr;
+    }
+    if (it != c->bufs.end()) {
+        hipStreamSynchronize(c->stream);
+        hipFree(it->second.first);
+        c->total -= old;
+        c->bufs.erase(it);
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        fail(c, MBD_ERR_OUT_OF_MEMORY, "workspace", std::string("hipMalloc failed for ") + name);
+        return nullptr;
+    }
+    c->bufs[name] = {p, bytes};
+    c->total += bytes;
+    return p;
+}
+
+template <typename T>
+T* wsT(mbd_ctx* c, const std::string& name, size_t count) {
+    return (T*)ws(c, name.c_str(), count * sizeof(T));
+}
+
+template <typename T> const char* tname();
+template <> const char* tname<double>() { return "d"; }
+template <> const char* tname<float>() { return "f"; }
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+struct EigResult {
+    int src;  // which D&C buffer holds the vectors
+};
+
+// Full dense symmetric eigensolver on a batch: reduction, D&C, back-transform.
+template <typename T>
+mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int nbatch, bool vectors, T* w_out,
+                   long long sW, MatBatch<T>* Xout) {
+    const std::string t = tname<T>();
+    const hipStream_t st = c->stream;
+    const int nbk = (nmax + 63) / 64;
+    const int ldz = round_up(nmax, 64);
+    const long long sZ = (long long)ldz * nmax;
+    // --- reduction workspace
+    SytrdWs<T> sw;
+    sw.A = A; sw.ns = ns; sw.nmax = nmax; sw.nbk_max = nbk; sw.maxchunk = nbk;
+    sw.ldp = round_up(nmax, 64);
+    sw.sP = (long long)sw.ldp * SYTRD_NBP;
+    sw.Vp = wsT<T>(c, "Vp" + t, sw.sP * nbatch);
+    sw.Wp = wsT<T>(c, "Wp" + t, sw.sP * nbatch);
+    sw.sC = nmax; sw.colbuf = wsT<T>(c, "colbuf" + t, (size_t)nmax * nbatch);
+    sw.sNP = nbk; sw.normpart = wsT<T>(c, "normpart" + t, (size_t)nbk * nbatch);
+    sw.sP1 = (long long)nbk * nbk * 64; sw.P1 = wsT<T>(c, "P1" + t, sw.sP1 * nbatch);
+    sw.sP2 = (long long)nbk * nbk * 64; sw.P2 = wsT<T>(c, "P2" + t, sw.sP2 * nbatch);
+    sw.sPS = (long long)nbk * 2 * SYTRD_NBP; sw.PS = wsT<T>(c, "PS" + t, sw.sPS * nbatch);
+    sw.sPV = (long long)nbk * nbk; sw.PV = wsT<T>(c, "PV" + t, sw.sPV * nbatch);
+    sw.sD = nmax;
+    sw.d = wsT<T>(c, "d" + t, (size_t)nmax * nbatch);
+    sw.e = wsT<T>(c, "e" + t, (size_t)nmax * nbatch);
+    sw.tau = wsT<T>(c, "tau" + t, (size_t)nmax * nbatch);
+    if (!sw.Vp || !sw.Wp || !sw.colbuf || !sw.normpart || !sw.P1 || !sw.P2 || !sw.PS || !sw.PV || !sw.d ||
+        !sw.e || !sw.tau)
+        return (mbd_status)c->err_code;
+    sytrd_launch<T>(sw, nbatch, nmax, st);
+    HIPCHK(hipGetLastError(), "sytrd");
+
+    // --- divide and conquer
+    StedcWs<T> dw;
+    dw.ns = ns; dw.nmax = nmax; dw.d_in = sw.d; dw.e_in = sw.e; dw.sDin = nmax;
+    dw.sV = nmax;
+    const size_t nv = (size_t)nmax * nbatch;
+    T* tv[12];
+    const char* tn[12] = {"D", "E", "ds", "zs", "dn", "zn", "mu", "lam", "zh", "rho", "rc", "rs"};
+    for (int k = 0; k < 12; k++) {
+        tv[k] = wsT<T>(c, std::string("dc_") + tn[k] + t, nv);
+        if (!tv[k]) return (mbd_status)c->err_code;
+    }
+    dw.D = tv[0]; dw.E = tv[1]; dw.ds = tv[2]; dw.zs = tv[3]; dw.dn = tv[4]; dw.zn = tv[5];
+    dw.mu = tv[6]; dw.lam = tv[7]; dw.zh = tv[8]; dw.rho = tv[9]; dw.rc = tv[10]; dw.rs = tv[11];
+    int* iv[10];
+    const char* in[10] = {"perm", "ndpos", "dfpos", "org", "outnd", "outdf", "rp", "rq", "Kcnt", "rotcnt"};
+    for (int k = 0; k < 10; k++) {
+        iv[k] = wsT<int>(c, std::string("dc_") + in[k], nv);
+        if (!iv[k]) return (mbd_status)c->err_code;
+    }
+    dw.perm = iv[0]; dw.ndpos = iv[1]; dw.dfpos = iv[2]; dw.org = iv[3]; dw.outnd = iv[4]; dw.outdf = iv[5];
+    dw.rp = iv[6]; dw.rq = iv[7]; dw.Kcnt = iv[8]; dw.rotcnt = iv[9];
+    dw.scale = wsT<T>(c, "dc_scale" + t, nbatch);
+    dw.Z0 = {wsT<T>(c, "Z0" + t, (size_t)sZ * nbatch), ldz, sZ};
+    dw.Z1 = {wsT<T>(c, "Z1" + t, (size_t)sZ * nbatch), ldz, sZ};
+    dw.U = {wsT<T>(c, "U" + t, (size_t)sZ * nbatch), ldz, sZ};
+    if (!dw.scale || !dw.Z0.p || !dw.Z1.p || !dw.U.p) return (mbd_status)c->err_code;
+    dw.w_out = w_out; dw.sW = sW;
+    const int src = stedc_launch<T>(dw, nbatch, nmax, st);
+    HIPCHK(hipGetLastError(), "stedc");
+    MatBatch<T> Z = src ? dw.Z1 : dw.Z0;
+
+    if (vectors) {
+        OrmtrWs<T> ow;
+        const int nsplit = (nmax + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
+        ow.A = A; ow.tau = sw.tau; ow.sD = nmax; ow.ns = ns; ow.X = Z; ow.nmax = nmax;
+        ow.sG = (long long)nsplit * 4096; ow.Gpart = wsT<T>(c, "Gpart" + t, ow.sG * nbatch);
+        ow.sT = 4096; ow.Tm = wsT<T>(c, "Tm" + t, (size_t)4096 * nbatch);
+        ow.sYp = (long long)nsplit * 64 * nmax; ow.Ypart = wsT<T>(c, "Ypart" + t, ow.sYp * nbatch);
+        ow.sY = (long long)64 * nmax; ow.Y = wsT<T>(c, "Yb" + t, ow.sY * nbatch);
+        if (!ow.Gpart || !ow.Tm || !ow.Ypart || !ow.Y) return (mbd_status)c->err_code;
+        ormtr_launch<T>(ow, nbatch, nmax, st);
+        HIPCHK(hipGetLastError(), "ormtr");
+    }
+    if (Xout) *Xout = Z;
+    return MBD_OK;
+}
+
+bool finite_ok(double x) { return std::isfinite(x); }
+
+// Validates the host-visible parts of a system.
+mbd_status check_system(mbd_ctx* c, const mbd_system* s, unsigned want, const mbd_result* o, bool allow_periodic) {
+    if (!s || !o) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "null system or result");
+    if (s->n_atoms < 1) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "n_atoms must be >= 1");
+    if (!s->coords || !s->alpha0 || !s->omega_or_c6 || !s->rvdw)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "null input array");
+    if (!(s->beta >= 0.0) || !finite_ok(s->beta))
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "beta must be finite and >= 0");
+    if (!(s->a > 0.0) || !finite_ok(s->a)) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "a must be > 0");
+    if (s->param_kind != MBD_PARAM_OMEGA && s->param_kind != MBD_PARAM_C6)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "unknown param_kind");
+    if (want & ~255u) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "unknown want bits");
+    if ((want & MBD_WANT_ENERGY) && !o->energy) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "energy output is NULL");
+    if ((want & MBD_WANT_GRAD_COORDS) && !o->grad_coords)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "grad_coords output is NULL");
+    if ((want & MBD_WANT_GRAD_ALPHA0) && !o->grad_alpha0)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "grad_alpha0 output is NULL");
+    if ((want & MBD_WANT_GRAD_OMEGA) && !o->grad_omega_or_c6)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "grad_omega_or_c6 output is NULL");
+    if ((want & MBD_WANT_GRAD_RVDW) && !o->grad_rvdw)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "grad_rvdw output is NULL");
+    if ((want & MBD_WANT_GRAD_LATTICE) && !o->grad_lattice)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "grad_lattice output is NULL");
+    if ((want & MBD_WANT_EIGVALS) && !o->eigvals) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "eigvals output is NULL");
+    if ((want & MBD_WANT_ERRORS) && !o->errors) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "errors output is NULL");
+    if (s->lattice) {
+        if (!allow_periodic) return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate_batch", "periodic systems are evaluated one at a time");
+        if (want & MBD_WANT_GRAD_RVDW)
+            return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate", "grad_rvdw is for finite systems");
+    } else if (want & MBD_WANT_GRAD_LATTICE) {
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "grad_lattice needs a lattice");
+    }
+    return MBD_OK;
+}
+
+SysDesc make_desc(const mbd_system* s, unsigned want, const mbd_result* o) {
+    SysDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.coords = s->coords; d.alpha0 = s->alpha0; d.omega_or_c6 = s->omega_or_c6; d.rvdw = s->rvdw;
+    d.N = s->n_atoms; d.param_kind = (int)s->param_kind; d.beta = s->beta; d.a = s->a;
+    d.energy = (want & MBD_WANT_ENERGY) ? o->energy : nullptr;
+    d.grad_coords = (want & MBD_WANT_GRAD_COORDS) ? o->grad_coords : nullptr;
+    d.grad_alpha0 = (want & MBD_WANT_GRAD_ALPHA0) ? o->grad_alpha0 : nullptr;
+    d.grad_omega = (want & MBD_WANT_GRAD_OMEGA) ? o->grad_omega_or_c6 : nullptr;
+    d.grad_rvdw = (want & MBD_WANT_GRAD_RVDW) ? o->grad_rvdw : nullptr;
+    d.grad_lattice = (want & MBD_WANT_GRAD_LATTICE) ? o->grad_lattice : nullptr;
+    d.eigvals = (want & MBD_WANT_EIGVALS) ? o->eigvals : nullptr;
+    d.errors = (want & MBD_WANT_ERRORS) ? o->errors : nullptr;
+    return d;
+}
+
+__global__ void grad_gate_kernel(const unsigned* status, int nsys, SysDesc* sd) {
+    // systems whose evaluation failed keep their gradient outputs untouched
+    const int s = blockIdx.x * 64 + threadIdx.x;
+    if (s >= nsys || status[s] == 0) return;
+    sd[s].grad_coords = nullptr; sd[s].grad_alpha0 = nullptr; sd[s].grad_omega = nullptr;
+    sd[s].grad_rvdw = nullptr; sd[s].grad_lattice = nullptr;
+    sd[s].N = 0;
+}
+
+// Finite systems (one or a batch), all stages on the context stream.
+mbd_status run_finite(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::vector<int>& codes) {
+    const hipStream_t st = c->stream;
+    const int nsys = (int)sds.size();
+    int Nmax = 0, ntot = 0;
+    for (auto& d : sds) {
+        d.atom_off = ntot;
+        ntot += d.N;
+        Nmax = std::max(Nmax, d.N);
+        d.weight = 0.5;
+        d.embed = 0;
+    }
+    for (int s = 0; s < nsys; s++) { sds[s].mat0 = s; sds[s].nmat = 1; }
+    const int nmax = 3 * Nmax;
+    const int ld = round_up(nmax, 64);
+    const long long stride = (long long)ld * nmax;
+    const bool grads = (want & (MBD_WANT_GRAD_COORDS | MBD_WANT_GRAD_ALPHA0 | MBD_WANT_GRAD_OMEGA |
+                                MBD_WANT_GRAD_RVDW)) != 0;
+    const bool fp32 = c->prec == MBD_FP32_REFINED;
+
+    SysDesc* sd_dev = (SysDesc*)ws(c, "sysdesc", sizeof(SysDesc) * nsys);
+    int* ns_dev = wsT<int>(c, "ns", nsys);
+    unsigned* status = wsT<unsigned>(c, "status", nsys);
+    double* lmin = wsT<double>(c, "lmin", nsys);
+    double* om = wsT<double>(c, "om", ntot);
+    double* cc = wsT<double>(c, "cc", ntot);
+    double* lam = wsT<double>(c, "lam64", (size_t)nmax * nsys);
+    double* sc = wsT<double>(c, "sc64", (size_t)nmax * nsys);
+    MatBatch<double> A64 = {wsT<double>(c, "A64", (size_t)stride * nsys), ld, stride};
+    MatBatch<float> A32 = {nullptr, ld, stride};
+    if (fp32) A32.p = wsT<float>(c, "A32", (size_t)stride * nsys);
+    if (!sd_dev || !ns_dev || !status || !lmin || !om || !cc || !lam || !sc || !A64.p || (fp32 && !A32.p))
+        return (mbd_status)c->err_code;
+    std::vector<int> nsh(nsys);
+    for (int s = 0; s < nsys; s++) nsh[s] = 3 * sds[s].N;
+    HIPCHK(hipMemcpyAsync(sd_dev, sds.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st), "upload");
+    fill_u32_launch(st, status, nsys, 0u);
+    mbd_prep_launch(st, sd_dev, nsys, Nmax, om, cc, status);
+    mbd_assemble_finite_launch(st, sd_dev, nsys, Nmax, om, cc, A64, A32, status);
+    HIPCHK(hipGetLastError(), "assemble");
+
+    MatBatch<double> X;
+    std::vector<double> stats_h;
+    double* stats = nullptr;
+    if (!fp32) {
+        mbd_status r = run_eig<double>(c, A64, ns_dev, nmax, nsys, grads, lam, nmax, &X);
+        if (r != MBD_OK) return r;
+    } else {
+        float* lam32 = wsT<float>(c, "lam32", (size_t)nmax * nsys);
+        if (!lam32) return (mbd_status)c->err_code;
+        MatBatch<float> X32;
+        mbd_status r = run_eig<float>(c, A32, ns_dev, nmax, nsys, true, lam32, nmax, &X32);
+        if (r != MBD_OK) return r;
+        // one Ogita-Aishima step in FP64 against the FP64 Q held in A64
+        MatBatch<double> Xd = {wsT<double>(c, "oaX", (size_t)stride * nsys), ld, stride};
+        MatBatch<double> Y = {wsT<double>(c, "oaY", (size_t)stride * nsys), ld, stride};
+        MatBatch<double> S = {wsT<double>(c, "oaS", (size_t)stride * nsys), ld, stride};
+        double* colpart = wsT<double>(c, "oacol", (size_t)4 * nmax * nsys);
+        stats = wsT<double>(c, "oastats", (size_t)4 * nsys);
+        if (!Xd.p || !Y.p || !S.p || !colpart || !stats) return (mbd_status)c->err_code;
+        MatBatch<double> G = Y;  // G = X^T X lives in Y until Y = Q X is needed... (see below)
+        oa_f2d_launch(st, ns_dev, nmax, nsys, X32, Xd);
+        // Y = Q X
+        gemm_batched<double>(st, false, false, ns_dev, nmax, nsys, A64.p, ld, stride, Xd.p, ld, stride, Y.p, ld,
+                             stride, 1.0, 0.0, false);
+        // S = X^T Y
+        gemm_batched<double>(st, true, false, ns_dev, nmax, nsys, Xd.p, ld, stride, Y.p, ld, stride, S.p, ld,
+                             stride, 1.0, 0.0, false);
+        // G = X^T X (lower) into A64 (Q no longer needed)
+        G = A64;
+        gemm_batched<double>(st, true, false, ns_dev, nmax, nsys, Xd.p, ld, stride, Xd.p, ld, stride, G.p, ld,
+                             stride, 1.0, 0.0, true);
+        oa_stats_launch(st, ns_dev, nmax, nsys, S, G, lam, nmax, colpart, stats);
+        oa_update_launch(st, ns_dev, nmax, nsys, S, G, lam, nmax, stats);
+        // X' = X + X E  (into Y)
+        copy_mat_launch(st, ns_dev, nmax, nsys, Xd, Y);
+        gemm_batched<double>(st, false, false, ns_dev, nmax, nsys, Xd.p, ld, stride, S.p, ld, stride, Y.p, ld,
+                             stride, 1.0, 1.0, false);
+        HIPCHK(hipGetLastError(), "refine");
+        X = Y;
+    }
+    mbd_energy_launch(st, sd_dev, nsys, ns_dev, lam, nmax, om, status, lmin);
+    HIPCHK(hipGetLastError(), "energy");
+    if (grads) {
+        hipLaunchKernelGGL(grad_gate_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, status, nsys, sd_dev);
+        mbd_invsqrt4_launch(st, ns_dev, nmax, nsys, lam, nmax, sc);
+        MatBatch<double> M = A64;
+        if (fp32) M = {wsT<double>(c, "oaS", (size_t)stride * nsys), ld, stride};  // S (E) is free now
+        mbd_inv_sqrt_launch(st, ns_dev, nmax, nsys, X, sc, nmax, M);
+        mbd_mirror_launch(st, ns_dev, nmax, nsys, M);
+        mbd_grad_finite_launch(st, sd_dev, nsys, Nmax, om, cc, M);
+        HIPCHK(hipGetLastError(), "gradients");
+    }
+    std::vector<unsigned> sth(nsys);
+    HIPCHK(hipMemcpyAsync(sth.data(), status, sizeof(unsigned) * nsys, hipMemcpyDeviceToHost, st), "status");
+    if (stats) {
+        stats_h.resize(4 * nsys);
+        HIPCHK(hipMemcpyAsync(stats_h.data(), stats, sizeof(double) * 4 * nsys, hipMemcpyDeviceToHost, st), "status");
+    }
+    HIPCHK(hipStreamSynchronize(st), "synchronize");
+    codes.assign(nsys, MBD_OK);
+    for (int s = 0; s < nsys; s++) {
+        if (sth[s] & (MBD_ST_BAD_INPUT | MBD_ST_COINCIDENT)) codes[s] = MBD_ERR_INVALID_ARGUMENT;
+        else if (sth[s] & MBD_ST_COLLAPSE) codes[s] = MBD_ERR_NEGATIVE_EIGENVALUE;
+        if (sds[s].errors && codes[s] != MBD_ERR_INVALID_ARGUMENT) {
+            double e3[3] = {0.0, 0.0, 0.0};
+            if (stats) { e3[0] = stats_h[4 * s + 1]; e3[1] = 1.0; e3[2] = stats_h[4 * s]; }
+            HIPCHK(hipMemcpy(sds[s].errors + 1, e3, sizeof(e3), hipMemcpyHostToDevice), "errors");
+        }
+    }
+    return MBD_OK;
+}
+
+mbd_status code_message(mbd_ctx* c, int code, const char* origin) {
+    if (code == MBD_OK) return MBD_OK;
+    if (code == MBD_ERR_INVALID_ARGUMENT)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, origin, "non-finite or non-positive per-atom input, or coincident atoms");
+    if (code == MBD_ERR_NEGATIVE_EIGENVALUE)
+        return fail(c, MBD_ERR_NEGATIVE_EIGENVALUE, origin, "Q has a non-positive eigenvalue (dipole collapse)");
+    return fail(c, (mbd_status)code, origin, "evaluation failed");
+}
+
+}  // namespace
+
+extern "C" {
+
+mbd_status mbd_create(mbd_ctx** ctx, int device, mbd_precision prec, void* hip_stream) {
+    if (!ctx) return MBD_ERR_INVALID_ARGUMENT;
+    *ctx = nullptr;
+    if (prec != MBD_FP64 && prec != MBD_FP32_REFINED) return MBD_ERR_INVALID_ARGUMENT;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return MBD_ERR_DEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return MBD_ERR_DEVICE;
+    mbd_ctx* c = new mbd_ctx();
+    c->device = device;
+    c->prec = prec;
+    c->stream = (hipStream_t)hip_stream;
+    const char* lim = std::getenv("MBD_WORKSPACE_LIMIT");
+    if (lim) c->limit = (size_t)std::strtoull(lim, nullptr, 10);
+    *ctx = c;
+    return MBD_OK;
+}
+
+mbd_status mbd_destroy(mbd_ctx* c) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto& kv : c->bufs) hipFree(kv.second.first);
+    delete c;
+    return MBD_OK;
+}
+
+mbd_status mbd_set_stream(mbd_ctx* c, void* hip_stream) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    hipStreamSynchronize(c->stream);
+    c->stream = (hipStream_t)hip_stream;
+    return MBD_OK;
+}
+
+mbd_status mbd_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_result* out) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    c->err_code = 0;
+    mbd_status r = check_system(c, s, want, out, true);
+    if (r != MBD_OK) return r;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_evaluate", "hipSetDevice");
+    if (s->lattice) return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate", "periodic systems not available in this build");
+    std::vector<SysDesc> sds(1, make_desc(s, want, out));
+    std::vector<int> codes;
+    r = run_finite(c, sds, want, codes);
+    if (r != MBD_OK) return r;
+    return code_message(c, codes[0], "mbd_evaluate");
+}
+
+mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, unsigned want, mbd_result* out,
+                              int32_t* status) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    c->err_code = 0;
+    if (n_sys < 1 || !sys || !out || !status)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate_batch", "bad batch arguments");
+    std::vector<SysDesc> sds(n_sys);
+    for (int i = 0; i < n_sys; i++) {
+        mbd_status r = check_system(c, &sys[i], want, &out[i], false);
+        if (r != MBD_OK) return r;
+        sds[i] = make_desc(&sys[i], want, &out[i]);
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_evaluate_batch", "hipSetDevice");
+    std::vector<int> codes;
+    mbd_status r = run_finite(c, sds, want, codes);
+    if (r != MBD_OK) return r;
+    mbd_status first = MBD_OK;
+    for (int i = 0; i < n_sys; i++) {
+        status[i] = codes[i];
+        if (codes[i] != MBD_OK && first == MBD_OK) first = (mbd_status)codes[i];
+    }
+    if (first != MBD_OK) return code_message(c, first, "mbd_evaluate_batch");
+    return MBD_OK;
+}
+
+mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* A, int32_t lda, int64_t stride,
+                    void* w, void* Z, int32_t ldz, int64_t zstride) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    c->err_code = 0;
+    if (n < 1 || nbatch < 1 || !A || !w || lda < n || stride < (int64_t)lda * n || (dtype != 0 && dtype != 1) ||
+        (Z && (ldz < n || zstride < (int64_t)ldz * n)))
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_eigh", "bad sizes or pointers");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_eigh", "hipSetDevice");
+    std::vector<int> nsh(nbatch, n);
+    int* ns_dev = wsT<int>(c, "eigh_ns", nbatch);
+    if (!ns_dev) return (mbd_status)c->err_code;
+    HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nbatch, hipMemcpyHostToDevice, c->stream), "upload");
+    mbd_status r;
+    if (dtype == 0) {
+        MatBatch<double> Ab = {(double*)A, lda, (long long)stride}, X;
+        r = run_eig<double>(c, Ab, ns_dev, n, nbatch, Z != nullptr, (double*)w, n, &X);
+        if (r == MBD_OK && Z)
+            HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, X.p, sizeof(double) * X.ld, sizeof(double) * n,
+                                    (size_t)n * 1, hipMemcpyDeviceToDevice, c->stream), "copy");
+        if (r == MBD_OK && Z && nbatch > 1)
+            for (int b = 1; b < nbatch; b++)
+                HIPCHK(hipMemcpy2DAsync((double*)Z + (long long)b * zstride, sizeof(double) * ldz, X.p + (long long)b * X.stride,
+                                        sizeof(double) * X.ld, sizeof(double) * n, n, hipMemcpyDeviceToDevice, c->stream),
+                       "copy");
+    } else {
+        MatBatch<float> Ab = {(float*)A, lda, (long long)stride}, X;
+        r = run_eig<float>(c, Ab, ns_dev, n, nbatch, Z != nullptr, (float*)w, n, &X);
+        if (r == MBD_OK && Z)
+            for (int b = 0; b < nbatch; b++)
+                HIPCHK(hipMemcpy2DAsync((float*)Z + (long long)b * zstride, sizeof(float) * ldz, X.p + (long long)b * X.stride,
+                                        sizeof(float) * X.ld, sizeof(float) * n, n, hipMemcpyDeviceToDevice, c->stream),
+                       "copy");
+    }
+    if (r != MBD_OK) return r;
+    HIPCHK(hipStreamSynchronize(c->stream), "mbd_eigh");
+    return MBD_OK;
+}
+
+mbd_status mbd_autotune(mbd_ctx* c, const int32_t*, int32_t, const char*) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    return fail(c, MBD_ERR_UNSUPPORTED, "mbd_autotune", "not available in this build");
+}
+
+mbd_status mbd_load_tuning(mbd_ctx* c, const char*) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    return fail(c, MBD_ERR_UNSUPPORTED, "mbd_load_tuning", "not available in this build");
+}
+
+int mbd_last_error(const mbd_ctx* c, const char** origin, const char** message) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    if (origin) *origin = c->err_origin.c_str();
+    if (message) *message = c->err_msg.c_str();
+    return c->err_code;
+}
+
+}  // extern "C"

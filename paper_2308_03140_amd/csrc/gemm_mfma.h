@@ -1,0 +1,170 @@
+// Tiled matrix-core (MFMA) GEMM core shared by every dense contraction of the
+// MBD path: the symmetric rank-2k trailing update of the Householder
+// reduction, the compact-WY back-transform, the divide-and-conquer merges,
+// Q^{-1/2} = X diag(lam^{-1/2}) X^T and the Ogita-Aishima refinement products.
+//
+// One 256-thread workgroup computes a 64x64 tile of C with 4 wavefronts in a
+// 2x2 arrangement, each wavefront owning 32x32 = 2x2 blocks of the 16x16x4
+// MFMA (v_mfma_f64_16x16x4f64 or v_mfma_f32_16x16x4f32, FP32 accumulation for
+// FP32).  K is staged through LDS in slabs of 16 with register prefetch of the
+// next slab.  The problem object P supplies the tile map, element loaders and
+// the epilogue, so masked Householder vectors, index-mapped eigenvector
+// columns, batch strides and triangle-only tile sets need no copies.
+#pragma once
+#include "mbd_internal.h"
+
+template <typename T> struct mfma4;
+template <> struct mfma4<double> { typedef double v __attribute__((ext_vector_type(4))); };
+template <> struct mfma4<float> { typedef float v __attribute__((ext_vector_type(4))); };
+
+__device__ __forceinline__ mfma4<double>::v mfma16x16x4(double a, double b, mfma4<double>::v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mfma4<float>::v mfma16x16x4(float a, float b, mfma4<float>::v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+#define GEMM_BM 64
+#define GEMM_BN 64
+#define GEMM_BK 16
+#define GEMM_PAD 4
+
+// Tile descriptor returned by P::tile()
+struct GemmTile {
+    int batch, m0, n0, K;
+    int o, k;  // problem-specific offsets (e.g. merge origin and order)
+};
+
+template <typename T, class P>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(P p) {
+    __shared__ T As[2][GEMM_BK][GEMM_BM + GEMM_PAD];
+    __shared__ T Bs[2][GEMM_BK][GEMM_BN + GEMM_PAD];
+    GemmTile t;
+    if (!p.tile(blockIdx.x, blockIdx.y, blockIdx.z, t)) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    typename mfma4<T>::v acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = typename mfma4<T>::v{0, 0, 0, 0};
+
+    T ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int ii = 0; ii < 4; ii++) {
+            int m, k;
+            if (P::A_M_CONTIG) { m = tid & 63; k = (tid >> 6) + 4 * ii; }
+            else { k = tid & 15; m = (tid >> 4) + 16 * ii; }
+            ra[ii] = p.a(t, t.m0 + m, k0 + k);
+            int n, kb;
+            if (P::B_N_CONTIG) { n = tid & 63; kb = (tid >> 6) + 4 * ii; }
+            else { kb = tid & 15; n = (tid >> 4) + 16 * ii; }
+            rb[ii] = p.b(t, k0 + kb, t.n0 + n);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int ii = 0; ii < 4; ii++) {
+            int m, k;
+            if (P::A_M_CONTIG) { m = tid & 63; k = (tid >> 6) + 4 * ii; }
+            else { k = tid & 15; m = (tid >> 4) + 16 * ii; }
+            As[buf][k][m] = ra[ii];
+            int n, kb;
+            if (P::B_N_CONTIG) { n = tid & 63; kb = (tid >> 6) + 4 * ii; }
+            else { kb = tid & 15; n = (tid >> 4) + 16 * ii; }
+            Bs[buf][kb][n] = rb[ii];
+        }
+    };
+
+    const int nk = (t.K + GEMM_BK - 1) / GEMM_BK;
+    if (nk > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt++) {
+            const int buf = kt & 1;
+            if (kt + 1 < nk) gload((kt + 1) * GEMM_BK);
+#pragma unroll
+            for (int kk = 0; kk < GEMM_BK; kk += 4) {
+                T af[2], bf[2];
+#pragma unroll
+                for (int i = 0; i < 2; i++) af[i] = As[buf][kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 2; j++) bf[j] = Bs[buf][kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < 2; i++)
+#pragma unroll
+                    for (int j = 0; j < 2; j++) acc[i][j] = mfma16x16x4(af[i], bf[j], acc[i][j]);
+            }
+            if (kt + 1 < nk) sstore(buf ^ 1);
+            __syncthreads();
+        }
+    }
+    // 16x16 MFMA result layout: lane holds column (lane & 15), rows 4*(lane>>4) + r
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                int row = t.m0 + wm * 32 + i * 16 + ((lane >> 4) << 2) + r;
+                int col = t.n0 + wn * 32 + j * 16 + (lane & 15);
+                p.store(t, row, col, acc[i][j][r]);
+            }
+}
+
+// Lower-triangle tile enumeration: linear index -> (ti, tj) with ti >= tj.
+__device__ __forceinline__ void lower_tile(int lin, int& ti, int& tj) {
+    int r = (int)((sqrtf(8.0f * (float)lin + 1.0f) - 1.0f) * 0.5f);
+    while ((r + 1) * (r + 2) / 2 <= lin) r++;
+    while (r * (r + 1) / 2 > lin) r--;
+    ti = r;
+    tj = lin - r * (r + 1) / 2;
+}
+
+// General batched C = alpha op(A) op(B) + beta C over matrices of order ns[b]
+// (M, N, K derived from ns through the m/n/k multipliers and offsets).
+template <typename T, bool TA, bool TB>
+struct GemmGeneral {
+    static constexpr bool A_M_CONTIG = !TA;
+    static constexpr bool B_N_CONTIG = TB;
+    const T* A; int lda; long long sA;
+    const T* B; int ldb; long long sB;
+    T* C; int ldc; long long sC;
+    const int* ns;       // per-matrix order, or nullptr => fixed M,N,K
+    int M, N, K;         // used when ns == nullptr
+    T alpha, beta;
+    int lower_only;      // only tiles (and elements) with row >= col
+    int tiles_n;         // tiles along N (grid.x = tiles_m * tiles_n, or lower count)
+    __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
+        t.batch = bz;
+        int Mb = ns ? ns[bz] : M, Nb = ns ? ns[bz] : N, Kb = ns ? ns[bz] : K;
+        int ti, tj;
+        if (lower_only) lower_tile(bx, ti, tj);
+        else { ti = bx / tiles_n; tj = bx % tiles_n; }
+        t.m0 = ti * GEMM_BM; t.n0 = tj * GEMM_BN; t.K = Kb;
+        return t.m0 < Mb && t.n0 < Nb;
+    }
+    __device__ T a(const GemmTile& t, int m, int k) const {
+        int Mb = ns ? ns[t.batch] : M, Kb = t.K;
+        if (m >= Mb || k >= Kb) return T(0);
+        const T* Ab = A + (long long)t.batch * sA;
+        return TA ? Ab[k + (long long)m * lda] : Ab[m + (long long)k * lda];
+    }
+    __device__ T b(const GemmTile& t, int k, int n) const {
+        int Nb = ns ? ns[t.batch] : N, Kb = t.K;
+        if (n >= Nb || k >= Kb) return T(0);
+        const T* Bb = B + (long long)t.batch * sB;
+        return TB ? Bb[n + (long long)k * ldb] : Bb[k + (long long)n * ldb];
+    }
+    __device__ void store(const GemmTile& t, int m, int n, T v) const {
+        int Mb = ns ? ns[t.batch] : M, Nb = ns ? ns[t.batch] : N;
+        if (m >= Mb || n >= Nb) return;
+        if (lower_only && m < n) return;
+        T* Cb = C + (long long)t.batch * sC + m + (long long)n * ldc;
+        *Cb = (beta == T(0)) ? alpha * v : alpha * v + beta * (*Cb);
+    }
+};

@@ -1,0 +1,314 @@
+// MBD-specific kernels: input preparation, assembly of Q (finite systems),
+// the energy reduction, Q^{-1/2} from the eigenpairs and the adjoint
+// contraction for the gradients (paper Secs. 2.1, 2.4, 2.7).
+#include "mbd_internal.h"
+#include "gemm_mfma.h"
+#include "mbd_kernels.h"
+#include "mbd_sys.h"
+
+// ---------------------------------------------------------------------------
+// pair tensors
+// ---------------------------------------------------------------------------
+// bare dipole tensor T_ab = (delta_ab r^2 - 3 r_a r_b)/r^5 (eq:dipole, explicit
+// form) and the Fermi damping g = 1/(1 + exp(-a (r/(beta (Rv_i+Rv_j)) - 1)))
+// (eq:fermi-damping with s_R = beta, a = 6 for MBD: eq:mbd-lr-dipole)
+struct PairTD {
+    double T[6];      // xx yy zz xy xz yz
+    double g, omg, dg_dr, dg_dR0;
+    double d, inv_d;
+};
+
+__device__ __forceinline__ void fermi_damp(double d, double R0, double a, double& g, double& omg, double& dg_dr,
+                                           double& dg_dR0) {
+    if (R0 <= 0.0) { g = 1.0; omg = 0.0; dg_dr = 0.0; dg_dR0 = 0.0; return; }
+    const double x = a * (d / R0 - 1.0);
+    if (x >= 0.0) { const double e = exp(-x); g = 1.0 / (1.0 + e); omg = e / (1.0 + e); }
+    else { const double e = exp(x); g = e / (1.0 + e); omg = 1.0 / (1.0 + e); }
+    const double gg = g * omg;
+    dg_dr = a / R0 * gg;
+    dg_dR0 = -a * d / (R0 * R0) * gg;
+}
+
+__device__ __forceinline__ int sym_idx(int a, int b) {
+    // xx yy zz xy xz yz
+    if (a == b) return a;
+    const int s = a + b;  // 1: xy, 2: xz, 3: yz
+    return 2 + s;
+}
+
+// ---------------------------------------------------------------------------
+// input preparation and validation: om_i, c_i = om_i sqrt(alpha0_i)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mbd_prep_kernel(const SysDesc* sd, double* om, double* cc,
+                                                         unsigned* status) {
+    const int s = blockIdx.y;
+    const SysDesc& S = sd[s];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= S.N) return;
+    const double a0 = S.alpha0[i];
+    const double p = S.omega_or_c6[i];
+    const double rv = S.rvdw[i];
+    const double x = S.coords[3 * i], y = S.coords[3 * i + 1], z = S.coords[3 * i + 2];
+    bool ok = isfinite(a0) && isfinite(p) && isfinite(rv) && isfinite(x) && isfinite(y) && isfinite(z) &&
+              a0 > 0.0 && p > 0.0 && rv > 0.0;
+    double w = S.param_kind == 1 ? 4.0 * p / (3.0 * a0 * a0) : p;
+    if (!ok) { w = 1.0; atomicOr(&status[s], MBD_ST_BAD_INPUT); }
+    om[S.atom_off + i] = w;
+    cc[S.atom_off + i] = ok ? w * sqrt(a0) : 0.0;
+}
+
+// Q of eq:q-matrix, finite system, both triangles; optional FP32 copy.
+// 16x16 atom pairs per workgroup.
+__global__ __launch_bounds__(256) void mbd_assemble_finite_kernel(const SysDesc* sd, const double* om,
+                                                                    const double* cc, MatBatch<double> Q,
+                                                                    MatBatch<float> Q32, unsigned* status) {
+    const int s = blockIdx.z;
+    const SysDesc& S = sd[s];
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (i >= S.N || j >= S.N) return;
+    double* Qb = Q.at(s);
+    float* Qf = Q32.p ? Q32.at(s) : nullptr;
+    const long long ld = Q.ld, ldf = Q32.ld;
+    double v[3][3];
+    if (i == j) {
+        const double w = om[S.atom_off + i];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) v[a][b] = (a == b) ? w * w : 0.0;
+    } else {
+        const double* R = S.coords;
+        const double rx = R[3 * j] - R[3 * i], ry = R[3 * j + 1] - R[3 * i + 1], rz = R[3 * j + 2] - R[3 * i + 2];
+        const double r2 = rx * rx + ry * ry + rz * rz;
+        double d = sqrt(r2);
+        const bool coincident = !(d >= 1e-8);
+        if (coincident) { atomicOr(&status[s], MBD_ST_COINCIDENT); d = 1.0; }
+        const double inv_d = 1.0 / d;
+        const double inv3 = inv_d * inv_d * inv_d, inv5 = inv3 * inv_d * inv_d;
+        double g, omg, gd, gR;
+        fermi_damp(d, S.beta * (S.rvdw[i] + S.rvdw[j]), S.a, g, omg, gd, gR);
+        // coincident or invalid pairs contribute nothing, keeping Q finite
+        const double pre = coincident ? 0.0 : cc[S.atom_off + i] * cc[S.atom_off + j] * g;
+        const double r[3] = {rx, ry, rz};
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) v[a][b] = pre * ((a == b ? inv3 : 0.0) - 3.0 * r[a] * r[b] * inv5);
+    }
+    for (int b = 0; b < 3; b++)
+        for (int a = 0; a < 3; a++) {
+            const long long row = 3 * i + a, col = 3 * j + b;
+            Qb[row + col * ld] = v[a][b];
+            if (Qf) Qf[row + col * ldf] = (float)v[a][b];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// energy: E = w sum_k sqrt(lambda_k) - (3/2) sum_i omega_i  (eq:mbd-energy),
+// periodic systems average over their q matrices (eq:brillouin-int)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mbd_energy_kernel(const SysDesc* sd, const int* ns, const double* lam,
+                                                           long long sL, const double* om, unsigned* status,
+                                                           double* lmin_out) {
+    __shared__ double red[4];
+    const int s = blockIdx.x;
+    const SysDesc& S = sd[s];
+    double esum = 0.0, lmin = 1e300;
+    for (int q = 0; q < S.nmat; q++) {
+        const int b = S.mat0 + q;
+        const int n = ns[b];
+        const double* L = lam + (long long)b * sL;
+        double part = 0.0, mn = 1e300;
+        for (int k = threadIdx.x; k < n; k += 256) {
+            const double x = L[k];
+            mn = fmin(mn, x);
+            part += x > 0.0 ? sqrt(x) : 0.0;
+        }
+        part = block_sum256(part, red);
+        mn = -block_max256(-mn, red);
+        esum += S.weight * part;
+        lmin = fmin(lmin, mn);
+    }
+    double wsum = 0.0;
+    for (int i = threadIdx.x; i < S.N; i += 256) wsum += om[S.atom_off + i];
+    wsum = block_sum256(wsum, red);
+    if (threadIdx.x == 0) {
+        const bool collapse = !(lmin > 0.0);
+        if (collapse) atomicOr(&status[s], MBD_ST_COLLAPSE);
+        if (S.energy) *S.energy = collapse ? __longlong_as_double(0x7ff8000000000000LL) : esum - 1.5 * wsum;
+        lmin_out[s] = lmin;
+        if (S.errors) S.errors[0] = lmin;
+    }
+    if (S.eigvals) {
+        for (int q = 0; q < S.nmat; q++) {
+            const int b = S.mat0 + q;
+            const double* L = lam + (long long)b * sL;
+            const int n3 = 3 * S.N;
+            for (int k = threadIdx.x; k < n3; k += 256)
+                S.eigvals[(long long)q * n3 + k] = S.embed ? L[2 * k] : L[k];
+        }
+    }
+}
+
+// sc_k = lambda_k^{-1/4}, so that Q^{-1/2} = (X sc)(X sc)^T
+__global__ __launch_bounds__(256) void mbd_invsqrt4_kernel(const int* ns, const double* lam, long long sL,
+                                                             double* sc) {
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= ns[b]) return;
+    const double x = lam[(long long)b * sL + k];
+    sc[(long long)b * sL + k] = x > 0.0 ? 1.0 / sqrt(sqrt(x)) : 0.0;
+}
+
+// M = (X sc)(X sc)^T, lower tiles
+struct ScaledSyrkProb {
+    static constexpr bool A_M_CONTIG = true;
+    static constexpr bool B_N_CONTIG = true;
+    const int* ns; MatBatch<double> X; const double* sc; long long sL; MatBatch<double> M;
+    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
+        t.batch = bz;
+        int ti, tj;
+        lower_tile(bx, ti, tj);
+        t.m0 = ti * GEMM_BM; t.n0 = tj * GEMM_BN; t.K = ns[bz];
+        return t.m0 < ns[bz];
+    }
+    __device__ double a(const GemmTile& t, int m, int k) const {
+        const int n = ns[t.batch];
+        if (m >= n || k >= n) return 0.0;
+        return X.at(t.batch)[m + (long long)k * X.ld] * sc[(long long)t.batch * sL + k];
+    }
+    __device__ double b(const GemmTile& t, int k, int nn) const { return a(t, nn, k); }
+    __device__ void store(const GemmTile& t, int m, int nn, double v) const {
+        const int n = ns[t.batch];
+        if (m >= n || nn >= n || m < nn) return;
+        M.at(t.batch)[m + (long long)nn * M.ld] = v;
+    }
+};
+
+void mbd_inv_sqrt_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> X,
+                         const double* sc, long long sL, MatBatch<double> M) {
+    ScaledSyrkProb p;
+    p.ns = ns; p.X = X; p.sc = sc; p.sL = sL; p.M = M;
+    const int t = (nmax + 63) / 64;
+    hipLaunchKernelGGL((gemm_mfma_kernel<double, ScaledSyrkProb>), dim3(t * (t + 1) / 2, 1, nbatch), dim3(256), 0,
+                       st, p);
+}
+
+// copy the lower triangle to the upper one
+__global__ __launch_bounds__(256) void mbd_mirror_kernel(const int* ns, MatBatch<double> M) {
+    const int b = blockIdx.z;
+    const int n = ns[b];
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (c >= n || r >= c) return;
+    double* Mb = M.at(b);
+    Mb[r + (long long)c * M.ld] = Mb[c + (long long)r * M.ld];
+}
+
+// ---------------------------------------------------------------------------
+// adjoint contraction, finite systems.  With M = Q^{-1/2}:
+//   dE/dR_k   = -1/2 sum_j c_k c_j sum_ab M_{ka,jb} d/dr (g T_ab)(R_j - R_k)
+//   dE/dalpha_k = S_k / (4 alpha_k),  S_k = sum_j c_k c_j sum_ab M_{ka,jb} g T_ab
+//   dE/domega_k = S_k / (2 omega_k) + omega_k/2 sum_a M_{ka,ka} - 3/2
+//   dE/dRv_k  = sum_j 1/2 c_k c_j beta dg/dR0 sum_ab M_{ka,jb} T_ab
+// (eq:mbd-gradient as (1/4) Tr(Q^{-1/2} dQ/dX); C6 input by the chain rule
+// through 4 C6 = 3 omega alpha0^2).  One workgroup per atom k; M_{ka,jb} is
+// read from columns 3k+a (M symmetric), so the loads are contiguous in j.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mbd_grad_finite_kernel(const SysDesc* sd, const double* om,
+                                                                const double* cc, MatBatch<double> M) {
+    __shared__ double red[4];
+    const int s = blockIdx.z;
+    const SysDesc& S = sd[s];
+    const int k = blockIdx.x;
+    if (k >= S.N) return;
+    const double* Mb = M.at(s);
+    const long long ld = M.ld;
+    const double* R = S.coords;
+    const double ck = cc[S.atom_off + k];
+    double f0 = 0, f1 = 0, f2 = 0, Ssum = 0, Usum = 0;
+    for (int j = threadIdx.x; j < S.N; j += 256) {
+        if (j == k) continue;
+        const double r[3] = {R[3 * j] - R[3 * k], R[3 * j + 1] - R[3 * k + 1], R[3 * j + 2] - R[3 * k + 2]};
+        const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double d = sqrt(r2), inv_d = 1.0 / d;
+        const double inv3 = inv_d * inv_d * inv_d, inv5 = inv3 * inv_d * inv_d, inv7 = inv5 * inv_d * inv_d;
+        double g, omg, gd, gR0;
+        fermi_damp(d, S.beta * (S.rvdw[k] + S.rvdw[j]), S.a, g, omg, gd, gR0);
+        const double cj = cc[S.atom_off + j];
+        double m[3][3];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) m[a][b] = Mb[(3 * j + b) + (long long)(3 * k + a) * ld];
+        double mt = 0.0, fc[3] = {0, 0, 0};
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                const double Tab = (a == b ? inv3 : 0.0) - 3.0 * r[a] * r[b] * inv5;
+                mt += m[a][b] * Tab;
+                for (int c = 0; c < 3; c++) {
+                    double dT = 15.0 * r[a] * r[b] * r[c] * inv7;
+                    if (a == b) dT -= 3.0 * r[c] * inv5;
+                    if (a == c) dT -= 3.0 * r[b] * inv5;
+                    if (b == c) dT -= 3.0 * r[a] * inv5;
+                    fc[c] += m[a][b] * (gd * r[c] * inv_d * Tab + g * dT);
+                }
+            }
+        const double pc = ck * cj;
+        f0 += pc * fc[0]; f1 += pc * fc[1]; f2 += pc * fc[2];
+        Ssum += pc * g * mt;
+        Usum += 0.5 * pc * S.beta * gR0 * mt;
+    }
+    f0 = block_sum256(f0, red);
+    f1 = block_sum256(f1, red);
+    f2 = block_sum256(f2, red);
+    Ssum = block_sum256(Ssum, red);
+    Usum = block_sum256(Usum, red);
+    if (threadIdx.x == 0) {
+        double tr = 0.0;
+        for (int a = 0; a < 3; a++) tr += Mb[(3 * k + a) + (long long)(3 * k + a) * ld];
+        const double a0 = S.alpha0[k];
+        const double w = om[S.atom_off + k];
+        const double dEda = Ssum / (4.0 * a0);
+        const double dEdw = Ssum / (2.0 * w) + 0.5 * w * tr - 1.5;
+        if (S.grad_coords) {
+            S.grad_coords[3 * k] = -0.5 * f0;
+            S.grad_coords[3 * k + 1] = -0.5 * f1;
+            S.grad_coords[3 * k + 2] = -0.5 * f2;
+        }
+        if (S.param_kind == 1) {
+            // omega = 4 C6/(3 alpha0^2)
+            if (S.grad_alpha0) S.grad_alpha0[k] = dEda - 2.0 * w / a0 * dEdw;
+            if (S.grad_omega) S.grad_omega[k] = dEdw * w / S.omega_or_c6[k];
+        } else {
+            if (S.grad_alpha0) S.grad_alpha0[k] = dEda;
+            if (S.grad_omega) S.grad_omega[k] = dEdw;
+        }
+        if (S.grad_rvdw) S.grad_rvdw[k] = Usum;
+    }
+}
+
+void mbd_prep_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, double* om, double* cc,
+                     unsigned* status) {
+    hipLaunchKernelGGL(mbd_prep_kernel, dim3((Nmax + 255) / 256, nsys), dim3(256), 0, st, sd, om, cc, status);
+}
+
+void mbd_assemble_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,
+                                const double* cc, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status) {
+    const int g = (Nmax + 15) / 16;
+    hipLaunchKernelGGL(mbd_assemble_finite_kernel, dim3(g, g, nsys), dim3(256), 0, st, sd, om, cc, Q, Q32, status);
+}
+
+void mbd_energy_launch(hipStream_t st, const SysDesc* sd, int nsys, const int* ns, const double* lam, long long sL,
+                       const double* om, unsigned* status, double* lmin) {
+    hipLaunchKernelGGL(mbd_energy_kernel, dim3(nsys), dim3(256), 0, st, sd, ns, lam, sL, om, status, lmin);
+}
+
+void mbd_invsqrt4_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const double* lam, long long sL,
+                         double* sc) {
+    hipLaunchKernelGGL(mbd_invsqrt4_kernel, dim3((nmax + 255) / 256, nbatch), dim3(256), 0, st, ns, lam, sL, sc);
+}
+
+void mbd_mirror_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> M) {
+    hipLaunchKernelGGL(mbd_mirror_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, M);
+}
+
+void mbd_grad_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,
+                            const double* cc, MatBatch<double> M) {
+    hipLaunchKernelGGL(mbd_grad_finite_kernel, dim3(Nmax, 1, nsys), dim3(256), 0, st, sd, om, cc, M);
+}

@@ -1,0 +1,250 @@
+// Back-transformation X = H_0 H_1 ... H_{n-2} Z of the tridiagonal
+// eigenvectors Z to the eigenvectors C of Q (eq:diagonalization, paper
+// Sec. 2.1).  Reflectors are grouped in blocks of 64 in compact-WY form
+// H_b..H_{b+63} = I - V T V^T (T upper triangular) and applied from the last
+// block to the first:
+//   G = V^T V           split-K over 512-row chunks, partials summed in order
+//   T                   from G and tau (forward column recurrence), one WG
+//   Y = T (V^T X)       split-K V^T X on matrix cores, then T applied per column
+//   X -= V Y            matrix cores
+// V is read straight from the reduced matrix with the unit diagonal and the
+// zeros above it supplied by the loader.
+#include "mbd_internal.h"
+#include "gemm_mfma.h"
+#include "mbd_kernels.h"
+
+// element (r, i) of the reflector matrix
+template <typename T>
+__device__ __forceinline__ T hh_v(const T* A, long long ld, int r, int i, int nref) {
+    if (i >= nref || r <= i) return T(0);
+    if (r == i + 1) return T(1);
+    return A[r + (long long)i * ld];
+}
+
+// Gpart[split] = V(rows of chunk)^T V(rows of chunk), 64 x 64
+template <typename T>
+struct VtvProb {
+    static constexpr bool A_M_CONTIG = false;
+    static constexpr bool B_N_CONTIG = false;
+    MatBatch<T> A; const int* ns; int b0; T* Gpart; long long sG;
+    __device__ bool tile(int, int by, int bz, GemmTile& t) const {
+        t.batch = bz;
+        const int n = ns[bz];
+        const int nref = n - 1;
+        if (b0 >= nref) return false;
+        const int m = n - b0 - 1;          // rows b0+1 .. n-1
+        const int r0 = by * ORMTR_CHUNK;
+        if (r0 >= m) return false;
+        t.m0 = 0; t.n0 = 0;
+        t.K = min(ORMTR_CHUNK, m - r0);
+        t.o = b0 + 1 + r0;
+        t.k = by;
+        return true;
+    }
+    __device__ T a(const GemmTile& t, int jj, int kk) const {
+        if (kk >= t.K) return T(0);
+        const int n = ns[t.batch];
+        return hh_v(A.at(t.batch), A.ld, t.o + kk, b0 + jj, n - 1);
+    }
+    __device__ T b(const GemmTile& t, int kk, int jj) const { return a(t, jj, kk); }
+    __device__ void store(const GemmTile& t, int m, int nn, T v) const {
+        Gpart[(long long)t.batch * sG + (long long)t.k * 4096 + m + nn * 64] = v;
+    }
+};
+
+// T factor of the block: T(j,j) = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) G(0:j, j)
+template <typename T>
+__global__ __launch_bounds__(256) void ormtr_tfactor_kernel(OrmtrWs<T> w, int b0) {
+    __shared__ T G[64][65];
+    __shared__ T Tm[64][65];
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int nref = n - 1;
+    if (b0 >= nref) return;
+    const int m = n - b0 - 1;
+    const int nsplit = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
+    const T* Gp = w.Gpart + (long long)b * w.sG;
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+        T s = T(0);
+        for (int q = 0; q < nsplit; q++) s += Gp[(long long)q * 4096 + idx];
+        G[idx & 63][idx >> 6] = s;
+        Tm[idx & 63][idx >> 6] = T(0);
+    }
+    __syncthreads();
+    const T* tau = w.tau + (long long)b * w.sD;
+    for (int j = 0; j < 64; j++) {
+        const int i = b0 + j;
+        const T tj = i < nref ? tau[i] : T(0);
+        // z = T(0:j,0:j) G(0:j, j) for rows k < j
+        T z = T(0);
+        const int k = threadIdx.x;
+        if (k < j)
+            for (int l = k; l < j; l++) z += Tm[k][l] * G[l][j];
+        __syncthreads();
+        if (k < j) Tm[k][j] = -tj * z;
+        if (k == j) Tm[j][j] = tj;
+        __syncthreads();
+    }
+    T* To = w.Tm + (long long)b * w.sT;
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) To[idx] = Tm[idx & 63][idx >> 6];
+}
+
+// Ypart[split] = V^T X over the rows of the chunk, 64 x n
+template <typename T>
+struct VtxProb {
+    static constexpr bool A_M_CONTIG = false;
+    static constexpr bool B_N_CONTIG = false;
+    MatBatch<T> A; MatBatch<T> X; const int* ns; int b0; T* Ypart; long long sYp; int nmax;
+    __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
+        t.batch = bz;
+        const int n = ns[bz];
+        if (b0 >= n - 1) return false;
+        const int m = n - b0 - 1;
+        const int r0 = by * ORMTR_CHUNK;
+        if (r0 >= m) return false;
+        t.m0 = 0;
+        t.n0 = bx * GEMM_BN;
+        if (t.n0 >= n) return false;
+        t.K = min(ORMTR_CHUNK, m - r0);
+        t.o = b0 + 1 + r0;
+        t.k = by;
+        return true;
+    }
+    __device__ T a(const GemmTile& t, int jj, int kk) const {
+        if (kk >= t.K) return T(0);
+        return hh_v(A.at(t.batch), A.ld, t.o + kk, b0 + jj, ns[t.batch] - 1);
+    }
+    __device__ T b(const GemmTile& t, int kk, int c) const {
+        if (kk >= t.K || c >= ns[t.batch]) return T(0);
+        return X.at(t.batch)[(t.o + kk) + (long long)c * X.ld];
+    }
+    __device__ void store(const GemmTile& t, int jj, int c, T v) const {
+        if (c >= ns[t.batch]) return;
+        Ypart[(long long)t.batch * sYp + (long long)t.k * 64 * nmax + jj + (long long)c * 64] = v;
+    }
+};
+
+// Y(:, c) = T * sum_split Ypart(:, c)
+template <typename T>
+__global__ __launch_bounds__(256) void ormtr_ty_kernel(OrmtrWs<T> w, int b0) {
+    __shared__ T Ts[64][65];
+    __shared__ T ys[64][65];
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    if (b0 >= n - 1) return;
+    const int c0 = blockIdx.x * 64;
+    if (c0 >= n) return;
+    const int m = n - b0 - 1;
+    const int nsplit = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
+    const T* To = w.Tm + (long long)b * w.sT;
+    const T* Yp = w.Ypart + (long long)b * w.sYp;
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+        const int jj = idx & 63, cc = idx >> 6;
+        Ts[jj][cc] = To[idx];
+        T s = T(0);
+        if (c0 + cc < n)
+            for (int q = 0; q < nsplit; q++) s += Yp[(long long)q * 64 * w.nmax + jj + (long long)(c0 + cc) * 64];
+        ys[cc][jj] = s;
+    }
+    __syncthreads();
+    T* Y = w.Y + (long long)b * w.sY;
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+        const int jj = idx & 63, cc = idx >> 6;
+        if (c0 + cc >= n) continue;
+        T s = T(0);
+        for (int l = jj; l < 64; l++) s += Ts[jj][l] * ys[cc][l];
+        Y[jj + (long long)(c0 + cc) * 64] = s;
+    }
+}
+
+// X(b0+1:n, :) -= V Y
+template <typename T>
+struct VyProb {
+    static constexpr bool A_M_CONTIG = true;
+    static constexpr bool B_N_CONTIG = false;
+    MatBatch<T> A; MatBatch<T> X; const int* ns; int b0; const T* Y; long long sY; int tiles_n;
+    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
+        t.batch = bz;
+        const int n = ns[bz];
+        if (b0 >= n - 1) return false;
+        const int m = n - b0 - 1;
+        t.m0 = (bx / tiles_n) * GEMM_BM;
+        t.n0 = (bx % tiles_n) * GEMM_BN;
+        t.K = 64;
+        return t.m0 < m && t.n0 < n;
+    }
+    __device__ T a(const GemmTile& t, int mm, int jj) const {
+        const int n = ns[t.batch];
+        const int r = b0 + 1 + mm;
+        if (r >= n) return T(0);
+        return hh_v(A.at(t.batch), A.ld, r, b0 + jj, n - 1);
+    }
+    __device__ T b(const GemmTile& t, int jj, int c) const {
+        if (c >= ns[t.batch]) return T(0);
+        return Y[(long long)t.batch * sY + jj + (long long)c * 64];
+    }
+    __device__ void store(const GemmTile& t, int mm, int c, T v) const {
+        const int n = ns[t.batch];
+        const int r = b0 + 1 + mm;
+        if (r >= n || c >= n) return;
+        X.at(t.batch)[r + (long long)c * X.ld] -= v;
+    }
+};
+
+template <typename T>
+void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st) {
+    const int nref = nmax - 1;
+    if (nref <= 0) return;
+    const int nblk = (nref + 63) / 64;
+    const int tiles = (nmax + 63) / 64;
+    const int nsplit = (nmax + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
+    for (int blk = nblk - 1; blk >= 0; blk--) {
+        const int b0 = blk * 64;
+        VtvProb<T> pg;
+        pg.A = w.A; pg.ns = w.ns; pg.b0 = b0; pg.Gpart = w.Gpart; pg.sG = w.sG;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, VtvProb<T>>), dim3(1, nsplit, nbatch), dim3(256), 0, st, pg);
+        hipLaunchKernelGGL(ormtr_tfactor_kernel<T>, dim3(1, 1, nbatch), dim3(256), 0, st, w, b0);
+        VtxProb<T> px;
+        px.A = w.A; px.X = w.X; px.ns = w.ns; px.b0 = b0; px.Ypart = w.Ypart; px.sYp = w.sYp; px.nmax = w.nmax;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, VtxProb<T>>), dim3(tiles, nsplit, nbatch), dim3(256), 0, st, px);
+        hipLaunchKernelGGL(ormtr_ty_kernel<T>, dim3(tiles, 1, nbatch), dim3(256), 0, st, w, b0);
+        VyProb<T> py;
+        py.A = w.A; py.X = w.X; py.ns = w.ns; py.b0 = b0; py.Y = w.Y; py.sY = w.sY; py.tiles_n = tiles;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, VyProb<T>>), dim3(tiles * tiles, 1, nbatch), dim3(256), 0, st, py);
+    }
+}
+
+template void ormtr_launch<double>(const OrmtrWs<double>&, int, int, hipStream_t);
+template void ormtr_launch<float>(const OrmtrWs<float>&, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// generic batched GEMM entry used by the refinement and gradient stages
+// ---------------------------------------------------------------------------
+template <typename T, bool TA, bool TB>
+static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
+                            long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
+                            T alpha, T beta, bool lower_only) {
+    GemmGeneral<T, TA, TB> p;
+    p.A = A; p.lda = lda; p.sA = sA; p.B = B; p.ldb = ldb; p.sB = sB; p.C = C; p.ldc = ldc; p.sC = sC;
+    p.ns = ns; p.M = p.N = p.K = nmax; p.alpha = alpha; p.beta = beta;
+    p.lower_only = lower_only ? 1 : 0;
+    const int t = (nmax + 63) / 64;
+    p.tiles_n = t;
+    const int grid = lower_only ? t * (t + 1) / 2 : t * t;
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB>>), dim3(grid, 1, nbatch), dim3(256), 0, st, p);
+}
+
+template <typename T>
+void gemm_batched(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int nbatch, const T* A,
+                  int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
+                  T alpha, T beta, bool lower_only) {
+    if (!ta && !tb) gemm_gen_launch<T, false, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only);
+    else if (ta && !tb) gemm_gen_launch<T, true, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only);
+    else if (!ta && tb) gemm_gen_launch<T, false, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only);
+    else gemm_gen_launch<T, true, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only);
+}
+
+template void gemm_batched<double>(hipStream_t, bool, bool, const int*, int, int, const double*, int, long long,
+                                   const double*, int, long long, double*, int, long long, double, double, bool);
+template void gemm_batched<float>(hipStream_t, bool, bool, const int*, int, int, const float*, int, long long,
+                                  const float*, int, long long, float*, int, long long, float, float, bool);

@@ -1,0 +1,144 @@
+// One refinement step of approximate eigenpairs (Ogita & Aishima, "Iterative
+// refinement for symmetric eigenvalue decomposition", 2018) in FP64 against
+// the FP64 Q, applied to FP32 eigenvectors from the FP32 diagonalisation:
+//   G = X^T X, R = I - G, S = X^T Q X
+//   lambda_i = S_ii / (1 - R_ii)
+//   E_ij = (S_ij + lambda_j R_ij)/(lambda_j - lambda_i)  if |lambda_i - lambda_j| > delta
+//        = R_ij / 2                                      otherwise (and on the diagonal)
+//   X <- X + X E
+// delta = 2 (||S - diag(lambda)||_F + max|lambda| ||R||_F), the Frobenius
+// bounds of the spectral norms in the method's separation threshold.
+// The products are batched GEMMs (gemm_mfma.h); these kernels do the
+// element-wise parts.
+#include "mbd_internal.h"
+#include "mbd_kernels.h"
+#include "mbd_sys.h"
+
+__global__ __launch_bounds__(256) void oa_f2d_kernel(const int* ns, MatBatch<float> X32, MatBatch<double> Xd) {
+    const int b = blockIdx.z;
+    const int n = ns[b];
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (c >= n || r >= n) return;
+    Xd.at(b)[r + (long long)c * Xd.ld] = (double)X32.at(b)[r + (long long)c * X32.ld];
+}
+
+__global__ __launch_bounds__(256) void copy_mat_kernel(const int* ns, MatBatch<double> src, MatBatch<double> dst) {
+    const int b = blockIdx.z;
+    const int n = ns[b];
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (c >= n || r >= n) return;
+    dst.at(b)[r + (long long)c * dst.ld] = src.at(b)[r + (long long)c * src.ld];
+}
+
+__global__ void fill_u32_kernel(unsigned* p, int n, unsigned v) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// lambda_i = S_ii / G_ii, then per-column partial sums of the squared
+// off-diagonal residuals (S - diag lambda) and R = I - G (G lower only)
+__global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
+                                                            double* lam, long long sL, double* colpart) {
+    __shared__ double red[4];
+    const int b = blockIdx.z;
+    const int n = ns[b];
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    const double* Sb = S.at(b);
+    const double* Gb = G.at(b);
+    double s2 = 0.0, r2 = 0.0, rmax = 0.0;
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const double sv = Sb[r + (long long)c * S.ld];
+        if (r != c) s2 += sv * sv;
+        const double gv = r >= c ? Gb[r + (long long)c * G.ld] : Gb[c + (long long)r * G.ld];
+        const double rv = (r == c ? 1.0 : 0.0) - gv;
+        r2 += rv * rv;
+        rmax = fmax(rmax, fabs(rv));
+    }
+    s2 = block_sum256(s2, red);
+    r2 = block_sum256(r2, red);
+    rmax = block_max256(rmax, red);
+    if (threadIdx.x == 0) {
+        const double gcc = Gb[c + (long long)c * G.ld];
+        const double l = Sb[c + (long long)c * S.ld] / gcc;
+        lam[(long long)b * sL + c] = l;
+        const long long o = (long long)b * 4 * sL + 4LL * c;
+        const double dl = Sb[c + (long long)c * S.ld] - l;
+        colpart[o] = s2 + dl * dl;
+        colpart[o + 1] = r2;
+        colpart[o + 2] = rmax;
+        colpart[o + 3] = fabs(l);
+    }
+}
+
+// per matrix: stats = {delta, max|R|}
+__global__ __launch_bounds__(256) void oa_delta_kernel(const int* ns, const double* colpart, long long sL,
+                                                         double* stats) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const int n = ns[b];
+    double s2 = 0, r2 = 0, rmax = 0, lmax = 0;
+    for (int c = threadIdx.x; c < n; c += 256) {
+        const long long o = (long long)b * 4 * sL + 4LL * c;
+        s2 += colpart[o];
+        r2 += colpart[o + 1];
+        rmax = fmax(rmax, colpart[o + 2]);
+        lmax = fmax(lmax, colpart[o + 3]);
+    }
+    s2 = block_sum256(s2, red);
+    r2 = block_sum256(r2, red);
+    rmax = block_max256(rmax, red);
+    lmax = block_max256(lmax, red);
+    if (threadIdx.x == 0) {
+        stats[4 * b] = 2.0 * (sqrt(s2) + lmax * sqrt(r2));
+        stats[4 * b + 1] = rmax;
+    }
+}
+
+// S <- E (in place)
+__global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
+                                                     const double* lam, long long sL, const double* stats) {
+    const int b = blockIdx.z;
+    const int n = ns[b];
+    const int j = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n || i >= n) return;
+    const double delta = stats[4 * b];
+    const double* Gb = G.at(b);
+    const double g = i >= j ? Gb[i + (long long)j * G.ld] : Gb[j + (long long)i * G.ld];
+    const double rij = (i == j ? 1.0 : 0.0) - g;
+    double* Sp = S.at(b) + i + (long long)j * S.ld;
+    const double li = lam[(long long)b * sL + i], lj = lam[(long long)b * sL + j];
+    const double dl = lj - li;
+    double e;
+    if (i != j && fabs(dl) > delta) e = (*Sp + lj * rij) / dl;
+    else e = 0.5 * rij;
+    *Sp = e;
+}
+
+void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd) {
+    hipLaunchKernelGGL(oa_f2d_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, X32, Xd);
+}
+
+void oa_stats_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S, MatBatch<double> G,
+                     double* lam, long long sL, double* colpart, double* stats) {
+    hipLaunchKernelGGL(oa_colstats_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, S, G, lam, sL, colpart);
+    hipLaunchKernelGGL(oa_delta_kernel, dim3(nbatch), dim3(256), 0, st, ns, colpart, sL, stats);
+}
+
+void oa_update_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S,
+                      MatBatch<double> G, const double* lam, long long sL, const double* stats) {
+    hipLaunchKernelGGL(oa_e_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, S, G, lam, sL,
+                       stats);
+}
+
+void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> src,
+                     MatBatch<double> dst) {
+    hipLaunchKernelGGL(copy_mat_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, src, dst);
+}
+
+void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+}

@@ -1,0 +1,472 @@
+// Symmetric tridiagonal eigensolver: divide and conquer (Cuppen's tearing
+// with rank-one merges), eigenvectors by the Loewner-formula recomputation of
+// the updating vector (Gu & Eisenstat) so they are orthogonal to working
+// precision, deflation of negligible z components and of close pole pairs
+// (Givens rotation), and merges multiplied out on matrix cores.  Second
+// stage of eq:diagonalization (paper Sec. 2.1).
+//
+// The tree is fixed bottom-up: leaves are single diagonal entries (every
+// off-diagonal torn: d_p - |e_{p-1}| - |e_p|), level L merges neighbouring
+// blocks [o, o+2^(L-1)) and [o+2^(L-1), o+2^L).  Each level is a fixed set of
+// launches over all merges of all matrices of a batch, so the sequence is
+// independent of the data and can be captured once in a HIP graph.
+//
+// Secular roots: one wavefront per root, bisection in the variable
+// mu = lambda - d_origin, where the origin is the pole the root is closer to,
+// so differences d_i - lambda are formed without cancellation.
+#include "mbd_internal.h"
+#include "gemm_mfma.h"
+#include "mbd_kernels.h"
+
+struct MergeInfo {
+    int o, k1, k;
+    __device__ __forceinline__ bool active() const { return k > k1; }
+};
+
+__device__ __forceinline__ MergeInfo merge_of(int p, int lev, int n) {
+    MergeInfo m;
+    const int size = 1 << lev, half = size >> 1;
+    m.o = (p >> lev) << lev;
+    m.k1 = min(half, n - m.o);
+    m.k = min(size, n - m.o);
+    return m;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_init_kernel(StedcWs<T> w) {
+    __shared__ T red[4];
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const T* d = w.d_in + (long long)b * w.sDin;
+    const T* e = w.e_in + (long long)b * w.sDin;
+    T mx = T(0);
+    for (int p = threadIdx.x; p < n; p += 256) {
+        mx = fmax(mx, fabs(d[p]));
+        if (p < n - 1) mx = fmax(mx, fabs(e[p]));
+    }
+    mx = block_max256(mx, red);
+    if (mx == T(0)) mx = T(1);
+    const T inv = T(1) / mx;
+    T* D = w.D + (long long)b * w.sV;
+    T* E = w.E + (long long)b * w.sV;
+    for (int p = threadIdx.x; p < n; p += 256) {
+        T el = p > 0 ? fabs(e[p - 1]) * inv : T(0);
+        T er = p < n - 1 ? fabs(e[p]) * inv : T(0);
+        D[p] = d[p] * inv - el - er;
+        E[p] = p < n - 1 ? e[p] * inv : T(0);
+    }
+    if (threadIdx.x == 0) w.scale[b] = mx;
+}
+
+// Z0 = I, Z1 = 0 on the n x n block
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_fill_kernel(StedcWs<T> w) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (c >= n || r >= n) return;
+    w.Z0.at(b)[r + (long long)c * w.Z0.ld] = (r == c) ? T(1) : T(0);
+    w.Z1.at(b)[r + (long long)c * w.Z1.ld] = T(0);
+}
+
+// merge inputs: z vector, sorted poles, permutation
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_setup_kernel(StedcWs<T> w, int lev, int src) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const MergeInfo m = merge_of(p, lev, n);
+    if (!m.active()) return;
+    const MatBatch<T>& Zc = src ? w.Z1 : w.Z0;
+    const T* Zb = Zc.at(b);
+    const long long ld = Zc.ld;
+    const T* D = w.D + (long long)b * w.sV;
+    const T ee = w.E[(long long)b * w.sV + m.o + m.k1 - 1];
+    const T sg = ee >= T(0) ? T(1) : T(-1);
+    const int lp = p - m.o;
+    const T dp = D[p];
+    const T inv_sqrt2 = T(0.70710678118654752440);
+    T zp = lp < m.k1 ? Zb[(m.o + m.k1 - 1) + (long long)p * ld] : sg * Zb[(m.o + m.k1) + (long long)p * ld];
+    zp *= inv_sqrt2;
+    int rank;
+    if (lp < m.k1) {
+        // elements of the second half strictly below dp
+        int lo = m.o + m.k1, hi = m.o + m.k;
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (D[mid] < dp) lo = mid + 1; else hi = mid; }
+        rank = lp + (lo - (m.o + m.k1));
+    } else {
+        int lo = m.o, hi = m.o + m.k1;
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (D[mid] <= dp) lo = mid + 1; else hi = mid; }
+        rank = (lp - m.k1) + (lo - m.o);
+    }
+    const long long base = (long long)b * w.sV + m.o;
+    w.ds[base + rank] = dp;
+    w.zs[base + rank] = zp;
+    w.perm[base + rank] = lp;
+    if (lp == 0) w.rho[base] = T(2) * fabs(ee);
+}
+
+// sequential deflation scan, one thread per merge
+template <typename T>
+__global__ __launch_bounds__(64) void stedc_deflate_kernel(StedcWs<T> w, int lev) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    const int o = t << lev;
+    if (o >= n) return;
+    const MergeInfo m = merge_of(o, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + o;
+    T* ds = w.ds + base;
+    T* zs = w.zs + base;
+    const int* perm = w.perm + base;
+    int* ndpos = w.ndpos + base;
+    int* dfpos = w.dfpos + base;
+    const T rho = w.rho[base];
+    T dmax = T(0), zmax = T(0);
+    for (int j = 0; j < m.k; j++) { dmax = fmax(dmax, fabs(ds[j])); zmax = fmax(zmax, fabs(zs[j])); }
+    const T tol = T(8) * num_limits<T>::eps * fmax(dmax, zmax);
+    int K = 0, ndf = 0, nrot = 0, pj = -1;
+    for (int jx = 0; jx < m.k; jx++) {
+        if (rho * fabs(zs[jx]) <= tol) { dfpos[ndf++] = jx; continue; }
+        if (pj < 0) { pj = jx; continue; }
+        T s = zs[pj], c = zs[jx];
+        const T tau = sqrt(c * c + s * s);
+        const T tt = ds[jx] - ds[pj];
+        c /= tau;
+        s = -s / tau;
+        if (fabs(tt * c * s) <= tol) {
+            zs[jx] = tau;
+            zs[pj] = T(0);
+            w.rp[base + nrot] = perm[pj];
+            w.rq[base + nrot] = perm[jx];
+            w.rc[base + nrot] = c;
+            w.rs[base + nrot] = s;
+            nrot++;
+            const T dpj = ds[pj] * c * c + ds[jx] * s * s;
+            ds[jx] = ds[pj] * s * s + ds[jx] * c * c;
+            ds[pj] = dpj;
+            dfpos[ndf++] = pj;
+            pj = jx;
+        } else {
+            ndpos[K++] = pj;
+            pj = jx;
+        }
+    }
+    if (pj >= 0) ndpos[K++] = pj;
+    for (int kk = 0; kk < K; kk++) {
+        w.dn[base + kk] = ds[ndpos[kk]];
+        w.zn[base + kk] = zs[ndpos[kk]];
+    }
+    w.Kcnt[base] = K;
+    w.rotcnt[base] = nrot;
+}
+
+// apply the deflation rotations to the eigenvector columns of the merge
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_rotate_kernel(StedcWs<T> w, int lev, int src) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const MergeInfo m = merge_of(r, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + m.o;
+    const int nrot = w.rotcnt[base];
+    if (nrot == 0) return;
+    const MatBatch<T>& Zc = src ? w.Z1 : w.Z0;
+    T* Zb = Zc.at(b);
+    const long long ld = Zc.ld;
+    for (int q = 0; q < nrot; q++) {
+        const long long ca = m.o + w.rp[base + q], cb = m.o + w.rq[base + q];
+        const T c = w.rc[base + q], s = w.rs[base + q];
+        const T x = Zb[r + ca * ld], y = Zb[r + cb * ld];
+        Zb[r + ca * ld] = c * x + s * y;
+        Zb[r + cb * ld] = c * y - s * x;
+    }
+}
+
+// secular equation 1 + rho sum z_i^2/(d_i - lambda) = 0, one wavefront per root
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_secular_kernel(StedcWs<T> w, int lev) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= n) return;
+    const MergeInfo m = merge_of(p, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + m.o;
+    const int K = w.Kcnt[base];
+    const int jx = p - m.o;
+    if (jx >= K) return;
+    const T* dn = w.dn + base;
+    const T* zn = w.zn + base;
+    const T rho = w.rho[base];
+    int org;
+    T lo, hi;
+    if (jx < K - 1) {
+        const T mid = T(0.5) * (dn[jx] + dn[jx + 1]);
+        T f = T(0);
+        for (int i = lane; i < K; i += 64) f += zn[i] * zn[i] / (dn[i] - mid);
+        f = T(1) + rho * wave_sum(f);
+        if (f >= T(0)) { org = jx; lo = T(0); hi = mid - dn[jx]; }
+        else { org = jx + 1; lo = mid - dn[jx + 1]; hi = T(0); }
+    } else {
+        T z2 = T(0);
+        for (int i = lane; i < K; i += 64) z2 += zn[i] * zn[i];
+        org = K - 1; lo = T(0); hi = rho * wave_sum(z2);
+    }
+    const T dorg = dn[org];
+    for (int it = 0; it < 400; it++) {
+        const T mm = T(0.5) * (lo + hi);
+        if (mm == lo || mm == hi) break;
+        T f = T(0);
+        for (int i = lane; i < K; i += 64) f += zn[i] * zn[i] / ((dn[i] - dorg) - mm);
+        f = T(1) + rho * wave_sum(f);
+        if (f < T(0)) lo = mm; else hi = mm;
+    }
+    if (lane == 0) {
+        const T mu = T(0.5) * (lo + hi);
+        w.org[base + jx] = org;
+        w.mu[base + jx] = mu;
+        w.lam[base + jx] = dorg + mu;
+    }
+}
+
+// Loewner formula for the updating vector consistent with the computed roots
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_zhat_kernel(StedcWs<T> w, int lev) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const MergeInfo m = merge_of(p, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + m.o;
+    const int K = w.Kcnt[base];
+    const int i = p - m.o;
+    if (i >= K) return;
+    const T* dn = w.dn + base;
+    const T* mu = w.mu + base;
+    const int* org = w.org + base;
+    const T di = dn[i];
+    T prod = ((dn[org[i]] - di) + mu[i]) / w.rho[base];
+    for (int j = 0; j < K; j++) {
+        if (j == i) continue;
+        prod *= ((dn[org[j]] - di) + mu[j]) / (dn[j] - di);
+    }
+    const T z = sqrt(fmax(prod, T(0)));
+    w.zh[base + i] = w.zn[base + i] >= T(0) ? z : -z;
+}
+
+// eigenvectors of D + rho z z^T: u_i = zhat_i / (d_i - lambda_j), normalised
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_vectors_kernel(StedcWs<T> w, int lev) {
+    __shared__ T red[4];
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int p = blockIdx.x;
+    if (p >= n) return;
+    const MergeInfo m = merge_of(p, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + m.o;
+    const int K = w.Kcnt[base];
+    const int jx = p - m.o;
+    if (jx >= K) return;
+    const T* dn = w.dn + base;
+    const T* zh = w.zh + base;
+    const T dorg = dn[w.org[base + jx]];
+    const T muj = w.mu[base + jx];
+    T ss = T(0);
+    for (int i = threadIdx.x; i < K; i += 256) {
+        const T u = zh[i] / ((dn[i] - dorg) - muj);
+        ss += u * u;
+    }
+    ss = block_sum256(ss, red);
+    const T inv = T(1) / sqrt(ss);
+    T* Ub = w.U.at(b);
+    const long long ld = w.U.ld;
+    for (int i = threadIdx.x; i < K; i += 256) {
+        const T u = zh[i] / ((dn[i] - dorg) - muj);
+        Ub[(m.o + i) + (long long)(m.o + jx) * ld] = u * inv;
+    }
+}
+
+// final ascending order of the merged spectrum (roots and deflated values)
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_order_kernel(StedcWs<T> w, int lev) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const MergeInfo m = merge_of(p, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + m.o;
+    const int K = w.Kcnt[base];
+    const T* lam = w.lam + base;
+    const T* ds = w.ds + base;
+    const int* dfpos = w.dfpos + base;
+    const int it = p - m.o;
+    auto val = [&](int q) -> T { return q < K ? lam[q] : ds[dfpos[q - K]]; };
+    const T v = val(it);
+    int rank = 0;
+    for (int q = 0; q < m.k; q++) {
+        const T u = val(q);
+        rank += (u < v) || (u == v && q < it);
+    }
+    if (it < K) w.outnd[base + it] = rank;
+    else w.outdf[base + it - K] = rank;
+    w.D[base + rank] = v;
+}
+
+// merged eigenvectors: Zn[:, outnd[j]] = Zc[:, perm[ndpos[.]]] U[:, j]
+template <typename T>
+struct DcMergeProb {
+    static constexpr bool A_M_CONTIG = true;
+    static constexpr bool B_N_CONTIG = false;
+    const int* ns;
+    int lev, tdim;
+    MatBatch<T> Zc, Zn, U;
+    const int* perm; const int* ndpos; const int* outnd; const int* Kcnt;
+    long long sV;
+    __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
+        t.batch = bz;
+        const int n = ns[bz];
+        const int o = by << lev;
+        if (o >= n) return false;
+        const MergeInfo m = merge_of(o, lev, n);
+        if (!m.active()) return false;
+        const int K = Kcnt[(long long)bz * sV + o];
+        t.m0 = (bx / tdim) * GEMM_BM;
+        t.n0 = (bx % tdim) * GEMM_BN;
+        t.K = K;
+        t.o = o;
+        t.k = m.k;
+        return t.m0 < m.k && t.n0 < K;
+    }
+    __device__ T a(const GemmTile& t, int mm, int kk) const {
+        if (mm >= t.k || kk >= t.K) return T(0);
+        const long long base = (long long)t.batch * sV + t.o;
+        const long long c = t.o + perm[base + ndpos[base + kk]];
+        return Zc.at(t.batch)[(t.o + mm) + c * Zc.ld];
+    }
+    __device__ T b(const GemmTile& t, int kk, int jj) const {
+        if (kk >= t.K || jj >= t.K) return T(0);
+        return U.at(t.batch)[(t.o + kk) + (long long)(t.o + jj) * U.ld];
+    }
+    __device__ void store(const GemmTile& t, int mm, int jj, T v) const {
+        if (mm >= t.k || jj >= t.K) return;
+        const long long base = (long long)t.batch * sV + t.o;
+        const long long c = t.o + outnd[base + jj];
+        Zn.at(t.batch)[(t.o + mm) + c * Zn.ld] = v;
+    }
+};
+
+// same product for small merges (k <= 64): one workgroup per merge
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_small_merge_kernel(StedcWs<T> w, int lev, int src) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int o = blockIdx.x << lev;
+    if (o >= n) return;
+    const MergeInfo m = merge_of(o, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + o;
+    const int K = w.Kcnt[base];
+    const MatBatch<T>& Zc = src ? w.Z1 : w.Z0;
+    const MatBatch<T>& Zn = src ? w.Z0 : w.Z1;
+    const T* Zcb = Zc.at(b);
+    T* Znb = Zn.at(b);
+    const T* Ub = w.U.at(b);
+    for (int idx = threadIdx.x; idx < m.k * K; idx += 256) {
+        const int r = idx % m.k, j = idx / m.k;
+        T acc = T(0);
+        for (int kk = 0; kk < K; kk++) {
+            const long long c = o + w.perm[base + w.ndpos[base + kk]];
+            acc += Zcb[(o + r) + c * Zc.ld] * Ub[(o + kk) + (long long)(o + j) * w.U.ld];
+        }
+        Znb[(o + r) + (long long)(o + w.outnd[base + j]) * Zn.ld] = acc;
+    }
+}
+
+// deflated columns and blocks without a merge at this level are copied
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_copy_kernel(StedcWs<T> w, int lev, int src) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int p = blockIdx.x;
+    if (p >= n) return;
+    const MergeInfo m = merge_of(p, lev, n);
+    const MatBatch<T>& Zc = src ? w.Z1 : w.Z0;
+    const MatBatch<T>& Zn = src ? w.Z0 : w.Z1;
+    const T* Zcb = Zc.at(b);
+    T* Znb = Zn.at(b);
+    long long sc, dc;
+    if (!m.active()) {
+        sc = dc = p;
+    } else {
+        const long long base = (long long)b * w.sV + m.o;
+        const int K = w.Kcnt[base];
+        const int it = p - m.o;
+        if (it < K) return;
+        const int q = it - K;
+        sc = m.o + w.perm[base + w.dfpos[base + q]];
+        dc = m.o + w.outdf[base + q];
+    }
+    for (int r = threadIdx.x; r < m.k; r += 256)
+        Znb[(m.o + r) + dc * Zn.ld] = Zcb[(m.o + r) + sc * Zc.ld];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_final_kernel(StedcWs<T> w) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    w.w_out[(long long)b * w.sW + p] = w.D[(long long)b * w.sV + p] * w.scale[b];
+}
+
+template <typename T>
+int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
+    const int gpos = (nmax + 255) / 256;
+    hipLaunchKernelGGL(stedc_init_kernel<T>, dim3(1, 1, nbatch), dim3(256), 0, st, w);
+    hipLaunchKernelGGL(stedc_fill_kernel<T>, dim3(gpos, nmax, nbatch), dim3(256), 0, st, w);
+    int L = 0;
+    while ((1 << L) < nmax) L++;
+    int src = 0;
+    for (int lev = 1; lev <= L; lev++) {
+        const int nmerge = (nmax + (1 << lev) - 1) >> lev;
+        hipLaunchKernelGGL(stedc_setup_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev, src);
+        hipLaunchKernelGGL(stedc_deflate_kernel<T>, dim3((nmerge + 63) / 64, 1, nbatch), dim3(64), 0, st, w,
+                           lev);
+        hipLaunchKernelGGL(stedc_rotate_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev, src);
+        hipLaunchKernelGGL(stedc_secular_kernel<T>, dim3((nmax + 3) / 4, 1, nbatch), dim3(256), 0, st, w, lev);
+        hipLaunchKernelGGL(stedc_zhat_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev);
+        hipLaunchKernelGGL(stedc_vectors_kernel<T>, dim3(nmax, 1, nbatch), dim3(256), 0, st, w, lev);
+        hipLaunchKernelGGL(stedc_order_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev);
+        if ((1 << lev) <= 64) {
+            hipLaunchKernelGGL(stedc_small_merge_kernel<T>, dim3(nmerge, 1, nbatch), dim3(256), 0, st, w, lev,
+                               src);
+        } else {
+            DcMergeProb<T> pr;
+            pr.ns = w.ns; pr.lev = lev;
+            pr.tdim = (1 << lev) / GEMM_BM;
+            pr.Zc = src ? w.Z1 : w.Z0;
+            pr.Zn = src ? w.Z0 : w.Z1;
+            pr.U = w.U;
+            pr.perm = w.perm; pr.ndpos = w.ndpos; pr.outnd = w.outnd; pr.Kcnt = w.Kcnt; pr.sV = w.sV;
+            hipLaunchKernelGGL((gemm_mfma_kernel<T, DcMergeProb<T>>), dim3(pr.tdim * pr.tdim, nmerge, nbatch),
+                               dim3(256), 0, st, pr);
+        }
+        hipLaunchKernelGGL(stedc_copy_kernel<T>, dim3(nmax, 1, nbatch), dim3(256), 0, st, w, lev, src);
+        src ^= 1;
+    }
+    hipLaunchKernelGGL(stedc_final_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w);
+    return src;
+}
+
+template int stedc_launch<double>(const StedcWs<double>&, int, int, hipStream_t);
+template int stedc_launch<float>(const StedcWs<float>&, int, int, hipStream_t);

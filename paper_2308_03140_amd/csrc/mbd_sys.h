@@ -1,0 +1,61 @@
+// Per-system device descriptor and MBD stage launchers (internal).
+#pragma once
+#include "mbd_internal.h"
+
+struct SysDesc {
+    const double* coords;
+    const double* alpha0;
+    const double* omega_or_c6;
+    const double* rvdw;
+    int N;
+    int param_kind;          // 0 omega, 1 C6
+    double beta, a;
+    int mat0, nmat;          // matrices of this system in the batch (periodic: one per q)
+    double weight;           // energy weight per sqrt(lambda) (1/2, or 1/(4 n_q) for embedded)
+    int embed;               // 1: matrices are 2n real embeddings of Hermitian Q(q)
+    int atom_off;            // offset of this system in the per-atom workspaces
+    double* energy;
+    double* grad_coords;
+    double* grad_alpha0;
+    double* grad_omega;
+    double* grad_rvdw;
+    double* grad_lattice;
+    double* eigvals;
+    double* errors;
+    // periodic data
+    double lat[9], linv[9], recip[9];
+    double vol, gamma, rc, kc, rdamp;
+};
+
+void mbd_prep_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, double* om, double* cc,
+                     unsigned* status);
+void mbd_assemble_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,
+                                const double* cc, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status);
+void mbd_energy_launch(hipStream_t st, const SysDesc* sd, int nsys, const int* ns, const double* lam,
+                       long long sL, const double* om, unsigned* status, double* lmin);
+void mbd_invsqrt4_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const double* lam, long long sL,
+                         double* sc);
+void mbd_inv_sqrt_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> X,
+                         const double* sc, long long sL, MatBatch<double> M);
+void mbd_mirror_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> M);
+void mbd_grad_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,
+                            const double* cc, MatBatch<double> M);
+
+// Ogita-Aishima refinement
+void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd);
+void oa_stats_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S, MatBatch<double> G,
+                     double* lam, long long sL, double* colpart, double* stats);
+void oa_update_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S,
+                      MatBatch<double> G, const double* lam, long long sL, const double* stats);
+void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> src,
+                     MatBatch<double> dst);
+void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v);
+
+// periodic (Ewald) assembly and adjoint
+void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
+                                  const double* qcart, int nq, const int* img, int nimg, const int* rec,
+                                  int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status);
+void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
+                              const double* qcart, int nq, const int* img, int nimg, const int* rec, int nrec,
+                              MatBatch<double> M, double* partial);
+void mbd_grad_periodic_reduce_launch(hipStream_t st, const SysDesc* sd, int nq, const double* partial);

@@ -1,0 +1,208 @@
+"""PyTorch-facing helpers over the C ABI: torch device tensors in, torch
+tensors out.  Only argument marshalling happens here; device memory comes from
+torch's allocator and work is enqueued on torch's current stream."""
+import ctypes
+
+import torch
+
+from . import _abi as A
+
+
+class MBDError(RuntimeError):
+    def __init__(self, code, origin, message):
+        super().__init__("MBD error %d in %s: %s" % (code, origin, message))
+        self.code = code
+        self.origin = origin
+        self.message = message
+
+
+class CollapseError(MBDError):
+    """Q is not positive definite (dipole collapse)."""
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _raise(ctx, code):
+    c, o, m = A.mbd_last_error(ctx.handle)
+    cls = CollapseError if code == A.MBD_ERR_NEGATIVE_EIGENVALUE else MBDError
+    raise cls(code, o, m)
+
+
+class Context:
+    """Owns an mbd_ctx bound to a device, a precision and torch's current stream."""
+
+    def __init__(self, device=0, precision="fp64"):
+        prec = {"fp64": A.MBD_FP64, "fp32_refined": A.MBD_FP32_REFINED}[precision]
+        self.device = torch.device("cuda", device)
+        self.precision = precision
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        st, h = A.mbd_create(device, prec, stream)
+        if st != A.MBD_OK:
+            raise MBDError(st, "mbd_create", "could not create context")
+        self.handle = h
+        self._stream = stream
+
+    def sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            A.mbd_set_stream(self.handle, s)
+            self._stream = s
+
+    def close(self):
+        if self.handle:
+            A.mbd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev(x, device):
+    return torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+
+
+def make_system(coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_frac=None,
+                kgrid=None, kshift=(0.0, 0.0, 0.0), param="omega", ewald=(0.0, 0.0, 0.0), device=None):
+    """Builds (MbdSystem, keep-alive list).  coords/alpha0/omega/rvdw: device tensors
+    (or array-likes copied to `device`); lattice and q_frac stay on the host."""
+    keep = []
+    dev = device if device is not None else coords.device
+    c = _dev(coords, dev).reshape(-1, 3)
+    a0 = _dev(alpha0, dev); w = _dev(omega, dev); rv = _dev(rvdw, dev)
+    keep += [c, a0, w, rv]
+    s = A.MbdSystem()
+    s.n_atoms = c.shape[0]
+    s.coords = c.data_ptr(); s.alpha0 = a0.data_ptr(); s.omega_or_c6 = w.data_ptr(); s.rvdw = rv.data_ptr()
+    s.param_kind = A.MBD_PARAM_C6 if param == "c6" else A.MBD_PARAM_OMEGA
+    s.beta = float(beta); s.a = float(a)
+    s.ewald_gamma, s.ewald_rc, s.ewald_kc = [float(x) for x in ewald]
+    if lattice is not None:
+        lat = (ctypes.c_double * 9)(*[float(x) for x in torch.as_tensor(lattice, dtype=torch.float64).reshape(-1).tolist()])
+        keep.append(lat)
+        s.lattice = ctypes.addressof(lat)
+        if q_frac is not None:
+            qf = torch.as_tensor(q_frac, dtype=torch.float64).reshape(-1).tolist()
+            qarr = (ctypes.c_double * len(qf))(*qf)
+            keep.append(qarr)
+            s.q_frac = ctypes.addressof(qarr)
+            s.n_q = len(qf) // 3
+        else:
+            s.n_q = 0
+            for i in range(3):
+                s.kgrid[i] = int(kgrid[i]) if kgrid is not None else 1
+                s.kshift[i] = float(kshift[i])
+    return s, keep
+
+
+def evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_frac=None,
+             kgrid=None, param="omega", gradients=True, eigvals=False, errors=True, ewald=(0.0, 0.0, 0.0)):
+    """Energy (and gradients) of one system.  Returns a dict of torch tensors."""
+    ctx.sync_stream()
+    dev = ctx.device
+    s, keep = make_system(coords, alpha0, omega, rvdw, beta, a, lattice, q_frac, kgrid,
+                          param=param, ewald=ewald, device=dev)
+    N = s.n_atoms
+    periodic = lattice is not None
+    nq = s.n_q if (periodic and s.n_q) else (int(torch.tensor(kgrid).prod()) if periodic else 1)
+    out = {"energy": torch.empty(1, dtype=torch.float64, device=dev)}
+    want = A.MBD_WANT_ENERGY
+    r = A.MbdResult()
+    r.energy = out["energy"].data_ptr()
+    if gradients:
+        out["grad_coords"] = torch.empty(N, 3, dtype=torch.float64, device=dev)
+        out["grad_alpha0"] = torch.empty(N, dtype=torch.float64, device=dev)
+        r.grad_coords = out["grad_coords"].data_ptr()
+        r.grad_alpha0 = out["grad_alpha0"].data_ptr()
+        want |= A.MBD_WANT_GRAD_COORDS | A.MBD_WANT_GRAD_ALPHA0
+        if periodic:
+            out["grad_lattice"] = torch.empty(3, 3, dtype=torch.float64, device=dev)
+            r.grad_lattice = out["grad_lattice"].data_ptr()
+            want |= A.MBD_WANT_GRAD_LATTICE
+        else:
+            out["grad_omega"] = torch.empty(N, dtype=torch.float64, device=dev)
+            out["grad_rvdw"] = torch.empty(N, dtype=torch.float64, device=dev)
+            r.grad_omega_or_c6 = out["grad_omega"].data_ptr()
+            r.grad_rvdw = out["grad_rvdw"].data_ptr()
+            want |= A.MBD_WANT_GRAD_OMEGA | A.MBD_WANT_GRAD_RVDW
+    if eigvals:
+        out["eigvals"] = torch.empty(nq, 3 * N, dtype=torch.float64, device=dev)
+        r.eigvals = out["eigvals"].data_ptr()
+        want |= A.MBD_WANT_EIGVALS
+    if errors:
+        out["errors"] = torch.zeros(4, dtype=torch.float64, device=dev)
+        r.errors = out["errors"].data_ptr()
+        want |= A.MBD_WANT_ERRORS
+    code = A.mbd_evaluate(ctx.handle, s, want, r)
+    if code != A.MBD_OK:
+        _raise(ctx, code)
+    return out
+
+
+def evaluate_batch(ctx, systems, gradients=True, errors=True):
+    """systems: list of dicts with coords, alpha0, omega, rvdw (, beta, a).  Finite only."""
+    ctx.sync_stream()
+    dev = ctx.device
+    n = len(systems)
+    sarr = (A.MbdSystem * n)()
+    rarr = (A.MbdResult * n)()
+    stat = (ctypes.c_int32 * n)()
+    keep, outs = [], []
+    want = A.MBD_WANT_ENERGY
+    if gradients:
+        want |= A.MBD_WANT_GRAD_COORDS | A.MBD_WANT_GRAD_ALPHA0 | A.MBD_WANT_GRAD_OMEGA
+    if errors:
+        want |= A.MBD_WANT_ERRORS
+    for i, sy in enumerate(systems):
+        s, k = make_system(sy["coords"], sy["alpha0"], sy["omega"], sy["rvdw"], sy.get("beta", 0.83),
+                           sy.get("a", 6.0), device=dev)
+        keep.append(k)
+        sarr[i] = s
+        N = s.n_atoms
+        o = {"energy": torch.empty(1, dtype=torch.float64, device=dev)}
+        rarr[i].energy = o["energy"].data_ptr()
+        if gradients:
+            o["grad_coords"] = torch.empty(N, 3, dtype=torch.float64, device=dev)
+            o["grad_alpha0"] = torch.empty(N, dtype=torch.float64, device=dev)
+            o["grad_omega"] = torch.empty(N, dtype=torch.float64, device=dev)
+            rarr[i].grad_coords = o["grad_coords"].data_ptr()
+            rarr[i].grad_alpha0 = o["grad_alpha0"].data_ptr()
+            rarr[i].grad_omega_or_c6 = o["grad_omega"].data_ptr()
+        if errors:
+            o["errors"] = torch.zeros(4, dtype=torch.float64, device=dev)
+            rarr[i].errors = o["errors"].data_ptr()
+        outs.append(o)
+    code = A.mbd_evaluate_batch(ctx.handle, sarr, want, rarr, stat)
+    for i in range(n):
+        outs[i]["status"] = int(stat[i])
+    if code not in (A.MBD_OK, A.MBD_ERR_NEGATIVE_EIGENVALUE):
+        _raise(ctx, code)
+    return outs
+
+
+def eigh(ctx, A_mat, vectors=True):
+    """Symmetric eigendecomposition of a (batch of) square device matrices
+    (float64 or float32).  Returns (w ascending, Z with eigenvectors as columns)."""
+    ctx.sync_stream()
+    M = A_mat
+    squeeze = M.dim() == 2
+    if squeeze:
+        M = M.unsqueeze(0)
+    M = M.contiguous().clone()
+    nb, n, _ = M.shape
+    dtype = 0 if M.dtype == torch.float64 else 1
+    w = torch.empty(nb, n, dtype=M.dtype, device=M.device)
+    Z = torch.empty(nb, n, n, dtype=M.dtype, device=M.device) if vectors else None
+    code = A.mbd_eigh(ctx.handle, dtype, n, nb, M.data_ptr(), n, n * n, w.data_ptr(),
+                      Z.data_ptr() if vectors else None, n, n * n)
+    if code != A.MBD_OK:
+        _raise(ctx, code)
+    if vectors:
+        Z = Z.transpose(1, 2)  # column-major result: Z[b][:, k] is eigenvector k
+    if squeeze:
+        return w[0], (Z[0] if vectors else None)
+    return w, Z

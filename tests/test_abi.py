@@ -1,0 +1,72 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+declared in include/mbd.h, and the ctypes structures match the C layout."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mbd.h")
+
+
+def _lib():
+    from paper_2308_03140_amd import _abi
+    if not os.path.exists(_abi.library_path):
+        from paper_2308_03140_amd import build
+        build.build(verbose=False)
+    return _abi
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:mbd_status|int)\s+(mbd_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    A = _lib()
+    names = _declared()
+    assert len(names) >= 9
+    L = ctypes.CDLL(A.library_path)
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", A.library_path], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (mbd_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    A = _lib()
+    fields_s = [f for f, _ in A.MbdSystem._fields_]
+    fields_r = [f for f, _ in A.MbdResult._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "mbd.h"', "int main(void){",
+           'printf("%zu %zu\\n", sizeof(mbd_system), sizeof(mbd_result));']
+    for f in fields_s:
+        src.append('printf("%%zu\\n", offsetof(mbd_system, %s));' % f)
+    for f in fields_r:
+        src.append('printf("%%zu\\n", offsetof(mbd_result, %s));' % f)
+    src.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == ctypes.sizeof(A.MbdSystem)
+    assert vals[1] == ctypes.sizeof(A.MbdResult)
+    offs = vals[2:]
+    for f, o in zip(fields_s, offs[:len(fields_s)]):
+        assert getattr(A.MbdSystem, f).offset == o, f
+    for f, o in zip(fields_r, offs[len(fields_s):]):
+        assert getattr(A.MbdResult, f).offset == o, f
+
+
+def test_null_context_is_rejected_without_device_work():
+    A = _lib()
+    L = A.lib()
+    assert L.mbd_destroy(None) == A.MBD_ERR_INVALID_ARGUMENT
+    assert L.mbd_evaluate(None, None, 0, None) == A.MBD_ERR_INVALID_ARGUMENT
+    assert L.mbd_last_error(None, None, None) == A.MBD_ERR_INVALID_ARGUMENT
+    h = ctypes.c_void_p()
+    # invalid precision is refused before any device query
+    assert L.mbd_create(ctypes.byref(h), 0, 7, None) == A.MBD_ERR_INVALID_ARGUMENT
