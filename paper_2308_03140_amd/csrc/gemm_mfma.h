@@ -17,6 +17,17 @@ template <typename T> struct mfma4;
 template <> struct mfma4<double> { typedef double v __attribute__((ext_vector_type(4))); };
 template <> struct mfma4<float> { typedef float v __attribute__((ext_vector_type(4))); };
 
+// Row of the 16x16 result held by (lane, register r); the column is lane & 15.
+// Measured on gfx950: the f32 form packs 4 consecutive rows per lane group,
+// the f64 form interleaves them with stride 4.
+template <typename T> struct mfma_rows;
+template <> struct mfma_rows<double> {
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct mfma_rows<float> {
+    static __device__ __forceinline__ int row(int lane, int r) { return ((lane >> 4) << 2) + r; }
+};
+
 __device__ __forceinline__ mfma4<double>::v mfma16x16x4(double a, double b, mfma4<double>::v c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -103,14 +114,13 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(P p) {
             __syncthreads();
         }
     }
-    // 16x16 MFMA result layout: lane holds column (lane & 15), rows 4*(lane>>4) + r
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                int row = t.m0 + wm * 32 + i * 16 + ((lane >> 4) << 2) + r;
+                int row = t.m0 + wm * 32 + i * 16 + mfma_rows<T>::row(lane, r);
                 int col = t.n0 + wn * 32 + j * 16 + (lane & 15);
                 p.store(t, row, col, acc[i][j][r]);
             }
