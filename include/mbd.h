@@ -164,6 +164,17 @@ mbd_status mbd_eigh(mbd_ctx *ctx, int32_t dtype, int32_t n, int32_t nbatch, void
 mbd_status mbd_autotune(mbd_ctx *ctx, const int32_t *sizes, int32_t nsizes, const char *table_json_path);
 mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
 
+/* Launch timing for measurement tools.  While enabled, every per-column SYMV
+ * launch of the Householder reduction (kind 0, the bandwidth-bound BLAS-2
+ * phase) and every trailing SYR2K launch (kind 1, the matrix-core BLAS-3
+ * phase) is bracketed by two HIP events on the context stream.  Enabling
+ * clears earlier records.  mbd_get_profile synchronises the stream and
+ * returns, for one kind, the summed event time (ms), the number of launches
+ * and the summed algorithmic work: bytes of the lower trailing triangle read
+ * (kind 0) or flops of the rank-2k update (kind 1). */
+mbd_status mbd_set_profiling(mbd_ctx *ctx, int enable);
+mbd_status mbd_get_profile(mbd_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, double *work);
+
 /* (code, origin, message) of the last error on the context; returns code.
  * origin and message stay valid until the next call on the context. */
 int mbd_last_error(const mbd_ctx *ctx, const char **origin, const char **message);

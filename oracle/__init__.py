@@ -221,6 +221,22 @@ def min_coupling_eig(R, alpha0, rvdw, beta=0.83, a=6.0):
     return mu.value
 
 
+def is_positive_definite(A):
+    """Cholesky test of a symmetric matrix (oracle's own factorisation)."""
+    A = _arr(A)
+    _load().orc_is_positive_definite.restype = ctypes.c_int
+    return bool(_load().orc_is_positive_definite(A.shape[0], _p(A)))
+
+
+def coupling_matrix(R, alpha0, rvdw, beta=0.83, a=6.0):
+    """alpha0^{1/2} T^lr alpha0^{1/2} (finite): Q of eq:q-matrix with omega = 1, minus I."""
+    R = _arr(R, (-1, 3))
+    N = R.shape[0]
+    S = assemble_finite(R, alpha0, np.ones(N), rvdw, beta, a)
+    S[np.diag_indices(3 * N)] -= 1.0
+    return S
+
+
 def dipole(r):
     T = np.empty(9); dT = np.empty(27)
     _load().orc_dipole(_p(_arr(r)), _p(T), _p(dT))

@@ -759,25 +759,44 @@ void orc_gauss_legendre(int n, double *x, double *w)
     }
 }
 
+/* dot product with four partial sums (plain, but not latency-bound) */
+static double dot4(const double *x, const double *y, int n)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 3 < n; k += 4) {
+        s0 += x[k] * y[k]; s1 += x[k + 1] * y[k + 1];
+        s2 += x[k + 2] * y[k + 2]; s3 += x[k + 3] * y[k + 3];
+    }
+    for (; k < n; k++) s0 += x[k] * y[k];
+    return (s0 + s1) + (s2 + s3);
+}
+
 /* In-place lower Cholesky of a row-major SPD matrix; returns 0 or 2 if not PD. */
 static int cholesky(int n, double *A)
 {
     for (int j = 0; j < n; j++) {
         double *aj = A + (size_t)j * n;
-        double s = aj[j];
-        for (int k = 0; k < j; k++) s -= aj[k] * aj[k];
+        double s = aj[j] - dot4(aj, aj, j);
         if (!(s > 0.0)) return 2;
         double l = sqrt(s);
         aj[j] = l;
 #pragma omp parallel for schedule(static)
         for (int i = j + 1; i < n; i++) {
             double *ai = A + (size_t)i * n;
-            double t = ai[j];
-            for (int k = 0; k < j; k++) t -= ai[k] * aj[k];
-            ai[j] = t / l;
+            ai[j] = (ai[j] - dot4(ai, aj, j)) / l;
         }
     }
     return 0;
+}
+
+int orc_is_positive_definite(int n, const double *A)
+{
+    double *C = (double *)malloc(sizeof(double) * (size_t)n * n);
+    memcpy(C, A, sizeof(double) * (size_t)n * n);
+    int rc = cholesky(n, C);
+    free(C);
+    return rc == 0;
 }
 
 int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,

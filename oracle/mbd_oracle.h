@@ -91,6 +91,9 @@ int orc_min_coupling_eig(int N, const double *R, const double *alpha0,
                          const double *rvdw, double beta, double a,
                          double *mu_min);
 
+/* 1 if the symmetric matrix (row-major) has a Cholesky factor, else 0. */
+int orc_is_positive_definite(int n, const double *A);
+
 /* Pairwise tensors for tests: bare T (eq:dipole), T^erfc (eq:terfc, with the
  * coefficient reading -r_a r_b C), and their first derivatives dT[c][a][b]. */
 void orc_dipole(const double *r, double *T, double *dT);

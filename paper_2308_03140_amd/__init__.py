@@ -20,7 +20,8 @@ from ._abi import (MBD_OK, MBD_ERR_INVALID_ARGUMENT, MBD_ERR_NEGATIVE_EIGENVALUE
 __all__ = [n for n in dir(_abi) if n.startswith("MBD_")] + [
     "MbdSystem", "MbdResult", "lib", "library_path",
     "mbd_create", "mbd_destroy", "mbd_set_stream", "mbd_evaluate", "mbd_evaluate_batch",
-    "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error",
+    "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error", "mbd_set_profiling",
+    "mbd_get_profile",
 ]
 
 mbd_create = _abi.mbd_create
@@ -32,3 +33,5 @@ mbd_eigh = _abi.mbd_eigh
 mbd_autotune = _abi.mbd_autotune
 mbd_load_tuning = _abi.mbd_load_tuning
 mbd_last_error = _abi.mbd_last_error
+mbd_set_profiling = _abi.mbd_set_profiling
+mbd_get_profile = _abi.mbd_get_profile

@@ -85,9 +85,13 @@ def lib():
                                ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int64]
         L.mbd_autotune.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_char_p]
         L.mbd_load_tuning.argtypes = [_P, ctypes.c_char_p]
+        L.mbd_set_profiling.argtypes = [_P, ctypes.c_int]
+        L.mbd_get_profile.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         L.mbd_last_error.argtypes = [_P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_char_p)]
         for f in ("mbd_create", "mbd_destroy", "mbd_set_stream", "mbd_evaluate", "mbd_evaluate_batch",
-                  "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error"):
+                  "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error", "mbd_set_profiling",
+                  "mbd_get_profile"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -128,6 +132,17 @@ def mbd_autotune(ctx, sizes, path=None):
 
 def mbd_load_tuning(ctx, path):
     return lib().mbd_load_tuning(ctx, path.encode())
+
+
+def mbd_set_profiling(ctx, enable):
+    return lib().mbd_set_profiling(ctx, int(bool(enable)))
+
+
+def mbd_get_profile(ctx, kind):
+    """Returns (status, total_ms, launches, work) for launch kind 0 (SYMV) or 1 (SYR2K)."""
+    ms = ctypes.c_double(); n = ctypes.c_int64(); w = ctypes.c_double()
+    st = lib().mbd_get_profile(ctx, int(kind), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w))
+    return st, ms.value, n.value, w.value
 
 
 def mbd_last_error(ctx):

@@ -22,6 +22,7 @@ struct mbd_ctx {
     size_t total = 0, limit = 0;
     int err_code = 0;
     std::string err_origin, err_msg;
+    LaunchProfiler prof;
 };
 
 namespace {
@@ -87,8 +88,8 @@ struct EigResult {
 
 // Full dense symmetric eigensolver on a batch: reduction, D&C, back-transform.
 template <typename T>
-mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int nbatch, bool vectors, T* w_out,
-                   long long sW, MatBatch<T>* Xout) {
+mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host, int nmax, int nbatch, bool vectors,
+                   T* w_out, long long sW, MatBatch<T>* Xout) {
     const std::string t = tname<T>();
     const hipStream_t st = c->stream;
     const int nbk = (nmax + 63) / 64;
@@ -114,7 +115,7 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int nbatc
     if (!sw.Vp || !sw.Wp || !sw.colbuf || !sw.normpart || !sw.P1 || !sw.P2 || !sw.PS || !sw.PV || !sw.d ||
         !sw.e || !sw.tau)
         return (mbd_status)c->err_code;
-    sytrd_launch<T>(sw, nbatch, nmax, st);
+    sytrd_launch<T>(sw, nbatch, nmax, st, ns_host, &c->prof);
     HIPCHK(hipGetLastError(), "sytrd");
 
     // --- divide and conquer
@@ -193,8 +194,8 @@ mbd_status check_system(mbd_ctx* c, const mbd_system* s, unsigned want, const mb
     if ((want & MBD_WANT_ERRORS) && !o->errors) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "errors output is NULL");
     if (s->lattice) {
         if (!allow_periodic) return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate_batch", "periodic systems are evaluated one at a time");
-        if (want & MBD_WANT_GRAD_RVDW)
-            return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate", "grad_rvdw is for finite systems");
+        if (want & (MBD_WANT_GRAD_RVDW | MBD_WANT_GRAD_OMEGA))
+            return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate", "grad_rvdw and grad_omega are for finite systems");
     } else if (want & MBD_WANT_GRAD_LATTICE) {
         return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "grad_lattice needs a lattice");
     }
@@ -226,8 +227,118 @@ __global__ void grad_gate_kernel(const unsigned* status, int nsys, SysDesc* sd) 
     sd[s].N = 0;
 }
 
-// Finite systems (one or a batch), all stages on the context stream.
-mbd_status run_finite(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::vector<int>& codes) {
+// Host-side description of a periodic evaluation: Cartesian q points, the
+// integer image list of the real-space sum and the reciprocal-vector list.
+struct PeriodicSetup {
+    std::vector<double> qcart;
+    std::vector<int> img, rec;
+};
+
+void inv3(const double* A, double* Ai) {
+    const double dt = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                      A[2] * (A[3] * A[7] - A[4] * A[6]);
+    Ai[0] = (A[4] * A[8] - A[5] * A[7]) / dt; Ai[1] = (A[2] * A[7] - A[1] * A[8]) / dt;
+    Ai[2] = (A[1] * A[5] - A[2] * A[4]) / dt; Ai[3] = (A[5] * A[6] - A[3] * A[8]) / dt;
+    Ai[4] = (A[0] * A[8] - A[2] * A[6]) / dt; Ai[5] = (A[2] * A[3] - A[0] * A[5]) / dt;
+    Ai[6] = (A[3] * A[7] - A[4] * A[6]) / dt; Ai[7] = (A[1] * A[6] - A[0] * A[7]) / dt;
+    Ai[8] = (A[0] * A[4] - A[1] * A[3]) / dt;
+}
+
+// Lattice, Ewald parameters (defaults of the paper's Sec. 3.3 when not
+// given), q mesh and term lists.  Reads coords and R_vdW back to the host.
+mbd_status setup_periodic(mbd_ctx* c, const mbd_system* s, SysDesc& d, PeriodicSetup& ps) {
+    const double* A = s->lattice;
+    for (int k = 0; k < 9; k++) {
+        if (!std::isfinite(A[k])) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "non-finite lattice");
+        d.lat[k] = A[k];
+    }
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(det > 0.0)) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "det(lattice) must be > 0");
+    inv3(A, d.linv);
+    const double twopi = 6.283185307179586476925;
+    for (int u = 0; u < 3; u++)
+        for (int k = 0; k < 3; k++) d.recip[u * 3 + k] = twopi * d.linv[k * 3 + u];
+    d.vol = det;
+    d.gamma = s->ewald_gamma > 0 ? s->ewald_gamma : 2.5 / std::cbrt(det);
+    d.rc = s->ewald_rc > 0 ? s->ewald_rc : 6.0 / d.gamma;
+    d.kc = s->ewald_kc > 0 ? s->ewald_kc : 10.0 * d.gamma;
+    const int N = s->n_atoms;
+    std::vector<double> R(3 * N), rv(N);
+    HIPCHK(hipMemcpy(R.data(), s->coords, sizeof(double) * 3 * N, hipMemcpyDeviceToHost), "read coords");
+    HIPCHK(hipMemcpy(rv.data(), s->rvdw, sizeof(double) * N, hipMemcpyDeviceToHost), "read rvdw");
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, rvmax = 0.0;
+    for (int i = 0; i < N; i++) {
+        for (int k = 0; k < 3; k++) { lo[k] = std::min(lo[k], R[3 * i + k]); hi[k] = std::max(hi[k], R[3 * i + k]); }
+        rvmax = std::max(rvmax, rv[i]);
+    }
+    if (!std::isfinite(rvmax)) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "non-finite rvdw");
+    const double maxd = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                  (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    if (!std::isfinite(maxd)) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "non-finite coordinates");
+    // (1 - g) > 1e-18  <=>  eta < 1 + ln(1e18 - 1)/a
+    const double rdamp = s->beta > 0 ? (1.0 + std::log(1.0 / 1e-18 - 1.0) / s->a) * s->beta * 2.0 * rvmax * 1.0000001 : 0.0;
+    d.rdamp = rdamp;
+    const double rreal = std::max(d.rc, rdamp);
+    // q mesh
+    ps.qcart.clear();
+    std::vector<double> qf;
+    if (s->n_q > 0) {
+        if (!s->q_frac) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "q_frac is NULL");
+        qf.assign(s->q_frac, s->q_frac + 3 * s->n_q);
+    } else {
+        for (int k = 0; k < 3; k++)
+            if (s->kgrid[k] < 1) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "kgrid must be >= 1");
+        for (int a = 1; a <= s->kgrid[0]; a++)
+            for (int b = 1; b <= s->kgrid[1]; b++)
+                for (int e = 1; e <= s->kgrid[2]; e++) {
+                    const int r3[3] = {a, b, e};
+                    for (int k = 0; k < 3; k++)
+                        qf.push_back((2.0 * r3[k] - s->kgrid[k] - 1) / (2.0 * s->kgrid[k]) + s->kshift[k]);
+                }
+    }
+    double qmax = 0.0;
+    for (size_t t = 0; t < qf.size() / 3; t++) {
+        double q[3];
+        for (int k = 0; k < 3; k++)
+            q[k] = qf[3 * t] * d.recip[k] + qf[3 * t + 1] * d.recip[3 + k] + qf[3 * t + 2] * d.recip[6 + k];
+        for (int k = 0; k < 3; k++) ps.qcart.push_back(q[k]);
+        qmax = std::max(qmax, std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]));
+    }
+    // image and reciprocal lists (box bound, then sphere filter)
+    ps.img.clear();
+    ps.rec.clear();
+    int nv[3], mv[3];
+    for (int v = 0; v < 3; v++) {
+        const double bl = std::sqrt(d.recip[3 * v] * d.recip[3 * v] + d.recip[3 * v + 1] * d.recip[3 * v + 1] +
+                                    d.recip[3 * v + 2] * d.recip[3 * v + 2]);
+        const double al = std::sqrt(A[3 * v] * A[3 * v] + A[3 * v + 1] * A[3 * v + 1] + A[3 * v + 2] * A[3 * v + 2]);
+        nv[v] = (int)std::ceil((rreal + maxd) * bl / twopi) + 1;
+        mv[v] = (int)std::ceil((d.kc + qmax) * al / twopi) + 1;
+    }
+    for (int x = -nv[0]; x <= nv[0]; x++)
+        for (int y = -nv[1]; y <= nv[1]; y++)
+            for (int z = -nv[2]; z <= nv[2]; z++) {
+                double Rn[3];
+                for (int k = 0; k < 3; k++) Rn[k] = x * A[k] + y * A[3 + k] + z * A[6 + k];
+                if (std::sqrt(Rn[0] * Rn[0] + Rn[1] * Rn[1] + Rn[2] * Rn[2]) > rreal + maxd + 1e-9) continue;
+                ps.img.push_back(x); ps.img.push_back(y); ps.img.push_back(z);
+            }
+    for (int x = -mv[0]; x <= mv[0]; x++)
+        for (int y = -mv[1]; y <= mv[1]; y++)
+            for (int z = -mv[2]; z <= mv[2]; z++) {
+                double G[3];
+                for (int k = 0; k < 3; k++) G[k] = x * d.recip[k] + y * d.recip[3 + k] + z * d.recip[6 + k];
+                if (std::sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]) > d.kc + qmax + 1e-9) continue;
+                ps.rec.push_back(x); ps.rec.push_back(y); ps.rec.push_back(z);
+            }
+    return MBD_OK;
+}
+
+// One or more finite systems, or one periodic system (per != nullptr: one
+// embedded matrix per q point), all stages on the context stream.
+mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::vector<int>& codes,
+                    const PeriodicSetup* per) {
     const hipStream_t st = c->stream;
     const int nsys = (int)sds.size();
     int Nmax = 0, ntot = 0;
@@ -235,75 +346,94 @@ mbd_status run_finite(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std:
         d.atom_off = ntot;
         ntot += d.N;
         Nmax = std::max(Nmax, d.N);
-        d.weight = 0.5;
-        d.embed = 0;
     }
-    for (int s = 0; s < nsys; s++) { sds[s].mat0 = s; sds[s].nmat = 1; }
-    const int nmax = 3 * Nmax;
+    const int nq = per ? (int)per->qcart.size() / 3 : 1;
+    const int nmat = per ? nq : nsys;
+    for (int s = 0; s < nsys; s++) {
+        sds[s].mat0 = per ? 0 : s;
+        sds[s].nmat = per ? nq : 1;
+        sds[s].weight = per ? 0.25 / nq : 0.5;
+        sds[s].embed = per ? 1 : 0;
+    }
+    const int nmax = per ? 6 * Nmax : 3 * Nmax;
     const int ld = round_up(nmax, 64);
     const long long stride = (long long)ld * nmax;
     const bool grads = (want & (MBD_WANT_GRAD_COORDS | MBD_WANT_GRAD_ALPHA0 | MBD_WANT_GRAD_OMEGA |
-                                MBD_WANT_GRAD_RVDW)) != 0;
+                                MBD_WANT_GRAD_RVDW | MBD_WANT_GRAD_LATTICE)) != 0;
     const bool fp32 = c->prec == MBD_FP32_REFINED;
 
     SysDesc* sd_dev = (SysDesc*)ws(c, "sysdesc", sizeof(SysDesc) * nsys);
-    int* ns_dev = wsT<int>(c, "ns", nsys);
+    int* ns_dev = wsT<int>(c, "ns", nmat);
     unsigned* status = wsT<unsigned>(c, "status", nsys);
     double* lmin = wsT<double>(c, "lmin", nsys);
     double* om = wsT<double>(c, "om", ntot);
     double* cc = wsT<double>(c, "cc", ntot);
-    double* lam = wsT<double>(c, "lam64", (size_t)nmax * nsys);
-    double* sc = wsT<double>(c, "sc64", (size_t)nmax * nsys);
-    MatBatch<double> A64 = {wsT<double>(c, "A64", (size_t)stride * nsys), ld, stride};
+    double* lam = wsT<double>(c, "lam64", (size_t)nmax * nmat);
+    double* sc = wsT<double>(c, "sc64", (size_t)nmax * nmat);
+    MatBatch<double> A64 = {wsT<double>(c, "A64", (size_t)stride * nmat), ld, stride};
     MatBatch<float> A32 = {nullptr, ld, stride};
-    if (fp32) A32.p = wsT<float>(c, "A32", (size_t)stride * nsys);
+    if (fp32) A32.p = wsT<float>(c, "A32", (size_t)stride * nmat);
     if (!sd_dev || !ns_dev || !status || !lmin || !om || !cc || !lam || !sc || !A64.p || (fp32 && !A32.p))
         return (mbd_status)c->err_code;
-    std::vector<int> nsh(nsys);
-    for (int s = 0; s < nsys; s++) nsh[s] = 3 * sds[s].N;
+    std::vector<int> nsh(nmat);
+    for (int b = 0; b < nmat; b++) nsh[b] = per ? 6 * sds[0].N : 3 * sds[b].N;
     HIPCHK(hipMemcpyAsync(sd_dev, sds.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st), "upload");
-    HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nmat, hipMemcpyHostToDevice, st), "upload");
     fill_u32_launch(st, status, nsys, 0u);
     mbd_prep_launch(st, sd_dev, nsys, Nmax, om, cc, status);
-    mbd_assemble_finite_launch(st, sd_dev, nsys, Nmax, om, cc, A64, A32, status);
+    double* qcart = nullptr;
+    int* img = nullptr;
+    int* rec = nullptr;
+    if (per) {
+        qcart = wsT<double>(c, "qcart", per->qcart.size());
+        img = wsT<int>(c, "img", per->img.size());
+        rec = wsT<int>(c, "rec", per->rec.size());
+        if (!qcart || !img || !rec) return (mbd_status)c->err_code;
+        HIPCHK(hipMemcpyAsync(qcart, per->qcart.data(), sizeof(double) * per->qcart.size(), hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(hipMemcpyAsync(img, per->img.data(), sizeof(int) * per->img.size(), hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(hipMemcpyAsync(rec, per->rec.data(), sizeof(int) * per->rec.size(), hipMemcpyHostToDevice, st), "upload");
+        mbd_assemble_periodic_launch(st, sd_dev, om, cc, qcart, nq, img, (int)per->img.size() / 3, rec,
+                                     (int)per->rec.size() / 3, A64, A32, status, sds[0].N);
+    } else {
+        mbd_assemble_finite_launch(st, sd_dev, nsys, Nmax, om, cc, A64, A32, status);
+    }
     HIPCHK(hipGetLastError(), "assemble");
 
     MatBatch<double> X;
     std::vector<double> stats_h;
     double* stats = nullptr;
     if (!fp32) {
-        mbd_status r = run_eig<double>(c, A64, ns_dev, nmax, nsys, grads, lam, nmax, &X);
+        mbd_status r = run_eig<double>(c, A64, ns_dev, nsh.data(), nmax, nmat, grads, lam, nmax, &X);
         if (r != MBD_OK) return r;
     } else {
-        float* lam32 = wsT<float>(c, "lam32", (size_t)nmax * nsys);
+        float* lam32 = wsT<float>(c, "lam32", (size_t)nmax * nmat);
         if (!lam32) return (mbd_status)c->err_code;
         MatBatch<float> X32;
-        mbd_status r = run_eig<float>(c, A32, ns_dev, nmax, nsys, true, lam32, nmax, &X32);
+        mbd_status r = run_eig<float>(c, A32, ns_dev, nsh.data(), nmax, nmat, true, lam32, nmax, &X32);
         if (r != MBD_OK) return r;
         // one Ogita-Aishima step in FP64 against the FP64 Q held in A64
-        MatBatch<double> Xd = {wsT<double>(c, "oaX", (size_t)stride * nsys), ld, stride};
-        MatBatch<double> Y = {wsT<double>(c, "oaY", (size_t)stride * nsys), ld, stride};
-        MatBatch<double> S = {wsT<double>(c, "oaS", (size_t)stride * nsys), ld, stride};
-        double* colpart = wsT<double>(c, "oacol", (size_t)4 * nmax * nsys);
-        stats = wsT<double>(c, "oastats", (size_t)4 * nsys);
+        MatBatch<double> Xd = {wsT<double>(c, "oaX", (size_t)stride * nmat), ld, stride};
+        MatBatch<double> Y = {wsT<double>(c, "oaY", (size_t)stride * nmat), ld, stride};
+        MatBatch<double> S = {wsT<double>(c, "oaS", (size_t)stride * nmat), ld, stride};
+        double* colpart = wsT<double>(c, "oacol", (size_t)4 * nmax * nmat);
+        stats = wsT<double>(c, "oastats", (size_t)4 * nmat);
         if (!Xd.p || !Y.p || !S.p || !colpart || !stats) return (mbd_status)c->err_code;
-        MatBatch<double> G = Y;  // G = X^T X lives in Y until Y = Q X is needed... (see below)
-        oa_f2d_launch(st, ns_dev, nmax, nsys, X32, Xd);
+        oa_f2d_launch(st, ns_dev, nmax, nmat, X32, Xd);
         // Y = Q X
-        gemm_batched<double>(st, false, false, ns_dev, nmax, nsys, A64.p, ld, stride, Xd.p, ld, stride, Y.p, ld,
+        gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, A64.p, ld, stride, Xd.p, ld, stride, Y.p, ld,
                              stride, 1.0, 0.0, false);
         // S = X^T Y
-        gemm_batched<double>(st, true, false, ns_dev, nmax, nsys, Xd.p, ld, stride, Y.p, ld, stride, S.p, ld,
+        gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Xd.p, ld, stride, Y.p, ld, stride, S.p, ld,
                              stride, 1.0, 0.0, false);
-        // G = X^T X (lower) into A64 (Q no longer needed)
-        G = A64;
-        gemm_batched<double>(st, true, false, ns_dev, nmax, nsys, Xd.p, ld, stride, Xd.p, ld, stride, G.p, ld,
+        // G = X^T X (lower) into A64: Q is not needed after Y = Q X
+        MatBatch<double> G = A64;
+        gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Xd.p, ld, stride, Xd.p, ld, stride, G.p, ld,
                              stride, 1.0, 0.0, true);
-        oa_stats_launch(st, ns_dev, nmax, nsys, S, G, lam, nmax, colpart, stats);
-        oa_update_launch(st, ns_dev, nmax, nsys, S, G, lam, nmax, stats);
+        oa_stats_launch(st, ns_dev, nmax, nmat, S, G, lam, nmax, colpart, stats);
+        oa_update_launch(st, ns_dev, nmax, nmat, S, G, lam, nmax, stats);
         // X' = X + X E  (into Y)
-        copy_mat_launch(st, ns_dev, nmax, nsys, Xd, Y);
-        gemm_batched<double>(st, false, false, ns_dev, nmax, nsys, Xd.p, ld, stride, S.p, ld, stride, Y.p, ld,
+        copy_mat_launch(st, ns_dev, nmax, nmat, Xd, Y);
+        gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, Xd.p, ld, stride, S.p, ld, stride, Y.p, ld,
                              stride, 1.0, 1.0, false);
         HIPCHK(hipGetLastError(), "refine");
         X = Y;
@@ -312,19 +442,27 @@ mbd_status run_finite(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std:
     HIPCHK(hipGetLastError(), "energy");
     if (grads) {
         hipLaunchKernelGGL(grad_gate_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, status, nsys, sd_dev);
-        mbd_invsqrt4_launch(st, ns_dev, nmax, nsys, lam, nmax, sc);
+        mbd_invsqrt4_launch(st, ns_dev, nmax, nmat, lam, nmax, sc);
         MatBatch<double> M = A64;
-        if (fp32) M = {wsT<double>(c, "oaS", (size_t)stride * nsys), ld, stride};  // S (E) is free now
-        mbd_inv_sqrt_launch(st, ns_dev, nmax, nsys, X, sc, nmax, M);
-        mbd_mirror_launch(st, ns_dev, nmax, nsys, M);
-        mbd_grad_finite_launch(st, sd_dev, nsys, Nmax, om, cc, M);
+        if (fp32) M = {wsT<double>(c, "oaS", (size_t)stride * nmat), ld, stride};  // S (E) is free now
+        mbd_inv_sqrt_launch(st, ns_dev, nmax, nmat, X, sc, nmax, M);
+        mbd_mirror_launch(st, ns_dev, nmax, nmat, M);
+        if (per) {
+            const int N = sds[0].N;
+            double* part = wsT<double>(c, "gpart", (size_t)nq * N * N * 13);
+            if (!part) return (mbd_status)c->err_code;
+            mbd_grad_periodic_launch(st, sd_dev, om, cc, qcart, nq, img, (int)per->img.size() / 3, rec,
+                                     (int)per->rec.size() / 3, M, part, N);
+        } else {
+            mbd_grad_finite_launch(st, sd_dev, nsys, Nmax, om, cc, M);
+        }
         HIPCHK(hipGetLastError(), "gradients");
     }
     std::vector<unsigned> sth(nsys);
     HIPCHK(hipMemcpyAsync(sth.data(), status, sizeof(unsigned) * nsys, hipMemcpyDeviceToHost, st), "status");
     if (stats) {
-        stats_h.resize(4 * nsys);
-        HIPCHK(hipMemcpyAsync(stats_h.data(), stats, sizeof(double) * 4 * nsys, hipMemcpyDeviceToHost, st), "status");
+        stats_h.resize(4 * nmat);
+        HIPCHK(hipMemcpyAsync(stats_h.data(), stats, sizeof(double) * 4 * nmat, hipMemcpyDeviceToHost, st), "status");
     }
     HIPCHK(hipStreamSynchronize(st), "synchronize");
     codes.assign(nsys, MBD_OK);
@@ -333,7 +471,15 @@ mbd_status run_finite(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std:
         else if (sth[s] & MBD_ST_COLLAPSE) codes[s] = MBD_ERR_NEGATIVE_EIGENVALUE;
         if (sds[s].errors && codes[s] != MBD_ERR_INVALID_ARGUMENT) {
             double e3[3] = {0.0, 0.0, 0.0};
-            if (stats) { e3[0] = stats_h[4 * s + 1]; e3[1] = 1.0; e3[2] = stats_h[4 * s]; }
+            if (stats) {
+                // worst matrix of the system
+                for (int q = 0; q < sds[s].nmat; q++) {
+                    const int b = sds[s].mat0 + q;
+                    e3[0] = std::max(e3[0], stats_h[4 * b + 1]);
+                    e3[2] = std::max(e3[2], stats_h[4 * b]);
+                }
+                e3[1] = 1.0;
+            }
             HIPCHK(hipMemcpy(sds[s].errors + 1, e3, sizeof(e3), hipMemcpyHostToDevice), "errors");
         }
     }
@@ -395,10 +541,16 @@ mbd_status mbd_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_resu
     mbd_status r = check_system(c, s, want, out, true);
     if (r != MBD_OK) return r;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_evaluate", "hipSetDevice");
-    if (s->lattice) return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate", "periodic systems not available in this build");
     std::vector<SysDesc> sds(1, make_desc(s, want, out));
     std::vector<int> codes;
-    r = run_finite(c, sds, want, codes);
+    if (s->lattice) {
+        PeriodicSetup ps;
+        r = setup_periodic(c, s, sds[0], ps);
+        if (r != MBD_OK) return r;
+        r = run_core(c, sds, want, codes, &ps);
+    } else {
+        r = run_core(c, sds, want, codes, nullptr);
+    }
     if (r != MBD_OK) return r;
     return code_message(c, codes[0], "mbd_evaluate");
 }
@@ -417,7 +569,7 @@ mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, 
     }
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_evaluate_batch", "hipSetDevice");
     std::vector<int> codes;
-    mbd_status r = run_finite(c, sds, want, codes);
+    mbd_status r = run_core(c, sds, want, codes, nullptr);
     if (r != MBD_OK) return r;
     mbd_status first = MBD_OK;
     for (int i = 0; i < n_sys; i++) {
@@ -443,7 +595,7 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
     mbd_status r;
     if (dtype == 0) {
         MatBatch<double> Ab = {(double*)A, lda, (long long)stride}, X;
-        r = run_eig<double>(c, Ab, ns_dev, n, nbatch, Z != nullptr, (double*)w, n, &X);
+        r = run_eig<double>(c, Ab, ns_dev, nsh.data(), n, nbatch, Z != nullptr, (double*)w, n, &X);
         if (r == MBD_OK && Z)
             HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, X.p, sizeof(double) * X.ld, sizeof(double) * n,
                                     (size_t)n * 1, hipMemcpyDeviceToDevice, c->stream), "copy");
@@ -454,7 +606,7 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
                        "copy");
     } else {
         MatBatch<float> Ab = {(float*)A, lda, (long long)stride}, X;
-        r = run_eig<float>(c, Ab, ns_dev, n, nbatch, Z != nullptr, (float*)w, n, &X);
+        r = run_eig<float>(c, Ab, ns_dev, nsh.data(), n, nbatch, Z != nullptr, (float*)w, n, &X);
         if (r == MBD_OK && Z)
             for (int b = 0; b < nbatch; b++)
                 HIPCHK(hipMemcpy2DAsync((float*)Z + (long long)b * zstride, sizeof(float) * ldz, X.p + (long long)b * X.stride,
@@ -474,6 +626,23 @@ mbd_status mbd_autotune(mbd_ctx* c, const int32_t*, int32_t, const char*) {
 mbd_status mbd_load_tuning(mbd_ctx* c, const char*) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;
     return fail(c, MBD_ERR_UNSUPPORTED, "mbd_load_tuning", "not available in this build");
+}
+
+mbd_status mbd_set_profiling(mbd_ctx* c, int enable) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    hipStreamSynchronize(c->stream);
+    c->prof.enabled = enable != 0;
+    c->prof.reset();
+    return MBD_OK;
+}
+
+mbd_status mbd_get_profile(mbd_ctx* c, int32_t kind, double* total_ms, int64_t* launches, double* work) {
+    if (!c || !total_ms || !launches || !work || kind < 0 || kind > 1) return MBD_ERR_INVALID_ARGUMENT;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_get_profile", "synchronize");
+    long long n = 0;
+    c->prof.summary(kind, total_ms, &n, work);
+    *launches = n;
+    return MBD_OK;
 }
 
 int mbd_last_error(const mbd_ctx* c, const char** origin, const char** message) {

@@ -361,8 +361,10 @@ int sytrd_tiles_per_chunk(int nbk_trail, int nbatch) {
 }
 
 template <typename T>
-void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st) {
+void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, const int* ns_host,
+                  LaunchProfiler* prof) {
     constexpr int NBP = SYTRD_NBP;
+    const bool timing = prof && prof->enabled && ns_host;
     const int nbk_max = w.nbk_max;
     hipLaunchKernelGGL(sytrd_init_kernel<T>, dim3(nbk_max, 1, nbatch), dim3(256), 0, st, w);
     int k0 = 0;
@@ -372,8 +374,18 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st) {
         const int nbt = nbk_max - b0;
         const int Kt = sytrd_tiles_per_chunk<T>(nbt, nbatch);
         const int gx = (nbt + Kt - 1) / Kt;
+        if (timing) prof->begin(st);
         hipLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j,
                            Kt);
+        if (timing) {
+            // algorithmic traffic: the lower trailing triangle, read once
+            double bytes = 0;
+            for (int b = 0; b < nbatch; b++) {
+                const double m = ns_host[b] - i - 1;
+                if (m > 0) bytes += m * (m + 1) * 0.5 * sizeof(T);
+            }
+            prof->end(st, 0, bytes);
+        }
         hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j,
                            Kt, gx * nbt);
         if (j == NBP - 1 && i + 2 < nmax) {
@@ -381,12 +393,21 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st) {
             const int tm = (nmax - t0 + 63) / 64;
             Syr2kProb<T, NBP> p;
             p.A = w.A; p.ns = w.ns; p.Vp = w.Vp; p.Wp = w.Wp; p.ldp = w.ldp; p.sP = w.sP; p.t0 = t0;
+            if (timing) prof->begin(st);
             hipLaunchKernelGGL((gemm_mfma_kernel<T, Syr2kProb<T, NBP>>), dim3(tm * (tm + 1) / 2, 1, nbatch),
                                dim3(256), 0, st, p);
+            if (timing) {
+                double flops = 0;
+                for (int b = 0; b < nbatch; b++) {
+                    const double m = ns_host[b] - t0;
+                    if (m > 0) flops += 2.0 * (2 * NBP) * m * (m + 1) * 0.5;
+                }
+                prof->end(st, 1, flops);
+            }
             k0 += NBP;
         }
     }
 }
 
-template void sytrd_launch<double>(const SytrdWs<double>&, int, int, hipStream_t);
-template void sytrd_launch<float>(const SytrdWs<float>&, int, int, hipStream_t);
+template void sytrd_launch<double>(const SytrdWs<double>&, int, int, hipStream_t, const int*, LaunchProfiler*);
+template void sytrd_launch<float>(const SytrdWs<float>&, int, int, hipStream_t, const int*, LaunchProfiler*);

@@ -2,6 +2,51 @@
 #pragma once
 #include "mbd_internal.h"
 
+#include <vector>
+
+// Optional HIP-event timing of individual launches (measurement tools only).
+// kind 0: per-column SYMV of the reduction (BLAS-2), 1: trailing SYR2K
+// (BLAS-3).  `work` is the algorithmic bytes (kind 0) or flops (kind 1) of
+// the launch.
+struct LaunchProfiler {
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> kind;
+    std::vector<double> work;
+    size_t used = 0;
+    void reset() { used = 0; kind.clear(); work.clear(); }
+    hipEvent_t next() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            hipEventCreate(&e);
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void begin(hipStream_t st) {
+        if (enabled) hipEventRecord(next(), st);
+    }
+    void end(hipStream_t st, int k, double w) {
+        if (!enabled) return;
+        hipEventRecord(next(), st);
+        kind.push_back(k);
+        work.push_back(w);
+    }
+    // total milliseconds, launches and work of one kind (after a stream sync)
+    void summary(int k, double* ms, long long* n, double* w) const {
+        double t = 0, ww = 0;
+        long long c = 0;
+        for (size_t i = 0; i < kind.size(); i++) {
+            if (kind[i] != k) continue;
+            float e = 0;
+            hipEventElapsedTime(&e, pool[2 * i], pool[2 * i + 1]);
+            t += e; ww += work[i]; c++;
+        }
+        *ms = t; *n = c; *w = ww;
+    }
+    ~LaunchProfiler() { for (auto e : pool) hipEventDestroy(e); }
+};
+
 #define SYTRD_NBP 32     // Householder panel width
 #define ORMTR_NBB 64     // reflectors per compact-WY block in the back-transform
 #define ORMTR_CHUNK 512  // rows per split-K chunk of V^T X
@@ -22,7 +67,8 @@ struct SytrdWs {
     T* d; T* e; T* tau; long long sD;      // outputs
 };
 template <typename T>
-void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st);
+void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, const int* ns_host,
+                  LaunchProfiler* prof);
 
 // --- Divide and conquer ------------------------------------------------------
 template <typename T>

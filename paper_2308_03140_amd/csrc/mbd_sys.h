@@ -54,8 +54,7 @@ void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v);
 // periodic (Ewald) assembly and adjoint
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                                   const double* qcart, int nq, const int* img, int nimg, const int* rec,
-                                  int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status);
+                                  int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N);
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                               const double* qcart, int nq, const int* img, int nimg, const int* rec, int nrec,
-                              MatBatch<double> M, double* partial);
-void mbd_grad_periodic_reduce_launch(hipStream_t st, const SysDesc* sd, int nq, const double* partial);
+                              MatBatch<double> M, double* partial, int N);
