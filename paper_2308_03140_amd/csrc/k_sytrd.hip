@@ -5,23 +5,42 @@
 //
 // Per panel of NBP columns, per column i (reflector H_i = I - tau v v^T with
 // v(i+1) = 1 annihilating A(i+2:n, i)):
-//   sytrd_symv   one pass over the not-yet-updated lower trailing matrix
-//                A(i+1:n, i+1:n), 64x64 tiles, each element read once and used
-//                for both y_R += A_RC v_C and y_C += A_RC^T v_R; also the panel
-//                products p = W^T v, s = V^T v and the scalar v^T A v.  This
-//                is the bandwidth-bound BLAS-2 half of the reduction.
-//   sytrd_finish reduces the tile partials per 64-row block, forms
-//                w = tau (A v - V p - W s) - (tau/2)(w^T v) v, and already
-//                applies the panel to the next column (so the next reflector
-//                can be built without another pass).
-// After the panel: A(t0:n, t0:n) -= V W^T + W V^T on matrix cores
-// (the BLAS-3 half).  All partial sums go through fixed-order reductions, so
-// results are bitwise reproducible.  Every kernel takes a batch index
-// (blockIdx.z) and the order of its own matrix, so one launch sequence
-// serves a single large matrix and batches of uneven matrices alike.
-#include "mbd_internal.h"
+//   SYMV phase    one pass over the not-yet-updated lower trailing matrix
+//                 A(i+1:n, i+1:n) in 64x64 tiles, each element read once and
+//                 used for both y_R += A_RC v_C and y_C += A_RC^T v_R; also
+//                 the panel products p = W^T v, s = V^T v and v^T A v.  This
+//                 is the bandwidth-bound BLAS-2 half of the reduction.
+//   finish phase  per 64-row block: reduce the tile partials, form
+//                 w = tau (A v - V p - W s) - (tau/2)(w^T v) v, and apply the
+//                 panel to the next column so its reflector can be built
+//                 without another pass.
+// After the panel: A(t0:n, t0:n) -= V W^T + W V^T on matrix cores (the BLAS-3
+// half).  All partial sums are reduced in a fixed order, so results are
+// bitwise reproducible.
+//
+// The two phases of all NBP columns of a panel run in one persistent
+// cooperative launch (a grid-wide sync after each phase), so the column loop
+// costs two grid barriers per column instead of two kernel launches.  A
+// launch-per-phase path with the same device code is kept for devices where
+// the cooperative launch is refused.  Every work item carries a batch index,
+// so one launch sequence serves a single large matrix and batches of uneven
+// matrices alike.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <string>
+
 #include "gemm_mfma.h"
+#include "mbd_internal.h"
 #include "mbd_kernels.h"
+
+namespace cg = cooperative_groups;
+
+template <typename T>
+struct Refl {
+    T beta, tau, scale;
+};
 
 template <typename T>
 __device__ __forceinline__ T refl_v(const T* col, int r, int s, int n, T scale) {
@@ -30,24 +49,37 @@ __device__ __forceinline__ T refl_v(const T* col, int r, int s, int n, T scale) 
 }
 
 // Reflector scalars from the updated column held in colbuf (LAPACK dlarfg
-// convention: beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta).
+// convention: beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta).  Called
+// by the whole workgroup: the block norms are summed in one parallel pass.
 template <typename T>
-__device__ __forceinline__ void refl_scalars(const SytrdWs<T>& w, int b, int i, int n, T& beta,
-                                             T& tau, T& scale) {
+__device__ __forceinline__ Refl<T> refl_scalars(const SytrdWs<T>& w, int b, int i, int n) {
+    __shared__ T red[4];
     const T* col = w.colbuf + (long long)b * w.sC;
     const T* np_ = w.normpart + (long long)b * w.sNP;
     const int nbk = (n + 63) >> 6;
-    T xn2 = T(0);
-    for (int R = (i >> 6); R < nbk; R++) xn2 += np_[R];
+    T part = T(0);
+    for (int R = (i >> 6) + (int)threadIdx.x; R < nbk; R += 256) part += np_[R];
+    const T xn2 = block_sum256(part, red);
     const T alpha = col[i + 1];
+    Refl<T> r;
     if (xn2 == T(0)) {
-        tau = T(0); beta = alpha; scale = T(0);
+        r.tau = T(0); r.beta = alpha; r.scale = T(0);
     } else {
-        T nrm = sqrt(alpha * alpha + xn2);
-        beta = alpha >= T(0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scale = T(1) / (alpha - beta);
+        const T nrm = sqrt(alpha * alpha + xn2);
+        r.beta = alpha >= T(0) ? -nrm : nrm;
+        r.tau = (r.beta - alpha) / r.beta;
+        r.scale = T(1) / (alpha - r.beta);
     }
+    return r;
+}
+
+// tiles per work item of the SYMV phase, from the trailing block count
+__host__ __device__ __forceinline__ int sytrd_kt(int nbt, int nbatch, int target) {
+    const long long tiles = (long long)nbt * (nbt + 1) / 2 * nbatch;
+    long long kt = (tiles + target - 1) / target;
+    if (kt < 1) kt = 1;
+    if (kt > 16) kt = 16;
+    return (int)kt;
 }
 
 template <typename T>
@@ -72,77 +104,29 @@ __global__ __launch_bounds__(256) void sytrd_init_kernel(SytrdWs<T> w) {
     if (threadIdx.x == 0) w.normpart[(long long)b * w.sNP + R] = q;
 }
 
+// ---------------------------------------------------------------------------
+// SYMV work item: tiles R in [C + q Kt, C + (q+1) Kt) of column strip C
+// ---------------------------------------------------------------------------
 template <typename T, int NBP>
-__global__ __launch_bounds__(256) void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
+__device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt, int C, int q, int slot,
+                          const Refl<T>& rf) {
     __shared__ T tb[64][65];
     __shared__ T rrow[4][64];
     __shared__ T red[4];
-    const int b = blockIdx.z;
-    const int n = w.ns[b];
-    const int slot = blockIdx.y * gridDim.x + blockIdx.x;
-    T* PV = w.PV + (long long)b * w.sPV;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (i > n - 2) { if (tid == 0) PV[slot] = T(0); return; }
     const int s = i + 1;
     const int b0 = s >> 6;
     const int nbk = (n + 63) >> 6;
-    const int C = b0 + blockIdx.y;
-    const int q = blockIdx.x;
-    if (C >= nbk) { if (tid == 0) PV[slot] = T(0); return; }
-    const int nch = (nbk - C + Kt - 1) / Kt;
-    if (q >= nch) { if (tid == 0) PV[slot] = T(0); return; }
-
     T* A = w.A.at(b);
-    const int ld = w.A.ld;
+    const long long ld = w.A.ld;
     const T* col = w.colbuf + (long long)b * w.sC;
-    T beta, tau, scale;
-    refl_scalars(w, b, i, n, beta, tau, scale);
-
     T* Vp = w.Vp + (long long)b * w.sP;
     T* Wp = w.Wp + (long long)b * w.sP;
     const int ldp = w.ldp;
-
-    if (q == 0) {
-        // store v for the rows of block C (panel column j and the matrix column i)
-        if (tid < 64) {
-            const int r = C * 64 + tid;
-            if (r < n) {
-                T vr = refl_v(col, r, s, n, scale);
-                Vp[r + (long long)j * ldp] = vr;
-                if (r >= s) A[r + (long long)i * ld] = vr;
-            }
-        }
-        if (C == b0 && tid == 0) {
-            w.d[(long long)b * w.sD + i] = col[i];
-            w.e[(long long)b * w.sD + i] = beta;
-            w.tau[(long long)b * w.sD + i] = tau;
-        }
-        // panel products over the rows of block C
-        T* PS = w.PS + (long long)b * w.sPS + (long long)C * (2 * NBP);
-        const int r = C * 64 + lane;
-        const bool rv = (r >= s && r < n);
-        const T vr = rv ? refl_v(col, r, s, n, scale) : T(0);
-        for (int k = wv; k < j; k += 4) {
-            T pw = rv ? Wp[r + (long long)k * ldp] * vr : T(0);
-            T pv = rv ? Vp[r + (long long)k * ldp] * vr : T(0);
-            pw = wave_sum(pw);
-            pv = wave_sum(pv);
-            if (lane == 0) { PS[k] = pw; PS[NBP + k] = pv; }
-        }
-    }
-
-    // column strip values
-    T vc[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) vc[k] = refl_v(col, C * 64 + wv * 16 + k, s, n, scale);
-    T cacc[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) cacc[k] = T(0);
-    T vav = T(0);
-
     const int Rb = C + q * Kt;
     const int Re = min(Rb + Kt, nbk);
     const int c0 = C * 64 + wv * 16;
+
     T a[16], an[16];
     auto load_tile = [&](int R, T* dst) {
         const int r = R * 64 + lane;
@@ -154,11 +138,49 @@ __global__ __launch_bounds__(256) void sytrd_symv_kernel(SytrdWs<T> w, int i, in
             dst[k] = ok ? A[r + (long long)c * ld] : T(0);
         }
     };
+    // the first tile is in flight while the vectors are formed
     load_tile(Rb, a);
+
+    if (q == 0) {
+        // v for the rows of block C: panel column j and matrix column i
+        if (tid < 64) {
+            const int r = C * 64 + tid;
+            if (r < n) {
+                const T vr = refl_v(col, r, s, n, rf.scale);
+                Vp[r + (long long)j * ldp] = vr;
+                if (r >= s) A[r + (long long)i * ld] = vr;
+            }
+        }
+        if (C == b0 && tid == 0) {
+            w.d[(long long)b * w.sD + i] = col[i];
+            w.e[(long long)b * w.sD + i] = rf.beta;
+            w.tau[(long long)b * w.sD + i] = rf.tau;
+        }
+        // panel products over the rows of block C
+        T* PS = w.PS + (long long)b * w.sPS + (long long)C * (2 * NBP);
+        const int r = C * 64 + lane;
+        const bool rv = (r >= s && r < n);
+        const T vr = rv ? refl_v(col, r, s, n, rf.scale) : T(0);
+        for (int k = wv; k < j; k += 4) {
+            T pw = rv ? Wp[r + (long long)k * ldp] * vr : T(0);
+            T pv = rv ? Vp[r + (long long)k * ldp] * vr : T(0);
+            pw = wave_sum(pw);
+            pv = wave_sum(pv);
+            if (lane == 0) { PS[k] = pw; PS[NBP + k] = pv; }
+        }
+    }
+
+    T vc[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) vc[k] = refl_v(col, c0 + k, s, n, rf.scale);
+    T cacc[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) cacc[k] = T(0);
+    T vav = T(0);
     for (int R = Rb; R < Re; R++) {
         if (R + 1 < Re) load_tile(R + 1, an);
         const int r = R * 64 + lane;
-        const T vr = refl_v(col, r, s, n, scale);
+        const T vr = refl_v(col, r, s, n, rf.scale);
         T rs = T(0);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
@@ -169,7 +191,7 @@ __global__ __launch_bounds__(256) void sytrd_symv_kernel(SytrdWs<T> w, int i, in
         rrow[wv][lane] = rs;
         __syncthreads();
         if (wv == 0) {
-            T y = (rrow[0][lane] + rrow[1][lane]) + (rrow[2][lane] + rrow[3][lane]);
+            const T y = (rrow[0][lane] + rrow[1][lane]) + (rrow[2][lane] + rrow[3][lane]);
             w.P1[(long long)b * w.sP1 + ((long long)C * w.nbk_max + R) * 64 + lane] = y;
             vav += vr * y;
         }
@@ -192,125 +214,212 @@ __global__ __launch_bounds__(256) void sytrd_symv_kernel(SytrdWs<T> w, int i, in
     }
     __syncthreads();
     if (tid < 64) {
-        T cs = (rrow[0][tid] + rrow[1][tid]) + (rrow[2][tid] + rrow[3][tid]);
+        const T cs = (rrow[0][tid] + rrow[1][tid]) + (rrow[2][tid] + rrow[3][tid]);
         w.P2[(long long)b * w.sP2 + ((long long)C * w.maxchunk + q) * 64 + tid] = cs;
-        vav += refl_v(col, C * 64 + tid, s, n, scale) * cs;
+        vav += refl_v(col, C * 64 + tid, s, n, rf.scale) * cs;
     }
     vav = block_sum256(vav, red);
-    if (tid == 0) PV[slot] = vav;
+    if (tid == 0) w.PV[(long long)b * w.sPV + slot] = vav;
 }
 
+// ---------------------------------------------------------------------------
+// finish work item: 64-row block R.  All independent global loads are issued
+// before the first reduction.
+// ---------------------------------------------------------------------------
 template <typename T, int NBP>
-__global__ __launch_bounds__(256) void sytrd_finish_kernel(SytrdWs<T> w, int i, int j, int Kt,
-                                                           int nslots) {
+__device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt, int nslots, int R) {
     static_assert(2 * NBP <= 64, "panel products are reduced by one wavefront");
+    static_assert(NBP % 4 == 0, "panel columns are split over 4 wavefronts");
     __shared__ T sps[2 * NBP];
-    __shared__ T rrow[4][64];
+    __shared__ T rr[5][4][64];
     __shared__ T red[4];
-    const int b = blockIdx.z;
-    const int n = w.ns[b];
-    if (i > n - 2) return;
     const int s = i + 1;
     const int b0 = s >> 6;
     const int nbk = (n + 63) >> 6;
-    const int R = b0 + blockIdx.x;
-    if (R >= nbk) return;
     const int tid = threadIdx.x, lane = tid & 63, part = tid >> 6;
-    const T tau = w.tau[(long long)b * w.sD + i];
     const T* PV = w.PV + (long long)b * w.sPV;
     const T* PS = w.PS + (long long)b * w.sPS;
     const T* P1 = w.P1 + (long long)b * w.sP1;
     const T* P2 = w.P2 + (long long)b * w.sP2;
-    T* Vp = w.Vp + (long long)b * w.sP;
+    const T* Vp = w.Vp + (long long)b * w.sP;
     T* Wp = w.Wp + (long long)b * w.sP;
     const int ldp = w.ldp;
-    T* A = w.A.at(b);
-    const int ld = w.A.ld;
+    const T* A = w.A.at(b);
+    const long long ld = w.A.ld;
+    const int r = R * 64 + lane;
+    const bool rv = (r >= s && r < n);
+    const int ls = s - b0 * 64;
 
-    // v^T A v
+    // ---- independent loads
+    const T tau = w.tau[(long long)b * w.sD + i];
     T acc = T(0);
     for (int sl = tid; sl < nslots; sl += 256) acc += PV[sl];
-    const T vAv = block_sum256(acc, red);
-    // p = W^T v (k < NBP), s = V^T v (NBP + k)
-    {
-        T x = T(0);
-        if (lane < 2 * NBP && (lane % NBP) < j)
-            for (int Cb = b0 + part; Cb < nbk; Cb += 4) x += PS[(long long)Cb * (2 * NBP) + lane];
-        rrow[part][lane] = x;
-        __syncthreads();
-        if (tid < 2 * NBP) sps[tid] = (rrow[0][tid] + rrow[1][tid]) + (rrow[2][tid] + rrow[3][tid]);
-        __syncthreads();
+    T psum = T(0);
+    if (lane < 2 * NBP && (lane % NBP) < j) {
+#pragma unroll 8
+        for (int Cb = b0 + part; Cb < nbk; Cb += 4) psum += PS[(long long)Cb * (2 * NBP) + lane];
     }
-    T pts = T(0);
-    for (int k = 0; k < j; k++) pts += sps[k] * sps[NBP + k];
-    const T wtv = tau * (vAv - T(2) * pts);
-
-    // y for the rows of block R
     const int nchR = (nbk - R + Kt - 1) / Kt;
     const int nitems = (R - b0 + 1) + nchR;
     T y = T(0);
+#pragma unroll 8
     for (int it = part; it < nitems; it += 4) {
-        if (it <= R - b0) {
-            const int Cb = b0 + it;
-            y += P1[((long long)Cb * w.nbk_max + R) * 64 + lane];
-        } else {
-            const int qq = it - (R - b0 + 1);
-            y += P2[((long long)R * w.maxchunk + qq) * 64 + lane];
+        if (it <= R - b0) y += P1[((long long)(b0 + it) * w.nbk_max + R) * 64 + lane];
+        else y += P2[((long long)R * w.maxchunk + (it - (R - b0 + 1))) * 64 + lane];
+    }
+    // y at row s (needed by every block for the update of column s): the
+    // diagonal-tile row sum plus the column sums of every chunk of strip b0
+    T ys = T(0);
+    if (part == 0) {
+        const int nch0 = (nbk - b0 + Kt - 1) / Kt;
+        for (int qq = lane; qq < nch0; qq += 64) ys += P2[((long long)b0 * w.maxchunk + qq) * 64 + ls];
+        if (lane == 0) ys += P1[((long long)b0 * w.nbk_max + b0) * 64 + ls];
+        ys = wave_sum(ys);
+    }
+    // panel rows: this wavefront owns columns k = part, part + 4, ... < j
+    T vr_k[NBP / 4], wr_k[NBP / 4], vs_k[NBP / 4], ws_k[NBP / 4];
+#pragma unroll
+    for (int t = 0; t < NBP / 4; t++) {
+        const int k = part + 4 * t;
+        const bool ok = k < j;
+        vr_k[t] = (ok && rv) ? Vp[r + (long long)k * ldp] : T(0);
+        wr_k[t] = (ok && rv) ? Wp[r + (long long)k * ldp] : T(0);
+        vs_k[t] = ok ? Vp[s + (long long)k * ldp] : T(0);
+        ws_k[t] = ok ? Wp[s + (long long)k * ldp] : T(0);
+    }
+    const T vr = rv ? Vp[r + (long long)j * ldp] : T(0);
+    const T acol = rv ? A[r + (long long)s * ld] : T(0);
+
+    // ---- reductions
+    const T vAv = block_sum256(acc, red);
+    rr[0][part][lane] = psum;
+    rr[1][part][lane] = y;
+    if (tid == 0) red[0] = ys;
+    __syncthreads();
+    if (tid < 2 * NBP) sps[tid] = (rr[0][0][tid] + rr[0][1][tid]) + (rr[0][2][tid] + rr[0][3][tid]);
+    const T yr = (rr[1][0][lane] + rr[1][1][lane]) + (rr[1][2][lane] + rr[1][3][lane]);
+    const T ysv = red[0];
+    __syncthreads();
+    T pts = T(0);
+    for (int k = 0; k < j; k++) pts += sps[k] * sps[NBP + k];
+    const T wtv = tau * (vAv - T(2) * pts);
+    // corr = V p + W s at row r and at row s, split over the wavefronts
+    T cr = T(0), csp = T(0);
+#pragma unroll
+    for (int t = 0; t < NBP / 4; t++) {
+        const int k = part + 4 * t;
+        if (k < j) {
+            cr += vr_k[t] * sps[k] + wr_k[t] * sps[NBP + k];
+            csp += vs_k[t] * sps[k] + ws_k[t] * sps[NBP + k];
         }
     }
+    rr[2][part][lane] = cr;
+    rr[3][part][lane] = csp;
     __syncthreads();
-    rrow[part][lane] = y;
-    __syncthreads();
-    y = (rrow[0][lane] + rrow[1][lane]) + (rrow[2][lane] + rrow[3][lane]);
-    __syncthreads();
-    const int r = R * 64 + lane;
-    const bool rv = (r >= s && r < n);
-    // corr = V p + W s over the previous panel columns
-    T cr = T(0);
-    if (rv)
-        for (int k = part; k < j; k += 4)
-            cr += Vp[r + (long long)k * ldp] * sps[k] + Wp[r + (long long)k * ldp] * sps[NBP + k];
-    rrow[part][lane] = cr;
-    __syncthreads();
-    cr = (rrow[0][lane] + rrow[1][lane]) + (rrow[2][lane] + rrow[3][lane]);
-    __syncthreads();
-    const T vr = rv ? Vp[r + (long long)j * ldp] : T(0);
-    const T wr = rv ? tau * (y - cr) - T(0.5) * tau * wtv * vr : T(0);
+    cr = (rr[2][0][lane] + rr[2][1][lane]) + (rr[2][2][lane] + rr[2][3][lane]);
+    csp = (rr[3][0][0] + rr[3][1][0]) + (rr[3][2][0] + rr[3][3][0]);
+    const T wr = rv ? tau * (yr - cr) - T(0.5) * tau * wtv * vr : T(0);
     if (part == 0 && r < n) Wp[r + (long long)j * ldp] = wr;
-
-    // w(s), needed by every block for the update of column s
-    T ws;
-    {
-        const int ls = s - b0 * 64;
-        T ys = P1[((long long)b0 * w.nbk_max + b0) * 64 + ls];
-        const int nch0 = (nbk - b0 + Kt - 1) / Kt;
-        for (int qq = 0; qq < nch0; qq++) ys += P2[((long long)b0 * w.maxchunk + qq) * 64 + ls];
-        T cs = T(0);
-        for (int k = 0; k < j; k++)
-            cs += Vp[s + (long long)k * ldp] * sps[k] + Wp[s + (long long)k * ldp] * sps[NBP + k];
-        ws = tau * (ys - cs) - T(0.5) * tau * wtv;
-    }
+    const T ws = tau * (ysv - csp) - T(0.5) * tau * wtv;
     // apply the panel (columns 0..j) to column s, rows of block R
     T u = T(0);
     if (rv) {
-        for (int k = part; k < j; k += 4)
-            u += Vp[r + (long long)k * ldp] * Wp[s + (long long)k * ldp] +
-                 Wp[r + (long long)k * ldp] * Vp[s + (long long)k * ldp];
-        if (part == 0) u += vr * ws + wr * T(1);
+#pragma unroll
+        for (int t = 0; t < NBP / 4; t++) {
+            const int k = part + 4 * t;
+            if (k < j) u += vr_k[t] * ws_k[t] + wr_k[t] * vs_k[t];
+        }
+        if (part == 0) u += vr * ws + wr;
     }
-    rrow[part][lane] = u;
+    rr[4][part][lane] = u;
     __syncthreads();
-    u = (rrow[0][lane] + rrow[1][lane]) + (rrow[2][lane] + rrow[3][lane]);
     if (part == 0) {
+        u = (rr[4][0][lane] + rr[4][1][lane]) + (rr[4][2][lane] + rr[4][3][lane]);
         T cval = T(0);
         if (rv) {
-            cval = A[r + (long long)s * ld] - u;
+            cval = acol - u;
             w.colbuf[(long long)b * w.sC + r] = cval;
             if (s == n - 1) w.d[(long long)b * w.sD + n - 1] = cval;
         }
         T q2 = (r >= s + 2 && r < n) ? cval * cval : T(0);
         q2 = wave_sum(q2);
         if (lane == 0) w.normpart[(long long)b * w.sNP + R] = q2;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+template <typename T, int NBP>
+__global__ __launch_bounds__(256) void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int slot = blockIdx.y * gridDim.x + blockIdx.x;
+    if (i > n - 2) { if (threadIdx.x == 0) w.PV[(long long)b * w.sPV + slot] = T(0); return; }
+    const int b0 = (i + 1) >> 6;
+    const int nbk = (n + 63) >> 6;
+    const int C = b0 + blockIdx.y;
+    const int q = blockIdx.x;
+    if (C >= nbk || q >= (nbk - C + Kt - 1) / Kt) {
+        if (threadIdx.x == 0) w.PV[(long long)b * w.sPV + slot] = T(0);
+        return;
+    }
+    const Refl<T> rf = refl_scalars(w, b, i, n);
+    symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, slot, rf);
+}
+
+template <typename T, int NBP>
+__global__ __launch_bounds__(256) void sytrd_finish_kernel(SytrdWs<T> w, int i, int j, int Kt, int nslots) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    if (i > n - 2) return;
+    const int b0 = (i + 1) >> 6;
+    const int nbk = (n + 63) >> 6;
+    const int R = b0 + blockIdx.x;
+    if (R >= nbk) return;
+    finish_item<T, NBP>(w, b, n, i, j, Kt, nslots, R);
+}
+
+// all columns [k0, k1) of one panel in one cooperative launch
+template <typename T, int NBP>
+__global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, int k1, int nbatch, int target) {
+    cg::grid_group grid = cg::this_grid();
+    const int P = gridDim.x;
+    for (int i = k0; i < k1; i++) {
+        const int j = i - k0;
+        const int b0 = (i + 1) >> 6;
+        const int nbt = w.nbk_max - b0;
+        const int Kt = sytrd_kt(nbt, nbatch, target);
+        const int gx = (nbt + Kt - 1) / Kt;
+        const int per_mat = gx * nbt;
+        // SYMV phase
+        int cur_b = -1;
+        Refl<T> rf = {T(0), T(0), T(0)};
+        for (int it = blockIdx.x; it < per_mat * nbatch; it += P) {
+            const int b = it / per_mat;
+            const int slot = it - b * per_mat;
+            const int strip = slot / gx, q = slot - strip * gx;
+            const int n = w.ns[b];
+            const int C = b0 + strip;
+            const int nbk = (n + 63) >> 6;
+            if (i > n - 2 || C >= nbk || q >= (nbk - C + Kt - 1) / Kt) {
+                if (threadIdx.x == 0) w.PV[(long long)b * w.sPV + slot] = T(0);
+                continue;
+            }
+            if (b != cur_b) { rf = refl_scalars(w, b, i, n); cur_b = b; }
+            symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, slot, rf);
+        }
+        grid.sync();
+        // finish phase
+        for (int it = blockIdx.x; it < nbt * nbatch; it += P) {
+            const int b = it / nbt;
+            const int R = b0 + (it - b * nbt);
+            const int n = w.ns[b];
+            if (i > n - 2 || R >= ((n + 63) >> 6)) continue;
+            finish_item<T, NBP>(w, b, n, i, j, Kt, per_mat, R);
+        }
+        grid.sync();
     }
 }
 
@@ -351,13 +460,24 @@ struct Syr2kProb {
     }
 };
 
+// persistent grid size for the cooperative panel kernel (0 if unavailable)
 template <typename T>
-int sytrd_tiles_per_chunk(int nbk_trail, int nbatch) {
-    long long tiles = (long long)nbk_trail * (nbk_trail + 1) / 2 * nbatch;
-    long long kt = tiles / 1536;
-    if (kt < 1) kt = 1;
-    if (kt > 8) kt = 8;
-    return (int)kt;
+static int sytrd_persistent_grid() {
+    static int cached = -1;
+    if (cached >= 0) return cached;
+    cached = 0;
+    int dev = 0, coop = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (!coop || ncu <= 0) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sytrd_panel_kernel<T, SYTRD_NBP>, 256, 0) != hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    cached = ncu * per_cu;
+    return cached;
 }
 
 template <typename T>
@@ -367,29 +487,56 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
     const bool timing = prof && prof->enabled && ns_host;
     const int nbk_max = w.nbk_max;
     hipLaunchKernelGGL(sytrd_init_kernel<T>, dim3(nbk_max, 1, nbatch), dim3(256), 0, st, w);
-    int k0 = 0;
-    for (int i = 0; i + 2 <= nmax; i++) {
-        const int j = i - k0;
-        const int b0 = (i + 1) >> 6;
-        const int nbt = nbk_max - b0;
-        const int Kt = sytrd_tiles_per_chunk<T>(nbt, nbatch);
-        const int gx = (nbt + Kt - 1) / Kt;
-        if (timing) prof->begin(st);
-        hipLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j,
-                           Kt);
-        if (timing) {
-            // algorithmic traffic: the lower trailing triangle, read once
-            double bytes = 0;
-            for (int b = 0; b < nbatch; b++) {
-                const double m = ns_host[b] - i - 1;
-                if (m > 0) bytes += m * (m + 1) * 0.5 * sizeof(T);
-            }
-            prof->end(st, 0, bytes);
+    // MBD_SYTRD_MODE=persistent selects the cooperative panel kernel; the
+    // default issues two launches per column (measured faster on gfx950,
+    // where a grid-wide barrier costs more than a dependent launch).
+    const char* mode = getenv("MBD_SYTRD_MODE");
+    const bool want_persistent = mode && std::string(mode) == "persistent";
+    const int P = want_persistent ? sytrd_persistent_grid<T>() : 0;
+    const bool persistent = P > 0;
+    for (int k0 = 0; k0 + 2 <= nmax; k0 += NBP) {
+        const int k1 = std::min(k0 + NBP, nmax - 1);
+        double bytes = 0;
+        if (timing)
+            for (int i = k0; i < k1; i++)
+                for (int b = 0; b < nbatch; b++) {
+                    const double m = ns_host[b] - i - 1;
+                    if (m > 0) bytes += m * (m + 1) * 0.5 * sizeof(T);
+                }
+        bool done = false;
+        if (persistent) {
+            if (timing) prof->begin(st);
+            SytrdWs<T> wc = w;
+            int a1 = k0, a2 = k1, a3 = nbatch, a4 = 2 * P;
+            void* args[] = {&wc, &a1, &a2, &a3, &a4};
+            done = hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T, NBP>, dim3(P), dim3(256), args, 0,
+                                              st) == hipSuccess;
+            if (!done) (void)hipGetLastError();
+            if (timing) prof->end(st, 0, done ? bytes : 0.0);
         }
-        hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j,
-                           Kt, gx * nbt);
-        if (j == NBP - 1 && i + 2 < nmax) {
-            const int t0 = k0 + NBP;
+        if (!done) {
+            for (int i = k0; i < k1; i++) {
+                const int j = i - k0;
+                const int b0 = (i + 1) >> 6;
+                const int nbt = nbk_max - b0;
+                const int Kt = sytrd_kt(nbt, nbatch, 1536);
+                const int gx = (nbt + Kt - 1) / Kt;
+                if (timing) prof->begin(st);
+                hipLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j, Kt);
+                if (timing) {
+                    double bb = 0;
+                    for (int b = 0; b < nbatch; b++) {
+                        const double m = ns_host[b] - i - 1;
+                        if (m > 0) bb += m * (m + 1) * 0.5 * sizeof(T);
+                    }
+                    prof->end(st, 0, bb);
+                }
+                hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j,
+                                   Kt, gx * nbt);
+            }
+        }
+        const int t0 = k0 + NBP;
+        if (k1 == k0 + NBP && t0 + 1 < nmax) {
             const int tm = (nmax - t0 + 63) / 64;
             Syr2kProb<T, NBP> p;
             p.A = w.A; p.ns = w.ns; p.Vp = w.Vp; p.Wp = w.Wp; p.ldp = w.ldp; p.sP = w.sP; p.t0 = t0;
@@ -404,7 +551,6 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                 }
                 prof->end(st, 1, flops);
             }
-            k0 += NBP;
         }
     }
 }
