@@ -790,6 +790,31 @@ static int cholesky(int n, double *A)
     return 0;
 }
 
+/* Lower Cholesky of I + K (K row-major, overwritten by L) for the frequency
+ * route, where I + K is close to the identity at large imaginary frequency:
+ * each pivot is carried as its deviation e_j from 1, so that
+ * ln det(I + K) = sum_j log1p(e_j) keeps its relative accuracy instead of
+ * losing it to log(1 + tiny).  Returns 0, or 2 if not positive definite. */
+static int cholesky_unit_shift(int n, double *K, double *logdet)
+{
+    double ld = 0.0;
+    for (int j = 0; j < n; j++) {
+        double *kj = K + (size_t)j * n;
+        double e = kj[j] - dot4(kj, kj, j);
+        if (!(1.0 + e > 0.0)) return 2;
+        double l = sqrt(1.0 + e);
+        kj[j] = l;
+        ld += log1p(e);
+#pragma omp parallel for schedule(static)
+        for (int i = j + 1; i < n; i++) {
+            double *ki = K + (size_t)i * n;
+            ki[j] = (ki[j] - dot4(ki, kj, j)) / l;
+        }
+    }
+    *logdet = ld;
+    return 0;
+}
+
 int orc_is_positive_definite(int n, const double *A)
 {
     double *C = (double *)malloc(sizeof(double) * (size_t)n * n);
@@ -819,19 +844,20 @@ int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
     for (int t = 0; t < npts && !rc; t++) {
         double u = 0.6 * (1.0 + x[t]) / (1.0 - x[t]);
         double du = 0.6 * 2.0 / ((1.0 - x[t]) * (1.0 - x[t])) * w[t];
-        /* I + alpha(iu)^{1/2} T alpha(iu)^{1/2} = D^{-1}(Q + u^2)D^{-1}, D = (Omega^2 + u^2)^{1/2} */
+        /* I + alpha(iu)^{1/2} T alpha(iu)^{1/2} = D^{-1}(Q + u^2)D^{-1} = I + K,
+         * D = (Omega^2 + u^2)^{1/2}, K = D^{-1}(Q - Omega^2)D^{-1} */
         for (int p = 0; p < n; p++) {
             double om = omega[p / 3];
             dsc[p] = 1.0 / sqrt(om * om + u * u);
         }
 #pragma omp parallel for schedule(static)
-        for (int p = 0; p < n; p++)
+        for (int p = 0; p < n; p++) {
+            double om = omega[p / 3];
             for (int s = 0; s < n; s++)
-                S[(size_t)p * n + s] = Q[(size_t)p * n + s] * dsc[p] * dsc[s] +
-                                       (p == s ? u * u * dsc[p] * dsc[p] : 0.0);
-        if (cholesky(n, S)) { rc = 2; break; }
+                S[(size_t)p * n + s] = (Q[(size_t)p * n + s] - (p == s ? om * om : 0.0)) * dsc[p] * dsc[s];
+        }
         double ld = 0.0;
-        for (int p = 0; p < n; p++) ld += 2.0 * log(S[(size_t)p * n + p]);
+        if (cholesky_unit_shift(n, S, &ld)) { rc = 2; break; }
         etot += du * ld / (2.0 * PI);
         /* rows of (Q + u^2)^{-1} = D^{-1} S^{-1} D^{-1} for the sampled atoms */
         for (int sa = 0; sa < nsample; sa++)
