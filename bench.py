@@ -79,8 +79,14 @@ def main():
     torch.cuda.synchronize()
 
     results = {}
+    tuned = {}
     for prec in ("fp64", "fp32_refined"):
         ctx = T.Context(0, prec)
+        log("[bench] %s autotune n=%d" % (prec, 3 * N))
+        t0 = time.perf_counter()
+        ctx.autotune([3 * N], os.path.join(ROOT, "gpurun_out", "tuning_%s.json" % prec)
+                     if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+        tuned[prec] = time.perf_counter() - t0
 
         def step():
             return T.evaluate(ctx, coords, a0, om, rv, beta=c["beta"], a=c["a"], gradients=True, errors=True)
@@ -140,6 +146,7 @@ def main():
                                "seed 2, 0.1 atoms/A^3, alpha0 x %.4f (collapse rule)" % c["alpha_scale"],
                    "path": "FP32 reduction/D&C/back-transform on matrix cores + 1 FP64 Ogita-Aishima step"},
         "fp64_s": results["fp64"]["s"],
+        "autotune_s": tuned,
         "speedup_fp32_refined_vs_fp64": results["fp64"]["s"] / results["fp32_refined"]["s"],
         "errors_vs_fp64": {"energy_per_atom_Ha": dE, "max_grad_coords_Ha_per_bohr": dG,
                            "max_grad_alpha0": dA,

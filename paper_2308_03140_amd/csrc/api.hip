@@ -23,9 +23,43 @@ struct mbd_ctx {
     int err_code = 0;
     std::string err_origin, err_msg;
     LaunchProfiler prof;
+    // autotuned SYMV work-item targets per matrix order, per precision (0 FP64, 1 FP32)
+    std::map<int, int> tune[2];
+    // captured batch launch sequences, keyed by batch signature
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        SysDesc* h_desc = nullptr;     // pinned staging of the system descriptors
+        int* h_ns = nullptr;           // pinned matrix orders
+        unsigned* h_status = nullptr;  // pinned status read-back
+        double* h_stats = nullptr;     // pinned refinement statistics
+        int* h_skip = nullptr;         // pinned second-step skip flags
+        int nsys = 0, nmat = 0;
+        bool ok = false;
+    };
+    std::map<std::string, Graph> graphs;
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    void drop_graphs() {
+        for (auto& kv : graphs) {
+            if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+            hipHostFree(kv.second.h_desc);
+            hipHostFree(kv.second.h_ns);
+            hipHostFree(kv.second.h_status);
+            hipHostFree(kv.second.h_stats);
+            hipHostFree(kv.second.h_skip);
+        }
+        graphs.clear();
+    }
 };
 
 namespace {
+
+// How run_core is being driven: eagerly (nullptr) or while capturing a graph,
+// in which case uploads come from and the status goes to pinned buffers.
+struct RunMode {
+    bool capturing = false;
+    mbd_ctx::Graph* g = nullptr;
+};
 
 mbd_status fail(mbd_ctx* c, mbd_status code, const char* origin, const std::string& msg) {
     if (c) {
@@ -56,6 +90,8 @@ void* ws(mbd_ctx* c, const char* name, size_t bytes) {
     }
     if (it != c->bufs.end()) {
         hipStreamSynchronize(c->stream);
+        if (c->gstream) hipStreamSynchronize(c->gstream);
+        c->drop_graphs();  // captured sequences hold the old address
         hipFree(it->second.first);
         c->total -= old;
         c->bufs.erase(it);
@@ -82,21 +118,24 @@ template <> const char* tname<float>() { return "f"; }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-struct EigResult {
-    int src;  // which D&C buffer holds the vectors
-};
+// SYMV work-item target for a matrix order: the tuned entry nearest in log(n)
+int tuned_target(const mbd_ctx* c, int prec, int n) {
+    const auto& t = c->tune[prec];
+    if (t.empty()) return 1536;
+    int best = 1536;
+    double bd = 1e300;
+    for (const auto& kv : t) {
+        const double d = std::fabs(std::log((double)kv.first) - std::log((double)n));
+        if (d < bd) { bd = d; best = kv.second; }
+    }
+    return best;
+}
 
-// Full dense symmetric eigensolver on a batch: reduction, D&C, back-transform.
+// Reduction workspace for a batch of nbatch matrices of order <= nmax.
 template <typename T>
-mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host, int nmax, int nbatch, bool vectors,
-                   T* w_out, long long sW, MatBatch<T>* Xout) {
+mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int nbatch, SytrdWs<T>& sw) {
     const std::string t = tname<T>();
-    const hipStream_t st = c->stream;
     const int nbk = (nmax + 63) / 64;
-    const int ldz = round_up(nmax, 64);
-    const long long sZ = (long long)ldz * nmax;
-    // --- reduction workspace
-    SytrdWs<T> sw;
     sw.A = A; sw.ns = ns; sw.nmax = nmax; sw.nbk_max = nbk; sw.maxchunk = nbk;
     sw.ldp = round_up(nmax, 64);
     sw.sP = (long long)sw.ldp * SYTRD_NBP;
@@ -115,6 +154,22 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     if (!sw.Vp || !sw.Wp || !sw.colbuf || !sw.normpart || !sw.P1 || !sw.P2 || !sw.PS || !sw.PV || !sw.d ||
         !sw.e || !sw.tau)
         return (mbd_status)c->err_code;
+    return MBD_OK;
+}
+
+// Full dense symmetric eigensolver on a batch: reduction, D&C, back-transform.
+template <typename T>
+mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host, int nmax, int nbatch, bool vectors,
+                   T* w_out, long long sW, MatBatch<T>* Xout) {
+    const std::string t = tname<T>();
+    const hipStream_t st = c->stream;
+    const int nbk = (nmax + 63) / 64;
+    const int ldz = round_up(nmax, 64);
+    const long long sZ = (long long)ldz * nmax;
+    // --- reduction
+    SytrdWs<T> sw;
+    if (make_sytrd_ws<T>(c, A, ns, nmax, nbatch, sw) != MBD_OK) return (mbd_status)c->err_code;
+    sw.chunk_target = tuned_target(c, sizeof(T) == 8 ? 0 : 1, nmax);
     sytrd_launch<T>(sw, nbatch, nmax, st, ns_host, &c->prof);
     HIPCHK(hipGetLastError(), "sytrd");
 
@@ -338,7 +393,8 @@ mbd_status setup_periodic(mbd_ctx* c, const mbd_system* s, SysDesc& d, PeriodicS
 // One or more finite systems, or one periodic system (per != nullptr: one
 // embedded matrix per q point), all stages on the context stream.
 mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::vector<int>& codes,
-                    const PeriodicSetup* per) {
+                    const PeriodicSetup* per, const RunMode* mode = nullptr) {
+    const bool capturing = mode && mode->capturing;
     const hipStream_t st = c->stream;
     const int nsys = (int)sds.size();
     int Nmax = 0, ntot = 0;
@@ -377,8 +433,13 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         return (mbd_status)c->err_code;
     std::vector<int> nsh(nmat);
     for (int b = 0; b < nmat; b++) nsh[b] = per ? 6 * sds[0].N : 3 * sds[b].N;
-    HIPCHK(hipMemcpyAsync(sd_dev, sds.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st), "upload");
-    HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nmat, hipMemcpyHostToDevice, st), "upload");
+    if (capturing) {
+        HIPCHK(hipMemcpyAsync(sd_dev, mode->g->h_desc, sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(hipMemcpyAsync(ns_dev, mode->g->h_ns, sizeof(int) * nmat, hipMemcpyHostToDevice, st), "upload");
+    } else {
+        HIPCHK(hipMemcpyAsync(sd_dev, sds.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nmat, hipMemcpyHostToDevice, st), "upload");
+    }
     fill_u32_launch(st, status, nsys, 0u);
     mbd_prep_launch(st, sd_dev, nsys, Nmax, om, cc, status);
     double* qcart = nullptr;
@@ -402,6 +463,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     MatBatch<double> X;
     std::vector<double> stats_h;
     double* stats = nullptr;
+    int* skip_dev = nullptr;
     if (!fp32) {
         mbd_status r = run_eig<double>(c, A64, ns_dev, nsh.data(), nmax, nmat, grads, lam, nmax, &X);
         if (r != MBD_OK) return r;
@@ -411,40 +473,56 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         MatBatch<float> X32;
         mbd_status r = run_eig<float>(c, A32, ns_dev, nsh.data(), nmax, nmat, true, lam32, nmax, &X32);
         if (r != MBD_OK) return r;
-        // one Ogita-Aishima step in FP64 against the FP64 Q held in A64
+        // Ogita-Aishima refinement in FP64 against the FP64 Q held in A64:
+        // step one for every matrix, step two where step one separated every
+        // pair but left a large second-order remainder (device-side flags)
         MatBatch<double> Xd = {wsT<double>(c, "oaX", (size_t)stride * nmat), ld, stride};
         MatBatch<double> Y = {wsT<double>(c, "oaY", (size_t)stride * nmat), ld, stride};
         MatBatch<double> S = {wsT<double>(c, "oaS", (size_t)stride * nmat), ld, stride};
+        MatBatch<double> G = {wsT<double>(c, "oaG", (size_t)stride * nmat), ld, stride};
         double* colpart = wsT<double>(c, "oacol", (size_t)4 * nmax * nmat);
-        stats = wsT<double>(c, "oastats", (size_t)4 * nmat);
-        if (!Xd.p || !Y.p || !S.p || !colpart || !stats) return (mbd_status)c->err_code;
+        stats = wsT<double>(c, "oastats", (size_t)8 * nmat);
+        unsigned* nclust = wsT<unsigned>(c, "oanclust", nmat);
+        int* skip2 = wsT<int>(c, "oaskip2", nmat);
+        if (!Xd.p || !Y.p || !S.p || !G.p || !colpart || !stats || !nclust || !skip2)
+            return (mbd_status)c->err_code;
         oa_f2d_launch(st, ns_dev, nmax, nmat, X32, Xd);
-        // Y = Q X
+        // step one: X0 in Xd -> X1 in Y
         gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, A64.p, ld, stride, Xd.p, ld, stride, Y.p, ld,
-                             stride, 1.0, 0.0, false);
-        // S = X^T Y
+                             stride, 1.0, 0.0, false);                                     // Y = Q X0
         gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Xd.p, ld, stride, Y.p, ld, stride, S.p, ld,
-                             stride, 1.0, 0.0, false);
-        // G = X^T X (lower) into A64: Q is not needed after Y = Q X
-        MatBatch<double> G = A64;
+                             stride, 1.0, 0.0, false);                                     // S = X0^T Q X0
         gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Xd.p, ld, stride, Xd.p, ld, stride, G.p, ld,
-                             stride, 1.0, 0.0, true);
-        oa_stats_launch(st, ns_dev, nmax, nmat, S, G, lam, nmax, colpart, stats);
-        oa_update_launch(st, ns_dev, nmax, nmat, S, G, lam, nmax, stats);
-        // X' = X + X E  (into Y)
+                             stride, 1.0, 0.0, true);                                      // G = X0^T X0
+        oa_stats_launch(st, ns_dev, nmax, nmat, S, G, lam, nmax, colpart, stats, nclust, nullptr);
+        oa_update_launch(st, ns_dev, nmax, nmat, S, G, lam, nmax, stats, nclust, colpart, nullptr);
         copy_mat_launch(st, ns_dev, nmax, nmat, Xd, Y);
         gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, Xd.p, ld, stride, S.p, ld, stride, Y.p, ld,
-                             stride, 1.0, 1.0, false);
+                             stride, 1.0, 1.0, false);                                     // Y = X0 + X0 E
+        // step two: X1 in Y -> X2 in S (skipped matrices copy X1)
+        oa_second_flags_launch(st, ns_dev, nmat, nclust, colpart, nmax, stats, skip2);
+        double* stats2 = stats + 4 * nmat;
+        gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, A64.p, ld, stride, Y.p, ld, stride, S.p, ld,
+                             stride, 1.0, 0.0, false, skip2);                              // S = Q X1
+        gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Y.p, ld, stride, S.p, ld, stride, Xd.p, ld,
+                             stride, 1.0, 0.0, false, skip2);                              // Xd = X1^T Q X1
+        gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Y.p, ld, stride, Y.p, ld, stride, G.p, ld,
+                             stride, 1.0, 0.0, true, skip2);                               // G = X1^T X1
+        oa_stats_launch(st, ns_dev, nmax, nmat, Xd, G, lam, nmax, colpart, stats2, nclust, skip2);
+        oa_update_launch(st, ns_dev, nmax, nmat, Xd, G, lam, nmax, stats2, nclust, colpart, skip2);
+        copy_mat_launch(st, ns_dev, nmax, nmat, Y, S);
+        gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, Y.p, ld, stride, Xd.p, ld, stride, S.p, ld,
+                             stride, 1.0, 1.0, false, skip2);                              // S = X1 + X1 E
+        skip_dev = skip2;
         HIPCHK(hipGetLastError(), "refine");
-        X = Y;
+        X = S;
     }
     mbd_energy_launch(st, sd_dev, nsys, ns_dev, lam, nmax, om, status, lmin);
     HIPCHK(hipGetLastError(), "energy");
     if (grads) {
         hipLaunchKernelGGL(grad_gate_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, status, nsys, sd_dev);
         mbd_invsqrt4_launch(st, ns_dev, nmax, nmat, lam, nmax, sc);
-        MatBatch<double> M = A64;
-        if (fp32) M = {wsT<double>(c, "oaS", (size_t)stride * nmat), ld, stride};  // S (E) is free now
+        MatBatch<double> M = A64;  // FP64: reflectors no longer needed; FP32: Q no longer needed
         mbd_inv_sqrt_launch(st, ns_dev, nmax, nmat, X, sc, nmax, M);
         mbd_mirror_launch(st, ns_dev, nmax, nmat, M);
         if (per) {
@@ -458,11 +536,24 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         }
         HIPCHK(hipGetLastError(), "gradients");
     }
+    if (capturing) {
+        HIPCHK(hipMemcpyAsync(mode->g->h_status, status, sizeof(unsigned) * nsys, hipMemcpyDeviceToHost, st), "status");
+        if (stats) {
+            HIPCHK(hipMemcpyAsync(mode->g->h_stats, stats, sizeof(double) * 8 * nmat, hipMemcpyDeviceToHost, st),
+                   "status");
+            HIPCHK(hipMemcpyAsync(mode->g->h_skip, skip_dev, sizeof(int) * nmat, hipMemcpyDeviceToHost, st),
+                   "status");
+        }
+        return MBD_OK;
+    }
     std::vector<unsigned> sth(nsys);
     HIPCHK(hipMemcpyAsync(sth.data(), status, sizeof(unsigned) * nsys, hipMemcpyDeviceToHost, st), "status");
+    std::vector<int> skip_h;
     if (stats) {
-        stats_h.resize(4 * nmat);
-        HIPCHK(hipMemcpyAsync(stats_h.data(), stats, sizeof(double) * 4 * nmat, hipMemcpyDeviceToHost, st), "status");
+        stats_h.resize(8 * nmat);
+        skip_h.resize(nmat);
+        HIPCHK(hipMemcpyAsync(stats_h.data(), stats, sizeof(double) * 8 * nmat, hipMemcpyDeviceToHost, st), "status");
+        HIPCHK(hipMemcpyAsync(skip_h.data(), skip_dev, sizeof(int) * nmat, hipMemcpyDeviceToHost, st), "status");
     }
     HIPCHK(hipStreamSynchronize(st), "synchronize");
     codes.assign(nsys, MBD_OK);
@@ -472,13 +563,14 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         if (sds[s].errors && codes[s] != MBD_ERR_INVALID_ARGUMENT) {
             double e3[3] = {0.0, 0.0, 0.0};
             if (stats) {
-                // worst matrix of the system
+                // worst matrix of the system: max|X^T X - I| and delta of the first
+                // step, number of steps taken
                 for (int q = 0; q < sds[s].nmat; q++) {
                     const int b = sds[s].mat0 + q;
                     e3[0] = std::max(e3[0], stats_h[4 * b + 1]);
                     e3[2] = std::max(e3[2], stats_h[4 * b]);
+                    e3[1] = std::max(e3[1], skip_h[b] ? 1.0 : 2.0);
                 }
-                e3[1] = 1.0;
             }
             HIPCHK(hipMemcpy(sds[s].errors + 1, e3, sizeof(e3), hipMemcpyHostToDevice), "errors");
         }
@@ -523,6 +615,11 @@ mbd_status mbd_destroy(mbd_ctx* c) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
+    if (c->gstream) hipStreamSynchronize(c->gstream);
+    c->drop_graphs();
+    if (c->gstream) hipStreamDestroy(c->gstream);
+    if (c->ev_in) hipEventDestroy(c->ev_in);
+    if (c->ev_out) hipEventDestroy(c->ev_out);
     for (auto& kv : c->bufs) hipFree(kv.second.first);
     delete c;
     return MBD_OK;
@@ -562,15 +659,92 @@ mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, 
     if (n_sys < 1 || !sys || !out || !status)
         return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate_batch", "bad batch arguments");
     std::vector<SysDesc> sds(n_sys);
+    std::string sig = std::to_string((int)c->prec) + ":" + std::to_string(want) + ":";
     for (int i = 0; i < n_sys; i++) {
         mbd_status r = check_system(c, &sys[i], want, &out[i], false);
         if (r != MBD_OK) return r;
         sds[i] = make_desc(&sys[i], want, &out[i]);
+        sig += std::to_string(sys[i].n_atoms) + ",";
     }
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_evaluate_batch", "hipSetDevice");
-    std::vector<int> codes;
-    mbd_status r = run_core(c, sds, want, codes, nullptr);
-    if (r != MBD_OK) return r;
+    std::vector<int> codes(n_sys, MBD_OK);
+    const char* nograph = std::getenv("MBD_NO_GRAPH");
+    const bool use_graph = !(nograph && nograph[0] == '1') && !c->prof.enabled;
+    auto it = use_graph ? c->graphs.find(sig) : c->graphs.end();
+    if (it != c->graphs.end() && it->second.ok) {
+        // replay: refresh the pinned descriptors, run after the caller's stream
+        mbd_ctx::Graph& g = it->second;
+        int Nt = 0;
+        for (int i = 0; i < n_sys; i++) {
+            sds[i].atom_off = Nt; Nt += sds[i].N;
+            sds[i].mat0 = i; sds[i].nmat = 1; sds[i].weight = 0.5; sds[i].embed = 0;
+        }
+        HIPCHK(hipStreamSynchronize(c->gstream), "graph");
+        std::memcpy(g.h_desc, sds.data(), sizeof(SysDesc) * n_sys);
+        HIPCHK(hipEventRecord(c->ev_in, c->stream), "graph");
+        HIPCHK(hipStreamWaitEvent(c->gstream, c->ev_in, 0), "graph");
+        HIPCHK(hipGraphLaunch(g.exec, c->gstream), "graph launch");
+        HIPCHK(hipEventRecord(c->ev_out, c->gstream), "graph");
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_out, 0), "graph");
+        HIPCHK(hipStreamSynchronize(c->gstream), "graph");
+        for (int i = 0; i < n_sys; i++) {
+            const unsigned st = g.h_status[i];
+            if (st & (MBD_ST_BAD_INPUT | MBD_ST_COINCIDENT)) codes[i] = MBD_ERR_INVALID_ARGUMENT;
+            else if (st & MBD_ST_COLLAPSE) codes[i] = MBD_ERR_NEGATIVE_EIGENVALUE;
+            if (sds[i].errors && codes[i] != MBD_ERR_INVALID_ARGUMENT) {
+                double e3[3] = {0.0, 0.0, 0.0};
+                if (c->prec == MBD_FP32_REFINED) {
+                    e3[0] = g.h_stats[4 * i + 1];
+                    e3[1] = g.h_skip[i] ? 1.0 : 2.0;
+                    e3[2] = g.h_stats[4 * i];
+                }
+                HIPCHK(hipMemcpy(sds[i].errors + 1, e3, sizeof(e3), hipMemcpyHostToDevice), "errors");
+            }
+        }
+    } else {
+        mbd_status r = run_core(c, sds, want, codes, nullptr);
+        if (r != MBD_OK) return r;
+        if (use_graph && it == c->graphs.end()) {
+            // capture the same launch sequence once for later calls of this signature
+            if (!c->gstream) {
+                if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
+                    hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+                    hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+                    return fail(c, MBD_ERR_DEVICE, "mbd_evaluate_batch", "stream creation");
+            }
+            mbd_ctx::Graph g;
+            g.nsys = n_sys;
+            g.nmat = n_sys;
+            bool ok = hipHostMalloc((void**)&g.h_desc, sizeof(SysDesc) * n_sys, 0) == hipSuccess &&
+                      hipHostMalloc((void**)&g.h_ns, sizeof(int) * n_sys, 0) == hipSuccess &&
+                      hipHostMalloc((void**)&g.h_status, sizeof(unsigned) * n_sys, 0) == hipSuccess &&
+                      hipHostMalloc((void**)&g.h_stats, sizeof(double) * 8 * n_sys, 0) == hipSuccess &&
+                      hipHostMalloc((void**)&g.h_skip, sizeof(int) * n_sys, 0) == hipSuccess;
+            if (ok) {
+                std::memcpy(g.h_desc, sds.data(), sizeof(SysDesc) * n_sys);
+                for (int i = 0; i < n_sys; i++) g.h_ns[i] = 3 * sds[i].N;
+                RunMode m;
+                m.capturing = true;
+                m.g = &g;
+                hipStream_t user = c->stream;
+                c->stream = c->gstream;
+                hipGraph_t graph = nullptr;
+                std::vector<int> dummy;
+                ok = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    const mbd_status rc = run_core(c, sds, want, dummy, nullptr, &m);
+                    const bool end_ok = hipStreamEndCapture(c->gstream, &graph) == hipSuccess;
+                    ok = rc == MBD_OK && end_ok && graph &&
+                         hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+                    if (graph) hipGraphDestroy(graph);
+                }
+                c->stream = user;
+                (void)hipGetLastError();
+            }
+            g.ok = ok && g.exec;
+            c->graphs[sig] = g;  // a failed capture is remembered: that signature stays eager
+        }
+    }
     mbd_status first = MBD_OK;
     for (int i = 0; i < n_sys; i++) {
         status[i] = codes[i];
@@ -618,14 +792,131 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
     return MBD_OK;
 }
 
-mbd_status mbd_autotune(mbd_ctx* c, const int32_t*, int32_t, const char*) {
-    if (!c) return MBD_ERR_INVALID_ARGUMENT;
-    return fail(c, MBD_ERR_UNSUPPORTED, "mbd_autotune", "not available in this build");
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+mbd_status autotune_size(mbd_ctx* c, int n, int* best_target, double* best_ms) {
+    const int ld = round_up(n, 64);
+    const long long stride = (long long)ld * n;
+    T* A = wsT<T>(c, std::string("tuneA") + tname<T>(), stride);
+    T* B = wsT<T>(c, std::string("tuneB") + tname<T>(), stride);
+    int* ns_dev = wsT<int>(c, "tune_ns", 1);
+    if (!A || !B || !ns_dev) return (mbd_status)c->err_code;
+    HIPCHK(hipMemcpyAsync(ns_dev, &n, sizeof(int), hipMemcpyHostToDevice, c->stream), "upload");
+    fill_sym_random_launch<T>(c->stream, n, B, ld, 12345u);
+    SytrdWs<T> sw;
+    MatBatch<T> Ab = {A, ld, stride};
+    if (make_sytrd_ws<T>(c, Ab, ns_dev, n, 1, sw) != MBD_OK) return (mbd_status)c->err_code;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0), "event");
+    HIPCHK(hipEventCreate(&e1), "event");
+    const int cand[] = {256, 512, 768, 1024, 1536, 2048, 3072, 4096};
+    *best_ms = 1e300;
+    *best_target = 1536;
+    int nh = n;
+    for (int target : cand) {
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 2; rep++) {
+            HIPCHK(hipMemcpyAsync(A, B, sizeof(T) * stride, hipMemcpyDeviceToDevice, c->stream), "copy");
+            sw.chunk_target = target;
+            HIPCHK(hipEventRecord(e0, c->stream), "event");
+            sytrd_launch<T>(sw, 1, n, c->stream, &nh, nullptr);
+            HIPCHK(hipEventRecord(e1, c->stream), "event");
+            HIPCHK(hipEventSynchronize(e1), "event");
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            ms_min = std::min(ms_min, ms);
+        }
+        if (ms_min < *best_ms) { *best_ms = ms_min; *best_target = target; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return MBD_OK;
 }
 
-mbd_status mbd_load_tuning(mbd_ctx* c, const char*) {
+bool write_tuning(const mbd_ctx* c, const char* path) {
+    FILE* f = std::fopen(path, "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    const char* names[2] = {"fp64", "fp32"};
+    for (int p = 0; p < 2; p++) {
+        std::fprintf(f, "  \"%s\": {", names[p]);
+        bool first = true;
+        for (const auto& kv : c->tune[p]) {
+            std::fprintf(f, "%s\"%d\": %d", first ? "" : ", ", kv.first, kv.second);
+            first = false;
+        }
+        std::fprintf(f, "}%s\n", p == 0 ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    return std::fclose(f) == 0;
+}
+
+// parses {"fp64": {"n": target, ...}, "fp32": {...}} (the format written above)
+bool read_tuning(mbd_ctx* c, const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    std::string txt;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, k);
+    std::fclose(f);
+    const char* names[2] = {"\"fp64\"", "\"fp32\""};
+    for (int p = 0; p < 2; p++) {
+        const size_t at = txt.find(names[p]);
+        if (at == std::string::npos) continue;
+        const size_t lb = txt.find('{', at), rb = txt.find('}', at);
+        if (lb == std::string::npos || rb == std::string::npos || rb < lb) return false;
+        const std::string body = txt.substr(lb + 1, rb - lb - 1);
+        size_t pos = 0;
+        std::map<int, int> tab;
+        while ((pos = body.find('"', pos)) != std::string::npos) {
+            const size_t q2 = body.find('"', pos + 1);
+            const size_t colon = body.find(':', q2);
+            if (q2 == std::string::npos || colon == std::string::npos) return false;
+            const int key = std::atoi(body.substr(pos + 1, q2 - pos - 1).c_str());
+            const int val = std::atoi(body.c_str() + colon + 1);
+            if (key <= 0 || val <= 0) return false;
+            tab[key] = val;
+            pos = body.find(',', colon);
+            if (pos == std::string::npos) break;
+        }
+        c->tune[p] = tab;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+mbd_status mbd_autotune(mbd_ctx* c, const int32_t* sizes, int32_t nsizes, const char* path) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;
-    return fail(c, MBD_ERR_UNSUPPORTED, "mbd_load_tuning", "not available in this build");
+    c->err_code = 0;
+    if (!sizes || nsizes < 1) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_autotune", "no sizes");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_autotune", "hipSetDevice");
+    const int p = c->prec == MBD_FP32_REFINED ? 1 : 0;
+    for (int k = 0; k < nsizes; k++) {
+        const int n = sizes[k];
+        if (n < 2) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_autotune", "sizes must be >= 2");
+        int target = 1536;
+        double ms = 0;
+        const mbd_status r = p ? autotune_size<float>(c, n, &target, &ms) : autotune_size<double>(c, n, &target, &ms);
+        if (r != MBD_OK) return r;
+        c->tune[p][n] = target;
+    }
+    if (path && !write_tuning(c, path)) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_autotune", "cannot write table");
+    return MBD_OK;
+}
+
+mbd_status mbd_load_tuning(mbd_ctx* c, const char* path) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    c->err_code = 0;
+    if (!path || !read_tuning(c, path))
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_load_tuning", "cannot read tuning table");
+    return MBD_OK;
 }
 
 mbd_status mbd_set_profiling(mbd_ctx* c, int enable) {

@@ -149,8 +149,10 @@ struct GemmGeneral {
     T alpha, beta;
     int lower_only;      // only tiles (and elements) with row >= col
     int tiles_n;         // tiles along N (grid.x = tiles_m * tiles_n, or lower count)
+    const int* skip;     // optional per-matrix flag: nonzero skips the matrix
     __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
+        if (skip && skip[bz]) return false;
         int Mb = ns ? ns[bz] : M, Nb = ns ? ns[bz] : N, Kb = ns ? ns[bz] : K;
         int ti, tj;
         if (lower_only) lower_tile(bx, ti, tj);

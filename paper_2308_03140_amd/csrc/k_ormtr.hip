@@ -223,11 +223,12 @@ template void ormtr_launch<float>(const OrmtrWs<float>&, int, int, hipStream_t);
 template <typename T, bool TA, bool TB>
 static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
                             long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
-                            T alpha, T beta, bool lower_only) {
+                            T alpha, T beta, bool lower_only, const int* skip) {
     GemmGeneral<T, TA, TB> p;
     p.A = A; p.lda = lda; p.sA = sA; p.B = B; p.ldb = ldb; p.sB = sB; p.C = C; p.ldc = ldc; p.sC = sC;
     p.ns = ns; p.M = p.N = p.K = nmax; p.alpha = alpha; p.beta = beta;
     p.lower_only = lower_only ? 1 : 0;
+    p.skip = skip;
     const int t = (nmax + 63) / 64;
     p.tiles_n = t;
     const int grid = lower_only ? t * (t + 1) / 2 : t * t;
@@ -237,14 +238,16 @@ static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch,
 template <typename T>
 void gemm_batched(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int nbatch, const T* A,
                   int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
-                  T alpha, T beta, bool lower_only) {
-    if (!ta && !tb) gemm_gen_launch<T, false, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only);
-    else if (ta && !tb) gemm_gen_launch<T, true, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only);
-    else if (!ta && tb) gemm_gen_launch<T, false, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only);
-    else gemm_gen_launch<T, true, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only);
+                  T alpha, T beta, bool lower_only, const int* skip) {
+    if (!ta && !tb) gemm_gen_launch<T, false, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip);
+    else if (ta && !tb) gemm_gen_launch<T, true, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip);
+    else if (!ta && tb) gemm_gen_launch<T, false, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip);
+    else gemm_gen_launch<T, true, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip);
 }
 
 template void gemm_batched<double>(hipStream_t, bool, bool, const int*, int, int, const double*, int, long long,
-                                   const double*, int, long long, double*, int, long long, double, double, bool);
+                                   const double*, int, long long, double*, int, long long, double, double, bool,
+                                   const int*);
 template void gemm_batched<float>(hipStream_t, bool, bool, const int*, int, int, const float*, int, long long,
-                                  const float*, int, long long, float*, int, long long, float, float, bool);
+                                  const float*, int, long long, float*, int, long long, float, float, bool,
+                                  const int*);

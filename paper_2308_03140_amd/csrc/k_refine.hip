@@ -1,18 +1,27 @@
-// One refinement step of approximate eigenpairs (Ogita & Aishima, "Iterative
+// Refinement of approximate eigenpairs (Ogita & Aishima, "Iterative
 // refinement for symmetric eigenvalue decomposition", 2018) in FP64 against
-// the FP64 Q, applied to FP32 eigenvectors from the FP32 diagonalisation:
+// the FP64 Q, applied to the eigenvectors of the FP32 diagonalisation:
 //   G = X^T X, R = I - G, S = X^T Q X
 //   lambda_i = S_ii / (1 - R_ii)
 //   E_ij = (S_ij + lambda_j R_ij)/(lambda_j - lambda_i)  if |lambda_i - lambda_j| > delta
 //        = R_ij / 2                                      otherwise (and on the diagonal)
 //   X <- X + X E
 // delta = 2 (||S - diag(lambda)||_F + max|lambda| ||R||_F), the Frobenius
-// bounds of the spectral norms in the method's separation threshold.
+// bounds of the spectral norms in the method's separation threshold.  Pairs
+// closer than delta are only orthogonalised by a step.
+// A step converges quadratically when every pair is separated: its leftover
+// is dominated by the second-order terms of the correction, of the size
+// eta = max_i sum_{j != i} E_ji^2 (the norm growth of column i).  A second
+// step is taken for a matrix whose first step met no pair inside delta and
+// had eta > OA_ETA_SECOND; the decision is made on the device through
+// per-matrix skip flags, so captured launch graphs stay valid.
 // The products are batched GEMMs (gemm_mfma.h); these kernels do the
 // element-wise parts.
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
+
+#define OA_ETA_SECOND 1e-9
 
 __global__ __launch_bounds__(256) void oa_f2d_kernel(const int* ns, MatBatch<float> X32, MatBatch<double> Xd) {
     const int b = blockIdx.z;
@@ -40,9 +49,11 @@ __global__ void fill_u32_kernel(unsigned* p, int n, unsigned v) {
 // lambda_i = S_ii / G_ii, then per-column partial sums of the squared
 // off-diagonal residuals (S - diag lambda) and R = I - G (G lower only)
 __global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
-                                                            double* lam, long long sL, double* colpart) {
+                                                            double* lam, long long sL, double* colpart,
+                                                            const int* skip) {
     __shared__ double red[4];
     const int b = blockIdx.z;
+    if (skip && skip[b]) return;
     const int n = ns[b];
     const int c = blockIdx.x;
     if (c >= n) return;
@@ -73,11 +84,13 @@ __global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatc
     }
 }
 
-// per matrix: stats = {delta, max|R|}
-__global__ __launch_bounds__(256) void oa_delta_kernel(const int* ns, const double* colpart, long long sL,
-                                                         double* stats) {
+// per matrix: stats = {delta, max|R|}; clears the cluster-pair counter and
+// the per-column accumulators of the correction's norm growth
+__global__ __launch_bounds__(256) void oa_delta_kernel(const int* ns, double* colpart, long long sL,
+                                                         double* stats, unsigned* nclust, const int* skip) {
     __shared__ double red[4];
     const int b = blockIdx.x;
+    if (skip && skip[b]) return;
     const int n = ns[b];
     double s2 = 0, r2 = 0, rmax = 0, lmax = 0;
     for (int c = threadIdx.x; c < n; c += 256) {
@@ -86,6 +99,7 @@ __global__ __launch_bounds__(256) void oa_delta_kernel(const int* ns, const doub
         r2 += colpart[o + 1];
         rmax = fmax(rmax, colpart[o + 2]);
         lmax = fmax(lmax, colpart[o + 3]);
+        colpart[o] = 0.0;  // reused as the column norm growth of E
     }
     s2 = block_sum256(s2, red);
     r2 = block_sum256(r2, red);
@@ -94,28 +108,61 @@ __global__ __launch_bounds__(256) void oa_delta_kernel(const int* ns, const doub
     if (threadIdx.x == 0) {
         stats[4 * b] = 2.0 * (sqrt(s2) + lmax * sqrt(r2));
         stats[4 * b + 1] = rmax;
+        nclust[b] = 0u;
     }
 }
 
-// S <- E (in place)
+// S <- E (in place); counts the pairs closer than delta and accumulates
+// sum_{i != j} E_ij^2 per column j into colpart[4 j]
 __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
-                                                     const double* lam, long long sL, const double* stats) {
+                                                     const double* lam, long long sL, const double* stats,
+                                                     unsigned* nclust, double* colpart, const int* skip) {
+    __shared__ double red[4];
     const int b = blockIdx.z;
+    if (skip && skip[b]) return;
     const int n = ns[b];
     const int j = blockIdx.y;
+    if (j >= n) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n || i >= n) return;
-    const double delta = stats[4 * b];
-    const double* Gb = G.at(b);
-    const double g = i >= j ? Gb[i + (long long)j * G.ld] : Gb[j + (long long)i * G.ld];
-    const double rij = (i == j ? 1.0 : 0.0) - g;
-    double* Sp = S.at(b) + i + (long long)j * S.ld;
-    const double li = lam[(long long)b * sL + i], lj = lam[(long long)b * sL + j];
-    const double dl = lj - li;
-    double e;
-    if (i != j && fabs(dl) > delta) e = (*Sp + lj * rij) / dl;
-    else e = 0.5 * rij;
-    *Sp = e;
+    double e2 = 0.0;
+    if (i < n) {
+        const double delta = stats[4 * b];
+        const double* Gb = G.at(b);
+        const double g = i >= j ? Gb[i + (long long)j * G.ld] : Gb[j + (long long)i * G.ld];
+        const double rij = (i == j ? 1.0 : 0.0) - g;
+        double* Sp = S.at(b) + i + (long long)j * S.ld;
+        const double li = lam[(long long)b * sL + i], lj = lam[(long long)b * sL + j];
+        const double dl = lj - li;
+        double e;
+        if (i != j && fabs(dl) > delta) {
+            e = (*Sp + lj * rij) / dl;
+        } else {
+            e = 0.5 * rij;
+            if (i < j) atomicAdd(&nclust[b], 1u);
+        }
+        *Sp = e;
+        if (i != j) e2 = e * e;
+    }
+    if (blockIdx.x * 256 >= n) return;  // uniform: the block holds no row
+    e2 = block_sum256(e2, red);
+    if (threadIdx.x == 0) atomicAdd(&colpart[(long long)b * 4 * sL + 4LL * j], e2);
+}
+
+// skip2[b] = 0 (take step two) iff step one met no pair inside delta and its
+// largest column norm growth exceeded OA_ETA_SECOND; stats[4b+2] = eta
+__global__ __launch_bounds__(256) void oa_second_flags_kernel(const int* ns, const unsigned* nclust,
+                                                                const double* colpart, long long sL,
+                                                                double* stats, int* skip2) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const int n = ns[b];
+    double eta = 0.0;
+    for (int c = threadIdx.x; c < n; c += 256) eta = fmax(eta, colpart[(long long)b * 4 * sL + 4LL * c]);
+    eta = block_max256(eta, red);
+    if (threadIdx.x == 0) {
+        stats[4 * b + 2] = eta;
+        skip2[b] = (nclust[b] == 0u && eta > OA_ETA_SECOND) ? 0 : 1;
+    }
 }
 
 void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd) {
@@ -123,15 +170,24 @@ void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch
 }
 
 void oa_stats_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S, MatBatch<double> G,
-                     double* lam, long long sL, double* colpart, double* stats) {
-    hipLaunchKernelGGL(oa_colstats_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, S, G, lam, sL, colpart);
-    hipLaunchKernelGGL(oa_delta_kernel, dim3(nbatch), dim3(256), 0, st, ns, colpart, sL, stats);
+                     double* lam, long long sL, double* colpart, double* stats, unsigned* nclust,
+                     const int* skip) {
+    hipLaunchKernelGGL(oa_colstats_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, S, G, lam, sL, colpart,
+                       skip);
+    hipLaunchKernelGGL(oa_delta_kernel, dim3(nbatch), dim3(256), 0, st, ns, colpart, sL, stats, nclust, skip);
 }
 
 void oa_update_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S,
-                      MatBatch<double> G, const double* lam, long long sL, const double* stats) {
+                      MatBatch<double> G, const double* lam, long long sL, const double* stats, unsigned* nclust,
+                      double* colpart, const int* skip) {
     hipLaunchKernelGGL(oa_e_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, S, G, lam, sL,
-                       stats);
+                       stats, nclust, colpart, skip);
+}
+
+void oa_second_flags_launch(hipStream_t st, const int* ns, int nbatch, const unsigned* nclust,
+                            const double* colpart, long long sL, double* stats, int* skip2) {
+    hipLaunchKernelGGL(oa_second_flags_kernel, dim3(nbatch), dim3(256), 0, st, ns, nclust, colpart, sL, stats,
+                       skip2);
 }
 
 void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> src,
@@ -142,3 +198,21 @@ void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBat
 void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
 }
+
+// symmetric pseudo-random test matrix (autotuner input): A_rc = A_cr in [-1, 1)
+template <typename T>
+__global__ __launch_bounds__(256) void fill_sym_random_kernel(int n, T* A, int ld, unsigned seed) {
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n || c >= n) return;
+    unsigned x = (unsigned)min(r, c) * 2654435761u ^ ((unsigned)max(r, c) * 2246822519u) ^ seed;
+    x ^= x >> 15; x *= 2654435761u; x ^= x >> 13; x *= 3266489917u; x ^= x >> 16;
+    A[r + (long long)c * ld] = (T)((double)x * (2.0 / 4294967296.0) - 1.0);
+}
+
+template <typename T>
+void fill_sym_random_launch(hipStream_t st, int n, T* A, int ld, unsigned seed) {
+    hipLaunchKernelGGL(fill_sym_random_kernel<T>, dim3((n + 255) / 256, n), dim3(256), 0, st, n, A, ld, seed);
+}
+template void fill_sym_random_launch<double>(hipStream_t, int, double*, int, unsigned);
+template void fill_sym_random_launch<float>(hipStream_t, int, float*, int, unsigned);

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void sytrd_init_kernel(SytrdWs<T> w) {
 // ---------------------------------------------------------------------------
 template <typename T, int NBP>
 __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt, int C, int q, int slot,
-                          const Refl<T>& rf) {
+                          const Refl<T>* rf_in) {
     __shared__ T tb[64][65];
     __shared__ T rrow[4][64];
     __shared__ T red[4];
@@ -138,8 +138,9 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
             dst[k] = ok ? A[r + (long long)c * ld] : T(0);
         }
     };
-    // the first tile is in flight while the vectors are formed
+    // the first tile is in flight while the reflector and vectors are formed
     load_tile(Rb, a);
+    const Refl<T> rf = rf_in ? *rf_in : refl_scalars(w, b, i, n);
 
     if (q == 0) {
         // v for the rows of block C: panel column j and matrix column i
@@ -365,8 +366,7 @@ __global__ __launch_bounds__(256) void sytrd_symv_kernel(SytrdWs<T> w, int i, in
         if (threadIdx.x == 0) w.PV[(long long)b * w.sPV + slot] = T(0);
         return;
     }
-    const Refl<T> rf = refl_scalars(w, b, i, n);
-    symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, slot, rf);
+    symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, slot, nullptr);
 }
 
 template <typename T, int NBP>
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, 
                 continue;
             }
             if (b != cur_b) { rf = refl_scalars(w, b, i, n); cur_b = b; }
-            symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, slot, rf);
+            symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, slot, &rf);
         }
         grid.sync();
         // finish phase
@@ -519,7 +519,7 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                 const int j = i - k0;
                 const int b0 = (i + 1) >> 6;
                 const int nbt = nbk_max - b0;
-                const int Kt = sytrd_kt(nbt, nbatch, 1536);
+                const int Kt = sytrd_kt(nbt, nbatch, w.chunk_target > 0 ? w.chunk_target : 1536);
                 const int gx = (nbt + Kt - 1) / Kt;
                 if (timing) prof->begin(st);
                 hipLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j, Kt);

@@ -65,6 +65,7 @@ struct SytrdWs {
     T* PS; long long sPS;                  // panel products per block [nbk][2*NBP]
     T* PV; long long sPV;                  // v^T A v partial per workgroup
     T* d; T* e; T* tau; long long sD;      // outputs
+    int chunk_target;                      // SYMV work items per launch (tuned)
 };
 template <typename T>
 void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, const int* ns_host,
@@ -108,4 +109,4 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st);
 template <typename T>
 void gemm_batched(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int nbatch,
                   const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C,
-                  int ldc, long long sC, T alpha, T beta, bool lower_only);
+                  int ldc, long long sC, T alpha, T beta, bool lower_only, const int* skip = nullptr);

@@ -44,12 +44,18 @@ void mbd_grad_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nma
 // Ogita-Aishima refinement
 void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd);
 void oa_stats_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S, MatBatch<double> G,
-                     double* lam, long long sL, double* colpart, double* stats);
+                     double* lam, long long sL, double* colpart, double* stats, unsigned* nclust,
+                     const int* skip);
 void oa_update_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S,
-                      MatBatch<double> G, const double* lam, long long sL, const double* stats);
+                      MatBatch<double> G, const double* lam, long long sL, const double* stats, unsigned* nclust,
+                      double* colpart, const int* skip);
+void oa_second_flags_launch(hipStream_t st, const int* ns, int nbatch, const unsigned* nclust,
+                            const double* colpart, long long sL, double* stats, int* skip2);
 void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> src,
                      MatBatch<double> dst);
 void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v);
+template <typename T>
+void fill_sym_random_launch(hipStream_t st, int n, T* A, int ld, unsigned seed);
 
 // periodic (Ewald) assembly and adjoint
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,

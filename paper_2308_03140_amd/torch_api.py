@@ -50,6 +50,19 @@ class Context:
             A.mbd_set_stream(self.handle, s)
             self._stream = s
 
+    def autotune(self, sizes, path=None):
+        """Time the reduction's launch-shape candidates for these matrix orders
+        (mbd_autotune) and keep the fastest in this context."""
+        self.sync_stream()
+        code = A.mbd_autotune(self.handle, [int(x) for x in sizes], path)
+        if code != A.MBD_OK:
+            _raise(self, code)
+
+    def load_tuning(self, path):
+        code = A.mbd_load_tuning(self.handle, path)
+        if code != A.MBD_OK:
+            _raise(self, code)
+
     def close(self):
         if self.handle:
             A.mbd_destroy(self.handle)

@@ -1,0 +1,73 @@
+"""Uneven batches of finite molecules in one launch sequence
+(mbd_evaluate_batch): per-molecule energy and force errors vs the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL_E = {"fp64": 1e-10, "fp32_refined": 1e-7}
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", params=["fp64", "fp32_refined"])
+def ctx(request):
+    from paper_2308_03140_amd import torch_api as T
+    c = T.Context(0, request.param)
+    yield c
+    c.close()
+
+
+def _mols(seed, count, nmin, nmax):
+    rng = np.random.default_rng(seed)
+    out = []
+    for m in range(count):
+        N = int(rng.integers(nmin, nmax + 1))
+        out.append(gen.finite_cluster(seed * 1000 + m, N, 12.0 * (N / 32.0) ** (1 / 3)))
+    return out
+
+
+@pytest.mark.parametrize("count,nmin,nmax", [(1, 5, 5), (7, 1, 30), (24, 10, 70)])
+def test_uneven_batch(ctx, count, nmin, nmax):
+    from paper_2308_03140_amd import torch_api as T
+    _note("batch %s count=%d N in [%d,%d]" % (ctx.precision, count, nmin, nmax))
+    mols = _mols(count + nmin, count, nmin, nmax)
+    outs = T.evaluate_batch(ctx, [dict(m, coords=torch.tensor(m["coords"], device="cuda")) for m in mols])
+    for m, o in zip(mols, outs):
+        assert o["status"] == 0
+        ref = oracle.mbd_finite(m["coords"], m["alpha0"], m["omega"], m["rvdw"], m["beta"], m["a"])
+        N = len(m["omega"])
+        assert abs(o["energy"].item() - ref["energy"]) / N <= TOL_E[ctx.precision]
+        assert np.abs(o["grad_coords"].cpu().numpy() - ref["grad_R"]).max() <= 1e-6
+        assert np.abs(o["grad_alpha0"].cpu().numpy() - ref["grad_alpha0"]).max() <= 1e-6
+        assert np.abs(o["grad_omega"].cpu().numpy() - ref["grad_omega"]).max() <= 1e-6
+
+
+def test_batch_repeat_and_status(ctx):
+    """Same signature twice (the second call replays the captured launch
+    sequence) with different inputs; a collapsed member reports its own status."""
+    from paper_2308_03140_amd import torch_api as T
+    _note("batch repeat %s" % ctx.precision)
+    mols = _mols(5, 6, 8, 40)
+    for rep in range(3):
+        ms = [dict(m, alpha0=m["alpha0"] * (1.0 + 0.1 * rep)) for m in mols]
+        outs = T.evaluate_batch(ctx, [dict(m, coords=torch.tensor(m["coords"], device="cuda")) for m in ms])
+        for m, o in zip(ms, outs):
+            ref = oracle.mbd_finite(m["coords"], m["alpha0"], m["omega"], m["rvdw"], m["beta"], m["a"])
+            assert abs(o["energy"].item() - ref["energy"]) / len(m["omega"]) <= TOL_E[ctx.precision]
+    bad = dict(mols[2], coords=np.array([[0.0, 0, 0], [0, 0, 3.0]]), alpha0=np.array([200.0, 200.0]),
+               omega=np.array([0.5, 0.5]), rvdw=np.array([1.0, 1.0]), beta=0.0)
+    ms = [mols[0], bad, mols[1]]
+    outs = T.evaluate_batch(ctx, [dict(m, coords=torch.tensor(m["coords"], device="cuda")) for m in ms])
+    assert [o["status"] for o in outs] == [0, 2, 0]
+    ref = oracle.mbd_finite(mols[1]["coords"], mols[1]["alpha0"], mols[1]["omega"], mols[1]["rvdw"])
+    assert abs(outs[2]["energy"].item() - ref["energy"]) / len(mols[1]["omega"]) <= TOL_E[ctx.precision]

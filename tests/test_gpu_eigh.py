@@ -100,3 +100,22 @@ def test_eigh_batched(ctx):
     w, Z = T.eigh(ctx, torch.tensor(As, device="cuda"))
     for b in range(3):
         _check(As[b], w[b].cpu().numpy(), Z[b].cpu().numpy(), 1e-12)
+
+
+def test_autotune_table_roundtrip(tmp_path):
+    from paper_2308_03140_amd import torch_api as T
+    _note("autotune")
+    path = str(tmp_path / "tune.json")
+    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32_refined", torch.float32, 2e-5)):
+        c = T.Context(0, prec)
+        c.autotune([150, 400], path)
+        c.close()
+        c2 = T.Context(0, prec)
+        c2.load_tuning(path)
+        A = gen.random_symmetric(99, 400)
+        w, Z = T.eigh(c2, torch.tensor(A, device="cuda", dtype=dt))
+        _check(A, w.double().cpu().numpy(), Z.double().cpu().numpy(), tol)
+        c2.close()
+    import json
+    tab = json.load(open(path))
+    assert set(tab) == {"fp64", "fp32"} and "400" in tab["fp32"]

@@ -117,3 +117,26 @@ def test_invalid_inputs(ctx):
     with pytest.raises(T.MBDError) as e:
         T.evaluate(ctx, coords, [float("nan"), 10.0], [0.5, 0.5], [3.0, 3.0])
     assert e.value.code == 1
+
+
+def test_config_n2000_golden(ctx):
+    """Full-size N=2000 cluster in the benchmark's launch configuration against
+    stored oracle values (frequency route, 48-point grid): energy per atom and
+    dE/dR of 8 sampled atoms.  The quadrature converges to ~1e-12 relative on
+    small clusters; the bound here is the path's own tolerance."""
+    import json
+    import os
+    _note("config N=2000 golden %s" % ctx.precision)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "cluster_n2000.json")) as f:
+        ref = json.load(f)
+    c = gen.cluster_n2000()
+    assert abs(c["alpha_scale"] - ref["alpha_scale"]) < 1e-15
+    out = _run(ctx, c)
+    N = len(c["omega"])
+    dE = abs(out["energy"].item() - ref["energy"]) / N
+    _note("  dE/N = %.3e" % dE)
+    assert dE <= TOL_E[ctx.precision], dE
+    g = out["grad_coords"].cpu().numpy()[ref["atoms"]]
+    err = np.abs(g - np.array(ref["grad_R_sample"])).max()
+    _note("  max |dE/dR - ref| = %.3e" % err)
+    assert err <= TOL_G, err
