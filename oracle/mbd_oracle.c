@@ -14,7 +14,7 @@
  *   Sec. 2.7  eq:fermi-damping, eq:mbd-lr-dipole (T^lr = g T, a = 6)
  *   Sec. 3.3  frequency grid map and Ewald defaults
  *
- * Readings where the paper is ambiguous (all documented in the design doc):
+ * Readings where the paper is silent, ambiguous or at odds with itself:
  *   - T_ab = (delta_ab r^2 - 3 r_a r_b)/r^5, the explicit form of eq:dipole.
  *   - eq:terfc: T^erfc_ab = (delta_ab r^2 B - r_a r_b C)/r^5 (the printed 3 in
  *     front of r_a r_b C is already inside C; without it T^erfc -> T as
