@@ -1,16 +1,25 @@
-"""Benchmark: N=2000 MBD energy + forces on one MI355X.
+"""Benchmark: MBD energy + forces on one MI355X.
 
-One step = one full evaluation of the hot path on the N=2000 finite cluster
-(n = 6000 real symmetric Q): assembly, Householder reduction, divide and
-conquer, back-transform, (refinement), energy, adjoint gradients.  Inputs are
-resident in HBM before timing starts.  The headline value is the FP32 +
+Headline (one step = one full evaluation of the hot path on the N=2000 finite
+cluster, n = 6000 real symmetric Q): assembly, Householder reduction, divide
+and conquer, back-transform, refinement, energy, adjoint gradients.  Inputs
+are resident in HBM before timing starts.  The value is the FP32 +
 Ogita-Aishima refinement path (seconds per evaluation, lower is better); the
-plain FP64 GPU path is timed the same way and reported beside it, with the
-error of every result against FP64.
+plain FP64 GPU path is timed the same way beside it, with the error of every
+result against FP64.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+Secondary legs, reported in the same JSON line:
+  batch     512 molecules, N ~ U{10..300}, energies + forces per molecule, one
+            captured launch graph per call (systems/s, FP32+refine and FP64,
+            per-molecule error of FP32+refine against FP64)
+  periodic  64-atom triclinic cell, 4x4x4 Monkhorst-Pack mesh (64 Hermitian
+            192x192 matrices in one batch), energy + dE/dR + dE/dlattice
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--legs c2,batch,periodic] [--tuning-dir DIR]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +31,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
+SYMV_SOURCE = os.path.join(ROOT, "paper_2308_03140_amd", "csrc", "k_sytrd.hip")
+SYMV_PMC = os.path.join(ROOT, "profiles", "sytrd_symv_fp32_n6000_pmc.txt")
 
 
 def log(*a):
@@ -32,8 +43,6 @@ def cpu_baseline(n_sample=300):
     """The oracle as it stands (Jacobi eigensolver, energy + gradients) on a
     bounded sample: the first n_sample atoms of the N=2000 cluster, scaled to
     N=2000 by the cubic cost law of the dense eigenproblem."""
-    import numpy as np
-
     import gen
     import oracle
     c = gen.cluster_n2000()
@@ -50,25 +59,39 @@ def cpu_baseline(n_sample=300):
                       % (n_sample, dt, n_sample, scale)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(q-point/molecule sharding is design-only); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def symv_traffic():
+    """HBM bytes per SYMV launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when the kernel source has changed since the counters were taken."""
+    if not os.path.exists(SYMV_PMC):
+        return None
+    kv = {}
+    with open(SYMV_PMC) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    with open(SYMV_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if kv.get("kernel_source_sha256_16") != sha or "hbm_bytes_per_launch" not in kv:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
-    import numpy as np
-    import torch
 
+def timed(fn, steps, warmup, torch):
+    out = None
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def leg_c2(args, torch, T, A):
     import gen
-    from paper_2308_03140_amd import _abi as A
-    from paper_2308_03140_amd import torch_api as T
-
     dev = torch.device("cuda", 0)
     c = gen.cluster_n2000()
     N = len(c["omega"])
@@ -77,32 +100,20 @@ def main():
     om = torch.tensor(c["omega"], device=dev)
     rv = torch.tensor(c["rvdw"], device=dev)
     torch.cuda.synchronize()
-
-    results = {}
-    tuned = {}
+    res = {}
     for prec in ("fp64", "fp32_refined"):
         ctx = T.Context(0, prec)
-        log("[bench] %s autotune n=%d" % (prec, 3 * N))
+        log("[bench] c2 %s autotune n=%d" % (prec, 3 * N))
         t0 = time.perf_counter()
-        ctx.autotune([3 * N], os.path.join(ROOT, "gpurun_out", "tuning_%s.json" % prec)
-                     if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
-        tuned[prec] = time.perf_counter() - t0
+        ctx.autotune([3 * N], os.path.join(args.tuning_dir, "tuning_%s.json" % prec) if args.tuning_dir else None)
+        tune_s = time.perf_counter() - t0
 
         def step():
             return T.evaluate(ctx, coords, a0, om, rv, beta=c["beta"], a=c["a"], gradients=True, errors=True)
 
-        log("[bench] %s warmup x%d" % (prec, args.warmup))
-        out = None
-        for _ in range(args.warmup):
-            out = step()
-        torch.cuda.synchronize()
-        log("[bench] %s timed x%d" % (prec, args.steps))
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            out = step()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        log("[bench] %s %.4f s/step" % (prec, dt))
+        log("[bench] c2 %s warmup x%d, timed x%d" % (prec, args.warmup, args.steps))
+        dt, out = timed(step, args.steps, args.warmup, torch)
+        log("[bench] c2 %s %.4f s/step" % (prec, dt))
         # launch-level timing of the reduction kernels (separate, profiled pass)
         A.mbd_set_profiling(ctx.handle, 1)
         step()
@@ -111,51 +122,166 @@ def main():
             st, ms, nl, work = A.mbd_get_profile(ctx.handle, kind)
             prof[kind] = (ms, nl, work)
         A.mbd_set_profiling(ctx.handle, 0)
-        results[prec] = {"s": dt, "out": {k: v.detach().cpu().numpy() for k, v in out.items()}, "prof": prof}
+        res[prec] = {"s": dt, "tune_s": tune_s, "prof": prof,
+                     "out": {k: v.detach().cpu().numpy() for k, v in out.items()}}
         ctx.close()
+    res["N"] = N
+    res["alpha_scale"] = c["alpha_scale"]
+    return res
 
-    e64 = results["fp64"]["out"]
-    e32 = results["fp32_refined"]["out"]
+
+def leg_batch(args, torch, T):
+    import numpy as np
+
+    import gen
+    dev = torch.device("cuda", 0)
+    mols = gen.molecule_batch()
+    systems = [{"coords": torch.tensor(m["coords"], device=dev), "alpha0": torch.tensor(m["alpha0"], device=dev),
+                "omega": torch.tensor(m["omega"], device=dev), "rvdw": torch.tensor(m["rvdw"], device=dev),
+                "beta": m["beta"], "a": m["a"]} for m in mols]
+    torch.cuda.synchronize()
+    nmax = max(3 * len(m["omega"]) for m in mols)
+    res = {}
+    for prec in ("fp32_refined", "fp64"):
+        ctx = T.Context(0, prec)
+        ctx.autotune([nmax])
+        log("[bench] batch %s warmup x%d, timed x%d" % (prec, args.warmup, args.steps))
+        dt, outs = timed(lambda: T.evaluate_batch(ctx, systems), args.steps, args.warmup, torch)
+        log("[bench] batch %s %.4f s/batch" % (prec, dt))
+        res[prec] = {"s": dt, "outs": [{k: (v.detach().cpu().numpy() if hasattr(v, "detach") else v)
+                                        for k, v in o.items()} for o in outs]}
+        ctx.close()
+    dE, dG, dA, dW, steps2, rem = [], [], [], [], 0, 0.0
+    for m, o32, o64 in zip(mols, res["fp32_refined"]["outs"], res["fp64"]["outs"]):
+        N = len(m["omega"])
+        dE.append(abs(float(o32["energy"][0]) - float(o64["energy"][0])) / N)
+        dG.append(float(np.abs(o32["grad_coords"] - o64["grad_coords"]).max()))
+        dA.append(float(np.abs(o32["grad_alpha0"] - o64["grad_alpha0"]).max()))
+        dW.append(float(np.abs(o32["grad_omega"] - o64["grad_omega"]).max()))
+        steps2 += int(o32["errors"][2] >= 2.0)
+        rem = max(rem, float(o32["errors"][3]))
+    sizes = [len(m["omega"]) for m in mols]
+    status = [o["status"] for o in res["fp32_refined"]["outs"]]
+    return {"workload": "512 molecules, N ~ U{10..300} (matrices 30..900), seed 4, one captured graph per call",
+            "n_systems": len(mols), "atoms_total": int(sum(sizes)),
+            "systems_per_s": len(mols) / res["fp32_refined"]["s"], "s_per_batch": res["fp32_refined"]["s"],
+            "fp64_systems_per_s": len(mols) / res["fp64"]["s"], "fp64_s_per_batch": res["fp64"]["s"],
+            "nonzero_status": int(sum(1 for s in status if s != 0)),
+            "molecules_with_second_refinement_step": steps2,
+            "max_refine_remainder_estimate": rem,
+            "errors_vs_fp64_per_molecule": {
+                "energy_per_atom_Ha": {"max": max(dE), "median": float(np.median(dE))},
+                "grad_coords_Ha_per_bohr": {"max": max(dG), "median": float(np.median(dG))},
+                "grad_alpha0": {"max": max(dA), "median": float(np.median(dA))},
+                "grad_omega": {"max": max(dW), "median": float(np.median(dW))}}}
+
+
+def leg_periodic(args, torch, T):
+    import numpy as np
+
+    import gen
+    dev = torch.device("cuda", 0)
+    c = gen.crystal_n64()
+    coords = torch.tensor(c["coords"], device=dev)
+    a0 = torch.tensor(c["alpha0"], device=dev)
+    om = torch.tensor(c["omega"], device=dev)
+    rv = torch.tensor(c["rvdw"], device=dev)
+    torch.cuda.synchronize()
+    res = {}
+    for prec in ("fp32_refined", "fp64"):
+        ctx = T.Context(0, prec)
+        ctx.autotune([6 * 64])
+
+        def step():
+            return T.evaluate(ctx, coords, a0, om, rv, beta=c["beta"], a=c["a"], lattice=c["lattice"],
+                              q_frac=c["q_frac"], gradients=True, errors=True)
+
+        log("[bench] periodic %s warmup x%d, timed x%d" % (prec, args.warmup, args.steps))
+        dt, out = timed(step, args.steps, args.warmup, torch)
+        log("[bench] periodic %s %.4f s/step" % (prec, dt))
+        res[prec] = {"s": dt, "out": {k: v.detach().cpu().numpy() for k, v in out.items()}}
+        ctx.close()
+    o32, o64 = res["fp32_refined"]["out"], res["fp64"]["out"]
+    return {"workload": "64-atom triclinic cell, 4x4x4 Monkhorst-Pack (64 Hermitian 192x192 = real 384x384), "
+                        "Ewald defaults, seed 3, alpha0 x %.4f" % c["alpha_scale"],
+            "s_per_eval": res["fp32_refined"]["s"], "fp64_s_per_eval": res["fp64"]["s"],
+            "errors_vs_fp64": {
+                "energy_per_atom_Ha": abs(float(o32["energy"][0]) - float(o64["energy"][0])) / 64,
+                "grad_coords_Ha_per_bohr": float(np.abs(o32["grad_coords"] - o64["grad_coords"]).max()),
+                "grad_alpha0": float(np.abs(o32["grad_alpha0"] - o64["grad_alpha0"]).max()),
+                "grad_lattice_Ha_per_bohr": float(np.abs(o32["grad_lattice"] - o64["grad_lattice"]).max())}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="c2,batch,periodic")
+    ap.add_argument("--tuning-dir", default=None, help="write the autotuner tables (JSON) here")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(q-point/molecule sharding is design-only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    legs = set(args.legs.split(","))
+
+    import numpy as np
+    import torch
+
+    from paper_2308_03140_amd import _abi as A
+    from paper_2308_03140_amd import torch_api as T
+
+    r = leg_c2(args, torch, T, A)
+    e64, e32 = r["fp64"]["out"], r["fp32_refined"]["out"]
+    N = r["N"]
     dE = abs(float(e32["energy"][0]) - float(e64["energy"][0])) / N
     dG = float(np.abs(e32["grad_coords"] - e64["grad_coords"]).max())
     dA = float(np.abs(e32["grad_alpha0"] - e64["grad_alpha0"]).max())
+    dW = float(np.abs(e32["grad_omega"] - e64["grad_omega"]).max())
 
     # roofline of the dominant kernel: the per-column SYMV of the FP32 reduction
-    ms, nl, byts = results["fp32_refined"]["prof"][0]
+    ms, nl, byts = r["fp32_refined"]["prof"][0]
     avg_s = ms * 1e-3 / max(nl, 1)
     bytes_per_launch = byts / max(nl, 1)
     achieved = bytes_per_launch / avg_s / 1e9
-    ms3, nl3, fl3 = results["fp32_refined"]["prof"][1]
-    ms64, nl64, b64 = results["fp64"]["prof"][0]
-    ms364, nl364, fl364 = results["fp64"]["prof"][1]
+    traffic = symv_traffic()
+    ms3, nl3, fl3 = r["fp32_refined"]["prof"][1]
+    ms64, nl64, b64 = r["fp64"]["prof"][0]
+    ms364, nl364, fl364 = r["fp64"]["prof"][1]
 
     line = {
         "metric": "N=2000 MBD energy+force time (s), FP32+refine vs FP64",
-        "value": results["fp32_refined"]["s"],
+        "value": r["fp32_refined"]["s"],
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": results["fp32_refined"]["s"] * 1e3,
+        "ms_per_step": r["fp32_refined"]["s"] * 1e3,
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "finite cluster N=2000 atoms (Q 6000x6000 real symmetric), energy + forces; "
-                               "seed 2, 0.1 atoms/A^3, alpha0 x %.4f (collapse rule)" % c["alpha_scale"],
-                   "path": "FP32 reduction/D&C/back-transform on matrix cores + 1 FP64 Ogita-Aishima step"},
-        "fp64_s": results["fp64"]["s"],
-        "autotune_s": tuned,
-        "speedup_fp32_refined_vs_fp64": results["fp64"]["s"] / results["fp32_refined"]["s"],
+                               "seed 2, 0.1 atoms/A^3, alpha0 x %.4f (collapse rule)" % r["alpha_scale"],
+                   "path": "FP32 reduction/D&C/back-transform on matrix cores + FP64 Ogita-Aishima refinement "
+                           "(second step only where the first leaves a large remainder)"},
+        "fp64_s": r["fp64"]["s"],
+        "autotune_s": {p: r[p]["tune_s"] for p in ("fp64", "fp32_refined")},
+        "speedup_fp32_refined_vs_fp64": r["fp64"]["s"] / r["fp32_refined"]["s"],
         "errors_vs_fp64": {"energy_per_atom_Ha": dE, "max_grad_coords_Ha_per_bohr": dG,
-                           "max_grad_alpha0": dA,
+                           "max_grad_alpha0": dA, "max_grad_omega": dW,
                            "refine_orth_residual_before": float(e32["errors"][1]),
+                           "refine_steps": float(e32["errors"][2]),
+                           "refine_remainder_estimate": float(e32["errors"][3]),
                            "lambda_min": float(e64["errors"][0])},
         "roofline": {"bound": "hbm", "kernel": "sytrd_symv_kernel<float> (BLAS-2 panel SYMV)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "launches": nl, "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "launches": nl, "avg_launch_us": avg_s * 1e6,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
         "phases": {
             "fp32_symv_GBs": achieved, "fp32_symv_total_ms": ms,
             "fp32_syr2k_TFs": fl3 / (ms3 * 1e-3) / 1e12 if ms3 > 0 else None, "fp32_syr2k_total_ms": ms3,
@@ -164,6 +290,10 @@ def main():
             "fp64_syr2k_TFs": fl364 / (ms364 * 1e-3) / 1e12 if ms364 > 0 else None, "fp64_syr2k_total_ms": ms364,
         },
     }
+    if "batch" in legs:
+        line["batch"] = leg_batch(args, torch, T)
+    if "periodic" in legs:
+        line["periodic"] = leg_periodic(args, torch, T)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline()

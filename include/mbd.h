@@ -110,9 +110,11 @@ typedef struct {
     double *grad_lattice;         /* [3][3] dE/dA_vc, Cartesian positions and
                                      fractional q fixed                           */
     double *eigvals;              /* [n_q or 1][3N] eigenvalues of Q ascending    */
-    double *errors;               /* [4]: lambda_min, refinement orthogonality
-                                     residual max|X^T X - I| (0 for FP64), number
-                                     of refinement steps, refinement threshold    */
+    double *errors;               /* [4]: lambda_min; for MBD_FP32_REFINED also
+                                     max|X^T X - I| of the FP32 eigenvectors, the
+                                     number of refinement steps taken (1 or 2) and
+                                     the estimated largest element error left in
+                                     Q^{-1/2} after the last step (0 for FP64)   */
 } mbd_result;
 
 /* Create a context on HIP device `device` with the given precision.

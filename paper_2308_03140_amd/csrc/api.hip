@@ -178,10 +178,10 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     dw.ns = ns; dw.nmax = nmax; dw.d_in = sw.d; dw.e_in = sw.e; dw.sDin = nmax;
     dw.sV = nmax;
     const size_t nv = (size_t)nmax * nbatch;
-    T* tv[12];
+    double* tv[12];
     const char* tn[12] = {"D", "E", "ds", "zs", "dn", "zn", "mu", "lam", "zh", "rho", "rc", "rs"};
     for (int k = 0; k < 12; k++) {
-        tv[k] = wsT<T>(c, std::string("dc_") + tn[k] + t, nv);
+        tv[k] = wsT<double>(c, std::string("dc_") + tn[k], nv);
         if (!tv[k]) return (mbd_status)c->err_code;
     }
     dw.D = tv[0]; dw.E = tv[1]; dw.ds = tv[2]; dw.zs = tv[3]; dw.dn = tv[4]; dw.zn = tv[5];
@@ -194,7 +194,7 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     }
     dw.perm = iv[0]; dw.ndpos = iv[1]; dw.dfpos = iv[2]; dw.org = iv[3]; dw.outnd = iv[4]; dw.outdf = iv[5];
     dw.rp = iv[6]; dw.rq = iv[7]; dw.Kcnt = iv[8]; dw.rotcnt = iv[9];
-    dw.scale = wsT<T>(c, "dc_scale" + t, nbatch);
+    dw.scale = wsT<double>(c, "dc_scale", nbatch);
     dw.Z0 = {wsT<T>(c, "Z0" + t, (size_t)sZ * nbatch), ldz, sZ};
     dw.Z1 = {wsT<T>(c, "Z1" + t, (size_t)sZ * nbatch), ldz, sZ};
     dw.U = {wsT<T>(c, "U" + t, (size_t)sZ * nbatch), ldz, sZ};
@@ -473,46 +473,28 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         MatBatch<float> X32;
         mbd_status r = run_eig<float>(c, A32, ns_dev, nsh.data(), nmax, nmat, true, lam32, nmax, &X32);
         if (r != MBD_OK) return r;
-        // Ogita-Aishima refinement in FP64 against the FP64 Q held in A64:
-        // step one for every matrix, step two where step one separated every
-        // pair but left a large second-order remainder (device-side flags)
+        // refinement in FP64 against the FP64 Q held in A64: step one for
+        // every matrix, step two where step one's remainder estimate is large
         MatBatch<double> Xd = {wsT<double>(c, "oaX", (size_t)stride * nmat), ld, stride};
         MatBatch<double> Y = {wsT<double>(c, "oaY", (size_t)stride * nmat), ld, stride};
         MatBatch<double> S = {wsT<double>(c, "oaS", (size_t)stride * nmat), ld, stride};
         MatBatch<double> G = {wsT<double>(c, "oaG", (size_t)stride * nmat), ld, stride};
-        double* colpart = wsT<double>(c, "oacol", (size_t)4 * nmax * nmat);
+        OaWork ow;
+        ow.colpart = wsT<double>(c, "oacol", oa_colpart_doubles(nmax, nmat));
+        ow.nclust = wsT<unsigned>(c, "oanclust", nmat);
+        ow.wstart = wsT<int>(c, "oawstart", (size_t)nmax * nmat);
+        ow.wlen = wsT<int>(c, "oawlen", (size_t)nmax * nmat);
+        ow.wv = wsT<double>(c, "oawv", (size_t)OA_KMAX * nmax * nmat);
         stats = wsT<double>(c, "oastats", (size_t)8 * nmat);
-        unsigned* nclust = wsT<unsigned>(c, "oanclust", nmat);
         int* skip2 = wsT<int>(c, "oaskip2", nmat);
-        if (!Xd.p || !Y.p || !S.p || !G.p || !colpart || !stats || !nclust || !skip2)
+        int* skip3 = wsT<int>(c, "oaskip3", nmat);
+        if (!Xd.p || !Y.p || !S.p || !G.p || !ow.colpart || !ow.nclust || !ow.wstart || !ow.wlen || !ow.wv ||
+            !stats || !skip2 || !skip3)
             return (mbd_status)c->err_code;
         oa_f2d_launch(st, ns_dev, nmax, nmat, X32, Xd);
-        // step one: X0 in Xd -> X1 in Y
-        gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, A64.p, ld, stride, Xd.p, ld, stride, Y.p, ld,
-                             stride, 1.0, 0.0, false);                                     // Y = Q X0
-        gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Xd.p, ld, stride, Y.p, ld, stride, S.p, ld,
-                             stride, 1.0, 0.0, false);                                     // S = X0^T Q X0
-        gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Xd.p, ld, stride, Xd.p, ld, stride, G.p, ld,
-                             stride, 1.0, 0.0, true);                                      // G = X0^T X0
-        oa_stats_launch(st, ns_dev, nmax, nmat, S, G, lam, nmax, colpart, stats, nclust, nullptr);
-        oa_update_launch(st, ns_dev, nmax, nmat, S, G, lam, nmax, stats, nclust, colpart, nullptr);
-        copy_mat_launch(st, ns_dev, nmax, nmat, Xd, Y);
-        gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, Xd.p, ld, stride, S.p, ld, stride, Y.p, ld,
-                             stride, 1.0, 1.0, false);                                     // Y = X0 + X0 E
-        // step two: X1 in Y -> X2 in S (skipped matrices copy X1)
-        oa_second_flags_launch(st, ns_dev, nmat, nclust, colpart, nmax, stats, skip2);
-        double* stats2 = stats + 4 * nmat;
-        gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, A64.p, ld, stride, Y.p, ld, stride, S.p, ld,
-                             stride, 1.0, 0.0, false, skip2);                              // S = Q X1
-        gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Y.p, ld, stride, S.p, ld, stride, Xd.p, ld,
-                             stride, 1.0, 0.0, false, skip2);                              // Xd = X1^T Q X1
-        gemm_batched<double>(st, true, false, ns_dev, nmax, nmat, Y.p, ld, stride, Y.p, ld, stride, G.p, ld,
-                             stride, 1.0, 0.0, true, skip2);                               // G = X1^T X1
-        oa_stats_launch(st, ns_dev, nmax, nmat, Xd, G, lam, nmax, colpart, stats2, nclust, skip2);
-        oa_update_launch(st, ns_dev, nmax, nmat, Xd, G, lam, nmax, stats2, nclust, colpart, skip2);
-        copy_mat_launch(st, ns_dev, nmax, nmat, Y, S);
-        gemm_batched<double>(st, false, false, ns_dev, nmax, nmat, Y.p, ld, stride, Xd.p, ld, stride, S.p, ld,
-                             stride, 1.0, 1.0, false, skip2);                              // S = X1 + X1 E
+        oa_step_launch(st, ns_dev, nmax, nmat, A64, Xd, Y, S, G, lam, nmax, ow, stats, nullptr, skip2);  // X1 in Y
+        oa_step_launch(st, ns_dev, nmax, nmat, A64, Y, S, Xd, G, lam, nmax, ow, stats + 4 * nmat, skip2,
+                       skip3);                                                                   // X2 in S
         skip_dev = skip2;
         HIPCHK(hipGetLastError(), "refine");
         X = S;
@@ -563,13 +545,13 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         if (sds[s].errors && codes[s] != MBD_ERR_INVALID_ARGUMENT) {
             double e3[3] = {0.0, 0.0, 0.0};
             if (stats) {
-                // worst matrix of the system: max|X^T X - I| and delta of the first
-                // step, number of steps taken
+                // worst matrix of the system: max|X^T X - I| before refinement,
+                // steps taken, remainder estimate of the last step
                 for (int q = 0; q < sds[s].nmat; q++) {
                     const int b = sds[s].mat0 + q;
                     e3[0] = std::max(e3[0], stats_h[4 * b + 1]);
-                    e3[2] = std::max(e3[2], stats_h[4 * b]);
                     e3[1] = std::max(e3[1], skip_h[b] ? 1.0 : 2.0);
+                    e3[2] = std::max(e3[2], skip_h[b] ? stats_h[4 * b + 2] : stats_h[4 * (nmat + b) + 2]);
                 }
             }
             HIPCHK(hipMemcpy(sds[s].errors + 1, e3, sizeof(e3), hipMemcpyHostToDevice), "errors");
@@ -696,7 +678,7 @@ mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, 
                 if (c->prec == MBD_FP32_REFINED) {
                     e3[0] = g.h_stats[4 * i + 1];
                     e3[1] = g.h_skip[i] ? 1.0 : 2.0;
-                    e3[2] = g.h_stats[4 * i];
+                    e3[2] = g.h_skip[i] ? g.h_stats[4 * i + 2] : g.h_stats[4 * (n_sys + i) + 2];
                 }
                 HIPCHK(hipMemcpy(sds[i].errors + 1, e3, sizeof(e3), hipMemcpyHostToDevice), "errors");
             }

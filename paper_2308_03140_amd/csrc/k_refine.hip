@@ -1,27 +1,43 @@
-// Refinement of approximate eigenpairs (Ogita & Aishima, "Iterative
-// refinement for symmetric eigenvalue decomposition", 2018) in FP64 against
-// the FP64 Q, applied to the eigenvectors of the FP32 diagonalisation:
-//   G = X^T X, R = I - G, S = X^T Q X
-//   lambda_i = S_ii / (1 - R_ii)
-//   E_ij = (S_ij + lambda_j R_ij)/(lambda_j - lambda_i)  if |lambda_i - lambda_j| > delta
-//        = R_ij / 2                                      otherwise (and on the diagonal)
-//   X <- X + X E
-// delta = 2 (||S - diag(lambda)||_F + max|lambda| ||R||_F), the Frobenius
-// bounds of the spectral norms in the method's separation threshold.  Pairs
-// closer than delta are only orthogonalised by a step.
-// A step converges quadratically when every pair is separated: its leftover
-// is dominated by the second-order terms of the correction, of the size
-// eta = max_i sum_{j != i} E_ji^2 (the norm growth of column i).  A second
-// step is taken for a matrix whose first step met no pair inside delta and
-// had eta > OA_ETA_SECOND; the decision is made on the device through
-// per-matrix skip flags, so captured launch graphs stay valid.
-// The products are batched GEMMs (gemm_mfma.h); these kernels do the
-// element-wise parts.
+// Refinement of approximate eigenpairs in FP64 against the FP64 Q, applied to
+// the eigenvectors of the FP32 diagonalisation (Ogita & Aishima, "Iterative
+// refinement for symmetric eigenvalue decomposition", 2018, with the treatment
+// of close eigenvalues of their 2019 sequel, "... II: clustered eigenvalues",
+// in Rayleigh-Ritz form).  One step on X (n x n, columns ~ eigenvectors):
+//
+//   S = X^T Q X, G = X^T X, R = I - G, lam_i = S_ii / G_ii
+//   delta = 2 (||S - diag(lam)||_F + max|lam| ||R||_F)   (Frobenius bounds of
+//           the spectral norms in the method's separation threshold; reported,
+//           not used: with FP32 eigenvectors of large matrices it exceeds the
+//           typical eigenvalue spacing, and grouping by it merges the spectrum)
+//   windows: column i joins the window of column i-1 when the linear
+//           correction between i and one of the OA_LINK previous columns,
+//           |S_ji + lam_i R_ji| / |lam_i - lam_j|, exceeds OA_TAU (the step is
+//           only second-order accurate for such pairs), or when their lam
+//           agree to rounding; windows are cut at OA_KMAX columns
+//   per window J: the generalised problem S_JJ v = mu G_JJ v (Cholesky of
+//           G_JJ, cyclic Jacobi), W_JJ = [v] (G-orthonormal), lam_J <- mu
+//   in the rotated basis X' = X W:  S' = W^T S W, R' = -W^T G W off the
+//           diagonal blocks, and
+//             E'_ij = (S'_ij + lam_j R'_ij) / (lam_j - lam_i)  i, j in different
+//                     windows with |lam_i - lam_j| above rounding level
+//             E'_ij = R'_ij / 2   other pairs of different windows (unresolved)
+//             E'_ii = R_ii / 2    single-column windows, 0 inside windows
+//   X <- X' + X' E' = X + X F,  F = (W - I) + W E'
+//
+// The leftover of a step is second order in the cross-window correction:
+// column j grows in norm by eta_j = sum_{i != j} E'_ij^2, and
+// rho = max_j eta_j max_r|X_rj|^2 / sqrt(lam_j) estimates the largest element
+// error it leaves in Q^{-1/2} = X diag(lam^{-1/2}) X^T.  A matrix takes a second step
+// when rho > OA_RHO_NEXT; the decision stays on the device (per-matrix skip
+// flags), so captured launch graphs remain valid.
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
 
-#define OA_ETA_SECOND 1e-9
+#define OA_RHO_NEXT 1e-8
+#define OA_TAU 1e-4
+#define OA_LINK 4
+#define OA_CP 6  // per-column partials: s2 (then eta), r2, max|R|, |lam|, max|x|, spare
 
 __global__ __launch_bounds__(256) void oa_f2d_kernel(const int* ns, MatBatch<float> X32, MatBatch<double> Xd) {
     const int b = blockIdx.z;
@@ -46,11 +62,15 @@ __global__ void fill_u32_kernel(unsigned* p, int n, unsigned v) {
     if (i < n) p[i] = v;
 }
 
-// lambda_i = S_ii / G_ii, then per-column partial sums of the squared
-// off-diagonal residuals (S - diag lambda) and R = I - G (G lower only)
+__device__ __forceinline__ double sym_lower(const double* G, int ld, int r, int c) {
+    return r >= c ? G[r + (long long)c * ld] : G[c + (long long)r * ld];
+}
+
+// lam_c = S_cc / G_cc and per-column partials of ||S - diag(lam)||_F^2,
+// ||R||_F^2, max|R|, |lam| and max|X| (G holds its lower triangle)
 __global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
-                                                            double* lam, long long sL, double* colpart,
-                                                            const int* skip) {
+                                                            MatBatch<double> X, double* lam, long long sL,
+                                                            double* colpart, const int* skip) {
     __shared__ double red[4];
     const int b = blockIdx.z;
     if (skip && skip[b]) return;
@@ -59,135 +79,379 @@ __global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatc
     if (c >= n) return;
     const double* Sb = S.at(b);
     const double* Gb = G.at(b);
-    double s2 = 0.0, r2 = 0.0, rmax = 0.0;
+    const double* Xb = X.at(b);
+    double s2 = 0.0, r2 = 0.0, rmax = 0.0, xmax = 0.0;
     for (int r = threadIdx.x; r < n; r += 256) {
         const double sv = Sb[r + (long long)c * S.ld];
         if (r != c) s2 += sv * sv;
-        const double gv = r >= c ? Gb[r + (long long)c * G.ld] : Gb[c + (long long)r * G.ld];
-        const double rv = (r == c ? 1.0 : 0.0) - gv;
+        const double rv = (r == c ? 1.0 : 0.0) - sym_lower(Gb, G.ld, r, c);
         r2 += rv * rv;
         rmax = fmax(rmax, fabs(rv));
+        xmax = fmax(xmax, fabs(Xb[r + (long long)c * X.ld]));
     }
     s2 = block_sum256(s2, red);
     r2 = block_sum256(r2, red);
     rmax = block_max256(rmax, red);
+    xmax = block_max256(xmax, red);
     if (threadIdx.x == 0) {
-        const double gcc = Gb[c + (long long)c * G.ld];
-        const double l = Sb[c + (long long)c * S.ld] / gcc;
+        const double scc = Sb[c + (long long)c * S.ld];
+        const double l = scc / Gb[c + (long long)c * G.ld];
         lam[(long long)b * sL + c] = l;
-        const long long o = (long long)b * 4 * sL + 4LL * c;
-        const double dl = Sb[c + (long long)c * S.ld] - l;
-        colpart[o] = s2 + dl * dl;
-        colpart[o + 1] = r2;
-        colpart[o + 2] = rmax;
-        colpart[o + 3] = fabs(l);
+        double* cp = colpart + ((long long)b * sL + c) * OA_CP;
+        cp[0] = s2 + (scc - l) * (scc - l);
+        cp[1] = r2;
+        cp[2] = rmax;
+        cp[3] = fabs(l);
+        cp[4] = xmax;
     }
 }
 
-// per matrix: stats = {delta, max|R|}; clears the cluster-pair counter and
-// the per-column accumulators of the correction's norm growth
+// per matrix: stats = {delta, max|R|, (rho), max|X|}; clears the unresolved
+// pair counter and the per-column accumulators of the correction
 __global__ __launch_bounds__(256) void oa_delta_kernel(const int* ns, double* colpart, long long sL,
                                                          double* stats, unsigned* nclust, const int* skip) {
     __shared__ double red[4];
     const int b = blockIdx.x;
     if (skip && skip[b]) return;
     const int n = ns[b];
-    double s2 = 0, r2 = 0, rmax = 0, lmax = 0;
+    double s2 = 0, r2 = 0, rmax = 0, lmax = 0, xmax = 0;
     for (int c = threadIdx.x; c < n; c += 256) {
-        const long long o = (long long)b * 4 * sL + 4LL * c;
-        s2 += colpart[o];
-        r2 += colpart[o + 1];
-        rmax = fmax(rmax, colpart[o + 2]);
-        lmax = fmax(lmax, colpart[o + 3]);
-        colpart[o] = 0.0;  // reused as the column norm growth of E
+        double* cp = colpart + ((long long)b * sL + c) * OA_CP;
+        s2 += cp[0];
+        r2 += cp[1];
+        rmax = fmax(rmax, cp[2]);
+        lmax = fmax(lmax, cp[3]);
+        xmax = fmax(xmax, cp[4]);
+        cp[0] = 0.0;  // reused as sum_i E'_ic^2 over cross-window i
     }
     s2 = block_sum256(s2, red);
     r2 = block_sum256(r2, red);
     rmax = block_max256(rmax, red);
     lmax = block_max256(lmax, red);
+    xmax = block_max256(xmax, red);
     if (threadIdx.x == 0) {
         stats[4 * b] = 2.0 * (sqrt(s2) + lmax * sqrt(r2));
         stats[4 * b + 1] = rmax;
+        stats[4 * b + 2] = 0.0;
+        stats[4 * b + 3] = xmax;
         nclust[b] = 0u;
     }
 }
 
-// S <- E (in place); counts the pairs closer than delta and accumulates
-// sum_{i != j} E_ij^2 per column j into colpart[4 j]
+// Windows: a new run starts at column i unless it links to one of the
+// OA_LINK previous columns; runs are cut into chunks of OA_KMAX columns.
+// One block per matrix; each thread scans a contiguous segment, with carries
+// across segments taken from LDS.  wstart[i] = first column of i's window,
+// wlen[i] = its length.
+__device__ __forceinline__ bool oa_break(const double* Sb, int lds, const double* Gb, int ldg, const double* L,
+                                         int i, double tiny) {
+    if (i == 0) return true;
+    const double li = L[i];
+    for (int d = 1; d <= OA_LINK && i - d >= 0; d++) {
+        const int j = i - d;
+        const double dl = fabs(li - L[j]);
+        const double sji = 0.5 * (Sb[j + (long long)i * lds] + Sb[i + (long long)j * lds]);
+        const double rji = -Gb[i + (long long)j * ldg];
+        if (dl <= tiny || fabs(sji + li * rji) > OA_TAU * dl) return false;
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(256) void oa_windows_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
+                                                           const double* lam, long long sL, const double* colpart,
+                                                           int* wstart, int* wlen, const int* skip) {
+    __shared__ int last[256], first[256];
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    if (skip && skip[b]) return;
+    const int n = ns[b];
+    const double* L = lam + (long long)b * sL;
+    const double* Sb = S.at(b);
+    const double* Gb = G.at(b);
+    const int t = threadIdx.x;
+    double lmax = 0.0;
+    for (int c = t; c < n; c += 256) lmax = fmax(lmax, colpart[((long long)b * sL + c) * OA_CP + 3]);
+    const double tiny = 64.0 * num_limits<double>::eps * block_max256(lmax, red);
+    const int seg = (n + 255) / 256;
+    const int i0 = min(n, t * seg), i1 = min(n, i0 + seg);
+    int* ws = wstart + (long long)b * sL;
+    int* wl = wlen + (long long)b * sL;
+    int lst = -1, fst = n;
+    for (int i = i0; i < i1; i++) {
+        const bool brk = oa_break(Sb, S.ld, Gb, G.ld, L, i, tiny);
+        wl[i] = brk ? 1 : 0;
+        if (brk) {
+            lst = i;
+            if (fst == n) fst = i;
+        }
+    }
+    last[t] = lst;
+    first[t] = fst;
+    __syncthreads();
+    int run = -1, nxt = n;
+    for (int u = 0; u < t; u++) run = max(run, last[u]);
+    for (int u = t + 1; u < 256; u++) nxt = min(nxt, first[u]);
+    for (int i = i0; i < i1; i++) {  // run starts
+        if (wl[i]) run = i;
+        ws[i] = run;
+    }
+    for (int i = i1 - 1; i >= i0; i--) {  // run ends, then chunks
+        const bool brk = wl[i] != 0;
+        const int rs = ws[i];
+        const int cs = rs + OA_KMAX * ((i - rs) / OA_KMAX);
+        ws[i] = cs;
+        wl[i] = min(cs + OA_KMAX, nxt) - cs;
+        if (brk) nxt = i;
+    }
+}
+
+// Rayleigh-Ritz per window of k >= 2 columns: one 64-lane block, k <= 32.
+// S_JJ (symmetrised) and G_JJ -> L = chol(G_JJ), A = L^-1 S_JJ L^-T, cyclic
+// Jacobi A = U diag(mu) U^T, V = L^-T U; columns ordered by ascending mu.
+// wv[(b sL + cs + r) * OA_KMAX + p] = V_pr, lam[cs + r] = mu_r.
+__global__ __launch_bounds__(64) void oa_rr_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
+                                                     double* lam, long long sL, const int* wstart, const int* wlen,
+                                                     double* wv, const int* skip) {
+    __shared__ double Am[OA_KMAX][OA_KMAX + 1], Lm[OA_KMAX][OA_KMAX + 1], Im[OA_KMAX][OA_KMAX + 1],
+        Um[OA_KMAX][OA_KMAX + 1];
+    __shared__ int rank[OA_KMAX];
+    const int b = blockIdx.z;
+    if (skip && skip[b]) return;
+    const int n = ns[b];
+    const int cs = blockIdx.x;
+    if (cs >= n) return;
+    const long long o = (long long)b * sL;
+    const int k = wlen[o + cs];
+    if (wstart[o + cs] != cs || k < 2) return;
+    const int tid = threadIdx.x;
+    const double* Sb = S.at(b);
+    const double* Gb = G.at(b);
+    for (int e = tid; e < k * k; e += 64) {
+        const int r = e % k, c = e / k;
+        Am[r][c] = 0.5 * (Sb[(cs + r) + (long long)(cs + c) * S.ld] + Sb[(cs + c) + (long long)(cs + r) * S.ld]);
+        Lm[r][c] = sym_lower(Gb, G.ld, cs + r, cs + c);
+        Um[r][c] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // Cholesky of G_JJ in place (lower)
+    for (int j = 0; j < k; j++) {
+        if (tid == 0) {
+            double d = Lm[j][j];
+            for (int p = 0; p < j; p++) d -= Lm[j][p] * Lm[j][p];
+            Lm[j][j] = sqrt(fmax(d, 1e-300));
+        }
+        __syncthreads();
+        if (tid > j && tid < k) {
+            double v = Lm[tid][j];
+            for (int p = 0; p < j; p++) v -= Lm[tid][p] * Lm[j][p];
+            Lm[tid][j] = v / Lm[j][j];
+        }
+        __syncthreads();
+    }
+    // L^-1, one column per lane
+    if (tid < k) {
+        const int c = tid;
+        for (int r = 0; r < k; r++) {
+            if (r < c) {
+                Im[r][c] = 0.0;
+                continue;
+            }
+            double v = r == c ? 1.0 : 0.0;
+            for (int p = c; p < r; p++) v -= Lm[r][p] * Im[p][c];
+            Im[r][c] = v / Lm[r][r];
+        }
+    }
+    __syncthreads();
+    // T = S_JJ L^-T into Lm, then A = L^-1 T into Am
+    for (int e = tid; e < k * k; e += 64) {
+        const int r = e % k, c = e / k;
+        double v = 0.0;
+        for (int m = 0; m <= c; m++) v += Am[r][m] * Im[c][m];
+        Lm[r][c] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += 64) {
+        const int r = e % k, c = e / k;
+        double v = 0.0;
+        for (int m = 0; m <= r; m++) v += Im[r][m] * Lm[m][c];
+        Am[r][c] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += 64) {
+        const int r = e % k, c = e / k;
+        if (r < c) {
+            const double v = 0.5 * (Am[r][c] + Am[c][r]);
+            Am[r][c] = v;
+            Am[c][r] = v;
+        }
+    }
+    __syncthreads();
+    // cyclic Jacobi: rotation (p, q) zeroes A_pq; lanes 0..31 update A,
+    // lanes 32..63 update U.  Every lane evaluates the same rotation test on
+    // the same LDS values, so the control flow stays uniform.
+    for (int sweep = 0; sweep < 40; sweep++) {
+        int rotated = 0;
+        for (int p = 0; p < k - 1; p++)
+            for (int q = p + 1; q < k; q++) {
+                const double app = Am[p][p], aqq = Am[q][q], apq = Am[p][q];
+                if (apq == 0.0 || !(fabs(apq) > 1e-17 * sqrt(fabs(app * aqq)))) continue;
+                rotated = 1;
+                const double th = (aqq - app) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                __syncthreads();
+                if (tid < k) {  // A <- A J
+                    const double arp = Am[tid][p], arq = Am[tid][q];
+                    Am[tid][p] = c * arp - s * arq;
+                    Am[tid][q] = s * arp + c * arq;
+                } else if (tid >= 32 && tid - 32 < k) {  // U <- U J
+                    const int r = tid - 32;
+                    const double urp = Um[r][p], urq = Um[r][q];
+                    Um[r][p] = c * urp - s * urq;
+                    Um[r][q] = s * urp + c * urq;
+                }
+                __syncthreads();
+                if (tid < k) {  // A <- J^T A
+                    const double apr = Am[p][tid], aqr = Am[q][tid];
+                    Am[p][tid] = c * apr - s * aqr;
+                    Am[q][tid] = s * apr + c * aqr;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    Am[p][q] = 0.0;
+                    Am[q][p] = 0.0;
+                }
+                __syncthreads();
+            }
+        if (!rotated) break;
+    }
+    if (tid < k) {
+        const double mu = Am[tid][tid];
+        int rk = 0;
+        for (int s2 = 0; s2 < k; s2++) {
+            const double ms = Am[s2][s2];
+            rk += (ms < mu || (ms == mu && s2 < tid)) ? 1 : 0;
+        }
+        rank[tid] = rk;
+        lam[o + cs + rk] = mu;
+    }
+    __syncthreads();
+    // V = L^-T U, written per output column
+    for (int e = tid; e < k * k; e += 64) {
+        const int p = e % k, r = e / k;
+        double v = 0.0;
+        for (int m = p; m < k; m++) v += Im[m][p] * Um[m][r];
+        wv[(o + cs + rank[r]) * OA_KMAX + p] = v;
+    }
+}
+
+// E' (in the rotated basis) into Eo; counts unresolved close pairs and
+// accumulates sum_i E'_ij^2 over cross-window i per column j
 __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
-                                                     const double* lam, long long sL, const double* stats,
-                                                     unsigned* nclust, double* colpart, const int* skip) {
+                                                     MatBatch<double> Eo, const double* lam, long long sL,
+                                                     const int* wstart, const int* wlen, const double* wv,
+                                                     const double* stats, unsigned* nclust, double* colpart,
+                                                     const int* skip) {
     __shared__ double red[4];
     const int b = blockIdx.z;
     if (skip && skip[b]) return;
     const int n = ns[b];
     const int j = blockIdx.y;
     if (j >= n) return;
+    if (blockIdx.x * 256 >= n) return;  // uniform: the block holds no row
     const int i = blockIdx.x * 256 + threadIdx.x;
+    const long long o = (long long)b * sL;
     double e2 = 0.0;
     if (i < n) {
-        const double delta = stats[4 * b];
+        const int wi = wstart[o + i], ki = wlen[o + i];
+        const int wj = wstart[o + j], kj = wlen[o + j];
+        const double* Sb = S.at(b);
         const double* Gb = G.at(b);
-        const double g = i >= j ? Gb[i + (long long)j * G.ld] : Gb[j + (long long)i * G.ld];
-        const double rij = (i == j ? 1.0 : 0.0) - g;
-        double* Sp = S.at(b) + i + (long long)j * S.ld;
-        const double li = lam[(long long)b * sL + i], lj = lam[(long long)b * sL + j];
-        const double dl = lj - li;
         double e;
-        if (i != j && fabs(dl) > delta) {
-            e = (*Sp + lj * rij) / dl;
+        if (wi == wj) {
+            e = (ki == 1) ? 0.5 * (1.0 - Gb[i + (long long)i * G.ld]) : 0.0;
         } else {
-            e = 0.5 * rij;
-            if (i < j) atomicAdd(&nclust[b], 1u);
+            const double* vi = wv + (o + i) * OA_KMAX;
+            const double* vj = wv + (o + j) * OA_KMAX;
+            double sp = 0.0, gp = 0.0;
+            for (int q = 0; q < kj; q++) {
+                const double cj = kj == 1 ? 1.0 : vj[q];
+                double ts = 0.0, tg = 0.0;
+                for (int p = 0; p < ki; p++) {
+                    const double ci = ki == 1 ? 1.0 : vi[p];
+                    ts += ci * Sb[(wi + p) + (long long)(wj + q) * S.ld];
+                    tg += ci * sym_lower(Gb, G.ld, wi + p, wj + q);
+                }
+                sp += ts * cj;
+                gp += tg * cj;
+            }
+            const double li = lam[o + i], lj = lam[o + j];
+            const double dl = lj - li;
+            if (fabs(dl) > 64.0 * num_limits<double>::eps * fmax(fabs(li), fabs(lj))) {
+                e = (sp - lj * gp) / dl;
+            } else {
+                e = -0.5 * gp;
+                if (i < j) atomicAdd(&nclust[b], 1u);
+            }
+            e2 = e * e;
         }
-        *Sp = e;
-        if (i != j) e2 = e * e;
+        Eo.at(b)[i + (long long)j * Eo.ld] = e;
     }
-    if (blockIdx.x * 256 >= n) return;  // uniform: the block holds no row
     e2 = block_sum256(e2, red);
-    if (threadIdx.x == 0) atomicAdd(&colpart[(long long)b * 4 * sL + 4LL * j], e2);
+    if (threadIdx.x == 0) atomicAdd(&colpart[(o + j) * OA_CP], e2);
 }
 
-// skip2[b] = 0 (take step two) iff step one met no pair inside delta and its
-// largest column norm growth exceeded OA_ETA_SECOND; stats[4b+2] = eta
-__global__ __launch_bounds__(256) void oa_second_flags_kernel(const int* ns, const unsigned* nclust,
-                                                                const double* colpart, long long sL,
-                                                                double* stats, int* skip2) {
+// F = (W - I) + W E' into Fo, W block diagonal over the windows
+__global__ __launch_bounds__(256) void oa_f_kernel(const int* ns, MatBatch<double> Ei, MatBatch<double> Fo,
+                                                     long long sL, const int* wstart, const int* wlen,
+                                                     const double* wv, const int* skip) {
+    const int b = blockIdx.z;
+    if (skip && skip[b]) return;
+    const int n = ns[b];
+    const int j = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n || i >= n) return;
+    const long long o = (long long)b * sL;
+    const int wi = wstart[o + i], ki = wlen[o + i];
+    const double* Eb = Ei.at(b);
+    double f;
+    if (ki == 1) {
+        f = Eb[i + (long long)j * Ei.ld];
+    } else {
+        const int p = i - wi;
+        f = (wstart[o + j] == wi) ? wv[(o + j) * OA_KMAX + p] - (i == j ? 1.0 : 0.0) : 0.0;
+        for (int a = 0; a < ki; a++) f += wv[(o + wi + a) * OA_KMAX + p] * Eb[(wi + a) + (long long)j * Ei.ld];
+    }
+    Fo.at(b)[i + (long long)j * Fo.ld] = f;
+}
+
+// rho = max_c eta_c max|x_c|^2 / sqrt(lam_c) -> stats[4b+2]; next[b] = 1
+// (skip the next step) unless rho > OA_RHO_NEXT
+__global__ __launch_bounds__(256) void oa_next_kernel(const int* ns, const double* colpart, const double* lam,
+                                                        long long sL, double* stats, const int* skip, int* next) {
     __shared__ double red[4];
     const int b = blockIdx.x;
+    if (skip && skip[b]) {
+        if (threadIdx.x == 0) next[b] = 1;
+        return;
+    }
     const int n = ns[b];
-    double eta = 0.0;
-    for (int c = threadIdx.x; c < n; c += 256) eta = fmax(eta, colpart[(long long)b * 4 * sL + 4LL * c]);
-    eta = block_max256(eta, red);
+    const long long o = (long long)b * sL;
+    double rho = 0.0;
+    for (int c = threadIdx.x; c < n; c += 256) {
+        const double* cp = colpart + (o + c) * OA_CP;
+        const double l = lam[o + c];
+        if (l > 0.0) rho = fmax(rho, cp[0] * cp[4] * cp[4] / sqrt(l));
+    }
+    rho = block_max256(rho, red);
     if (threadIdx.x == 0) {
-        stats[4 * b + 2] = eta;
-        skip2[b] = (nclust[b] == 0u && eta > OA_ETA_SECOND) ? 0 : 1;
+        stats[4 * b + 2] = rho;
+        next[b] = rho > OA_RHO_NEXT ? 0 : 1;
     }
 }
 
 void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd) {
     hipLaunchKernelGGL(oa_f2d_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, X32, Xd);
-}
-
-void oa_stats_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S, MatBatch<double> G,
-                     double* lam, long long sL, double* colpart, double* stats, unsigned* nclust,
-                     const int* skip) {
-    hipLaunchKernelGGL(oa_colstats_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, S, G, lam, sL, colpart,
-                       skip);
-    hipLaunchKernelGGL(oa_delta_kernel, dim3(nbatch), dim3(256), 0, st, ns, colpart, sL, stats, nclust, skip);
-}
-
-void oa_update_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S,
-                      MatBatch<double> G, const double* lam, long long sL, const double* stats, unsigned* nclust,
-                      double* colpart, const int* skip) {
-    hipLaunchKernelGGL(oa_e_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, S, G, lam, sL,
-                       stats, nclust, colpart, skip);
-}
-
-void oa_second_flags_launch(hipStream_t st, const int* ns, int nbatch, const unsigned* nclust,
-                            const double* colpart, long long sL, double* stats, int* skip2) {
-    hipLaunchKernelGGL(oa_second_flags_kernel, dim3(nbatch), dim3(256), 0, st, ns, nclust, colpart, sL, stats,
-                       skip2);
 }
 
 void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> src,
@@ -197,6 +461,34 @@ void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBat
 
 void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+}
+
+size_t oa_colpart_doubles(int nmax, int nbatch) { return (size_t)nbatch * nmax * OA_CP; }
+
+void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> Q, MatBatch<double> X,
+                    MatBatch<double> T1, MatBatch<double> T2, MatBatch<double> G, double* lam, long long sL,
+                    const OaWork& w, double* stats, const int* skip, int* next) {
+    const dim3 ge((nmax + 255) / 256, nmax, nbatch);
+    gemm_batched<double>(st, false, false, ns, nmax, nbatch, Q.p, Q.ld, Q.stride, X.p, X.ld, X.stride, T1.p,
+                         T1.ld, T1.stride, 1.0, 0.0, false, skip);                             // T1 = Q X
+    gemm_batched<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T1.p, T1.ld, T1.stride, T2.p,
+                         T2.ld, T2.stride, 1.0, 0.0, false, skip);                             // S = X^T Q X
+    gemm_batched<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, X.p, X.ld, X.stride, G.p, G.ld,
+                         G.stride, 1.0, 0.0, true, skip);                                      // G = X^T X
+    hipLaunchKernelGGL(oa_colstats_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, T2, G, X, lam, sL,
+                       w.colpart, skip);
+    hipLaunchKernelGGL(oa_delta_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, sL, stats, w.nclust, skip);
+    hipLaunchKernelGGL(oa_windows_kernel, dim3(nbatch), dim3(256), 0, st, ns, T2, G, lam, sL, w.colpart, w.wstart,
+                       w.wlen, skip);
+    hipLaunchKernelGGL(oa_rr_kernel, dim3(nmax, 1, nbatch), dim3(64), 0, st, ns, T2, G, lam, sL, w.wstart,
+                       w.wlen, w.wv, skip);
+    hipLaunchKernelGGL(oa_e_kernel, ge, dim3(256), 0, st, ns, T2, G, T1, lam, sL, w.wstart, w.wlen, w.wv, stats,
+                       w.nclust, w.colpart, skip);                                             // E' -> T1
+    hipLaunchKernelGGL(oa_f_kernel, ge, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, skip);  // F -> T2
+    hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, stats, skip, next);
+    hipLaunchKernelGGL(copy_mat_kernel, ge, dim3(256), 0, st, ns, X, T1);                       // T1 = X
+    gemm_batched<double>(st, false, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T2.p, T2.ld, T2.stride, T1.p,
+                         T1.ld, T1.stride, 1.0, 1.0, false, skip);                             // T1 = X + X F
 }
 
 // symmetric pseudo-random test matrix (autotuner input): A_rc = A_cr in [-1, 1)

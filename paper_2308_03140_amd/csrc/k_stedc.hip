@@ -34,26 +34,26 @@ __device__ __forceinline__ MergeInfo merge_of(int p, int lev, int n) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void stedc_init_kernel(StedcWs<T> w) {
-    __shared__ T red[4];
+    __shared__ double red[4];
     const int b = blockIdx.z;
     const int n = w.ns[b];
     const T* d = w.d_in + (long long)b * w.sDin;
     const T* e = w.e_in + (long long)b * w.sDin;
-    T mx = T(0);
+    double mx = 0.0;
     for (int p = threadIdx.x; p < n; p += 256) {
-        mx = fmax(mx, fabs(d[p]));
-        if (p < n - 1) mx = fmax(mx, fabs(e[p]));
+        mx = fmax(mx, fabs((double)d[p]));
+        if (p < n - 1) mx = fmax(mx, fabs((double)e[p]));
     }
     mx = block_max256(mx, red);
-    if (mx == T(0)) mx = T(1);
-    const T inv = T(1) / mx;
-    T* D = w.D + (long long)b * w.sV;
-    T* E = w.E + (long long)b * w.sV;
+    if (mx == 0.0) mx = 1.0;
+    const double inv = 1.0 / mx;
+    double* D = w.D + (long long)b * w.sV;
+    double* E = w.E + (long long)b * w.sV;
     for (int p = threadIdx.x; p < n; p += 256) {
-        T el = p > 0 ? fabs(e[p - 1]) * inv : T(0);
-        T er = p < n - 1 ? fabs(e[p]) * inv : T(0);
-        D[p] = d[p] * inv - el - er;
-        E[p] = p < n - 1 ? e[p] * inv : T(0);
+        const double el = p > 0 ? fabs((double)e[p - 1]) * inv : 0.0;
+        const double er = p < n - 1 ? fabs((double)e[p]) * inv : 0.0;
+        D[p] = (double)d[p] * inv - el - er;
+        E[p] = p < n - 1 ? (double)e[p] * inv : 0.0;
     }
     if (threadIdx.x == 0) w.scale[b] = mx;
 }
@@ -82,13 +82,14 @@ __global__ __launch_bounds__(256) void stedc_setup_kernel(StedcWs<T> w, int lev,
     const MatBatch<T>& Zc = src ? w.Z1 : w.Z0;
     const T* Zb = Zc.at(b);
     const long long ld = Zc.ld;
-    const T* D = w.D + (long long)b * w.sV;
-    const T ee = w.E[(long long)b * w.sV + m.o + m.k1 - 1];
-    const T sg = ee >= T(0) ? T(1) : T(-1);
+    const double* D = w.D + (long long)b * w.sV;
+    const double ee = w.E[(long long)b * w.sV + m.o + m.k1 - 1];
+    const double sg = ee >= 0.0 ? 1.0 : -1.0;
     const int lp = p - m.o;
-    const T dp = D[p];
-    const T inv_sqrt2 = T(0.70710678118654752440);
-    T zp = lp < m.k1 ? Zb[(m.o + m.k1 - 1) + (long long)p * ld] : sg * Zb[(m.o + m.k1) + (long long)p * ld];
+    const double dp = D[p];
+    const double inv_sqrt2 = 0.70710678118654752440;
+    double zp = lp < m.k1 ? (double)Zb[(m.o + m.k1 - 1) + (long long)p * ld]
+                          : sg * (double)Zb[(m.o + m.k1) + (long long)p * ld];
     zp *= inv_sqrt2;
     int rank;
     if (lp < m.k1) {
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void stedc_setup_kernel(StedcWs<T> w, int lev,
     w.ds[base + rank] = dp;
     w.zs[base + rank] = zp;
     w.perm[base + rank] = lp;
-    if (lp == 0) w.rho[base] = T(2) * fabs(ee);
+    if (lp == 0) w.rho[base] = 2.0 * fabs(ee);
 }
 
 // sequential deflation scan, one thread per merge
@@ -119,33 +120,34 @@ __global__ __launch_bounds__(64) void stedc_deflate_kernel(StedcWs<T> w, int lev
     const MergeInfo m = merge_of(o, lev, n);
     if (!m.active()) return;
     const long long base = (long long)b * w.sV + o;
-    T* ds = w.ds + base;
-    T* zs = w.zs + base;
+    double* ds = w.ds + base;
+    double* zs = w.zs + base;
     const int* perm = w.perm + base;
     int* ndpos = w.ndpos + base;
     int* dfpos = w.dfpos + base;
-    const T rho = w.rho[base];
-    T dmax = T(0), zmax = T(0);
+    const double rho = w.rho[base];
+    double dmax = 0.0, zmax = 0.0;
     for (int j = 0; j < m.k; j++) { dmax = fmax(dmax, fabs(ds[j])); zmax = fmax(zmax, fabs(zs[j])); }
-    const T tol = T(8) * num_limits<T>::eps * fmax(dmax, zmax);
+    // deflation at the precision of the eigenvector matrices
+    const double tol = 8.0 * (double)num_limits<T>::eps * fmax(dmax, zmax);
     int K = 0, ndf = 0, nrot = 0, pj = -1;
     for (int jx = 0; jx < m.k; jx++) {
         if (rho * fabs(zs[jx]) <= tol) { dfpos[ndf++] = jx; continue; }
         if (pj < 0) { pj = jx; continue; }
-        T s = zs[pj], c = zs[jx];
-        const T tau = sqrt(c * c + s * s);
-        const T tt = ds[jx] - ds[pj];
+        double s = zs[pj], c = zs[jx];
+        const double tau = sqrt(c * c + s * s);
+        const double tt = ds[jx] - ds[pj];
         c /= tau;
         s = -s / tau;
         if (fabs(tt * c * s) <= tol) {
             zs[jx] = tau;
-            zs[pj] = T(0);
+            zs[pj] = 0.0;
             w.rp[base + nrot] = perm[pj];
             w.rq[base + nrot] = perm[jx];
             w.rc[base + nrot] = c;
             w.rs[base + nrot] = s;
             nrot++;
-            const T dpj = ds[pj] * c * c + ds[jx] * s * s;
+            const double dpj = ds[pj] * c * c + ds[jx] * s * s;
             ds[jx] = ds[pj] * s * s + ds[jx] * c * c;
             ds[pj] = dpj;
             dfpos[ndf++] = pj;
@@ -181,10 +183,10 @@ __global__ __launch_bounds__(256) void stedc_rotate_kernel(StedcWs<T> w, int lev
     const long long ld = Zc.ld;
     for (int q = 0; q < nrot; q++) {
         const long long ca = m.o + w.rp[base + q], cb = m.o + w.rq[base + q];
-        const T c = w.rc[base + q], s = w.rs[base + q];
-        const T x = Zb[r + ca * ld], y = Zb[r + cb * ld];
-        Zb[r + ca * ld] = c * x + s * y;
-        Zb[r + cb * ld] = c * y - s * x;
+        const double c = w.rc[base + q], s = w.rs[base + q];
+        const double x = Zb[r + ca * ld], y = Zb[r + cb * ld];
+        Zb[r + ca * ld] = (T)(c * x + s * y);
+        Zb[r + cb * ld] = (T)(c * y - s * x);
     }
 }
 
@@ -202,34 +204,34 @@ __global__ __launch_bounds__(256) void stedc_secular_kernel(StedcWs<T> w, int le
     const int K = w.Kcnt[base];
     const int jx = p - m.o;
     if (jx >= K) return;
-    const T* dn = w.dn + base;
-    const T* zn = w.zn + base;
-    const T rho = w.rho[base];
+    const double* dn = w.dn + base;
+    const double* zn = w.zn + base;
+    const double rho = w.rho[base];
     int org;
-    T lo, hi;
+    double lo, hi;
     if (jx < K - 1) {
-        const T mid = T(0.5) * (dn[jx] + dn[jx + 1]);
-        T f = T(0);
+        const double mid = 0.5 * (dn[jx] + dn[jx + 1]);
+        double f = 0.0;
         for (int i = lane; i < K; i += 64) f += zn[i] * zn[i] / (dn[i] - mid);
-        f = T(1) + rho * wave_sum(f);
-        if (f >= T(0)) { org = jx; lo = T(0); hi = mid - dn[jx]; }
-        else { org = jx + 1; lo = mid - dn[jx + 1]; hi = T(0); }
+        f = 1.0 + rho * wave_sum(f);
+        if (f >= 0.0) { org = jx; lo = 0.0; hi = mid - dn[jx]; }
+        else { org = jx + 1; lo = mid - dn[jx + 1]; hi = 0.0; }
     } else {
-        T z2 = T(0);
+        double z2 = 0.0;
         for (int i = lane; i < K; i += 64) z2 += zn[i] * zn[i];
-        org = K - 1; lo = T(0); hi = rho * wave_sum(z2);
+        org = K - 1; lo = 0.0; hi = rho * wave_sum(z2);
     }
-    const T dorg = dn[org];
-    for (int it = 0; it < 400; it++) {
-        const T mm = T(0.5) * (lo + hi);
+    const double dorg = dn[org];
+    for (int it = 0; it < 1100; it++) {
+        const double mm = 0.5 * (lo + hi);
         if (mm == lo || mm == hi) break;
-        T f = T(0);
+        double f = 0.0;
         for (int i = lane; i < K; i += 64) f += zn[i] * zn[i] / ((dn[i] - dorg) - mm);
-        f = T(1) + rho * wave_sum(f);
-        if (f < T(0)) lo = mm; else hi = mm;
+        f = 1.0 + rho * wave_sum(f);
+        if (f < 0.0) lo = mm; else hi = mm;
     }
     if (lane == 0) {
-        const T mu = T(0.5) * (lo + hi);
+        const double mu = 0.5 * (lo + hi);
         w.org[base + jx] = org;
         w.mu[base + jx] = mu;
         w.lam[base + jx] = dorg + mu;
@@ -249,23 +251,23 @@ __global__ __launch_bounds__(256) void stedc_zhat_kernel(StedcWs<T> w, int lev) 
     const int K = w.Kcnt[base];
     const int i = p - m.o;
     if (i >= K) return;
-    const T* dn = w.dn + base;
-    const T* mu = w.mu + base;
+    const double* dn = w.dn + base;
+    const double* mu = w.mu + base;
     const int* org = w.org + base;
-    const T di = dn[i];
-    T prod = ((dn[org[i]] - di) + mu[i]) / w.rho[base];
+    const double di = dn[i];
+    double prod = ((dn[org[i]] - di) + mu[i]) / w.rho[base];
     for (int j = 0; j < K; j++) {
         if (j == i) continue;
         prod *= ((dn[org[j]] - di) + mu[j]) / (dn[j] - di);
     }
-    const T z = sqrt(fmax(prod, T(0)));
-    w.zh[base + i] = w.zn[base + i] >= T(0) ? z : -z;
+    const double z = sqrt(fmax(prod, 0.0));
+    w.zh[base + i] = w.zn[base + i] >= 0.0 ? z : -z;
 }
 
 // eigenvectors of D + rho z z^T: u_i = zhat_i / (d_i - lambda_j), normalised
 template <typename T>
 __global__ __launch_bounds__(256) void stedc_vectors_kernel(StedcWs<T> w, int lev) {
-    __shared__ T red[4];
+    __shared__ double red[4];
     const int b = blockIdx.z;
     const int n = w.ns[b];
     const int p = blockIdx.x;
@@ -276,22 +278,22 @@ __global__ __launch_bounds__(256) void stedc_vectors_kernel(StedcWs<T> w, int le
     const int K = w.Kcnt[base];
     const int jx = p - m.o;
     if (jx >= K) return;
-    const T* dn = w.dn + base;
-    const T* zh = w.zh + base;
-    const T dorg = dn[w.org[base + jx]];
-    const T muj = w.mu[base + jx];
-    T ss = T(0);
+    const double* dn = w.dn + base;
+    const double* zh = w.zh + base;
+    const double dorg = dn[w.org[base + jx]];
+    const double muj = w.mu[base + jx];
+    double ss = 0.0;
     for (int i = threadIdx.x; i < K; i += 256) {
-        const T u = zh[i] / ((dn[i] - dorg) - muj);
+        const double u = zh[i] / ((dn[i] - dorg) - muj);
         ss += u * u;
     }
     ss = block_sum256(ss, red);
-    const T inv = T(1) / sqrt(ss);
+    const double inv = 1.0 / sqrt(ss);
     T* Ub = w.U.at(b);
     const long long ld = w.U.ld;
     for (int i = threadIdx.x; i < K; i += 256) {
-        const T u = zh[i] / ((dn[i] - dorg) - muj);
-        Ub[(m.o + i) + (long long)(m.o + jx) * ld] = u * inv;
+        const double u = zh[i] / ((dn[i] - dorg) - muj);
+        Ub[(m.o + i) + (long long)(m.o + jx) * ld] = (T)(u * inv);
     }
 }
 
@@ -306,15 +308,15 @@ __global__ __launch_bounds__(256) void stedc_order_kernel(StedcWs<T> w, int lev)
     if (!m.active()) return;
     const long long base = (long long)b * w.sV + m.o;
     const int K = w.Kcnt[base];
-    const T* lam = w.lam + base;
-    const T* ds = w.ds + base;
+    const double* lam = w.lam + base;
+    const double* ds = w.ds + base;
     const int* dfpos = w.dfpos + base;
     const int it = p - m.o;
-    auto val = [&](int q) -> T { return q < K ? lam[q] : ds[dfpos[q - K]]; };
-    const T v = val(it);
+    auto val = [&](int q) -> double { return q < K ? lam[q] : ds[dfpos[q - K]]; };
+    const double v = val(it);
     int rank = 0;
     for (int q = 0; q < m.k; q++) {
-        const T u = val(q);
+        const double u = val(q);
         rank += (u < v) || (u == v && q < it);
     }
     if (it < K) w.outnd[base + it] = rank;
@@ -426,7 +428,7 @@ __global__ __launch_bounds__(256) void stedc_final_kernel(StedcWs<T> w) {
     const int n = w.ns[b];
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
-    w.w_out[(long long)b * w.sW + p] = w.D[(long long)b * w.sV + p] * w.scale[b];
+    w.w_out[(long long)b * w.sW + p] = (T)(w.D[(long long)b * w.sV + p] * w.scale[b]);
 }
 
 template <typename T>

@@ -77,10 +77,14 @@ struct StedcWs {
     const int* ns;
     int nmax;
     const T* d_in; const T* e_in; long long sDin;
-    T* D; T* E; long long sV;     // per-matrix vectors of length nmax (stride sV)
-    T* scale;                     // [nbatch]
-    MatBatch<T> Z0, Z1, U;        // eigenvector ping-pong and secular vector blocks
-    T* ds; T* zs; T* dn; T* zn; T* mu; T* lam; T* zh; T* rho; T* rc; T* rs;
+    // The rank-one-update algebra (poles, updating vector, secular roots,
+    // Loewner vector, eigenvector formation) runs in FP64 for both T; only
+    // the eigenvector matrices and their products are in T.
+    double* D; double* E; long long sV;  // per-matrix vectors of length nmax (stride sV)
+    double* scale;                       // [nbatch]
+    MatBatch<T> Z0, Z1, U;               // eigenvector ping-pong and secular vector blocks
+    double* ds; double* zs; double* dn; double* zn; double* mu; double* lam; double* zh; double* rho;
+    double* rc; double* rs;
     int* perm; int* ndpos; int* dfpos; int* org; int* outnd; int* outdf; int* rp; int* rq;
     int* Kcnt; int* rotcnt;
     T* w_out; long long sW;       // eigenvalues (ascending) out

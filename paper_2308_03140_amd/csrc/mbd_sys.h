@@ -41,16 +41,23 @@ void mbd_mirror_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatB
 void mbd_grad_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,
                             const double* cc, MatBatch<double> M);
 
-// Ogita-Aishima refinement
+// Ogita-Aishima refinement (one step per call; see k_refine.hip)
+#define OA_KMAX 32  // largest window of close eigenvalues solved by Rayleigh-Ritz
+struct OaWork {
+    double* colpart;  // [nbatch][nmax][6] per-column partial sums
+    unsigned* nclust; // [nbatch] unresolved close pairs of the last step
+    int* wstart;      // [nbatch][nmax] first column of each column's window
+    int* wlen;        // [nbatch][nmax] window length
+    double* wv;       // [nbatch][nmax][OA_KMAX] window rotation, per column
+};
+size_t oa_colpart_doubles(int nmax, int nbatch);
 void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd);
-void oa_stats_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S, MatBatch<double> G,
-                     double* lam, long long sL, double* colpart, double* stats, unsigned* nclust,
-                     const int* skip);
-void oa_update_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> S,
-                      MatBatch<double> G, const double* lam, long long sL, const double* stats, unsigned* nclust,
-                      double* colpart, const int* skip);
-void oa_second_flags_launch(hipStream_t st, const int* ns, int nbatch, const unsigned* nclust,
-                            const double* colpart, long long sL, double* stats, int* skip2);
+// X (in) -> T1 (out, refined); T2 and G are scratch; stats[4b..4b+3] =
+// {delta, max|I - X^T X|, rho, max|X|}; next[b] = 1 where no further step is
+// needed; matrices with skip[b] != 0 get T1 = X and keep lam
+void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> Q, MatBatch<double> X,
+                    MatBatch<double> T1, MatBatch<double> T2, MatBatch<double> G, double* lam, long long sL,
+                    const OaWork& w, double* stats, const int* skip, int* next);
 void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> src,
                      MatBatch<double> dst);
 void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v);

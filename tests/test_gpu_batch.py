@@ -71,3 +71,40 @@ def test_batch_repeat_and_status(ctx):
     assert [o["status"] for o in outs] == [0, 2, 0]
     ref = oracle.mbd_finite(mols[1]["coords"], mols[1]["alpha0"], mols[1]["omega"], mols[1]["rvdw"])
     assert abs(outs[2]["energy"].item() - ref["energy"]) / len(mols[1]["omega"]) <= TOL_E[ctx.precision]
+
+
+def test_molecule_batch_512():
+    """The 512-molecule workload (N ~ U{10..300}) in one batched call with
+    FP32 + refinement: every molecule against the FP64 GPU path, and a seeded
+    sample (plus the largest molecule) against the oracle."""
+    from paper_2308_03140_amd import torch_api as T
+    _note("molecule batch 512")
+    mols = gen.molecule_batch()
+    systems = [dict(m, coords=torch.tensor(m["coords"], device="cuda")) for m in mols]
+    c32 = T.Context(0, "fp32_refined")
+    c64 = T.Context(0, "fp64")
+    o32 = T.evaluate_batch(c32, systems)
+    o64 = T.evaluate_batch(c64, systems)
+    worst = {"E": 0.0, "R": 0.0, "a": 0.0, "w": 0.0}
+    for m, a, b in zip(mols, o32, o64):
+        assert a["status"] == 0 and b["status"] == 0
+        N = len(m["omega"])
+        worst["E"] = max(worst["E"], abs(a["energy"].item() - b["energy"].item()) / N)
+        for k, key in (("R", "grad_coords"), ("a", "grad_alpha0"), ("w", "grad_omega")):
+            worst[k] = max(worst[k], (a[key] - b[key]).abs().max().item())
+    _note("  worst vs FP64: %s" % worst)
+    assert worst["E"] <= 1e-7 and max(worst["R"], worst["a"], worst["w"]) <= 1e-6, worst
+    rng = np.random.default_rng(41)
+    sample = sorted(set(rng.choice(len(mols), 6, replace=False).tolist())
+                    | {int(np.argmax([len(m["omega"]) for m in mols]))})
+    for i in sample:
+        m = mols[i]
+        ref = oracle.mbd_finite(m["coords"], m["alpha0"], m["omega"], m["rvdw"], m["beta"], m["a"])
+        N = len(m["omega"])
+        for o, tolE in ((o32[i], 1e-7), (o64[i], 1e-10)):
+            assert abs(o["energy"].item() - ref["energy"]) / N <= tolE, (i, N)
+            assert np.abs(o["grad_coords"].cpu().numpy() - ref["grad_R"]).max() <= 1e-6, (i, N)
+            assert np.abs(o["grad_alpha0"].cpu().numpy() - ref["grad_alpha0"]).max() <= 1e-6, (i, N)
+            assert np.abs(o["grad_omega"].cpu().numpy() - ref["grad_omega"]).max() <= 1e-6, (i, N)
+    c32.close()
+    c64.close()
