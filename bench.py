@@ -39,7 +39,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample=300):
+def cpu_baseline(n_sample=700):
     """The oracle as it stands (Jacobi eigensolver, energy + gradients) on a
     bounded sample: the first n_sample atoms of the N=2000 cluster, scaled to
     N=2000 by the cubic cost law of the dense eigenproblem."""
@@ -212,6 +212,30 @@ def leg_periodic(args, torch, T):
                 "grad_lattice_Ha_per_bohr": float(np.abs(o32["grad_lattice"] - o64["grad_lattice"]).max())}}
 
 
+def pmc_pass(torch, T):
+    """Runs under rocprofv3 --pmc: one FP32+refine N=2000 evaluation (after an
+    autotuned warm-up evaluation) and one device-to-device copy of 2^28 floats
+    (1 GiB read + 1 GiB written) whose counters calibrate FETCH_SIZE/WRITE_SIZE."""
+    import gen
+    dev = torch.device("cuda", 0)
+    c = gen.cluster_n2000()
+    args = [torch.tensor(c[k], device=dev) for k in ("coords", "alpha0", "omega", "rvdw")]
+    ctx = T.Context(0, "fp32_refined")
+    ctx.autotune([3 * len(c["omega"])])
+    T.evaluate(ctx, *args, beta=c["beta"], a=c["a"])
+    torch.cuda.synchronize()
+    log("[bench] pmc pass: evaluation")
+    T.evaluate(ctx, *args, beta=c["beta"], a=c["a"])
+    torch.cuda.synchronize()
+    x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    log("[bench] pmc pass: 1 GiB copy")
+    y.copy_(x)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +244,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="c2,batch,periodic")
     ap.add_argument("--tuning-dir", default=None, help="write the autotuner tables (JSON) here")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="counter-collection pass: one FP32+refine N=2000 evaluation, then a plain device copy "
+                         "of 1 GiB (the calibration kernel of known traffic); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -233,6 +260,9 @@ def main():
     from paper_2308_03140_amd import _abi as A
     from paper_2308_03140_amd import torch_api as T
 
+    if args.pmc_pass:
+        pmc_pass(torch, T)
+        return
     r = leg_c2(args, torch, T, A)
     e64, e32 = r["fp64"]["out"], r["fp32_refined"]["out"]
     N = r["N"]

@@ -37,6 +37,12 @@
 
 namespace cg = cooperative_groups;
 
+// occupancy target of the SYMV kernel (waves per SIMD): the largest at which
+// the compiler keeps the tile loop free of register spills
+template <typename T> struct SymvWaves;
+template <> struct SymvWaves<float> { static constexpr int value = 4; };
+template <> struct SymvWaves<double> { static constexpr int value = 2; };
+
 template <typename T>
 struct Refl {
     T beta, tau, scale;
@@ -74,11 +80,12 @@ __device__ __forceinline__ Refl<T> refl_scalars(const SytrdWs<T>& w, int b, int 
 }
 
 // tiles per work item of the SYMV phase, from the trailing block count
+#define SYTRD_KTMAX 16
 __host__ __device__ __forceinline__ int sytrd_kt(int nbt, int nbatch, int target) {
     const long long tiles = (long long)nbt * (nbt + 1) / 2 * nbatch;
     long long kt = (tiles + target - 1) / target;
     if (kt < 1) kt = 1;
-    if (kt > 16) kt = 16;
+    if (kt > SYTRD_KTMAX) kt = SYTRD_KTMAX;
     return (int)kt;
 }
 
@@ -112,6 +119,7 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
                           const Refl<T>* rf_in) {
     __shared__ T tb[64][65];
     __shared__ T rrow[4][64];
+    __shared__ T rpart[SYTRD_KTMAX][4][64];  // per-tile, per-wave row partials
     __shared__ T red[4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int s = i + 1;
@@ -128,6 +136,12 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
     const int c0 = C * 64 + wv * 16;
 
     T a[16], an[16];
+    // column base pointers are wave-uniform (scalar registers); the row is a
+    // 32-bit per-lane offset
+    // The wave's 16 columns are one buffer resource; masked elements (outside
+    // the trailing matrix or above the diagonal) read as zero through an
+    // out-of-range offset.
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(A + (long long)c0 * ld, (unsigned)(16 * ld * (long long)sizeof(T)));
     auto load_tile = [&](int R, T* dst) {
         const int r = R * 64 + lane;
         const bool rok = (r < n) && (r >= s);
@@ -135,7 +149,7 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
         for (int k = 0; k < 16; k++) {
             const int c = c0 + k;
             const bool ok = rok && (c < n) && (c >= s) && (R > C || r >= c);
-            dst[k] = ok ? A[r + (long long)c * ld] : T(0);
+            dst[k] = buf_load<T>(rsrc, ok ? (unsigned)((k * (int)ld + r) * (int)sizeof(T)) : OOB_OFFSET);
         }
     };
     // the first tile is in flight while the reflector and vectors are formed
@@ -157,17 +171,28 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
             w.e[(long long)b * w.sD + i] = rf.beta;
             w.tau[(long long)b * w.sD + i] = rf.tau;
         }
-        // panel products over the rows of block C
+        // panel products over the rows of block C: wave wv takes columns
+        // k = wv, wv + 4, ...; all loads are issued before the reductions
         T* PS = w.PS + (long long)b * w.sPS + (long long)C * (2 * NBP);
         const int r = C * 64 + lane;
         const bool rv = (r >= s && r < n);
         const T vr = rv ? refl_v(col, r, s, n, rf.scale) : T(0);
-        for (int k = wv; k < j; k += 4) {
-            T pw = rv ? Wp[r + (long long)k * ldp] * vr : T(0);
-            T pv = rv ? Vp[r + (long long)k * ldp] * vr : T(0);
-            pw = wave_sum(pw);
-            pv = wave_sum(pv);
-            if (lane == 0) { PS[k] = pw; PS[NBP + k] = pv; }
+        T pw[NBP / 4], pv[NBP / 4];
+#pragma unroll
+        for (int t = 0; t < NBP / 4; t++) {
+            const int k = wv + 4 * t;
+            const bool ok = rv && k < j;
+            pw[t] = ok ? Wp[r + (long long)k * ldp] : T(0);
+            pv[t] = ok ? Vp[r + (long long)k * ldp] : T(0);
+        }
+#pragma unroll
+        for (int t = 0; t < NBP / 4; t++) {
+            const int k = wv + 4 * t;
+            if (k < j) {
+                const T sw = wave_sum(pw[t] * vr);
+                const T sv = wave_sum(pv[t] * vr);
+                if (lane == 0) { PS[k] = sw; PS[NBP + k] = sv; }
+            }
         }
     }
 
@@ -178,6 +203,9 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
 #pragma unroll
     for (int k = 0; k < 16; k++) cacc[k] = T(0);
     T vav = T(0);
+    // each wavefront streams its 16 columns through the chunk without block
+    // barriers; its row partials go to its own LDS slot and are summed over
+    // the 4 wavefronts in a fixed order after the loop
     for (int R = Rb; R < Re; R++) {
         if (R + 1 < Re) load_tile(R + 1, an);
         const int r = R * 64 + lane;
@@ -189,18 +217,18 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
             const bool offd = (R > C) || (r != c0 + k);
             cacc[k] += offd ? a[k] * vr : T(0);
         }
-        rrow[wv][lane] = rs;
-        __syncthreads();
-        if (wv == 0) {
-            const T y = (rrow[0][lane] + rrow[1][lane]) + (rrow[2][lane] + rrow[3][lane]);
-            w.P1[(long long)b * w.sP1 + ((long long)C * w.nbk_max + R) * 64 + lane] = y;
-            vav += vr * y;
-        }
-        __syncthreads();
+        rpart[R - Rb][wv][lane] = rs;
         if (R + 1 < Re) {
 #pragma unroll
             for (int k = 0; k < 16; k++) a[k] = an[k];
         }
+    }
+    __syncthreads();
+    for (int t = wv; t < Re - Rb; t += 4) {
+        const T y = (rpart[t][0][lane] + rpart[t][1][lane]) + (rpart[t][2][lane] + rpart[t][3][lane]);
+        const int R = Rb + t;
+        w.P1[(long long)b * w.sP1 + ((long long)C * w.nbk_max + R) * 64 + lane] = y;
+        vav += refl_v(col, R * 64 + lane, s, n, rf.scale) * y;
     }
     // column sums of the strip: transpose through LDS
 #pragma unroll
@@ -353,7 +381,8 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
 // kernels
 // ---------------------------------------------------------------------------
 template <typename T, int NBP>
-__global__ __launch_bounds__(256) void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SymvWaves<T>::value)))
+void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
     const int slot = blockIdx.y * gridDim.x + blockIdx.x;
@@ -505,14 +534,18 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                 }
         bool done = false;
         if (persistent) {
-            if (timing) prof->begin(st);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timing) {
+                prof->pair(&e0, &e1, 0, bytes);
+                hipEventRecord(e0, st);
+            }
             SytrdWs<T> wc = w;
             int a1 = k0, a2 = k1, a3 = nbatch, a4 = 2 * P;
             void* args[] = {&wc, &a1, &a2, &a3, &a4};
             done = hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T, NBP>, dim3(P), dim3(256), args, 0,
                                               st) == hipSuccess;
             if (!done) (void)hipGetLastError();
-            if (timing) prof->end(st, 0, done ? bytes : 0.0);
+            if (timing) hipEventRecord(e1, st);
         }
         if (!done) {
             for (int i = k0; i < k1; i++) {
@@ -521,15 +554,19 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                 const int nbt = nbk_max - b0;
                 const int Kt = sytrd_kt(nbt, nbatch, w.chunk_target > 0 ? w.chunk_target : 1536);
                 const int gx = (nbt + Kt - 1) / Kt;
-                if (timing) prof->begin(st);
-                hipLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j, Kt);
                 if (timing) {
                     double bb = 0;
                     for (int b = 0; b < nbatch; b++) {
                         const double m = ns_host[b] - i - 1;
                         if (m > 0) bb += m * (m + 1) * 0.5 * sizeof(T);
                     }
-                    prof->end(st, 0, bb);
+                    hipEvent_t e0, e1;
+                    prof->pair(&e0, &e1, 0, bb);
+                    hipExtLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, e0, e1,
+                                          0, w, i, j, Kt);
+                } else {
+                    hipLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j,
+                                       Kt);
                 }
                 hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j,
                                    Kt, gx * nbt);
@@ -540,16 +577,19 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
             const int tm = (nmax - t0 + 63) / 64;
             Syr2kProb<T, NBP> p;
             p.A = w.A; p.ns = w.ns; p.Vp = w.Vp; p.Wp = w.Wp; p.ldp = w.ldp; p.sP = w.sP; p.t0 = t0;
-            if (timing) prof->begin(st);
-            hipLaunchKernelGGL((gemm_mfma_kernel<T, Syr2kProb<T, NBP>>), dim3(tm * (tm + 1) / 2, 1, nbatch),
-                               dim3(256), 0, st, p);
             if (timing) {
                 double flops = 0;
                 for (int b = 0; b < nbatch; b++) {
                     const double m = ns_host[b] - t0;
                     if (m > 0) flops += 2.0 * (2 * NBP) * m * (m + 1) * 0.5;
                 }
-                prof->end(st, 1, flops);
+                hipEvent_t e0, e1;
+                prof->pair(&e0, &e1, 1, flops);
+                hipExtLaunchKernelGGL((gemm_mfma_kernel<T, Syr2kProb<T, NBP>>), dim3(tm * (tm + 1) / 2, 1, nbatch),
+                                      dim3(256), 0, st, e0, e1, 0, p);
+            } else {
+                hipLaunchKernelGGL((gemm_mfma_kernel<T, Syr2kProb<T, NBP>>), dim3(tm * (tm + 1) / 2, 1, nbatch),
+                                   dim3(256), 0, st, p);
             }
         }
     }

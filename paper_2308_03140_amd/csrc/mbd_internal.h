@@ -69,6 +69,23 @@ __device__ __forceinline__ T block_max256(T v, T* red) {
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// Raw buffer loads (gfx9 descriptor, stride 0).  A byte offset at or beyond
+// num_records reads as zero, so masked elements are fetched without a branch
+// by giving them the offset OOB_OFFSET.
+// ---------------------------------------------------------------------------
+#define OOB_OFFSET 0x80000000u
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 template <typename T> struct num_limits;
 template <> struct num_limits<double> { static constexpr double eps = 2.220446049250313e-16; };
 template <> struct num_limits<float> { static constexpr float eps = 1.1920929e-07f; };

@@ -3,6 +3,7 @@
 #include "mbd_internal.h"
 
 #include <vector>
+#include <hip/hip_ext.h>
 
 // Optional HIP-event timing of individual launches (measurement tools only).
 // kind 0: per-column SYMV of the reduction (BLAS-2), 1: trailing SYR2K
@@ -23,12 +24,11 @@ struct LaunchProfiler {
         }
         return pool[used++];
     }
-    void begin(hipStream_t st) {
-        if (enabled) hipEventRecord(next(), st);
-    }
-    void end(hipStream_t st, int k, double w) {
-        if (!enabled) return;
-        hipEventRecord(next(), st);
+    // Event pair for one launch through hipExtLaunchKernelGGL, which stamps
+    // the dispatch's own start and end (no extra packets on the stream).
+    void pair(hipEvent_t* start, hipEvent_t* stop, int k, double w) {
+        *start = next();
+        *stop = next();
         kind.push_back(k);
         work.push_back(w);
     }
