@@ -4,8 +4,8 @@ Rule (applied before any timing): with mu_min the smallest eigenvalue of
 alpha0^{1/2} T^lr alpha0^{1/2}, if 1 + mu_min <= 0.05 all alpha0 are scaled by
 s = 0.9/|mu_min| (so 1 + s mu_min = 0.1); else s = 1.  mu_min is bracketed by
 the oracle's Cholesky test (S - t I is positive definite iff t < mu_min), so
-only the oracle is called.  The N=8000 cluster reuses the N=2000 factor (same
-density and distributions; its oracle factorisation is out of reach on CPU).
+only the oracle is called.  The N=8000 cluster is bracketed the same way
+(about 11 Cholesky factorisations of order 24000 on the CPU).
 
     python gen/make_alpha_scale.py [names...]
 """
@@ -53,7 +53,9 @@ def main(names):
         if name == "cluster_n2000":
             s, mu = scale_for(gen.finite_cluster(2, 2000, gen.cube_side_for_density(2000)))
             table[name] = s
-            table["cluster_n8000"] = s
+        elif name == "cluster_n8000":
+            s, mu = scale_for(gen.finite_cluster(5, 8000, gen.cube_side_for_density(8000)))
+            table[name] = s
         elif name == "crystal_n64":
             c = gen.crystal_n64()
             mu = 1e300

@@ -136,22 +136,21 @@ template <typename T>
 mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int nbatch, SytrdWs<T>& sw) {
     const std::string t = tname<T>();
     const int nbk = (nmax + 63) / 64;
-    sw.A = A; sw.ns = ns; sw.nmax = nmax; sw.nbk_max = nbk; sw.maxchunk = nbk;
+    sw.A = A; sw.ns = ns; sw.nmax = nmax; sw.nbk_max = nbk;
     sw.ldp = round_up(nmax, 64);
     sw.sP = (long long)sw.ldp * SYTRD_NBP;
     sw.Vp = wsT<T>(c, "Vp" + t, sw.sP * nbatch);
     sw.Wp = wsT<T>(c, "Wp" + t, sw.sP * nbatch);
     sw.sC = nmax; sw.colbuf = wsT<T>(c, "colbuf" + t, (size_t)nmax * nbatch);
     sw.sNP = nbk; sw.normpart = wsT<T>(c, "normpart" + t, (size_t)nbk * nbatch);
-    sw.sP1 = (long long)nbk * nbk * 64; sw.P1 = wsT<T>(c, "P1" + t, sw.sP1 * nbatch);
-    sw.sP2 = (long long)nbk * nbk * 64; sw.P2 = wsT<T>(c, "P2" + t, sw.sP2 * nbatch);
-    sw.sPS = (long long)nbk * 2 * SYTRD_NBP; sw.PS = wsT<T>(c, "PS" + t, sw.sPS * nbatch);
-    sw.sPV = (long long)nbk * nbk; sw.PV = wsT<T>(c, "PV" + t, sw.sPV * nbatch);
+    sw.sY = 2LL * SYTRD_YCOPIES * nmax; sw.yacc = wsT<T>(c, "yacc" + t, (size_t)sw.sY * nbatch);
+    sw.sS = 2LL * SYTRD_YCOPIES * 2 * SYTRD_NBP; sw.sacc = wsT<T>(c, "sacc" + t, (size_t)sw.sS * nbatch);
+    sw.vacc = wsT<T>(c, "vacc" + t, (size_t)2 * SYTRD_VCOPIES * nbatch);
     sw.sD = nmax;
     sw.d = wsT<T>(c, "d" + t, (size_t)nmax * nbatch);
     sw.e = wsT<T>(c, "e" + t, (size_t)nmax * nbatch);
     sw.tau = wsT<T>(c, "tau" + t, (size_t)nmax * nbatch);
-    if (!sw.Vp || !sw.Wp || !sw.colbuf || !sw.normpart || !sw.P1 || !sw.P2 || !sw.PS || !sw.PV || !sw.d ||
+    if (!sw.Vp || !sw.Wp || !sw.colbuf || !sw.normpart || !sw.yacc || !sw.sacc || !sw.vacc || !sw.d ||
         !sw.e || !sw.tau)
         return (mbd_status)c->err_code;
     return MBD_OK;
@@ -208,8 +207,9 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
         OrmtrWs<T> ow;
         const int nsplit = (nmax + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
         ow.A = A; ow.tau = sw.tau; ow.sD = nmax; ow.ns = ns; ow.X = Z; ow.nmax = nmax;
-        ow.sG = (long long)nsplit * 4096; ow.Gpart = wsT<T>(c, "Gpart" + t, ow.sG * nbatch);
-        ow.sT = 4096; ow.Tm = wsT<T>(c, "Tm" + t, (size_t)4096 * nbatch);
+        const int nblk = (nmax - 1 + 63) / 64;
+        ow.sG = (long long)nblk * nsplit * 4096; ow.Gpart = wsT<T>(c, "Gpart" + t, ow.sG * nbatch);
+        ow.sT = (long long)nblk * 4096; ow.Tm = wsT<T>(c, "Tm" + t, (size_t)ow.sT * nbatch);
         ow.sYp = (long long)nsplit * 64 * nmax; ow.Ypart = wsT<T>(c, "Ypart" + t, ow.sYp * nbatch);
         ow.sY = (long long)64 * nmax; ow.Y = wsT<T>(c, "Yb" + t, ow.sY * nbatch);
         if (!ow.Gpart || !ow.Tm || !ow.Ypart || !ow.Y) return (mbd_status)c->err_code;

@@ -26,11 +26,13 @@ template <typename T>
 struct VtvProb {
     static constexpr bool A_M_CONTIG = false;
     static constexpr bool B_N_CONTIG = false;
-    MatBatch<T> A; const int* ns; int b0; T* Gpart; long long sG;
-    __device__ bool tile(int, int by, int bz, GemmTile& t) const {
+    MatBatch<T> A; const int* ns; T* Gpart; long long sG; int nsplit;
+    // grid: x = reflector block, y = row chunk, z = matrix; t.k = x*nsplit + y
+    __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
         const int n = ns[bz];
         const int nref = n - 1;
+        const int b0 = bx * 64;
         if (b0 >= nref) return false;
         const int m = n - b0 - 1;          // rows b0+1 .. n-1
         const int r0 = by * ORMTR_CHUNK;
@@ -38,13 +40,13 @@ struct VtvProb {
         t.m0 = 0; t.n0 = 0;
         t.K = min(ORMTR_CHUNK, m - r0);
         t.o = b0 + 1 + r0;
-        t.k = by;
+        t.k = bx * nsplit + by;
         return true;
     }
     __device__ T a(const GemmTile& t, int jj, int kk) const {
         if (kk >= t.K) return T(0);
-        const int n = ns[t.batch];
-        return hh_v(A.at(t.batch), A.ld, t.o + kk, b0 + jj, n - 1);
+        const int b0 = (t.k / nsplit) * 64;
+        return hh_v(A.at(t.batch), A.ld, t.o + kk, b0 + jj, ns[t.batch] - 1);
     }
     __device__ T b(const GemmTile& t, int kk, int jj) const { return a(t, jj, kk); }
     __device__ void store(const GemmTile& t, int m, int nn, T v) const {
@@ -52,21 +54,24 @@ struct VtvProb {
     }
 };
 
-// T factor of the block: T(j,j) = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) G(0:j, j)
+// T factor of every block (one workgroup each): T(j,j) = tau_j,
+// T(0:j, j) = -tau_j T(0:j,0:j) G(0:j, j), G = V^T V summed over row chunks
 template <typename T>
-__global__ __launch_bounds__(256) void ormtr_tfactor_kernel(OrmtrWs<T> w, int b0) {
+__global__ __launch_bounds__(256) void ormtr_tfactor_kernel(OrmtrWs<T> w, int nsplit) {
     __shared__ T G[64][65];
     __shared__ T Tm[64][65];
     const int b = blockIdx.z;
     const int n = w.ns[b];
     const int nref = n - 1;
+    const int blk = blockIdx.x;
+    const int b0 = blk * 64;
     if (b0 >= nref) return;
     const int m = n - b0 - 1;
-    const int nsplit = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
-    const T* Gp = w.Gpart + (long long)b * w.sG;
+    const int ns_used = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
+    const T* Gp = w.Gpart + (long long)b * w.sG + (long long)blk * nsplit * 4096;
     for (int idx = threadIdx.x; idx < 4096; idx += 256) {
         T s = T(0);
-        for (int q = 0; q < nsplit; q++) s += Gp[(long long)q * 4096 + idx];
+        for (int q = 0; q < ns_used; q++) s += Gp[(long long)q * 4096 + idx];
         G[idx & 63][idx >> 6] = s;
         Tm[idx & 63][idx >> 6] = T(0);
     }
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(256) void ormtr_tfactor_kernel(OrmtrWs<T> w, int b0
         if (k == j) Tm[j][j] = tj;
         __syncthreads();
     }
-    T* To = w.Tm + (long long)b * w.sT;
+    T* To = w.Tm + (long long)b * w.sT + (long long)blk * 4096;
     for (int idx = threadIdx.x; idx < 4096; idx += 256) To[idx] = Tm[idx & 63][idx >> 6];
 }
 
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(256) void ormtr_ty_kernel(OrmtrWs<T> w, int b0) {
     if (c0 >= n) return;
     const int m = n - b0 - 1;
     const int nsplit = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
-    const T* To = w.Tm + (long long)b * w.sT;
+    const T* To = w.Tm + (long long)b * w.sT + (long long)(b0 / 64) * 4096;
     const T* Yp = w.Ypart + (long long)b * w.sYp;
     for (int idx = threadIdx.x; idx < 4096; idx += 256) {
         const int jj = idx & 63, cc = idx >> 6;
@@ -198,12 +203,13 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     const int nblk = (nref + 63) / 64;
     const int tiles = (nmax + 63) / 64;
     const int nsplit = (nmax + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
+    // Gram matrices and T factors of all blocks up front (independent)
+    VtvProb<T> pg;
+    pg.A = w.A; pg.ns = w.ns; pg.Gpart = w.Gpart; pg.sG = w.sG; pg.nsplit = nsplit;
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, VtvProb<T>>), dim3(nblk, nsplit, nbatch), dim3(256), 0, st, pg);
+    hipLaunchKernelGGL(ormtr_tfactor_kernel<T>, dim3(nblk, 1, nbatch), dim3(256), 0, st, w, nsplit);
     for (int blk = nblk - 1; blk >= 0; blk--) {
         const int b0 = blk * 64;
-        VtvProb<T> pg;
-        pg.A = w.A; pg.ns = w.ns; pg.b0 = b0; pg.Gpart = w.Gpart; pg.sG = w.sG;
-        hipLaunchKernelGGL((gemm_mfma_kernel<T, VtvProb<T>>), dim3(1, nsplit, nbatch), dim3(256), 0, st, pg);
-        hipLaunchKernelGGL(ormtr_tfactor_kernel<T>, dim3(1, 1, nbatch), dim3(256), 0, st, w, b0);
         VtxProb<T> px;
         px.A = w.A; px.X = w.X; px.ns = w.ns; px.b0 = b0; px.Ypart = w.Ypart; px.sYp = w.sYp; px.nmax = w.nmax;
         hipLaunchKernelGGL((gemm_mfma_kernel<T, VtxProb<T>>), dim3(tiles, nsplit, nbatch), dim3(256), 0, st, px);

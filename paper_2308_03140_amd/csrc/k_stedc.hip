@@ -14,6 +14,8 @@
 // Secular roots: one wavefront per root, bisection in the variable
 // mu = lambda - d_origin, where the origin is the pole the root is closer to,
 // so differences d_i - lambda are formed without cancellation.
+#include <algorithm>
+
 #include "mbd_internal.h"
 #include "gemm_mfma.h"
 #include "mbd_kernels.h"
@@ -164,6 +166,88 @@ __global__ __launch_bounds__(64) void stedc_deflate_kernel(StedcWs<T> w, int lev
     }
     w.Kcnt[base] = K;
     w.rotcnt[base] = nrot;
+}
+
+// The same scan for merges of up to DEFL_LDS entries: one workgroup stages
+// the poles and the updating vector in LDS, so the serial scan by one thread
+// never waits on global memory; compaction and write-back are parallel.
+#define DEFL_LDS 7168
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_deflate_lds_kernel(StedcWs<T> w, int lev) {
+    __shared__ double sd[DEFL_LDS], sz[DEFL_LDS];
+    __shared__ int snd[DEFL_LDS];
+    __shared__ double red[4];
+    __shared__ int cnt;
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int o = blockIdx.x << lev;
+    if (o >= n) return;
+    const MergeInfo m = merge_of(o, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + o;
+    double* ds = w.ds + base;
+    double* zs = w.zs + base;
+    const int* perm = w.perm + base;
+    int* dfpos = w.dfpos + base;
+    const int k = m.k;
+    double dmax = 0.0, zmax = 0.0;
+    for (int j = threadIdx.x; j < k; j += 256) {
+        const double d = ds[j], z = zs[j];
+        sd[j] = d;
+        sz[j] = z;
+        dmax = fmax(dmax, fabs(d));
+        zmax = fmax(zmax, fabs(z));
+    }
+    dmax = block_max256(dmax, red);
+    zmax = block_max256(zmax, red);
+    // deflation at the precision of the eigenvector matrices
+    const double tol = 8.0 * (double)num_limits<T>::eps * fmax(dmax, zmax);
+    const double rho = w.rho[base];
+    if (threadIdx.x == 0) {
+        int K = 0, ndf = 0, nrot = 0, pj = -1;
+        for (int jx = 0; jx < k; jx++) {
+            if (rho * fabs(sz[jx]) <= tol) { dfpos[ndf++] = jx; continue; }
+            if (pj < 0) { pj = jx; continue; }
+            double sn = sz[pj], c = sz[jx];
+            const double tau = sqrt(c * c + sn * sn);
+            const double tt = sd[jx] - sd[pj];
+            c /= tau;
+            sn = -sn / tau;
+            if (fabs(tt * c * sn) <= tol) {
+                sz[jx] = tau;
+                sz[pj] = 0.0;
+                w.rp[base + nrot] = perm[pj];
+                w.rq[base + nrot] = perm[jx];
+                w.rc[base + nrot] = c;
+                w.rs[base + nrot] = sn;
+                nrot++;
+                const double dpj = sd[pj] * c * c + sd[jx] * sn * sn;
+                sd[jx] = sd[pj] * sn * sn + sd[jx] * c * c;
+                sd[pj] = dpj;
+                dfpos[ndf++] = pj;
+                pj = jx;
+            } else {
+                snd[K++] = pj;
+                pj = jx;
+            }
+        }
+        if (pj >= 0) snd[K++] = pj;
+        cnt = K;
+        w.Kcnt[base] = K;
+        w.rotcnt[base] = nrot;
+    }
+    __syncthreads();
+    const int K = cnt;
+    for (int j = threadIdx.x; j < k; j += 256) {
+        ds[j] = sd[j];
+        zs[j] = sz[j];
+    }
+    for (int kk = threadIdx.x; kk < K; kk += 256) {
+        const int p = snd[kk];
+        w.ndpos[base + kk] = p;
+        w.dn[base + kk] = sd[p];
+        w.zn[base + kk] = sz[p];
+    }
 }
 
 // apply the deflation rotations to the eigenvector columns of the merge
@@ -442,8 +526,12 @@ int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     for (int lev = 1; lev <= L; lev++) {
         const int nmerge = (nmax + (1 << lev) - 1) >> lev;
         hipLaunchKernelGGL(stedc_setup_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev, src);
-        hipLaunchKernelGGL(stedc_deflate_kernel<T>, dim3((nmerge + 63) / 64, 1, nbatch), dim3(64), 0, st, w,
-                           lev);
+        const int msize = std::min(1 << lev, nmax);
+        if (msize > 64 && msize <= DEFL_LDS)
+            hipLaunchKernelGGL(stedc_deflate_lds_kernel<T>, dim3(nmerge, 1, nbatch), dim3(256), 0, st, w, lev);
+        else
+            hipLaunchKernelGGL(stedc_deflate_kernel<T>, dim3((nmerge + 63) / 64, 1, nbatch), dim3(64), 0, st, w,
+                               lev);
         hipLaunchKernelGGL(stedc_rotate_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev, src);
         hipLaunchKernelGGL(stedc_secular_kernel<T>, dim3((nmax + 3) / 4, 1, nbatch), dim3(256), 0, st, w, lev);
         hipLaunchKernelGGL(stedc_zhat_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev);

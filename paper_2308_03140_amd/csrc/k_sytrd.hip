@@ -8,15 +8,16 @@
 //   SYMV phase    one pass over the not-yet-updated lower trailing matrix
 //                 A(i+1:n, i+1:n) in 64x64 tiles, each element read once and
 //                 used for both y_R += A_RC v_C and y_C += A_RC^T v_R; also
-//                 the panel products p = W^T v, s = V^T v and v^T A v.  This
-//                 is the bandwidth-bound BLAS-2 half of the reduction.
-//   finish phase  per 64-row block: reduce the tile partials, form
+//                 the panel products p = W^T v, s = V^T v and v^T A v, all
+//                 added into per-column accumulators with float atomics.
+//                 This is the bandwidth-bound BLAS-2 half of the reduction.
+//   finish phase  per 64-row block: read the accumulated y, form
 //                 w = tau (A v - V p - W s) - (tau/2)(w^T v) v, and apply the
 //                 panel to the next column so its reflector can be built
 //                 without another pass.
 // After the panel: A(t0:n, t0:n) -= V W^T + W V^T on matrix cores (the BLAS-3
-// half).  All partial sums are reduced in a fixed order, so results are
-// bitwise reproducible.
+// half).  The accumulation order of the atomics varies, so results agree
+// between runs to rounding, not bitwise.
 //
 // The two phases of all NBP columns of a panel run in one persistent
 // cooperative launch (a grid-wide sync after each phase), so the column loop
@@ -89,6 +90,25 @@ __host__ __device__ __forceinline__ int sytrd_kt(int nbt, int nbatch, int target
     return (int)kt;
 }
 
+// Accumulators of column i live in parity slot (i & 1).  To keep atomic
+// contention low they are spread over copies: y and the panel products over
+// SYTRD_YC copies chosen by column strip, v^T A v over SYTRD_VC copies chosen
+// by workgroup; the finish phase adds the copies.
+#define SYTRD_YC SYTRD_YCOPIES
+#define SYTRD_VC SYTRD_VCOPIES
+template <typename T>
+__device__ __forceinline__ T* yacc_of(const SytrdWs<T>& w, int b, int i, int copy) {
+    return w.yacc + (long long)b * w.sY + ((i & 1) * SYTRD_YC + copy) * (long long)w.nmax;
+}
+template <typename T>
+__device__ __forceinline__ T* sacc_of(const SytrdWs<T>& w, int b, int i, int copy) {
+    return w.sacc + (long long)b * w.sS + ((i & 1) * SYTRD_YC + copy) * (2 * SYTRD_NBP);
+}
+template <typename T>
+__device__ __forceinline__ T* vacc_of(const SytrdWs<T>& w, int b, int i) {
+    return w.vacc + (long long)b * (2 * SYTRD_VC) + (i & 1) * SYTRD_VC;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void sytrd_init_kernel(SytrdWs<T> w) {
     const int b = blockIdx.z;
@@ -98,6 +118,15 @@ __global__ __launch_bounds__(256) void sytrd_init_kernel(SytrdWs<T> w) {
     if (R >= nbk) return;
     const T* A = w.A.at(b);
     T* col = w.colbuf + (long long)b * w.sC;
+    // both parity slots of the accumulators start at zero
+    for (int t = threadIdx.x; t < 2 * SYTRD_YC * 64; t += 256) {
+        const int r = R * 64 + (t & 63);
+        if (r < n) w.yacc[(long long)b * w.sY + (t >> 6) * (long long)w.nmax + r] = T(0);
+    }
+    if (R == 0) {
+        for (int t = threadIdx.x; t < 2 * SYTRD_YC * 2 * SYTRD_NBP; t += 256) w.sacc[(long long)b * w.sS + t] = T(0);
+        for (int t = threadIdx.x; t < 2 * SYTRD_VC; t += 256) w.vacc[(long long)b * (2 * SYTRD_VC) + t] = T(0);
+    }
     if (n == 1) {
         if (threadIdx.x == 0) w.d[(long long)b * w.sD] = A[0];
         return;
@@ -112,10 +141,13 @@ __global__ __launch_bounds__(256) void sytrd_init_kernel(SytrdWs<T> w) {
 }
 
 // ---------------------------------------------------------------------------
-// SYMV work item: tiles R in [C + q Kt, C + (q+1) Kt) of column strip C
+// SYMV work item: tiles R in [C + q Kt, C + (q+1) Kt) of column strip C.
+// Row sums, column sums, the panel products and v^T A v are added into the
+// column's accumulators with hardware float atomics, so the finish phase
+// reads one value per row.
 // ---------------------------------------------------------------------------
 template <typename T, int NBP>
-__device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt, int C, int q, int slot,
+__device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt, int C, int q,
                           const Refl<T>* rf_in) {
     __shared__ T tb[64][65];
     __shared__ T rrow[4][64];
@@ -130,14 +162,13 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
     const T* col = w.colbuf + (long long)b * w.sC;
     T* Vp = w.Vp + (long long)b * w.sP;
     T* Wp = w.Wp + (long long)b * w.sP;
+    T* yacc = yacc_of(w, b, i, C % SYTRD_YC);
     const int ldp = w.ldp;
     const int Rb = C + q * Kt;
     const int Re = min(Rb + Kt, nbk);
     const int c0 = C * 64 + wv * 16;
 
     T a[16], an[16];
-    // column base pointers are wave-uniform (scalar registers); the row is a
-    // 32-bit per-lane offset
     // The wave's 16 columns are one buffer resource; masked elements (outside
     // the trailing matrix or above the diagonal) read as zero through an
     // out-of-range offset.
@@ -173,7 +204,7 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
         }
         // panel products over the rows of block C: wave wv takes columns
         // k = wv, wv + 4, ...; all loads are issued before the reductions
-        T* PS = w.PS + (long long)b * w.sPS + (long long)C * (2 * NBP);
+        T* sacc = sacc_of(w, b, i, C % SYTRD_YC);
         const int r = C * 64 + lane;
         const bool rv = (r >= s && r < n);
         const T vr = rv ? refl_v(col, r, s, n, rf.scale) : T(0);
@@ -191,7 +222,10 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
             if (k < j) {
                 const T sw = wave_sum(pw[t] * vr);
                 const T sv = wave_sum(pv[t] * vr);
-                if (lane == 0) { PS[k] = sw; PS[NBP + k] = sv; }
+                if (lane == 0) {
+                    unsafeAtomicAdd(&sacc[k], sw);
+                    unsafeAtomicAdd(&sacc[NBP + k], sv);
+                }
             }
         }
     }
@@ -205,7 +239,7 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
     T vav = T(0);
     // each wavefront streams its 16 columns through the chunk without block
     // barriers; its row partials go to its own LDS slot and are summed over
-    // the 4 wavefronts in a fixed order after the loop
+    // the 4 wavefronts after the loop
     for (int R = Rb; R < Re; R++) {
         if (R + 1 < Re) load_tile(R + 1, an);
         const int r = R * 64 + lane;
@@ -226,9 +260,11 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
     __syncthreads();
     for (int t = wv; t < Re - Rb; t += 4) {
         const T y = (rpart[t][0][lane] + rpart[t][1][lane]) + (rpart[t][2][lane] + rpart[t][3][lane]);
-        const int R = Rb + t;
-        w.P1[(long long)b * w.sP1 + ((long long)C * w.nbk_max + R) * 64 + lane] = y;
-        vav += refl_v(col, R * 64 + lane, s, n, rf.scale) * y;
+        const int r = (Rb + t) * 64 + lane;
+        if (r >= s && r < n) {
+            unsafeAtomicAdd(&yacc[r], y);
+            vav += refl_v(col, r, s, n, rf.scale) * y;
+        }
     }
     // column sums of the strip: transpose through LDS
 #pragma unroll
@@ -244,32 +280,31 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
     __syncthreads();
     if (tid < 64) {
         const T cs = (rrow[0][tid] + rrow[1][tid]) + (rrow[2][tid] + rrow[3][tid]);
-        w.P2[(long long)b * w.sP2 + ((long long)C * w.maxchunk + q) * 64 + tid] = cs;
-        vav += refl_v(col, C * 64 + tid, s, n, rf.scale) * cs;
+        const int c = C * 64 + tid;
+        if (c >= s && c < n) {
+            unsafeAtomicAdd(&yacc[c], cs);
+            vav += refl_v(col, c, s, n, rf.scale) * cs;
+        }
     }
     vav = block_sum256(vav, red);
-    if (tid == 0) w.PV[(long long)b * w.sPV + slot] = vav;
+    if (tid == 0) unsafeAtomicAdd(vacc_of(w, b, i) + (C * 7 + q) % SYTRD_VC, vav);
 }
 
 // ---------------------------------------------------------------------------
-// finish work item: 64-row block R.  All independent global loads are issued
-// before the first reduction.
+// finish work item: 64-row block R.  Reads y = A v, the panel products and
+// v^T A v from the column's accumulators, forms w, applies the panel to the
+// next column, and clears the other parity slot for the next column.
 // ---------------------------------------------------------------------------
 template <typename T, int NBP>
-__device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt, int nslots, int R) {
+__device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int R) {
+    static_assert(SYTRD_VC == 256, "one v^T A v copy per thread");
     static_assert(2 * NBP <= 64, "panel products are reduced by one wavefront");
     static_assert(NBP % 4 == 0, "panel columns are split over 4 wavefronts");
     __shared__ T sps[2 * NBP];
-    __shared__ T rr[5][4][64];
-    __shared__ T red[4];
+    __shared__ T rr[3][4][64];
     const int s = i + 1;
     const int b0 = s >> 6;
-    const int nbk = (n + 63) >> 6;
     const int tid = threadIdx.x, lane = tid & 63, part = tid >> 6;
-    const T* PV = w.PV + (long long)b * w.sPV;
-    const T* PS = w.PS + (long long)b * w.sPS;
-    const T* P1 = w.P1 + (long long)b * w.sP1;
-    const T* P2 = w.P2 + (long long)b * w.sP2;
     const T* Vp = w.Vp + (long long)b * w.sP;
     T* Wp = w.Wp + (long long)b * w.sP;
     const int ldp = w.ldp;
@@ -277,35 +312,23 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     const long long ld = w.A.ld;
     const int r = R * 64 + lane;
     const bool rv = (r >= s && r < n);
-    const int ls = s - b0 * 64;
+    __shared__ T red[4];
 
     // ---- independent loads
     const T tau = w.tau[(long long)b * w.sD + i];
-    T acc = T(0);
-    for (int sl = tid; sl < nslots; sl += 256) acc += PV[sl];
-    T psum = T(0);
-    if (lane < 2 * NBP && (lane % NBP) < j) {
-#pragma unroll 8
-        for (int Cb = b0 + part; Cb < nbk; Cb += 4) psum += PS[(long long)Cb * (2 * NBP) + lane];
+    const T vpart = vacc_of(w, b, i)[tid];  // SYTRD_VC == blockDim
+    T sp = T(0);
+    if (tid < 2 * NBP && (tid % NBP) < j) {
+#pragma unroll
+        for (int c = 0; c < SYTRD_YC; c++) sp += sacc_of(w, b, i, c)[tid];
     }
-    const int nchR = (nbk - R + Kt - 1) / Kt;
-    const int nitems = (R - b0 + 1) + nchR;
-    T y = T(0);
-#pragma unroll 8
-    for (int it = part; it < nitems; it += 4) {
-        if (it <= R - b0) y += P1[((long long)(b0 + it) * w.nbk_max + R) * 64 + lane];
-        else y += P2[((long long)R * w.maxchunk + (it - (R - b0 + 1))) * 64 + lane];
+    T yr = T(0), ysv = T(0);
+#pragma unroll
+    for (int c = 0; c < SYTRD_YC; c++) {
+        const T* yc = yacc_of(w, b, i, c);
+        if (rv) yr += yc[r];
+        ysv += yc[s];
     }
-    // y at row s (needed by every block for the update of column s): the
-    // diagonal-tile row sum plus the column sums of every chunk of strip b0
-    T ys = T(0);
-    if (part == 0) {
-        const int nch0 = (nbk - b0 + Kt - 1) / Kt;
-        for (int qq = lane; qq < nch0; qq += 64) ys += P2[((long long)b0 * w.maxchunk + qq) * 64 + ls];
-        if (lane == 0) ys += P1[((long long)b0 * w.nbk_max + b0) * 64 + ls];
-        ys = wave_sum(ys);
-    }
-    // panel rows: this wavefront owns columns k = part, part + 4, ... < j
     T vr_k[NBP / 4], wr_k[NBP / 4], vs_k[NBP / 4], ws_k[NBP / 4];
 #pragma unroll
     for (int t = 0; t < NBP / 4; t++) {
@@ -318,17 +341,18 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     }
     const T vr = rv ? Vp[r + (long long)j * ldp] : T(0);
     const T acol = rv ? A[r + (long long)s * ld] : T(0);
+    if (tid < 2 * NBP) sps[tid] = sp;
+    const T vAv = block_sum256(vpart, red);
 
-    // ---- reductions
-    const T vAv = block_sum256(acc, red);
-    rr[0][part][lane] = psum;
-    rr[1][part][lane] = y;
-    if (tid == 0) red[0] = ys;
-    __syncthreads();
-    if (tid < 2 * NBP) sps[tid] = (rr[0][0][tid] + rr[0][1][tid]) + (rr[0][2][tid] + rr[0][3][tid]);
-    const T yr = (rr[1][0][lane] + rr[1][1][lane]) + (rr[1][2][lane] + rr[1][3][lane]);
-    const T ysv = red[0];
-    __syncthreads();
+    // clear the other parity slot for column i + 1 (its SYMV runs after this
+    // kernel): rows of block R, and the scalars once per matrix
+    for (int c = part; c < SYTRD_YC; c += 4)
+        if (R * 64 + lane < n) yacc_of(w, b, i + 1, c)[R * 64 + lane] = T(0);
+    if (R == b0) {
+        for (int t = tid; t < SYTRD_YC * 2 * NBP; t += 256) sacc_of(w, b, i + 1, 0)[t] = T(0);
+        vacc_of(w, b, i + 1)[tid] = T(0);
+    }
+
     T pts = T(0);
     for (int k = 0; k < j; k++) pts += sps[k] * sps[NBP + k];
     const T wtv = tau * (vAv - T(2) * pts);
@@ -342,11 +366,11 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
             csp += vs_k[t] * sps[k] + ws_k[t] * sps[NBP + k];
         }
     }
-    rr[2][part][lane] = cr;
-    rr[3][part][lane] = csp;
+    rr[0][part][lane] = cr;
+    rr[1][part][lane] = csp;
     __syncthreads();
-    cr = (rr[2][0][lane] + rr[2][1][lane]) + (rr[2][2][lane] + rr[2][3][lane]);
-    csp = (rr[3][0][0] + rr[3][1][0]) + (rr[3][2][0] + rr[3][3][0]);
+    cr = (rr[0][0][lane] + rr[0][1][lane]) + (rr[0][2][lane] + rr[0][3][lane]);
+    csp = (rr[1][0][0] + rr[1][1][0]) + (rr[1][2][0] + rr[1][3][0]);
     const T wr = rv ? tau * (yr - cr) - T(0.5) * tau * wtv * vr : T(0);
     if (part == 0 && r < n) Wp[r + (long long)j * ldp] = wr;
     const T ws = tau * (ysv - csp) - T(0.5) * tau * wtv;
@@ -360,10 +384,10 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
         }
         if (part == 0) u += vr * ws + wr;
     }
-    rr[4][part][lane] = u;
+    rr[2][part][lane] = u;
     __syncthreads();
     if (part == 0) {
-        u = (rr[4][0][lane] + rr[4][1][lane]) + (rr[4][2][lane] + rr[4][3][lane]);
+        u = (rr[2][0][lane] + rr[2][1][lane]) + (rr[2][2][lane] + rr[2][3][lane]);
         T cval = T(0);
         if (rv) {
             cval = acol - u;
@@ -385,21 +409,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SymvWaves<T
 void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
-    const int slot = blockIdx.y * gridDim.x + blockIdx.x;
-    if (i > n - 2) { if (threadIdx.x == 0) w.PV[(long long)b * w.sPV + slot] = T(0); return; }
+    if (i > n - 2) return;
     const int b0 = (i + 1) >> 6;
     const int nbk = (n + 63) >> 6;
     const int C = b0 + blockIdx.y;
     const int q = blockIdx.x;
-    if (C >= nbk || q >= (nbk - C + Kt - 1) / Kt) {
-        if (threadIdx.x == 0) w.PV[(long long)b * w.sPV + slot] = T(0);
-        return;
-    }
-    symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, slot, nullptr);
+    if (C >= nbk || q >= (nbk - C + Kt - 1) / Kt) return;
+    symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, nullptr);
 }
 
 template <typename T, int NBP>
-__global__ __launch_bounds__(256) void sytrd_finish_kernel(SytrdWs<T> w, int i, int j, int Kt, int nslots) {
+__global__ __launch_bounds__(256) void sytrd_finish_kernel(SytrdWs<T> w, int i, int j) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
     if (i > n - 2) return;
@@ -407,7 +427,7 @@ __global__ __launch_bounds__(256) void sytrd_finish_kernel(SytrdWs<T> w, int i, 
     const int nbk = (n + 63) >> 6;
     const int R = b0 + blockIdx.x;
     if (R >= nbk) return;
-    finish_item<T, NBP>(w, b, n, i, j, Kt, nslots, R);
+    finish_item<T, NBP>(w, b, n, i, j, R);
 }
 
 // all columns [k0, k1) of one panel in one cooperative launch
@@ -432,12 +452,9 @@ __global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, 
             const int n = w.ns[b];
             const int C = b0 + strip;
             const int nbk = (n + 63) >> 6;
-            if (i > n - 2 || C >= nbk || q >= (nbk - C + Kt - 1) / Kt) {
-                if (threadIdx.x == 0) w.PV[(long long)b * w.sPV + slot] = T(0);
-                continue;
-            }
+            if (i > n - 2 || C >= nbk || q >= (nbk - C + Kt - 1) / Kt) continue;
             if (b != cur_b) { rf = refl_scalars(w, b, i, n); cur_b = b; }
-            symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, slot, &rf);
+            symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, &rf);
         }
         grid.sync();
         // finish phase
@@ -446,7 +463,7 @@ __global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, 
             const int R = b0 + (it - b * nbt);
             const int n = w.ns[b];
             if (i > n - 2 || R >= ((n + 63) >> 6)) continue;
-            finish_item<T, NBP>(w, b, n, i, j, Kt, per_mat, R);
+            finish_item<T, NBP>(w, b, n, i, j, R);
         }
         grid.sync();
     }
@@ -568,8 +585,7 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                     hipLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j,
                                        Kt);
                 }
-                hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j,
-                                   Kt, gx * nbt);
+                hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j);
             }
         }
         const int t0 = k0 + NBP;

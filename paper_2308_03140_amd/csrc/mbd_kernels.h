@@ -47,7 +47,9 @@ struct LaunchProfiler {
     ~LaunchProfiler() { for (auto e : pool) hipEventDestroy(e); }
 };
 
-#define SYTRD_NBP 32     // Householder panel width
+#define SYTRD_NBP 32
+#define SYTRD_YCOPIES 8    // atomic accumulator copies (y, panel products)
+#define SYTRD_VCOPIES 256  // atomic accumulator copies (v^T A v)     // Householder panel width
 #define ORMTR_NBB 64     // reflectors per compact-WY block in the back-transform
 #define ORMTR_CHUNK 512  // rows per split-K chunk of V^T X
 
@@ -56,14 +58,13 @@ template <typename T>
 struct SytrdWs {
     MatBatch<T> A;     // matrices, lower triangle used, overwritten by reflectors
     const int* ns;     // per-matrix order (device)
-    int nmax, nbk_max, maxchunk;
+    int nmax, nbk_max;
     T* Vp; T* Wp; int ldp; long long sP;   // panels, column-major nmax x SYTRD_NBP
     T* colbuf; long long sC;               // updated current column
     T* normpart; long long sNP;            // per 64-row block squared norms
-    T* P1; long long sP1;                  // row-sum partial per tile [nbk][nbk][64]
-    T* P2; long long sP2;                  // column-sum partial per chunk [nbk][maxchunk][64]
-    T* PS; long long sPS;                  // panel products per block [nbk][2*NBP]
-    T* PV; long long sPV;                  // v^T A v partial per workgroup
+    T* yacc; long long sY;                 // y = A v, [2 parities][SYTRD_YCOPIES][nmax] per matrix
+    T* sacc; long long sS;                 // W^T v, V^T v, [2][SYTRD_YCOPIES][2*NBP]
+    T* vacc;                               // v^T A v, [2][SYTRD_VCOPIES] per matrix
     T* d; T* e; T* tau; long long sD;      // outputs
     int chunk_target;                      // SYMV work items per launch (tuned)
 };
@@ -100,8 +101,8 @@ struct OrmtrWs {
     const T* tau; long long sD;
     const int* ns;
     MatBatch<T> X;     // in: tridiagonal eigenvectors; out: eigenvectors of A
-    T* Gpart; long long sG;   // [nsplit][64*64]
-    T* Tm; long long sT;      // [64*64]
+    T* Gpart; long long sG;   // [nblk][nsplit][64*64]
+    T* Tm; long long sT;      // [nblk][64*64]
     T* Ypart; long long sYp;  // [nsplit][64*nmax]
     T* Y; long long sY;       // [64*nmax]
     int nmax;

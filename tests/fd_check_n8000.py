@@ -1,0 +1,97 @@
+"""Large-system gradient check: the N=8000 cluster (Q of order 24000, 4.6 GB
+in FP64).  dE/dR and dE/dalpha0 come from the adjoint kernels through the
+torch.autograd.Function; each sampled component is compared with a central
+difference of FP64 GPU energies (h = 1e-4 bohr for positions, 1e-5 relative
+for alpha0).  The oracle is not run at this size; the gradient formula itself
+is pinned against the oracle at smaller sizes.
+
+    python tests/fd_check_n8000.py [--coords 20] [--alpha 4] [--out FILE]
+
+Prints one line per component as it goes and a JSON summary at the end.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import gen  # noqa: E402
+
+
+def run(n_coords=20, n_alpha=4, h=1e-4, h_rel_alpha=1e-5, seed=55, natoms=None, out=None, log=print):
+    import torch
+
+    from paper_2308_03140_amd import torch_api as T
+    from paper_2308_03140_amd.autograd import mbd_energy
+
+    dev = torch.device("cuda", 0)
+    c = gen.cluster_n8000() if natoms is None else gen.cluster_dense(5, natoms, name="cluster_n8000")
+    N = len(c["omega"])
+    ctx = T.Context(0, "fp64")
+    R = torch.tensor(c["coords"], device=dev, requires_grad=True)
+    a0 = torch.tensor(c["alpha0"], device=dev, requires_grad=True)
+    om = torch.tensor(c["omega"], device=dev)
+    rv = torch.tensor(c["rvdw"], device=dev)
+    t0 = time.perf_counter()
+    E = mbd_energy(R, a0, om, rv, ctx, beta=c["beta"], a=c["a"])
+    E.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    gR = R.grad.cpu().numpy()
+    gA = a0.grad.cpu().numpy()
+    log("N=%d energy %.12f Ha, energy+gradients %.2f s" % (N, E.item(), t_grad))
+
+    def energy(coords, alpha0):
+        o = T.evaluate(ctx, coords, alpha0, om, rv, beta=c["beta"], a=c["a"], gradients=False, errors=False)
+        return o["energy"].item()
+
+    rng = np.random.default_rng(seed)
+    atoms = rng.choice(N, n_coords, replace=False)
+    comps = rng.integers(0, 3, n_coords)
+    Rd = R.detach().clone()
+    Ad = a0.detach().clone()
+    rows = []
+    t0 = time.perf_counter()
+    for k, (i, x) in enumerate(zip(atoms, comps)):
+        Rp = Rd.clone(); Rp[i, x] += h
+        Rm = Rd.clone(); Rm[i, x] -= h
+        fd = (energy(Rp, Ad) - energy(Rm, Ad)) / (2 * h)
+        err = abs(fd - gR[i, x])
+        rows.append({"kind": "R", "atom": int(i), "comp": int(x), "analytic": float(gR[i, x]), "fd": fd, "err": err})
+        log("  [%2d] dE/dR[%d,%d] analytic %+.10e fd %+.10e |diff| %.2e" % (k, i, x, gR[i, x], fd, err))
+    t_fd = (time.perf_counter() - t0) / max(1, 2 * n_coords)
+    alist = rng.choice(N, n_alpha, replace=False) if n_alpha else []
+    for k, i in enumerate(alist):
+        ha = h_rel_alpha * float(Ad[i])
+        Ap = Ad.clone(); Ap[i] += ha
+        Am = Ad.clone(); Am[i] -= ha
+        fd = (energy(Rd, Ap) - energy(Rd, Am)) / (2 * ha)
+        err = abs(fd - gA[i])
+        rows.append({"kind": "alpha0", "atom": int(i), "analytic": float(gA[i]), "fd": fd, "err": err})
+        log("  [%2d] dE/dalpha0[%d] analytic %+.10e fd %+.10e |diff| %.2e" % (k, i, gA[i], fd, err))
+    ctx.close()
+    res = {"workload": "finite cluster N=%d (Q %dx%d), seed 5, alpha0 x %.4f" % (N, 3 * N, 3 * N, c["alpha_scale"]),
+           "energy": E.item(), "h_bohr": h, "h_rel_alpha0": h_rel_alpha,
+           "max_err_grad_R": max([r["err"] for r in rows if r["kind"] == "R"] or [0.0]),
+           "max_err_grad_alpha0": max([r["err"] for r in rows if r["kind"] == "alpha0"] or [0.0]),
+           "s_energy_gradients": t_grad, "s_energy_only": t_fd, "components": rows}
+    if out:
+        with open(out, "w") as f:
+            json.dump(res, f, indent=1)
+    return res
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--coords", type=int, default=20)
+    ap.add_argument("--alpha", type=int, default=4)
+    ap.add_argument("--atoms", type=int, default=None, help="smaller cluster at the same density (testing)")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    r = run(a.coords, a.alpha, natoms=a.atoms, out=a.out, log=lambda s: print(s, flush=True))
+    print(json.dumps({k: v for k, v in r.items() if k != "components"}), flush=True)
