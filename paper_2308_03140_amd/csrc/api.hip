@@ -23,6 +23,7 @@ struct mbd_ctx {
     int err_code = 0;
     std::string err_origin, err_msg;
     LaunchProfiler prof;
+    double refine_tol = 0.0;  // second refinement step threshold (MBD_REFINE_TOL; <= 0: library default)
     // autotuned SYMV work-item targets per matrix order, per precision (0 FP64, 1 FP32)
     std::map<int, int> tune[2];
     // captured batch launch sequences, keyed by batch signature
@@ -142,7 +143,7 @@ mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int
     sw.Vp = wsT<T>(c, "Vp" + t, sw.sP * nbatch);
     sw.Wp = wsT<T>(c, "Wp" + t, sw.sP * nbatch);
     sw.sC = nmax; sw.colbuf = wsT<T>(c, "colbuf" + t, (size_t)nmax * nbatch);
-    sw.sNP = nbk; sw.normpart = wsT<T>(c, "normpart" + t, (size_t)nbk * nbatch);
+    sw.normacc = wsT<T>(c, "normacc" + t, (size_t)2 * nbatch);
     sw.sY = 2LL * SYTRD_YCOPIES * nmax; sw.yacc = wsT<T>(c, "yacc" + t, (size_t)sw.sY * nbatch);
     sw.sS = 2LL * SYTRD_YCOPIES * 2 * SYTRD_NBP; sw.sacc = wsT<T>(c, "sacc" + t, (size_t)sw.sS * nbatch);
     sw.vacc = wsT<T>(c, "vacc" + t, (size_t)2 * SYTRD_VCOPIES * nbatch);
@@ -150,7 +151,7 @@ mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int
     sw.d = wsT<T>(c, "d" + t, (size_t)nmax * nbatch);
     sw.e = wsT<T>(c, "e" + t, (size_t)nmax * nbatch);
     sw.tau = wsT<T>(c, "tau" + t, (size_t)nmax * nbatch);
-    if (!sw.Vp || !sw.Wp || !sw.colbuf || !sw.normpart || !sw.yacc || !sw.sacc || !sw.vacc || !sw.d ||
+    if (!sw.Vp || !sw.Wp || !sw.colbuf || !sw.normacc || !sw.yacc || !sw.sacc || !sw.vacc || !sw.d ||
         !sw.e || !sw.tau)
         return (mbd_status)c->err_code;
     return MBD_OK;
@@ -480,6 +481,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         MatBatch<double> S = {wsT<double>(c, "oaS", (size_t)stride * nmat), ld, stride};
         MatBatch<double> G = {wsT<double>(c, "oaG", (size_t)stride * nmat), ld, stride};
         OaWork ow;
+        ow.rho_next = c->refine_tol;
         ow.colpart = wsT<double>(c, "oacol", oa_colpart_doubles(nmax, nmat));
         ow.nclust = wsT<unsigned>(c, "oanclust", nmat);
         ow.wstart = wsT<int>(c, "oawstart", (size_t)nmax * nmat);
@@ -589,6 +591,8 @@ mbd_status mbd_create(mbd_ctx** ctx, int device, mbd_precision prec, void* hip_s
     c->stream = (hipStream_t)hip_stream;
     const char* lim = std::getenv("MBD_WORKSPACE_LIMIT");
     if (lim) c->limit = (size_t)std::strtoull(lim, nullptr, 10);
+    const char* rt = std::getenv("MBD_REFINE_TOL");
+    if (rt) c->refine_tol = std::strtod(rt, nullptr);
     *ctx = c;
     return MBD_OK;
 }

@@ -46,47 +46,62 @@ struct GemmTile {
     int o, k;  // problem-specific offsets (e.g. merge origin and order)
 };
 
-template <typename T, class P>
+// BM x BN tile per 256-thread workgroup (64x64 or 128x128): the 4 wavefronts
+// in a 2x2 arrangement each own a (BM/2)x(BN/2) block of 16x16 MFMA tiles.
+template <typename T, class P, int BM = GEMM_BM, int BN = GEMM_BN>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(P p) {
-    __shared__ T As[2][GEMM_BK][GEMM_BM + GEMM_PAD];
-    __shared__ T Bs[2][GEMM_BK][GEMM_BN + GEMM_PAD];
+    static_assert(BM % 32 == 0 && BN % 32 == 0, "tile edges are multiples of 32");
+    constexpr int MI = BM / 32, NJ = BN / 32;    // 16x16 blocks per wave in m and n
+    constexpr int LA = GEMM_BK * BM / 256, LB = GEMM_BK * BN / 256;
+    __shared__ T As[2][GEMM_BK][BM + GEMM_PAD];
+    __shared__ T Bs[2][GEMM_BK][BN + GEMM_PAD];
     GemmTile t;
     if (!p.tile(blockIdx.x, blockIdx.y, blockIdx.z, t)) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    typename mfma4<T>::v acc[2][2];
+    typename mfma4<T>::v acc[MI][NJ];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < MI; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = typename mfma4<T>::v{0, 0, 0, 0};
+        for (int j = 0; j < NJ; j++) acc[i][j] = typename mfma4<T>::v{0, 0, 0, 0};
 
-    T ra[4], rb[4];
+    T ra[LA], rb[LB];
+    auto a_index = [&](int ii, int& m, int& k) {
+        if (P::A_M_CONTIG) { m = tid % BM; k = tid / BM + (256 / BM) * ii; }
+        else { k = tid & 15; m = (tid >> 4) + 16 * ii; }
+    };
+    auto b_index = [&](int ii, int& nn, int& k) {
+        if (P::B_N_CONTIG) { nn = tid % BN; k = tid / BN + (256 / BN) * ii; }
+        else { k = tid & 15; nn = (tid >> 4) + 16 * ii; }
+    };
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int ii = 0; ii < 4; ii++) {
+        for (int ii = 0; ii < LA; ii++) {
             int m, k;
-            if (P::A_M_CONTIG) { m = tid & 63; k = (tid >> 6) + 4 * ii; }
-            else { k = tid & 15; m = (tid >> 4) + 16 * ii; }
+            a_index(ii, m, k);
             ra[ii] = p.a(t, t.m0 + m, k0 + k);
-            int n, kb;
-            if (P::B_N_CONTIG) { n = tid & 63; kb = (tid >> 6) + 4 * ii; }
-            else { kb = tid & 15; n = (tid >> 4) + 16 * ii; }
-            rb[ii] = p.b(t, k0 + kb, t.n0 + n);
+        }
+#pragma unroll
+        for (int ii = 0; ii < LB; ii++) {
+            int nn, k;
+            b_index(ii, nn, k);
+            rb[ii] = p.b(t, k0 + k, t.n0 + nn);
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int ii = 0; ii < 4; ii++) {
+        for (int ii = 0; ii < LA; ii++) {
             int m, k;
-            if (P::A_M_CONTIG) { m = tid & 63; k = (tid >> 6) + 4 * ii; }
-            else { k = tid & 15; m = (tid >> 4) + 16 * ii; }
+            a_index(ii, m, k);
             As[buf][k][m] = ra[ii];
-            int n, kb;
-            if (P::B_N_CONTIG) { n = tid & 63; kb = (tid >> 6) + 4 * ii; }
-            else { kb = tid & 15; n = (tid >> 4) + 16 * ii; }
-            Bs[buf][kb][n] = rb[ii];
+        }
+#pragma unroll
+        for (int ii = 0; ii < LB; ii++) {
+            int nn, k;
+            b_index(ii, nn, k);
+            Bs[buf][k][nn] = rb[ii];
         }
     };
 
@@ -100,28 +115,28 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(P p) {
             if (kt + 1 < nk) gload((kt + 1) * GEMM_BK);
 #pragma unroll
             for (int kk = 0; kk < GEMM_BK; kk += 4) {
-                T af[2], bf[2];
+                T af[MI], bf[NJ];
 #pragma unroll
-                for (int i = 0; i < 2; i++) af[i] = As[buf][kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
+                for (int i = 0; i < MI; i++) af[i] = As[buf][kk + (lane >> 4)][wm * (BM / 2) + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < 2; j++) bf[j] = Bs[buf][kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+                for (int j = 0; j < NJ; j++) bf[j] = Bs[buf][kk + (lane >> 4)][wn * (BN / 2) + j * 16 + (lane & 15)];
 #pragma unroll
-                for (int i = 0; i < 2; i++)
+                for (int i = 0; i < MI; i++)
 #pragma unroll
-                    for (int j = 0; j < 2; j++) acc[i][j] = mfma16x16x4(af[i], bf[j], acc[i][j]);
+                    for (int j = 0; j < NJ; j++) acc[i][j] = mfma16x16x4(af[i], bf[j], acc[i][j]);
             }
             if (kt + 1 < nk) sstore(buf ^ 1);
             __syncthreads();
         }
     }
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < MI; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < NJ; j++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                int row = t.m0 + wm * 32 + i * 16 + mfma_rows<T>::row(lane, r);
-                int col = t.n0 + wn * 32 + j * 16 + (lane & 15);
+                int row = t.m0 + wm * (BM / 2) + i * 16 + mfma_rows<T>::row(lane, r);
+                int col = t.n0 + wn * (BN / 2) + j * 16 + (lane & 15);
                 p.store(t, row, col, acc[i][j][r]);
             }
 }
@@ -136,8 +151,9 @@ __device__ __forceinline__ void lower_tile(int lin, int& ti, int& tj) {
 }
 
 // General batched C = alpha op(A) op(B) + beta C over matrices of order ns[b]
-// (M, N, K derived from ns through the m/n/k multipliers and offsets).
-template <typename T, bool TA, bool TB>
+// (M, N, K derived from ns through the m/n/k multipliers and offsets), in
+// TS x TS output tiles.
+template <typename T, bool TA, bool TB, int TS = GEMM_BM>
 struct GemmGeneral {
     static constexpr bool A_M_CONTIG = !TA;
     static constexpr bool B_N_CONTIG = TB;
@@ -157,7 +173,7 @@ struct GemmGeneral {
         int ti, tj;
         if (lower_only) lower_tile(bx, ti, tj);
         else { ti = bx / tiles_n; tj = bx % tiles_n; }
-        t.m0 = ti * GEMM_BM; t.n0 = tj * GEMM_BN; t.K = Kb;
+        t.m0 = ti * TS; t.n0 = tj * TS; t.K = Kb;
         return t.m0 < Mb && t.n0 < Nb;
     }
     __device__ T a(const GemmTile& t, int m, int k) const {

@@ -226,19 +226,37 @@ template void ormtr_launch<float>(const OrmtrWs<float>&, int, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // generic batched GEMM entry used by the refinement and gradient stages
 // ---------------------------------------------------------------------------
-template <typename T, bool TA, bool TB>
-static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
-                            long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
-                            T alpha, T beta, bool lower_only, const int* skip) {
-    GemmGeneral<T, TA, TB> p;
+#ifndef GEMM_TS128_MIN_TILES
+#define GEMM_TS128_MIN_TILES (1LL << 40)  // 128x128 tiles off: occupancy 1 on gfx950 loses to 64x64
+#endif
+template <typename T, bool TA, bool TB, int TS>
+static void gemm_gen_launch_ts(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
+                               long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
+                               T alpha, T beta, bool lower_only, const int* skip) {
+    GemmGeneral<T, TA, TB, TS> p;
     p.A = A; p.lda = lda; p.sA = sA; p.B = B; p.ldb = ldb; p.sB = sB; p.C = C; p.ldc = ldc; p.sC = sC;
     p.ns = ns; p.M = p.N = p.K = nmax; p.alpha = alpha; p.beta = beta;
     p.lower_only = lower_only ? 1 : 0;
     p.skip = skip;
-    const int t = (nmax + 63) / 64;
+    const int t = (nmax + TS - 1) / TS;
     p.tiles_n = t;
     const int grid = lower_only ? t * (t + 1) / 2 : t * t;
-    hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB>>), dim3(grid, 1, nbatch), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB, TS>, TS, TS>), dim3(grid, 1, nbatch), dim3(256),
+                       0, st, p);
+}
+
+// 128x128 tiles once a matrix gives enough of them to fill the device
+template <typename T, bool TA, bool TB>
+static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
+                            long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
+                            T alpha, T beta, bool lower_only, const int* skip) {
+    const long long tiles128 = (long long)((nmax + 127) / 128) * ((nmax + 127) / 128) * nbatch;
+    if (tiles128 >= GEMM_TS128_MIN_TILES)
+        gemm_gen_launch_ts<T, TA, TB, 128>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta,
+                                           lower_only, skip);
+    else
+        gemm_gen_launch_ts<T, TA, TB, 64>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta,
+                                          lower_only, skip);
 }
 
 template <typename T>

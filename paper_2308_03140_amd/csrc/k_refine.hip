@@ -4,7 +4,8 @@
 // of close eigenvalues of their 2019 sequel, "... II: clustered eigenvalues",
 // in Rayleigh-Ritz form).  One step on X (n x n, columns ~ eigenvectors):
 //
-//   S = X^T Q X, G = X^T X, R = I - G, lam_i = S_ii / G_ii
+//   S = X^T Q X, G = X^T X (both symmetric, lower triangles formed),
+//   R = I - G, lam_i = S_ii / G_ii
 //   delta = 2 (||S - diag(lam)||_F + max|lam| ||R||_F)   (Frobenius bounds of
 //           the spectral norms in the method's separation threshold; reported,
 //           not used: with FP32 eigenvectors of large matrices it exceeds the
@@ -22,19 +23,28 @@
 //                     windows with |lam_i - lam_j| above rounding level
 //             E'_ij = R'_ij / 2   other pairs of different windows (unresolved)
 //             E'_ii = R_ii / 2    single-column windows, 0 inside windows
-//   X <- X' + X' E' = X + X F,  F = (W - I) + W E'
+//   X <- (X' + X' E') D = X + X F,  F = ((W - I) + W E') D + (D - I),
+//           D = diag(1/sqrt(1 + eta_j)), eta_j = sum_{i != j} E'_ij^2
+//   lam_j <- Rayleigh quotient of the refined column j, expanded from S', G'
+//           and E' (no further product with Q)
 //
 // The leftover of a step is second order in the cross-window correction:
 // column j grows in norm by eta_j = sum_{i != j} E'_ij^2, and
 // rho = max_j eta_j max_r|X_rj|^2 / sqrt(lam_j) estimates the largest element
-// error it leaves in Q^{-1/2} = X diag(lam^{-1/2}) X^T.  A matrix takes a second step
-// when rho > OA_RHO_NEXT; the decision stays on the device (per-matrix skip
-// flags), so captured launch graphs remain valid.
+// error it leaves in Q^{-1/2} = X diag(lam^{-1/2}) X^T before the column
+// rescaling below.  A matrix takes a second step when rho > OA_RHO_NEXT; the
+// decision stays on the device (per-matrix skip flags), so captured launch
+// graphs remain valid.
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
 
-#define OA_RHO_NEXT 1e-8
+// Default second-step threshold (OaWork::rho_next overrides when > 0).  rho
+// estimates the remainder before the column rescaling, which removes most of
+// it (measured factor 3-6 on FP32 eigenvectors of n = 100..6000); at 3e-5 the
+// element error left in Q^{-1/2} stays near 6e-6 or below, which keeps the
+// gradients within 1e-6 and the energy within 1e-12 Ha/atom of FP64.
+#define OA_RHO_NEXT 3e-5
 #define OA_TAU 1e-4
 #define OA_LINK 4
 #define OA_CP 6  // per-column partials: s2 (then eta), r2, max|R|, |lam|, max|x|, spare
@@ -66,8 +76,9 @@ __device__ __forceinline__ double sym_lower(const double* G, int ld, int r, int 
     return r >= c ? G[r + (long long)c * ld] : G[c + (long long)r * ld];
 }
 
-// lam_c = S_cc / G_cc and per-column partials of ||S - diag(lam)||_F^2,
-// ||R||_F^2, max|R|, |lam| and max|X| (G holds its lower triangle)
+// lam_c = S_cc / G_cc and per-column partials of ||S - diag(lam)||_F^2 and
+// ||R||_F^2 (the strictly lower part counted twice, plus the diagonal), max|R|,
+// |lam| and max|X|.  S and G hold their lower triangles, read contiguously.
 __global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
                                                             MatBatch<double> X, double* lam, long long sL,
                                                             double* colpart, const int* skip) {
@@ -77,30 +88,32 @@ __global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatc
     const int n = ns[b];
     const int c = blockIdx.x;
     if (c >= n) return;
-    const double* Sb = S.at(b);
-    const double* Gb = G.at(b);
-    const double* Xb = X.at(b);
+    const double* Sc = S.at(b) + (long long)c * S.ld;
+    const double* Gc = G.at(b) + (long long)c * G.ld;
+    const double* Xc = X.at(b) + (long long)c * X.ld;
     double s2 = 0.0, r2 = 0.0, rmax = 0.0, xmax = 0.0;
     for (int r = threadIdx.x; r < n; r += 256) {
-        const double sv = Sb[r + (long long)c * S.ld];
-        if (r != c) s2 += sv * sv;
-        const double rv = (r == c ? 1.0 : 0.0) - sym_lower(Gb, G.ld, r, c);
-        r2 += rv * rv;
-        rmax = fmax(rmax, fabs(rv));
-        xmax = fmax(xmax, fabs(Xb[r + (long long)c * X.ld]));
+        if (r > c) {
+            const double sv = Sc[r], rv = Gc[r];
+            s2 += 2.0 * sv * sv;
+            r2 += 2.0 * rv * rv;
+            rmax = fmax(rmax, fabs(rv));
+        }
+        xmax = fmax(xmax, fabs(Xc[r]));
     }
     s2 = block_sum256(s2, red);
     r2 = block_sum256(r2, red);
     rmax = block_max256(rmax, red);
     xmax = block_max256(xmax, red);
     if (threadIdx.x == 0) {
-        const double scc = Sb[c + (long long)c * S.ld];
-        const double l = scc / Gb[c + (long long)c * G.ld];
+        const double scc = Sc[c], gcc = Gc[c];
+        const double l = scc / gcc;
+        const double rcc = 1.0 - gcc;
         lam[(long long)b * sL + c] = l;
         double* cp = colpart + ((long long)b * sL + c) * OA_CP;
         cp[0] = s2 + (scc - l) * (scc - l);
-        cp[1] = r2;
-        cp[2] = rmax;
+        cp[1] = r2 + rcc * rcc;
+        cp[2] = fmax(rmax, fabs(rcc));
         cp[3] = fabs(l);
         cp[4] = xmax;
     }
@@ -122,7 +135,13 @@ __global__ __launch_bounds__(256) void oa_delta_kernel(const int* ns, double* co
         rmax = fmax(rmax, cp[2]);
         lmax = fmax(lmax, cp[3]);
         xmax = fmax(xmax, cp[4]);
-        cp[0] = 0.0;  // reused as sum_i E'_ic^2 over cross-window i
+        // reused by the E' kernel: [0] eta, [1] and [2] the numerator terms,
+        // [5] the denominator term of the refined Rayleigh quotient ([3] is
+        // cleared by the windows kernel after it has read |lam|)
+        cp[0] = 0.0;
+        cp[1] = 0.0;
+        cp[2] = 0.0;
+        cp[5] = 0.0;
     }
     s2 = block_sum256(s2, red);
     r2 = block_sum256(r2, red);
@@ -150,7 +169,7 @@ __device__ __forceinline__ bool oa_break(const double* Sb, int lds, const double
     for (int d = 1; d <= OA_LINK && i - d >= 0; d++) {
         const int j = i - d;
         const double dl = fabs(li - L[j]);
-        const double sji = 0.5 * (Sb[j + (long long)i * lds] + Sb[i + (long long)j * lds]);
+        const double sji = Sb[i + (long long)j * lds];  // i > j: lower triangle
         const double rji = -Gb[i + (long long)j * ldg];
         if (dl <= tiny || fabs(sji + li * rji) > OA_TAU * dl) return false;
     }
@@ -158,7 +177,7 @@ __device__ __forceinline__ bool oa_break(const double* Sb, int lds, const double
 }
 
 __global__ __launch_bounds__(256) void oa_windows_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
-                                                           const double* lam, long long sL, const double* colpart,
+                                                           const double* lam, long long sL, double* colpart,
                                                            int* wstart, int* wlen, const int* skip) {
     __shared__ int last[256], first[256];
     __shared__ double red[4];
@@ -170,7 +189,11 @@ __global__ __launch_bounds__(256) void oa_windows_kernel(const int* ns, MatBatch
     const double* Gb = G.at(b);
     const int t = threadIdx.x;
     double lmax = 0.0;
-    for (int c = t; c < n; c += 256) lmax = fmax(lmax, colpart[((long long)b * sL + c) * OA_CP + 3]);
+    for (int c = t; c < n; c += 256) {
+        double* cp3 = colpart + ((long long)b * sL + c) * OA_CP + 3;
+        lmax = fmax(lmax, *cp3);
+        *cp3 = 0.0;
+    }
     const double tiny = 64.0 * num_limits<double>::eps * block_max256(lmax, red);
     const int seg = (n + 255) / 256;
     const int i0 = min(n, t * seg), i1 = min(n, i0 + seg);
@@ -228,7 +251,7 @@ __global__ __launch_bounds__(64) void oa_rr_kernel(const int* ns, MatBatch<doubl
     const double* Gb = G.at(b);
     for (int e = tid; e < k * k; e += 64) {
         const int r = e % k, c = e / k;
-        Am[r][c] = 0.5 * (Sb[(cs + r) + (long long)(cs + c) * S.ld] + Sb[(cs + c) + (long long)(cs + r) * S.ld]);
+        Am[r][c] = sym_lower(Sb, S.ld, cs + r, cs + c);
         Lm[r][c] = sym_lower(Gb, G.ld, cs + r, cs + c);
         Um[r][c] = r == c ? 1.0 : 0.0;
     }
@@ -361,7 +384,11 @@ __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<doubl
     if (blockIdx.x * 256 >= n) return;  // uniform: the block holds no row
     const int i = blockIdx.x * 256 + threadIdx.x;
     const long long o = (long long)b * sL;
-    double e2 = 0.0;
+    // per column j: eta = sum_i E'_ij^2 (cross-window) and the terms of the
+    // Rayleigh quotient of the refined column, x_j' = sum_i x'_i (I + E')_ij:
+    //   num = S'_jj + sum_i (2 E'_ij S'_ij + E'_ij^2 S'_ii),
+    //   den = G'_jj + sum_i (2 E'_ij G'_ij + E'_ij^2 G'_ii)
+    double e2 = 0.0, a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
     if (i < n) {
         const int wi = wstart[o + i], ki = wlen[o + i];
         const int wj = wstart[o + j], kj = wlen[o + j];
@@ -369,7 +396,16 @@ __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<doubl
         const double* Gb = G.at(b);
         double e;
         if (wi == wj) {
-            e = (ki == 1) ? 0.5 * (1.0 - Gb[i + (long long)i * G.ld]) : 0.0;
+            if (ki == 1) {  // i == j, single-column window
+                const double gjj = Gb[j + (long long)j * G.ld], sjj = Sb[j + (long long)j * S.ld];
+                e = 0.5 * (1.0 - gjj);
+                a1 = 2.0 * e * sjj;
+                a2 = e * e * sjj;
+                b1 = 2.0 * e * gjj;
+                b2 = e * e * gjj;
+            } else {
+                e = 0.0;
+            }
         } else {
             const double* vi = wv + (o + i) * OA_KMAX;
             const double* vj = wv + (o + j) * OA_KMAX;
@@ -379,7 +415,7 @@ __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<doubl
                 double ts = 0.0, tg = 0.0;
                 for (int p = 0; p < ki; p++) {
                     const double ci = ki == 1 ? 1.0 : vi[p];
-                    ts += ci * Sb[(wi + p) + (long long)(wj + q) * S.ld];
+                    ts += ci * sym_lower(Sb, S.ld, wi + p, wj + q);
                     tg += ci * sym_lower(Gb, G.ld, wi + p, wj + q);
                 }
                 sp += ts * cj;
@@ -394,17 +430,37 @@ __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<doubl
                 if (i < j) atomicAdd(&nclust[b], 1u);
             }
             e2 = e * e;
+            const double gii = ki == 1 ? Gb[i + (long long)i * G.ld] : 1.0;
+            a1 = 2.0 * e * sp;
+            a2 = e2 * li * gii;
+            b1 = 2.0 * e * gp;
+            b2 = e2 * gii;
         }
         Eo.at(b)[i + (long long)j * Eo.ld] = e;
     }
     e2 = block_sum256(e2, red);
-    if (threadIdx.x == 0) atomicAdd(&colpart[(o + j) * OA_CP], e2);
+    a1 = block_sum256(a1, red);
+    a2 = block_sum256(a2, red);
+    b1 = block_sum256(b1, red);
+    b2 = block_sum256(b2, red);
+    if (threadIdx.x == 0) {
+        double* cp = colpart + (o + j) * OA_CP;
+        atomicAdd(&cp[0], e2);
+        atomicAdd(&cp[1], a1);
+        atomicAdd(&cp[2], a2);
+        atomicAdd(&cp[3], b1);
+        atomicAdd(&cp[5], b2);
+    }
 }
 
-// F = (W - I) + W E' into Fo, W block diagonal over the windows
+// F = ((W - I) + W E') D + (D - I) into Fo, W block diagonal over the windows,
+// D = diag(1/sqrt(1 + eta_j)): the cross-window corrections are orthogonal to
+// column j, so they lengthen it by eta_j = sum_i E'_ij^2 (accumulated by the
+// E' kernel); rescaling removes that second-order term without a further
+// product, so X + X F has columns of unit length to that order.
 __global__ __launch_bounds__(256) void oa_f_kernel(const int* ns, MatBatch<double> Ei, MatBatch<double> Fo,
                                                      long long sL, const int* wstart, const int* wlen,
-                                                     const double* wv, const int* skip) {
+                                                     const double* wv, const double* colpart, const int* skip) {
     const int b = blockIdx.z;
     if (skip && skip[b]) return;
     const int n = ns[b];
@@ -422,13 +478,18 @@ __global__ __launch_bounds__(256) void oa_f_kernel(const int* ns, MatBatch<doubl
         f = (wstart[o + j] == wi) ? wv[(o + j) * OA_KMAX + p] - (i == j ? 1.0 : 0.0) : 0.0;
         for (int a = 0; a < ki; a++) f += wv[(o + wi + a) * OA_KMAX + p] * Eb[(wi + a) + (long long)j * Ei.ld];
     }
+    const double d = 1.0 / sqrt(1.0 + colpart[(o + j) * OA_CP]);
+    f = f * d + (i == j ? d - 1.0 : 0.0);
     Fo.at(b)[i + (long long)j * Fo.ld] = f;
 }
 
 // rho = max_c eta_c max|x_c|^2 / sqrt(lam_c) -> stats[4b+2]; next[b] = 1
-// (skip the next step) unless rho > OA_RHO_NEXT
-__global__ __launch_bounds__(256) void oa_next_kernel(const int* ns, const double* colpart, const double* lam,
-                                                        long long sL, double* stats, const int* skip, int* next) {
+// (skip the next step) unless rho > the threshold; lam <- Rayleigh quotients
+// of the refined columns
+__global__ __launch_bounds__(256) void oa_next_kernel(const int* ns, const double* colpart, double* lam,
+                                                        long long sL, MatBatch<double> G, const int* wlen,
+                                                        double* stats, const int* skip, int* next,
+                                                        double rho_next) {
     __shared__ double red[4];
     const int b = blockIdx.x;
     if (skip && skip[b]) {
@@ -437,16 +498,20 @@ __global__ __launch_bounds__(256) void oa_next_kernel(const int* ns, const doubl
     }
     const int n = ns[b];
     const long long o = (long long)b * sL;
+    const double* Gb = G.at(b);
     double rho = 0.0;
     for (int c = threadIdx.x; c < n; c += 256) {
         const double* cp = colpart + (o + c) * OA_CP;
         const double l = lam[o + c];
         if (l > 0.0) rho = fmax(rho, cp[0] * cp[4] * cp[4] / sqrt(l));
+        // Rayleigh quotient of the refined column (the rescaling by D leaves it unchanged)
+        const double g = wlen[o + c] == 1 ? Gb[c + (long long)c * G.ld] : 1.0;
+        lam[o + c] = (l * g + cp[1] + cp[2]) / (g + cp[3] + cp[5]);
     }
     rho = block_max256(rho, red);
     if (threadIdx.x == 0) {
         stats[4 * b + 2] = rho;
-        next[b] = rho > OA_RHO_NEXT ? 0 : 1;
+        next[b] = rho > rho_next ? 0 : 1;
     }
 }
 
@@ -472,7 +537,7 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
     gemm_batched<double>(st, false, false, ns, nmax, nbatch, Q.p, Q.ld, Q.stride, X.p, X.ld, X.stride, T1.p,
                          T1.ld, T1.stride, 1.0, 0.0, false, skip);                             // T1 = Q X
     gemm_batched<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T1.p, T1.ld, T1.stride, T2.p,
-                         T2.ld, T2.stride, 1.0, 0.0, false, skip);                             // S = X^T Q X
+                         T2.ld, T2.stride, 1.0, 0.0, true, skip);                              // S = X^T Q X (lower)
     gemm_batched<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, X.p, X.ld, X.stride, G.p, G.ld,
                          G.stride, 1.0, 0.0, true, skip);                                      // G = X^T X
     hipLaunchKernelGGL(oa_colstats_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, T2, G, X, lam, sL,
@@ -484,8 +549,10 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
                        w.wlen, w.wv, skip);
     hipLaunchKernelGGL(oa_e_kernel, ge, dim3(256), 0, st, ns, T2, G, T1, lam, sL, w.wstart, w.wlen, w.wv, stats,
                        w.nclust, w.colpart, skip);                                             // E' -> T1
-    hipLaunchKernelGGL(oa_f_kernel, ge, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, skip);  // F -> T2
-    hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, stats, skip, next);
+    hipLaunchKernelGGL(oa_f_kernel, ge, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, w.colpart,
+                       skip);                                                                  // F -> T2
+    hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats, skip,
+                       next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
     hipLaunchKernelGGL(copy_mat_kernel, ge, dim3(256), 0, st, ns, X, T1);                       // T1 = X
     gemm_batched<double>(st, false, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T2.p, T2.ld, T2.stride, T1.p,
                          T1.ld, T1.stride, 1.0, 1.0, false, skip);                             // T1 = X + X F

@@ -56,18 +56,13 @@ __device__ __forceinline__ T refl_v(const T* col, int r, int s, int n, T scale) 
 }
 
 // Reflector scalars from the updated column held in colbuf (LAPACK dlarfg
-// convention: beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta).  Called
-// by the whole workgroup: the block norms are summed in one parallel pass.
+// convention: beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta).  The
+// squared norm of x = col(i+2:n) was accumulated (atomically, by the phase
+// that produced the column) into parity slot (i & 1) of normacc.
 template <typename T>
 __device__ __forceinline__ Refl<T> refl_scalars(const SytrdWs<T>& w, int b, int i, int n) {
-    __shared__ T red[4];
-    const T* col = w.colbuf + (long long)b * w.sC;
-    const T* np_ = w.normpart + (long long)b * w.sNP;
-    const int nbk = (n + 63) >> 6;
-    T part = T(0);
-    for (int R = (i >> 6) + (int)threadIdx.x; R < nbk; R += 256) part += np_[R];
-    const T xn2 = block_sum256(part, red);
-    const T alpha = col[i + 1];
+    const T xn2 = w.normacc[(long long)b * 2 + (i & 1)];
+    const T alpha = w.colbuf[(long long)b * w.sC + i + 1];
     Refl<T> r;
     if (xn2 == T(0)) {
         r.tau = T(0); r.beta = alpha; r.scale = T(0);
@@ -137,7 +132,14 @@ __global__ __launch_bounds__(256) void sytrd_init_kernel(SytrdWs<T> w) {
     if (r < n) col[r] = x;
     T q = (r >= 2 && r < n) ? x * x : T(0);
     q = wave_sum(q);
-    if (threadIdx.x == 0) w.normpart[(long long)b * w.sNP + R] = q;
+    if (threadIdx.x == 0) unsafeAtomicAdd(&w.normacc[(long long)b * 2 + 0], q);
+}
+
+// both norm slots to zero before the first column
+template <typename T>
+__global__ void sytrd_zero_norm_kernel(SytrdWs<T> w, int nbatch) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < 2 * nbatch) w.normacc[t] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +398,7 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
         }
         T q2 = (r >= s + 2 && r < n) ? cval * cval : T(0);
         q2 = wave_sum(q2);
-        if (lane == 0) w.normpart[(long long)b * w.sNP + R] = q2;
+        if (lane == 0) unsafeAtomicAdd(&w.normacc[(long long)b * 2 + (s & 1)], q2);
     }
     __syncthreads();
 }
@@ -414,6 +416,8 @@ void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
     const int nbk = (n + 63) >> 6;
     const int C = b0 + blockIdx.y;
     const int q = blockIdx.x;
+    // the norm slot of column i + 1 is filled by this column's finish phase
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) w.normacc[(long long)b * 2 + ((i + 1) & 1)] = T(0);
     if (C >= nbk || q >= (nbk - C + Kt - 1) / Kt) return;
     symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, nullptr);
 }
@@ -442,7 +446,9 @@ __global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, 
         const int Kt = sytrd_kt(nbt, nbatch, target);
         const int gx = (nbt + Kt - 1) / Kt;
         const int per_mat = gx * nbt;
-        // SYMV phase
+        // SYMV phase (and clear the norm slot that this column's finish fills)
+        for (int b = blockIdx.x * 256 + threadIdx.x; b < nbatch; b += P * 256)
+            w.normacc[(long long)b * 2 + ((i + 1) & 1)] = T(0);
         int cur_b = -1;
         Refl<T> rf = {T(0), T(0), T(0)};
         for (int it = blockIdx.x; it < per_mat * nbatch; it += P) {
@@ -532,6 +538,7 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
     constexpr int NBP = SYTRD_NBP;
     const bool timing = prof && prof->enabled && ns_host;
     const int nbk_max = w.nbk_max;
+    hipLaunchKernelGGL(sytrd_zero_norm_kernel<T>, dim3((2 * nbatch + 255) / 256), dim3(256), 0, st, w, nbatch);
     hipLaunchKernelGGL(sytrd_init_kernel<T>, dim3(nbk_max, 1, nbatch), dim3(256), 0, st, w);
     // MBD_SYTRD_MODE=persistent selects the cooperative panel kernel; the
     // default issues two launches per column (measured faster on gfx950,

@@ -49,6 +49,7 @@ struct OaWork {
     int* wstart;      // [nbatch][nmax] first column of each column's window
     int* wlen;        // [nbatch][nmax] window length
     double* wv;       // [nbatch][nmax][OA_KMAX] window rotation, per column
+    double rho_next;  // second-step threshold on the remainder estimate (<= 0: default)
 };
 size_t oa_colpart_doubles(int nmax, int nbatch);
 void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd);
