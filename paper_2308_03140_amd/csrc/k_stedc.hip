@@ -306,16 +306,34 @@ __global__ __launch_bounds__(256) void stedc_secular_kernel(StedcWs<T> w, int le
         org = K - 1; lo = 0.0; hi = rho * wave_sum(z2);
     }
     const double dorg = dn[org];
-    for (int it = 0; it < 1100; it++) {
-        const double mm = 0.5 * (lo + hi);
-        if (mm == lo || mm == hi) break;
-        double f = 0.0;
-        for (int i = lane; i < K; i += 64) f += zn[i] * zn[i] / ((dn[i] - dorg) - mm);
+    // safeguarded Newton in mu: f is increasing between the poles, so the sign
+    // of f(x) keeps the bracket [lo, hi]; a Newton step leaving it is replaced
+    // by bisection.  Stops when |f| is at its rounding level or the bracket
+    // is relatively tight (the Loewner step only needs d_i - lambda =
+    // (d_i - d_org) - mu to relative accuracy).
+    double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 120; it++) {
+        double f = 0.0, fp = 0.0, fa = 0.0;
+        for (int i = lane; i < K; i += 64) {
+            const double t = 1.0 / ((dn[i] - dorg) - x);
+            const double z2 = zn[i] * zn[i];
+            f += z2 * t;
+            fp += z2 * t * t;
+            fa += fabs(z2 * t);
+        }
         f = 1.0 + rho * wave_sum(f);
-        if (f < 0.0) lo = mm; else hi = mm;
+        fp = rho * wave_sum(fp);
+        fa = 1.0 + rho * wave_sum(fa);
+        if (f < 0.0) lo = x; else hi = x;
+        if (fabs(f) <= 4.0 * num_limits<double>::eps * fa) break;
+        if (hi - lo <= 4.0 * num_limits<double>::eps * fmax(fabs(lo), fabs(hi))) break;
+        double xn = x - f / fp;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (xn == x) break;
+        x = xn;
     }
     if (lane == 0) {
-        const double mu = 0.5 * (lo + hi);
+        const double mu = x;
         w.org[base + jx] = org;
         w.mu[base + jx] = mu;
         w.lam[base + jx] = dorg + mu;
