@@ -4,8 +4,11 @@ Rule (applied before any timing): with mu_min the smallest eigenvalue of
 alpha0^{1/2} T^lr alpha0^{1/2}, if 1 + mu_min <= 0.05 all alpha0 are scaled by
 s = 0.9/|mu_min| (so 1 + s mu_min = 0.1); else s = 1.  mu_min is bracketed by
 the oracle's Cholesky test (S - t I is positive definite iff t < mu_min), so
-only the oracle is called.  The N=8000 cluster is bracketed the same way
-(about 11 Cholesky factorisations of order 24000 on the CPU).
+only the oracle is called.  For the N=8000 cluster (order 24000, where one
+oracle factorisation takes a quarter of an hour) mu_min is first located by a
+Lanczos iteration with full reorthogonalisation on the oracle's coupling
+matrix (matrix-vector products only), then confirmed by one oracle Cholesky
+test just below it.
 
     python gen/make_alpha_scale.py [names...]
 """
@@ -36,6 +39,40 @@ def mu_min_bisect(S, lo=-4.0, hi=0.0, tol=2e-3):
     return 0.5 * (lo + hi)
 
 
+def mu_min_lanczos(S, iters=400, seed=0):
+    """Smallest eigenvalue of symmetric S by Lanczos with full
+    reorthogonalisation; returns the smallest Ritz value."""
+    n = S.shape[0]
+    rng = np.random.default_rng(seed)
+    V = np.zeros((iters + 1, n))
+    v = rng.standard_normal(n)
+    V[0] = v / np.linalg.norm(v)
+    alpha, beta = [], []
+    for k in range(iters):
+        w = S @ V[k]
+        a = float(V[k] @ w)
+        w -= a * V[k] + (beta[-1] * V[k - 1] if k > 0 else 0.0)
+        w -= V[:k + 1].T @ (V[:k + 1] @ w)  # full reorthogonalisation
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        if b < 1e-12:
+            break
+        beta.append(b)
+        V[k + 1] = w / b
+    m = len(alpha)
+    Tm = np.diag(alpha) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+    return float(np.linalg.eigvalsh(Tm)[0])
+
+
+def scale_lanczos(c):
+    S = oracle.coupling_matrix(c["coords"], c["alpha0"], c["rvdw"], c["beta"], c["a"])
+    mu = mu_min_lanczos(S)
+    # a Ritz value lies above mu_min; confirm with one oracle Cholesky that
+    # mu_min > mu - 2e-3 (S - (mu - 2e-3) I positive definite)
+    assert oracle.is_positive_definite(S - (mu - 2e-3) * np.eye(S.shape[0])), "Lanczos missed mu_min"
+    return (0.9 / abs(mu) if 1.0 + mu <= 0.05 else 1.0), mu
+
+
 def scale_for(c):
     S = oracle.coupling_matrix(c["coords"], c["alpha0"], c["rvdw"], c["beta"], c["a"])
     # quick test: no rescale needed if S + 0.95 I is positive definite
@@ -54,7 +91,7 @@ def main(names):
             s, mu = scale_for(gen.finite_cluster(2, 2000, gen.cube_side_for_density(2000)))
             table[name] = s
         elif name == "cluster_n8000":
-            s, mu = scale_for(gen.finite_cluster(5, 8000, gen.cube_side_for_density(8000)))
+            s, mu = scale_lanczos(gen.finite_cluster(5, 8000, gen.cube_side_for_density(8000)))
             table[name] = s
         elif name == "crystal_n64":
             c = gen.crystal_n64()
