@@ -153,7 +153,8 @@ mbd_status mbd_evaluate_batch(mbd_ctx *ctx, int32_t n_sys, const mbd_system *sys
  * the Householder reduction, divide-and-conquer tridiagonal solve and
  * back-transform used for Q.  A: [nbatch] matrices of order n, column-major
  * with leading dimension lda, consecutive matrices `stride` elements apart,
- * lower triangle read and DESTROYED.  w: [nbatch][n] eigenvalues ascending.
+ * lower triangle read (copied into a library workspace first; A itself is
+ * not modified).  w: [nbatch][n] eigenvalues ascending.
  * Z (may be NULL): [nbatch] n x n eigenvector matrices, leading dimension ldz,
  * stride `zstride`.  dtype: 0 = FP64, 1 = FP32 (then A, w, Z are float). */
 mbd_status mbd_eigh(mbd_ctx *ctx, int32_t dtype, int32_t n, int32_t nbatch, void *A, int32_t lda,

@@ -142,7 +142,8 @@ mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int
     sw.sP = (long long)sw.ldp * SYTRD_NBP;
     sw.Vp = wsT<T>(c, "Vp" + t, sw.sP * nbatch);
     sw.Wp = wsT<T>(c, "Wp" + t, sw.sP * nbatch);
-    sw.sC = nmax; sw.colbuf = wsT<T>(c, "colbuf" + t, (size_t)nmax * nbatch);
+    // padded to whole 64-row blocks: the SYMV phase reads it in 16-byte segments
+    sw.sC = round_up(nmax, 64); sw.colbuf = wsT<T>(c, "colbuf" + t, (size_t)sw.sC * nbatch);
     sw.normacc = wsT<T>(c, "normacc" + t, (size_t)2 * nbatch);
     sw.sY = 2LL * SYTRD_YCOPIES * nmax; sw.yacc = wsT<T>(c, "yacc" + t, (size_t)sw.sY * nbatch);
     sw.sS = 2LL * SYTRD_YCOPIES * 2 * SYTRD_NBP; sw.sacc = wsT<T>(c, "sacc" + t, (size_t)sw.sS * nbatch);
@@ -753,8 +754,20 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
     if (!ns_dev) return (mbd_status)c->err_code;
     HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nbatch, hipMemcpyHostToDevice, c->stream), "upload");
     mbd_status r;
+    // the reduction reads the matrices in 16-byte segments of 64-row-aligned
+    // columns: stage them into a workspace with a leading dimension that is a
+    // multiple of 64 (the caller's A is left unchanged)
+    const int lds = round_up(n, 64);
+    const long long sts = (long long)lds * n;
+    const size_t es = dtype == 0 ? sizeof(double) : sizeof(float);
+    void* As = dtype == 0 ? (void*)wsT<double>(c, "eighA", (size_t)sts * nbatch) : (void*)wsT<float>(c, "eighA32", (size_t)sts * nbatch);
+    if (!As) return (mbd_status)c->err_code;
+    for (int b = 0; b < nbatch; b++)
+        HIPCHK(hipMemcpy2DAsync((char*)As + (size_t)b * sts * es, es * lds, (const char*)A + (size_t)b * stride * es,
+                                es * lda, es * n, n, hipMemcpyDeviceToDevice, c->stream),
+               "stage");
     if (dtype == 0) {
-        MatBatch<double> Ab = {(double*)A, lda, (long long)stride}, X;
+        MatBatch<double> Ab = {(double*)As, lds, sts}, X;
         r = run_eig<double>(c, Ab, ns_dev, nsh.data(), n, nbatch, Z != nullptr, (double*)w, n, &X);
         if (r == MBD_OK && Z)
             HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, X.p, sizeof(double) * X.ld, sizeof(double) * n,
@@ -765,7 +778,7 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
                                         sizeof(double) * X.ld, sizeof(double) * n, n, hipMemcpyDeviceToDevice, c->stream),
                        "copy");
     } else {
-        MatBatch<float> Ab = {(float*)A, lda, (long long)stride}, X;
+        MatBatch<float> Ab = {(float*)As, lds, sts}, X;
         r = run_eig<float>(c, Ab, ns_dev, nsh.data(), n, nbatch, Z != nullptr, (float*)w, n, &X);
         if (r == MBD_OK && Z)
             for (int b = 0; b < nbatch; b++)

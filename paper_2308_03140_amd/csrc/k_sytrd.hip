@@ -144,18 +144,31 @@ __global__ void sytrd_zero_norm_kernel(SytrdWs<T> w, int nbatch) {
 
 // ---------------------------------------------------------------------------
 // SYMV work item: tiles R in [C + q Kt, C + (q+1) Kt) of column strip C.
-// Row sums, column sums, the panel products and v^T A v are added into the
-// column's accumulators with hardware float atomics, so the finish phase
-// reads one value per row.
+// Wavefront wv streams the 16 columns c0 = 64 C + 16 wv ... c0 + 15.  Each
+// lane loads 16 bytes of one column segment (RPL consecutive rows: 4 floats
+// or 2 doubles), so one load instruction covers RPL columns x 64 rows and a
+// tile takes 16 / RPL loads per lane.  The column buffer entries of the
+// tile's rows come with the same batch of loads, and the next tile is
+// requested before the current one is reduced, unconditionally (a tile past
+// the chunk reads zeros through the out-of-range offset): the in-order load
+// counter then never waits for more than the tile in use.  Row sums, column
+// sums, the panel products and v^T A v are added into the column's
+// accumulators with hardware float atomics, so the finish phase reads one
+// value per row.
 // ---------------------------------------------------------------------------
 template <typename T, int NBP>
 __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt, int C, int q,
                           const Refl<T>* rf_in) {
-    __shared__ T tb[64][65];
-    __shared__ T rrow[4][64];
+    constexpr int RPL = 16 / (int)sizeof(T);  // rows per lane per load
+    constexpr int LPC = 64 / RPL;             // lanes per column segment
+    constexpr int NI = 16 / RPL;              // loads per lane per tile
+    typedef typename Vec16<T>::v VT;
     __shared__ T rpart[SYTRD_KTMAX][4][64];  // per-tile, per-wave row partials
+    __shared__ T vrow[SYTRD_KTMAX][64];      // reflector entries of the tile rows
     __shared__ T red[4];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane / LPC, rq = lane % LPC;
     const int s = i + 1;
     const int b0 = s >> 6;
     const int nbk = (n + 63) >> 6;
@@ -170,24 +183,33 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
     const int Re = min(Rb + Kt, nbk);
     const int c0 = C * 64 + wv * 16;
 
-    T a[16], an[16];
-    // The wave's 16 columns are one buffer resource; masked elements (outside
-    // the trailing matrix or above the diagonal) read as zero through an
-    // out-of-range offset.
-    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(A + (long long)c0 * ld, (unsigned)(16 * ld * (long long)sizeof(T)));
-    auto load_tile = [&](int R, T* dst) {
-        const int r = R * 64 + lane;
-        const bool rok = (r < n) && (r >= s);
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            const int c = c0 + k;
-            const bool ok = rok && (c < n) && (c >= s) && (R > C || r >= c);
-            dst[k] = buf_load<T>(rsrc, ok ? (unsigned)((k * (int)ld + r) * (int)sizeof(T)) : OOB_OFFSET);
-        }
-    };
-    // the first tile is in flight while the reflector and vectors are formed
-    load_tile(Rb, a);
+    // the column buffer is padded to 64 nbk rows; the wave's strip holds
+    // ncols columns of the matrix
+    const __amdgpu_buffer_rsrc_t csrc = make_rsrc(col, (unsigned)(nbk * 64 * (int)sizeof(T)));
+    const int ncols = max(0, min(16, n - c0));
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(A + (long long)c0 * ld, (unsigned)(ncols * ld * (long long)sizeof(T)));
+    // reflector scalars and this lane's column entries are requested first,
+    // so waiting for them never waits for a tile
     const Refl<T> rf = rf_in ? *rf_in : refl_scalars(w, b, i, n);
+    unsigned coff[NI];
+    bool cok[NI];
+    T craw[NI];
+#pragma unroll
+    for (int k = 0; k < NI; k++) {
+        const int c = c0 + RPL * k + g;
+        cok[k] = c >= s && c < n;
+        coff[k] = (unsigned)((RPL * k + g) * ld * (long long)sizeof(T));
+        craw[k] = buf_load<T>(csrc, cok[k] ? (unsigned)(c * (int)sizeof(T)) : OOB_OFFSET);
+    }
+    VT buf[NI + 1];  // tile column segments and the column buffer rows
+    auto issue = [&](int R) {
+        // past the chunk every offset lands at or beyond OOB_OFFSET
+        const unsigned roff = R < Re ? (unsigned)((R * 64 + RPL * rq) * (int)sizeof(T)) : OOB_OFFSET;
+#pragma unroll
+        for (int k = 0; k < NI; k++) buf[k] = buf_load16<T>(rsrc, cok[k] ? coff[k] + roff : OOB_OFFSET);
+        buf[NI] = buf_load16<T>(csrc, roff);
+    };
+    issue(Rb);
 
     if (q == 0) {
         // v for the rows of block C: panel column j and matrix column i
@@ -232,31 +254,59 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
         }
     }
 
-    T vc[16];
+    T vc[NI], cacc[NI];
 #pragma unroll
-    for (int k = 0; k < 16; k++) vc[k] = refl_v(col, c0 + k, s, n, rf.scale);
-    T cacc[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) cacc[k] = T(0);
-    T vav = T(0);
-    // each wavefront streams its 16 columns through the chunk without block
-    // barriers; its row partials go to its own LDS slot and are summed over
-    // the 4 wavefronts after the loop
+    for (int k = 0; k < NI; k++) {
+        const int c = c0 + RPL * k + g;
+        vc[k] = cok[k] ? (c == s ? T(1) : craw[k] * rf.scale) : T(0);
+        cacc[k] = T(0);
+    }
     for (int R = Rb; R < Re; R++) {
-        if (R + 1 < Re) load_tile(R + 1, an);
-        const int r = R * 64 + lane;
-        const T vr = refl_v(col, r, s, n, rf.scale);
-        T rs = T(0);
+        const int r0 = R * 64 + RPL * rq;
+        T vr[RPL], rs[RPL];
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
-            rs += a[k] * vc[k];
-            const bool offd = (R > C) || (r != c0 + k);
-            cacc[k] += offd ? a[k] * vr : T(0);
+        for (int e = 0; e < RPL; e++) {
+            const int r = r0 + e;
+            vr[e] = (r < s || r >= n) ? T(0) : (r == s ? T(1) : buf[NI][e] * rf.scale);
+            rs[e] = T(0);
         }
-        rpart[R - Rb][wv][lane] = rs;
-        if (R + 1 < Re) {
 #pragma unroll
-            for (int k = 0; k < 16; k++) a[k] = an[k];
+        for (int k = 0; k < NI; k++) {
+            const int c = c0 + RPL * k + g;
+#pragma unroll
+            for (int e = 0; e < RPL; e++) {
+                const int r = r0 + e;
+                // rows past n (padding) and, on the diagonal tile, above the
+                // diagonal are not part of the lower trailing matrix
+                const T x = (r < n && (R > C || r >= c)) ? buf[k][e] : T(0);
+                rs[e] += x * vc[k];
+                cacc[k] += (R > C || r != c) ? x * vr[e] : T(0);
+            }
+        }
+        issue(R + 1);
+        // row sums over the RPL column groups of the wave
+#pragma unroll
+        for (int e = 0; e < RPL; e++)
+#pragma unroll
+            for (int o = LPC; o < 64; o <<= 1) rs[e] += __shfl_xor(rs[e], o, 64);
+        if (g == 0) {
+#pragma unroll
+            for (int e = 0; e < RPL; e++) {
+                rpart[R - Rb][wv][RPL * rq + e] = rs[e];
+                if (wv == 0) vrow[R - Rb][RPL * rq + e] = vr[e];
+            }
+        }
+    }
+    // column sums over the LPC row groups of each column
+    T vav = T(0);
+#pragma unroll
+    for (int k = 0; k < NI; k++) {
+        T x = cacc[k];
+#pragma unroll
+        for (int o = 1; o < LPC; o <<= 1) x += __shfl_xor(x, o, 64);
+        if (rq == 0 && cok[k]) {
+            unsafeAtomicAdd(&yacc[c0 + RPL * k + g], x);
+            vav += vc[k] * x;
         }
     }
     __syncthreads();
@@ -265,27 +315,7 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
         const int r = (Rb + t) * 64 + lane;
         if (r >= s && r < n) {
             unsafeAtomicAdd(&yacc[r], y);
-            vav += refl_v(col, r, s, n, rf.scale) * y;
-        }
-    }
-    // column sums of the strip: transpose through LDS
-#pragma unroll
-    for (int k = 0; k < 16; k++) tb[wv * 16 + k][lane] = cacc[k];
-    __syncthreads();
-    {
-        const int cc = tid & 63, part = tid >> 6;
-        T ps = T(0);
-#pragma unroll
-        for (int l = 0; l < 16; l++) ps += tb[cc][part * 16 + l];
-        rrow[part][cc] = ps;
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const T cs = (rrow[0][tid] + rrow[1][tid]) + (rrow[2][tid] + rrow[3][tid]);
-        const int c = C * 64 + tid;
-        if (c >= s && c < n) {
-            unsafeAtomicAdd(&yacc[c], cs);
-            vav += refl_v(col, c, s, n, rf.scale) * cs;
+            vav += vrow[t][lane] * y;
         }
     }
     vav = block_sum256(vav, red);

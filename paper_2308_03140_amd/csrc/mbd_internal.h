@@ -75,8 +75,16 @@ __device__ __forceinline__ T block_max256(T v, T* red) {
 // by giving them the offset OOB_OFFSET.
 // ---------------------------------------------------------------------------
 #define OOB_OFFSET 0x80000000u
+// The descriptor must be wave-uniform: base and size are passed through
+// readfirstlane so the compiler keeps it in scalar registers (a descriptor it
+// cannot prove uniform is wrapped in a per-load waterfall loop).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+    const unsigned long long a = (unsigned long long)base;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    const unsigned nb = __builtin_amdgcn_readfirstlane(bytes);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((unsigned long long)hi << 32) | lo), (short)0, (int)nb,
+                                             0x00020000);
 }
 template <typename T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
 template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
@@ -84,6 +92,12 @@ template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsr
 }
 template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+// 16 bytes per lane: 4 floats or 2 doubles (offset a multiple of 16)
+template <typename T> struct Vec16 { typedef T v __attribute__((ext_vector_type(16 / sizeof(T)))); };
+template <typename T>
+__device__ __forceinline__ typename Vec16<T>::v buf_load16(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(typename Vec16<T>::v, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
 template <typename T> struct num_limits;

@@ -60,7 +60,7 @@ struct SytrdWs {
     const int* ns;     // per-matrix order (device)
     int nmax, nbk_max;
     T* Vp; T* Wp; int ldp; long long sP;   // panels, column-major nmax x SYTRD_NBP
-    T* colbuf; long long sC;               // updated current column
+    T* colbuf; long long sC;               // updated current column (rows padded to 64 nbk_max)
     T* normacc;                            // ||col(i+2:n)||^2, [2 parities] per matrix
     T* yacc; long long sY;                 // y = A v, [2 parities][SYTRD_YCOPIES][nmax] per matrix
     T* sacc; long long sS;                 // W^T v, V^T v, [2][SYTRD_YCOPIES][2*NBP]
