@@ -227,31 +227,24 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
             w.tau[(long long)b * w.sD + i] = rf.tau;
         }
         // panel products over the rows of block C: wave wv takes columns
-        // k = wv, wv + 4, ...; all loads are issued before the reductions
+        // k = wv + 4 t, t < 8, of W and of V; the 16 sums of a wave come out
+        // of one multi-value butterfly, lane 4 u holding sum u
+        static_assert(NBP == 32, "eight panel columns per wave");
         T* sacc = sacc_of(w, b, i, C % SYTRD_YC);
         const int r = C * 64 + lane;
         const bool rv = (r >= s && r < n);
         const T vr = rv ? refl_v(col, r, s, n, rf.scale) : T(0);
-        T pw[NBP / 4], pv[NBP / 4];
+        T pr[16];
 #pragma unroll
-        for (int t = 0; t < NBP / 4; t++) {
+        for (int t = 0; t < 8; t++) {
             const int k = wv + 4 * t;
             const bool ok = rv && k < j;
-            pw[t] = ok ? Wp[r + (long long)k * ldp] : T(0);
-            pv[t] = ok ? Vp[r + (long long)k * ldp] : T(0);
+            pr[t] = ok ? Wp[r + (long long)k * ldp] * vr : T(0);
+            pr[8 + t] = ok ? Vp[r + (long long)k * ldp] * vr : T(0);
         }
-#pragma unroll
-        for (int t = 0; t < NBP / 4; t++) {
-            const int k = wv + 4 * t;
-            if (k < j) {
-                const T sw = wave_sum(pw[t] * vr);
-                const T sv = wave_sum(pv[t] * vr);
-                if (lane == 0) {
-                    unsafeAtomicAdd(&sacc[k], sw);
-                    unsafeAtomicAdd(&sacc[NBP + k], sv);
-                }
-            }
-        }
+        const T ps = wave_sum16(pr);
+        const int u = lane >> 2, k = wv + 4 * (u & 7);
+        if ((lane & 3) == 0 && k < j) unsafeAtomicAdd(&sacc[(u >> 3) * NBP + k], ps);
     }
 
     T vc[NI], cacc[NI];
@@ -284,30 +277,36 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
             }
         }
         issue(R + 1);
-        // row sums over the RPL column groups of the wave
+        // row sums over the RPL column groups of the wave (lane bits 5, 4
+        // for floats, bit 5 for doubles): lane (rq, g) ends with row RPL rq + g
+        T rsum;
+        if constexpr (RPL == 4) {
+            rsum = pair_sum_b4(pair_sum_b5(rs[0], rs[2]), pair_sum_b5(rs[1], rs[3]));
+        } else {
+            rsum = pair_sum_b5(rs[0], rs[1]);
+        }
+        rpart[R - Rb][wv][RPL * rq + g] = rsum;
+        if (wv == 0 && g == 0) {
 #pragma unroll
-        for (int e = 0; e < RPL; e++)
-#pragma unroll
-            for (int o = LPC; o < 64; o <<= 1) rs[e] += __shfl_xor(rs[e], o, 64);
-        if (g == 0) {
-#pragma unroll
-            for (int e = 0; e < RPL; e++) {
-                rpart[R - Rb][wv][RPL * rq + e] = rs[e];
-                if (wv == 0) vrow[R - Rb][RPL * rq + e] = vr[e];
-            }
+            for (int e = 0; e < RPL; e++) vrow[R - Rb][RPL * rq + e] = vr[e];
         }
     }
-    // column sums over the LPC row groups of each column
+    // column sums over the LPC row groups (lane bits below 6 - log2 RPL): lane
+    // l ends with the sum of column index k = (l >> 2) mod NI of group g
     T vav = T(0);
 #pragma unroll
-    for (int k = 0; k < NI; k++) {
-        T x = cacc[k];
-#pragma unroll
-        for (int o = 1; o < LPC; o <<= 1) x += __shfl_xor(x, o, 64);
-        if (rq == 0 && cok[k]) {
-            unsafeAtomicAdd(&yacc[c0 + RPL * k + g], x);
-            vav += vc[k] * x;
-        }
+    for (int k = 0; k < NI; k++) vav += vc[k] * cacc[k];
+    T csum;
+    if constexpr (NI == 4) {
+        csum = quad_sum(pair_sum_b2(pair_sum_b3(cacc[0], cacc[2]), pair_sum_b3(cacc[1], cacc[3])));
+    } else {
+        const T u0 = pair_sum_b4(cacc[0], cacc[4]), u1 = pair_sum_b4(cacc[1], cacc[5]);
+        const T u2 = pair_sum_b4(cacc[2], cacc[6]), u3 = pair_sum_b4(cacc[3], cacc[7]);
+        csum = quad_sum(pair_sum_b2(pair_sum_b3(u0, u2), pair_sum_b3(u1, u3)));
+    }
+    {
+        const int c = c0 + RPL * ((lane >> 2) % NI) + g;
+        if ((lane & 3) == 0 && c >= s && c < n) unsafeAtomicAdd(&yacc[c], csum);
     }
     __syncthreads();
     for (int t = wv; t < Re - Rb; t += 4) {

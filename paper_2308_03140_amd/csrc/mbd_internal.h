@@ -26,14 +26,120 @@ static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 static inline long long ceil_div_ll(long long a, long long b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------------------
-// Wavefront / block reductions (deterministic: fixed butterfly then lane-0
-// broadcast, so every lane sees bit-identical values)
+// Cross-lane primitives on the VALU (no LDS round trip).  DPP row
+// permutations act within 16-lane rows: quad xor 1, quad xor 2, the mirror of
+// each 8-lane half (lane l <-> 7 - l) and of each row (l <-> 15 - l).  The
+// permlane swaps exchange rows between two registers: swap32(a, b) leaves
+// a = [a lanes 0-31, b lanes 0-31], b = [a lanes 32-63, b lanes 32-63];
+// swap16(a, b) leaves a = [a row 0, b row 0, a row 2, b row 2] and
+// b = [a row 1, b row 1, a row 3, b row 3].
+// ---------------------------------------------------------------------------
+#define DPP_QUAD_XOR1 0xB1
+#define DPP_QUAD_XOR2 0x4E
+#define DPP_HALF_MIRROR 0x141
+#define DPP_ROW_MIRROR 0x140
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned x) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __builtin_bit_cast(float, dpp_u32<CTRL>(__builtin_bit_cast(unsigned, x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = dpp_u32<CTRL>((unsigned)u), hi = dpp_u32<CTRL>((unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// (the swap results are copied to scalars before the bit cast: a bit cast
+// applied directly to an element of the returned vector reads element 0)
+__device__ __forceinline__ void swap32(float& a, float& b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b), false,
+                                              false);
+    const unsigned r0 = r[0], r1 = r[1];
+    a = __builtin_bit_cast(float, r0);
+    b = __builtin_bit_cast(float, r1);
+}
+__device__ __forceinline__ void swap16(float& a, float& b) {
+    auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b), false,
+                                              false);
+    const unsigned r0 = r[0], r1 = r[1];
+    a = __builtin_bit_cast(float, r0);
+    b = __builtin_bit_cast(float, r1);
+}
+__device__ __forceinline__ void swap32(double& a, double& b) {
+    const unsigned long long ua = __builtin_bit_cast(unsigned long long, a), ub = __builtin_bit_cast(unsigned long long, b);
+    auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    const unsigned long long na = ((unsigned long long)(unsigned)hi[0] << 32) | (unsigned)lo[0];
+    const unsigned long long nb = ((unsigned long long)(unsigned)hi[1] << 32) | (unsigned)lo[1];
+    a = __builtin_bit_cast(double, na);
+    b = __builtin_bit_cast(double, nb);
+}
+__device__ __forceinline__ void swap16(double& a, double& b) {
+    const unsigned long long ua = __builtin_bit_cast(unsigned long long, a), ub = __builtin_bit_cast(unsigned long long, b);
+    auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    const unsigned long long na = ((unsigned long long)(unsigned)hi[0] << 32) | (unsigned)lo[0];
+    const unsigned long long nb = ((unsigned long long)(unsigned)hi[1] << 32) | (unsigned)lo[1];
+    a = __builtin_bit_cast(double, na);
+    b = __builtin_bit_cast(double, nb);
+}
+
+// Pairwise reduction steps of a multi-value butterfly.  Each takes two values
+// x, y per lane and returns, in lanes where the named lane bit is 0, x summed
+// over the lane pair that differs in that bit (with the bits below it for the
+// mirror forms), and y in lanes where it is 1.
+template <typename T>
+__device__ __forceinline__ T pair_sum_b5(T x, T y) { swap32(x, y); return x + y; }
+template <typename T>
+__device__ __forceinline__ T pair_sum_b4(T x, T y) { swap16(x, y); return x + y; }
+template <typename T>
+__device__ __forceinline__ T pair_sum_b3(T x, T y) {
+    const bool hi = (threadIdx.x & 8) != 0;
+    return (hi ? y : x) + dpp<DPP_ROW_MIRROR>(hi ? x : y);
+}
+template <typename T>
+__device__ __forceinline__ T pair_sum_b2(T x, T y) {
+    const bool hi = (threadIdx.x & 4) != 0;
+    return (hi ? y : x) + dpp<DPP_HALF_MIRROR>(hi ? x : y);
+}
+// full sum over lane bits 1 and 0
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v) {
+    v += dpp<DPP_QUAD_XOR2>(v);
+    return v + dpp<DPP_QUAD_XOR1>(v);
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront / block reductions (deterministic: a fixed butterfly whose two
+// operands every lane of a pair adds in the same order, so every lane sees
+// bit-identical values)
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
+    v = quad_sum(v);
+    v += dpp<DPP_HALF_MIRROR>(v);
+    v += dpp<DPP_ROW_MIRROR>(v);
+    T a = v, b = v;
+    swap16(a, b);
+    v = a + b;
+    a = v; b = v;
+    swap32(a, b);
+    return a + b;
+}
+
+// Sixteen sums at once: returns in lane l the sum over the wave of v[l >> 2].
+template <typename T>
+__device__ __forceinline__ T wave_sum16(const T (&v)[16]) {
+    T u[8], w[4];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return __shfl(v, 0, 64);
+    for (int i = 0; i < 8; i++) u[i] = pair_sum_b5(v[i], v[i + 8]);
+#pragma unroll
+    for (int i = 0; i < 4; i++) w[i] = pair_sum_b4(u[i], u[i + 4]);
+    const T z0 = pair_sum_b3(w[0], w[2]), z1 = pair_sum_b3(w[1], w[3]);
+    return quad_sum(pair_sum_b2(z0, z1));
 }
 
 template <typename T>
