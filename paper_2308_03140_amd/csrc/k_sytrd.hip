@@ -209,38 +209,42 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
         for (int k = 0; k < NI; k++) buf[k] = buf_load16<T>(rsrc, cok[k] ? coff[k] + roff : OOB_OFFSET);
         buf[NI] = buf_load16<T>(csrc, roff);
     };
-    issue(Rb);
-
+    // the first work item of a strip also handles the rows of block C: it
+    // stores v there (panel column j and matrix column i) and forms the panel
+    // products W^T v and V^T v over those rows; its loads are unconditional
+    // (rows clamped, results masked) and requested before the tile's
+    const int rq0 = C * 64 + lane;
+    const int rq0c = rq0 < n ? rq0 : n - 1;
+    static_assert(NBP == 32, "eight panel columns per wave");
+    T cq = T(0), di = T(0), pwl[8], pvl[8];
     if (q == 0) {
-        // v for the rows of block C: panel column j and matrix column i
-        if (tid < 64) {
-            const int r = C * 64 + tid;
-            if (r < n) {
-                const T vr = refl_v(col, r, s, n, rf.scale);
-                Vp[r + (long long)j * ldp] = vr;
-                if (r >= s) A[r + (long long)i * ld] = vr;
-            }
-        }
-        if (C == b0 && tid == 0) {
-            w.d[(long long)b * w.sD + i] = col[i];
-            w.e[(long long)b * w.sD + i] = rf.beta;
-            w.tau[(long long)b * w.sD + i] = rf.tau;
-        }
-        // panel products over the rows of block C: wave wv takes columns
-        // k = wv + 4 t, t < 8, of W and of V; the 16 sums of a wave come out
-        // of one multi-value butterfly, lane 4 u holding sum u
-        static_assert(NBP == 32, "eight panel columns per wave");
-        T* sacc = sacc_of(w, b, i, C % SYTRD_YC);
-        const int r = C * 64 + lane;
-        const bool rv = (r >= s && r < n);
-        const T vr = rv ? refl_v(col, r, s, n, rf.scale) : T(0);
-        T pr[16];
+        cq = col[rq0c];
+        if (C == b0) di = col[i];
 #pragma unroll
         for (int t = 0; t < 8; t++) {
             const int k = wv + 4 * t;
-            const bool ok = rv && k < j;
-            pr[t] = ok ? Wp[r + (long long)k * ldp] * vr : T(0);
-            pr[8 + t] = ok ? Vp[r + (long long)k * ldp] * vr : T(0);
+            pwl[t] = Wp[rq0c + (long long)k * ldp];
+            pvl[t] = Vp[rq0c + (long long)k * ldp];
+        }
+    }
+    issue(Rb);
+
+    if (q == 0) {
+        const bool rv = rq0 >= s && rq0 < n;
+        const T vq = rv ? (rq0 == s ? T(1) : cq * rf.scale) : T(0);
+        if (wv == 0 && rq0 < n) {
+            Vp[rq0 + (long long)j * ldp] = vq;
+            if (rq0 >= s) A[rq0 + (long long)i * ld] = vq;
+        }
+        // the 16 sums of a wave (columns k = wv + 4 t of W and of V) come out
+        // of one multi-value butterfly, lane 4 u holding sum u
+        T* sacc = sacc_of(w, b, i, C % SYTRD_YC);
+        T pr[16];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const bool ok = rv && wv + 4 * t < j;
+            pr[t] = ok ? pwl[t] * vq : T(0);
+            pr[8 + t] = ok ? pvl[t] * vq : T(0);
         }
         const T ps = wave_sum16(pr);
         const int u = lane >> 2, k = wv + 4 * (u & 7);
@@ -318,7 +322,14 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
         }
     }
     vav = block_sum256(vav, red);
-    if (tid == 0) unsafeAtomicAdd(vacc_of(w, b, i) + (C * 7 + q) % SYTRD_VC, vav);
+    if (tid == 0) {
+        unsafeAtomicAdd(vacc_of(w, b, i) + (C * 7 + q) % SYTRD_VC, vav);
+        if (q == 0 && C == b0) {
+            w.d[(long long)b * w.sD + i] = di;
+            w.e[(long long)b * w.sD + i] = rf.beta;
+            w.tau[(long long)b * w.sD + i] = rf.tau;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -345,33 +356,50 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     const bool rv = (r >= s && r < n);
     __shared__ T red[4];
 
-    // ---- independent loads
+    // ---- independent loads, all unconditional (rows clamped into the
+    // matrix, panel columns k >= j masked afterwards) so that they form one
+    // round trip instead of a chain of branch-guarded load/wait pairs
+    const int rc = r < n ? r : n - 1;
     const T tau = w.tau[(long long)b * w.sD + i];
     const T vpart = vacc_of(w, b, i)[tid];  // SYTRD_VC == blockDim
-    T sp = T(0);
-    if (tid < 2 * NBP && (tid % NBP) < j) {
-#pragma unroll
-        for (int c = 0; c < SYTRD_YC; c++) sp += sacc_of(w, b, i, c)[tid];
-    }
-    T yr = T(0), ysv = T(0);
+    T spc[SYTRD_YC], yrc[SYTRD_YC], ysc[SYTRD_YC];
 #pragma unroll
     for (int c = 0; c < SYTRD_YC; c++) {
+        spc[c] = sacc_of(w, b, i, c)[tid & (2 * NBP - 1)];
         const T* yc = yacc_of(w, b, i, c);
-        if (rv) yr += yc[r];
-        ysv += yc[s];
+        yrc[c] = yc[rc];
+        ysc[c] = yc[s];
     }
     T vr_k[NBP / 4], wr_k[NBP / 4], vs_k[NBP / 4], ws_k[NBP / 4];
 #pragma unroll
     for (int t = 0; t < NBP / 4; t++) {
         const int k = part + 4 * t;
-        const bool ok = k < j;
-        vr_k[t] = (ok && rv) ? Vp[r + (long long)k * ldp] : T(0);
-        wr_k[t] = (ok && rv) ? Wp[r + (long long)k * ldp] : T(0);
-        vs_k[t] = ok ? Vp[s + (long long)k * ldp] : T(0);
-        ws_k[t] = ok ? Wp[s + (long long)k * ldp] : T(0);
+        vr_k[t] = Vp[rc + (long long)k * ldp];
+        wr_k[t] = Wp[rc + (long long)k * ldp];
+        vs_k[t] = Vp[s + (long long)k * ldp];
+        ws_k[t] = Wp[s + (long long)k * ldp];
     }
-    const T vr = rv ? Vp[r + (long long)j * ldp] : T(0);
-    const T acol = rv ? A[r + (long long)s * ld] : T(0);
+    const T vr_l = Vp[rc + (long long)j * ldp];
+    const T acol_l = A[rc + (long long)s * ld];
+    T sp = T(0), yr = T(0), ysv = T(0);
+#pragma unroll
+    for (int c = 0; c < SYTRD_YC; c++) {
+        sp += spc[c];
+        yr += yrc[c];
+        ysv += ysc[c];
+    }
+    if (!(tid < 2 * NBP && (tid % NBP) < j)) sp = T(0);
+    if (!rv) yr = T(0);
+#pragma unroll
+    for (int t = 0; t < NBP / 4; t++) {
+        const bool ok = part + 4 * t < j;
+        vr_k[t] = (ok && rv) ? vr_k[t] : T(0);
+        wr_k[t] = (ok && rv) ? wr_k[t] : T(0);
+        vs_k[t] = ok ? vs_k[t] : T(0);
+        ws_k[t] = ok ? ws_k[t] : T(0);
+    }
+    const T vr = rv ? vr_l : T(0);
+    const T acol = rv ? acol_l : T(0);
     if (tid < 2 * NBP) sps[tid] = sp;
     const T vAv = block_sum256(vpart, red);
 
