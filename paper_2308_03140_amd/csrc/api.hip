@@ -214,7 +214,8 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
         ow.sT = (long long)nblk * 4096; ow.Tm = wsT<T>(c, "Tm" + t, (size_t)ow.sT * nbatch);
         ow.sYp = (long long)nsplit * 64 * nmax; ow.Ypart = wsT<T>(c, "Ypart" + t, ow.sYp * nbatch);
         ow.sY = (long long)64 * nmax; ow.Y = wsT<T>(c, "Yb" + t, ow.sY * nbatch);
-        if (!ow.Gpart || !ow.Tm || !ow.Ypart || !ow.Y) return (mbd_status)c->err_code;
+        ow.sVT = (long long)nblk * 64 * nmax; ow.VT = wsT<T>(c, "VT" + t, (size_t)ow.sVT * nbatch);
+        if (!ow.Gpart || !ow.Tm || !ow.Ypart || !ow.Y || !ow.VT) return (mbd_status)c->err_code;
         ormtr_launch<T>(ow, nbatch, nmax, st);
         HIPCHK(hipGetLastError(), "ormtr");
     }

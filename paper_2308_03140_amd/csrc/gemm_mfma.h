@@ -3,10 +3,10 @@
 // reduction, the compact-WY back-transform, the divide-and-conquer merges,
 // Q^{-1/2} = X diag(lam^{-1/2}) X^T and the Ogita-Aishima refinement products.
 //
-// One 256-thread workgroup computes a 64x64 tile of C with 4 wavefronts in a
-// 2x2 arrangement, each wavefront owning 32x32 = 2x2 blocks of the 16x16x4
-// MFMA (v_mfma_f64_16x16x4f64 or v_mfma_f32_16x16x4f32, FP32 accumulation for
-// FP32).  K is staged through LDS in slabs of 16 with register prefetch of the
+// A workgroup of WM x WN wavefronts computes a BM x BN tile of C (default 64x64
+// with 2x2 wavefronts), each wavefront owning a block of the 16x16x4 MFMA
+// (v_mfma_f64_16x16x4f64 or v_mfma_f32_16x16x4f32, FP32 accumulation for
+// FP32).  K is staged through LDS in slabs of BK with register prefetch of the
 // next slab.  The problem object P supplies the tile map, element loaders and
 // the epilogue, so masked Householder vectors, index-mapped eigenvector
 // columns, batch strides and triangle-only tile sets need no copies.
@@ -46,20 +46,22 @@ struct GemmTile {
     int o, k;  // problem-specific offsets (e.g. merge origin and order)
 };
 
-// BM x BN tile per 256-thread workgroup (64x64 or 128x128): the 4 wavefronts
-// in a 2x2 arrangement each own a (BM/2)x(BN/2) block of 16x16 MFMA tiles.
-template <typename T, class P, int BM = GEMM_BM, int BN = GEMM_BN>
-__global__ __launch_bounds__(256) void gemm_mfma_kernel(P p) {
-    static_assert(BM % 32 == 0 && BN % 32 == 0, "tile edges are multiples of 32");
-    constexpr int MI = BM / 32, NJ = BN / 32;    // 16x16 blocks per wave in m and n
-    constexpr int LA = GEMM_BK * BM / 256, LB = GEMM_BK * BN / 256;
-    __shared__ T As[2][GEMM_BK][BM + GEMM_PAD];
-    __shared__ T Bs[2][GEMM_BK][BN + GEMM_PAD];
+// BM x BN tile per workgroup of WM x WN wavefronts, each owning a
+// (BM/WM) x (BN/WN) block of 16x16 MFMA tiles; K staged in LDS slabs of BK.
+template <typename T, class P, int BM = GEMM_BM, int BN = GEMM_BN, int BK = GEMM_BK, int WM = 2, int WN = 2>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_mfma_kernel(P p) {
+    constexpr int NT = 64 * WM * WN;
+    static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tiles are multiples of 16");
+    constexpr int MI = BM / WM / 16, NJ = BN / WN / 16;   // 16x16 blocks per wave in m and n
+    constexpr int LA = BK * BM / NT, LB = BK * BN / NT;
+    static_assert(LA * NT == BK * BM && LB * NT == BK * BN, "slab loads divide evenly");
+    __shared__ T As[2][BK][BM + GEMM_PAD];
+    __shared__ T Bs[2][BK][BN + GEMM_PAD];
     GemmTile t;
     if (!p.tile(blockIdx.x, blockIdx.y, blockIdx.z, t)) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave % WN;
 
     typename mfma4<T>::v acc[MI][NJ];
 #pragma unroll
@@ -69,12 +71,12 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(P p) {
 
     T ra[LA], rb[LB];
     auto a_index = [&](int ii, int& m, int& k) {
-        if (P::A_M_CONTIG) { m = tid % BM; k = tid / BM + (256 / BM) * ii; }
-        else { k = tid & 15; m = (tid >> 4) + 16 * ii; }
+        if (P::A_M_CONTIG) { m = tid % BM; k = tid / BM + (NT / BM) * ii; }
+        else { k = tid % BK; m = tid / BK + (NT / BK) * ii; }
     };
     auto b_index = [&](int ii, int& nn, int& k) {
-        if (P::B_N_CONTIG) { nn = tid % BN; k = tid / BN + (256 / BN) * ii; }
-        else { k = tid & 15; nn = (tid >> 4) + 16 * ii; }
+        if (P::B_N_CONTIG) { nn = tid % BN; k = tid / BN + (NT / BN) * ii; }
+        else { k = tid % BK; nn = tid / BK + (NT / BK) * ii; }
     };
     auto gload = [&](int k0) {
 #pragma unroll
@@ -105,21 +107,21 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(P p) {
         }
     };
 
-    const int nk = (t.K + GEMM_BK - 1) / GEMM_BK;
+    const int nk = (t.K + BK - 1) / BK;
     if (nk > 0) {
         gload(0);
         sstore(0);
         __syncthreads();
         for (int kt = 0; kt < nk; kt++) {
             const int buf = kt & 1;
-            if (kt + 1 < nk) gload((kt + 1) * GEMM_BK);
+            if (kt + 1 < nk) gload((kt + 1) * BK);
 #pragma unroll
-            for (int kk = 0; kk < GEMM_BK; kk += 4) {
+            for (int kk = 0; kk < BK; kk += 4) {
                 T af[MI], bf[NJ];
 #pragma unroll
-                for (int i = 0; i < MI; i++) af[i] = As[buf][kk + (lane >> 4)][wm * (BM / 2) + i * 16 + (lane & 15)];
+                for (int i = 0; i < MI; i++) af[i] = As[buf][kk + (lane >> 4)][wm * (BM / WM) + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < NJ; j++) bf[j] = Bs[buf][kk + (lane >> 4)][wn * (BN / 2) + j * 16 + (lane & 15)];
+                for (int j = 0; j < NJ; j++) bf[j] = Bs[buf][kk + (lane >> 4)][wn * (BN / WN) + j * 16 + (lane & 15)];
 #pragma unroll
                 for (int i = 0; i < MI; i++)
 #pragma unroll
@@ -135,8 +137,8 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(P p) {
         for (int j = 0; j < NJ; j++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                int row = t.m0 + wm * (BM / 2) + i * 16 + mfma_rows<T>::row(lane, r);
-                int col = t.n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+                int row = t.m0 + wm * (BM / WM) + i * 16 + mfma_rows<T>::row(lane, r);
+                int col = t.n0 + wn * (BN / WN) + j * 16 + (lane & 15);
                 p.store(t, row, col, acc[i][j][r]);
             }
 }

@@ -2,11 +2,14 @@
 // eigenvectors Z to the eigenvectors C of Q (eq:diagonalization, paper
 // Sec. 2.1).  Reflectors are grouped in blocks of 64 in compact-WY form
 // H_b..H_{b+63} = I - V T V^T (T upper triangular) and applied from the last
-// block to the first:
+// block to the first.  Up front, for all blocks at once (independent of X):
 //   G = V^T V           split-K over 512-row chunks, partials summed in order
 //   T                   from G and tau (forward column recurrence), one WG
-//   Y = T (V^T X)       split-K V^T X on matrix cores, then T applied per column
-//   X -= V Y            matrix cores
+//   VT = V T            matrix cores, stored densely per block
+// then per block:
+//   Ypart = V^T X       split-K over 512-row chunks on matrix cores
+//   Y = sum Ypart       wide elementwise reduction
+//   X -= VT Y           matrix cores (a rank-64 update: bound by the X traffic)
 // V is read straight from the reduced matrix with the unit diagonal and the
 // zeros above it supplied by the loader.
 #include "mbd_internal.h"
@@ -70,8 +73,16 @@ __global__ __launch_bounds__(256) void ormtr_tfactor_kernel(OrmtrWs<T> w, int ns
     const int ns_used = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
     const T* Gp = w.Gpart + (long long)b * w.sG + (long long)blk * nsplit * 4096;
     for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+        // partials in groups of 8 independent loads (split index clamped,
+        // value masked) summed in split order
         T s = T(0);
-        for (int q = 0; q < ns_used; q++) s += Gp[(long long)q * 4096 + idx];
+        for (int q0 = 0; q0 < ns_used; q0 += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = Gp[(long long)min(q0 + u, ns_used - 1) * 4096 + idx];
+#pragma unroll
+            for (int u = 0; u < 8; u++) s += q0 + u < ns_used ? v[u] : T(0);
+        }
         G[idx & 63][idx >> 6] = s;
         Tm[idx & 63][idx >> 6] = T(0);
     }
@@ -129,45 +140,67 @@ struct VtxProb {
     }
 };
 
-// Y(:, c) = T * sum_split Ypart(:, c)
+// VT(block) = V T: rows b0+1 .. n-1 of the block's reflectors times its T
+// factor; grid x = 64-row tile, y = block, z = matrix
 template <typename T>
-__global__ __launch_bounds__(256) void ormtr_ty_kernel(OrmtrWs<T> w, int b0) {
-    __shared__ T Ts[64][65];
-    __shared__ T ys[64][65];
+struct VtProb {
+    static constexpr bool A_M_CONTIG = true;
+    static constexpr bool B_N_CONTIG = false;
+    MatBatch<T> A; const int* ns; const T* Tm; long long sT; T* VT; long long sVT; int nmax;
+    __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
+        t.batch = bz;
+        const int n = ns[bz];
+        const int b0 = by * 64;
+        if (b0 >= n - 1) return false;
+        const int m = n - b0 - 1;
+        t.m0 = bx * GEMM_BM;
+        t.n0 = 0;
+        t.K = 64;
+        t.o = b0;
+        t.k = m;
+        return t.m0 < m;
+    }
+    __device__ T a(const GemmTile& t, int mm, int kk) const {
+        if (mm >= t.k) return T(0);
+        return hh_v(A.at(t.batch), A.ld, t.o + 1 + mm, t.o + kk, ns[t.batch] - 1);
+    }
+    __device__ T b(const GemmTile& t, int kk, int jj) const {
+        return Tm[(long long)t.batch * sT + (long long)(t.o / 64) * 4096 + kk + jj * 64];
+    }
+    __device__ void store(const GemmTile& t, int mm, int jj, T v) const {
+        if (mm >= t.k) return;
+        VT[(long long)t.batch * sVT + (long long)(t.o / 64) * 64 * nmax + (long long)jj * nmax + mm] = v;
+    }
+};
+
+// Y(:, c) = sum over the row chunks of Ypart(:, c)
+template <typename T>
+__global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
     if (b0 >= n - 1) return;
-    const int c0 = blockIdx.x * 64;
-    if (c0 >= n) return;
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;  // jj + 64 c
+    if (idx >= 64LL * n) return;
     const int m = n - b0 - 1;
-    const int nsplit = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
-    const T* To = w.Tm + (long long)b * w.sT + (long long)(b0 / 64) * 4096;
-    const T* Yp = w.Ypart + (long long)b * w.sYp;
-    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
-        const int jj = idx & 63, cc = idx >> 6;
-        Ts[jj][cc] = To[idx];
-        T s = T(0);
-        if (c0 + cc < n)
-            for (int q = 0; q < nsplit; q++) s += Yp[(long long)q * 64 * w.nmax + jj + (long long)(c0 + cc) * 64];
-        ys[cc][jj] = s;
+    const int nsu = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
+    const T* Yp = w.Ypart + (long long)b * w.sYp + idx;
+    T s = T(0);
+    for (int q0 = 0; q0 < nsu; q0 += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = Yp[(long long)min(q0 + u, nsu - 1) * 64 * w.nmax];
+#pragma unroll
+        for (int u = 0; u < 8; u++) s += q0 + u < nsu ? v[u] : T(0);
     }
-    __syncthreads();
-    T* Y = w.Y + (long long)b * w.sY;
-    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
-        const int jj = idx & 63, cc = idx >> 6;
-        if (c0 + cc >= n) continue;
-        T s = T(0);
-        for (int l = jj; l < 64; l++) s += Ts[jj][l] * ys[cc][l];
-        Y[jj + (long long)(c0 + cc) * 64] = s;
-    }
+    w.Y[(long long)b * w.sY + idx] = s;
 }
 
-// X(b0+1:n, :) -= V Y
+// X(b0+1:n, :) -= VT Y
 template <typename T>
 struct VyProb {
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = false;
-    MatBatch<T> A; MatBatch<T> X; const int* ns; int b0; const T* Y; long long sY; int tiles_n;
+    MatBatch<T> X; const int* ns; int b0; const T* VT; long long sVT; int nmax; const T* Y; long long sY; int tiles_n;
     __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
         t.batch = bz;
         const int n = ns[bz];
@@ -176,13 +209,12 @@ struct VyProb {
         t.m0 = (bx / tiles_n) * GEMM_BM;
         t.n0 = (bx % tiles_n) * GEMM_BN;
         t.K = 64;
+        t.k = m;
         return t.m0 < m && t.n0 < n;
     }
     __device__ T a(const GemmTile& t, int mm, int jj) const {
-        const int n = ns[t.batch];
-        const int r = b0 + 1 + mm;
-        if (r >= n) return T(0);
-        return hh_v(A.at(t.batch), A.ld, r, b0 + jj, n - 1);
+        if (mm >= t.k) return T(0);
+        return VT[(long long)t.batch * sVT + (long long)(b0 / 64) * 64 * nmax + (long long)jj * nmax + mm];
     }
     __device__ T b(const GemmTile& t, int jj, int c) const {
         if (c >= ns[t.batch]) return T(0);
@@ -208,14 +240,18 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     pg.A = w.A; pg.ns = w.ns; pg.Gpart = w.Gpart; pg.sG = w.sG; pg.nsplit = nsplit;
     hipLaunchKernelGGL((gemm_mfma_kernel<T, VtvProb<T>>), dim3(nblk, nsplit, nbatch), dim3(256), 0, st, pg);
     hipLaunchKernelGGL(ormtr_tfactor_kernel<T>, dim3(nblk, 1, nbatch), dim3(256), 0, st, w, nsplit);
+    VtProb<T> pv;
+    pv.A = w.A; pv.ns = w.ns; pv.Tm = w.Tm; pv.sT = w.sT; pv.VT = w.VT; pv.sVT = w.sVT; pv.nmax = w.nmax;
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, VtProb<T>>), dim3(tiles, nblk, nbatch), dim3(256), 0, st, pv);
     for (int blk = nblk - 1; blk >= 0; blk--) {
         const int b0 = blk * 64;
         VtxProb<T> px;
         px.A = w.A; px.X = w.X; px.ns = w.ns; px.b0 = b0; px.Ypart = w.Ypart; px.sYp = w.sYp; px.nmax = w.nmax;
         hipLaunchKernelGGL((gemm_mfma_kernel<T, VtxProb<T>>), dim3(tiles, nsplit, nbatch), dim3(256), 0, st, px);
-        hipLaunchKernelGGL(ormtr_ty_kernel<T>, dim3(tiles, 1, nbatch), dim3(256), 0, st, w, b0);
+        hipLaunchKernelGGL(ormtr_ysum_kernel<T>, dim3((64 * nmax + 255) / 256, 1, nbatch), dim3(256), 0, st, w, b0);
         VyProb<T> py;
-        py.A = w.A; py.X = w.X; py.ns = w.ns; py.b0 = b0; py.Y = w.Y; py.sY = w.sY; py.tiles_n = tiles;
+        py.X = w.X; py.ns = w.ns; py.b0 = b0; py.VT = w.VT; py.sVT = w.sVT; py.nmax = w.nmax; py.Y = w.Y; py.sY = w.sY;
+        py.tiles_n = tiles;
         hipLaunchKernelGGL((gemm_mfma_kernel<T, VyProb<T>>), dim3(tiles * tiles, 1, nbatch), dim3(256), 0, st, py);
     }
 }

@@ -168,16 +168,47 @@ __global__ __launch_bounds__(64) void stedc_deflate_kernel(StedcWs<T> w, int lev
     w.rotcnt[base] = nrot;
 }
 
-// The same scan for merges of up to DEFL_LDS entries: one workgroup stages
-// the poles and the updating vector in LDS, so the serial scan by one thread
-// never waits on global memory; compaction and write-back are parallel.
+// Exclusive prefix sum of one int per thread over a 256-thread block; the
+// total comes back through *total.  tmp holds 256 ints of LDS.
+__device__ __forceinline__ int block_exscan256(int v, int* tmp, int* total) {
+    const int tid = threadIdx.x;
+    __syncthreads();
+    tmp[tid] = v;
+    for (int off = 1; off < 256; off <<= 1) {
+        __syncthreads();
+        const int x = tid >= off ? tmp[tid - off] : 0;
+        __syncthreads();
+        tmp[tid] += x;
+    }
+    __syncthreads();
+    *total = tmp[255];
+    const int r = tmp[tid] - v;
+    __syncthreads();
+    return r;
+}
+
+// The same deflation for merges of up to DEFL_LDS entries, one workgroup per
+// merge, with the poles and the updating vector in LDS and the scan made
+// parallel.  The z-deflation flags depend only on the original values; so
+// does the rotation test of every adjacent pair of the remaining entries
+// unless the pair before it rotated.  Those tests are precomputed in
+// parallel; one thread then walks only the candidate pairs and the chains of
+// rotations that follow them (re-testing with the rotated values), skipping
+// 16 flags per LDS read.  The output positions of the sequential scan
+// (deflated entries in scan order, kept entries in list order, rotations in
+// order) follow from block prefix sums, so the results are the sequential
+// scan's, bit for bit.
 #define DEFL_LDS 7168
 template <typename T>
 __global__ __launch_bounds__(256) void stedc_deflate_lds_kernel(StedcWs<T> w, int lev) {
+    static_assert((DEFL_LDS + 255) / 256 <= 32, "one 32-bit z-deflation mask per thread chunk");
     __shared__ double sd[DEFL_LDS], sz[DEFL_LDS];
-    __shared__ int snd[DEFL_LDS];
+    __shared__ int sL[DEFL_LDS];
+    __shared__ __align__(16) unsigned char cand[DEFL_LDS];
+    __shared__ unsigned char rotf[DEFL_LDS];
+    __shared__ int tmp[256];
     __shared__ double red[4];
-    __shared__ int cnt;
+    const int tid = threadIdx.x;
     const int b = blockIdx.z;
     const int n = w.ns[b];
     const int o = blockIdx.x << lev;
@@ -191,7 +222,7 @@ __global__ __launch_bounds__(256) void stedc_deflate_lds_kernel(StedcWs<T> w, in
     int* dfpos = w.dfpos + base;
     const int k = m.k;
     double dmax = 0.0, zmax = 0.0;
-    for (int j = threadIdx.x; j < k; j += 256) {
+    for (int j = tid; j < k; j += 256) {
         const double d = ds[j], z = zs[j];
         sd[j] = d;
         sz[j] = z;
@@ -203,50 +234,127 @@ __global__ __launch_bounds__(256) void stedc_deflate_lds_kernel(StedcWs<T> w, in
     // deflation at the precision of the eigenvector matrices
     const double tol = 8.0 * (double)num_limits<T>::eps * fmax(dmax, zmax);
     const double rho = w.rho[base];
-    if (threadIdx.x == 0) {
-        int K = 0, ndf = 0, nrot = 0, pj = -1;
-        for (int jx = 0; jx < k; jx++) {
-            if (rho * fabs(sz[jx]) <= tol) { dfpos[ndf++] = jx; continue; }
-            if (pj < 0) { pj = jx; continue; }
-            double sn = sz[pj], c = sz[jx];
-            const double tau = sqrt(c * c + sn * sn);
+
+    // z-deflation flags of this thread's contiguous chunk, and the list L of
+    // the remaining entries in index order
+    const int per = (k + 255) / 256;
+    const int j0 = min(k, tid * per), j1 = min(k, j0 + per);
+    unsigned zmask = 0;
+    int cnt = 0;
+    for (int j = j0; j < j1; j++) {
+        if (rho * fabs(sz[j]) <= tol) zmask |= 1u << (j - j0);
+        else cnt++;
+    }
+    int K0;
+    const int t0 = block_exscan256(cnt, tmp, &K0);
+    {
+        int t = t0;
+        for (int j = j0; j < j1; j++)
+            if (!((zmask >> (j - j0)) & 1u)) sL[t++] = j;
+    }
+    __syncthreads();
+    // rotation tests of adjacent list pairs on the original values
+    for (int t = tid; t < K0; t += 256) {
+        unsigned char c = 0;
+        if (t >= 1) {
+            const int pj = sL[t - 1], jx = sL[t];
+            double sn = sz[pj], cs = sz[jx];
+            const double tau = sqrt(cs * cs + sn * sn);
             const double tt = sd[jx] - sd[pj];
-            c /= tau;
+            cs /= tau;
             sn = -sn / tau;
-            if (fabs(tt * c * sn) <= tol) {
+            c = fabs(tt * cs * sn) <= tol ? 1 : 0;
+        }
+        cand[t] = c;
+        rotf[t] = 0;
+    }
+    for (int t = K0 + tid; t < ((K0 + 15) & ~15); t += 256) cand[t] = 0;  // pad to a 16-flag boundary
+    __syncthreads();
+    if (tid == 0) {
+        int nrot = 0;
+        bool prev = false;  // the pair before rotated: re-test with its values
+        int t = 1;
+        while (t < K0) {
+            if (!prev) {
+                if ((t & 15) == 0) {
+                    const uint4 q = *reinterpret_cast<const uint4*>(&cand[t]);
+                    if ((q.x | q.y | q.z | q.w) == 0u) { t += 16; continue; }
+                }
+                if (!cand[t]) { t++; continue; }
+            }
+            const int pj = sL[t - 1], jx = sL[t];
+            double sn = sz[pj], cs = sz[jx];
+            const double tau = sqrt(cs * cs + sn * sn);
+            const double tt = sd[jx] - sd[pj];
+            cs /= tau;
+            sn = -sn / tau;
+            if (fabs(tt * cs * sn) <= tol) {
                 sz[jx] = tau;
                 sz[pj] = 0.0;
                 w.rp[base + nrot] = perm[pj];
                 w.rq[base + nrot] = perm[jx];
-                w.rc[base + nrot] = c;
+                w.rc[base + nrot] = cs;
                 w.rs[base + nrot] = sn;
                 nrot++;
-                const double dpj = sd[pj] * c * c + sd[jx] * sn * sn;
-                sd[jx] = sd[pj] * sn * sn + sd[jx] * c * c;
+                const double dpj = sd[pj] * cs * cs + sd[jx] * sn * sn;
+                sd[jx] = sd[pj] * sn * sn + sd[jx] * cs * cs;
                 sd[pj] = dpj;
-                dfpos[ndf++] = pj;
-                pj = jx;
+                rotf[t] = 1;
+                prev = true;
             } else {
-                snd[K++] = pj;
-                pj = jx;
+                prev = false;
             }
+            t++;
         }
-        if (pj >= 0) snd[K++] = pj;
-        cnt = K;
-        w.Kcnt[base] = K;
         w.rotcnt[base] = nrot;
     }
     __syncthreads();
-    const int K = cnt;
-    for (int j = threadIdx.x; j < k; j += 256) {
+    // output positions: at index j the sequential scan appends j to the
+    // deflated list (z-deflated), or the list predecessor L[t-1] of j = L[t]
+    // to the deflated list (the pair rotated) or to the kept list (it did not)
+    int cdf = 0, cnd = 0;
+    {
+        int t = t0;
+        for (int j = j0; j < j1; j++) {
+            if ((zmask >> (j - j0)) & 1u) { cdf++; continue; }
+            if (t >= 1) { if (rotf[t]) cdf++; else cnd++; }
+            t++;
+        }
+    }
+    int ndf_tot, nnd_tot;
+    int odf = block_exscan256(cdf, tmp, &ndf_tot);
+    int ond = block_exscan256(cnd, tmp, &nnd_tot);
+    {
+        int t = t0;
+        for (int j = j0; j < j1; j++) {
+            if ((zmask >> (j - j0)) & 1u) { dfpos[odf++] = j; continue; }
+            if (t >= 1) {
+                const int p = sL[t - 1];
+                if (rotf[t]) {
+                    dfpos[odf++] = p;
+                } else {
+                    w.ndpos[base + ond] = p;
+                    w.dn[base + ond] = sd[p];
+                    w.zn[base + ond] = sz[p];
+                    ond++;
+                }
+            }
+            t++;
+        }
+    }
+    const int K = K0 > 0 ? nnd_tot + 1 : 0;
+    if (tid == 0) {
+        if (K0 > 0) {
+            const int p = sL[K0 - 1];
+            w.ndpos[base + K - 1] = p;
+            w.dn[base + K - 1] = sd[p];
+            w.zn[base + K - 1] = sz[p];
+        }
+        w.Kcnt[base] = K;
+    }
+    for (int j = tid; j < k; j += 256) {
         ds[j] = sd[j];
         zs[j] = sz[j];
-    }
-    for (int kk = threadIdx.x; kk < K; kk += 256) {
-        const int p = snd[kk];
-        w.ndpos[base + kk] = p;
-        w.dn[base + kk] = sd[p];
-        w.zn[base + kk] = sz[p];
     }
 }
 
@@ -341,11 +449,15 @@ __global__ __launch_bounds__(256) void stedc_secular_kernel(StedcWs<T> w, int le
 }
 
 // Loewner formula for the updating vector consistent with the computed roots
+// Loewner updating vector zhat_i = sqrt(prod_j (lambda_j - d_i) / (d_j - d_i)
+// * (lambda_i - d_i) / rho), signed like z_i; one wavefront per i, the
+// factors strided over the lanes and multiplied across the wave.
 template <typename T>
 __global__ __launch_bounds__(256) void stedc_zhat_kernel(StedcWs<T> w, int lev) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (p >= n) return;
     const MergeInfo m = merge_of(p, lev, n);
     if (!m.active()) return;
@@ -357,16 +469,15 @@ __global__ __launch_bounds__(256) void stedc_zhat_kernel(StedcWs<T> w, int lev) 
     const double* mu = w.mu + base;
     const int* org = w.org + base;
     const double di = dn[i];
-    double prod = ((dn[org[i]] - di) + mu[i]) / w.rho[base];
-    for (int j = 0; j < K; j++) {
-        if (j == i) continue;
-        prod *= ((dn[org[j]] - di) + mu[j]) / (dn[j] - di);
+    double prod = 1.0;
+    for (int j = lane; j < K; j += 64)
+        if (j != i) prod *= ((dn[org[j]] - di) + mu[j]) / (dn[j] - di);
+    prod = wave_prod(prod) * (((dn[org[i]] - di) + mu[i]) / w.rho[base]);
+    if (lane == 0) {
+        const double z = sqrt(fmax(prod, 0.0));
+        w.zh[base + i] = w.zn[base + i] >= 0.0 ? z : -z;
     }
-    const double z = sqrt(fmax(prod, 0.0));
-    w.zh[base + i] = w.zn[base + i] >= 0.0 ? z : -z;
 }
-
-// eigenvectors of D + rho z z^T: u_i = zhat_i / (d_i - lambda_j), normalised
 template <typename T>
 __global__ __launch_bounds__(256) void stedc_vectors_kernel(StedcWs<T> w, int lev) {
     __shared__ double red[4];
@@ -400,11 +511,14 @@ __global__ __launch_bounds__(256) void stedc_vectors_kernel(StedcWs<T> w, int le
 }
 
 // final ascending order of the merged spectrum (roots and deflated values)
+// position of every eigenvalue of the merge in ascending order (ties by
+// index); one wavefront per value, the comparisons strided over the lanes
 template <typename T>
 __global__ __launch_bounds__(256) void stedc_order_kernel(StedcWs<T> w, int lev) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (p >= n) return;
     const MergeInfo m = merge_of(p, lev, n);
     if (!m.active()) return;
@@ -416,14 +530,17 @@ __global__ __launch_bounds__(256) void stedc_order_kernel(StedcWs<T> w, int lev)
     const int it = p - m.o;
     auto val = [&](int q) -> double { return q < K ? lam[q] : ds[dfpos[q - K]]; };
     const double v = val(it);
-    int rank = 0;
-    for (int q = 0; q < m.k; q++) {
+    int cnt = 0;
+    for (int q = lane; q < m.k; q += 64) {
         const double u = val(q);
-        rank += (u < v) || (u == v && q < it);
+        cnt += (u < v) || (u == v && q < it);
     }
-    if (it < K) w.outnd[base + it] = rank;
-    else w.outdf[base + it - K] = rank;
-    w.D[base + rank] = v;
+    const int rank = (int)wave_sum((double)cnt);
+    if (lane == 0) {
+        if (it < K) w.outnd[base + it] = rank;
+        else w.outdf[base + it - K] = rank;
+        w.D[base + rank] = v;
+    }
 }
 
 // merged eigenvectors: Zn[:, outnd[j]] = Zc[:, perm[ndpos[.]]] U[:, j]
@@ -552,9 +669,9 @@ int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
                                lev);
         hipLaunchKernelGGL(stedc_rotate_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev, src);
         hipLaunchKernelGGL(stedc_secular_kernel<T>, dim3((nmax + 3) / 4, 1, nbatch), dim3(256), 0, st, w, lev);
-        hipLaunchKernelGGL(stedc_zhat_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev);
+        hipLaunchKernelGGL(stedc_zhat_kernel<T>, dim3((nmax + 3) / 4, 1, nbatch), dim3(256), 0, st, w, lev);
         hipLaunchKernelGGL(stedc_vectors_kernel<T>, dim3(nmax, 1, nbatch), dim3(256), 0, st, w, lev);
-        hipLaunchKernelGGL(stedc_order_kernel<T>, dim3(gpos, 1, nbatch), dim3(256), 0, st, w, lev);
+        hipLaunchKernelGGL(stedc_order_kernel<T>, dim3((nmax + 3) / 4, 1, nbatch), dim3(256), 0, st, w, lev);
         if ((1 << lev) <= 64) {
             hipLaunchKernelGGL(stedc_small_merge_kernel<T>, dim3(nmerge, 1, nbatch), dim3(256), 0, st, w, lev,
                                src);

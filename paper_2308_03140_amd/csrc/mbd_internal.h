@@ -130,6 +130,21 @@ __device__ __forceinline__ T wave_sum(T v) {
     return a + b;
 }
 
+// Product over the wavefront, with the same butterfly (bit-identical in
+// every lane).
+__device__ __forceinline__ double wave_prod(double v) {
+    v *= dpp<DPP_QUAD_XOR1>(v);
+    v *= dpp<DPP_QUAD_XOR2>(v);
+    v *= dpp<DPP_HALF_MIRROR>(v);
+    v *= dpp<DPP_ROW_MIRROR>(v);
+    double a = v, b = v;
+    swap16(a, b);
+    v = a * b;
+    a = v; b = v;
+    swap32(a, b);
+    return a * b;
+}
+
 // Sixteen sums at once: returns in lane l the sum over the wave of v[l >> 2].
 template <typename T>
 __device__ __forceinline__ T wave_sum16(const T (&v)[16]) {

@@ -103,6 +103,7 @@ struct OrmtrWs {
     MatBatch<T> X;     // in: tridiagonal eigenvectors; out: eigenvectors of A
     T* Gpart; long long sG;   // [nblk][nsplit][64*64]
     T* Tm; long long sT;      // [nblk][64*64]
+    T* VT; long long sVT;     // [nblk][64][nmax]: V T of each block, rows b0+1.. from 0
     T* Ypart; long long sYp;  // [nsplit][64*nmax]
     T* Y; long long sY;       // [64*nmax]
     int nmax;

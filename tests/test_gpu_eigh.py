@@ -119,3 +119,28 @@ def test_autotune_table_roundtrip(tmp_path):
     import json
     tab = json.load(open(path))
     assert set(tab) == {"fp64", "fp32"} and "400" in tab["fp32"]
+
+
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 3e-5)])
+def test_eigh_clustered_n1100(ctx, dtype, tol):
+    """Order 1100: merges of 1024 and 2048 entries deflate in the LDS kernel
+    (several entries per thread, rotation chains from 8-fold clusters and
+    negligible z components), and the back-transform splits V^T X over three
+    512-row chunks.  Residual and orthogonality are checked directly, the
+    eigenvalues against LAPACK's (numpy) solver."""
+    from paper_2308_03140_amd import torch_api as T
+    _note("eigh clustered n=1100 %s" % dtype)
+    rng = np.random.default_rng(1100)
+    n = 1100
+    lam = np.concatenate([np.repeat(np.linspace(-2.0, 2.0, 100), 8), rng.uniform(-2.0, 2.0, n - 800)])
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Qm * lam) @ Qm.T
+    A = 0.5 * (A + A.T)
+    w, Z = T.eigh(ctx, torch.tensor(A, device="cuda", dtype=getattr(torch, dtype)))
+    torch.cuda.synchronize()
+    w = w.double().cpu().numpy()
+    Z = Z.double().cpu().numpy()
+    nrm = np.abs(A).sum(axis=1).max()
+    assert np.abs(w - np.linalg.eigvalsh(A)).max() <= tol * nrm
+    assert np.abs(A @ Z - Z * w).max() <= tol * nrm
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= tol * n / 100
