@@ -157,7 +157,8 @@ __global__ __launch_bounds__(256) void mbd_invsqrt4_kernel(const int* ns, const 
     sc[(long long)b * sL + k] = x > 0.0 ? 1.0 / sqrt(sqrt(x)) : 0.0;
 }
 
-// M = (X sc)(X sc)^T, lower tiles
+// M = (X sc)(X sc)^T, lower tiles of TS x TS
+template <int TS>
 struct ScaledSyrkProb {
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = true;
@@ -166,7 +167,7 @@ struct ScaledSyrkProb {
         t.batch = bz;
         int ti, tj;
         lower_tile(bx, ti, tj);
-        t.m0 = ti * GEMM_BM; t.n0 = tj * GEMM_BN; t.K = ns[bz];
+        t.m0 = ti * TS; t.n0 = tj * TS; t.K = ns[bz];
         return t.m0 < ns[bz];
     }
     __device__ double a(const GemmTile& t, int m, int k) const {
@@ -182,13 +183,23 @@ struct ScaledSyrkProb {
     }
 };
 
+// large matrices take 128 x 128 tiles (2 x 4 wavefronts, 8-deep K slabs: the
+// FP64 shape that measured fastest on gfx950), batches of small ones 64 x 64
 void mbd_inv_sqrt_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> X,
                          const double* sc, long long sL, MatBatch<double> M) {
-    ScaledSyrkProb p;
-    p.ns = ns; p.X = X; p.sc = sc; p.sL = sL; p.M = M;
-    const int t = (nmax + 63) / 64;
-    hipLaunchKernelGGL((gemm_mfma_kernel<double, ScaledSyrkProb>), dim3(t * (t + 1) / 2, 1, nbatch), dim3(256), 0,
-                       st, p);
+    if (nmax >= 2048) {
+        ScaledSyrkProb<128> p;
+        p.ns = ns; p.X = X; p.sc = sc; p.sL = sL; p.M = M;
+        const int t = (nmax + 127) / 128;
+        hipLaunchKernelGGL((gemm_mfma_kernel<double, ScaledSyrkProb<128>, 128, 128, 8, 2, 4>),
+                           dim3(t * (t + 1) / 2, 1, nbatch), dim3(512), 0, st, p);
+    } else {
+        ScaledSyrkProb<64> p;
+        p.ns = ns; p.X = X; p.sc = sc; p.sL = sL; p.M = M;
+        const int t = (nmax + 63) / 64;
+        hipLaunchKernelGGL((gemm_mfma_kernel<double, ScaledSyrkProb<64>>), dim3(t * (t + 1) / 2, 1, nbatch),
+                           dim3(256), 0, st, p);
+    }
 }
 
 // copy the lower triangle to the upper one

@@ -262,9 +262,15 @@ template void ormtr_launch<float>(const OrmtrWs<float>&, int, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // generic batched GEMM entry used by the refinement and gradient stages
 // ---------------------------------------------------------------------------
-#ifndef GEMM_TS128_MIN_TILES
-#define GEMM_TS128_MIN_TILES (1LL << 40)  // 128x128 tiles off: occupancy 1 on gfx950 loses to 64x64
-#endif
+// Large matrices take 128 x 128 tiles: twice the flops per byte staged from
+// L2 of the 64 x 64 tile.  Launch shape per type, measured on gfx950 at order
+// 6000: FP64 with 2 x 4 wavefronts and 8-deep K slabs (58 vs 50 TFLOP/s),
+// FP32 with 4 x 4 wavefronts and 16-deep slabs (99 vs 88 TFLOP/s).
+#define GEMM_TS128_MIN_ORDER 2048
+template <typename T> struct Gemm128Shape;
+template <> struct Gemm128Shape<double> { static constexpr int BK = 8, WM = 2, WN = 4; };
+template <> struct Gemm128Shape<float> { static constexpr int BK = 16, WM = 4, WN = 4; };
+
 template <typename T, bool TA, bool TB, int TS>
 static void gemm_gen_launch_ts(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
                                long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
@@ -277,17 +283,23 @@ static void gemm_gen_launch_ts(hipStream_t st, const int* ns, int nmax, int nbat
     const int t = (nmax + TS - 1) / TS;
     p.tiles_n = t;
     const int grid = lower_only ? t * (t + 1) / 2 : t * t;
-    hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB, TS>, TS, TS>), dim3(grid, 1, nbatch), dim3(256),
-                       0, st, p);
+    if constexpr (TS == 128) {
+        typedef Gemm128Shape<T> S;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB, TS>, TS, TS, S::BK, S::WM, S::WN>),
+                           dim3(grid, 1, nbatch), dim3(64 * S::WM * S::WN), 0, st, p);
+    } else {
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB, TS>, TS, TS>), dim3(grid, 1, nbatch),
+                           dim3(256), 0, st, p);
+    }
 }
 
-// 128x128 tiles once a matrix gives enough of them to fill the device
+// 128x128 tiles for large matrices; batches of small ones keep 64x64 (less
+// padding waste at the ragged edges)
 template <typename T, bool TA, bool TB>
 static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
                             long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
                             T alpha, T beta, bool lower_only, const int* skip) {
-    const long long tiles128 = (long long)((nmax + 127) / 128) * ((nmax + 127) / 128) * nbatch;
-    if (tiles128 >= GEMM_TS128_MIN_TILES)
+    if (nmax >= GEMM_TS128_MIN_ORDER)
         gemm_gen_launch_ts<T, TA, TB, 128>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta,
                                            lower_only, skip);
     else
