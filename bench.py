@@ -213,15 +213,17 @@ def leg_periodic(args, torch, T):
 
 
 def pmc_pass(torch, T):
-    """Runs under rocprofv3 --pmc: one FP32+refine N=2000 evaluation (after an
-    autotuned warm-up evaluation) and one device-to-device copy of 2^28 floats
-    (1 GiB read + 1 GiB written) whose counters calibrate FETCH_SIZE/WRITE_SIZE."""
+    """Runs under rocprofv3 --pmc: two FP32+refine N=2000 evaluations with every
+    kernel dispatched individually (no launch graph, default launch shapes, so
+    the counter collection sees each dispatch), then one device-to-device copy
+    of 2^28 floats (1 GiB read + 1 GiB written) whose counters calibrate
+    FETCH_SIZE and WRITE_SIZE."""
     import gen
+    os.environ["MBD_NO_GRAPH"] = "1"
     dev = torch.device("cuda", 0)
     c = gen.cluster_n2000()
     args = [torch.tensor(c[k], device=dev) for k in ("coords", "alpha0", "omega", "rvdw")]
     ctx = T.Context(0, "fp32_refined")
-    ctx.autotune([3 * len(c["omega"])])
     T.evaluate(ctx, *args, beta=c["beta"], a=c["a"])
     torch.cuda.synchronize()
     log("[bench] pmc pass: evaluation")
@@ -236,6 +238,69 @@ def pmc_pass(torch, T):
     ctx.close()
 
 
+def _pmc_dispatches(d):
+    """(kernel name, summed counter value) per dispatch, in dispatch order, from
+    a rocprofv3 --pmc CSV directory (one counter per run)."""
+    import csv
+    files = [os.path.join(r, f) for r, _, fs in os.walk(d) for f in fs if f.endswith("counter_collection.csv")]
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    per = {}
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                key = int(row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                name = row.get("Kernel_Name", "")
+                val = float(row.get("Counter_Value", 0.0))
+                if key in per:
+                    per[key][1] += val
+                else:
+                    per[key] = [name, val]
+    return [tuple(per[k]) for k in sorted(per)]
+
+
+def pmc_summary(fetch_dir, write_dir):
+    """Turns the FETCH_SIZE and WRITE_SIZE runs of --pmc-pass into the HBM bytes
+    per SYMV launch (profiles/sytrd_symv_fp32_n6000_pmc.txt): counters are in
+    KiB per dispatch; each is scaled by bytes/counter measured on the 1 GiB copy
+    of the same run."""
+    out = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        disp = _pmc_dispatches(d)
+        symv = [v for k, v in disp if "sytrd_symv_kernel<float" in k]
+        if len(symv) < 5999:
+            raise SystemExit("%s: %d SYMV dispatches, expected two evaluations" % (name, len(symv)))
+        symv = symv[-5999:]  # the second evaluation
+        copies = [v for k, v in disp if "copy" in k.lower()]
+        if not copies:
+            raise SystemExit("%s: no copy dispatch for the calibration" % name)
+        cal = float(1 << 30) / max(copies)  # bytes per counter unit on the 1 GiB copy
+        out[name] = (sum(symv) / len(symv), max(copies), cal)
+    with open(SYMV_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    fetch, wr = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    hbm = fetch[0] * fetch[2] + wr[0] * wr[2]
+    lines = [
+        "# rocprofv3 counters of sytrd_symv_kernel<float> at N=2000 (n=6000), FP32+refine path",
+        "# commands (repository root, MI355X):",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- python3 bench.py --pmc-pass",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- python3 bench.py --pmc-pass",
+        "#   python3 bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
+        "# averages over the 5999 SYMV dispatches of the second evaluation; calibration on the 1 GiB copy",
+        "symv_fetch_counter_avg = %.3f" % fetch[0],
+        "symv_write_counter_avg = %.3f" % wr[0],
+        "copy_fetch_counter = %.3f" % fetch[1],
+        "copy_write_counter = %.3f" % wr[1],
+        "bytes_per_fetch_unit = %.6f" % fetch[2],
+        "bytes_per_write_unit = %.6f" % wr[2],
+        "hbm_bytes_per_launch = %.1f" % hbm,
+        "kernel_source_sha256_16 = %s" % sha,
+    ]
+    with open(SYMV_PMC, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +309,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="c2,batch,periodic")
     ap.add_argument("--tuning-dir", default=None, help="write the autotuner tables (JSON) here")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="write the SYMV HBM-traffic file under profiles/ from two --pmc-pass counter runs")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="counter-collection pass: one FP32+refine N=2000 evaluation, then a plain device copy "
                          "of 1 GiB (the calibration kernel of known traffic); prints no JSON line")
@@ -253,6 +320,9 @@ def main():
               "(q-point/molecule sharding is design-only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
 
     import numpy as np
     import torch

@@ -187,14 +187,17 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     }
     dw.D = tv[0]; dw.E = tv[1]; dw.ds = tv[2]; dw.zs = tv[3]; dw.dn = tv[4]; dw.zn = tv[5];
     dw.mu = tv[6]; dw.lam = tv[7]; dw.zh = tv[8]; dw.rho = tv[9]; dw.rc = tv[10]; dw.rs = tv[11];
-    int* iv[10];
-    const char* in[10] = {"perm", "ndpos", "dfpos", "org", "outnd", "outdf", "rp", "rq", "Kcnt", "rotcnt"};
-    for (int k = 0; k < 10; k++) {
+    int* iv[17];
+    const char* in[17] = {"perm", "ndpos", "dfpos", "org", "outnd", "outdf", "rp", "rq", "Kcnt", "rotcnt",
+                          "sup", "ltop", "lbot", "ktop", "kbot", "ctop", "cbot"};
+    for (int k = 0; k < 17; k++) {
         iv[k] = wsT<int>(c, std::string("dc_") + in[k], nv);
         if (!iv[k]) return (mbd_status)c->err_code;
     }
     dw.perm = iv[0]; dw.ndpos = iv[1]; dw.dfpos = iv[2]; dw.org = iv[3]; dw.outnd = iv[4]; dw.outdf = iv[5];
     dw.rp = iv[6]; dw.rq = iv[7]; dw.Kcnt = iv[8]; dw.rotcnt = iv[9];
+    dw.sup = iv[10]; dw.ltop = iv[11]; dw.lbot = iv[12]; dw.ktop = iv[13]; dw.kbot = iv[14];
+    dw.ctop = iv[15]; dw.cbot = iv[16];
     dw.scale = wsT<double>(c, "dc_scale", nbatch);
     dw.Z0 = {wsT<T>(c, "Z0" + t, (size_t)sZ * nbatch), ldz, sZ};
     dw.Z1 = {wsT<T>(c, "Z1" + t, (size_t)sZ * nbatch), ldz, sZ};

@@ -157,49 +157,24 @@ __global__ __launch_bounds__(256) void mbd_invsqrt4_kernel(const int* ns, const 
     sc[(long long)b * sL + k] = x > 0.0 ? 1.0 / sqrt(sqrt(x)) : 0.0;
 }
 
-// M = (X sc)(X sc)^T, lower tiles of TS x TS
-template <int TS>
-struct ScaledSyrkProb {
-    static constexpr bool A_M_CONTIG = true;
-    static constexpr bool B_N_CONTIG = true;
-    const int* ns; MatBatch<double> X; const double* sc; long long sL; MatBatch<double> M;
-    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
-        t.batch = bz;
-        int ti, tj;
-        lower_tile(bx, ti, tj);
-        t.m0 = ti * TS; t.n0 = tj * TS; t.K = ns[bz];
-        return t.m0 < ns[bz];
-    }
-    __device__ double a(const GemmTile& t, int m, int k) const {
-        const int n = ns[t.batch];
-        if (m >= n || k >= n) return 0.0;
-        return X.at(t.batch)[m + (long long)k * X.ld] * sc[(long long)t.batch * sL + k];
-    }
-    __device__ double b(const GemmTile& t, int k, int nn) const { return a(t, nn, k); }
-    __device__ void store(const GemmTile& t, int m, int nn, double v) const {
-        const int n = ns[t.batch];
-        if (m >= n || nn >= n || m < nn) return;
-        M.at(t.batch)[m + (long long)nn * M.ld] = v;
-    }
-};
+// X(:, c) *= sc_c (X is not needed afterwards)
+__global__ __launch_bounds__(256) void mbd_scale_cols_kernel(const int* ns, MatBatch<double> X, const double* sc,
+                                                               long long sL) {
+    const int b = blockIdx.z;
+    const int n = ns[b];
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (c >= n || r >= n) return;
+    X.at(b)[r + (long long)c * X.ld] *= sc[(long long)b * sL + c];
+}
 
-// large matrices take 128 x 128 tiles (2 x 4 wavefronts, 8-deep K slabs: the
-// FP64 shape that measured fastest on gfx950), batches of small ones 64 x 64
+// M = (X sc)(X sc)^T, lower triangle: the columns of X are scaled in place,
+// then the symmetric product runs as a plain lower-triangle GEMM
 void mbd_inv_sqrt_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> X,
                          const double* sc, long long sL, MatBatch<double> M) {
-    if (nmax >= 2048) {
-        ScaledSyrkProb<128> p;
-        p.ns = ns; p.X = X; p.sc = sc; p.sL = sL; p.M = M;
-        const int t = (nmax + 127) / 128;
-        hipLaunchKernelGGL((gemm_mfma_kernel<double, ScaledSyrkProb<128>, 128, 128, 8, 2, 4>),
-                           dim3(t * (t + 1) / 2, 1, nbatch), dim3(512), 0, st, p);
-    } else {
-        ScaledSyrkProb<64> p;
-        p.ns = ns; p.X = X; p.sc = sc; p.sL = sL; p.M = M;
-        const int t = (nmax + 63) / 64;
-        hipLaunchKernelGGL((gemm_mfma_kernel<double, ScaledSyrkProb<64>>), dim3(t * (t + 1) / 2, 1, nbatch),
-                           dim3(256), 0, st, p);
-    }
+    hipLaunchKernelGGL(mbd_scale_cols_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, X, sc, sL);
+    gemm_batched<double>(st, false, true, ns, nmax, nbatch, X.p, X.ld, X.stride, X.p, X.ld, X.stride, M.p, M.ld,
+                         M.stride, 1.0, 0.0, true);
 }
 
 // copy the lower triangle to the upper one

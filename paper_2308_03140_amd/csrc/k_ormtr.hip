@@ -105,8 +105,8 @@ __global__ __launch_bounds__(256) void ormtr_tfactor_kernel(OrmtrWs<T> w, int ns
     for (int idx = threadIdx.x; idx < 4096; idx += 256) To[idx] = Tm[idx & 63][idx >> 6];
 }
 
-// Ypart[split] = V^T X over the rows of the chunk, 64 x n
-template <typename T>
+// Ypart[split] = V^T X over the rows of the chunk, 64 x n, in 64 x TN tiles
+template <typename T, int TN>
 struct VtxProb {
     static constexpr bool A_M_CONTIG = false;
     static constexpr bool B_N_CONTIG = false;
@@ -119,7 +119,7 @@ struct VtxProb {
         const int r0 = by * ORMTR_CHUNK;
         if (r0 >= m) return false;
         t.m0 = 0;
-        t.n0 = bx * GEMM_BN;
+        t.n0 = bx * TN;
         if (t.n0 >= n) return false;
         t.K = min(ORMTR_CHUNK, m - r0);
         t.o = b0 + 1 + r0;
@@ -195,8 +195,8 @@ __global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0) {
     w.Y[(long long)b * w.sY + idx] = s;
 }
 
-// X(b0+1:n, :) -= VT Y
-template <typename T>
+// X(b0+1:n, :) -= VT Y, in TS x TS output tiles
+template <typename T, int TS>
 struct VyProb {
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = false;
@@ -206,8 +206,8 @@ struct VyProb {
         const int n = ns[bz];
         if (b0 >= n - 1) return false;
         const int m = n - b0 - 1;
-        t.m0 = (bx / tiles_n) * GEMM_BM;
-        t.n0 = (bx % tiles_n) * GEMM_BN;
+        t.m0 = (bx / tiles_n) * TS;
+        t.n0 = (bx % tiles_n) * TS;
         t.K = 64;
         t.k = m;
         return t.m0 < m && t.n0 < n;
@@ -245,14 +245,17 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     hipLaunchKernelGGL((gemm_mfma_kernel<T, VtProb<T>>), dim3(tiles, nblk, nbatch), dim3(256), 0, st, pv);
     for (int blk = nblk - 1; blk >= 0; blk--) {
         const int b0 = blk * 64;
-        VtxProb<T> px;
+        // (64 x 128 tiles measured slower here: 53 vs 47 us per block at n = 6000)
+        VtxProb<T, 64> px;
         px.A = w.A; px.X = w.X; px.ns = w.ns; px.b0 = b0; px.Ypart = w.Ypart; px.sYp = w.sYp; px.nmax = w.nmax;
-        hipLaunchKernelGGL((gemm_mfma_kernel<T, VtxProb<T>>), dim3(tiles, nsplit, nbatch), dim3(256), 0, st, px);
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, VtxProb<T, 64>>), dim3(tiles, nsplit, nbatch), dim3(256), 0, st, px);
         hipLaunchKernelGGL(ormtr_ysum_kernel<T>, dim3((64 * nmax + 255) / 256, 1, nbatch), dim3(256), 0, st, w, b0);
-        VyProb<T> py;
+        // (128 x 128 tiles measured slower for this K = 64 update: 94 vs 83 us per
+        // block at n = 6000)
+        VyProb<T, 64> py;
         py.X = w.X; py.ns = w.ns; py.b0 = b0; py.VT = w.VT; py.sVT = w.sVT; py.nmax = w.nmax; py.Y = w.Y; py.sY = w.sY;
         py.tiles_n = tiles;
-        hipLaunchKernelGGL((gemm_mfma_kernel<T, VyProb<T>>), dim3(tiles * tiles, 1, nbatch), dim3(256), 0, st, py);
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, VyProb<T, 64>>), dim3(tiles * tiles, 1, nbatch), dim3(256), 0, st, py);
     }
 }
 
@@ -262,21 +265,14 @@ template void ormtr_launch<float>(const OrmtrWs<float>&, int, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // generic batched GEMM entry used by the refinement and gradient stages
 // ---------------------------------------------------------------------------
-// Large matrices take 128 x 128 tiles: twice the flops per byte staged from
-// L2 of the 64 x 64 tile.  Launch shape per type, measured on gfx950 at order
-// 6000: FP64 with 2 x 4 wavefronts and 8-deep K slabs (58 vs 50 TFLOP/s),
-// FP32 with 4 x 4 wavefronts and 16-deep slabs (99 vs 88 TFLOP/s).
-#define GEMM_TS128_MIN_ORDER 2048
-template <typename T> struct Gemm128Shape;
-template <> struct Gemm128Shape<double> { static constexpr int BK = 8, WM = 2, WN = 4; };
-template <> struct Gemm128Shape<float> { static constexpr int BK = 16, WM = 4, WN = 4; };
-
 template <typename T, bool TA, bool TB, int TS>
 static void gemm_gen_launch_ts(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
                                long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
-                               T alpha, T beta, bool lower_only, const int* skip) {
+                               T alpha, T beta, bool lower_only, const int* skip, const T* Cin, int ldcin,
+                               long long sCin) {
     GemmGeneral<T, TA, TB, TS> p;
     p.A = A; p.lda = lda; p.sA = sA; p.B = B; p.ldb = ldb; p.sB = sB; p.C = C; p.ldc = ldc; p.sC = sC;
+    p.Cin = Cin; p.ldcin = ldcin; p.sCin = sCin;
     p.ns = ns; p.M = p.N = p.K = nmax; p.alpha = alpha; p.beta = beta;
     p.lower_only = lower_only ? 1 : 0;
     p.skip = skip;
@@ -298,28 +294,29 @@ static void gemm_gen_launch_ts(hipStream_t st, const int* ns, int nmax, int nbat
 template <typename T, bool TA, bool TB>
 static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
                             long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
-                            T alpha, T beta, bool lower_only, const int* skip) {
+                            T alpha, T beta, bool lower_only, const int* skip, const T* Cin, int ldcin,
+                            long long sCin) {
     if (nmax >= GEMM_TS128_MIN_ORDER)
         gemm_gen_launch_ts<T, TA, TB, 128>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta,
-                                           lower_only, skip);
+                                           lower_only, skip, Cin, ldcin, sCin);
     else
         gemm_gen_launch_ts<T, TA, TB, 64>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta,
-                                          lower_only, skip);
+                                          lower_only, skip, Cin, ldcin, sCin);
 }
 
 template <typename T>
 void gemm_batched(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int nbatch, const T* A,
                   int lda, long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
-                  T alpha, T beta, bool lower_only, const int* skip) {
-    if (!ta && !tb) gemm_gen_launch<T, false, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip);
-    else if (ta && !tb) gemm_gen_launch<T, true, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip);
-    else if (!ta && tb) gemm_gen_launch<T, false, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip);
-    else gemm_gen_launch<T, true, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip);
+                  T alpha, T beta, bool lower_only, const int* skip, const T* Cin, int ldcin, long long sCin) {
+    if (!ta && !tb) gemm_gen_launch<T, false, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, Cin, ldcin, sCin);
+    else if (ta && !tb) gemm_gen_launch<T, true, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, Cin, ldcin, sCin);
+    else if (!ta && tb) gemm_gen_launch<T, false, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, Cin, ldcin, sCin);
+    else gemm_gen_launch<T, true, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, Cin, ldcin, sCin);
 }
 
 template void gemm_batched<double>(hipStream_t, bool, bool, const int*, int, int, const double*, int, long long,
                                    const double*, int, long long, double*, int, long long, double, double, bool,
-                                   const int*);
+                                   const int*, const double*, int, long long);
 template void gemm_batched<float>(hipStream_t, bool, bool, const int*, int, int, const float*, int, long long,
-                                  const float*, int, long long, float*, int, long long, float, float, bool,
-                                  const int*);
+                                   const float*, int, long long, float*, int, long long, float, float, bool,
+                                   const int*, const float*, int, long long);

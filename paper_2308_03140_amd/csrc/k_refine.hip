@@ -58,8 +58,11 @@ __global__ __launch_bounds__(256) void oa_f2d_kernel(const int* ns, MatBatch<flo
     Xd.at(b)[r + (long long)c * Xd.ld] = (double)X32.at(b)[r + (long long)c * X32.ld];
 }
 
-__global__ __launch_bounds__(256) void copy_mat_kernel(const int* ns, MatBatch<double> src, MatBatch<double> dst) {
+// dst = src; with only_skipped, just for the matrices whose skip flag is set
+__global__ __launch_bounds__(256) void copy_mat_kernel(const int* ns, MatBatch<double> src, MatBatch<double> dst,
+                                                         const int* only_skipped = nullptr) {
     const int b = blockIdx.z;
+    if (only_skipped && !only_skipped[b]) return;
     const int n = ns[b];
     const int c = blockIdx.y;
     const int r = blockIdx.x * 256 + threadIdx.x;
@@ -553,9 +556,10 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
                        skip);                                                                  // F -> T2
     hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats, skip,
                        next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
-    hipLaunchKernelGGL(copy_mat_kernel, ge, dim3(256), 0, st, ns, X, T1);                       // T1 = X
     gemm_batched<double>(st, false, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T2.p, T2.ld, T2.stride, T1.p,
-                         T1.ld, T1.stride, 1.0, 1.0, false, skip);                             // T1 = X + X F
+                         T1.ld, T1.stride, 1.0, 1.0, false, skip, X.p, X.ld, X.stride);        // T1 = X + X F
+    // a matrix that skips this step passes X through unchanged
+    if (skip) hipLaunchKernelGGL(copy_mat_kernel, ge, dim3(256), 0, st, ns, X, T1, skip);
 }
 
 // symmetric pseudo-random test matrix (autotuner input): A_rc = A_cr in [-1, 1)

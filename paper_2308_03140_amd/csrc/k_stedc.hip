@@ -132,10 +132,12 @@ __global__ __launch_bounds__(64) void stedc_deflate_kernel(StedcWs<T> w, int lev
     for (int j = 0; j < m.k; j++) { dmax = fmax(dmax, fabs(ds[j])); zmax = fmax(zmax, fabs(zs[j])); }
     // deflation at the precision of the eigenvector matrices
     const double tol = 8.0 * (double)num_limits<T>::eps * fmax(dmax, zmax);
-    int K = 0, ndf = 0, nrot = 0, pj = -1;
+    int* sup = w.sup + base;
+    int K = 0, ndf = 0, nrot = 0, pj = -1, spj = 0;
     for (int jx = 0; jx < m.k; jx++) {
         if (rho * fabs(zs[jx]) <= tol) { dfpos[ndf++] = jx; continue; }
-        if (pj < 0) { pj = jx; continue; }
+        const int sjx = perm[jx] < m.k1 ? 1 : 2;
+        if (pj < 0) { pj = jx; spj = sjx; continue; }
         double s = zs[pj], c = zs[jx];
         const double tau = sqrt(c * c + s * s);
         const double tt = ds[jx] - ds[pj];
@@ -154,12 +156,15 @@ __global__ __launch_bounds__(64) void stedc_deflate_kernel(StedcWs<T> w, int lev
             ds[pj] = dpj;
             dfpos[ndf++] = pj;
             pj = jx;
+            spj |= sjx;  // the survivor carries both columns' rows
         } else {
+            sup[K] = spj;
             ndpos[K++] = pj;
             pj = jx;
+            spj = sjx;
         }
     }
-    if (pj >= 0) ndpos[K++] = pj;
+    if (pj >= 0) { sup[K] = spj; ndpos[K++] = pj; }
     for (int kk = 0; kk < K; kk++) {
         w.dn[base + kk] = ds[ndpos[kk]];
         w.zn[base + kk] = zs[ndpos[kk]];
@@ -309,6 +314,14 @@ __global__ __launch_bounds__(256) void stedc_deflate_lds_kernel(StedcWs<T> w, in
         w.rotcnt[base] = nrot;
     }
     __syncthreads();
+    // rows carried by the kept entry at list position u: its own half's and
+    // those of the entries rotated into it (the chain of rotated pairs ending
+    // at u)
+    auto chain_support = [&](int u) {
+        int sp = perm[sL[u]] < m.k1 ? 1 : 2;
+        for (int q = u; q >= 1 && rotf[q]; q--) sp |= perm[sL[q - 1]] < m.k1 ? 1 : 2;
+        return sp;
+    };
     // output positions: at index j the sequential scan appends j to the
     // deflated list (z-deflated), or the list predecessor L[t-1] of j = L[t]
     // to the deflated list (the pair rotated) or to the kept list (it did not)
@@ -336,6 +349,7 @@ __global__ __launch_bounds__(256) void stedc_deflate_lds_kernel(StedcWs<T> w, in
                     w.ndpos[base + ond] = p;
                     w.dn[base + ond] = sd[p];
                     w.zn[base + ond] = sz[p];
+                    w.sup[base + ond] = chain_support(t - 1);
                     ond++;
                 }
             }
@@ -349,12 +363,49 @@ __global__ __launch_bounds__(256) void stedc_deflate_lds_kernel(StedcWs<T> w, in
             w.ndpos[base + K - 1] = p;
             w.dn[base + K - 1] = sd[p];
             w.zn[base + K - 1] = sz[p];
+            w.sup[base + K - 1] = chain_support(K0 - 1);
         }
         w.Kcnt[base] = K;
     }
     for (int j = tid; j < k; j += 256) {
         ds[j] = sd[j];
         zs[j] = sz[j];
+    }
+}
+
+// per merge, the kept columns whose rows reach the first half (ltop) and the
+// second half (lbot), each in kept order; one workgroup per merge
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_split_kernel(StedcWs<T> w, int lev) {
+    __shared__ int tmp[256];
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int o = blockIdx.x << lev;
+    if (o >= n) return;
+    const MergeInfo m = merge_of(o, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + o;
+    const int K = w.Kcnt[base];
+    const int per = (K + 255) / 256;
+    const int q0 = min(K, (int)threadIdx.x * per), q1 = min(K, q0 + per);
+    int ct = 0, cb = 0;
+    for (int q = q0; q < q1; q++) {
+        const int sp = w.sup[base + q];
+        ct += sp & 1;
+        cb += sp >> 1;
+    }
+    int nt, nb;
+    int ot = block_exscan256(ct, tmp, &nt);
+    int ob = block_exscan256(cb, tmp, &nb);
+    for (int q = q0; q < q1; q++) {
+        const int sp = w.sup[base + q];
+        const int col = w.perm[base + w.ndpos[base + q]];
+        if (sp & 1) { w.ltop[base + ot] = q; w.ctop[base + ot] = col; ot++; }
+        if (sp & 2) { w.lbot[base + ob] = q; w.cbot[base + ob] = col; ob++; }
+    }
+    if (threadIdx.x == 0) {
+        w.ktop[base] = nt;
+        w.kbot[base] = nb;
     }
 }
 
@@ -546,12 +597,19 @@ __global__ __launch_bounds__(256) void stedc_order_kernel(StedcWs<T> w, int lev)
 // merged eigenvectors: Zn[:, outnd[j]] = Zc[:, perm[ndpos[.]]] U[:, j]
 template <typename T>
 struct DcMergeProb {
+    // Zn(rows of half h, outnd(j)) = sum over the kept columns q with rows in
+    // half h of Zc(rows of h, column of q) U(q, j): the merge's eigenvector
+    // block is block diagonal except for columns rotated across the halves,
+    // so each half multiplies only its own columns (half the flops of the
+    // dense product when no rotation crosses).  grid x = half x row tiles x
+    // column tiles, y = merge, z = matrix.
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = false;
     const int* ns;
-    int lev, tdim;
+    int lev, tdim, tdh;
     MatBatch<T> Zc, Zn, U;
-    const int* perm; const int* ndpos; const int* outnd; const int* Kcnt;
+    const int* outnd; const int* Kcnt; const int* ltop; const int* lbot; const int* ktop; const int* kbot;
+    const int* ctop; const int* cbot;
     long long sV;
     __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
@@ -560,29 +618,35 @@ struct DcMergeProb {
         if (o >= n) return false;
         const MergeInfo m = merge_of(o, lev, n);
         if (!m.active()) return false;
-        const int K = Kcnt[(long long)bz * sV + o];
-        t.m0 = (bx / tdim) * GEMM_BM;
-        t.n0 = (bx % tdim) * GEMM_BN;
-        t.K = K;
+        const long long base = (long long)bz * sV + o;
+        const int h = bx / (tdh * tdim), rem = bx - h * (tdh * tdim);
+        const int K = Kcnt[base];
+        t.m0 = (rem / tdim) * GEMM_BM;
+        t.n0 = (rem % tdim) * GEMM_BN;
         t.o = o;
-        t.k = m.k;
-        return t.m0 < m.k && t.n0 < K;
+        t.e0 = h ? m.k1 : 0;                  // first row of the half
+        t.k = h ? m.k - m.k1 : m.k1;          // rows of the half
+        t.K = h ? kbot[base] : ktop[base];    // columns with rows there
+        t.e1 = K;
+        return t.m0 < t.k && t.n0 < K;        // a half with no columns writes zeros
     }
-    __device__ T a(const GemmTile& t, int mm, int kk) const {
-        if (mm >= t.k || kk >= t.K) return T(0);
+    __device__ T a(const GemmTile& t, int mm, int q) const {
+        if (mm >= t.k || q >= t.K) return T(0);
         const long long base = (long long)t.batch * sV + t.o;
-        const long long c = t.o + perm[base + ndpos[base + kk]];
-        return Zc.at(t.batch)[(t.o + mm) + c * Zc.ld];
+        const long long c = t.o + (t.e0 ? cbot : ctop)[base + q];
+        return Zc.at(t.batch)[(t.o + t.e0 + mm) + c * Zc.ld];
     }
-    __device__ T b(const GemmTile& t, int kk, int jj) const {
-        if (kk >= t.K || jj >= t.K) return T(0);
+    __device__ T b(const GemmTile& t, int q, int jj) const {
+        if (q >= t.K || jj >= t.e1) return T(0);
+        const long long base = (long long)t.batch * sV + t.o;
+        const int kk = (t.e0 ? lbot : ltop)[base + q];
         return U.at(t.batch)[(t.o + kk) + (long long)(t.o + jj) * U.ld];
     }
     __device__ void store(const GemmTile& t, int mm, int jj, T v) const {
-        if (mm >= t.k || jj >= t.K) return;
+        if (mm >= t.k || jj >= t.e1) return;
         const long long base = (long long)t.batch * sV + t.o;
         const long long c = t.o + outnd[base + jj];
-        Zn.at(t.batch)[(t.o + mm) + c * Zn.ld] = v;
+        Zn.at(t.batch)[(t.o + t.e0 + mm) + c * Zn.ld] = v;
     }
 };
 
@@ -676,14 +740,17 @@ int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
             hipLaunchKernelGGL(stedc_small_merge_kernel<T>, dim3(nmerge, 1, nbatch), dim3(256), 0, st, w, lev,
                                src);
         } else {
+            hipLaunchKernelGGL(stedc_split_kernel<T>, dim3(nmerge, 1, nbatch), dim3(256), 0, st, w, lev);
             DcMergeProb<T> pr;
             pr.ns = w.ns; pr.lev = lev;
             pr.tdim = (1 << lev) / GEMM_BM;
+            pr.tdh = (1 << (lev - 1)) / GEMM_BM;
             pr.Zc = src ? w.Z1 : w.Z0;
             pr.Zn = src ? w.Z0 : w.Z1;
             pr.U = w.U;
-            pr.perm = w.perm; pr.ndpos = w.ndpos; pr.outnd = w.outnd; pr.Kcnt = w.Kcnt; pr.sV = w.sV;
-            hipLaunchKernelGGL((gemm_mfma_kernel<T, DcMergeProb<T>>), dim3(pr.tdim * pr.tdim, nmerge, nbatch),
+            pr.outnd = w.outnd; pr.Kcnt = w.Kcnt; pr.ltop = w.ltop; pr.lbot = w.lbot; pr.ktop = w.ktop;
+            pr.kbot = w.kbot; pr.ctop = w.ctop; pr.cbot = w.cbot; pr.sV = w.sV;
+            hipLaunchKernelGGL((gemm_mfma_kernel<T, DcMergeProb<T>>), dim3(2 * pr.tdh * pr.tdim, nmerge, nbatch),
                                dim3(256), 0, st, pr);
         }
         hipLaunchKernelGGL(stedc_copy_kernel<T>, dim3(nmax, 1, nbatch), dim3(256), 0, st, w, lev, src);

@@ -88,6 +88,11 @@ struct StedcWs {
     double* rc; double* rs;
     int* perm; int* ndpos; int* dfpos; int* org; int* outnd; int* outdf; int* rp; int* rq;
     int* Kcnt; int* rotcnt;
+    // support of each kept column of a merge (1: first half's rows, 2: second
+    // half's, 3: both, after a rotation across the halves) and, per half, the
+    // kept columns with support there (count at the merge origin)
+    int* sup; int* ltop; int* lbot; int* ktop; int* kbot;
+    int* ctop; int* cbot;  // the listed columns' positions in the merge's eigenvector block
     T* w_out; long long sW;       // eigenvalues (ascending) out
 };
 // Returns 0 if the eigenvectors ended in Z0, 1 if in Z1.
@@ -111,8 +116,10 @@ struct OrmtrWs {
 template <typename T>
 void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st);
 
-// --- generic batched GEMM (C = alpha op(A) op(B) + beta C, order ns[b]) ------
+// --- generic batched GEMM (C = alpha op(A) op(B) + beta Cin, order ns[b]; Cin
+// defaults to C) ---------------------------------------------------------------
 template <typename T>
 void gemm_batched(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int nbatch,
                   const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C,
-                  int ldc, long long sC, T alpha, T beta, bool lower_only, const int* skip = nullptr);
+                  int ldc, long long sC, T alpha, T beta, bool lower_only, const int* skip = nullptr,
+                  const T* Cin = nullptr, int ldcin = 0, long long sCin = 0);

@@ -35,6 +35,7 @@ void mbd_energy_launch(hipStream_t st, const SysDesc* sd, int nsys, const int* n
                        long long sL, const double* om, unsigned* status, double* lmin);
 void mbd_invsqrt4_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const double* lam, long long sL,
                          double* sc);
+// lower triangle of M = X diag(sc)^2 X^T; the columns of X are scaled in place
 void mbd_inv_sqrt_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> X,
                          const double* sc, long long sL, MatBatch<double> M);
 void mbd_mirror_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> M);

@@ -108,3 +108,26 @@ def test_molecule_batch_512():
             assert np.abs(o["grad_omega"].cpu().numpy() - ref["grad_omega"]).max() <= 1e-6, (i, N)
     c32.close()
     c64.close()
+
+
+@pytest.mark.parametrize("tol", ["1e-30", "1e30"])
+def test_refinement_second_step_forced_and_suppressed(monkeypatch, tol):
+    """FP32 + refinement with the second refinement step taken by every
+    molecule (threshold 1e-30) and by none (1e30): the second step's products
+    and the pass-through of molecules that skip it both reach the oracle."""
+    from paper_2308_03140_amd import torch_api as T
+    _note("refinement second step, MBD_REFINE_TOL=%s" % tol)
+    monkeypatch.setenv("MBD_REFINE_TOL", tol)
+    c = T.Context(0, "fp32_refined")
+    try:
+        mols = _mols(77, 6, 8, 60)
+        outs = T.evaluate_batch(c, [dict(m, coords=torch.tensor(m["coords"], device="cuda")) for m in mols])
+        for m, o in zip(mols, outs):
+            assert o["status"] == 0
+            ref = oracle.mbd_finite(m["coords"], m["alpha0"], m["omega"], m["rvdw"], m["beta"], m["a"])
+            N = len(m["omega"])
+            assert abs(o["energy"].item() - ref["energy"]) / N <= 1e-7
+            assert np.abs(o["grad_coords"].cpu().numpy() - ref["grad_R"]).max() <= 1e-6
+            assert np.abs(o["grad_omega"].cpu().numpy() - ref["grad_omega"]).max() <= 1e-6
+    finally:
+        c.close()
