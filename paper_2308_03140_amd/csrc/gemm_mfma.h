@@ -10,7 +10,17 @@
 // next slab.  The problem object P supplies the tile map, element loaders and
 // the epilogue, so masked Householder vectors, index-mapped eigenvector
 // columns, batch strides and triangle-only tile sets need no copies.
+//
+// A problem may also define EPI_VEC = true for a read-modify-write epilogue
+// on 16-byte column segments: its C tile is requested before the K loop
+// through
+//   Vec16<T>::v epi_load(const GemmTile&, int m, int n)   rows m .. m+RPL-1 of column n
+// and, once the accumulators have been transposed through LDS so that every
+// thread holds RPL = 16/sizeof(T) consecutive rows of one column, written by
+//   void epi_store(const GemmTile&, int m, int n, Vec16<T>::v acc, Vec16<T>::v cin)
+// (m, n in the problem's tile coordinates; m is a multiple of RPL).
 #pragma once
+#include <type_traits>
 #include "mbd_internal.h"
 
 template <typename T> struct mfma4;
@@ -40,6 +50,10 @@ __device__ __forceinline__ mfma4<float>::v mfma16x16x4(float a, float b, mfma4<f
 #define GEMM_BK 16
 #define GEMM_PAD 4
 
+template <class P, class = void> struct gemm_epi_vec : std::false_type {};
+template <class P>
+struct gemm_epi_vec<P, std::void_t<decltype(P::EPI_VEC)>> : std::integral_constant<bool, P::EPI_VEC> {};
+
 // Tile descriptor returned by P::tile()
 struct GemmTile {
     int batch, m0, n0, K;
@@ -56,13 +70,33 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_mfma_kernel(P p) {
     constexpr int MI = BM / WM / 16, NJ = BN / WN / 16;   // 16x16 blocks per wave in m and n
     constexpr int LA = BK * BM / NT, LB = BK * BN / NT;
     static_assert(LA * NT == BK * BM && LB * NT == BK * BN, "slab loads divide evenly");
-    __shared__ T As[2][BK][BM + GEMM_PAD];
-    __shared__ T Bs[2][BK][BN + GEMM_PAD];
+    constexpr bool EV = gemm_epi_vec<P>::value;
+    constexpr int RPL = 16 / (int)sizeof(T);
+    constexpr int ELD = BM + RPL;  // column stride of the transposed C tile
+    constexpr int STAGE = 2 * BK * (BM + GEMM_PAD) + 2 * BK * (BN + GEMM_PAD);
+    constexpr int LDSN = EV && BN * ELD > STAGE ? BN * ELD : STAGE;
+    // K slabs of A and B; with EV the same space later holds the C tile
+    __shared__ __align__(16) T lds[LDSN];
+    T(*As)[BK][BM + GEMM_PAD] = reinterpret_cast<T(*)[BK][BM + GEMM_PAD]>(lds);
+    T(*Bs)[BK][BN + GEMM_PAD] = reinterpret_cast<T(*)[BK][BN + GEMM_PAD]>(lds + 2 * BK * (BM + GEMM_PAD));
     GemmTile t;
     if (!p.tile(blockIdx.x, blockIdx.y, blockIdx.z, t)) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
+
+    typedef typename Vec16<T>::v VT;
+    constexpr int CPC = BM / RPL;                // vectors per tile column
+    constexpr int NV = EV ? BM * BN / (NT * RPL) : 1;  // vectors per thread
+    static_assert(!EV || NV * NT * RPL == BM * BN, "the C tile divides into 16-byte vectors");
+    VT cin[NV];
+    if constexpr (EV) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int idx = tid + v * NT;
+            cin[v] = p.epi_load(t, t.m0 + (idx % CPC) * RPL, t.n0 + idx / CPC);
+        }
+    }
 
     typename mfma4<T>::v acc[MI][NJ];
 #pragma unroll
@@ -132,16 +166,43 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_mfma_kernel(P p) {
             __syncthreads();
         }
     }
+    if constexpr (EV) {
+        // the K loop ended on a barrier, so the staging space is free: write
+        // the accumulators column-major, then read them back as 16-byte runs
 #pragma unroll
-    for (int i = 0; i < MI; i++)
+        for (int i = 0; i < MI; i++)
 #pragma unroll
-        for (int j = 0; j < NJ; j++)
+            for (int j = 0; j < NJ; j++) {
+                const int col = wn * (BN / WN) + j * 16 + (lane & 15);
+                if constexpr (sizeof(T) == 4) {
+                    // FP32 layout: the lane's 4 values are consecutive rows
+                    const int row = wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
+                    *reinterpret_cast<VT*>(&lds[col * ELD + row]) = acc[i][j];
+                } else {
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                int row = t.m0 + wm * (BM / WM) + i * 16 + mfma_rows<T>::row(lane, r);
-                int col = t.n0 + wn * (BN / WN) + j * 16 + (lane & 15);
-                p.store(t, row, col, acc[i][j][r]);
+                    for (int r = 0; r < 4; r++)
+                        lds[col * ELD + wm * (BM / WM) + i * 16 + mfma_rows<T>::row(lane, r)] = acc[i][j][r];
+                }
             }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int idx = tid + v * NT;
+            const int m = (idx % CPC) * RPL, c = idx / CPC;
+            p.epi_store(t, t.m0 + m, t.n0 + c, *reinterpret_cast<const VT*>(&lds[c * ELD + m]), cin[v]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < MI; i++)
+#pragma unroll
+            for (int j = 0; j < NJ; j++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    int row = t.m0 + wm * (BM / WM) + i * 16 + mfma_rows<T>::row(lane, r);
+                    int col = t.n0 + wn * (BN / WN) + j * 16 + (lane & 15);
+                    p.store(t, row, col, acc[i][j][r]);
+                }
+    }
 }
 
 // Launch shape of the 128 x 128 tile per type, measured on gfx950 at order

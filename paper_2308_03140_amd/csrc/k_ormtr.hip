@@ -195,37 +195,55 @@ __global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0) {
     w.Y[(long long)b * w.sY + idx] = s;
 }
 
-// X(b0+1:n, :) -= VT Y, in TS x TS output tiles
+// X(b0+1:n, :) -= VT Y, in TS x TS output tiles.  Tile rows are absolute
+// rows of X counted from b0 (a multiple of 64), so that with the 64-padded
+// leading dimension every 16-byte column segment is aligned; row b0 itself
+// is outside the update (its VT row is zero) and is never written.  The
+// epilogue reads X before the K loop and writes it back in 16-byte segments.
 template <typename T, int TS>
 struct VyProb {
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = false;
+    static constexpr bool EPI_VEC = true;
+    typedef typename Vec16<T>::v Vec;
+    static constexpr int RPL = 16 / (int)sizeof(T);
     MatBatch<T> X; const int* ns; int b0; const T* VT; long long sVT; int nmax; const T* Y; long long sY; int tiles_n;
     __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
         t.batch = bz;
         const int n = ns[bz];
         if (b0 >= n - 1) return false;
-        const int m = n - b0 - 1;
-        t.m0 = (bx / tiles_n) * TS;
+        t.m0 = b0 + (bx / tiles_n) * TS;
         t.n0 = (bx % tiles_n) * TS;
         t.K = 64;
-        t.k = m;
-        return t.m0 < m && t.n0 < n;
+        return t.m0 < n && t.n0 < n;
     }
-    __device__ T a(const GemmTile& t, int mm, int jj) const {
-        if (mm >= t.k) return T(0);
-        return VT[(long long)t.batch * sVT + (long long)(b0 / 64) * 64 * nmax + (long long)jj * nmax + mm];
+    __device__ T a(const GemmTile& t, int r, int jj) const {
+        if (r <= b0 || r >= ns[t.batch]) return T(0);
+        return VT[(long long)t.batch * sVT + (long long)(b0 / 64) * 64 * nmax + (long long)jj * nmax + (r - b0 - 1)];
     }
     __device__ T b(const GemmTile& t, int jj, int c) const {
         if (c >= ns[t.batch]) return T(0);
         return Y[(long long)t.batch * sY + jj + (long long)c * 64];
     }
-    __device__ void store(const GemmTile& t, int mm, int c, T v) const {
+    __device__ Vec epi_load(const GemmTile& t, int r, int c) const {
         const int n = ns[t.batch];
-        const int r = b0 + 1 + mm;
-        if (r >= n || c >= n) return;
-        X.at(t.batch)[r + (long long)c * X.ld] -= v;
+        if (r >= n || c >= n) return Vec{};
+        // r + RPL - 1 < ld: the run stays inside the padded column
+        return *reinterpret_cast<const Vec*>(X.at(t.batch) + r + (long long)c * X.ld);
     }
+    __device__ void epi_store(const GemmTile& t, int r, int c, Vec acc, Vec cin) const {
+        const int n = ns[t.batch];
+        if (r >= n || c >= n) return;
+        T* x = X.at(t.batch) + r + (long long)c * X.ld;
+        if (r > b0 && r + RPL <= n) {
+            *reinterpret_cast<Vec*>(x) = cin - acc;
+        } else {
+#pragma unroll
+            for (int e = 0; e < RPL; e++)
+                if (r + e > b0 && r + e < n) x[e] = cin[e] - acc[e];
+        }
+    }
+    __device__ void store(const GemmTile&, int, int, T) const {}
 };
 
 template <typename T>

@@ -533,10 +533,17 @@ __global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, 
 }
 
 // Trailing update A(t0:n, t0:n) -= V W^T + W V^T, lower TS x TS tiles only.
+// t0 is a multiple of the panel width and the leading dimension a multiple of
+// 64, so the epilogue reads A before the K loop and writes it back in aligned
+// 16-byte column segments (elements above the diagonal left untouched).
 template <typename T, int NBP, int TS>
 struct Syr2kProb {
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = true;
+    static constexpr bool EPI_VEC = true;
+    typedef typename Vec16<T>::v Vec;
+    static constexpr int RPL = 16 / (int)sizeof(T);
+    static_assert(NBP % RPL == 0, "panel starts align to 16-byte segments");
     MatBatch<T> A;
     const int* ns;
     const T* Vp; const T* Wp; int ldp; long long sP;
@@ -562,11 +569,24 @@ struct Syr2kProb {
         const long long o = (long long)t.batch * sP + c;
         return k < NBP ? Wp[o + (long long)k * ldp] : Vp[o + (long long)(k - NBP) * ldp];
     }
-    __device__ void store(const GemmTile& t, int m, int nn, T v) const {
+    __device__ Vec epi_load(const GemmTile& t, int m, int nn) const {
         const int r = t0 + m, c = t0 + nn, nb_ = ns[t.batch];
-        if (r >= nb_ || c >= nb_ || r < c) return;
-        A.at(t.batch)[r + (long long)c * A.ld] -= v;
+        if (r >= nb_ || c >= nb_ || r + RPL <= c) return Vec{};
+        return *reinterpret_cast<const Vec*>(A.at(t.batch) + r + (long long)c * A.ld);
     }
+    __device__ void epi_store(const GemmTile& t, int m, int nn, Vec acc, Vec cin) const {
+        const int r = t0 + m, c = t0 + nn, nb_ = ns[t.batch];
+        if (r >= nb_ || c >= nb_ || r + RPL <= c) return;
+        T* a = A.at(t.batch) + r + (long long)c * A.ld;
+        if (r >= c && r + RPL <= nb_) {
+            *reinterpret_cast<Vec*>(a) = cin - acc;
+        } else {
+#pragma unroll
+            for (int e = 0; e < RPL; e++)
+                if (r + e >= c && r + e < nb_) a[e] = cin[e] - acc[e];
+        }
+    }
+    __device__ void store(const GemmTile&, int, int, T) const {}
 };
 
 // persistent grid size for the cooperative panel kernel (0 if unavailable)
