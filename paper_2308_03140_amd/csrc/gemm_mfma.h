@@ -223,6 +223,51 @@ __device__ __forceinline__ void lower_tile(int lin, int& ti, int& tj) {
     tj = lin - r * (r + 1) / 2;
 }
 
+// XCD-aware tile order.  The 8 XCDs of the chip take workgroups round robin
+// (workgroup bx runs on XCD bx mod 8) and each has its own L2, so workgroup
+// bx = x + 8k is given the k-th tile of a contiguous share x of a banded
+// order: bands of GEMM_BAND tile rows walked column by column.  The tiles an
+// XCD runs at once then share A panels (same band) and B panels (same
+// column) in its L2.  Any grid size works: the map is a bijection.
+#define GEMM_NXCD 8
+#define GEMM_BAND 8
+__device__ __forceinline__ int xcd_virtual(int bx, int G) {
+    const int x = bx % GEMM_NXCD, k = bx / GEMM_NXCD;
+    const int q = G / GEMM_NXCD, r = G % GEMM_NXCD;
+    return x * q + min(x, r) + k;
+}
+// full tm x tn grid
+__device__ __forceinline__ void band_tile(int v, int tm, int tn, int& ti, int& tj) {
+    const int band = v / (GEMM_BAND * tn);
+    const int idx = v - band * GEMM_BAND * tn;
+    const int rows = min(GEMM_BAND, tm - band * GEMM_BAND);
+    ti = band * GEMM_BAND + idx % rows;
+    tj = idx / rows;
+}
+// lower triangle (ti >= tj) of a t x t grid: band b holds rows r0 = b BAND ..
+// r0 + rows - 1, first the r0 x rows rectangle left of the diagonal block,
+// column by column, then the diagonal block's lower triangle, column by column
+__device__ __forceinline__ void band_lower_tile(int v, int t, int& ti, int& tj) {
+    int r0 = 0, rows = min(GEMM_BAND, t);
+    for (;;) {
+        const int cnt = r0 * rows + rows * (rows + 1) / 2;
+        if (v < cnt || r0 + rows >= t) break;
+        v -= cnt;
+        r0 += rows;
+        rows = min(GEMM_BAND, t - r0);
+    }
+    if (v < r0 * rows) {
+        ti = r0 + v % rows;
+        tj = v / rows;
+        return;
+    }
+    v -= r0 * rows;
+    int c = 0;
+    while (c < rows - 1 && v >= rows - c) { v -= rows - c; c++; }
+    tj = r0 + c;
+    ti = r0 + c + v;
+}
+
 // General batched C = alpha op(A) op(B) + beta C over matrices of order ns[b]
 // (M, N, K derived from ns through the m/n/k multipliers and offsets), in
 // TS x TS output tiles.
@@ -245,8 +290,9 @@ struct GemmGeneral {
         if (skip && skip[bz]) return false;
         int Mb = ns ? ns[bz] : M, Nb = ns ? ns[bz] : N, Kb = ns ? ns[bz] : K;
         int ti, tj;
-        if (lower_only) lower_tile(bx, ti, tj);
-        else { ti = bx / tiles_n; tj = bx % tiles_n; }
+        const int v = xcd_virtual(bx, gridDim.x);
+        if (lower_only) band_lower_tile(v, tiles_n, ti, tj);
+        else band_tile(v, tiles_n, tiles_n, ti, tj);
         t.m0 = ti * TS; t.n0 = tj * TS; t.K = Kb;
         return t.m0 < Mb && t.n0 < Nb;
     }
