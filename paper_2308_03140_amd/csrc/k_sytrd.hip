@@ -75,14 +75,36 @@ __device__ __forceinline__ Refl<T> refl_scalars(const SytrdWs<T>& w, int b, int 
     return r;
 }
 
-// tiles per work item of the SYMV phase, from the trailing block count
+// Tiles per work item of the SYMV phase: the fewest that keep the launch
+// within `target` workgroups.  Strip c (c = 1 .. nbt tiles long) splits into
+// ceil(c / Kt) work items, nbt = q Kt + r strips in all, so a launch has
+//   nbatch (Kt q (q + 1) / 2 + r (q + 1))
+// workgroups; with the target at the number of workgroups the device holds
+// at once the launch runs in a single round (a second, nearly empty round
+// would cost another full memory latency).
 #define SYTRD_KTMAX 16
+__host__ __device__ __forceinline__ long long sytrd_items(int nbt, int nbatch, int kt) {
+    const long long q = nbt / kt, r = nbt % kt;
+    return ((long long)kt * q * (q + 1) / 2 + r * (q + 1)) * nbatch;
+}
 __host__ __device__ __forceinline__ int sytrd_kt(int nbt, int nbatch, int target) {
-    const long long tiles = (long long)nbt * (nbt + 1) / 2 * nbatch;
-    long long kt = (tiles + target - 1) / target;
-    if (kt < 1) kt = 1;
-    if (kt > SYTRD_KTMAX) kt = SYTRD_KTMAX;
-    return (int)kt;
+    for (int kt = 1; kt < SYTRD_KTMAX; kt++)
+        if (sytrd_items(nbt, nbatch, kt) <= target) return kt;
+    return SYTRD_KTMAX;
+}
+
+// The last columns of a matrix are reduced by one workgroup with the trailing
+// block packed in LDS (sytrd_tail_kernel): M0 columns at most, the largest
+// order whose packed lower triangle and two vectors fit in 160 KB.  The
+// panel path stops at a panel boundary, tail_start, so that the trailing
+// block it leaves has had every panel update applied.
+template <typename T> struct SytrdTail;
+template <> struct SytrdTail<float> { static constexpr int M0 = 256; };
+template <> struct SytrdTail<double> { static constexpr int M0 = 192; };
+template <typename T>
+__host__ __device__ __forceinline__ int sytrd_tail_start(int n) {
+    constexpr int M0 = SytrdTail<T>::M0;
+    return n <= M0 ? 0 : (n - M0 + SYTRD_NBP - 1) / SYTRD_NBP * SYTRD_NBP;
 }
 
 // Accumulators of column i live in parity slot (i & 1).  To keep atomic
@@ -461,6 +483,136 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
 }
 
 // ---------------------------------------------------------------------------
+// tail: unblocked reduction of the trailing block A(k0:n, k0:n), m = n - k0
+// <= M0, one workgroup of 1024 threads per matrix: thread (q, r) = tid / 256,
+// tid % 256 works on row r and on the columns c = q (mod 4), so that each
+// SIMD holds four waves.  The lower triangle is held packed by columns in
+// LDS (column c holds rows c .. m-1).  Per column i: the reflector of
+// x = A(i+1:m, i) with the panel path's convention (beta = -sign(alpha) ||x||,
+// tau = (beta - alpha) / beta, v(i+1) = 1, v(r) = x(r) / (alpha - beta)),
+// y = tau A v over the trailing block, w = y - (tau / 2)(y^T v) v, and the
+// rank-2 update A -= v w^T + w v^T of its lower triangle.  d, e, tau and the
+// reflectors (stored in A below the diagonal) are written as the panel path
+// writes them.
+// ---------------------------------------------------------------------------
+#define SYTRD_TAIL_THREADS 1024
+template <typename T>
+__device__ __forceinline__ T block_sum1024(T v, T* red) {
+    v = wave_sum(v);
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wv] = v;
+    __syncthreads();
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < 16; k++) s += red[k];
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<T> w) {
+    constexpr int M0 = SytrdTail<T>::M0;
+    constexpr int Q = SYTRD_TAIL_THREADS / 256;
+    static_assert(M0 <= 256, "one row per thread of a quarter");
+    __shared__ T L[M0 * (M0 + 1) / 2];
+    __shared__ T vv[M0], ww[M0];
+    __shared__ T yp[Q][M0];
+    __shared__ T red[SYTRD_TAIL_THREADS / 64];
+    const int b = blockIdx.x;
+    const int n = w.ns[b];
+    const int k0 = sytrd_tail_start<T>(n);
+    const int m = n - k0;
+    if (m <= 0) return;
+    T* A = w.A.at(b) + k0 + (long long)k0 * w.A.ld;
+    const long long ld = w.A.ld;
+    const int r = threadIdx.x & 255;
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+    const bool rv = r < m;
+    // start of packed column c
+    auto cs = [m](int c) { return c * m - c * (c - 1) / 2; };
+
+    // load the lower triangle, quarter q taking columns c = q (mod 4), 8
+    // columns per round with the loads issued together from clamped (always
+    // valid) addresses and the values masked afterwards
+    constexpr int U = 8;
+    for (int c0 = q; c0 < m; c0 += Q * U) {
+        T t[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = min(c0 + Q * u, m - 1);
+            const int rr = min(max(r, c), m - 1);
+            t[u] = A[rr + (long long)c * ld];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + Q * u;
+            if (c < m && rv && r >= c) L[cs(c) + r - c] = t[u];
+        }
+    }
+    __syncthreads();
+
+    const int csr = rv ? cs(r) : 0;
+    T* d = w.d + (long long)b * w.sD + k0;
+    T* e = w.e + (long long)b * w.sD + k0;
+    T* tau_o = w.tau + (long long)b * w.sD + k0;
+    for (int i = 0; i + 1 < m; i++) {
+        const int ci = cs(i);
+        const T xr = (r > i && rv) ? L[ci + r - i] : T(0);
+        const T alpha = L[ci + 1];
+        const T xn2 = block_sum1024(q == 0 && r > i + 1 ? xr * xr : T(0), red);
+        T beta, tau, scale;
+        if (xn2 == T(0)) {
+            tau = T(0); beta = alpha; scale = T(0);
+        } else {
+            const T nrm = sqrt(alpha * alpha + xn2);
+            beta = alpha >= T(0) ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scale = T(1) / (alpha - beta);
+        }
+        const T vr = (r == i + 1) ? T(1) : (r > i + 1 && rv ? xr * scale : T(0));
+        if (q == 0) {
+            if (rv) vv[r] = vr;
+            if (r > i && rv) A[r + (long long)i * ld] = vr;
+            if (r == 0) {
+                d[i] = L[ci];
+                e[i] = beta;
+                tau_o[i] = tau;
+            }
+        }
+        __syncthreads();
+        if (tau != T(0)) {
+            // y(r) = tau sum_c A(r, c) v(c) over the trailing block, quarter q
+            // taking c = i + 1 + q, i + 1 + q + 4, ...
+            T ys = T(0);
+            if (r > i && rv) {
+                int c = i + 1 + q, csc = cs(c);
+                for (; c < m; c += Q) {
+                    ys += L[r >= c ? csc + r - c : csr + c - r] * vv[c];
+                    csc += Q * m - Q * c - Q * (Q - 1) / 2;  // cs(c + Q) - cs(c)
+                }
+            }
+            if (rv) yp[q][r] = ys;
+            __syncthreads();
+            const T yr = rv ? tau * ((yp[0][r] + yp[1][r]) + (yp[2][r] + yp[3][r])) : T(0);
+            const T ytv = block_sum1024(q == 0 ? yr * vr : T(0), red);
+            const T wr = yr - T(0.5) * tau * ytv * vr;
+            if (q == 0 && rv) ww[r] = wr;
+            __syncthreads();
+            // A(r, c) -= v(r) w(c) + w(r) v(c), c = i + 1 + q, ... <= r
+            if (r > i && rv) {
+                int c = i + 1 + q, csc = cs(c);
+                for (; c <= r; c += Q) {
+                    L[csc + r - c] -= vr * ww[c] + wr * vv[c];
+                    csc += Q * m - Q * c - Q * (Q - 1) / 2;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) d[m - 1] = L[cs(m - 1)];
+}
+
+// ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 template <typename T, int NBP>
@@ -468,7 +620,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SymvWaves<T
 void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
-    if (i > n - 2) return;
+    if (i > n - 2 || i >= sytrd_tail_start<T>(n)) return;
     const int b0 = (i + 1) >> 6;
     const int nbk = (n + 63) >> 6;
     const int C = b0 + blockIdx.y;
@@ -483,7 +635,7 @@ template <typename T, int NBP>
 __global__ __launch_bounds__(256) void sytrd_finish_kernel(SytrdWs<T> w, int i, int j) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
-    if (i > n - 2) return;
+    if (i > n - 2 || i >= sytrd_tail_start<T>(n)) return;
     const int b0 = (i + 1) >> 6;
     const int nbk = (n + 63) >> 6;
     const int R = b0 + blockIdx.x;
@@ -515,7 +667,7 @@ __global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, 
             const int n = w.ns[b];
             const int C = b0 + strip;
             const int nbk = (n + 63) >> 6;
-            if (i > n - 2 || C >= nbk || q >= (nbk - C + Kt - 1) / Kt) continue;
+            if (i > n - 2 || i >= sytrd_tail_start<T>(n) || C >= nbk || q >= (nbk - C + Kt - 1) / Kt) continue;
             if (b != cur_b) { rf = refl_scalars(w, b, i, n); cur_b = b; }
             symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, &rf);
         }
@@ -525,7 +677,7 @@ __global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, 
             const int b = it / nbt;
             const int R = b0 + (it - b * nbt);
             const int n = w.ns[b];
-            if (i > n - 2 || R >= ((n + 63) >> 6)) continue;
+            if (i > n - 2 || i >= sytrd_tail_start<T>(n) || R >= ((n + 63) >> 6)) continue;
             finish_item<T, NBP>(w, b, n, i, j, R);
         }
         grid.sync();
@@ -551,7 +703,7 @@ struct Syr2kProb {
     __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
         t.batch = bz;
         const int mb = ns[bz] - t0;
-        if (mb <= 0) return false;
+        if (mb <= 0 || t0 - NBP >= sytrd_tail_start<T>(ns[bz])) return false;
         int ti, tj;
         lower_tile(bx, ti, tj);
         t.m0 = ti * TS; t.n0 = tj * TS; t.K = 2 * NBP;
@@ -624,7 +776,10 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
     const bool want_persistent = mode && std::string(mode) == "persistent";
     const int P = want_persistent ? sytrd_persistent_grid<T>() : 0;
     const bool persistent = P > 0;
-    for (int k0 = 0; k0 + 2 <= nmax; k0 += NBP) {
+    // panels up to the tail of the largest matrix (smaller ones drop out of
+    // the per-column kernels at their own tail start)
+    const int kend = sytrd_tail_start<T>(nmax);
+    for (int k0 = 0; k0 < kend && k0 + 2 <= nmax; k0 += NBP) {
         const int k1 = std::min(k0 + NBP, nmax - 1);
         double bytes = 0;
         if (timing)
@@ -707,6 +862,7 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
             }
         }
     }
+    hipLaunchKernelGGL(sytrd_tail_kernel<T>, dim3(nbatch), dim3(SYTRD_TAIL_THREADS), 0, st, w);
 }
 
 template void sytrd_launch<double>(const SytrdWs<double>&, int, int, hipStream_t, const int*, LaunchProfiler*);
