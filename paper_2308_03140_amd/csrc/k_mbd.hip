@@ -178,14 +178,36 @@ void mbd_inv_sqrt_launch(hipStream_t st, const int* ns, int nmax, int nbatch, Ma
 }
 
 // copy the lower triangle to the upper one
-__global__ __launch_bounds__(256) void mbd_mirror_kernel(const int* ns, MatBatch<double> M) {
+// upper triangle := transpose of the lower one, in 64 x 64 tiles: tile
+// (I, J), I >= J, is read by columns (rows and columns clamped into the
+// matrix, so the loads are unconditional), transposed through LDS and
+// written by columns into tile (J, I); only elements below the diagonal are
+// copied.  Matrices whose skip flag is set are left alone.
+__global__ __launch_bounds__(256) void mbd_mirror_kernel(const int* ns, MatBatch<double> M, const int* skip) {
+    __shared__ double tile[64][65];
     const int b = blockIdx.z;
+    if (skip && skip[b]) return;
     const int n = ns[b];
-    const int c = blockIdx.y;
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (c >= n || r >= c) return;
+    const int ti = blockIdx.x, tj = blockIdx.y;
+    const int r0 = ti * 64, c0 = tj * 64;
+    if (tj > ti || r0 >= n) return;
     double* Mb = M.at(b);
-    Mb[r + (long long)c * M.ld] = Mb[c + (long long)r * M.ld];
+    const long long ld = M.ld;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int r = min(r0 + lane, n - 1), c = min(c0 + wv + 4 * k, n - 1);
+        v[k] = Mb[r + (long long)c * ld];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) tile[wv + 4 * k][lane] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int r = r0 + wv + 4 * k, c = c0 + lane;
+        if (r < n && r > c) Mb[c + (long long)r * ld] = tile[lane][wv + 4 * k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -290,8 +312,9 @@ void mbd_invsqrt4_launch(hipStream_t st, const int* ns, int nmax, int nbatch, co
     hipLaunchKernelGGL(mbd_invsqrt4_kernel, dim3((nmax + 255) / 256, nbatch), dim3(256), 0, st, ns, lam, sL, sc);
 }
 
-void mbd_mirror_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> M) {
-    hipLaunchKernelGGL(mbd_mirror_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, M);
+void mbd_mirror_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> M, const int* skip) {
+    const int t = (nmax + 63) / 64;
+    hipLaunchKernelGGL(mbd_mirror_kernel, dim3(t, t, nbatch), dim3(256), 0, st, ns, M, skip);
 }
 
 void mbd_grad_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,

@@ -49,25 +49,29 @@
 #define OA_LINK 4
 #define OA_CP 6  // per-column partials: s2 (then eta), r2, max|R|, |lam|, max|x|, spare
 
+// one workgroup per column (rows in steps of 256): grid (nmax, 1, nbatch)
 __global__ __launch_bounds__(256) void oa_f2d_kernel(const int* ns, MatBatch<float> X32, MatBatch<double> Xd) {
     const int b = blockIdx.z;
     const int n = ns[b];
-    const int c = blockIdx.y;
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (c >= n || r >= n) return;
-    Xd.at(b)[r + (long long)c * Xd.ld] = (double)X32.at(b)[r + (long long)c * X32.ld];
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    const float* src = X32.at(b) + (long long)c * X32.ld;
+    double* dst = Xd.at(b) + (long long)c * Xd.ld;
+    for (int r = threadIdx.x; r < n; r += 256) dst[r] = (double)src[r];
 }
 
-// dst = src; with only_skipped, just for the matrices whose skip flag is set
+// dst = src; with only_skipped, just for the matrices whose skip flag is set;
+// one workgroup per column: grid (nmax, 1, nbatch)
 __global__ __launch_bounds__(256) void copy_mat_kernel(const int* ns, MatBatch<double> src, MatBatch<double> dst,
                                                          const int* only_skipped = nullptr) {
     const int b = blockIdx.z;
     if (only_skipped && !only_skipped[b]) return;
     const int n = ns[b];
-    const int c = blockIdx.y;
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (c >= n || r >= n) return;
-    dst.at(b)[r + (long long)c * dst.ld] = src.at(b)[r + (long long)c * src.ld];
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    const double* sc = src.at(b) + (long long)c * src.ld;
+    double* dc = dst.at(b) + (long long)c * dst.ld;
+    for (int r = threadIdx.x; r < n; r += 256) dc[r] = sc[r];
 }
 
 __global__ void fill_u32_kernel(unsigned* p, int n, unsigned v) {
@@ -84,7 +88,7 @@ __device__ __forceinline__ double sym_lower(const double* G, int ld, int r, int 
 // |lam| and max|X|.  S and G hold their lower triangles, read contiguously.
 __global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
                                                             MatBatch<double> X, double* lam, long long sL,
-                                                            double* colpart, const int* skip) {
+                                                            double* colpart, double* gdiag, const int* skip) {
     __shared__ double red[4];
     const int b = blockIdx.z;
     if (skip && skip[b]) return;
@@ -113,6 +117,7 @@ __global__ __launch_bounds__(256) void oa_colstats_kernel(const int* ns, MatBatc
         const double l = scc / gcc;
         const double rcc = 1.0 - gcc;
         lam[(long long)b * sL + c] = l;
+        gdiag[(long long)b * sL + c] = gcc;
         double* cp = colpart + ((long long)b * sL + c) * OA_CP;
         cp[0] = s2 + (scc - l) * (scc - l);
         cp[1] = r2 + rcc * rcc;
@@ -371,75 +376,119 @@ __global__ __launch_bounds__(64) void oa_rr_kernel(const int* ns, MatBatch<doubl
     }
 }
 
-// E' (in the rotated basis) into Eo; counts unresolved close pairs and
-// accumulates sum_i E'_ij^2 over cross-window i per column j
+// E' (in the rotated basis) into Eo, one workgroup per column j (grid
+// (nmax, 1, nbatch)); counts unresolved close pairs and sums over the rows
+// the column terms below.  S and G hold both triangles (mirrored).  The
+// rotated entries S'_ij = sum_p sum_q W(p, i) S(wi + p, wj + q) W(q, j) are
+// formed in two steps: the column s1 = sum_q W(q, j) S(:, wj + q) (and g1 from
+// G) is built once per chunk of OA_ECH rows, plus the OA_KMAX rows on either
+// side that windows of the chunk's rows can reach, in LDS; each row then
+// applies its own window's coefficients to s1 and g1.
+#define OA_ECH 2048
 __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
                                                      MatBatch<double> Eo, const double* lam, long long sL,
                                                      const int* wstart, const int* wlen, const double* wv,
                                                      const double* stats, unsigned* nclust, double* colpart,
-                                                     const int* skip) {
+                                                     const double* gdiag, const int* skip) {
     __shared__ double red[4];
+    __shared__ double s1[OA_ECH + 2 * OA_KMAX], g1[OA_ECH + 2 * OA_KMAX];
     const int b = blockIdx.z;
     if (skip && skip[b]) return;
     const int n = ns[b];
-    const int j = blockIdx.y;
+    const int j = blockIdx.x;
     if (j >= n) return;
-    if (blockIdx.x * 256 >= n) return;  // uniform: the block holds no row
-    const int i = blockIdx.x * 256 + threadIdx.x;
     const long long o = (long long)b * sL;
+    const double* Sb = S.at(b);
+    const double* Gb = G.at(b);
+    double* Ej = Eo.at(b) + (long long)j * Eo.ld;
+    const int wj = wstart[o + j], kj = wlen[o + j];
+    const double lj = lam[o + j];
+    const double* vj = wv + (o + j) * OA_KMAX;
     // per column j: eta = sum_i E'_ij^2 (cross-window) and the terms of the
     // Rayleigh quotient of the refined column, x_j' = sum_i x'_i (I + E')_ij:
     //   num = S'_jj + sum_i (2 E'_ij S'_ij + E'_ij^2 S'_ii),
     //   den = G'_jj + sum_i (2 E'_ij G'_ij + E'_ij^2 G'_ii)
     double e2 = 0.0, a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
-    if (i < n) {
-        const int wi = wstart[o + i], ki = wlen[o + i];
-        const int wj = wstart[o + j], kj = wlen[o + j];
-        const double* Sb = S.at(b);
-        const double* Gb = G.at(b);
-        double e;
-        if (wi == wj) {
-            if (ki == 1) {  // i == j, single-column window
-                const double gjj = Gb[j + (long long)j * G.ld], sjj = Sb[j + (long long)j * S.ld];
-                e = 0.5 * (1.0 - gjj);
-                a1 = 2.0 * e * sjj;
-                a2 = e * e * sjj;
-                b1 = 2.0 * e * gjj;
-                b2 = e * e * gjj;
-            } else {
-                e = 0.0;
-            }
-        } else {
-            const double* vi = wv + (o + i) * OA_KMAX;
-            const double* vj = wv + (o + j) * OA_KMAX;
-            double sp = 0.0, gp = 0.0;
+    for (int r0 = 0; r0 < n; r0 += OA_ECH) {
+        const int lo = max(0, r0 - OA_KMAX), hi = min(n, r0 + OA_ECH + OA_KMAX);
+        __syncthreads();  // the previous chunk's readers are done
+        for (int r = lo + threadIdx.x; r < hi; r += 256) {
+            double sv = 0.0, gv = 0.0;
             for (int q = 0; q < kj; q++) {
-                const double cj = kj == 1 ? 1.0 : vj[q];
-                double ts = 0.0, tg = 0.0;
-                for (int p = 0; p < ki; p++) {
-                    const double ci = ki == 1 ? 1.0 : vi[p];
-                    ts += ci * sym_lower(Sb, S.ld, wi + p, wj + q);
-                    tg += ci * sym_lower(Gb, G.ld, wi + p, wj + q);
-                }
-                sp += ts * cj;
-                gp += tg * cj;
+                const double cq = kj == 1 ? 1.0 : vj[q];
+                sv += cq * Sb[r + (long long)(wj + q) * S.ld];
+                gv += cq * Gb[r + (long long)(wj + q) * G.ld];
             }
-            const double li = lam[o + i], lj = lam[o + j];
-            const double dl = lj - li;
-            if (fabs(dl) > 64.0 * num_limits<double>::eps * fmax(fabs(li), fabs(lj))) {
-                e = (sp - lj * gp) / dl;
-            } else {
-                e = -0.5 * gp;
-                if (i < j) atomicAdd(&nclust[b], 1u);
-            }
-            e2 = e * e;
-            const double gii = ki == 1 ? Gb[i + (long long)i * G.ld] : 1.0;
-            a1 = 2.0 * e * sp;
-            a2 = e2 * li * gii;
-            b1 = 2.0 * e * gp;
-            b2 = e2 * gii;
+            s1[r - lo] = sv;
+            g1[r - lo] = gv;
         }
-        Eo.at(b)[i + (long long)j * Eo.ld] = e;
+        __syncthreads();
+        const int rend = min(n, r0 + OA_ECH);
+        // four rows per thread and round, their loads issued together (rows
+        // clamped into the chunk, results of rows past its end discarded)
+        constexpr int RU = 4;
+        for (int i0 = r0 + threadIdx.x; i0 < rend; i0 += RU * 256) {
+            int wiu[RU], kiu[RU];
+            double liu[RU], gdu[RU];
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                const int i = min(i0 + 256 * u, rend - 1);
+                wiu[u] = wstart[o + i];
+                kiu[u] = wlen[o + i];
+                liu[u] = lam[o + i];
+                gdu[u] = gdiag[o + i];
+            }
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                const int i = i0 + 256 * u;
+                if (i >= rend) continue;
+                const int wi = wiu[u], ki = kiu[u];
+                double e;
+                if (wi == wj) {
+                    if (ki == 1) {  // i == j, single-column window
+                        const double gjj = g1[i - lo], sjj = s1[i - lo];
+                        e = 0.5 * (1.0 - gjj);
+                        a1 += 2.0 * e * sjj;
+                        a2 += e * e * sjj;
+                        b1 += 2.0 * e * gjj;
+                        b2 += e * e * gjj;
+                    } else {
+                        e = 0.0;
+                    }
+                } else {
+                    double sp, gp;
+                    if (ki == 1) {
+                        sp = s1[i - lo];
+                        gp = g1[i - lo];
+                    } else {
+                        const double* vi = wv + (o + i) * OA_KMAX;
+                        sp = 0.0;
+                        gp = 0.0;
+                        for (int p = 0; p < ki; p++) {
+                            const double cp_ = vi[p];
+                            sp += cp_ * s1[wi + p - lo];
+                            gp += cp_ * g1[wi + p - lo];
+                        }
+                    }
+                    const double li = liu[u];
+                    const double dl = lj - li;
+                    if (fabs(dl) > 64.0 * num_limits<double>::eps * fmax(fabs(li), fabs(lj))) {
+                        e = (sp - lj * gp) / dl;
+                    } else {
+                        e = -0.5 * gp;
+                        if (i < j) atomicAdd(&nclust[b], 1u);
+                    }
+                    const double ee = e * e;
+                    const double gii = ki == 1 ? gdu[u] : 1.0;
+                    e2 += ee;
+                    a1 += 2.0 * e * sp;
+                    a2 += ee * li * gii;
+                    b1 += 2.0 * e * gp;
+                    b2 += ee * gii;
+                }
+                Ej[i] = e;
+            }
+        }
     }
     e2 = block_sum256(e2, red);
     a1 = block_sum256(a1, red);
@@ -447,12 +496,13 @@ __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<doubl
     b1 = block_sum256(b1, red);
     b2 = block_sum256(b2, red);
     if (threadIdx.x == 0) {
+        // zeroed by the delta and window passes; this workgroup is the only writer
         double* cp = colpart + (o + j) * OA_CP;
-        atomicAdd(&cp[0], e2);
-        atomicAdd(&cp[1], a1);
-        atomicAdd(&cp[2], a2);
-        atomicAdd(&cp[3], b1);
-        atomicAdd(&cp[5], b2);
+        cp[0] = e2;
+        cp[1] = a1;
+        cp[2] = a2;
+        cp[3] = b1;
+        cp[5] = b2;
     }
 }
 
@@ -467,23 +517,25 @@ __global__ __launch_bounds__(256) void oa_f_kernel(const int* ns, MatBatch<doubl
     const int b = blockIdx.z;
     if (skip && skip[b]) return;
     const int n = ns[b];
-    const int j = blockIdx.y;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n || i >= n) return;
+    const int j = blockIdx.x;
+    if (j >= n) return;
     const long long o = (long long)b * sL;
-    const int wi = wstart[o + i], ki = wlen[o + i];
-    const double* Eb = Ei.at(b);
-    double f;
-    if (ki == 1) {
-        f = Eb[i + (long long)j * Ei.ld];
-    } else {
-        const int p = i - wi;
-        f = (wstart[o + j] == wi) ? wv[(o + j) * OA_KMAX + p] - (i == j ? 1.0 : 0.0) : 0.0;
-        for (int a = 0; a < ki; a++) f += wv[(o + wi + a) * OA_KMAX + p] * Eb[(wi + a) + (long long)j * Ei.ld];
-    }
+    const double* Ej = Ei.at(b) + (long long)j * Ei.ld;
+    double* Fj = Fo.at(b) + (long long)j * Fo.ld;
+    const int wsj = wstart[o + j];
     const double d = 1.0 / sqrt(1.0 + colpart[(o + j) * OA_CP]);
-    f = f * d + (i == j ? d - 1.0 : 0.0);
-    Fo.at(b)[i + (long long)j * Fo.ld] = f;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int wi = wstart[o + i], ki = wlen[o + i];
+        double f;
+        if (ki == 1) {
+            f = Ej[i];
+        } else {
+            const int p = i - wi;
+            f = (wsj == wi) ? wv[(o + j) * OA_KMAX + p] - (i == j ? 1.0 : 0.0) : 0.0;
+            for (int a = 0; a < ki; a++) f += wv[(o + wi + a) * OA_KMAX + p] * Ej[wi + a];
+        }
+        Fj[i] = f * d + (i == j ? d - 1.0 : 0.0);
+    }
 }
 
 // rho = max_c eta_c max|x_c|^2 / sqrt(lam_c) -> stats[4b+2]; next[b] = 1
@@ -519,12 +571,12 @@ __global__ __launch_bounds__(256) void oa_next_kernel(const int* ns, const doubl
 }
 
 void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd) {
-    hipLaunchKernelGGL(oa_f2d_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, X32, Xd);
+    hipLaunchKernelGGL(oa_f2d_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, X32, Xd);
 }
 
 void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> src,
                      MatBatch<double> dst) {
-    hipLaunchKernelGGL(copy_mat_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, src, dst);
+    hipLaunchKernelGGL(copy_mat_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, src, dst);
 }
 
 void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v) {
@@ -536,7 +588,7 @@ size_t oa_colpart_doubles(int nmax, int nbatch) { return (size_t)nbatch * nmax *
 void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> Q, MatBatch<double> X,
                     MatBatch<double> T1, MatBatch<double> T2, MatBatch<double> G, double* lam, long long sL,
                     const OaWork& w, double* stats, const int* skip, int* next) {
-    const dim3 ge((nmax + 255) / 256, nmax, nbatch);
+    const dim3 gc(nmax, 1, nbatch);  // one workgroup per column
     gemm_batched<double>(st, false, false, ns, nmax, nbatch, Q.p, Q.ld, Q.stride, X.p, X.ld, X.stride, T1.p,
                          T1.ld, T1.stride, 1.0, 0.0, false, skip);                             // T1 = Q X
     gemm_batched<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T1.p, T1.ld, T1.stride, T2.p,
@@ -544,22 +596,25 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
     gemm_batched<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, X.p, X.ld, X.stride, G.p, G.ld,
                          G.stride, 1.0, 0.0, true, skip);                                      // G = X^T X
     hipLaunchKernelGGL(oa_colstats_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, T2, G, X, lam, sL,
-                       w.colpart, skip);
+                       w.colpart, w.gdiag, skip);
     hipLaunchKernelGGL(oa_delta_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, sL, stats, w.nclust, skip);
     hipLaunchKernelGGL(oa_windows_kernel, dim3(nbatch), dim3(256), 0, st, ns, T2, G, lam, sL, w.colpart, w.wstart,
                        w.wlen, skip);
     hipLaunchKernelGGL(oa_rr_kernel, dim3(nmax, 1, nbatch), dim3(64), 0, st, ns, T2, G, lam, sL, w.wstart,
                        w.wlen, w.wv, skip);
-    hipLaunchKernelGGL(oa_e_kernel, ge, dim3(256), 0, st, ns, T2, G, T1, lam, sL, w.wstart, w.wlen, w.wv, stats,
-                       w.nclust, w.colpart, skip);                                             // E' -> T1
-    hipLaunchKernelGGL(oa_f_kernel, ge, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, w.colpart,
+    // both triangles of S and G for the column-contiguous reads of the E' pass
+    mbd_mirror_launch(st, ns, nmax, nbatch, T2, skip);
+    mbd_mirror_launch(st, ns, nmax, nbatch, G, skip);
+    hipLaunchKernelGGL(oa_e_kernel, gc, dim3(256), 0, st, ns, T2, G, T1, lam, sL, w.wstart, w.wlen, w.wv, stats,
+                       w.nclust, w.colpart, w.gdiag, skip);                                    // E' -> T1
+    hipLaunchKernelGGL(oa_f_kernel, gc, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, w.colpart,
                        skip);                                                                  // F -> T2
     hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats, skip,
                        next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
     gemm_batched<double>(st, false, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T2.p, T2.ld, T2.stride, T1.p,
                          T1.ld, T1.stride, 1.0, 1.0, false, skip, X.p, X.ld, X.stride);        // T1 = X + X F
     // a matrix that skips this step passes X through unchanged
-    if (skip) hipLaunchKernelGGL(copy_mat_kernel, ge, dim3(256), 0, st, ns, X, T1, skip);
+    if (skip) hipLaunchKernelGGL(copy_mat_kernel, gc, dim3(256), 0, st, ns, X, T1, skip);
 }
 
 // symmetric pseudo-random test matrix (autotuner input): A_rc = A_cr in [-1, 1)

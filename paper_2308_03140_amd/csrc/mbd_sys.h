@@ -38,7 +38,8 @@ void mbd_invsqrt4_launch(hipStream_t st, const int* ns, int nmax, int nbatch, co
 // lower triangle of M = X diag(sc)^2 X^T; the columns of X are scaled in place
 void mbd_inv_sqrt_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> X,
                          const double* sc, long long sL, MatBatch<double> M);
-void mbd_mirror_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> M);
+void mbd_mirror_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> M,
+                       const int* skip = nullptr);
 void mbd_grad_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,
                             const double* cc, MatBatch<double> M);
 
@@ -50,6 +51,7 @@ struct OaWork {
     int* wstart;      // [nbatch][nmax] first column of each column's window
     int* wlen;        // [nbatch][nmax] window length
     double* wv;       // [nbatch][nmax][OA_KMAX] window rotation, per column
+    double* gdiag;    // [nbatch][nmax] diagonal of X^T X
     double rho_next;  // second-step threshold on the remainder estimate (<= 0: default)
 };
 size_t oa_colpart_doubles(int nmax, int nbatch);
