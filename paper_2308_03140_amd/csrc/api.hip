@@ -500,9 +500,9 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
             !stats || !skip2 || !skip3)
             return (mbd_status)c->err_code;
         oa_f2d_launch(st, ns_dev, nmax, nmat, X32, Xd);
-        oa_step_launch(st, ns_dev, nmax, nmat, A64, Xd, Y, S, G, lam, nmax, ow, stats, nullptr, skip2);  // X1 in Y
+        oa_step_launch(st, ns_dev, nmax, nmat, A64, Xd, Y, S, G, lam, nmax, ow, stats, nullptr, skip2, X32);  // X1 in Y
         oa_step_launch(st, ns_dev, nmax, nmat, A64, Y, S, Xd, G, lam, nmax, ow, stats + 4 * nmat, skip2,
-                       skip3);                                                                   // X2 in S
+                       skip3, MatBatch<float>{nullptr, 0, 0});                                                                   // X2 in S
         skip_dev = skip2;
         HIPCHK(hipGetLastError(), "refine");
         X = S;

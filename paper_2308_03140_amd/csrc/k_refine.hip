@@ -36,6 +36,7 @@
 // decision stays on the device (per-matrix skip flags), so captured launch
 // graphs remain valid.
 #include "mbd_internal.h"
+#include "gemm_mfma.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
 
@@ -538,6 +539,129 @@ __global__ __launch_bounds__(256) void oa_f_kernel(const int* ns, MatBatch<doubl
     }
 }
 
+// Update of the first step, whose X holds the FP32 eigenvectors exactly:
+// F = F_blk + F_small, with
+//   F_blk   the entries inside multi-column windows, (W - I)_ij d_j +
+//           delta_ij (d_j - 1): order one (the Rayleigh-Ritz rotations);
+//   F_small everything else, (W E')_ij d_j and the single-window diagonal
+//           E'_jj d_j + (d_j - 1): at most the linear correction's size.
+// X + X F_blk is formed exactly in FP64 (at most OA_KMAX columns per output
+// column); X F_small = X32 fl32(F_small) runs on the FP32 matrix cores and is
+// added in FP64.  Its rounding error, about 6e-8 |F_small| relative, stays
+// far below the step's second-order remainder |F_small|^2 and the element
+// error it leaves in Q^{-1/2}.
+__global__ __launch_bounds__(256) void oa_fsmall_kernel(const int* ns, MatBatch<double> Ei, MatBatch<float> Fs,
+                                                          long long sL, const int* wstart, const int* wlen,
+                                                          const double* wv, const double* colpart, const int* skip) {
+    const int b = blockIdx.z;
+    if (skip && skip[b]) return;
+    const int n = ns[b];
+    const int j = blockIdx.x;
+    if (j >= n) return;
+    const long long o = (long long)b * sL;
+    const double* Ej = Ei.at(b) + (long long)j * Ei.ld;
+    float* Fj = Fs.at(b) + (long long)j * Fs.ld;
+    const int wsj = wstart[o + j];
+    const double d = 1.0 / sqrt(1.0 + colpart[(o + j) * OA_CP]);
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int wi = wstart[o + i], ki = wlen[o + i];
+        double f;
+        if (ki == 1) {
+            f = Ej[i] * d + (i == j ? d - 1.0 : 0.0);
+        } else if (wi == wsj) {
+            f = 0.0;  // inside column j's window: F_blk
+        } else {
+            const int p = i - wi;
+            f = 0.0;
+            for (int a = 0; a < ki; a++) f += wv[(o + wi + a) * OA_KMAX + p] * Ej[wi + a];
+            f *= d;
+        }
+        Fj[i] = (float)f;
+    }
+}
+
+// T1 = X + X F_blk, one workgroup per column j
+__global__ __launch_bounds__(256) void oa_fblock_kernel(const int* ns, MatBatch<double> X, MatBatch<double> T1,
+                                                          long long sL, const int* wstart, const int* wlen,
+                                                          const double* wv, const double* colpart, const int* skip) {
+    const int b = blockIdx.z;
+    if (skip && skip[b]) return;
+    const int n = ns[b];
+    const int j = blockIdx.x;
+    if (j >= n) return;
+    const long long o = (long long)b * sL;
+    const int wsj = wstart[o + j], kj = wlen[o + j];
+    const double* Xb = X.at(b);
+    double* Tj = T1.at(b) + (long long)j * T1.ld;
+    const double* Xj = Xb + (long long)j * X.ld;
+    if (kj == 1) {
+        for (int r = threadIdx.x; r < n; r += 256) Tj[r] = Xj[r];
+        return;
+    }
+    const double d = 1.0 / sqrt(1.0 + colpart[(o + j) * OA_CP]);
+    const double* vj = wv + (o + j) * OA_KMAX;
+    for (int r = threadIdx.x; r < n; r += 256) {
+        double t = Xj[r];
+        for (int p = 0; p < kj; p++) {
+            const int i = wsj + p;
+            const double fb = (vj[p] - (i == j ? 1.0 : 0.0)) * d + (i == j ? d - 1.0 : 0.0);
+            t += Xb[r + (long long)i * X.ld] * fb;
+        }
+        Tj[r] = t;
+    }
+}
+
+// T1 += X32 F_small: FP32 operands on the matrix cores, FP64 accumulation of
+// the result into T1
+template <int TS>
+struct XfSmallProb {
+    static constexpr bool A_M_CONTIG = true;
+    static constexpr bool B_N_CONTIG = false;
+    MatBatch<float> X; MatBatch<float> F; MatBatch<double> C; const int* ns; const int* skip; int tiles_n;
+    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
+        t.batch = bz;
+        if (skip && skip[bz]) return false;
+        const int n = ns[bz];
+        int ti, tj;
+        band_tile(xcd_virtual(bx, gridDim.x), tiles_n, tiles_n, ti, tj);
+        t.m0 = ti * TS; t.n0 = tj * TS; t.K = n;
+        return t.m0 < n && t.n0 < n;
+    }
+    __device__ float a(const GemmTile& t, int m, int k) const {
+        const int n = ns[t.batch];
+        if (m >= n || k >= n) return 0.0f;
+        return X.at(t.batch)[m + (long long)k * X.ld];
+    }
+    __device__ float b(const GemmTile& t, int k, int c) const {
+        const int n = ns[t.batch];
+        if (k >= n || c >= n) return 0.0f;
+        return F.at(t.batch)[k + (long long)c * F.ld];
+    }
+    __device__ void store(const GemmTile& t, int m, int c, float v) const {
+        const int n = ns[t.batch];
+        if (m >= n || c >= n) return;
+        C.at(t.batch)[m + (long long)c * C.ld] += (double)v;
+    }
+};
+
+static void xf_small_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32,
+                            MatBatch<float> Fs, MatBatch<double> T1, const int* skip) {
+    if (nmax >= GEMM_TS128_MIN_ORDER) {
+        typedef Gemm128Shape<float> S;
+        XfSmallProb<128> p;
+        p.X = X32; p.F = Fs; p.C = T1; p.ns = ns; p.skip = skip;
+        p.tiles_n = (nmax + 127) / 128;
+        hipLaunchKernelGGL((gemm_mfma_kernel<float, XfSmallProb<128>, 128, 128, S::BK, S::WM, S::WN>),
+                           dim3(p.tiles_n * p.tiles_n, 1, nbatch), dim3(64 * S::WM * S::WN), 0, st, p);
+    } else {
+        XfSmallProb<64> p;
+        p.X = X32; p.F = Fs; p.C = T1; p.ns = ns; p.skip = skip;
+        p.tiles_n = (nmax + 63) / 64;
+        hipLaunchKernelGGL((gemm_mfma_kernel<float, XfSmallProb<64>>), dim3(p.tiles_n * p.tiles_n, 1, nbatch),
+                           dim3(256), 0, st, p);
+    }
+}
+
 // rho = max_c eta_c max|x_c|^2 / sqrt(lam_c) -> stats[4b+2]; next[b] = 1
 // (skip the next step) unless rho > the threshold; lam <- Rayleigh quotients
 // of the refined columns
@@ -587,7 +711,7 @@ size_t oa_colpart_doubles(int nmax, int nbatch) { return (size_t)nbatch * nmax *
 
 void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> Q, MatBatch<double> X,
                     MatBatch<double> T1, MatBatch<double> T2, MatBatch<double> G, double* lam, long long sL,
-                    const OaWork& w, double* stats, const int* skip, int* next) {
+                    const OaWork& w, double* stats, const int* skip, int* next, MatBatch<float> X32) {
     const dim3 gc(nmax, 1, nbatch);  // one workgroup per column
     gemm_batched<double>(st, false, false, ns, nmax, nbatch, Q.p, Q.ld, Q.stride, X.p, X.ld, X.stride, T1.p,
                          T1.ld, T1.stride, 1.0, 0.0, false, skip);                             // T1 = Q X
@@ -607,12 +731,25 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
     mbd_mirror_launch(st, ns, nmax, nbatch, G, skip);
     hipLaunchKernelGGL(oa_e_kernel, gc, dim3(256), 0, st, ns, T2, G, T1, lam, sL, w.wstart, w.wlen, w.wv, stats,
                        w.nclust, w.colpart, w.gdiag, skip);                                    // E' -> T1
-    hipLaunchKernelGGL(oa_f_kernel, gc, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, w.colpart,
-                       skip);                                                                  // F -> T2
-    hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats, skip,
-                       next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
-    gemm_batched<double>(st, false, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T2.p, T2.ld, T2.stride, T1.p,
-                         T1.ld, T1.stride, 1.0, 1.0, false, skip, X.p, X.ld, X.stride);        // T1 = X + X F
+    if (X32.p) {
+        // X is the FP32 eigenvectors: T1 = X + X F_blk (FP64), then
+        // T1 += X32 fl32(F_small) on the FP32 matrix cores; F_small in T2's memory
+        const MatBatch<float> Fs = {(float*)T2.p, T2.ld, 2 * T2.stride};
+        hipLaunchKernelGGL(oa_fsmall_kernel, gc, dim3(256), 0, st, ns, T1, Fs, sL, w.wstart, w.wlen, w.wv,
+                           w.colpart, skip);                                                   // F_small -> T2
+        hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats,
+                           skip, next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
+        hipLaunchKernelGGL(oa_fblock_kernel, gc, dim3(256), 0, st, ns, X, T1, sL, w.wstart, w.wlen, w.wv,
+                           w.colpart, skip);                                                   // T1 = X + X F_blk
+        xf_small_launch(st, ns, nmax, nbatch, X32, Fs, T1, skip);                              // T1 += X F_small
+    } else {
+        hipLaunchKernelGGL(oa_f_kernel, gc, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, w.colpart,
+                           skip);                                                              // F -> T2
+        hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats,
+                           skip, next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
+        gemm_batched<double>(st, false, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T2.p, T2.ld, T2.stride, T1.p,
+                             T1.ld, T1.stride, 1.0, 1.0, false, skip, X.p, X.ld, X.stride);    // T1 = X + X F
+    }
     // a matrix that skips this step passes X through unchanged
     if (skip) hipLaunchKernelGGL(copy_mat_kernel, gc, dim3(256), 0, st, ns, X, T1, skip);
 }

@@ -58,10 +58,12 @@ size_t oa_colpart_doubles(int nmax, int nbatch);
 void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd);
 // X (in) -> T1 (out, refined); T2 and G are scratch; stats[4b..4b+3] =
 // {delta, max|I - X^T X|, rho, max|X|}; next[b] = 1 where no further step is
-// needed; matrices with skip[b] != 0 get T1 = X and keep lam
+// needed; matrices with skip[b] != 0 get T1 = X and keep lam.  X32.p != nullptr
+// states that X holds exactly the FP32 matrix X32, whose products the update
+// then runs on the FP32 matrix cores
 void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> Q, MatBatch<double> X,
                     MatBatch<double> T1, MatBatch<double> T2, MatBatch<double> G, double* lam, long long sL,
-                    const OaWork& w, double* stats, const int* skip, int* next);
+                    const OaWork& w, double* stats, const int* skip, int* next, MatBatch<float> X32);
 void copy_mat_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> src,
                      MatBatch<double> dst);
 void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v);
