@@ -285,32 +285,31 @@ struct GemmGeneral {
     int lower_only;      // only tiles (and elements) with row >= col
     int tiles_n;         // tiles along N (grid.x = tiles_m * tiles_n, or lower count)
     const int* skip;     // optional per-matrix flag: nonzero skips the matrix
+    // the orders travel in the tile (t.o = M, t.k = N, t.K = K), read once
     __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
         if (skip && skip[bz]) return false;
-        int Mb = ns ? ns[bz] : M, Nb = ns ? ns[bz] : N, Kb = ns ? ns[bz] : K;
+        const int Mb = ns ? ns[bz] : M, Nb = ns ? ns[bz] : N, Kb = ns ? ns[bz] : K;
         int ti, tj;
         const int v = xcd_virtual(bx, gridDim.x);
         if (lower_only) band_lower_tile(v, tiles_n, ti, tj);
         else band_tile(v, tiles_n, tiles_n, ti, tj);
         t.m0 = ti * TS; t.n0 = tj * TS; t.K = Kb;
+        t.o = Mb; t.k = Nb;
         return t.m0 < Mb && t.n0 < Nb;
     }
     __device__ T a(const GemmTile& t, int m, int k) const {
-        int Mb = ns ? ns[t.batch] : M, Kb = t.K;
-        if (m >= Mb || k >= Kb) return T(0);
+        if (m >= t.o || k >= t.K) return T(0);
         const T* Ab = A + (long long)t.batch * sA;
         return TA ? Ab[k + (long long)m * lda] : Ab[m + (long long)k * lda];
     }
     __device__ T b(const GemmTile& t, int k, int n) const {
-        int Nb = ns ? ns[t.batch] : N, Kb = t.K;
-        if (n >= Nb || k >= Kb) return T(0);
+        if (n >= t.k || k >= t.K) return T(0);
         const T* Bb = B + (long long)t.batch * sB;
         return TB ? Bb[n + (long long)k * ldb] : Bb[k + (long long)n * ldb];
     }
     __device__ void store(const GemmTile& t, int m, int n, T v) const {
-        int Mb = ns ? ns[t.batch] : M, Nb = ns ? ns[t.batch] : N;
-        if (m >= Mb || n >= Nb) return;
+        if (m >= t.o || n >= t.k) return;
         if (lower_only && m < n) return;
         T* Cb = C + (long long)t.batch * sC + m + (long long)n * ldc;
         if (beta == T(0)) { *Cb = alpha * v; return; }

@@ -33,6 +33,7 @@ struct VtvProb {
     // grid: x = reflector block, y = row chunk, z = matrix; t.k = x*nsplit + y
     __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
+        t.e0 = ns[bz];  // order, read once
         const int n = ns[bz];
         const int nref = n - 1;
         const int b0 = bx * 64;
@@ -49,7 +50,7 @@ struct VtvProb {
     __device__ T a(const GemmTile& t, int jj, int kk) const {
         if (kk >= t.K) return T(0);
         const int b0 = (t.k / nsplit) * 64;
-        return hh_v(A.at(t.batch), A.ld, t.o + kk, b0 + jj, ns[t.batch] - 1);
+        return hh_v(A.at(t.batch), A.ld, t.o + kk, b0 + jj, t.e0 - 1);
     }
     __device__ T b(const GemmTile& t, int kk, int jj) const { return a(t, jj, kk); }
     __device__ void store(const GemmTile& t, int m, int nn, T v) const {
@@ -113,6 +114,7 @@ struct VtxProb {
     MatBatch<T> A; MatBatch<T> X; const int* ns; int b0; T* Ypart; long long sYp; int nmax;
     __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
+        t.e0 = ns[bz];  // order, read once
         const int n = ns[bz];
         if (b0 >= n - 1) return false;
         const int m = n - b0 - 1;
@@ -128,14 +130,14 @@ struct VtxProb {
     }
     __device__ T a(const GemmTile& t, int jj, int kk) const {
         if (kk >= t.K) return T(0);
-        return hh_v(A.at(t.batch), A.ld, t.o + kk, b0 + jj, ns[t.batch] - 1);
+        return hh_v(A.at(t.batch), A.ld, t.o + kk, b0 + jj, t.e0 - 1);
     }
     __device__ T b(const GemmTile& t, int kk, int c) const {
-        if (kk >= t.K || c >= ns[t.batch]) return T(0);
+        if (kk >= t.K || c >= t.e0) return T(0);
         return X.at(t.batch)[(t.o + kk) + (long long)c * X.ld];
     }
     __device__ void store(const GemmTile& t, int jj, int c, T v) const {
-        if (c >= ns[t.batch]) return;
+        if (c >= t.e0) return;
         Ypart[(long long)t.batch * sYp + (long long)t.k * 64 * nmax + jj + (long long)c * 64] = v;
     }
 };
@@ -149,6 +151,7 @@ struct VtProb {
     MatBatch<T> A; const int* ns; const T* Tm; long long sT; T* VT; long long sVT; int nmax;
     __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
+        t.e0 = ns[bz];  // order, read once
         const int n = ns[bz];
         const int b0 = by * 64;
         if (b0 >= n - 1) return false;
@@ -162,7 +165,7 @@ struct VtProb {
     }
     __device__ T a(const GemmTile& t, int mm, int kk) const {
         if (mm >= t.k) return T(0);
-        return hh_v(A.at(t.batch), A.ld, t.o + 1 + mm, t.o + kk, ns[t.batch] - 1);
+        return hh_v(A.at(t.batch), A.ld, t.o + 1 + mm, t.o + kk, t.e0 - 1);
     }
     __device__ T b(const GemmTile& t, int kk, int jj) const {
         return Tm[(long long)t.batch * sT + (long long)(t.o / 64) * 4096 + kk + jj * 64];
@@ -210,6 +213,7 @@ struct VyProb {
     MatBatch<T> X; const int* ns; int b0; const T* VT; long long sVT; int nmax; const T* Y; long long sY; int tiles_n;
     __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
         t.batch = bz;
+        t.e0 = ns[bz];  // order, read once
         const int n = ns[bz];
         if (b0 >= n - 1) return false;
         t.m0 = b0 + (bx / tiles_n) * TS;
@@ -218,21 +222,21 @@ struct VyProb {
         return t.m0 < n && t.n0 < n;
     }
     __device__ T a(const GemmTile& t, int r, int jj) const {
-        if (r <= b0 || r >= ns[t.batch]) return T(0);
+        if (r <= b0 || r >= t.e0) return T(0);
         return VT[(long long)t.batch * sVT + (long long)(b0 / 64) * 64 * nmax + (long long)jj * nmax + (r - b0 - 1)];
     }
     __device__ T b(const GemmTile& t, int jj, int c) const {
-        if (c >= ns[t.batch]) return T(0);
+        if (c >= t.e0) return T(0);
         return Y[(long long)t.batch * sY + jj + (long long)c * 64];
     }
     __device__ Vec epi_load(const GemmTile& t, int r, int c) const {
-        const int n = ns[t.batch];
+        const int n = t.e0;
         if (r >= n || c >= n) return Vec{};
         // r + RPL - 1 < ld: the run stays inside the padded column
         return *reinterpret_cast<const Vec*>(X.at(t.batch) + r + (long long)c * X.ld);
     }
     __device__ void epi_store(const GemmTile& t, int r, int c, Vec acc, Vec cin) const {
-        const int n = ns[t.batch];
+        const int n = t.e0;
         if (r >= n || c >= n) return;
         T* x = X.at(t.batch) + r + (long long)c * X.ld;
         if (r > b0 && r + RPL <= n) {

@@ -620,6 +620,7 @@ struct XfSmallProb {
     MatBatch<float> X; MatBatch<float> F; MatBatch<double> C; const int* ns; const int* skip; int tiles_n;
     __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
         t.batch = bz;
+        t.e0 = ns[bz];  // order, read once
         if (skip && skip[bz]) return false;
         const int n = ns[bz];
         int ti, tj;
@@ -628,17 +629,17 @@ struct XfSmallProb {
         return t.m0 < n && t.n0 < n;
     }
     __device__ float a(const GemmTile& t, int m, int k) const {
-        const int n = ns[t.batch];
+        const int n = t.e0;
         if (m >= n || k >= n) return 0.0f;
         return X.at(t.batch)[m + (long long)k * X.ld];
     }
     __device__ float b(const GemmTile& t, int k, int c) const {
-        const int n = ns[t.batch];
+        const int n = t.e0;
         if (k >= n || c >= n) return 0.0f;
         return F.at(t.batch)[k + (long long)c * F.ld];
     }
     __device__ void store(const GemmTile& t, int m, int c, float v) const {
-        const int n = ns[t.batch];
+        const int n = t.e0;
         if (m >= n || c >= n) return;
         C.at(t.batch)[m + (long long)c * C.ld] += (double)v;
     }

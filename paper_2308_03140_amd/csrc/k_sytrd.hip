@@ -702,6 +702,7 @@ struct Syr2kProb {
     int t0;
     __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
         t.batch = bz;
+        t.e0 = ns[bz];  // order, read once
         const int mb = ns[bz] - t0;
         if (mb <= 0 || t0 - NBP >= sytrd_tail_start<T>(ns[bz])) return false;
         int ti, tj;
@@ -711,23 +712,23 @@ struct Syr2kProb {
     }
     __device__ T a(const GemmTile& t, int m, int k) const {
         const int r = t0 + m;
-        if (r >= ns[t.batch]) return T(0);
+        if (r >= t.e0) return T(0);
         const long long o = (long long)t.batch * sP + r;
         return k < NBP ? Vp[o + (long long)k * ldp] : Wp[o + (long long)(k - NBP) * ldp];
     }
     __device__ T b(const GemmTile& t, int k, int nn) const {
         const int c = t0 + nn;
-        if (c >= ns[t.batch]) return T(0);
+        if (c >= t.e0) return T(0);
         const long long o = (long long)t.batch * sP + c;
         return k < NBP ? Wp[o + (long long)k * ldp] : Vp[o + (long long)(k - NBP) * ldp];
     }
     __device__ Vec epi_load(const GemmTile& t, int m, int nn) const {
-        const int r = t0 + m, c = t0 + nn, nb_ = ns[t.batch];
+        const int r = t0 + m, c = t0 + nn, nb_ = t.e0;
         if (r >= nb_ || c >= nb_ || r + RPL <= c) return Vec{};
         return *reinterpret_cast<const Vec*>(A.at(t.batch) + r + (long long)c * A.ld);
     }
     __device__ void epi_store(const GemmTile& t, int m, int nn, Vec acc, Vec cin) const {
-        const int r = t0 + m, c = t0 + nn, nb_ = ns[t.batch];
+        const int r = t0 + m, c = t0 + nn, nb_ = t.e0;
         if (r >= nb_ || c >= nb_ || r + RPL <= c) return;
         T* a = A.at(t.batch) + r + (long long)c * A.ld;
         if (r >= c && r + RPL <= nb_) {
