@@ -54,6 +54,10 @@ template <class P, class = void> struct gemm_epi_vec : std::false_type {};
 template <class P>
 struct gemm_epi_vec<P, std::void_t<decltype(P::EPI_VEC)>> : std::integral_constant<bool, P::EPI_VEC> {};
 
+template <class P, class = void> struct gemm_k_uniform : std::false_type {};
+template <class P>
+struct gemm_k_uniform<P, std::void_t<decltype(P::K_UNIFORM)>> : std::integral_constant<bool, P::K_UNIFORM> {};
+
 // Tile descriptor returned by P::tile()
 struct GemmTile {
     int batch, m0, n0, K;
@@ -105,13 +109,24 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_mfma_kernel(P p) {
         for (int j = 0; j < NJ; j++) acc[i][j] = typename mfma4<T>::v{0, 0, 0, 0};
 
     T ra[LA], rb[LB];
+    // along a contiguous dimension of 64 or more, a wavefront's 64 lanes share
+    // one k; a problem whose loader gathers through a k-indexed table marks it
+    // wave-uniform (K_UNIFORM), so the gather goes through the scalar unit
+    // (for plain operands the scalar address arithmetic measured slower)
+    constexpr bool KU = gemm_k_uniform<P>::value;
     auto a_index = [&](int ii, int& m, int& k) {
-        if (P::A_M_CONTIG) { m = tid % BM; k = tid / BM + (NT / BM) * ii; }
-        else { k = tid % BK; m = tid / BK + (NT / BK) * ii; }
+        if (P::A_M_CONTIG) {
+            m = tid % BM;
+            k = tid / BM + (NT / BM) * ii;
+            if constexpr (KU && BM % 64 == 0) k = __builtin_amdgcn_readfirstlane(k);
+        } else { k = tid % BK; m = tid / BK + (NT / BK) * ii; }
     };
     auto b_index = [&](int ii, int& nn, int& k) {
-        if (P::B_N_CONTIG) { nn = tid % BN; k = tid / BN + (NT / BN) * ii; }
-        else { k = tid % BK; nn = tid / BK + (NT / BK) * ii; }
+        if (P::B_N_CONTIG) {
+            nn = tid % BN;
+            k = tid / BN + (NT / BN) * ii;
+            if constexpr (KU && BN % 64 == 0) k = __builtin_amdgcn_readfirstlane(k);
+        } else { k = tid % BK; nn = tid / BK + (NT / BK) * ii; }
     };
     auto gload = [&](int k0) {
 #pragma unroll

@@ -594,8 +594,9 @@ __global__ __launch_bounds__(256) void stedc_order_kernel(StedcWs<T> w, int lev)
     }
 }
 
-// merged eigenvectors: Zn[:, outnd[j]] = Zc[:, perm[ndpos[.]]] U[:, j]
-template <typename T>
+// merged eigenvectors: Zn[:, outnd[j]] = Zc[:, perm[ndpos[.]]] U[:, j], in
+// TS x TS output tiles
+template <typename T, int TS>
 struct DcMergeProb {
     // Zn(rows of half h, outnd(j)) = sum over the kept columns q with rows in
     // half h of Zc(rows of h, column of q) U(q, j): the merge's eigenvector
@@ -605,6 +606,7 @@ struct DcMergeProb {
     // column tiles, y = merge, z = matrix.
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = false;
+    static constexpr bool K_UNIFORM = true;  // A's column comes from a q-indexed table
     const int* ns;
     int lev, tdim, tdh;
     MatBatch<T> Zc, Zn, U;
@@ -621,8 +623,8 @@ struct DcMergeProb {
         const long long base = (long long)bz * sV + o;
         const int h = bx / (tdh * tdim), rem = bx - h * (tdh * tdim);
         const int K = Kcnt[base];
-        t.m0 = (rem / tdim) * GEMM_BM;
-        t.n0 = (rem % tdim) * GEMM_BN;
+        t.m0 = (rem / tdim) * TS;
+        t.n0 = (rem % tdim) * TS;
         t.o = o;
         t.e0 = h ? m.k1 : 0;                  // first row of the half
         t.k = h ? m.k - m.k1 : m.k1;          // rows of the half
@@ -741,17 +743,29 @@ int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
                                src);
         } else {
             hipLaunchKernelGGL(stedc_split_kernel<T>, dim3(nmerge, 1, nbatch), dim3(256), 0, st, w, lev);
-            DcMergeProb<T> pr;
-            pr.ns = w.ns; pr.lev = lev;
-            pr.tdim = (1 << lev) / GEMM_BM;
-            pr.tdh = (1 << (lev - 1)) / GEMM_BM;
-            pr.Zc = src ? w.Z1 : w.Z0;
-            pr.Zn = src ? w.Z0 : w.Z1;
-            pr.U = w.U;
-            pr.outnd = w.outnd; pr.Kcnt = w.Kcnt; pr.ltop = w.ltop; pr.lbot = w.lbot; pr.ktop = w.ktop;
-            pr.kbot = w.kbot; pr.ctop = w.ctop; pr.cbot = w.cbot; pr.sV = w.sV;
-            hipLaunchKernelGGL((gemm_mfma_kernel<T, DcMergeProb<T>>), dim3(2 * pr.tdh * pr.tdim, nmerge, nbatch),
-                               dim3(256), 0, st, pr);
+            auto setup = [&](auto& pr, int ts) {
+                pr.ns = w.ns; pr.lev = lev;
+                pr.tdim = (1 << lev) / ts;
+                pr.tdh = (1 << (lev - 1)) / ts;
+                pr.Zc = src ? w.Z1 : w.Z0;
+                pr.Zn = src ? w.Z0 : w.Z1;
+                pr.U = w.U;
+                pr.outnd = w.outnd; pr.Kcnt = w.Kcnt; pr.ltop = w.ltop; pr.lbot = w.lbot; pr.ktop = w.ktop;
+                pr.kbot = w.kbot; pr.ctop = w.ctop; pr.cbot = w.cbot; pr.sV = w.sV;
+            };
+            if ((1 << lev) >= GEMM_TS128_MIN_ORDER) {
+                // merges of 2048 and more: 128 x 128 tiles
+                typedef Gemm128Shape<T> S;
+                DcMergeProb<T, 128> pr;
+                setup(pr, 128);
+                hipLaunchKernelGGL((gemm_mfma_kernel<T, DcMergeProb<T, 128>, 128, 128, S::BK, S::WM, S::WN>),
+                                   dim3(2 * pr.tdh * pr.tdim, nmerge, nbatch), dim3(64 * S::WM * S::WN), 0, st, pr);
+            } else {
+                DcMergeProb<T, 64> pr;
+                setup(pr, 64);
+                hipLaunchKernelGGL((gemm_mfma_kernel<T, DcMergeProb<T, 64>>), dim3(2 * pr.tdh * pr.tdim, nmerge, nbatch),
+                                   dim3(256), 0, st, pr);
+            }
         }
         hipLaunchKernelGGL(stedc_copy_kernel<T>, dim3(nmax, 1, nbatch), dim3(256), 0, st, w, lev, src);
         src ^= 1;
