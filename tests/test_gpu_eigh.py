@@ -57,6 +57,29 @@ def test_eigh_fp32_random(ctx, n):
     _check(A, w.double().cpu().numpy(), Z.double().cpu().numpy(), 2e-5)
 
 
+# orders around the hand-over from the panel path to the LDS tail kernel (the
+# last <= 256 columns in FP32, <= 192 in FP64, from a 32-column panel boundary):
+# whole matrix in the tail, one panel then the tail, two panels then the tail
+@pytest.mark.parametrize("n", [256, 257, 289, 320])
+def test_eigh_fp32_tail_boundary(ctx, n):
+    from paper_2308_03140_amd import torch_api as T
+    _note("eigh fp32 tail boundary n=%d" % n)
+    A = gen.random_symmetric(3000 + n, n)
+    w, Z = T.eigh(ctx, torch.tensor(A, device="cuda", dtype=torch.float32))
+    torch.cuda.synchronize()
+    _check(A, w.double().cpu().numpy(), Z.double().cpu().numpy(), 2e-5)
+
+
+@pytest.mark.parametrize("n", [192, 193, 225])
+def test_eigh_fp64_tail_boundary(ctx, n):
+    from paper_2308_03140_amd import torch_api as T
+    _note("eigh fp64 tail boundary n=%d" % n)
+    A = gen.random_symmetric(4000 + n, n)
+    w, Z = T.eigh(ctx, torch.tensor(A, device="cuda"))
+    torch.cuda.synchronize()
+    _check(A, w.cpu().numpy(), Z.cpu().numpy(), 1e-12)
+
+
 def test_eigh_degenerate_cases(ctx):
     from paper_2308_03140_amd import torch_api as T
     _note("eigh degenerate")
