@@ -384,22 +384,32 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     const int rc = r < n ? r : n - 1;
     const T tau = w.tau[(long long)b * w.sD + i];
     const T vpart = vacc_of(w, b, i)[tid];  // SYTRD_VC == blockDim
-    T spc[SYTRD_YC], yrc[SYTRD_YC], ysc[SYTRD_YC];
+    T spc[SYTRD_YC], yrc[SYTRD_YC];
 #pragma unroll
     for (int c = 0; c < SYTRD_YC; c++) {
         spc[c] = sacc_of(w, b, i, c)[tid & (2 * NBP - 1)];
-        const T* yc = yacc_of(w, b, i, c);
-        yrc[c] = yc[rc];
-        ysc[c] = yc[s];
+        yrc[c] = yacc_of(w, b, i, c)[rc];
     }
-    T vr_k[NBP / 4], wr_k[NBP / 4], vs_k[NBP / 4], ws_k[NBP / 4];
+    // the wave-uniform values at row s (the accumulator copies and the
+    // wave's panel entries) come from one load, a value per lane, and are
+    // broadcast from their lanes afterwards
+    static_assert(SYTRD_YC + 2 * (NBP / 4) <= 64, "row-s values fit in a wavefront");
+    T srow;
+    {
+        const int l = lane;
+        const T* src;
+        if (l < SYTRD_YC) src = yacc_of(w, b, i, l) + s;
+        else if (l < SYTRD_YC + NBP / 4) src = Vp + s + (long long)(part + 4 * (l - SYTRD_YC)) * ldp;
+        else if (l < SYTRD_YC + NBP / 2) src = Wp + s + (long long)(part + 4 * (l - SYTRD_YC - NBP / 4)) * ldp;
+        else src = yacc_of(w, b, i, 0) + s;
+        srow = *src;
+    }
+    T vr_k[NBP / 4], wr_k[NBP / 4];
 #pragma unroll
     for (int t = 0; t < NBP / 4; t++) {
         const int k = part + 4 * t;
         vr_k[t] = Vp[rc + (long long)k * ldp];
         wr_k[t] = Wp[rc + (long long)k * ldp];
-        vs_k[t] = Vp[s + (long long)k * ldp];
-        ws_k[t] = Wp[s + (long long)k * ldp];
     }
     const T vr_l = Vp[rc + (long long)j * ldp];
     const T acol_l = A[rc + (long long)s * ld];
@@ -408,7 +418,13 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     for (int c = 0; c < SYTRD_YC; c++) {
         sp += spc[c];
         yr += yrc[c];
-        ysv += ysc[c];
+        ysv += lane_value(srow, c);
+    }
+    T vs_k[NBP / 4], ws_k[NBP / 4];
+#pragma unroll
+    for (int t = 0; t < NBP / 4; t++) {
+        vs_k[t] = lane_value(srow, SYTRD_YC + t);
+        ws_k[t] = lane_value(srow, SYTRD_YC + NBP / 4 + t);
     }
     if (!(tid < 2 * NBP && (tid % NBP) < j)) sp = T(0);
     if (!rv) yr = T(0);

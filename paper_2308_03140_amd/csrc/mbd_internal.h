@@ -215,6 +215,17 @@ template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_r
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 // 16 bytes per lane: 4 floats or 2 doubles (offset a multiple of 16)
+// value of v in lane l (l wave-uniform) in every lane
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 template <typename T> struct Vec16 { typedef T v __attribute__((ext_vector_type(16 / sizeof(T)))); };
 template <typename T>
 __device__ __forceinline__ typename Vec16<T>::v buf_load16(__amdgpu_buffer_rsrc_t r, unsigned off) {
