@@ -384,11 +384,25 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     const int rc = r < n ? r : n - 1;
     const T tau = w.tau[(long long)b * w.sD + i];
     const T vpart = vacc_of(w, b, i)[tid];  // SYTRD_VC == blockDim
+    // wavefront 0 forms w and the next column: only it needs the panel
+    // products, y at row r, v(r) and the column of A (a wave-uniform branch)
+    const bool w0 = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
     T spc[SYTRD_YC], yrc[SYTRD_YC];
+    T vr_l = T(0), acol_l = T(0);
+    if (w0) {
 #pragma unroll
-    for (int c = 0; c < SYTRD_YC; c++) {
-        spc[c] = sacc_of(w, b, i, c)[tid & (2 * NBP - 1)];
-        yrc[c] = yacc_of(w, b, i, c)[rc];
+        for (int c = 0; c < SYTRD_YC; c++) {
+            spc[c] = sacc_of(w, b, i, c)[tid & (2 * NBP - 1)];
+            yrc[c] = yacc_of(w, b, i, c)[rc];
+        }
+        vr_l = Vp[rc + (long long)j * ldp];
+        acol_l = A[rc + (long long)s * ld];
+    } else {
+#pragma unroll
+        for (int c = 0; c < SYTRD_YC; c++) {
+            spc[c] = T(0);
+            yrc[c] = T(0);
+        }
     }
     // the wave-uniform values at row s (the accumulator copies and the
     // wave's panel entries) come from one load, a value per lane, and are
@@ -411,8 +425,6 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
         vr_k[t] = Vp[rc + (long long)k * ldp];
         wr_k[t] = Wp[rc + (long long)k * ldp];
     }
-    const T vr_l = Vp[rc + (long long)j * ldp];
-    const T acol_l = A[rc + (long long)s * ld];
     T sp = T(0), yr = T(0), ysv = T(0);
 #pragma unroll
     for (int c = 0; c < SYTRD_YC; c++) {
