@@ -858,12 +858,10 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
         }
         const int t0 = k0 + NBP;
         if (k1 == k0 + NBP && t0 + 1 < nmax) {
-            // K = 2 NBP is only 4 slabs deep: the 128 x 128 tile's prologue and
-            // epilogue outweigh its lower L2 traffic (measured 7.5 vs 6.2 ms
+            // K = 2 NBP is only 4 slabs deep: a 128 x 128 tile's prologue and
+            // epilogue outweighed its lower L2 traffic (measured 7.5 vs 6.2 ms
             // FP32, 9.3 vs 7.5 ms FP64 per N=2000 reduction), so 64 x 64 tiles
-            const bool big = false;
-            const int ts = big ? 128 : 64;
-            const int tm = (nmax - t0 + ts - 1) / ts;
+            const int tm = (nmax - t0 + 63) / 64;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timing) {
                 double flops = 0;
@@ -873,22 +871,12 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                 }
                 prof->pair(&e0, &e1, 1, flops);
             }
-            if (big) {
-                typedef Gemm128Shape<T> S;
-                Syr2kProb<T, NBP, 128> p;
-                p.A = w.A; p.ns = w.ns; p.Vp = w.Vp; p.Wp = w.Wp; p.ldp = w.ldp; p.sP = w.sP; p.t0 = t0;
-                auto k = gemm_mfma_kernel<T, Syr2kProb<T, NBP, 128>, 128, 128, S::BK, S::WM, S::WN>;
-                const dim3 grid(tm * (tm + 1) / 2, 1, nbatch), block(64 * S::WM * S::WN);
-                if (timing) hipExtLaunchKernelGGL(k, grid, block, 0, st, e0, e1, 0, p);
-                else hipLaunchKernelGGL(k, grid, block, 0, st, p);
-            } else {
-                Syr2kProb<T, NBP, 64> p;
-                p.A = w.A; p.ns = w.ns; p.Vp = w.Vp; p.Wp = w.Wp; p.ldp = w.ldp; p.sP = w.sP; p.t0 = t0;
-                auto k = gemm_mfma_kernel<T, Syr2kProb<T, NBP, 64>>;
-                const dim3 grid(tm * (tm + 1) / 2, 1, nbatch), block(256);
-                if (timing) hipExtLaunchKernelGGL(k, grid, block, 0, st, e0, e1, 0, p);
-                else hipLaunchKernelGGL(k, grid, block, 0, st, p);
-            }
+            Syr2kProb<T, NBP, 64> p;
+            p.A = w.A; p.ns = w.ns; p.Vp = w.Vp; p.Wp = w.Wp; p.ldp = w.ldp; p.sP = w.sP; p.t0 = t0;
+            auto k = gemm_mfma_kernel<T, Syr2kProb<T, NBP, 64>>;
+            const dim3 grid(tm * (tm + 1) / 2, 1, nbatch), block(256);
+            if (timing) hipExtLaunchKernelGGL(k, grid, block, 0, st, e0, e1, 0, p);
+            else hipLaunchKernelGGL(k, grid, block, 0, st, p);
         }
     }
     hipLaunchKernelGGL(sytrd_tail_kernel<T>, dim3(nbatch), dim3(SYTRD_TAIL_THREADS), 0, st, w);
