@@ -25,7 +25,7 @@ struct mbd_ctx {
     LaunchProfiler prof;
     double refine_tol = 0.0;  // second refinement step threshold (MBD_REFINE_TOL; <= 0: library default)
     // autotuned SYMV work-item targets per matrix order, per precision (0 FP64, 1 FP32)
-    std::map<int, int> tune[2];
+    std::map<int, std::pair<int, int>> tune[2];  // order -> SYMV work-item targets (upper, lower range)
     // captured batch launch sequences, keyed by batch signature
     struct Graph {
         hipGraphExec_t exec = nullptr;
@@ -120,10 +120,11 @@ template <> const char* tname<float>() { return "f"; }
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // SYMV work-item target for a matrix order: the tuned entry nearest in log(n)
-int tuned_target(const mbd_ctx* c, int prec, int n) {
+// targets of the tuned order nearest to n (log scale); 1536 for both ranges
+// when nothing is tuned
+std::pair<int, int> tuned_target(const mbd_ctx* c, int prec, int n) {
     const auto& t = c->tune[prec];
-    if (t.empty()) return 1536;
-    int best = 1536;
+    std::pair<int, int> best = {1536, 1536};
     double bd = 1e300;
     for (const auto& kv : t) {
         const double d = std::fabs(std::log((double)kv.first) - std::log((double)n));
@@ -170,7 +171,9 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     // --- reduction
     SytrdWs<T> sw;
     if (make_sytrd_ws<T>(c, A, ns, nmax, nbatch, sw) != MBD_OK) return (mbd_status)c->err_code;
-    sw.chunk_target = tuned_target(c, sizeof(T) == 8 ? 0 : 1, nmax);
+    const std::pair<int, int> tg = tuned_target(c, sizeof(T) == 8 ? 0 : 1, nmax);
+    sw.chunk_target = tg.first;
+    sw.chunk_target_lo = tg.second;
     sytrd_launch<T>(sw, nbatch, nmax, st, ns_host, &c->prof);
     HIPCHK(hipGetLastError(), "sytrd");
 
@@ -801,7 +804,7 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
 namespace {
 
 template <typename T>
-mbd_status autotune_size(mbd_ctx* c, int n, int* best_target, double* best_ms) {
+mbd_status autotune_size(mbd_ctx* c, int n, int* best_target, int* best_lo, double* best_ms) {
     const int ld = round_up(n, 64);
     const long long stride = (long long)ld * n;
     T* A = wsT<T>(c, std::string("tuneA") + tname<T>(), stride);
@@ -813,30 +816,44 @@ mbd_status autotune_size(mbd_ctx* c, int n, int* best_target, double* best_ms) {
     SytrdWs<T> sw;
     MatBatch<T> Ab = {A, ld, stride};
     if (make_sytrd_ws<T>(c, Ab, ns_dev, n, 1, sw) != MBD_OK) return (mbd_status)c->err_code;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0), "event");
-    HIPCHK(hipEventCreate(&e1), "event");
     const int cand[] = {256, 512, 768, 1024, 1536, 2048, 3072, 4096};
-    *best_ms = 1e300;
-    *best_target = 1536;
     int nh = n;
+    // Each candidate runs the reduction with a start/stop event pair on every
+    // SYMV launch; the kernel times are summed separately over the upper
+    // quarter of trailing sizes and below it (the two tuned ranges), and each
+    // range keeps its fastest candidate.  Kernel time, not the wall time of
+    // an eager reduction, whose host launch rate can hide the differences.
+    LaunchProfiler prof;
+    prof.enabled = true;
+    const int nbk = (n + 63) / 64;
+    double best_up = 1e300, best_low = 1e300;
+    *best_target = *best_lo = 1536;
     for (int target : cand) {
-        float ms_min = 1e30f;
+        double up = 1e300, low = 1e300;
         for (int rep = 0; rep < 2; rep++) {
             HIPCHK(hipMemcpyAsync(A, B, sizeof(T) * stride, hipMemcpyDeviceToDevice, c->stream), "copy");
             sw.chunk_target = target;
-            HIPCHK(hipEventRecord(e0, c->stream), "event");
-            sytrd_launch<T>(sw, 1, n, c->stream, &nh, nullptr);
-            HIPCHK(hipEventRecord(e1, c->stream), "event");
-            HIPCHK(hipEventSynchronize(e1), "event");
-            float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
-            ms_min = std::min(ms_min, ms);
+            sw.chunk_target_lo = target;
+            prof.reset();
+            sytrd_launch<T>(sw, 1, n, c->stream, &nh, &prof);
+            HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+            double u = 0, l = 0;
+            int col = 0;
+            for (size_t q = 0; q < prof.kind.size(); q++) {
+                if (prof.kind[q] != 0) continue;  // SYMV launches, one per column in order
+                float ms = 0;
+                hipEventElapsedTime(&ms, prof.pool[2 * q], prof.pool[2 * q + 1]);
+                const int nbt = nbk - ((col + 1) >> 6);
+                (4 * nbt >= 3 * nbk ? u : l) += ms;
+                col++;
+            }
+            up = std::min(up, u);
+            low = std::min(low, l);
         }
-        if (ms_min < *best_ms) { *best_ms = ms_min; *best_target = target; }
+        if (up < best_up) { best_up = up; *best_target = target; }
+        if (low < best_low) { best_low = low; *best_lo = target; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    *best_ms = best_up + best_low;
     return MBD_OK;
 }
 
@@ -849,7 +866,7 @@ bool write_tuning(const mbd_ctx* c, const char* path) {
         std::fprintf(f, "  \"%s\": {", names[p]);
         bool first = true;
         for (const auto& kv : c->tune[p]) {
-            std::fprintf(f, "%s\"%d\": %d", first ? "" : ", ", kv.first, kv.second);
+            std::fprintf(f, "%s\"%d\": [%d, %d]", first ? "" : ", ", kv.first, kv.second.first, kv.second.second);
             first = false;
         }
         std::fprintf(f, "}%s\n", p == 0 ? "," : "");
@@ -858,7 +875,8 @@ bool write_tuning(const mbd_ctx* c, const char* path) {
     return std::fclose(f) == 0;
 }
 
-// parses {"fp64": {"n": target, ...}, "fp32": {...}} (the format written above)
+// parses {"fp64": {"n": [upper, lower], ...}, "fp32": {...}} (the format
+// written above); a single number sets both targets
 bool read_tuning(mbd_ctx* c, const char* path) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
@@ -875,16 +893,27 @@ bool read_tuning(mbd_ctx* c, const char* path) {
         if (lb == std::string::npos || rb == std::string::npos || rb < lb) return false;
         const std::string body = txt.substr(lb + 1, rb - lb - 1);
         size_t pos = 0;
-        std::map<int, int> tab;
+        std::map<int, std::pair<int, int>> tab;
         while ((pos = body.find('"', pos)) != std::string::npos) {
             const size_t q2 = body.find('"', pos + 1);
             const size_t colon = body.find(':', q2);
             if (q2 == std::string::npos || colon == std::string::npos) return false;
             const int key = std::atoi(body.substr(pos + 1, q2 - pos - 1).c_str());
-            const int val = std::atoi(body.c_str() + colon + 1);
-            if (key <= 0 || val <= 0) return false;
-            tab[key] = val;
-            pos = body.find(',', colon);
+            size_t v = body.find_first_not_of(" \t\n", colon + 1);
+            if (v == std::string::npos) return false;
+            int hi, lo;
+            if (body[v] == '[') {
+                const size_t comma = body.find(',', v), rbk = body.find(']', v);
+                if (comma == std::string::npos || rbk == std::string::npos || comma > rbk) return false;
+                hi = std::atoi(body.c_str() + v + 1);
+                lo = std::atoi(body.c_str() + comma + 1);
+                pos = body.find(',', rbk);
+            } else {
+                hi = lo = std::atoi(body.c_str() + v);
+                pos = body.find(',', v);
+            }
+            if (key <= 0 || hi <= 0 || lo <= 0) return false;
+            tab[key] = {hi, lo};
             if (pos == std::string::npos) break;
         }
         c->tune[p] = tab;
@@ -905,11 +934,11 @@ mbd_status mbd_autotune(mbd_ctx* c, const int32_t* sizes, int32_t nsizes, const 
     for (int k = 0; k < nsizes; k++) {
         const int n = sizes[k];
         if (n < 2) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_autotune", "sizes must be >= 2");
-        int target = 1536;
+        int target = 1536, lo = 1536;
         double ms = 0;
-        const mbd_status r = p ? autotune_size<float>(c, n, &target, &ms) : autotune_size<double>(c, n, &target, &ms);
+        const mbd_status r = p ? autotune_size<float>(c, n, &target, &lo, &ms) : autotune_size<double>(c, n, &target, &lo, &ms);
         if (r != MBD_OK) return r;
-        c->tune[p][n] = target;
+        c->tune[p][n] = {target, lo};
     }
     if (path && !write_tuning(c, path)) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_autotune", "cannot write table");
     return MBD_OK;

@@ -837,7 +837,11 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                 const int j = i - k0;
                 const int b0 = (i + 1) >> 6;
                 const int nbt = nbk_max - b0;
-                const int Kt = sytrd_kt(nbt, nbatch, w.chunk_target > 0 ? w.chunk_target : 1536);
+                // trailing sizes in the upper quarter stream many tiles per
+                // workgroup already; below it fewer, longer work items measured
+                // faster, so each range has its own tuned target
+                const int tgt = 4 * nbt >= 3 * nbk_max ? w.chunk_target : w.chunk_target_lo;
+                const int Kt = sytrd_kt(nbt, nbatch, tgt > 0 ? tgt : 1536);
                 const int gx = (nbt + Kt - 1) / Kt;
                 if (timing) {
                     double bb = 0;

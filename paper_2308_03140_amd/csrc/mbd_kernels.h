@@ -66,7 +66,8 @@ struct SytrdWs {
     T* sacc; long long sS;                 // W^T v, V^T v, [2][SYTRD_YCOPIES][2*NBP]
     T* vacc;                               // v^T A v, [2][SYTRD_VCOPIES] per matrix
     T* d; T* e; T* tau; long long sD;      // outputs
-    int chunk_target;                      // SYMV work items per launch (tuned)
+    int chunk_target;                      // SYMV workgroups per launch, trailing sizes in the upper quarter (tuned)
+    int chunk_target_lo;                   // the same below it (tuned)
 };
 template <typename T>
 void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, const int* ns_host,

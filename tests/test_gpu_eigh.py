@@ -142,6 +142,18 @@ def test_autotune_table_roundtrip(tmp_path):
     import json
     tab = json.load(open(path))
     assert set(tab) == {"fp64", "fp32"} and "400" in tab["fp32"]
+    # each order maps to [upper-range target, lower-range target]
+    assert all(len(v) == 2 and min(v) > 0 for p in tab.values() for v in p.values())
+    # a table may also give one target for both ranges
+    with open(path, "w") as f:
+        json.dump({"fp64": {"400": 768}, "fp32": {"400": [1536, 512]}}, f)
+    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32_refined", torch.float32, 2e-5)):
+        c3 = T.Context(0, prec)
+        c3.load_tuning(path)
+        A = gen.random_symmetric(98, 400)
+        w, Z = T.eigh(c3, torch.tensor(A, device="cuda", dtype=dt))
+        _check(A, w.double().cpu().numpy(), Z.double().cpu().numpy(), tol)
+        c3.close()
 
 
 @pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 3e-5)])
