@@ -307,6 +307,32 @@ def pmc_summary(fetch_dir, write_dir):
     print("\n".join(lines))
 
 
+def trace_summary(trace_dir, steps, warmup):
+    """Average duration of the FP32 SYMV kernel over the evaluations of a
+    `--legs c2` run traced by rocprofv3 --kernel-trace (its kernel_trace.csv
+    under trace_dir): the autotuner's candidate launches come first and are
+    left out."""
+    import csv
+    files = [os.path.join(r, f) for r, _, fs in os.walk(trace_dir) for f in fs if f.endswith("kernel_trace.csv")]
+    if not files:
+        raise SystemExit("no kernel_trace.csv under %s" % trace_dir)
+    rows = []
+    for fn in files:
+        with open(fn) as f:
+            rows += [r for r in csv.DictReader(f) if r["Kernel_Name"].startswith("void sytrd_symv_kernel<float")]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3 for r in rows]
+    per = symv_launches(6000)
+    n_eval = warmup + steps + 1  # warm-up, timed (captured graphs), one profiled eager evaluation
+    if len(dur) < n_eval * per:
+        raise SystemExit("%d SYMV launches, fewer than %d evaluations of %d" % (len(dur), n_eval, per))
+    ev, timed, prof = dur[-n_eval * per:], dur[-(steps + 1) * per:-per], dur[-per:]
+    print("all %d calls: %.2f us" % (len(dur), sum(dur) / len(dur)))
+    print("the %d launches of the %d evaluations: %.2f us" % (len(ev), n_eval, sum(ev) / len(ev)))
+    print("the %d launches of the %d timed (captured-graph) evaluations: %.2f us" % (len(timed), steps, sum(timed) / len(timed)))
+    print("the %d launches of the profiled evaluation: %.2f us" % (len(prof), sum(prof) / len(prof)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +343,9 @@ def main():
     ap.add_argument("--tuning-dir", default=None, help="write the autotuner tables (JSON) here")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write the SYMV HBM-traffic file under profiles/ from two --pmc-pass counter runs")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR", default=None,
+                    help="average SYMV kernel duration per evaluation from a rocprofv3 --kernel-trace run of "
+                         "--legs c2 with the same --steps/--warmup")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="counter-collection pass: one FP32+refine N=2000 evaluation, then a plain device copy "
                          "of 1 GiB (the calibration kernel of known traffic); prints no JSON line")
@@ -328,6 +357,9 @@ def main():
     legs = set(args.legs.split(","))
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.steps, args.warmup)
         return
 
     import numpy as np
