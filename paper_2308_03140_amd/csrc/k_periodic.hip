@@ -95,36 +95,64 @@ __device__ __forceinline__ bool image_term(const double* x, double gamma, double
 }
 
 // one thread per (q, i, j): assemble the embedded Q(q)
-__global__ __launch_bounds__(128) void mbd_assemble_periodic_kernel(const SysDesc* sd, const double* om,
-                                                                      const double* cc, const double* qcart,
-                                                                      const int* img, int nimg, const int* rec,
-                                                                      int nrec, MatBatch<double> Q,
-                                                                      MatBatch<float> Q32, unsigned* status) {
+// One workgroup per ordered atom pair (i, j), one lane per q-point (grid y
+// covers q-points in groups of 64).  The real-space image terms depend on the
+// pair and the image only: each is formed once, by one lane, into LDS (in
+// groups of 64 images), and every lane adds it with its own phase e^{-i q.x}.
+#define PER_LANES 64
+__global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const SysDesc* sd, const double* om,
+                                                                          const double* cc, const double* qcart,
+                                                                          int nq, const int* img, int nimg,
+                                                                          const int* rec, int nrec, MatBatch<double> Q,
+                                                                          MatBatch<float> Q32, unsigned* status) {
+    __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9];
+    __shared__ int oks[PER_LANES];
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
-    const int q = blockIdx.y;
-    const long long pid = (long long)blockIdx.x * 128 + threadIdx.x;
+    const int q = blockIdx.y * PER_LANES + threadIdx.x;
+    const bool qv_ok = q < nq;
+    const long long pid = blockIdx.x;
     if (pid >= (long long)N * N) return;
     const int i = (int)(pid % N), j = (int)(pid / N);
     const double* R = S.coords;
     const double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
-    const double qv[3] = {qcart[3 * q], qcart[3 * q + 1], qcart[3 * q + 2]};
+    const int qc = qv_ok ? q : 0;
+    const double qv[3] = {qcart[3 * qc], qcart[3 * qc + 1], qcart[3 * qc + 2]};
     const double R0 = S.beta * (S.rvdw[i] + S.rvdw[j]);
     double Tre[9], Tim[9];
     for (int k = 0; k < 9; k++) { Tre[k] = 0.0; Tim[k] = 0.0; }
-    for (int t = 0; t < nimg; t++) {
-        const double n0 = img[3 * t], n1 = img[3 * t + 1], n2 = img[3 * t + 2];
-        double x[3];
-        for (int c = 0; c < 3; c++) x[c] = r[c] + n0 * S.lat[c] + n1 * S.lat[3 + c] + n2 * S.lat[6 + c];
-        const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        if (d2 == 0.0) continue;
-        if (i != j && d2 < 1e-16) atomicOr(&status[0], MBD_ST_COINCIDENT);
-        double F[9];
-        if (!image_term(x, S.gamma, S.rc, R0, S.a, F, nullptr)) continue;
-        double sph, cph;
-        sincos(-(qv[0] * x[0] + qv[1] * x[1] + qv[2] * x[2]), &sph, &cph);
-        for (int k = 0; k < 9; k++) { Tre[k] += F[k] * cph; Tim[k] += F[k] * sph; }
+    for (int t0 = 0; t0 < nimg; t0 += PER_LANES) {
+        {
+            const int t = t0 + (int)threadIdx.x;
+            int ok = 0;
+            if (t < nimg) {
+                const double n0 = img[3 * t], n1 = img[3 * t + 1], n2 = img[3 * t + 2];
+                double x[3];
+                for (int c = 0; c < 3; c++) x[c] = r[c] + n0 * S.lat[c] + n1 * S.lat[3 + c] + n2 * S.lat[6 + c];
+                const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+                if (d2 != 0.0) {
+                    if (i != j && d2 < 1e-16 && blockIdx.y == 0) atomicOr(&status[0], MBD_ST_COINCIDENT);
+                    double F[9];
+                    if (image_term(x, S.gamma, S.rc, R0, S.a, F, nullptr)) {
+                        ok = 1;
+                        for (int c = 0; c < 3; c++) xs[threadIdx.x][c] = x[c];
+                        for (int k = 0; k < 9; k++) Fs[threadIdx.x][k] = F[k];
+                    }
+                }
+            }
+            oks[threadIdx.x] = ok;
+        }
+        __syncthreads();
+        const int tn = min(PER_LANES, nimg - t0);
+        for (int u = 0; u < tn; u++) {
+            if (!oks[u]) continue;
+            double sph, cph;
+            sincos(-(qv[0] * xs[u][0] + qv[1] * xs[u][1] + qv[2] * xs[u][2]), &sph, &cph);
+            for (int k = 0; k < 9; k++) { Tre[k] += Fs[u][k] * cph; Tim[k] += Fs[u][k] * sph; }
+        }
+        __syncthreads();
     }
+    if (!qv_ok) return;
     const double pref = 4.0 * M_PI / S.vol;
     const double g4 = 1.0 / (4.0 * S.gamma * S.gamma);
     for (int t = 0; t < nrec; t++) {
@@ -183,14 +211,21 @@ __global__ __launch_bounds__(128) void mbd_assemble_periodic_kernel(const SysDes
 //                                      Omega Ainv_cv)
 //   to dE/dalpha_i, dE/dalpha_j        X = T_ij(q) / (2 alpha)
 // Partial results per (q, i, j): {P, dR[3], dA[9]}.
-__global__ __launch_bounds__(128) void mbd_grad_periodic_kernel(const SysDesc* sd, const double* om,
-                                                                  const double* cc, const double* qcart,
-                                                                  const int* img, int nimg, const int* rec,
-                                                                  int nrec, MatBatch<double> M, double* part) {
+// Same layout as the assembly: one workgroup per ordered pair, one lane per
+// q-point, each real-space image term (F and its derivatives) formed once
+// into LDS and added by every lane with its own phase and M(q).
+__global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysDesc* sd, const double* om,
+                                                                      const double* cc, const double* qcart, int nq,
+                                                                      const int* img, int nimg, const int* rec,
+                                                                      int nrec, MatBatch<double> M, double* part) {
+    __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9], dFs[PER_LANES][27];
+    __shared__ int ns_[PER_LANES][3], oks[PER_LANES];
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
-    const int q = blockIdx.y;
-    const long long pid = (long long)blockIdx.x * 128 + threadIdx.x;
+    const int q0 = blockIdx.y * PER_LANES + threadIdx.x;
+    const bool qv_ok = q0 < nq;
+    const int q = qv_ok ? q0 : 0;
+    const long long pid = blockIdx.x;
     if (pid >= (long long)N * N) return;
     const int i = (int)(pid % N), j = (int)(pid / N);
     double* out = part + ((long long)q * N * N + pid) * 13;
@@ -212,14 +247,33 @@ __global__ __launch_bounds__(128) void mbd_grad_periodic_kernel(const SysDesc* s
     for (int v = 0; v < 3; v++) rho[v] = S.linv[v] * r[0] + S.linv[3 + v] * r[1] + S.linv[6 + v] * r[2];
     double P = 0.0, dR[3] = {0, 0, 0}, dA[9];
     for (int k = 0; k < 9; k++) dA[k] = 0.0;
-    for (int t = 0; t < nimg; t++) {
-        const int nn[3] = {img[3 * t], img[3 * t + 1], img[3 * t + 2]};
-        double x[3];
-        for (int c = 0; c < 3; c++) x[c] = r[c] + nn[0] * S.lat[c] + nn[1] * S.lat[3 + c] + nn[2] * S.lat[6 + c];
-        const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        if (d2 == 0.0) continue;
-        double F[9], dF[27];
-        if (!image_term(x, S.gamma, S.rc, R0, S.a, F, dF)) continue;
+    for (int t0 = 0; t0 < nimg; t0 += PER_LANES) {
+        {
+            const int t = t0 + (int)threadIdx.x;
+            int ok = 0;
+            if (t < nimg) {
+                const int nn[3] = {img[3 * t], img[3 * t + 1], img[3 * t + 2]};
+                double x[3];
+                for (int c = 0; c < 3; c++) x[c] = r[c] + nn[0] * S.lat[c] + nn[1] * S.lat[3 + c] + nn[2] * S.lat[6 + c];
+                const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+                double F[9], dF[27];
+                if (d2 != 0.0 && image_term(x, S.gamma, S.rc, R0, S.a, F, dF)) {
+                    ok = 1;
+                    for (int c = 0; c < 3; c++) { xs[threadIdx.x][c] = x[c]; ns_[threadIdx.x][c] = nn[c]; }
+                    for (int k = 0; k < 9; k++) Fs[threadIdx.x][k] = F[k];
+                    for (int k = 0; k < 27; k++) dFs[threadIdx.x][k] = dF[k];
+                }
+            }
+            oks[threadIdx.x] = ok;
+        }
+        __syncthreads();
+        const int tn = min(PER_LANES, nimg - t0);
+        for (int u = 0; u < tn; u++) {
+        if (!oks[u]) continue;
+        const double* x = xs[u];
+        const double* F = Fs[u];
+        const double* dF = dFs[u];
+        const int* nn = ns_[u];
         double sph, cph;
         sincos(-(qv[0] * x[0] + qv[1] * x[1] + qv[2] * x[2]), &sph, &cph);
         double SF = 0.0, SFi = 0.0, SdF[3] = {0, 0, 0}, SdFi[3] = {0, 0, 0};
@@ -242,6 +296,8 @@ __global__ __launch_bounds__(128) void mbd_grad_periodic_kernel(const SysDesc* s
                                  qv[c] * rho[v] * (SF * sph + SFi * cph);
             }
         }
+        }
+        __syncthreads();
     }
     const double pref = 4.0 * M_PI / S.vol;
     const double g4 = 1.0 / (4.0 * S.gamma * S.gamma);
@@ -296,6 +352,7 @@ __global__ __launch_bounds__(128) void mbd_grad_periodic_kernel(const SysDesc* s
         const double self = 4.0 * S.gamma * S.gamma * S.gamma / (3.0 * SQRT_PI);
         P -= self * (Mr[0] + Mr[4] + Mr[8]);
     }
+    if (!qv_ok) return;
     out[0] = P;
     for (int c = 0; c < 3; c++) out[1 + c] = dR[c];
     for (int k = 0; k < 9; k++) out[4 + k] = dA[k];
@@ -360,15 +417,15 @@ void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const doubl
                                   const double* qcart, int nq, const int* img, int nimg, const int* rec,
                                   int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N) {
     const long long pairs = (long long)N * N;
-    hipLaunchKernelGGL(mbd_assemble_periodic_kernel, dim3((unsigned)((pairs + 127) / 128), nq), dim3(128), 0, st, sd,
-                       om, cc, qcart, img, nimg, rec, nrec, Q, Q32, status);
+    hipLaunchKernelGGL(mbd_assemble_periodic_kernel, dim3((unsigned)pairs, (nq + PER_LANES - 1) / PER_LANES),
+                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, img, nimg, rec, nrec, Q, Q32, status);
 }
 
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                               const double* qcart, int nq, const int* img, int nimg, const int* rec, int nrec,
                               MatBatch<double> M, double* partial, int N) {
     const long long pairs = (long long)N * N;
-    hipLaunchKernelGGL(mbd_grad_periodic_kernel, dim3((unsigned)((pairs + 127) / 128), nq), dim3(128), 0, st, sd, om,
-                       cc, qcart, img, nimg, rec, nrec, M, partial);
+    hipLaunchKernelGGL(mbd_grad_periodic_kernel, dim3((unsigned)pairs, (nq + PER_LANES - 1) / PER_LANES),
+                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, img, nimg, rec, nrec, M, partial);
     hipLaunchKernelGGL(mbd_grad_periodic_reduce_kernel, dim3(N + 1), dim3(256), 0, st, sd, nq, cc, partial);
 }
