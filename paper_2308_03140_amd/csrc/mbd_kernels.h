@@ -48,7 +48,7 @@ struct LaunchProfiler {
 };
 
 #define SYTRD_NBP 32
-#define SYTRD_YCOPIES 8    // atomic accumulator copies (y, panel products)
+#define SYTRD_YCOPIES 4    // atomic accumulator copies (y, panel products; 8 -> 4 measured faster, 2 no better)
 #define SYTRD_VCOPIES 256  // atomic accumulator copies (v^T A v)     // Householder panel width
 #define ORMTR_NBB 64     // reflectors per compact-WY block in the back-transform
 #define ORMTR_CHUNK 512  // rows per split-K chunk of V^T X
