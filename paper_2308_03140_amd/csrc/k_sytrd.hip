@@ -361,7 +361,7 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
 // ---------------------------------------------------------------------------
 template <typename T, int NBP>
 __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int R) {
-    static_assert(SYTRD_VC == 256, "one v^T A v copy per thread");
+    static_assert(SYTRD_VC == 256, "four v^T A v copies per lane of wavefront 0");
     static_assert(2 * NBP <= 64, "panel products are reduced by one wavefront");
     static_assert(NBP % 4 == 0, "panel columns are split over 4 wavefronts");
     __shared__ T sps[2 * NBP];
@@ -376,25 +376,25 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     const long long ld = w.A.ld;
     const int r = R * 64 + lane;
     const bool rv = (r >= s && r < n);
-    __shared__ T red[4];
 
     // ---- independent loads, all unconditional (rows clamped into the
     // matrix, panel columns k >= j masked afterwards) so that they form one
     // round trip instead of a chain of branch-guarded load/wait pairs
     const int rc = r < n ? r : n - 1;
     const T tau = w.tau[(long long)b * w.sD + i];
-    const T vpart = vacc_of(w, b, i)[tid];  // SYTRD_VC == blockDim
     // wavefront 0 forms w and the next column: only it needs the panel
     // products, y at row r, v(r) and the column of A (a wave-uniform branch)
     const bool w0 = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
     T spc[SYTRD_YC], yrc[SYTRD_YC];
-    T vr_l = T(0), acol_l = T(0);
+    T vr_l = T(0), acol_l = T(0), vq[4];
     if (w0) {
 #pragma unroll
         for (int c = 0; c < SYTRD_YC; c++) {
             spc[c] = sacc_of(w, b, i, c)[tid & (2 * NBP - 1)];
             yrc[c] = yacc_of(w, b, i, c)[rc];
         }
+#pragma unroll
+        for (int c = 0; c < 4; c++) vq[c] = vacc_of(w, b, i)[lane + 64 * c];
         vr_l = Vp[rc + (long long)j * ldp];
         acol_l = A[rc + (long long)s * ld];
     } else {
@@ -403,6 +403,8 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
             spc[c] = T(0);
             yrc[c] = T(0);
         }
+#pragma unroll
+        for (int c = 0; c < 4; c++) vq[c] = T(0);
     }
     // the wave-uniform values at row s (the accumulator copies and the
     // wave's panel entries) come from one load, a value per lane, and are
@@ -451,7 +453,9 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     const T vr = rv ? vr_l : T(0);
     const T acol = rv ? acol_l : T(0);
     if (tid < 2 * NBP) sps[tid] = sp;
-    const T vAv = block_sum256(vpart, red);
+    // v^T A v is needed by wavefront 0 only (w at row r and at row s)
+    const T vAv = wave_sum((vq[0] + vq[1]) + (vq[2] + vq[3]));
+    __syncthreads();
 
     // clear the other parity slot for column i + 1 (its SYMV runs after this
     // kernel): rows of block R, and the scalars once per matrix
