@@ -300,11 +300,19 @@ struct GemmGeneral {
     int lower_only;      // only tiles (and elements) with row >= col
     int tiles_n;         // tiles along N (grid.x = tiles_m * tiles_n, or lower count)
     const int* skip;     // optional per-matrix flag: nonzero skips the matrix
-    // the orders travel in the tile (t.o = M, t.k = N, t.K = K), read once
+    // Optional second product with the same A, orders and scaling (B2 set:
+    // grid.z = 2 nbatch, odd z computes C2 = alpha op(A) op(B2) + beta C2).
+    // Two products in one launch leave fewer partly filled rounds of tiles.
+    const T* B2 = nullptr; int ldb2 = 0; long long sB2 = 0;
+    T* C2 = nullptr; int ldc2 = 0; long long sC2 = 0;
+    // the orders travel in the tile (t.o = M, t.k = N, t.K = K), read once;
+    // t.e1 selects the product
     __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
-        t.batch = bz;
-        if (skip && skip[bz]) return false;
-        const int Mb = ns ? ns[bz] : M, Nb = ns ? ns[bz] : N, Kb = ns ? ns[bz] : K;
+        const int b = B2 ? (bz >> 1) : bz;
+        t.batch = b;
+        t.e1 = B2 ? (bz & 1) : 0;
+        if (skip && skip[b]) return false;
+        const int Mb = ns ? ns[b] : M, Nb = ns ? ns[b] : N, Kb = ns ? ns[b] : K;
         int ti, tj;
         const int v = xcd_virtual(bx, gridDim.x);
         if (lower_only) band_lower_tile(v, tiles_n, ti, tj);
@@ -320,13 +328,15 @@ struct GemmGeneral {
     }
     __device__ T b(const GemmTile& t, int k, int n) const {
         if (n >= t.k || k >= t.K) return T(0);
-        const T* Bb = B + (long long)t.batch * sB;
-        return TB ? Bb[n + (long long)k * ldb] : Bb[k + (long long)n * ldb];
+        const T* Bb = t.e1 ? B2 + (long long)t.batch * sB2 : B + (long long)t.batch * sB;
+        const int ld = t.e1 ? ldb2 : ldb;
+        return TB ? Bb[n + (long long)k * ld] : Bb[k + (long long)n * ld];
     }
     __device__ void store(const GemmTile& t, int m, int n, T v) const {
         if (m >= t.o || n >= t.k) return;
         if (lower_only && m < n) return;
-        T* Cb = C + (long long)t.batch * sC + m + (long long)n * ldc;
+        T* Cb = t.e1 ? C2 + (long long)t.batch * sC2 + m + (long long)n * ldc2
+                     : C + (long long)t.batch * sC + m + (long long)n * ldc;
         if (beta == T(0)) { *Cb = alpha * v; return; }
         const T cin = Cin ? Cin[(long long)t.batch * sCin + m + (long long)n * ldcin] : *Cb;
         *Cb = alpha * v + beta * cin;

@@ -292,10 +292,16 @@ template <typename T, bool TA, bool TB, int TS>
 static void gemm_gen_launch_ts(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
                                long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
                                T alpha, T beta, bool lower_only, const int* skip, const T* Cin, int ldcin,
-                               long long sCin) {
+                               long long sCin, const GemmSecond<T>* second) {
     GemmGeneral<T, TA, TB, TS> p;
     p.A = A; p.lda = lda; p.sA = sA; p.B = B; p.ldb = ldb; p.sB = sB; p.C = C; p.ldc = ldc; p.sC = sC;
     p.Cin = Cin; p.ldcin = ldcin; p.sCin = sCin;
+    int nz = nbatch;
+    if (second) {
+        p.B2 = second->B; p.ldb2 = second->ldb; p.sB2 = second->sB;
+        p.C2 = second->C; p.ldc2 = second->ldc; p.sC2 = second->sC;
+        nz = 2 * nbatch;
+    }
     p.ns = ns; p.M = p.N = p.K = nmax; p.alpha = alpha; p.beta = beta;
     p.lower_only = lower_only ? 1 : 0;
     p.skip = skip;
@@ -305,9 +311,9 @@ static void gemm_gen_launch_ts(hipStream_t st, const int* ns, int nmax, int nbat
     if constexpr (TS == 128) {
         typedef Gemm128Shape<T> S;
         hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB, TS>, TS, TS, S::BK, S::WM, S::WN>),
-                           dim3(grid, 1, nbatch), dim3(64 * S::WM * S::WN), 0, st, p);
+                           dim3(grid, 1, nz), dim3(64 * S::WM * S::WN), 0, st, p);
     } else {
-        hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB, TS>, TS, TS>), dim3(grid, 1, nbatch),
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, GemmGeneral<T, TA, TB, TS>, TS, TS>), dim3(grid, 1, nz),
                            dim3(256), 0, st, p);
     }
 }
@@ -318,13 +324,13 @@ template <typename T, bool TA, bool TB>
 static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
                             long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
                             T alpha, T beta, bool lower_only, const int* skip, const T* Cin, int ldcin,
-                            long long sCin) {
+                            long long sCin, const GemmSecond<T>* second = nullptr) {
     if (nmax >= GEMM_TS128_MIN_ORDER)
         gemm_gen_launch_ts<T, TA, TB, 128>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta,
-                                           lower_only, skip, Cin, ldcin, sCin);
+                                           lower_only, skip, Cin, ldcin, sCin, second);
     else
         gemm_gen_launch_ts<T, TA, TB, 64>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta,
-                                          lower_only, skip, Cin, ldcin, sCin);
+                                          lower_only, skip, Cin, ldcin, sCin, second);
 }
 
 template <typename T>
@@ -336,6 +342,29 @@ void gemm_batched(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int
     else if (!ta && tb) gemm_gen_launch<T, false, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, Cin, ldcin, sCin);
     else gemm_gen_launch<T, true, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, Cin, ldcin, sCin);
 }
+
+// C = alpha op(A) op(B) + beta C and C2 = alpha op(A) op(B2) + beta C2 in one
+// launch (grid.z = 2 nbatch, at most 65535)
+template <typename T>
+void gemm_batched_pair(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int nbatch, const T* A, int lda,
+                       long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
+                       const GemmSecond<T>& second, T alpha, T beta, bool lower_only, const int* skip) {
+    if (2 * (long long)nbatch > 65535) {
+        gemm_batched<T>(st, ta, tb, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only,
+                        skip);
+        gemm_batched<T>(st, ta, tb, ns, nmax, nbatch, A, lda, sA, second.B, second.ldb, second.sB, second.C,
+                        second.ldc, second.sC, alpha, beta, lower_only, skip);
+        return;
+    }
+    const GemmSecond<T>* s2 = &second;
+    if (!ta && !tb) gemm_gen_launch<T, false, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, nullptr, 0, 0, s2);
+    else if (ta && !tb) gemm_gen_launch<T, true, false>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, nullptr, 0, 0, s2);
+    else if (!ta && tb) gemm_gen_launch<T, false, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, nullptr, 0, 0, s2);
+    else gemm_gen_launch<T, true, true>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, lower_only, skip, nullptr, 0, 0, s2);
+}
+template void gemm_batched_pair<double>(hipStream_t, bool, bool, const int*, int, int, const double*, int, long long,
+                                        const double*, int, long long, double*, int, long long,
+                                        const GemmSecond<double>&, double, double, bool, const int*);
 
 template void gemm_batched<double>(hipStream_t, bool, bool, const int*, int, int, const double*, int, long long,
                                    const double*, int, long long, double*, int, long long, double, double, bool,

@@ -716,10 +716,10 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
     const dim3 gc(nmax, 1, nbatch);  // one workgroup per column
     gemm_batched<double>(st, false, false, ns, nmax, nbatch, Q.p, Q.ld, Q.stride, X.p, X.ld, X.stride, T1.p,
                          T1.ld, T1.stride, 1.0, 0.0, false, skip);                             // T1 = Q X
-    gemm_batched<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T1.p, T1.ld, T1.stride, T2.p,
-                         T2.ld, T2.stride, 1.0, 0.0, true, skip);                              // S = X^T Q X (lower)
-    gemm_batched<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, X.p, X.ld, X.stride, G.p, G.ld,
-                         G.stride, 1.0, 0.0, true, skip);                                      // G = X^T X
+    // S = X^T Q X and G = X^T X (lower triangles) in one launch
+    const GemmSecond<double> g2 = {X.p, X.ld, X.stride, G.p, G.ld, G.stride};
+    gemm_batched_pair<double>(st, true, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T1.p, T1.ld, T1.stride, T2.p,
+                              T2.ld, T2.stride, g2, 1.0, 0.0, true, skip);
     hipLaunchKernelGGL(oa_colstats_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, T2, G, X, lam, sL,
                        w.colpart, w.gdiag, skip);
     hipLaunchKernelGGL(oa_delta_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, sL, stats, w.nclust, skip);

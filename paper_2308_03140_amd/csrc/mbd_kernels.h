@@ -124,3 +124,13 @@ void gemm_batched(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int
                   const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C,
                   int ldc, long long sC, T alpha, T beta, bool lower_only, const int* skip = nullptr,
                   const T* Cin = nullptr, int ldcin = 0, long long sCin = 0);
+// the second product of a pair launch: C2 = alpha op(A) op(B2) + beta C2
+template <typename T>
+struct GemmSecond {
+    const T* B; int ldb; long long sB;
+    T* C; int ldc; long long sC;
+};
+template <typename T>
+void gemm_batched_pair(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int nbatch, const T* A, int lda,
+                       long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
+                       const GemmSecond<T>& second, T alpha, T beta, bool lower_only, const int* skip = nullptr);
