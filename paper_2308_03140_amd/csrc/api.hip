@@ -119,9 +119,9 @@ template <> const char* tname<float>() { return "f"; }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// SYMV work-item target for a matrix order: the tuned entry nearest in log(n)
-// targets of the tuned order nearest to n (log scale); 1536 for both ranges
-// when nothing is tuned
+// SYMV work-item targets (upper and lower range of trailing sizes) for a
+// matrix order: those of the tuned order nearest to n on a log scale, 1536
+// for both ranges when nothing is tuned
 std::pair<int, int> tuned_target(const mbd_ctx* c, int prec, int n) {
     const auto& t = c->tune[prec];
     std::pair<int, int> best = {1536, 1536};
