@@ -496,10 +496,11 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         ow.wlen = wsT<int>(c, "oawlen", (size_t)nmax * nmat);
         ow.wv = wsT<double>(c, "oawv", (size_t)OA_KMAX * nmax * nmat);
         ow.gdiag = wsT<double>(c, "oagdiag", (size_t)nmax * nmat);
+        ow.fexp = wsT<int>(c, "oafexp", (size_t)nmax * nmat);
         stats = wsT<double>(c, "oastats", (size_t)8 * nmat);
         int* skip2 = wsT<int>(c, "oaskip2", nmat);
         int* skip3 = wsT<int>(c, "oaskip3", nmat);
-        if (!Xd.p || !Y.p || !S.p || !G.p || !ow.colpart || !ow.nclust || !ow.wstart || !ow.wlen || !ow.wv || !ow.gdiag ||
+        if (!Xd.p || !Y.p || !S.p || !G.p || !ow.colpart || !ow.nclust || !ow.wstart || !ow.wlen || !ow.wv || !ow.gdiag || !ow.fexp ||
             !stats || !skip2 || !skip3)
             return (mbd_status)c->err_code;
         oa_f2d_launch(st, ns_dev, nmax, nmat, X32, Xd);

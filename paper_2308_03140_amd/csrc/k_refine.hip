@@ -546,13 +546,13 @@ __global__ __launch_bounds__(256) void oa_f_kernel(const int* ns, MatBatch<doubl
 //   F_small everything else, (W E')_ij d_j and the single-window diagonal
 //           E'_jj d_j + (d_j - 1): at most the linear correction's size.
 // X + X F_blk is formed exactly in FP64 (at most OA_KMAX columns per output
-// column); X F_small = X32 fl32(F_small) runs on the FP32 matrix cores and is
-// added in FP64.  Its rounding error, about 6e-8 |F_small| relative, stays
-// far below the step's second-order remainder |F_small|^2 and the element
-// error it leaves in Q^{-1/2}.
+// column); X F_small = X32 fl32(F_small) runs on the matrix cores in split
+// FP16 (below) and is added in FP64.  fexp[j] is the power of two that brings
+// the largest |F_small(:, j)| into [2^14, 2^15) for that split.
 __global__ __launch_bounds__(256) void oa_fsmall_kernel(const int* ns, MatBatch<double> Ei, MatBatch<float> Fs,
-                                                          long long sL, const int* wstart, const int* wlen,
+                                                          int* fexp, long long sL, const int* wstart, const int* wlen,
                                                           const double* wv, const double* colpart, const int* skip) {
+    __shared__ float red[4];
     const int b = blockIdx.z;
     if (skip && skip[b]) return;
     const int n = ns[b];
@@ -563,6 +563,7 @@ __global__ __launch_bounds__(256) void oa_fsmall_kernel(const int* ns, MatBatch<
     float* Fj = Fs.at(b) + (long long)j * Fs.ld;
     const int wsj = wstart[o + j];
     const double d = 1.0 / sqrt(1.0 + colpart[(o + j) * OA_CP]);
+    float fmx = 0.0f;
     for (int i = threadIdx.x; i < n; i += 256) {
         const int wi = wstart[o + i], ki = wlen[o + i];
         double f;
@@ -577,7 +578,10 @@ __global__ __launch_bounds__(256) void oa_fsmall_kernel(const int* ns, MatBatch<
             f *= d;
         }
         Fj[i] = (float)f;
+        fmx = fmaxf(fmx, fabsf((float)f));
     }
+    fmx = block_max256(fmx, red);
+    if (threadIdx.x == 0) fexp[o + j] = fmx > 0.0f ? min(110, max(-60, 14 - ilogbf(fmx))) : 0;
 }
 
 // T1 = X + X F_blk, one workgroup per column j
@@ -613,53 +617,164 @@ __global__ __launch_bounds__(256) void oa_fblock_kernel(const int* ns, MatBatch<
 
 // T1 += X32 F_small: FP32 operands on the matrix cores, FP64 accumulation of
 // the result into T1
+// ---------------------------------------------------------------------------
+// C += X32 F_small on the FP16 matrix cores (v_mfma_f32_16x16x32_f16: lane l
+// holds A(m = l % 16, k = 8 (l / 16) + e) and B(k = 8 (l / 16) + e, n = l % 16),
+// e = 0..7, and result rows 4 (l / 16) + r of column l % 16).
+//
+// Each FP32 operand y is split as y = yh + yl, yh = fp16(y), yl = fp16(y - yh),
+// after exact power-of-two scalings that keep both parts in FP16's normal
+// range: X by 2^14 (|x| <= 1 in orthonormal columns), column j of F_small by
+// 2^fexp[j].  X F is taken as Xh Fh + Xh Fl + Xl Fh with FP32 accumulation;
+// the dropped Xl Fl and the parts' rounding leave about 5e-7 |X| |F_small|,
+// far below the step's second-order remainder |F_small|^2.  Three FP16 MFMA
+// products cost less than one FP32 one.  The accumulators are unscaled and
+// added to C in FP64.
+//
+// TS x TS tiles, 2 x 2 wavefronts, K in slabs of 32 staged through LDS
+// (double buffered) as rows of k-contiguous FP16 values, so that each MFMA
+// fragment is one 16-byte LDS read.
+// ---------------------------------------------------------------------------
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <int TS>
-struct XfSmallProb {
-    static constexpr bool A_M_CONTIG = true;
-    static constexpr bool B_N_CONTIG = false;
-    MatBatch<float> X; MatBatch<float> F; MatBatch<double> C; const int* ns; const int* skip; int tiles_n;
-    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
-        t.batch = bz;
-        t.e0 = ns[bz];  // order, read once
-        if (skip && skip[bz]) return false;
-        const int n = ns[bz];
-        int ti, tj;
-        band_tile(xcd_virtual(bx, gridDim.x), tiles_n, tiles_n, ti, tj);
-        t.m0 = ti * TS; t.n0 = tj * TS; t.K = n;
-        return t.m0 < n && t.n0 < n;
+__global__ __launch_bounds__(256) void xf_small_f16_kernel(MatBatch<float> X, MatBatch<float> F, const int* fexp,
+                                                             long long sL, MatBatch<double> C, const int* ns,
+                                                             const int* skip, int tiles_n) {
+    constexpr int BK = 32;              // K of one MFMA step and of one slab
+    constexpr int WT = TS / 2;          // wavefront tile
+    constexpr int MI = WT / 16, NJ = WT / 16;
+    constexpr int LDK = BK + 8;         // halfs per LDS row: 80 bytes, 16-byte aligned
+    constexpr int KPT = BK * TS / 256;  // k values per thread and operand in a slab
+    static_assert(KPT % 8 == 0 && TS * (BK / KPT) == 256, "whole 16-byte LDS row pieces per thread");
+    constexpr int TSZ = TS * LDK;
+    __shared__ __align__(16) _Float16 lds[2][4][TSZ];  // [buffer][Xh, Xl, Fh, Fl]
+    const int b = blockIdx.z;
+    if (skip && skip[b]) return;
+    const int n = ns[b];
+    int ti, tj;
+    band_tile(xcd_virtual(blockIdx.x, gridDim.x), tiles_n, tiles_n, ti, tj);
+    const int m0 = ti * TS, n0 = tj * TS;
+    if (m0 >= n || n0 >= n) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const long long o = (long long)b * sL;
+
+    // staging: thread (rr, kq) loads row m0 + rr of X and column n0 + rr of
+    // F for k = k0 + kq .. k0 + kq + KPT - 1; rows and columns past the order
+    // read a clamped address and are zeroed, and so is k past the order
+    const int rr = tid % TS, kq = (tid / TS) * KPT;
+    const int mr = m0 + rr, nc = n0 + rr;
+    const float* xrow = X.at(b) + (mr < n ? mr : n - 1);
+    const float* fcol = F.at(b) + (long long)(nc < n ? nc : n - 1) * F.ld;
+    const float xsc = mr < n ? 16384.0f : 0.0f;
+    const float fsc = nc < n ? ldexpf(1.0f, fexp[o + nc]) : 0.0f;
+    float xa[KPT], fa[KPT];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < KPT; e++) {
+            const int k = k0 + kq + e;
+            xa[e] = xrow[(long long)(k < n ? k : n - 1) * X.ld];
+        }
+        // F's rows up to the next multiple of 32 lie inside its column (the
+        // leading dimension is a multiple of 64): 16-byte loads
+#pragma unroll
+        for (int e = 0; e < KPT; e += 4) {
+            const f32x4 v = *reinterpret_cast<const f32x4*>(fcol + k0 + kq + e);
+            fa[e] = v[0]; fa[e + 1] = v[1]; fa[e + 2] = v[2]; fa[e + 3] = v[3];
+        }
+#pragma unroll
+        for (int e = 0; e < KPT; e++) {
+            const bool ok = k0 + kq + e < n;
+            xa[e] = ok ? xa[e] * xsc : 0.0f;
+            fa[e] = ok ? fa[e] * fsc : 0.0f;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < KPT / 8; q++) {
+            half8 xh, xl, fh, fl;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const float x = xa[8 * q + e], f = fa[8 * q + e];
+                const _Float16 h = (_Float16)x, g = (_Float16)f;
+                xh[e] = h; xl[e] = (_Float16)(x - (float)h);
+                fh[e] = g; fl[e] = (_Float16)(f - (float)g);
+            }
+            const int off = rr * LDK + kq + 8 * q;
+            *reinterpret_cast<half8*>(&lds[buf][0][off]) = xh;
+            *reinterpret_cast<half8*>(&lds[buf][1][off]) = xl;
+            *reinterpret_cast<half8*>(&lds[buf][2][off]) = fh;
+            *reinterpret_cast<half8*>(&lds[buf][3][off]) = fl;
+        }
+    };
+
+    f32x4 acc[MI][NJ];
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < NJ; j++) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int fo = (lane & 15) * LDK + 8 * (lane >> 4);  // fragment offset inside a 16-row group
+    const int nk = (n + BK - 1) / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt++) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * BK);
+        half8 ah[MI], al[MI], bh[NJ], bl[NJ];
+#pragma unroll
+        for (int i = 0; i < MI; i++) {
+            const int r = (wm * WT + 16 * i) * LDK + fo;
+            ah[i] = *reinterpret_cast<const half8*>(&lds[buf][0][r]);
+            al[i] = *reinterpret_cast<const half8*>(&lds[buf][1][r]);
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            const int r = (wn * WT + 16 * j) * LDK + fo;
+            bh[j] = *reinterpret_cast<const half8*>(&lds[buf][2][r]);
+            bl[j] = *reinterpret_cast<const half8*>(&lds[buf][3][r]);
+        }
+        // the two small cross terms first, then the leading one
+#pragma unroll
+        for (int i = 0; i < MI; i++)
+#pragma unroll
+            for (int j = 0; j < NJ; j++) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        if (kt + 1 < nk) sstore(buf ^ 1);
+        __syncthreads();
     }
-    __device__ float a(const GemmTile& t, int m, int k) const {
-        const int n = t.e0;
-        if (m >= n || k >= n) return 0.0f;
-        return X.at(t.batch)[m + (long long)k * X.ld];
+    double* Cb = C.at(b);
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int col = n0 + wn * WT + 16 * j + (lane & 15);
+        if (col >= n) continue;
+        const double sc = ldexp(1.0, -(14 + fexp[o + col]));
+#pragma unroll
+        for (int i = 0; i < MI; i++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = m0 + wm * WT + 16 * i + 4 * (lane >> 4) + r;
+                if (row < n) Cb[row + (long long)col * C.ld] += (double)acc[i][j][r] * sc;
+            }
     }
-    __device__ float b(const GemmTile& t, int k, int c) const {
-        const int n = t.e0;
-        if (k >= n || c >= n) return 0.0f;
-        return F.at(t.batch)[k + (long long)c * F.ld];
-    }
-    __device__ void store(const GemmTile& t, int m, int c, float v) const {
-        const int n = t.e0;
-        if (m >= n || c >= n) return;
-        C.at(t.batch)[m + (long long)c * C.ld] += (double)v;
-    }
-};
+}
 
 static void xf_small_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32,
-                            MatBatch<float> Fs, MatBatch<double> T1, const int* skip) {
+                            MatBatch<float> Fs, const int* fexp, long long sL, MatBatch<double> T1,
+                            const int* skip) {
     if (nmax >= GEMM_TS128_MIN_ORDER) {
-        typedef Gemm128Shape<float> S;
-        XfSmallProb<128> p;
-        p.X = X32; p.F = Fs; p.C = T1; p.ns = ns; p.skip = skip;
-        p.tiles_n = (nmax + 127) / 128;
-        hipLaunchKernelGGL((gemm_mfma_kernel<float, XfSmallProb<128>, 128, 128, S::BK, S::WM, S::WN>),
-                           dim3(p.tiles_n * p.tiles_n, 1, nbatch), dim3(64 * S::WM * S::WN), 0, st, p);
+        const int t = (nmax + 127) / 128;
+        hipLaunchKernelGGL(xf_small_f16_kernel<128>, dim3(t * t, 1, nbatch), dim3(256), 0, st, X32, Fs, fexp, sL,
+                           T1, ns, skip, t);
     } else {
-        XfSmallProb<64> p;
-        p.X = X32; p.F = Fs; p.C = T1; p.ns = ns; p.skip = skip;
-        p.tiles_n = (nmax + 63) / 64;
-        hipLaunchKernelGGL((gemm_mfma_kernel<float, XfSmallProb<64>>), dim3(p.tiles_n * p.tiles_n, 1, nbatch),
-                           dim3(256), 0, st, p);
+        const int t = (nmax + 63) / 64;
+        hipLaunchKernelGGL(xf_small_f16_kernel<64>, dim3(t * t, 1, nbatch), dim3(256), 0, st, X32, Fs, fexp, sL,
+                           T1, ns, skip, t);
     }
 }
 
@@ -734,15 +849,15 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
                        w.nclust, w.colpart, w.gdiag, skip);                                    // E' -> T1
     if (X32.p) {
         // X is the FP32 eigenvectors: T1 = X + X F_blk (FP64), then
-        // T1 += X32 fl32(F_small) on the FP32 matrix cores; F_small in T2's memory
+        // T1 += X32 fl32(F_small) on the FP16 matrix cores; F_small in T2's memory
         const MatBatch<float> Fs = {(float*)T2.p, T2.ld, 2 * T2.stride};
-        hipLaunchKernelGGL(oa_fsmall_kernel, gc, dim3(256), 0, st, ns, T1, Fs, sL, w.wstart, w.wlen, w.wv,
-                           w.colpart, skip);                                                   // F_small -> T2
+        hipLaunchKernelGGL(oa_fsmall_kernel, gc, dim3(256), 0, st, ns, T1, Fs, w.fexp, sL, w.wstart, w.wlen,
+                           w.wv, w.colpart, skip);                                             // F_small -> T2
         hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats,
                            skip, next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
         hipLaunchKernelGGL(oa_fblock_kernel, gc, dim3(256), 0, st, ns, X, T1, sL, w.wstart, w.wlen, w.wv,
                            w.colpart, skip);                                                   // T1 = X + X F_blk
-        xf_small_launch(st, ns, nmax, nbatch, X32, Fs, T1, skip);                              // T1 += X F_small
+        xf_small_launch(st, ns, nmax, nbatch, X32, Fs, w.fexp, sL, T1, skip);                  // T1 += X F_small
     } else {
         hipLaunchKernelGGL(oa_f_kernel, gc, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, w.colpart,
                            skip);                                                              // F -> T2

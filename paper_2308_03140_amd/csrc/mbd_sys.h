@@ -52,6 +52,7 @@ struct OaWork {
     int* wlen;        // [nbatch][nmax] window length
     double* wv;       // [nbatch][nmax][OA_KMAX] window rotation, per column
     double* gdiag;    // [nbatch][nmax] diagonal of X^T X
+    int* fexp;        // [nbatch][nmax] power-of-two scale of each F_small column (first step)
     double rho_next;  // second-step threshold on the remainder estimate (<= 0: default)
 };
 size_t oa_colpart_doubles(int nmax, int nbatch);
@@ -60,7 +61,7 @@ void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch
 // {delta, max|I - X^T X|, rho, max|X|}; next[b] = 1 where no further step is
 // needed; matrices with skip[b] != 0 get T1 = X and keep lam.  X32.p != nullptr
 // states that X holds exactly the FP32 matrix X32, whose products the update
-// then runs on the FP32 matrix cores
+// then runs on the FP16 matrix cores (split operands)
 void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> Q, MatBatch<double> X,
                     MatBatch<double> T1, MatBatch<double> T2, MatBatch<double> G, double* lam, long long sL,
                     const OaWork& w, double* stats, const int* skip, int* next, MatBatch<float> X32);
