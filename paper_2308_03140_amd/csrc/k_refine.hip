@@ -684,20 +684,17 @@ __global__ __launch_bounds__(256) void xf_small_f16_kernel(MatBatch<float> X, Ma
             const f32x4 v = *reinterpret_cast<const f32x4*>(fcol + k0 + kq + e);
             fa[e] = v[0]; fa[e + 1] = v[1]; fa[e + 2] = v[2]; fa[e + 3] = v[3];
         }
-#pragma unroll
-        for (int e = 0; e < KPT; e++) {
-            const bool ok = k0 + kq + e < n;
-            xa[e] = ok ? xa[e] * xsc : 0.0f;
-            fa[e] = ok ? fa[e] * fsc : 0.0f;
-        }
     };
-    auto sstore = [&](int buf) {
+    // masking, scaling and the split happen here, after the slab's MFMAs,
+    // so that the loads of the next slab are not waited for before them
+    auto sstore = [&](int buf, int k0) {
 #pragma unroll
         for (int q = 0; q < KPT / 8; q++) {
             half8 xh, xl, fh, fl;
 #pragma unroll
             for (int e = 0; e < 8; e++) {
-                const float x = xa[8 * q + e], f = fa[8 * q + e];
+                const bool ok = k0 + kq + 8 * q + e < n;
+                const float x = ok ? xa[8 * q + e] * xsc : 0.0f, f = ok ? fa[8 * q + e] * fsc : 0.0f;
                 const _Float16 h = (_Float16)x, g = (_Float16)f;
                 xh[e] = h; xl[e] = (_Float16)(x - (float)h);
                 fh[e] = g; fl[e] = (_Float16)(f - (float)g);
@@ -718,7 +715,7 @@ __global__ __launch_bounds__(256) void xf_small_f16_kernel(MatBatch<float> X, Ma
     const int fo = (lane & 15) * LDK + 8 * (lane >> 4);  // fragment offset inside a 16-row group
     const int nk = (n + BK - 1) / BK;
     gload(0);
-    sstore(0);
+    sstore(0, 0);
     __syncthreads();
     for (int kt = 0; kt < nk; kt++) {
         const int buf = kt & 1;
@@ -745,7 +742,7 @@ __global__ __launch_bounds__(256) void xf_small_f16_kernel(MatBatch<float> X, Ma
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
             }
-        if (kt + 1 < nk) sstore(buf ^ 1);
+        if (kt + 1 < nk) sstore(buf ^ 1, (kt + 1) * BK);
         __syncthreads();
     }
     double* Cb = C.at(b);
