@@ -626,8 +626,9 @@ __global__ __launch_bounds__(256) void oa_fblock_kernel(const int* ns, MatBatch<
 // after exact power-of-two scalings that keep both parts in FP16's normal
 // range: X by 2^14 (|x| <= 1 in orthonormal columns), column j of F_small by
 // 2^fexp[j].  X F is taken as Xh Fh + Xh Fl + Xl Fh with FP32 accumulation;
-// the dropped Xl Fl and the parts' rounding leave about 5e-7 |X| |F_small|,
-// far below the step's second-order remainder |F_small|^2.  Three FP16 MFMA
+// the dropped Xl Fl and the parts' rounding leave about 2^-22 |X| |F_small|
+// per term, below the FP32 accumulation error that follows and far below the
+// step's second-order remainder |F_small|^2.  Three FP16 MFMA
 // products cost less than one FP32 one.  The accumulators are unscaled and
 // added to C in FP64.
 //
