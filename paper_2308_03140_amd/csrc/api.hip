@@ -5,6 +5,7 @@
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
+#include "gemm_mfma.h"  // GEMM_TS128_MIN_ORDER (merge sizes that take the split product)
 
 #include <cmath>
 #include <cstdio>
@@ -206,6 +207,16 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     dw.Z1 = {wsT<T>(c, "Z1" + t, (size_t)sZ * nbatch), ldz, sZ};
     dw.U = {wsT<T>(c, "U" + t, (size_t)sZ * nbatch), ldz, sZ};
     if (!dw.scale || !dw.Z0.p || !dw.Z1.p || !dw.U.p) return (mbd_status)c->err_code;
+    dw.GA0 = dw.GA1 = dw.GB0 = dw.GB1 = nullptr;
+    // FP32 merges of 2048 and more (which exist once the order exceeds half
+    // of that) take the split product on gathered operands
+    if (sizeof(T) == 4 && 2 * nmax > GEMM_TS128_MIN_ORDER) {
+        dw.GA0 = wsT<T>(c, "GA0" + t, (size_t)sZ * nbatch + 64);
+        dw.GA1 = wsT<T>(c, "GA1" + t, (size_t)sZ * nbatch + 64);
+        dw.GB0 = wsT<T>(c, "GB0" + t, (size_t)sZ * nbatch + 64);
+        dw.GB1 = wsT<T>(c, "GB1" + t, (size_t)sZ * nbatch + 64);
+        if (!dw.GA0 || !dw.GA1 || !dw.GB0 || !dw.GB1) return (mbd_status)c->err_code;
+    }
     dw.w_out = w_out; dw.sW = sW;
     const int src = stedc_launch<T>(dw, nbatch, nmax, st);
     HIPCHK(hipGetLastError(), "stedc");

@@ -220,6 +220,128 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_mfma_kernel(P p) {
     }
 }
 
+// Split-FP16 variant for FP32 problems: C = op(A) op(B) through three FP16
+// MFMA products.  Each operand value y, first multiplied by the problem's
+// power of two (a_scale(t, m) for A's row m, b_scale(t, n) for B's column n,
+// chosen so that |y| < 2^15), is split as y = yh + yl with yh = fp16(y) and
+// yl = fp16(y - yh); the product is taken as Ah Bh + Ah Bl + Al Bh with FP32
+// accumulation (v_mfma_f32_16x16x32_f16).  The parts keep about 22 of FP32's
+// 24 bits and the dropped Al Bl term is of the same order, so the result
+// matches an FP32 product to within its own accumulation error.  p.store
+// receives the scaled accumulator and undoes the scaling.
+//
+// B is read by p.b4(t, k, n): the values at k .. k+3 of column n (k a
+// multiple of 4), from a clamped address; p.b_keep(t, k, n) says which of
+// them count.  The masking happens when the slab is written to LDS, after
+// the previous slab's MFMAs, so the loads stay in flight meanwhile.
+//
+// TS x TS tiles, 2 x 2 wavefronts; thread (r, kq) stages row m0 + r of A and
+// column n0 + r of B over KPT consecutive k of each 32-deep slab, as 16-byte
+// rows of k-contiguous FP16 values in LDS (double buffered), so that each
+// MFMA fragment (lane l: rows l % 16, k = 8 (l / 16) .. + 7) is one LDS read.
+typedef _Float16 gemm_half8 __attribute__((ext_vector_type(8)));
+typedef float gemm_f32x4 __attribute__((ext_vector_type(4)));
+
+template <class P, int TS>
+__global__ __launch_bounds__(256) void gemm_f16x3_kernel(P p) {
+    constexpr int BK = 32;
+    constexpr int WT = TS / 2;
+    constexpr int MI = WT / 16, NJ = WT / 16;
+    constexpr int LDK = BK + 8;         // halfs per LDS row: 80 bytes, 16-byte aligned
+    constexpr int KPT = BK * TS / 256;  // k values per thread and operand in a slab
+    static_assert(KPT % 8 == 0 && TS * (BK / KPT) == 256, "whole 16-byte LDS row pieces per thread");
+    constexpr bool KU = gemm_k_uniform<P>::value;
+    __shared__ __align__(16) _Float16 lds[2][4][TS * LDK];  // [buffer][Ah, Al, Bh, Bl]
+    GemmTile t;
+    if (!p.tile(blockIdx.x, blockIdx.y, blockIdx.z, t)) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int rr = tid % TS, kq = (tid / TS) * KPT;  // kq is wave-uniform
+    const int mr = t.m0 + rr, nc = t.n0 + rr;
+    const float as = p.a_scale(t, mr), bs = p.b_scale(t, nc);
+    float xa[KPT], fa[KPT];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < KPT; e++) {
+            int k = k0 + kq + e;
+            if constexpr (KU) k = __builtin_amdgcn_readfirstlane(k);
+            xa[e] = p.a(t, mr, k);
+        }
+#pragma unroll
+        for (int e = 0; e < KPT; e += 4) {
+            const gemm_f32x4 v = p.b4(t, k0 + kq + e, nc);
+            fa[e] = v[0]; fa[e + 1] = v[1]; fa[e + 2] = v[2]; fa[e + 3] = v[3];
+        }
+    };
+    auto sstore = [&](int buf, int k0) {
+#pragma unroll
+        for (int q = 0; q < KPT / 8; q++) {
+            gemm_half8 ah, al, bh, bl;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const float x = xa[8 * q + e] * as;
+                const float y = p.b_keep(t, k0 + kq + 8 * q + e, nc) ? fa[8 * q + e] * bs : 0.0f;
+                const _Float16 h = (_Float16)x, g = (_Float16)y;
+                ah[e] = h; al[e] = (_Float16)(x - (float)h);
+                bh[e] = g; bl[e] = (_Float16)(y - (float)g);
+            }
+            const int off = rr * LDK + kq + 8 * q;
+            *reinterpret_cast<gemm_half8*>(&lds[buf][0][off]) = ah;
+            *reinterpret_cast<gemm_half8*>(&lds[buf][1][off]) = al;
+            *reinterpret_cast<gemm_half8*>(&lds[buf][2][off]) = bh;
+            *reinterpret_cast<gemm_half8*>(&lds[buf][3][off]) = bl;
+        }
+    };
+    gemm_f32x4 acc[MI][NJ];
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < NJ; j++) acc[i][j] = gemm_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int fo = (lane & 15) * LDK + 8 * (lane >> 4);
+    const int nk = (t.K + BK - 1) / BK;
+    if (nk > 0) {
+        gload(0);
+        sstore(0, 0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt++) {
+            const int buf = kt & 1;
+            if (kt + 1 < nk) gload((kt + 1) * BK);
+            gemm_half8 ah[MI], al[MI], bh[NJ], bl[NJ];
+#pragma unroll
+            for (int i = 0; i < MI; i++) {
+                const int r = (wm * WT + 16 * i) * LDK + fo;
+                ah[i] = *reinterpret_cast<const gemm_half8*>(&lds[buf][0][r]);
+                al[i] = *reinterpret_cast<const gemm_half8*>(&lds[buf][1][r]);
+            }
+#pragma unroll
+            for (int j = 0; j < NJ; j++) {
+                const int r = (wn * WT + 16 * j) * LDK + fo;
+                bh[j] = *reinterpret_cast<const gemm_half8*>(&lds[buf][2][r]);
+                bl[j] = *reinterpret_cast<const gemm_half8*>(&lds[buf][3][r]);
+            }
+            // the two small cross terms first, then the leading one
+#pragma unroll
+            for (int i = 0; i < MI; i++)
+#pragma unroll
+                for (int j = 0; j < NJ; j++) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+            if (kt + 1 < nk) sstore(buf ^ 1, (kt + 1) * BK);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < NJ; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                p.store(t, t.m0 + wm * WT + 16 * i + 4 * (lane >> 4) + r, t.n0 + wn * WT + 16 * j + (lane & 15),
+                        acc[i][j][r]);
+}
+
 // Launch shape of the 128 x 128 tile per type, measured on gfx950 at order
 // 6000: FP64 with 2 x 4 wavefronts and 8-deep K slabs (58 vs 50 TFLOP/s for
 // 64 x 64 tiles), FP32 with 4 x 4 wavefronts and 16-deep slabs (99 vs 88).

@@ -652,6 +652,94 @@ struct DcMergeProb {
     }
 };
 
+// Operands of the split-FP16 merge product, gathered into contiguous columns
+// per half h of a merge at origin o (layout of U, rows and columns counted
+// from o):
+//   GAh(o + mm, o + q) = Zc(o + e0_h + mm, o + c_h(q)), mm < rows of h, q < K_h
+//   GBh(o + q, o + jj) = U(o + l_h(q), o + jj),          q < K_h, jj < K
+// grid x = column, y = merge, z = matrix.
+template <typename T>
+__global__ __launch_bounds__(256) void stedc_gather_merge_kernel(StedcWs<T> w, int lev, int src) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int o = blockIdx.y << lev;
+    if (o >= n) return;
+    const MergeInfo m = merge_of(o, lev, n);
+    if (!m.active()) return;
+    const long long base = (long long)b * w.sV + o;
+    const int x = blockIdx.x;
+    const int K = w.Kcnt[base], kt = w.ktop[base], kb = w.kbot[base];
+    const long long ld = w.U.ld;
+    const long long off = (long long)b * w.U.stride + (o + (long long)x) * ld + o;
+    if (x < K) {
+        const T* Uc = w.U.at(b) + (o + (long long)x) * ld + o;
+        for (int q = threadIdx.x; q < kt; q += 256) w.GB0[off + q] = Uc[w.ltop[base + q]];
+        for (int q = threadIdx.x; q < kb; q += 256) w.GB1[off + q] = Uc[w.lbot[base + q]];
+    }
+    const MatBatch<T>& Zc = src ? w.Z1 : w.Z0;
+    if (x < kt) {
+        const T* Zcol = Zc.at(b) + (o + (long long)w.ctop[base + x]) * Zc.ld + o;
+        for (int r = threadIdx.x; r < m.k1; r += 256) w.GA0[off + r] = Zcol[r];
+    }
+    if (x < kb) {
+        const T* Zcol = Zc.at(b) + (o + (long long)w.cbot[base + x]) * Zc.ld + o + m.k1;
+        for (int r = threadIdx.x; r < m.k - m.k1; r += 256) w.GA1[off + r] = Zcol[r];
+    }
+}
+
+// The merge product of DcMergeProb on the FP16 matrix cores with split
+// operands (FP32 only, 128 x 128 tiles), reading the operands gathered by
+// stedc_gather_merge_kernel (B 16 bytes at a time).  Both hold entries of
+// orthonormal columns (|z| <= 1), so a fixed 2^14 keeps them in FP16's
+// normal range.
+struct DcMergeSplitProb {
+    const int* ns;
+    int lev, tdim, tdh;
+    MatBatch<float> Zn, GA0, GA1, GB0, GB1;
+    const int* outnd; const int* Kcnt; const int* ktop; const int* kbot;
+    long long sV;
+    __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
+        t.batch = bz;
+        const int n = ns[bz];
+        const int o = by << lev;
+        if (o >= n) return false;
+        const MergeInfo m = merge_of(o, lev, n);
+        if (!m.active()) return false;
+        const long long base = (long long)bz * sV + o;
+        const int h = bx / (tdh * tdim), rem = bx - h * (tdh * tdim);
+        const int K = Kcnt[base];
+        t.m0 = (rem / tdim) * 128;
+        t.n0 = (rem % tdim) * 128;
+        t.o = o;
+        t.e0 = h ? m.k1 : 0;                  // first row of the half
+        t.k = h ? m.k - m.k1 : m.k1;          // rows of the half
+        t.K = h ? kbot[base] : ktop[base];    // columns with rows there
+        t.e1 = K;
+        return t.m0 < t.k && t.n0 < K;
+    }
+    __device__ float a_scale(const GemmTile&, int) const { return 16384.0f; }
+    __device__ float b_scale(const GemmTile&, int) const { return 16384.0f; }
+    __device__ float a(const GemmTile& t, int mm, int q) const {
+        if (mm >= t.k || q >= t.K) return 0.0f;
+        const MatBatch<float>& G = t.e0 ? GA1 : GA0;
+        return G.at(t.batch)[(t.o + mm) + (long long)(t.o + q) * G.ld];
+    }
+    // rows q .. q+3 of gathered column jj (clamped to a listed column); the
+    // buffers carry 64 elements of padding past the last matrix
+    __device__ gemm_f32x4 b4(const GemmTile& t, int q, int jj) const {
+        const MatBatch<float>& G = t.e0 ? GB1 : GB0;
+        const int jc = jj < t.e1 ? jj : t.e1 - 1;
+        return *reinterpret_cast<const gemm_f32x4*>(G.at(t.batch) + (t.o + q) + (long long)(t.o + jc) * G.ld);
+    }
+    __device__ bool b_keep(const GemmTile& t, int q, int jj) const { return q < t.K && jj < t.e1; }
+    __device__ void store(const GemmTile& t, int mm, int jj, float v) const {
+        if (mm >= t.k || jj >= t.e1) return;
+        const long long base = (long long)t.batch * sV + t.o;
+        const long long c = t.o + outnd[base + jj];
+        Zn.at(t.batch)[(t.o + t.e0 + mm) + c * Zn.ld] = v * (1.0f / (16384.0f * 16384.0f));
+    }
+};
+
 // same product for small merges (k <= 64): one workgroup per merge
 template <typename T>
 __global__ __launch_bounds__(256) void stedc_small_merge_kernel(StedcWs<T> w, int lev, int src) {
@@ -753,7 +841,25 @@ int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
                 pr.outnd = w.outnd; pr.Kcnt = w.Kcnt; pr.ltop = w.ltop; pr.lbot = w.lbot; pr.ktop = w.ktop;
                 pr.kbot = w.kbot; pr.ctop = w.ctop; pr.cbot = w.cbot; pr.sV = w.sV;
             };
-            if ((1 << lev) >= GEMM_TS128_MIN_ORDER) {
+            if ((1 << lev) >= GEMM_TS128_MIN_ORDER && sizeof(T) == 4 && w.GA0 && w.GA1 && w.GB0 && w.GB1) {
+                // FP32 merges of 2048 and more: both operands gathered into
+                // contiguous columns, then the product on the FP16 matrix
+                // cores with split operands
+                hipLaunchKernelGGL(stedc_gather_merge_kernel<T>, dim3(std::min(1 << lev, nmax), nmerge, nbatch),
+                                   dim3(256), 0, st, w, lev, src);
+                DcMergeSplitProb pr;
+                pr.ns = w.ns; pr.lev = lev;
+                pr.tdim = (1 << lev) / 128;
+                pr.tdh = (1 << (lev - 1)) / 128;
+                pr.Zn = {(float*)(src ? w.Z0 : w.Z1).p, w.Z0.ld, w.Z0.stride};
+                pr.GA0 = {(float*)w.GA0, w.U.ld, w.U.stride};
+                pr.GA1 = {(float*)w.GA1, w.U.ld, w.U.stride};
+                pr.GB0 = {(float*)w.GB0, w.U.ld, w.U.stride};
+                pr.GB1 = {(float*)w.GB1, w.U.ld, w.U.stride};
+                pr.outnd = w.outnd; pr.Kcnt = w.Kcnt; pr.ktop = w.ktop; pr.kbot = w.kbot; pr.sV = w.sV;
+                hipLaunchKernelGGL((gemm_f16x3_kernel<DcMergeSplitProb, 128>), dim3(2 * pr.tdh * pr.tdim, nmerge, nbatch),
+                                   dim3(256), 0, st, pr);
+            } else if ((1 << lev) >= GEMM_TS128_MIN_ORDER) {
                 // merges of 2048 and more: 128 x 128 tiles
                 typedef Gemm128Shape<T> S;
                 DcMergeProb<T, 128> pr;

@@ -94,6 +94,9 @@ struct StedcWs {
     // kept columns with support there (count at the merge origin)
     int* sup; int* ltop; int* lbot; int* ktop; int* kbot;
     int* ctop; int* cbot;  // the listed columns' positions in the merge's eigenvector block
+    // FP32 merges of 2048 and more: their operands gathered per half (layout
+    // of U, 64 elements of padding), or null
+    T* GA0; T* GA1; T* GB0; T* GB1;
     T* w_out; long long sW;       // eigenvalues (ascending) out
 };
 // Returns 0 if the eigenvectors ended in Z0, 1 if in Z1.
