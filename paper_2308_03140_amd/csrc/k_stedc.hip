@@ -451,14 +451,31 @@ __global__ __launch_bounds__(256) void stedc_secular_kernel(StedcWs<T> w, int le
     const double* zn = w.zn + base;
     const double rho = w.rho[base];
     int org;
-    double lo, hi;
+    double lo, hi, x0 = 0.0;
+    bool guess = false;
     if (jx < K - 1) {
         const double mid = 0.5 * (dn[jx] + dn[jx + 1]);
         double f = 0.0;
         for (int i = lane; i < K; i += 64) f += zn[i] * zn[i] / (dn[i] - mid);
-        f = 1.0 + rho * wave_sum(f);
+        const double fs = wave_sum(f);
+        f = 1.0 + rho * fs;
         if (f >= 0.0) { org = jx; lo = 0.0; hi = mid - dn[jx]; }
         else { org = jx + 1; lo = mid - dn[jx + 1]; hi = 0.0; }
+        // starting point: the root of the two nearest poles' terms with the
+        // others frozen at their values at the midpoint, a quadratic in
+        // x = lambda - d_org (the bracket and its bisection fallback stay)
+        const double za = zn[jx] * zn[jx], zb = zn[jx + 1] * zn[jx + 1];
+        const double c = 1.0 + rho * (fs - za / (dn[jx] - mid) - zb / (dn[jx + 1] - mid));
+        const double da = dn[jx] - dn[org], db = dn[jx + 1] - dn[org];
+        const double B = -(c * (da + db) + rho * (za + zb));
+        const double C = c * da * db + rho * (za * db + zb * da);
+        const double disc = B * B - 4.0 * c * C;
+        if (c != 0.0 && disc >= 0.0) {
+            const double q = -0.5 * (B + (B >= 0.0 ? sqrt(disc) : -sqrt(disc)));
+            const double r1 = q / c, r2 = q != 0.0 ? C / q : r1;
+            if (r1 > lo && r1 < hi) { x0 = r1; guess = true; }
+            else if (r2 > lo && r2 < hi) { x0 = r2; guess = true; }
+        }
     } else {
         double z2 = 0.0;
         for (int i = lane; i < K; i += 64) z2 += zn[i] * zn[i];
@@ -470,7 +487,7 @@ __global__ __launch_bounds__(256) void stedc_secular_kernel(StedcWs<T> w, int le
     // by bisection.  Stops when |f| is at its rounding level or the bracket
     // is relatively tight (the Loewner step only needs d_i - lambda =
     // (d_i - d_org) - mu to relative accuracy).
-    double x = 0.5 * (lo + hi);
+    double x = guess ? x0 : 0.5 * (lo + hi);
     for (int it = 0; it < 120; it++) {
         double f = 0.0, fp = 0.0, fa = 0.0;
         for (int i = lane; i < K; i += 64) {
