@@ -229,10 +229,11 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
         const int nblk = (nmax - 1 + 63) / 64;
         ow.sG = (long long)nblk * nsplit * 4096; ow.Gpart = wsT<T>(c, "Gpart" + t, ow.sG * nbatch);
         ow.sT = (long long)nblk * 4096; ow.Tm = wsT<T>(c, "Tm" + t, (size_t)ow.sT * nbatch);
-        ow.sYp = (long long)nsplit * 64 * nmax; ow.Ypart = wsT<T>(c, "Ypart" + t, ow.sYp * nbatch);
-        ow.sY = (long long)64 * nmax; ow.Y = wsT<T>(c, "Yb" + t, ow.sY * nbatch);
+        ow.sYp = (long long)nsplit * 128 * nmax; ow.Ypart = wsT<T>(c, "Ypart" + t, ow.sYp * nbatch);
+        ow.sY = (long long)128 * nmax; ow.Y = wsT<T>(c, "Yb" + t, ow.sY * nbatch);
+        ow.sC = (long long)(nblk / 2 + 1) * 4096; ow.Cp = wsT<T>(c, "Cpair" + t, (size_t)ow.sC * nbatch);
         ow.sVT = (long long)nblk * 64 * nmax; ow.VT = wsT<T>(c, "VT" + t, (size_t)ow.sVT * nbatch);
-        if (!ow.Gpart || !ow.Tm || !ow.Ypart || !ow.Y || !ow.VT) return (mbd_status)c->err_code;
+        if (!ow.Gpart || !ow.Tm || !ow.Ypart || !ow.Y || !ow.VT || !ow.Cp) return (mbd_status)c->err_code;
         ormtr_launch<T>(ow, nbatch, nmax, st);
         HIPCHK(hipGetLastError(), "ormtr");
     }

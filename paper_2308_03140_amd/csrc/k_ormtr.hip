@@ -6,10 +6,14 @@
 //   G = V^T V           split-K over 512-row chunks, partials summed in order
 //   T                   from G and tau (forward column recurrence), one WG
 //   VT = V T            matrix cores, stored densely per block
-// then per block:
-//   Ypart = V^T X       split-K over 512-row chunks on matrix cores
-//   Y = sum Ypart       wide elementwise reduction
-//   X -= VT Y           matrix cores (a rank-64 update: bound by the X traffic)
+// then per pair of blocks h = k+1 (applied first) and k, in one pass over X:
+//   Ypart = [V_k V_h]^T X   split-K over 512-row chunks on matrix cores
+//   Y = sum Ypart           wide elementwise reduction: P_k (rows 0..63), P_h
+//   Y_k = P_k - C_k P_h     C_k = V_k^T VT_h, computed up front for all pairs
+//   X -= VT_k Y_k + VT_h P_h  matrix cores (a rank-128 update)
+// which is block h's update followed by block k's; a block left over (block
+// 0 of an odd count) is applied alone.  Both passes are bound by the X
+// traffic, so pairing halves it.
 // V is read straight from the reduced matrix with the unit diagonal and the
 // zeros above it supplied by the loader.
 #include "mbd_internal.h"
@@ -106,12 +110,14 @@ __global__ __launch_bounds__(256) void ormtr_tfactor_kernel(OrmtrWs<T> w, int ns
     for (int idx = threadIdx.x; idx < 4096; idx += 256) To[idx] = Tm[idx & 63][idx >> 6];
 }
 
-// Ypart[split] = V^T X over the rows of the chunk, 64 x n, in 64 x TN tiles
-template <typename T, int TN>
+// Ypart[split] = V^T X over the rows of the chunk for the NR reflectors from
+// b0 (one block, or a pair), NR x n, in 64 x TN tiles (grid x = NR / 64 row
+// tiles x column tiles)
+template <typename T, int TN, int NR = 64>
 struct VtxProb {
     static constexpr bool A_M_CONTIG = false;
     static constexpr bool B_N_CONTIG = false;
-    MatBatch<T> A; MatBatch<T> X; const int* ns; int b0; T* Ypart; long long sYp; int nmax;
+    MatBatch<T> A; MatBatch<T> X; const int* ns; int b0; T* Ypart; long long sYp; int nmax; int tiles_n;
     __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
         t.e0 = ns[bz];  // order, read once
@@ -120,8 +126,8 @@ struct VtxProb {
         const int m = n - b0 - 1;
         const int r0 = by * ORMTR_CHUNK;
         if (r0 >= m) return false;
-        t.m0 = 0;
-        t.n0 = bx * TN;
+        t.m0 = (bx / tiles_n) * 64;
+        t.n0 = (bx % tiles_n) * TN;
         if (t.n0 >= n) return false;
         t.K = min(ORMTR_CHUNK, m - r0);
         t.o = b0 + 1 + r0;
@@ -138,7 +144,40 @@ struct VtxProb {
     }
     __device__ void store(const GemmTile& t, int jj, int c, T v) const {
         if (c >= t.e0) return;
-        Ypart[(long long)t.batch * sYp + (long long)t.k * 64 * nmax + jj + (long long)c * 64] = v;
+        Ypart[(long long)t.batch * sYp + (long long)t.k * NR * nmax + jj + (long long)c * NR] = v;
+    }
+};
+
+// C_k = V_k^T VT_h (64 x 64) for every pair of blocks k, h = k+1, one
+// workgroup per pair (pair p holds k = nblk - 2 - 2p): the sum runs over the
+// rows of VT_h, b0h+1 .. n-1 (none when block h lies past the order)
+template <typename T>
+struct CpairProb {
+    static constexpr bool A_M_CONTIG = false;
+    static constexpr bool B_N_CONTIG = false;
+    MatBatch<T> A; const int* ns; const T* VT; long long sVT; T* Cp; long long sC; int nmax; int nblk;
+    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
+        t.batch = bz;
+        const int n = ns[bz];
+        t.e0 = n;  // order, read once
+        const int k = nblk - 2 - 2 * bx;
+        if (k < 0) return false;
+        t.m0 = 0; t.n0 = 0;
+        t.o = 64 * k + 64;  // b0 of block h
+        t.K = max(0, n - t.o - 1);
+        t.k = bx;
+        return true;
+    }
+    __device__ T a(const GemmTile& t, int i, int kk) const {
+        if (kk >= t.K) return T(0);
+        return hh_v(A.at(t.batch), A.ld, t.o + 1 + kk, t.o - 64 + i, t.e0 - 1);
+    }
+    __device__ T b(const GemmTile& t, int kk, int j) const {
+        if (kk >= t.K) return T(0);
+        return VT[(long long)t.batch * sVT + (long long)(t.o / 64) * 64 * nmax + (long long)j * nmax + kk];
+    }
+    __device__ void store(const GemmTile& t, int i, int j, T v) const {
+        Cp[(long long)t.batch * sC + (long long)t.k * 4096 + i + j * 64] = v;
     }
 };
 
@@ -176,14 +215,14 @@ struct VtProb {
     }
 };
 
-// Y(:, c) = sum over the row chunks of Ypart(:, c)
+// Y(:, c) = sum over the row chunks of Ypart(:, c), NR rows per column
 template <typename T>
-__global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0) {
+__global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0, int NR) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
     if (b0 >= n - 1) return;
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;  // jj + 64 c
-    if (idx >= 64LL * n) return;
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;  // jj + NR c
+    if (idx >= (long long)NR * n) return;
     const int m = n - b0 - 1;
     const int nsu = (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
     const T* Yp = w.Ypart + (long long)b * w.sYp + idx;
@@ -191,11 +230,36 @@ __global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0) {
     for (int q0 = 0; q0 < nsu; q0 += 8) {
         T v[8];
 #pragma unroll
-        for (int u = 0; u < 8; u++) v[u] = Yp[(long long)min(q0 + u, nsu - 1) * 64 * w.nmax];
+        for (int u = 0; u < 8; u++) v[u] = Yp[(long long)min(q0 + u, nsu - 1) * NR * w.nmax];
 #pragma unroll
         for (int u = 0; u < 8; u++) s += q0 + u < nsu ? v[u] : T(0);
     }
     w.Y[(long long)b * w.sY + idx] = s;
+}
+
+// Y_k = P_k - C_k P_h for pair p (blocks k = b0k / 64 and k + 1): Y holds
+// P_k in rows 0..63 and P_h in rows 64..127 of each column; four columns
+// per workgroup
+template <typename T>
+__global__ __launch_bounds__(256) void ormtr_pair_fix_kernel(OrmtrWs<T> w, int b0k, int p) {
+    __shared__ T C[64][65];
+    __shared__ T Ph[4][64];
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    if (b0k >= n - 1) return;
+    const T* Cg = w.Cp + (long long)b * w.sC + (long long)p * 4096;
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) C[idx & 63][idx >> 6] = Cg[idx];
+    const int lc = threadIdx.x >> 6, i = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + lc;
+    T* Y = w.Y + (long long)b * w.sY;
+    if (c < n) Ph[lc][i] = Y[64 + i + (long long)c * 128];
+    __syncthreads();
+    if (c < n) {
+        T s = T(0);
+#pragma unroll 8
+        for (int j = 0; j < 64; j++) s += C[i][j] * Ph[lc][j];
+        Y[i + (long long)c * 128] -= s;
+    }
 }
 
 // X(b0+1:n, :) -= VT Y, in TS x TS output tiles.  Tile rows are absolute
@@ -203,7 +267,10 @@ __global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0) {
 // leading dimension every 16-byte column segment is aligned; row b0 itself
 // is outside the update (its VT row is zero) and is never written.  The
 // epilogue reads X before the K loop and writes it back in 16-byte segments.
-template <typename T, int TS>
+// With NR = 128 the K dimension spans the pair: columns kk < 64 are VT_k
+// (rows from b0 + 1), kk >= 64 VT_h (rows from b0 + 65); both blocks' VT are
+// adjacent in the VT buffer, and Y holds Y_k over P_h.
+template <typename T, int TS, int NR = 64>
 struct VyProb {
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = false;
@@ -218,16 +285,17 @@ struct VyProb {
         if (b0 >= n - 1) return false;
         t.m0 = b0 + (bx / tiles_n) * TS;
         t.n0 = (bx % tiles_n) * TS;
-        t.K = 64;
+        t.K = NR;
         return t.m0 < n && t.n0 < n;
     }
     __device__ T a(const GemmTile& t, int r, int jj) const {
-        if (r <= b0 || r >= t.e0) return T(0);
-        return VT[(long long)t.batch * sVT + (long long)(b0 / 64) * 64 * nmax + (long long)jj * nmax + (r - b0 - 1)];
+        const int r0 = jj < 64 ? b0 : b0 + 64;  // the reflector block's first row b0 (+1 below)
+        if (r <= r0 || r >= t.e0) return T(0);
+        return VT[(long long)t.batch * sVT + (long long)(b0 / 64) * 64 * nmax + (long long)jj * nmax + (r - r0 - 1)];
     }
     __device__ T b(const GemmTile& t, int jj, int c) const {
         if (c >= t.e0) return T(0);
-        return Y[(long long)t.batch * sY + jj + (long long)c * 64];
+        return Y[(long long)t.batch * sY + jj + (long long)c * NR];
     }
     __device__ Vec epi_load(const GemmTile& t, int r, int c) const {
         const int n = t.e0;
@@ -265,18 +333,43 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     VtProb<T> pv;
     pv.A = w.A; pv.ns = w.ns; pv.Tm = w.Tm; pv.sT = w.sT; pv.VT = w.VT; pv.sVT = w.sVT; pv.nmax = w.nmax;
     hipLaunchKernelGGL((gemm_mfma_kernel<T, VtProb<T>>), dim3(tiles, nblk, nbatch), dim3(256), 0, st, pv);
-    for (int blk = nblk - 1; blk >= 0; blk--) {
-        const int b0 = blk * 64;
-        // (64 x 128 tiles measured slower here: 53 vs 47 us per block at n = 6000)
-        VtxProb<T, 64> px;
+    const int npair = nblk / 2;
+    if (npair > 0) {
+        CpairProb<T> pc;
+        pc.A = w.A; pc.ns = w.ns; pc.VT = w.VT; pc.sVT = w.sVT; pc.Cp = w.Cp; pc.sC = w.sC; pc.nmax = w.nmax;
+        pc.nblk = nblk;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, CpairProb<T>>), dim3(npair, 1, nbatch), dim3(256), 0, st, pc);
+    }
+    // pairs (k, k+1) from the last block down, then block 0 alone if left
+    // (64 x 128 tiles measured slower for V^T X: 53 vs 47 us per block at
+    // n = 6000; 32-deep K slabs too, 48.5 vs 45.5 us; 128 x 128 tiles for the
+    // K = 64 update, 94 vs 83 us per block)
+    int blk = nblk - 1;
+    for (; blk >= 1; blk -= 2) {
+        const int b0 = (blk - 1) * 64;  // block k of the pair
+        const int p = (nblk - 1 - blk) / 2;
+        VtxProb<T, 64, 128> px;
         px.A = w.A; px.X = w.X; px.ns = w.ns; px.b0 = b0; px.Ypart = w.Ypart; px.sYp = w.sYp; px.nmax = w.nmax;
-        // (32-deep K slabs measured slower here: 48.5 vs 45.5 us per block at n = 6000)
-        hipLaunchKernelGGL((gemm_mfma_kernel<T, VtxProb<T, 64>>), dim3(tiles, nsplit, nbatch), dim3(256), 0, st, px);
-        hipLaunchKernelGGL(ormtr_ysum_kernel<T>, dim3((64 * nmax + 255) / 256, 1, nbatch), dim3(256), 0, st, w, b0);
-        // (128 x 128 tiles measured slower for this K = 64 update: 94 vs 83 us per
-        // block at n = 6000)
-        VyProb<T, 64> py;
+        px.tiles_n = tiles;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, VtxProb<T, 64, 128>>), dim3(2 * tiles, nsplit, nbatch), dim3(256), 0,
+                           st, px);
+        hipLaunchKernelGGL(ormtr_ysum_kernel<T>, dim3((128 * nmax + 255) / 256, 1, nbatch), dim3(256), 0, st, w, b0,
+                           128);
+        hipLaunchKernelGGL(ormtr_pair_fix_kernel<T>, dim3((nmax + 3) / 4, 1, nbatch), dim3(256), 0, st, w, b0, p);
+        VyProb<T, 64, 128> py;
         py.X = w.X; py.ns = w.ns; py.b0 = b0; py.VT = w.VT; py.sVT = w.sVT; py.nmax = w.nmax; py.Y = w.Y; py.sY = w.sY;
+        py.tiles_n = tiles;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, VyProb<T, 64, 128>>), dim3(tiles * tiles, 1, nbatch), dim3(256), 0, st,
+                           py);
+    }
+    if (blk == 0) {
+        VtxProb<T, 64> px;
+        px.A = w.A; px.X = w.X; px.ns = w.ns; px.b0 = 0; px.Ypart = w.Ypart; px.sYp = w.sYp; px.nmax = w.nmax;
+        px.tiles_n = tiles;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, VtxProb<T, 64>>), dim3(tiles, nsplit, nbatch), dim3(256), 0, st, px);
+        hipLaunchKernelGGL(ormtr_ysum_kernel<T>, dim3((64 * nmax + 255) / 256, 1, nbatch), dim3(256), 0, st, w, 0, 64);
+        VyProb<T, 64> py;
+        py.X = w.X; py.ns = w.ns; py.b0 = 0; py.VT = w.VT; py.sVT = w.sVT; py.nmax = w.nmax; py.Y = w.Y; py.sY = w.sY;
         py.tiles_n = tiles;
         hipLaunchKernelGGL((gemm_mfma_kernel<T, VyProb<T, 64>>), dim3(tiles * tiles, 1, nbatch), dim3(256), 0, st, py);
     }

@@ -113,8 +113,9 @@ struct OrmtrWs {
     T* Gpart; long long sG;   // [nblk][nsplit][64*64]
     T* Tm; long long sT;      // [nblk][64*64]
     T* VT; long long sVT;     // [nblk][64][nmax]: V T of each block, rows b0+1.. from 0
-    T* Ypart; long long sYp;  // [nsplit][64*nmax]
-    T* Y; long long sY;       // [64*nmax]
+    T* Ypart; long long sYp;  // [nsplit][128*nmax]
+    T* Y; long long sY;       // [128*nmax]: Y of a block, or Y_k over P_h of a pair
+    T* Cp; long long sC;      // [nblk/2][64*64]: V_k^T VT_h per pair of blocks
     int nmax;
 };
 template <typename T>
