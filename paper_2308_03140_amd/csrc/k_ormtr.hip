@@ -148,38 +148,65 @@ struct VtxProb {
     }
 };
 
-// C_k = V_k^T VT_h (64 x 64) for every pair of blocks k, h = k+1, one
-// workgroup per pair (pair p holds k = nblk - 2 - 2p): the sum runs over the
-// rows of VT_h, b0h+1 .. n-1 (none when block h lies past the order)
+// C_k = V_k^T VT_h (64 x 64) for every pair of blocks k, h = k+1 (pair p
+// holds k = nblk - 2 - 2p): the sum runs over the rows of VT_h, b0h+1 ..
+// n-1, split over 512-row chunks (grid x = pair, y = chunk); the partials
+// go to Cpart and are summed in chunk order by ormtr_cpair_sum_kernel.  The
+// first chunk is written even when block h lies past the order (zeros).
 template <typename T>
 struct CpairProb {
     static constexpr bool A_M_CONTIG = false;
     static constexpr bool B_N_CONTIG = false;
-    MatBatch<T> A; const int* ns; const T* VT; long long sVT; T* Cp; long long sC; int nmax; int nblk;
-    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
+    MatBatch<T> A; const int* ns; const T* VT; long long sVT; T* Cpart; long long sCp; int nmax; int nblk; int nsplit;
+    __device__ bool tile(int bx, int by, int bz, GemmTile& t) const {
         t.batch = bz;
         const int n = ns[bz];
         t.e0 = n;  // order, read once
         const int k = nblk - 2 - 2 * bx;
         if (k < 0) return false;
+        const int b0h = 64 * k + 64;
+        const int m = max(0, n - b0h - 1);
+        const int r0 = by * ORMTR_CHUNK;
+        if (by > 0 && r0 >= m) return false;
         t.m0 = 0; t.n0 = 0;
-        t.o = 64 * k + 64;  // b0 of block h
-        t.K = max(0, n - t.o - 1);
-        t.k = bx;
+        t.o = b0h + 1 + r0;        // first row of the chunk
+        t.K = max(0, min(ORMTR_CHUNK, m - r0));
+        t.k = bx * nsplit + by;
+        t.e1 = b0h;
         return true;
     }
     __device__ T a(const GemmTile& t, int i, int kk) const {
         if (kk >= t.K) return T(0);
-        return hh_v(A.at(t.batch), A.ld, t.o + 1 + kk, t.o - 64 + i, t.e0 - 1);
+        return hh_v(A.at(t.batch), A.ld, t.o + kk, t.e1 - 64 + i, t.e0 - 1);
     }
     __device__ T b(const GemmTile& t, int kk, int j) const {
         if (kk >= t.K) return T(0);
-        return VT[(long long)t.batch * sVT + (long long)(t.o / 64) * 64 * nmax + (long long)j * nmax + kk];
+        return VT[(long long)t.batch * sVT + (long long)(t.e1 / 64) * 64 * nmax + (long long)j * nmax +
+                  (t.o - t.e1 - 1 + kk)];
     }
     __device__ void store(const GemmTile& t, int i, int j, T v) const {
-        Cp[(long long)t.batch * sC + (long long)t.k * 4096 + i + j * 64] = v;
+        Cpart[(long long)t.batch * sCp + (long long)t.k * 4096 + i + j * 64] = v;
     }
 };
+
+// Cp[p] = sum over the row chunks of Cpart[p] (in chunk order), one
+// workgroup per pair
+template <typename T>
+__global__ __launch_bounds__(256) void ormtr_cpair_sum_kernel(OrmtrWs<T> w, int nblk, int nsplit) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    const int p = blockIdx.x;
+    const int b0h = 64 * (nblk - 2 - 2 * p) + 64;
+    const int m = max(0, n - b0h - 1);
+    const int nsu = max(1, (m + ORMTR_CHUNK - 1) / ORMTR_CHUNK);
+    const T* Cq = w.Gpart + (long long)b * w.sG + (long long)p * nsplit * 4096;
+    T* Co = w.Cp + (long long)b * w.sC + (long long)p * 4096;
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+        T s = T(0);
+        for (int q = 0; q < nsu; q++) s += Cq[(long long)q * 4096 + idx];
+        Co[idx] = s;
+    }
+}
 
 // VT(block) = V T: rows b0+1 .. n-1 of the block's reflectors times its T
 // factor; grid x = 64-row tile, y = block, z = matrix
@@ -238,26 +265,32 @@ __global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0, i
 }
 
 // Y_k = P_k - C_k P_h for pair p (blocks k = b0k / 64 and k + 1): Y holds
-// P_k in rows 0..63 and P_h in rows 64..127 of each column; four columns
-// per workgroup
+// P_k in rows 0..63 and P_h in rows 64..127 of each column; 64 columns per
+// workgroup, so that C_k is staged once for all of them
 template <typename T>
 __global__ __launch_bounds__(256) void ormtr_pair_fix_kernel(OrmtrWs<T> w, int b0k, int p) {
     __shared__ T C[64][65];
-    __shared__ T Ph[4][64];
+    __shared__ T Ph[64][65];
     const int b = blockIdx.z;
     const int n = w.ns[b];
     if (b0k >= n - 1) return;
+    const int c0 = blockIdx.x * 64;
+    if (c0 >= n) return;
     const T* Cg = w.Cp + (long long)b * w.sC + (long long)p * 4096;
-    for (int idx = threadIdx.x; idx < 4096; idx += 256) C[idx & 63][idx >> 6] = Cg[idx];
-    const int lc = threadIdx.x >> 6, i = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + lc;
     T* Y = w.Y + (long long)b * w.sY;
-    if (c < n) Ph[lc][i] = Y[64 + i + (long long)c * 128];
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+        const int i = idx & 63, q = idx >> 6;
+        C[i][q] = Cg[idx];
+        Ph[q][i] = c0 + q < n ? Y[64 + i + (long long)(c0 + q) * 128] : T(0);
+    }
     __syncthreads();
-    if (c < n) {
+    const int i = threadIdx.x & 63;
+    for (int q = threadIdx.x >> 6; q < 64; q += 4) {
+        const int c = c0 + q;
+        if (c >= n) break;
         T s = T(0);
 #pragma unroll 8
-        for (int j = 0; j < 64; j++) s += C[i][j] * Ph[lc][j];
+        for (int j = 0; j < 64; j++) s += C[i][j] * Ph[q][j];
         Y[i + (long long)c * 128] -= s;
     }
 }
@@ -335,10 +368,13 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     hipLaunchKernelGGL((gemm_mfma_kernel<T, VtProb<T>>), dim3(tiles, nblk, nbatch), dim3(256), 0, st, pv);
     const int npair = nblk / 2;
     if (npair > 0) {
+        // the Gram partials are consumed by the T factors: their buffer
+        // takes the C_k partials
         CpairProb<T> pc;
-        pc.A = w.A; pc.ns = w.ns; pc.VT = w.VT; pc.sVT = w.sVT; pc.Cp = w.Cp; pc.sC = w.sC; pc.nmax = w.nmax;
-        pc.nblk = nblk;
-        hipLaunchKernelGGL((gemm_mfma_kernel<T, CpairProb<T>>), dim3(npair, 1, nbatch), dim3(256), 0, st, pc);
+        pc.A = w.A; pc.ns = w.ns; pc.VT = w.VT; pc.sVT = w.sVT; pc.Cpart = w.Gpart; pc.sCp = w.sG;
+        pc.nmax = w.nmax; pc.nblk = nblk; pc.nsplit = nsplit;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, CpairProb<T>>), dim3(npair, nsplit, nbatch), dim3(256), 0, st, pc);
+        hipLaunchKernelGGL(ormtr_cpair_sum_kernel<T>, dim3(npair, 1, nbatch), dim3(256), 0, st, w, nblk, nsplit);
     }
     // pairs (k, k+1) from the last block down, then block 0 alone if left
     // (64 x 128 tiles measured slower for V^T X: 53 vs 47 us per block at
@@ -355,7 +391,7 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st) {
                            st, px);
         hipLaunchKernelGGL(ormtr_ysum_kernel<T>, dim3((128 * nmax + 255) / 256, 1, nbatch), dim3(256), 0, st, w, b0,
                            128);
-        hipLaunchKernelGGL(ormtr_pair_fix_kernel<T>, dim3((nmax + 3) / 4, 1, nbatch), dim3(256), 0, st, w, b0, p);
+        hipLaunchKernelGGL(ormtr_pair_fix_kernel<T>, dim3((nmax + 63) / 64, 1, nbatch), dim3(256), 0, st, w, b0, p);
         VyProb<T, 64, 128> py;
         py.X = w.X; py.ns = w.ns; py.b0 = b0; py.VT = w.VT; py.sVT = w.sVT; py.nmax = w.nmax; py.Y = w.Y; py.sY = w.sY;
         py.tiles_n = tiles;
