@@ -177,16 +177,30 @@ def mbd_periodic(R, lattice, q_frac, alpha0, omega, rvdw, beta=0.83, a=6.0,
     E = np.zeros(1); eigs = np.empty((nq, 3 * N))
     gR = np.empty((N, 3)) if gradients else None
     ga = np.empty(N) if gradients else None
+    gw = np.empty(N) if gradients else None
+    gv = np.empty(N) if gradients else None
     gl = np.empty((3, 3)) if gradients else None
     rcode = _load().orc_mbd_periodic(N, _p(R), _p(L), nq, _p(qf), ctypes.c_double(gamma),
                                      ctypes.c_double(rc), ctypes.c_double(kc),
                                      _p(_arr(alpha0)), _p(_arr(omega)), _p(_arr(rvdw)),
                                      ctypes.c_double(beta), ctypes.c_double(a), _p(E),
-                                     _p(gR), _p(ga), _p(gl), _p(eigs))
+                                     _p(gR), _p(ga), _p(gw), _p(gv), _p(gl), _p(eigs))
     _check(rcode, "mbd_periodic")
     out = {"energy": float(E[0]), "eigs": eigs}
     if gradients:
-        out.update(grad_R=gR, grad_alpha0=ga, grad_lattice=gl)
+        out.update(grad_R=gR, grad_alpha0=ga, grad_omega=gw, grad_rvdw=gv, grad_lattice=gl)
+    return out
+
+
+def mbd_periodic_c6(R, lattice, q_frac, alpha0, c6, rvdw, beta=0.83, a=6.0, **kw):
+    """Periodic MBD with C6 input: omega = 4 C6 / (3 alpha0^2) (eq:osc-param);
+    the alpha0 gradient at fixed C6 and the C6 gradient by the chain rule."""
+    alpha0 = _arr(alpha0); c6 = _arr(c6)
+    omega = 4.0 * c6 / (3.0 * alpha0 ** 2)
+    out = mbd_periodic(R, lattice, q_frac, alpha0, omega, rvdw, beta, a, gradients=True, **kw)
+    dEdw = out["grad_omega"]
+    out["grad_alpha0_c6"] = out["grad_alpha0"] - 2.0 * omega / alpha0 * dEdw
+    out["grad_c6"] = dEdw * omega / c6
     return out
 
 
@@ -198,17 +212,21 @@ def gauss_legendre(n):
 
 def mbd_finite_freq(R, alpha0, omega, rvdw, beta=0.83, a=6.0, npts=30, sample_atoms=()):
     """Finite MBD energy by the frequency route (eq:log-formula), optionally with
-    dE/dR of the listed atoms from Q^{-1/2} = (2/pi) int (Q + u^2)^{-1} du."""
+    dE/dR, dE/dalpha0 and dE/domega of the listed atoms from
+    Q^{-1/2} = (2/pi) int (Q + u^2)^{-1} du."""
     R = _arr(R, (-1, 3)); N = R.shape[0]
     atoms = np.ascontiguousarray(np.asarray(sample_atoms, dtype=np.int32))
     ns = atoms.size
     E = np.zeros(1)
     g = np.zeros((max(ns, 1), 3))
+    ga = np.zeros(max(ns, 1))
+    gw = np.zeros(max(ns, 1))
     rc = _load().orc_mbd_finite_freq(N, _p(R), _p(_arr(alpha0)), _p(_arr(omega)), _p(_arr(rvdw)),
                                      ctypes.c_double(beta), ctypes.c_double(a), npts, _p(E), ns,
-                                     atoms.ctypes.data_as(_I) if ns else None, _p(g))
+                                     atoms.ctypes.data_as(_I) if ns else None, _p(g), _p(ga), _p(gw))
     _check(rc, "mbd_finite_freq")
-    return {"energy": float(E[0]), "grad_R_sample": g[:ns]}
+    return {"energy": float(E[0]), "grad_R_sample": g[:ns], "grad_alpha0_sample": ga[:ns],
+            "grad_omega_sample": gw[:ns]}
 
 
 def min_coupling_eig(R, alpha0, rvdw, beta=0.83, a=6.0):

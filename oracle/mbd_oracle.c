@@ -439,16 +439,19 @@ static void lattice_free(lattice_t *L) { free(L->img); free(L->rec); }
  *   T[ab]            T_ij(q)
  *   dR[c][ab]        d/dr_c
  *   dA[v][c][ab]     d/dA_vc (Cartesian positions, fractional q fixed)
- * dR, dA may be NULL. */
+ *   d0[ab]           d/dR0, R0 = beta (Rv_i + Rv_j) the damping radius (only
+ *                    the damping correction -(1-g) T depends on it)
+ * dR, dA, d0 may be NULL. */
 static void bloch_pair(const lattice_t *L, const double *r, int self,
                        const double *q, double R0, double a,
                        double *Tre, double *Tim, double *dRre, double *dRim,
-                       double *dAre, double *dAim)
+                       double *dAre, double *dAim, double *d0re, double *d0im)
 {
     const double gamma = L->gamma;
     memset(Tre, 0, 9 * sizeof(double)); memset(Tim, 0, 9 * sizeof(double));
     if (dRre) { memset(dRre, 0, 27 * sizeof(double)); memset(dRim, 0, 27 * sizeof(double)); }
     if (dAre) { memset(dAre, 0, 81 * sizeof(double)); memset(dAim, 0, 81 * sizeof(double)); }
+    if (d0re) { memset(d0re, 0, 9 * sizeof(double)); memset(d0im, 0, 9 * sizeof(double)); }
     double rho[3];
     for (int v = 0; v < 3; v++) {
         rho[v] = 0.0;
@@ -462,7 +465,7 @@ static void bloch_pair(const lattice_t *L, const double *r, int self,
             x[d] = r[d] + nn[0] * L->A[d] + nn[1] * L->A[3 + d] + nn[2] * L->A[6 + d];
         double dist = norm3(x);
         if (dist == 0.0) continue;  /* n = 0, i = j */
-        double F[9] = {0}, dF[27] = {0};
+        double F[9] = {0}, dF[27] = {0}, F0[9] = {0};
         int any = 0;
         if (dist < L->rc) {
             double Te[9], dTe[27];
@@ -476,7 +479,7 @@ static void bloch_pair(const lattice_t *L, const double *r, int self,
         if (omg > DAMP_TAIL) {
             double T0[9], dT0[27];
             orc_dipole(x, T0, dT0);
-            for (int k = 0; k < 9; k++) F[k] -= omg * T0[k];
+            for (int k = 0; k < 9; k++) { F[k] -= omg * T0[k]; F0[k] = gR0 * T0[k]; }
             for (int c = 0; c < 3; c++)
                 for (int k = 0; k < 9; k++)
                     dF[c * 9 + k] -= omg * dT0[c * 9 + k] - gd * x[c] / dist * T0[k];
@@ -486,6 +489,8 @@ static void bloch_pair(const lattice_t *L, const double *r, int self,
         double ph = -(q[0] * x[0] + q[1] * x[1] + q[2] * x[2]);
         double cph = cos(ph), sph = sin(ph);
         for (int k = 0; k < 9; k++) { Tre[k] += F[k] * cph; Tim[k] += F[k] * sph; }
+        if (d0re)
+            for (int k = 0; k < 9; k++) { d0re[k] += F0[k] * cph; d0im[k] += F0[k] * sph; }
         if (dRre)
             for (int c = 0; c < 3; c++)
                 for (int k = 0; k < 9; k++) {
@@ -603,7 +608,7 @@ int orc_assemble_periodic(int N, const double *R, const double *lattice,
             double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
             double Tre[9], Tim[9];
             bloch_pair(&L, r, i == j, q, beta * (rvdw[i] + rvdw[j]), a, Tre, Tim,
-                       NULL, NULL, NULL, NULL);
+                       NULL, NULL, NULL, NULL, NULL, NULL);
             double cc = ci * omega[j] * sqrt(alpha0[j]);
             for (int p = 0; p < 3; p++)
                 for (int s = 0; s < 3; s++) {
@@ -622,11 +627,12 @@ int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
                      const double *alpha0, const double *omega,
                      const double *rvdw, double beta, double a,
                      double *energy, double *grad_R, double *grad_alpha0,
+                     double *grad_omega, double *grad_rvdw,
                      double *grad_lattice, double *eigs)
 {
     if (N < 1 || nq < 1 || det3(lattice) <= 0.0) return 1;
     int n = 3 * N, m = 2 * n;
-    int want_grad = grad_R || grad_alpha0 || grad_lattice;
+    int want_grad = grad_R || grad_alpha0 || grad_omega || grad_rvdw || grad_lattice;
     double Ainv[9], B[9];
     inv3(lattice, Ainv);
     for (int u = 0; u < 3; u++)
@@ -654,6 +660,8 @@ int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
     double esum = 0.0;
     if (grad_R) memset(grad_R, 0, sizeof(double) * 3 * N);
     if (grad_alpha0) memset(grad_alpha0, 0, sizeof(double) * N);
+    if (grad_omega) memset(grad_omega, 0, sizeof(double) * N);
+    if (grad_rvdw) memset(grad_rvdw, 0, sizeof(double) * N);
     if (grad_lattice) memset(grad_lattice, 0, sizeof(double) * 9);
     int rc_out = 0;
     for (int t = 0; t < nq; t++) {
@@ -673,11 +681,15 @@ int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
         double wq = 1.0 / nq;
         double *gRloc = (double *)calloc((size_t)3 * N, sizeof(double));
         double *galoc = (double *)calloc(N, sizeof(double));
+        double *gwloc = (double *)calloc(N, sizeof(double));
+        double *gvloc = (double *)calloc(N, sizeof(double));
         double gl[9] = {0};
 #pragma omp parallel
         {
             double *gRt = (double *)calloc((size_t)3 * N, sizeof(double));
             double *gat = (double *)calloc(N, sizeof(double));
+            double *gwt = (double *)calloc(N, sizeof(double));
+            double *gvt = (double *)calloc(N, sizeof(double));
             double glt[9] = {0};
 #pragma omp for schedule(dynamic)
             for (int i = 0; i < N; i++) {
@@ -685,9 +697,9 @@ int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
                 for (int j = 0; j < N; j++) {
                     double cj = omega[j] * sqrt(alpha0[j]);
                     double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
-                    double Tre[9], Tim[9], dRre[27], dRim[27], dAre[81], dAim[81];
+                    double Tre[9], Tim[9], dRre[27], dRim[27], dAre[81], dAim[81], d0re[9], d0im[9];
                     bloch_pair(&L, r, i == j, q, beta * (rvdw[i] + rvdw[j]), a, Tre, Tim,
-                               dRre, dRim, dAre, dAim);
+                               dRre, dRim, dAre, dAim, d0re, d0im);
                     double cc = ci * cj;
                     /* M_{jb,ia} */
                     double Mre[9], Mim[9];
@@ -700,6 +712,14 @@ int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
                     for (int k = 0; k < 9; k++) P += Mre[k] * Tre[k] - Mim[k] * Tim[k];
                     gat[i] += 0.25 * wq * cc * P / (2.0 * alpha0[i]);
                     gat[j] += 0.25 * wq * cc * P / (2.0 * alpha0[j]);
+                    /* c_i = omega_i sqrt(alpha0_i): dc_i/domega_i = c_i/omega_i */
+                    gwt[i] += 0.25 * wq * cc * P / omega[i];
+                    gwt[j] += 0.25 * wq * cc * P / omega[j];
+                    /* R0 = beta (Rv_i + Rv_j) */
+                    double P0 = 0.0;
+                    for (int k = 0; k < 9; k++) P0 += Mre[k] * d0re[k] - Mim[k] * d0im[k];
+                    gvt[i] += 0.25 * wq * cc * beta * P0;
+                    gvt[j] += 0.25 * wq * cc * beta * P0;
                     if (i != j)
                         for (int c = 0; c < 3; c++) {
                             double X = 0.0;
@@ -720,15 +740,27 @@ int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
             {
                 for (int k = 0; k < 3 * N; k++) gRloc[k] += gRt[k];
                 for (int k = 0; k < N; k++) galoc[k] += gat[k];
+                for (int k = 0; k < N; k++) gwloc[k] += gwt[k];
+                for (int k = 0; k < N; k++) gvloc[k] += gvt[k];
                 for (int k = 0; k < 9; k++) gl[k] += glt[k];
             }
-            free(gRt); free(gat);
+            free(gRt); free(gat); free(gwt); free(gvt);
+        }
+        /* omega_i^2 on the diagonal of Q(q): (1/4) 2 omega_i Re Tr M_ii */
+        for (int i = 0; i < N; i++) {
+            double tr = 0.0;
+            for (int c = 0; c < 3; c++) tr += ME[(size_t)(3 * i + c) * m + 3 * i + c];
+            gwloc[i] += 0.25 * wq * 2.0 * omega[i] * tr;
         }
         if (grad_R) for (int k = 0; k < 3 * N; k++) grad_R[k] += gRloc[k];
         if (grad_alpha0) for (int k = 0; k < N; k++) grad_alpha0[k] += galoc[k];
+        if (grad_omega) for (int k = 0; k < N; k++) grad_omega[k] += gwloc[k];
+        if (grad_rvdw) for (int k = 0; k < N; k++) grad_rvdw[k] += gvloc[k];
         if (grad_lattice) for (int k = 0; k < 9; k++) grad_lattice[k] += gl[k];
-        free(gRloc); free(galoc);
+        free(gRloc); free(galoc); free(gwloc); free(gvloc);
     }
+    /* -(3/2) sum_i omega_i */
+    if (grad_omega && !rc_out) for (int k = 0; k < N; k++) grad_omega[k] -= 1.5;
     if (energy) *energy = rc_out ? NAN : esum / nq;
     lattice_free(&L);
     free(Qre); free(Qim); free(lam); free(V); free(ME);
@@ -827,7 +859,8 @@ int orc_is_positive_definite(int n, const double *A)
 int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
                         const double *omega, const double *rvdw, double beta,
                         double a, int npts, double *energy, int nsample,
-                        const int *atoms, double *grad_R_sample)
+                        const int *atoms, double *grad_R_sample,
+                        double *grad_alpha0_sample, double *grad_omega_sample)
 {
     if (N < 1 || npts < 1) return 1;
     int n = 3 * N;
@@ -884,7 +917,7 @@ int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
         for (int sa = 0; sa < nsample; sa++) {
             int k = atoms[sa];
             double ck = omega[k] * sqrt(alpha0[k]);
-            double gk[3] = {0, 0, 0};
+            double gk[3] = {0, 0, 0}, Sk = 0.0;
             for (int j = 0; j < N; j++) {
                 if (j == k) continue;
                 double cj = omega[j] * sqrt(alpha0[j]);
@@ -893,6 +926,10 @@ int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
                 double T[9], dT[27], g, omg, gd, gR0;
                 orc_dipole(r, T, dT);
                 fermi(d, beta * (rvdw[k] + rvdw[j]), a, &g, &omg, &gd, &gR0);
+                /* S_k = sum_j c_k c_j sum_ab M_{ka,jb} g T_ab */
+                for (int p = 0; p < 3; p++)
+                    for (int s2 = 0; s2 < 3; s2++)
+                        Sk += ck * cj * Mrows[((size_t)sa * 3 + p) * n + 3 * j + s2] * g * T[p * 3 + s2];
                 for (int c = 0; c < 3; c++) {
                     double acc = 0.0;
                     for (int p = 0; p < 3; p++)
@@ -903,7 +940,13 @@ int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
                     gk[c] -= 0.5 * ck * cj * acc;
                 }
             }
-            for (int c = 0; c < 3; c++) grad_R_sample[3 * sa + c] = gk[c];
+            if (grad_R_sample) for (int c = 0; c < 3; c++) grad_R_sample[3 * sa + c] = gk[c];
+            /* dQ/dalpha0_k and dQ/domega_k through c_k and the omega_k^2
+             * diagonal: (1/4) Tr(M dQ) as in the eigenvalue route */
+            double tr = 0.0;
+            for (int c = 0; c < 3; c++) tr += Mrows[((size_t)sa * 3 + c) * n + 3 * k + c];
+            if (grad_alpha0_sample) grad_alpha0_sample[sa] = Sk / (4.0 * alpha0[k]);
+            if (grad_omega_sample) grad_omega_sample[sa] = Sk / (2.0 * omega[k]) + 0.5 * omega[k] * tr - 1.5;
         }
     }
     free(Q); free(S); free(x); free(w); free(Mrows); free(y); free(dsc);

@@ -63,6 +63,9 @@ int orc_assemble_periodic(int N, const double *R, const double *lattice,
 
 /* Periodic MBD per unit cell: E = mean over the q list of E(q)
  * (eq:brillouin-int).  q_frac [nq][3] fractional in the reciprocal basis.
+ * Gradients (each may be NULL) are q-averages of (1/4) Re Tr(M(q) dQ(q)),
+ * M = Q^{-1/2}, minus (3/2) d(sum omega): dE/dR [N][3], dE/dalpha0,
+ * dE/domega and dE/dRv [N] (through the damping correction), and
  * grad_lattice [3][3] = dE/dA_{vc} with Cartesian positions, fractional q,
  * gamma and the term sets fixed.  eigs: nq x 3N Hermitian eigenvalues. */
 int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
@@ -70,6 +73,7 @@ int orc_mbd_periodic(int N, const double *R, const double *lattice, int nq,
                      const double *alpha0, const double *omega,
                      const double *rvdw, double beta, double a,
                      double *energy, double *grad_R, double *grad_alpha0,
+                     double *grad_omega, double *grad_rvdw,
                      double *grad_lattice, double *eigs);
 
 /* Gauss-Legendre nodes/weights on [-1, 1] (Newton on P_n). */
@@ -78,13 +82,16 @@ void orc_gauss_legendre(int n, double *x, double *w);
 /* Finite MBD energy by the imaginary-frequency route eq:log-formula, with the
  * Hermitian form alpha^{1/2} T alpha^{1/2}, eq:dyn-pol and the grid map
  * u = 0.6 (1+x)/(1-x) of Sec. 3.3; ln det by the oracle's own Cholesky.
- * Optionally (nsample > 0) the gradient dE/dR of the listed atoms from
- * Q^{-1/2} = (2/pi) int_0^inf (Q + u^2)^{-1} du, reusing the same factors.
+ * Optionally (nsample > 0) the gradients dE/dR [nsample][3], dE/dalpha0 and
+ * dE/domega [nsample] of the listed atoms from the rows of
+ * Q^{-1/2} = (2/pi) int_0^inf (Q + u^2)^{-1} du, reusing the same factors
+ * (each gradient output may be NULL).
  * Returns 2 if a Cholesky factorisation fails (collapse). */
 int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
                         const double *omega, const double *rvdw, double beta,
                         double a, int npts, double *energy, int nsample,
-                        const int *atoms, double *grad_R_sample);
+                        const int *atoms, double *grad_R_sample,
+                        double *grad_alpha0_sample, double *grad_omega_sample);
 
 /* Smallest eigenvalue of alpha0^{1/2} T^lr alpha0^{1/2} (finite). */
 int orc_min_coupling_eig(int N, const double *R, const double *alpha0,

@@ -4,11 +4,13 @@ the oracle (and the seeded input generators); run from the repository root:
     python tests/golden/make_golden.py crystal_n64 cluster_n2000
 
 crystal_n64.json   64-atom triclinic cell, 4x4x4 Monkhorst-Pack mesh: energy
-                   per cell, dE/dR, dE/dalpha0, dE/dA from the oracle's Jacobi
-                   route (Hermitian matrices by real embedding).
+                   per cell, dE/dR, dE/dalpha0, dE/domega, dE/dRv, dE/dA from
+                   the oracle's Jacobi route (Hermitian matrices by real
+                   embedding).
 cluster_n2000.json N=2000 cluster: energy by the frequency route (48-point
-                   Gauss-Legendre grid, oracle Cholesky) and dE/dR of 8 seeded
-                   atoms from Q^{-1/2} = (2/pi) int (Q + u^2)^{-1} du.
+                   Gauss-Legendre grid, oracle Cholesky) and dE/dR, dE/dalpha0,
+                   dE/domega of 8 seeded atoms from the rows of
+                   Q^{-1/2} = (2/pi) int (Q + u^2)^{-1} du.
 """
 import json
 import os
@@ -29,7 +31,8 @@ def crystal_n64():
     out = oracle.mbd_periodic(c["coords"], c["lattice"], c["q_frac"], c["alpha0"], c["omega"], c["rvdw"],
                               c["beta"], c["a"])
     return {"alpha_scale": c["alpha_scale"], "energy": out["energy"], "grad_R": out["grad_R"].tolist(),
-            "grad_alpha0": out["grad_alpha0"].tolist(), "grad_lattice": out["grad_lattice"].tolist(),
+            "grad_alpha0": out["grad_alpha0"].tolist(), "grad_omega": out["grad_omega"].tolist(),
+            "grad_rvdw": out["grad_rvdw"].tolist(), "grad_lattice": out["grad_lattice"].tolist(),
             "eig_min": float(out["eigs"].min())}
 
 
@@ -39,7 +42,9 @@ def cluster_n2000():
     out = oracle.mbd_finite_freq(c["coords"], c["alpha0"], c["omega"], c["rvdw"], c["beta"], c["a"],
                                  npts=48, sample_atoms=atoms)
     return {"alpha_scale": c["alpha_scale"], "energy": out["energy"], "atoms": atoms,
-            "grad_R_sample": out["grad_R_sample"].tolist(), "route": "frequency, 48 points"}
+            "grad_R_sample": out["grad_R_sample"].tolist(),
+            "grad_alpha0_sample": out["grad_alpha0_sample"].tolist(),
+            "grad_omega_sample": out["grad_omega_sample"].tolist(), "route": "frequency, 48 points"}
 
 
 if __name__ == "__main__":

@@ -234,6 +234,16 @@ def test_frequency_route_equals_eigen_route():
     Ef = oracle.mbd_finite_freq(coords, a0, om, rv, npts=40, sample_atoms=[0, 5])
     assert abs(Ef["energy"] - Ee["energy"]) < 1e-11 * abs(Ee["energy"]) + 1e-15
     np.testing.assert_allclose(Ef["grad_R_sample"], Ee["grad_R"][[0, 5]], atol=1e-10)
+    np.testing.assert_allclose(Ef["grad_alpha0_sample"], Ee["grad_alpha0"][[0, 5]], atol=1e-11)
+    np.testing.assert_allclose(Ef["grad_omega_sample"], Ee["grad_omega"][[0, 5]], atol=1e-10)
+    # and against central differences of the frequency-route energy itself
+    h = 1e-4 * a0[5]
+    ap, am = a0.copy(), a0.copy()
+    ap[5] += h
+    am[5] -= h
+    fd = (oracle.mbd_finite_freq(coords, ap, om, rv, npts=40)["energy"]
+          - oracle.mbd_finite_freq(coords, am, om, rv, npts=40)["energy"]) / (2 * h)
+    np.testing.assert_allclose(Ef["grad_alpha0_sample"][1], fd, rtol=1e-6)
 
 
 def test_gauss_legendre_integrates_polynomials():
@@ -376,3 +386,81 @@ def test_periodic_gradients_fd():
     np.testing.assert_allclose(out["grad_alpha0"][1], _fd(lambda x: E(a=x), a0, 1, 1e-4),
                                rtol=1e-6)
     assert abs(out["grad_R"].sum(axis=0)).max() < 1e-15
+
+
+def test_periodic_omega_rvdw_gradients_fd():
+    R, lat, a0, om, rv = _cell()
+    qf = oracle.monkhorst_pack(2, 2, 1)
+    g, rc, kc = oracle.ewald_defaults(lat)
+    kw = dict(gamma=g, rc=rc, kc=kc)
+    out = oracle.mbd_periodic(R, lat, qf, a0, om, rv, **kw)
+
+    def E(w=om, v=rv):
+        return oracle.mbd_periodic(R, lat, qf, a0, w, v, gradients=False, **kw)["energy"]
+
+    for i in range(3):
+        np.testing.assert_allclose(out["grad_omega"][i], _fd(lambda x: E(w=x), om, i, 1e-5),
+                                   rtol=1e-7, atol=1e-10)
+        np.testing.assert_allclose(out["grad_rvdw"][i], _fd(lambda x: E(v=x), rv, i, 1e-5),
+                                   rtol=1e-6, atol=1e-11)
+    # the damping radius matters here: a non-trivial R_vdW derivative
+    assert abs(out["grad_rvdw"]).max() > 1e-5
+    # Euler: Q(s omega) = s^2 Q(omega), so E is homogeneous of degree one in omega
+    assert abs(np.dot(om, out["grad_omega"]) - out["energy"]) < 1e-13
+
+
+def test_periodic_c6_chain_rule():
+    R, lat, a0, om, rv = _cell(seed=9, N=2)
+    qf = oracle.monkhorst_pack(2, 1, 1)
+    c6 = 0.75 * om * a0 ** 2
+    out = oracle.mbd_periodic_c6(R, lat, qf, a0, c6, rv)
+
+    def Ec6(a, c):
+        return oracle.mbd_periodic(R, lat, qf, a, 4.0 * c / (3.0 * a ** 2), rv, gradients=False)["energy"]
+
+    fd_a = _fd(lambda a: Ec6(a, c6), a0, 1, 1e-4 * a0[1])
+    fd_c = _fd(lambda c: Ec6(a0, c), c6, 1, 1e-4 * c6[1])
+    np.testing.assert_allclose(out["grad_alpha0_c6"][1], fd_a, rtol=1e-6)
+    np.testing.assert_allclose(out["grad_c6"][1], fd_c, rtol=1e-6)
+
+
+def test_periodic_single_atom_lorentz_energy():
+    """One atom per simple cubic cell at q = 0: the lattice sum of T is the
+    Lorentz field -4 pi/(3 L^3) I (tin-foil, no k = 0 term), so Q(0) =
+    omega^2 (1 - 4 pi alpha0/(3 L^3)) I and the energy per cell has the closed
+    form (3/2) omega (sqrt(1 - 4 pi alpha0/(3 L^3)) - 1).  This fixes the
+    normalisation of the periodic energy: one half of sum sqrt(lambda) per
+    q-matrix (each Hermitian eigenvalue counted once), minus (3/2) sum omega,
+    averaged over q (eq:brillouin-int); it tends to 0 like L^-3."""
+    a0, om, rv = 11.0, 0.6, 3.5
+    prev = None
+    for L in (40.0, 80.0, 160.0):
+        E = oracle.mbd_periodic(np.zeros((1, 3)), np.eye(3) * L, [[0.0, 0.0, 0.0]], [a0], [om], [rv],
+                                gradients=False)["energy"]
+        cf = 1.5 * om * (np.sqrt(1.0 - 4.0 * np.pi * a0 / (3.0 * L ** 3)) - 1.0)
+        assert abs(E - cf) < 1e-12, (L, E, cf)
+        if prev is not None:
+            assert abs(prev / E - 8.0) < 0.01
+        prev = E
+
+
+def test_periodic_large_box_limit_dimer():
+    """A heterodimer in a growing simple cubic cell at q = 0 approaches the
+    finite dimer (closed form) with a leading L^-3 error (the images' dipole
+    field) and an L^-5 correction: the ratio of successive errors at L, 2L is
+    close to 8, and two Richardson steps (L^-3, then L^-5) reach the finite
+    energy to about 1e-9 Ha."""
+    Rd = 7.5
+    coords, a0, om, rv, beta = _dimer(R=Rd)
+    Efin, _ = _dimer_closed_form_energy(Rd, a0, om, rv, beta)
+    d = {}
+    for L in (40.0, 80.0, 160.0):
+        E = oracle.mbd_periodic(coords + L / 2, np.eye(3) * L, [[0.0, 0.0, 0.0]], a0, om, rv, beta,
+                                gradients=False)["energy"]
+        d[L] = E - Efin
+    assert abs(d[40.0] / d[80.0] - 8.0) < 0.2
+    assert abs(d[80.0] / d[160.0] - 8.0) < 0.05
+    r1 = (8.0 * d[80.0] - d[40.0]) / 7.0
+    r2 = (8.0 * d[160.0] - d[80.0]) / 7.0
+    assert abs(r2) < 2e-8
+    assert abs((32.0 * r2 - r1) / 31.0) < 2e-9
