@@ -50,7 +50,9 @@ typedef enum {
     MBD_ERR_INVALID_ARGUMENT = 1,   /* bad pointer, size, flag or input value */
     MBD_ERR_NEGATIVE_EIGENVALUE = 2,/* Q not positive definite: the "dipole
                                        collapse" of Sec. 2.1 (complex energy) */
-    MBD_ERR_NOT_CONVERGED = 3,      /* refinement did not reach its target    */
+    MBD_ERR_NOT_CONVERGED = 3,      /* MBD_FP32_REFINED: the FP64 refinement
+                                       missed its target and the FP64 fallback
+                                       is disabled (env MBD_REFINE_FALLBACK=0) */
     MBD_ERR_OUT_OF_MEMORY = 4,      /* device allocation failed or exceeded
                                        MBD_WORKSPACE_LIMIT (bytes, env var)   */
     MBD_ERR_DEVICE = 5,             /* HIP runtime error                      */
@@ -60,8 +62,15 @@ typedef enum {
 /* Arithmetic of the diagonalisation.  MBD_FP64: everything in FP64.
  * MBD_FP32_REFINED: Householder reduction, tridiagonal solve and
  * back-transform in FP32 on matrix cores with FP32 accumulation, then one
- * Ogita-Aishima refinement step of the eigenpairs in FP64 against the FP64 Q;
- * the sqrt(lambda) energy sum, the gradients and the Ewald sums stay FP64. */
+ * Ogita-Aishima refinement step of the eigenpairs in FP64 against the FP64 Q
+ * (a second one where the first leaves a large remainder estimate or cuts a
+ * run of linked near-degenerate columns into windows); the sqrt(lambda)
+ * energy sum, the gradients and the Ewald sums stay FP64.  A system whose
+ * refinement still misses its target after the second step is re-evaluated
+ * on the MBD_FP64 path (then errors[2] = 0), or, with the environment
+ * variable MBD_REFINE_FALLBACK=0 at mbd_create, reported as
+ * MBD_ERR_NOT_CONVERGED.  MBD_REFINE_TOL (at mbd_create) overrides the
+ * remainder threshold, default 3e-5. */
 typedef enum { MBD_FP64 = 0, MBD_FP32_REFINED = 1 } mbd_precision;
 
 /* Second oscillator parameter: omega (Ha) or C6 (Ha bohr^6), related by
@@ -73,7 +82,7 @@ enum {
     MBD_WANT_GRAD_COORDS = 2,
     MBD_WANT_GRAD_ALPHA0 = 4,
     MBD_WANT_GRAD_OMEGA = 8,       /* gradient w.r.t. omega or C6 (param_kind) */
-    MBD_WANT_GRAD_RVDW = 16,       /* finite systems only                      */
+    MBD_WANT_GRAD_RVDW = 16,       /* through the damping radius beta(Rv_i+Rv_j) */
     MBD_WANT_GRAD_LATTICE = 32,    /* periodic systems only                    */
     MBD_WANT_EIGVALS = 64,
     MBD_WANT_ERRORS = 128
@@ -114,7 +123,10 @@ typedef struct {
                                      max|X^T X - I| of the FP32 eigenvectors, the
                                      number of refinement steps taken (1 or 2) and
                                      the estimated largest element error left in
-                                     Q^{-1/2} after the last step (0 for FP64)   */
+                                     Q^{-1/2} after the last step; [1..3] are 0
+                                     for MBD_FP64 and for a system re-evaluated
+                                     on the FP64 path after the refinement missed
+                                     its target.  Written on the device.        */
 } mbd_result;
 
 /* Create a context on HIP device `device` with the given precision.
@@ -135,7 +147,10 @@ mbd_status mbd_set_stream(mbd_ctx *ctx, void *hip_stream);
  * MBD_ERR_NEGATIVE_EIGENVALUE with energy = NaN and, if MBD_WANT_ERRORS,
  * errors[0] = lambda_min; gradients are then not written.  Coincident atoms
  * (distance < 1e-8 bohr) and non-finite or non-positive per-atom inputs give
- * MBD_ERR_INVALID_ARGUMENT. */
+ * MBD_ERR_INVALID_ARGUMENT.  MBD_ERR_NOT_CONVERGED: see mbd_precision.
+ * Periodic systems: the host reads coords and rvdw back once, ordered after
+ * the work already queued on the context's stream, to build the image and
+ * reciprocal-vector lists. */
 mbd_status mbd_evaluate(mbd_ctx *ctx, const mbd_system *sys, unsigned want, mbd_result *out);
 
 /* Many independent finite systems (molecules of uneven size) in one batched

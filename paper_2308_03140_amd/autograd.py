@@ -6,7 +6,9 @@ The forward pass calls mbd_evaluate once with the gradient outputs requested
 for the inputs that need them (the adjoint contraction of the paper's
 eq:mbd-gradient, read as (1/4) Tr(Q^{-1/2} dQ/dX), runs in the library's HIP
 kernels); the backward pass only scales the stored gradients by grad_output.
-Double backward is not supported.
+Double backward is not supported: the backward is marked once-differentiable,
+so asking for a second derivative raises instead of treating the stored
+gradients as constants.
 """
 import ctypes
 
@@ -43,9 +45,9 @@ class MBDEnergy(torch.autograd.Function):
             out("coords", (N, 3), A.MBD_WANT_GRAD_COORDS, "grad_coords")
         if need[1]:
             out("alpha0", (N,), A.MBD_WANT_GRAD_ALPHA0, "grad_alpha0")
-        if need[2] and not periodic:
+        if need[2]:
             out("omega", (N,), A.MBD_WANT_GRAD_OMEGA, "grad_omega_or_c6")
-        if need[3] and not periodic:
+        if need[3]:
             out("rvdw", (N,), A.MBD_WANT_GRAD_RVDW, "grad_rvdw")
         if periodic and need[4]:
             out("lattice", (3, 3), A.MBD_WANT_GRAD_LATTICE, "grad_lattice")
@@ -57,6 +59,7 @@ class MBDEnergy(torch.autograd.Function):
         return E[0].clone()
 
     @staticmethod
+    @torch.autograd.function.once_differentiable
     def backward(ctx, gE):
         g = ctx.grads
 
@@ -66,10 +69,6 @@ class MBDEnergy(torch.autograd.Function):
             v = gE * g[name]
             return v.to(dev) if dev is not None else v
 
-        if ctx.needs_input_grad[2] and "omega" not in g:
-            raise RuntimeError("dE/domega is available for finite systems only")
-        if ctx.needs_input_grad[3] and "rvdw" not in g:
-            raise RuntimeError("dE/dR_vdW is available for finite systems only")
         return (scaled("coords"), scaled("alpha0"), scaled("omega"), scaled("rvdw"),
                 scaled("lattice", ctx.lattice_device), None, None, None, None, None)
 

@@ -25,6 +25,7 @@ struct mbd_ctx {
     std::string err_origin, err_msg;
     LaunchProfiler prof;
     double refine_tol = 0.0;  // second refinement step threshold (MBD_REFINE_TOL; <= 0: library default)
+    bool refine_fallback = true;  // FP64 re-evaluation of unconverged systems (MBD_REFINE_FALLBACK=0: off)
     // autotuned SYMV work-item targets per matrix order, per precision (0 FP64, 1 FP32)
     std::map<int, std::pair<int, int>> tune[2];  // order -> SYMV work-item targets (upper, lower range)
     // captured batch launch sequences, keyed by batch signature
@@ -33,8 +34,6 @@ struct mbd_ctx {
         SysDesc* h_desc = nullptr;     // pinned staging of the system descriptors
         int* h_ns = nullptr;           // pinned matrix orders
         unsigned* h_status = nullptr;  // pinned status read-back
-        double* h_stats = nullptr;     // pinned refinement statistics
-        int* h_skip = nullptr;         // pinned second-step skip flags
         int nsys = 0, nmat = 0;
         bool ok = false;
     };
@@ -47,8 +46,6 @@ struct mbd_ctx {
             hipHostFree(kv.second.h_desc);
             hipHostFree(kv.second.h_ns);
             hipHostFree(kv.second.h_status);
-            hipHostFree(kv.second.h_stats);
-            hipHostFree(kv.second.h_skip);
         }
         graphs.clear();
     }
@@ -243,6 +240,14 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
 
 bool finite_ok(double x) { return std::isfinite(x); }
 
+// status word of a system -> its mbd_status
+int status_code(unsigned st) {
+    if (st & (MBD_ST_BAD_INPUT | MBD_ST_COINCIDENT)) return MBD_ERR_INVALID_ARGUMENT;
+    if (st & MBD_ST_COLLAPSE) return MBD_ERR_NEGATIVE_EIGENVALUE;
+    if (st & MBD_ST_NOT_CONVERGED) return MBD_ERR_NOT_CONVERGED;
+    return MBD_OK;
+}
+
 // Validates the host-visible parts of a system.
 mbd_status check_system(mbd_ctx* c, const mbd_system* s, unsigned want, const mbd_result* o, bool allow_periodic) {
     if (!s || !o) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "null system or result");
@@ -270,8 +275,6 @@ mbd_status check_system(mbd_ctx* c, const mbd_system* s, unsigned want, const mb
     if ((want & MBD_WANT_ERRORS) && !o->errors) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "errors output is NULL");
     if (s->lattice) {
         if (!allow_periodic) return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate_batch", "periodic systems are evaluated one at a time");
-        if (want & (MBD_WANT_GRAD_RVDW | MBD_WANT_GRAD_OMEGA))
-            return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate", "grad_rvdw and grad_omega are for finite systems");
     } else if (want & MBD_WANT_GRAD_LATTICE) {
         return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "grad_lattice needs a lattice");
     }
@@ -341,8 +344,10 @@ mbd_status setup_periodic(mbd_ctx* c, const mbd_system* s, SysDesc& d, PeriodicS
     d.kc = s->ewald_kc > 0 ? s->ewald_kc : 10.0 * d.gamma;
     const int N = s->n_atoms;
     std::vector<double> R(3 * N), rv(N);
-    HIPCHK(hipMemcpy(R.data(), s->coords, sizeof(double) * 3 * N, hipMemcpyDeviceToHost), "read coords");
-    HIPCHK(hipMemcpy(rv.data(), s->rvdw, sizeof(double) * N, hipMemcpyDeviceToHost), "read rvdw");
+    // read on the context stream, so the values are those of the work queued before this call
+    HIPCHK(hipMemcpyAsync(R.data(), s->coords, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c->stream), "read coords");
+    HIPCHK(hipMemcpyAsync(rv.data(), s->rvdw, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream), "read rvdw");
+    HIPCHK(hipStreamSynchronize(c->stream), "read coords");
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, rvmax = 0.0;
     for (int i = 0; i < N; i++) {
         for (int k = 0; k < 3; k++) { lo[k] = std::min(lo[k], R[3 * i + k]); hi[k] = std::max(hi[k], R[3 * i + k]); }
@@ -482,9 +487,9 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     HIPCHK(hipGetLastError(), "assemble");
 
     MatBatch<double> X;
-    std::vector<double> stats_h;
     double* stats = nullptr;
-    int* skip_dev = nullptr;
+    int* skip_dev = nullptr;  // per matrix: refinement step one was enough
+    int* conv_dev = nullptr;  // per matrix: the last step met its target
     if (!fp32) {
         mbd_status r = run_eig<double>(c, A64, ns_dev, nsh.data(), nmax, nmat, grads, lam, nmax, &X);
         if (r != MBD_OK) return r;
@@ -520,10 +525,12 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         oa_step_launch(st, ns_dev, nmax, nmat, A64, Y, S, Xd, G, lam, nmax, ow, stats + 4 * nmat, skip2,
                        skip3, MatBatch<float>{nullptr, 0, 0});                                                                   // X2 in S
         skip_dev = skip2;
+        conv_dev = skip3;
         HIPCHK(hipGetLastError(), "refine");
         X = S;
     }
-    mbd_energy_launch(st, sd_dev, nsys, ns_dev, lam, nmax, om, status, lmin);
+    mbd_energy_launch(st, sd_dev, nsys, ns_dev, lam, nmax, om, status, lmin, conv_dev);
+    mbd_errors_launch(st, sd_dev, nsys, nmat, stats, skip_dev);
     HIPCHK(hipGetLastError(), "energy");
     if (grads) {
         hipLaunchKernelGGL(grad_gate_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, status, nsys, sd_dev);
@@ -533,7 +540,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         mbd_mirror_launch(st, ns_dev, nmax, nmat, M);
         if (per) {
             const int N = sds[0].N;
-            double* part = wsT<double>(c, "gpart", (size_t)nq * N * N * 13);
+            double* part = wsT<double>(c, "gpart", (size_t)nq * N * N * PER_PART);
             if (!part) return (mbd_status)c->err_code;
             mbd_grad_periodic_launch(st, sd_dev, om, cc, qcart, nq, img, (int)per->img.size() / 3, rec,
                                      (int)per->rec.size() / 3, M, part, N);
@@ -544,43 +551,13 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     }
     if (capturing) {
         HIPCHK(hipMemcpyAsync(mode->g->h_status, status, sizeof(unsigned) * nsys, hipMemcpyDeviceToHost, st), "status");
-        if (stats) {
-            HIPCHK(hipMemcpyAsync(mode->g->h_stats, stats, sizeof(double) * 8 * nmat, hipMemcpyDeviceToHost, st),
-                   "status");
-            HIPCHK(hipMemcpyAsync(mode->g->h_skip, skip_dev, sizeof(int) * nmat, hipMemcpyDeviceToHost, st),
-                   "status");
-        }
         return MBD_OK;
     }
     std::vector<unsigned> sth(nsys);
     HIPCHK(hipMemcpyAsync(sth.data(), status, sizeof(unsigned) * nsys, hipMemcpyDeviceToHost, st), "status");
-    std::vector<int> skip_h;
-    if (stats) {
-        stats_h.resize(8 * nmat);
-        skip_h.resize(nmat);
-        HIPCHK(hipMemcpyAsync(stats_h.data(), stats, sizeof(double) * 8 * nmat, hipMemcpyDeviceToHost, st), "status");
-        HIPCHK(hipMemcpyAsync(skip_h.data(), skip_dev, sizeof(int) * nmat, hipMemcpyDeviceToHost, st), "status");
-    }
     HIPCHK(hipStreamSynchronize(st), "synchronize");
-    codes.assign(nsys, MBD_OK);
-    for (int s = 0; s < nsys; s++) {
-        if (sth[s] & (MBD_ST_BAD_INPUT | MBD_ST_COINCIDENT)) codes[s] = MBD_ERR_INVALID_ARGUMENT;
-        else if (sth[s] & MBD_ST_COLLAPSE) codes[s] = MBD_ERR_NEGATIVE_EIGENVALUE;
-        if (sds[s].errors && codes[s] != MBD_ERR_INVALID_ARGUMENT) {
-            double e3[3] = {0.0, 0.0, 0.0};
-            if (stats) {
-                // worst matrix of the system: max|X^T X - I| before refinement,
-                // steps taken, remainder estimate of the last step
-                for (int q = 0; q < sds[s].nmat; q++) {
-                    const int b = sds[s].mat0 + q;
-                    e3[0] = std::max(e3[0], stats_h[4 * b + 1]);
-                    e3[1] = std::max(e3[1], skip_h[b] ? 1.0 : 2.0);
-                    e3[2] = std::max(e3[2], skip_h[b] ? stats_h[4 * b + 2] : stats_h[4 * (nmat + b) + 2]);
-                }
-            }
-            HIPCHK(hipMemcpy(sds[s].errors + 1, e3, sizeof(e3), hipMemcpyHostToDevice), "errors");
-        }
-    }
+    codes.resize(nsys);
+    for (int s = 0; s < nsys; s++) codes[s] = status_code(sth[s]);
     return MBD_OK;
 }
 
@@ -590,7 +567,31 @@ mbd_status code_message(mbd_ctx* c, int code, const char* origin) {
         return fail(c, MBD_ERR_INVALID_ARGUMENT, origin, "non-finite or non-positive per-atom input, or coincident atoms");
     if (code == MBD_ERR_NEGATIVE_EIGENVALUE)
         return fail(c, MBD_ERR_NEGATIVE_EIGENVALUE, origin, "Q has a non-positive eigenvalue (dipole collapse)");
+    if (code == MBD_ERR_NOT_CONVERGED)
+        return fail(c, MBD_ERR_NOT_CONVERGED, origin,
+                    "FP64 refinement of the FP32 eigenpairs missed its target (FP64 fallback disabled)");
     return fail(c, (mbd_status)code, origin, "evaluation failed");
+}
+
+// Re-evaluates, on the FP64 path, the systems of a FP32+refine evaluation
+// whose refinement did not converge (codes[s] == MBD_ERR_NOT_CONVERGED),
+// unless the fallback is disabled.  Their errors[1..3] then read 0 (no
+// refinement step).  per: the periodic setup of a single periodic system.
+mbd_status refine_fallback(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::vector<int>& codes,
+                           const PeriodicSetup* per) {
+    if (c->prec != MBD_FP32_REFINED || !c->refine_fallback) return MBD_OK;
+    std::vector<SysDesc> redo;
+    std::vector<int> idx;
+    for (size_t s = 0; s < sds.size(); s++)
+        if (codes[s] == MBD_ERR_NOT_CONVERGED) { redo.push_back(sds[s]); idx.push_back((int)s); }
+    if (redo.empty()) return MBD_OK;
+    std::vector<int> c2;
+    c->prec = MBD_FP64;
+    const mbd_status r = run_core(c, redo, want, c2, per);
+    c->prec = MBD_FP32_REFINED;
+    if (r != MBD_OK) return r;
+    for (size_t k = 0; k < idx.size(); k++) codes[idx[k]] = c2[k];
+    return MBD_OK;
 }
 
 }  // namespace
@@ -615,6 +616,8 @@ mbd_status mbd_create(mbd_ctx** ctx, int device, mbd_precision prec, void* hip_s
     if (lim) c->limit = (size_t)std::strtoull(lim, nullptr, 10);
     const char* rt = std::getenv("MBD_REFINE_TOL");
     if (rt) c->refine_tol = std::strtod(rt, nullptr);
+    const char* fb = std::getenv("MBD_REFINE_FALLBACK");
+    if (fb && fb[0] == '0') c->refine_fallback = false;
     *ctx = c;
     return MBD_OK;
 }
@@ -653,8 +656,10 @@ mbd_status mbd_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_resu
         r = setup_periodic(c, s, sds[0], ps);
         if (r != MBD_OK) return r;
         r = run_core(c, sds, want, codes, &ps);
+        if (r == MBD_OK) r = refine_fallback(c, sds, want, codes, &ps);
     } else {
         r = run_core(c, sds, want, codes, nullptr);
+        if (r == MBD_OK) r = refine_fallback(c, sds, want, codes, nullptr);
     }
     if (r != MBD_OK) return r;
     return code_message(c, codes[0], "mbd_evaluate");
@@ -695,20 +700,7 @@ mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, 
         HIPCHK(hipEventRecord(c->ev_out, c->gstream), "graph");
         HIPCHK(hipStreamWaitEvent(c->stream, c->ev_out, 0), "graph");
         HIPCHK(hipStreamSynchronize(c->gstream), "graph");
-        for (int i = 0; i < n_sys; i++) {
-            const unsigned st = g.h_status[i];
-            if (st & (MBD_ST_BAD_INPUT | MBD_ST_COINCIDENT)) codes[i] = MBD_ERR_INVALID_ARGUMENT;
-            else if (st & MBD_ST_COLLAPSE) codes[i] = MBD_ERR_NEGATIVE_EIGENVALUE;
-            if (sds[i].errors && codes[i] != MBD_ERR_INVALID_ARGUMENT) {
-                double e3[3] = {0.0, 0.0, 0.0};
-                if (c->prec == MBD_FP32_REFINED) {
-                    e3[0] = g.h_stats[4 * i + 1];
-                    e3[1] = g.h_skip[i] ? 1.0 : 2.0;
-                    e3[2] = g.h_skip[i] ? g.h_stats[4 * i + 2] : g.h_stats[4 * (n_sys + i) + 2];
-                }
-                HIPCHK(hipMemcpy(sds[i].errors + 1, e3, sizeof(e3), hipMemcpyHostToDevice), "errors");
-            }
-        }
+        for (int i = 0; i < n_sys; i++) codes[i] = status_code(g.h_status[i]);
     } else {
         mbd_status r = run_core(c, sds, want, codes, nullptr);
         if (r != MBD_OK) return r;
@@ -725,9 +717,7 @@ mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, 
             g.nmat = n_sys;
             bool ok = hipHostMalloc((void**)&g.h_desc, sizeof(SysDesc) * n_sys, 0) == hipSuccess &&
                       hipHostMalloc((void**)&g.h_ns, sizeof(int) * n_sys, 0) == hipSuccess &&
-                      hipHostMalloc((void**)&g.h_status, sizeof(unsigned) * n_sys, 0) == hipSuccess &&
-                      hipHostMalloc((void**)&g.h_stats, sizeof(double) * 8 * n_sys, 0) == hipSuccess &&
-                      hipHostMalloc((void**)&g.h_skip, sizeof(int) * n_sys, 0) == hipSuccess;
+                      hipHostMalloc((void**)&g.h_status, sizeof(unsigned) * n_sys, 0) == hipSuccess;
             if (ok) {
                 std::memcpy(g.h_desc, sds.data(), sizeof(SysDesc) * n_sys);
                 for (int i = 0; i < n_sys; i++) g.h_ns[i] = 3 * sds[i].N;
@@ -752,6 +742,10 @@ mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, 
             g.ok = ok && g.exec;
             c->graphs[sig] = g;  // a failed capture is remembered: that signature stays eager
         }
+    }
+    {
+        const mbd_status r = refine_fallback(c, sds, want, codes, nullptr);
+        if (r != MBD_OK) return r;
     }
     mbd_status first = MBD_OK;
     for (int i = 0; i < n_sys; i++) {

@@ -102,17 +102,21 @@ __global__ __launch_bounds__(256) void mbd_assemble_finite_kernel(const SysDesc*
 
 // ---------------------------------------------------------------------------
 // energy: E = w sum_k sqrt(lambda_k) - (3/2) sum_i omega_i  (eq:mbd-energy),
-// periodic systems average over their q matrices (eq:brillouin-int)
+// periodic systems average over their q matrices (eq:brillouin-int).
+// conv (may be null): per matrix, 0 where the refinement did not converge;
+// such a system gets the MBD_ST_NOT_CONVERGED status bit.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void mbd_energy_kernel(const SysDesc* sd, const int* ns, const double* lam,
                                                            long long sL, const double* om, unsigned* status,
-                                                           double* lmin_out) {
+                                                           double* lmin_out, const int* conv) {
     __shared__ double red[4];
     const int s = blockIdx.x;
     const SysDesc& S = sd[s];
     double esum = 0.0, lmin = 1e300;
+    bool conv_ok = true;
     for (int q = 0; q < S.nmat; q++) {
         const int b = S.mat0 + q;
+        if (conv && conv[b] == 0) conv_ok = false;
         const int n = ns[b];
         const double* L = lam + (long long)b * sL;
         double part = 0.0, mn = 1e300;
@@ -132,6 +136,7 @@ __global__ __launch_bounds__(256) void mbd_energy_kernel(const SysDesc* sd, cons
     if (threadIdx.x == 0) {
         const bool collapse = !(lmin > 0.0);
         if (collapse) atomicOr(&status[s], MBD_ST_COLLAPSE);
+        if (!conv_ok) atomicOr(&status[s], MBD_ST_NOT_CONVERGED);
         if (S.energy) *S.energy = collapse ? __longlong_as_double(0x7ff8000000000000LL) : esum - 1.5 * wsum;
         lmin_out[s] = lmin;
         if (S.errors) S.errors[0] = lmin;
@@ -145,6 +150,32 @@ __global__ __launch_bounds__(256) void mbd_energy_kernel(const SysDesc* sd, cons
                 S.eigvals[(long long)q * n3 + k] = S.embed ? L[2 * k] : L[k];
         }
     }
+}
+
+// errors[1..3] of each system that asks for them: over the system's
+// matrices, the largest max|X^T X - I| of the FP32 eigenvectors, the number of
+// refinement steps taken and the remainder estimate of the last step (all
+// zero without refinement: stats == null).  stats holds {delta, max|R|, rho,
+// max|X|} per matrix for step one, then for step two; one[b] != 0 where step
+// one was enough.
+__global__ __launch_bounds__(64) void mbd_errors_kernel(const SysDesc* sd, int nsys, int nmat, const double* stats,
+                                                          const int* one) {
+    const int s = blockIdx.x * 64 + threadIdx.x;
+    if (s >= nsys) return;
+    const SysDesc& S = sd[s];
+    if (!S.errors) return;
+    double e1 = 0.0, e2 = 0.0, e3 = 0.0;
+    if (stats) {
+        for (int q = 0; q < S.nmat; q++) {
+            const int b = S.mat0 + q;
+            e1 = fmax(e1, stats[4 * b + 1]);
+            e2 = fmax(e2, one[b] ? 1.0 : 2.0);
+            e3 = fmax(e3, one[b] ? stats[4 * b + 2] : stats[4 * (nmat + b) + 2]);
+        }
+    }
+    S.errors[1] = e1;
+    S.errors[2] = e2;
+    S.errors[3] = e3;
 }
 
 // sc_k = lambda_k^{-1/4}, so that Q^{-1/2} = (X sc)(X sc)^T
@@ -303,8 +334,12 @@ void mbd_assemble_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int
 }
 
 void mbd_energy_launch(hipStream_t st, const SysDesc* sd, int nsys, const int* ns, const double* lam, long long sL,
-                       const double* om, unsigned* status, double* lmin) {
-    hipLaunchKernelGGL(mbd_energy_kernel, dim3(nsys), dim3(256), 0, st, sd, ns, lam, sL, om, status, lmin);
+                       const double* om, unsigned* status, double* lmin, const int* conv) {
+    hipLaunchKernelGGL(mbd_energy_kernel, dim3(nsys), dim3(256), 0, st, sd, ns, lam, sL, om, status, lmin, conv);
+}
+
+void mbd_errors_launch(hipStream_t st, const SysDesc* sd, int nsys, int nmat, const double* stats, const int* one) {
+    hipLaunchKernelGGL(mbd_errors_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sd, nsys, nmat, stats, one);
 }
 
 void mbd_invsqrt4_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const double* lam, long long sL,

@@ -31,9 +31,11 @@ __device__ __forceinline__ void fermi_pair(double d, double R0, double a, double
 }
 
 // Real-space image term F(x) = T^erfc(x) [|x| < rc] - (1-g) T(x) and, if
-// dF != nullptr, dF[c][ab] = dF_ab/dx_c.  Returns false when the term is empty.
+// dF != nullptr, dF[c][ab] = dF_ab/dx_c and F0[ab] = dF_ab/dR0 = (dg/dR0) T(x),
+// R0 = beta (Rv_i + Rv_j) the damping radius (dg/dR0 = -(d/R0) dg/dd).
+// Returns false when the term is empty.
 __device__ __forceinline__ bool image_term(const double* x, double gamma, double rc, double R0, double a,
-                                           double* F, double* dF) {
+                                           double* F, double* dF, double* F0 = nullptr) {
     const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
     const double d = sqrt(r2);
     const bool erfc_on = d < rc;
@@ -63,6 +65,11 @@ __device__ __forceinline__ bool image_term(const double* x, double gamma, double
     const double b = B - w, cc = C - 3.0 * w;
     for (int p = 0; p < 3; p++)
         for (int s = 0; s < 3; s++) F[p * 3 + s] = (p == s ? b * inv3 : 0.0) - cc * x[p] * x[s] * inv5;
+    if (F0) {
+        const double g0 = damp_on ? -gd * d / R0 : 0.0;
+        for (int p = 0; p < 3; p++)
+            for (int s = 0; s < 3; s++) F0[p * 3 + s] = g0 * ((p == s ? inv3 : 0.0) - 3.0 * x[p] * x[s] * inv5);
+    }
     if (dF) {
         // d/dd of the bare tensor pieces: d(1/d^3) = -3/d^4, d(3/d^5) = -15/d^6
         // damping: -(1-g) T, d(1-g)/dd = -gd
@@ -210,7 +217,12 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
 //                                      dG/dA_vc = -G_c Ainv[:, v], dOmega/dA_vc =
 //                                      Omega Ainv_cv)
 //   to dE/dalpha_i, dE/dalpha_j        X = T_ij(q) / (2 alpha)
-// Partial results per (q, i, j): {P, dR[3], dA[9]}.
+//   to dE/domega_i, dE/domega_j        X = T_ij(q) / omega (through c = omega
+//                                      sqrt(alpha0); the omega^2 diagonal adds
+//                                      (1/2) omega_i Re Tr M_ii(q) per q)
+//   to dE/dRv_i, dE/dRv_j              X = beta dT_ij(q)/dR0 (damping radius
+//                                      R0 = beta (Rv_i + Rv_j))
+// Partial results per (q, i, j): {P, dR[3], dA[9], P0}.
 // Same layout as the assembly: one workgroup per ordered pair, one lane per
 // q-point, each real-space image term (F and its derivatives) formed once
 // into LDS and added by every lane with its own phase and M(q).
@@ -218,7 +230,7 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
                                                                       const double* cc, const double* qcart, int nq,
                                                                       const int* img, int nimg, const int* rec,
                                                                       int nrec, MatBatch<double> M, double* part) {
-    __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9], dFs[PER_LANES][27];
+    __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9], dFs[PER_LANES][27], F0s[PER_LANES][9];
     __shared__ int ns_[PER_LANES][3], oks[PER_LANES];
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
@@ -228,7 +240,7 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
     const long long pid = blockIdx.x;
     if (pid >= (long long)N * N) return;
     const int i = (int)(pid % N), j = (int)(pid / N);
-    double* out = part + ((long long)q * N * N + pid) * 13;
+    double* out = part + ((long long)q * N * N + pid) * PER_PART;
     if (S.N == 0) return;
     const double* R = S.coords;
     const double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
@@ -245,7 +257,7 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
     // rho = A^{-T} r  (rho_v = sum_d Ainv[d][v] r_d)
     double rho[3];
     for (int v = 0; v < 3; v++) rho[v] = S.linv[v] * r[0] + S.linv[3 + v] * r[1] + S.linv[6 + v] * r[2];
-    double P = 0.0, dR[3] = {0, 0, 0}, dA[9];
+    double P = 0.0, P0 = 0.0, dR[3] = {0, 0, 0}, dA[9];
     for (int k = 0; k < 9; k++) dA[k] = 0.0;
     for (int t0 = 0; t0 < nimg; t0 += PER_LANES) {
         {
@@ -256,12 +268,13 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
                 double x[3];
                 for (int c = 0; c < 3; c++) x[c] = r[c] + nn[0] * S.lat[c] + nn[1] * S.lat[3 + c] + nn[2] * S.lat[6 + c];
                 const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-                double F[9], dF[27];
-                if (d2 != 0.0 && image_term(x, S.gamma, S.rc, R0, S.a, F, dF)) {
+                double F[9], dF[27], F0[9];
+                if (d2 != 0.0 && image_term(x, S.gamma, S.rc, R0, S.a, F, dF, F0)) {
                     ok = 1;
                     for (int c = 0; c < 3; c++) { xs[threadIdx.x][c] = x[c]; ns_[threadIdx.x][c] = nn[c]; }
                     for (int k = 0; k < 9; k++) Fs[threadIdx.x][k] = F[k];
                     for (int k = 0; k < 27; k++) dFs[threadIdx.x][k] = dF[k];
+                    for (int k = 0; k < 9; k++) F0s[threadIdx.x][k] = F0[k];
                 }
             }
             oks[threadIdx.x] = ok;
@@ -276,11 +289,14 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
         const int* nn = ns_[u];
         double sph, cph;
         sincos(-(qv[0] * x[0] + qv[1] * x[1] + qv[2] * x[2]), &sph, &cph);
-        double SF = 0.0, SFi = 0.0, SdF[3] = {0, 0, 0}, SdFi[3] = {0, 0, 0};
+        double SF = 0.0, SFi = 0.0, SdF[3] = {0, 0, 0}, SdFi[3] = {0, 0, 0}, SF0 = 0.0, SF0i = 0.0;
         for (int k = 0; k < 9; k++) {
             SF += Mr[k] * F[k];
             SFi += Mi[k] * F[k];
+            SF0 += Mr[k] * F0s[u][k];
+            SF0i += Mi[k] * F0s[u][k];
         }
+        P0 += SF0 * cph - SF0i * sph;
         for (int c = 0; c < 3; c++)
             for (int k = 0; k < 9; k++) {
                 SdF[c] += Mr[k] * dF[c * 9 + k];
@@ -356,11 +372,13 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
     out[0] = P;
     for (int c = 0; c < 3; c++) out[1 + c] = dR[c];
     for (int k = 0; k < 9; k++) out[4 + k] = dA[k];
+    out[13] = P0;
 }
 
 // per-atom reduction in a fixed order; atom N (one extra block) sums the lattice term
-__global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const SysDesc* sd, int nq, const double* cc,
-                                                                         const double* part) {
+__global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const SysDesc* sd, int nq, const double* om,
+                                                                         const double* cc, const double* part,
+                                                                         MatBatch<double> M) {
     __shared__ double red[4];
     const SysDesc& S = sd[0];
     const int N = S.N;
@@ -368,13 +386,13 @@ __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const Sys
     const int k = blockIdx.x;
     const double wq = 0.25 / nq;
     if (k < N) {
-        double g0 = 0, g1 = 0, g2 = 0, ga = 0;
+        double g0 = 0, g1 = 0, g2 = 0, ga = 0, gv = 0, tr = 0;
         const long long NN = (long long)N * N;
         for (long long idx = threadIdx.x; idx < (long long)nq * N; idx += 256) {
             const int q = (int)(idx / N), o = (int)(idx % N);
             // k as j (second index), partner i = o
-            const double* pj = part + ((long long)q * NN + (long long)k * N + o) * 13;   // pid = i + j*N: i=o, j=k
-            const double* pi = part + ((long long)q * NN + (long long)o * N + k) * 13;   // i=k, j=o
+            const double* pj = part + ((long long)q * NN + (long long)k * N + o) * PER_PART;   // pid = i + j*N: i=o, j=k
+            const double* pi = part + ((long long)q * NN + (long long)o * N + k) * PER_PART;   // i=k, j=o
             const double cj = cc[S.atom_off + o] * cc[S.atom_off + k];
             if (o != k) {
                 g0 += cj * (pj[1] - pi[1]);
@@ -382,18 +400,38 @@ __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const Sys
                 g2 += cj * (pj[3] - pi[3]);
             }
             ga += cj * (pj[0] + pi[0]);
+            gv += cj * (pj[13] + pi[13]);
+        }
+        // Re Tr M_kk(q), summed over q
+        for (int q = threadIdx.x; q < nq; q += 256) {
+            const double* Mb = M.at(q);
+            for (int c = 0; c < 3; c++) tr += Mb[(3 * k + c) + (long long)(3 * k + c) * M.ld];
         }
         g0 = block_sum256(g0, red);
         g1 = block_sum256(g1, red);
         g2 = block_sum256(g2, red);
         ga = block_sum256(ga, red);
+        gv = block_sum256(gv, red);
+        tr = block_sum256(tr, red);
         if (threadIdx.x == 0) {
             if (S.grad_coords) {
                 S.grad_coords[3 * k] = wq * g0;
                 S.grad_coords[3 * k + 1] = wq * g1;
                 S.grad_coords[3 * k + 2] = wq * g2;
             }
-            if (S.grad_alpha0) S.grad_alpha0[k] = wq * ga / (2.0 * S.alpha0[k]);
+            const double a0 = S.alpha0[k];
+            const double w = om[S.atom_off + k];
+            const double dEda = wq * ga / (2.0 * a0);
+            const double dEdw = wq * ga / w + wq * 2.0 * w * tr - 1.5;
+            if (S.param_kind == 1) {
+                // omega = 4 C6/(3 alpha0^2)
+                if (S.grad_alpha0) S.grad_alpha0[k] = dEda - 2.0 * w / a0 * dEdw;
+                if (S.grad_omega) S.grad_omega[k] = dEdw * w / S.omega_or_c6[k];
+            } else {
+                if (S.grad_alpha0) S.grad_alpha0[k] = dEda;
+                if (S.grad_omega) S.grad_omega[k] = dEdw;
+            }
+            if (S.grad_rvdw) S.grad_rvdw[k] = wq * S.beta * gv;
         }
     } else {
         double la[9];
@@ -403,7 +441,7 @@ __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const Sys
             const long long pid = idx % ((long long)N * N);
             const int i = (int)(pid % N), j = (int)(pid / N);
             const double cij = cc[S.atom_off + i] * cc[S.atom_off + j];
-            const double* p = part + idx * 13;
+            const double* p = part + idx * PER_PART;
             for (int v = 0; v < 9; v++) la[v] += cij * p[4 + v];
         }
         for (int v = 0; v < 9; v++) {
@@ -427,5 +465,5 @@ void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* o
     const long long pairs = (long long)N * N;
     hipLaunchKernelGGL(mbd_grad_periodic_kernel, dim3((unsigned)pairs, (nq + PER_LANES - 1) / PER_LANES),
                        dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, img, nimg, rec, nrec, M, partial);
-    hipLaunchKernelGGL(mbd_grad_periodic_reduce_kernel, dim3(N + 1), dim3(256), 0, st, sd, nq, cc, partial);
+    hipLaunchKernelGGL(mbd_grad_periodic_reduce_kernel, dim3(N + 1), dim3(256), 0, st, sd, nq, om, cc, partial, M);
 }

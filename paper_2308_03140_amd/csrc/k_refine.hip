@@ -32,9 +32,13 @@
 // column j grows in norm by eta_j = sum_{i != j} E'_ij^2, and
 // rho = max_j eta_j max_r|X_rj|^2 / sqrt(lam_j) estimates the largest element
 // error it leaves in Q^{-1/2} = X diag(lam^{-1/2}) X^T before the column
-// rescaling below.  A matrix takes a second step when rho > OA_RHO_NEXT; the
-// decision stays on the device (per-matrix skip flags), so captured launch
-// graphs remain valid.
+// rescaling below.  A matrix takes a second step when rho > OA_RHO_NEXT or
+// when the step cut a run of linked columns into windows of OA_KMAX (a cut
+// between columns whose lam agree to rounding is harmless and not counted):
+// the second step's runs then form around the old cut, where the pairs left
+// over sit.  If the second step again ends with rho above the threshold or
+// with a cut, the matrix is reported as not converged.  The decisions stay on
+// the device (per-matrix flags), so captured launch graphs remain valid.
 #include "mbd_internal.h"
 #include "gemm_mfma.h"
 #include "mbd_kernels.h"
@@ -187,7 +191,8 @@ __device__ __forceinline__ bool oa_break(const double* Sb, int lds, const double
 
 __global__ __launch_bounds__(256) void oa_windows_kernel(const int* ns, MatBatch<double> S, MatBatch<double> G,
                                                            const double* lam, long long sL, double* colpart,
-                                                           int* wstart, int* wlen, const int* skip) {
+                                                           int* wstart, int* wlen, unsigned* nclust,
+                                                           const int* skip) {
     __shared__ int last[256], first[256];
     __shared__ double red[4];
     const int b = blockIdx.x;
@@ -227,14 +232,20 @@ __global__ __launch_bounds__(256) void oa_windows_kernel(const int* ns, MatBatch
         if (wl[i]) run = i;
         ws[i] = run;
     }
+    unsigned ncut = 0;
     for (int i = i1 - 1; i >= i0; i--) {  // run ends, then chunks
         const bool brk = wl[i] != 0;
         const int rs = ws[i];
         const int cs = rs + OA_KMAX * ((i - rs) / OA_KMAX);
+        // a chunk boundary inside a run: the linked pair (i - 1, i) is
+        // left to the linear correction, which the link test judged
+        // inaccurate for it (harmless only when their lam agree to rounding)
+        if (cs == i && i != rs && fabs(L[i] - L[i - 1]) > tiny) ncut++;
         ws[i] = cs;
         wl[i] = min(cs + OA_KMAX, nxt) - cs;
         if (brk) nxt = i;
     }
+    if (ncut) atomicAdd(&nclust[b], ncut);
 }
 
 // Rayleigh-Ritz per window of k >= 2 columns: one 64-lane block, k <= 32.
@@ -476,8 +487,9 @@ __global__ __launch_bounds__(256) void oa_e_kernel(const int* ns, MatBatch<doubl
                     if (fabs(dl) > 64.0 * num_limits<double>::eps * fmax(fabs(li), fabs(lj))) {
                         e = (sp - lj * gp) / dl;
                     } else {
+                        // lam agree to rounding: the pair's rotation leaves
+                        // Q^{-1/2} unchanged, only its symmetric part is kept
                         e = -0.5 * gp;
-                        if (i < j) atomicAdd(&nclust[b], 1u);
                     }
                     const double ee = e * e;
                     const double gii = ki == 1 ? gdu[u] : 1.0;
@@ -777,12 +789,14 @@ static void xf_small_launch(hipStream_t st, const int* ns, int nmax, int nbatch,
 }
 
 // rho = max_c eta_c max|x_c|^2 / sqrt(lam_c) -> stats[4b+2]; next[b] = 1
-// (skip the next step) unless rho > the threshold; lam <- Rayleigh quotients
-// of the refined columns
+// (skip the next step) unless rho > the threshold or the step left pairs it
+// could not treat accurately (runs of linked columns cut into windows, pairs
+// of different windows whose lam agree to rounding); lam <- Rayleigh
+// quotients of the refined columns
 __global__ __launch_bounds__(256) void oa_next_kernel(const int* ns, const double* colpart, double* lam,
                                                         long long sL, MatBatch<double> G, const int* wlen,
-                                                        double* stats, const int* skip, int* next,
-                                                        double rho_next) {
+                                                        double* stats, const unsigned* nclust, const int* skip,
+                                                        int* next, double rho_next) {
     __shared__ double red[4];
     const int b = blockIdx.x;
     if (skip && skip[b]) {
@@ -804,7 +818,7 @@ __global__ __launch_bounds__(256) void oa_next_kernel(const int* ns, const doubl
     rho = block_max256(rho, red);
     if (threadIdx.x == 0) {
         stats[4 * b + 2] = rho;
-        next[b] = rho > rho_next ? 0 : 1;
+        next[b] = (rho > rho_next || nclust[b] != 0u) ? 0 : 1;
     }
 }
 
@@ -837,7 +851,7 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
                        w.colpart, w.gdiag, skip);
     hipLaunchKernelGGL(oa_delta_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, sL, stats, w.nclust, skip);
     hipLaunchKernelGGL(oa_windows_kernel, dim3(nbatch), dim3(256), 0, st, ns, T2, G, lam, sL, w.colpart, w.wstart,
-                       w.wlen, skip);
+                       w.wlen, w.nclust, skip);
     hipLaunchKernelGGL(oa_rr_kernel, dim3(nmax, 1, nbatch), dim3(64), 0, st, ns, T2, G, lam, sL, w.wstart,
                        w.wlen, w.wv, skip);
     // both triangles of S and G for the column-contiguous reads of the E' pass
@@ -852,7 +866,7 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
         hipLaunchKernelGGL(oa_fsmall_kernel, gc, dim3(256), 0, st, ns, T1, Fs, w.fexp, sL, w.wstart, w.wlen,
                            w.wv, w.colpart, skip);                                             // F_small -> T2
         hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats,
-                           skip, next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
+                           w.nclust, skip, next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
         hipLaunchKernelGGL(oa_fblock_kernel, gc, dim3(256), 0, st, ns, X, T1, sL, w.wstart, w.wlen, w.wv,
                            w.colpart, skip);                                                   // T1 = X + X F_blk
         xf_small_launch(st, ns, nmax, nbatch, X32, Fs, w.fexp, sL, T1, skip);                  // T1 += X F_small
@@ -860,7 +874,7 @@ void oa_step_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatc
         hipLaunchKernelGGL(oa_f_kernel, gc, dim3(256), 0, st, ns, T1, T2, sL, w.wstart, w.wlen, w.wv, w.colpart,
                            skip);                                                              // F -> T2
         hipLaunchKernelGGL(oa_next_kernel, dim3(nbatch), dim3(256), 0, st, ns, w.colpart, lam, sL, G, w.wlen, stats,
-                           skip, next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
+                           w.nclust, skip, next, w.rho_next > 0.0 ? w.rho_next : OA_RHO_NEXT);
         gemm_batched<double>(st, false, false, ns, nmax, nbatch, X.p, X.ld, X.stride, T2.p, T2.ld, T2.stride, T1.p,
                              T1.ld, T1.stride, 1.0, 1.0, false, skip, X.p, X.ld, X.stride);    // T1 = X + X F
     }

@@ -11,9 +11,11 @@
 // launches over all merges of all matrices of a batch, so the sequence is
 // independent of the data and can be captured once in a HIP graph.
 //
-// Secular roots: one wavefront per root, bisection in the variable
-// mu = lambda - d_origin, where the origin is the pole the root is closer to,
-// so differences d_i - lambda are formed without cancellation.
+// Secular roots: one wavefront per root, a safeguarded Newton iteration in the
+// variable mu = lambda - d_origin, where the origin is the pole the root is
+// closer to, so differences d_i - lambda are formed without cancellation; the
+// sign of the secular function keeps a bracket and a bisection step replaces
+// any Newton step that leaves it.
 #include <algorithm>
 
 #include "mbd_internal.h"

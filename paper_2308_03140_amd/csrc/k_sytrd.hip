@@ -19,15 +19,13 @@
 // half).  The accumulation order of the atomics varies, so results agree
 // between runs to rounding, not bitwise.
 //
-// The two phases of all NBP columns of a panel run in one persistent
-// cooperative launch (a grid-wide sync after each phase), so the column loop
-// costs two grid barriers per column instead of two kernel launches.  A
-// launch-per-phase path with the same device code is kept for devices where
-// the cooperative launch is refused.  Every work item carries a batch index,
-// so one launch sequence serves a single large matrix and batches of uneven
-// matrices alike.
-#include <hip/hip_cooperative_groups.h>
-
+// Each phase is one launch per column: two dependent launches per column.  A
+// cooperative kernel with a grid-wide barrier after each phase and a single
+// launch that fused the phases through device-scope counters were both
+// measured slower on gfx950 (a grid barrier or a release fence per workgroup
+// costs more than a dependent launch).  Every work item carries a batch
+// index, so one launch sequence serves a single large matrix and batches of
+// uneven matrices alike.
 #include <algorithm>
 #include <cstdlib>
 #include <string>
@@ -36,7 +34,6 @@
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 
-namespace cg = cooperative_groups;
 
 // occupancy target of the SYMV kernel (waves per SIMD): the largest at which
 // the compiler keeps the tile loop free of register spills
@@ -675,47 +672,6 @@ __global__ __launch_bounds__(256) void sytrd_finish_kernel(SytrdWs<T> w, int i, 
     finish_item<T, NBP>(w, b, n, i, j, R);
 }
 
-// all columns [k0, k1) of one panel in one cooperative launch
-template <typename T, int NBP>
-__global__ __launch_bounds__(256) void sytrd_panel_kernel(SytrdWs<T> w, int k0, int k1, int nbatch, int target) {
-    cg::grid_group grid = cg::this_grid();
-    const int P = gridDim.x;
-    for (int i = k0; i < k1; i++) {
-        const int j = i - k0;
-        const int b0 = (i + 1) >> 6;
-        const int nbt = w.nbk_max - b0;
-        const int Kt = sytrd_kt(nbt, nbatch, target);
-        const int gx = (nbt + Kt - 1) / Kt;
-        const int per_mat = gx * nbt;
-        // SYMV phase (and clear the norm slot that this column's finish fills)
-        for (int b = blockIdx.x * 256 + threadIdx.x; b < nbatch; b += P * 256)
-            w.normacc[(long long)b * 2 + ((i + 1) & 1)] = T(0);
-        int cur_b = -1;
-        Refl<T> rf = {T(0), T(0), T(0)};
-        for (int it = blockIdx.x; it < per_mat * nbatch; it += P) {
-            const int b = it / per_mat;
-            const int slot = it - b * per_mat;
-            const int strip = slot / gx, q = slot - strip * gx;
-            const int n = w.ns[b];
-            const int C = b0 + strip;
-            const int nbk = (n + 63) >> 6;
-            if (i > n - 2 || i >= sytrd_tail_start<T>(n) || C >= nbk || q >= (nbk - C + Kt - 1) / Kt) continue;
-            if (b != cur_b) { rf = refl_scalars(w, b, i, n); cur_b = b; }
-            symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, &rf);
-        }
-        grid.sync();
-        // finish phase
-        for (int it = blockIdx.x; it < nbt * nbatch; it += P) {
-            const int b = it / nbt;
-            const int R = b0 + (it - b * nbt);
-            const int n = w.ns[b];
-            if (i > n - 2 || i >= sytrd_tail_start<T>(n) || R >= ((n + 63) >> 6)) continue;
-            finish_item<T, NBP>(w, b, n, i, j, R);
-        }
-        grid.sync();
-    }
-}
-
 // Trailing update A(t0:n, t0:n) -= V W^T + W V^T, lower TS x TS tiles only.
 // t0 is a multiple of the panel width and the leading dimension a multiple of
 // 64, so the epilogue reads A before the K loop and writes it back in aligned
@@ -774,26 +730,6 @@ struct Syr2kProb {
     __device__ void store(const GemmTile&, int, int, T) const {}
 };
 
-// persistent grid size for the cooperative panel kernel (0 if unavailable)
-template <typename T>
-static int sytrd_persistent_grid() {
-    static int cached = -1;
-    if (cached >= 0) return cached;
-    cached = 0;
-    int dev = 0, coop = 0, ncu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (!coop || ncu <= 0) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sytrd_panel_kernel<T, SYTRD_NBP>, 256, 0) != hipSuccess ||
-        per_cu <= 0) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    cached = ncu * per_cu;
-    return cached;
-}
-
 template <typename T>
 void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, const int* ns_host,
                   LaunchProfiler* prof) {
@@ -802,41 +738,12 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
     const int nbk_max = w.nbk_max;
     hipLaunchKernelGGL(sytrd_zero_norm_kernel<T>, dim3((2 * nbatch + 255) / 256), dim3(256), 0, st, w, nbatch);
     hipLaunchKernelGGL(sytrd_init_kernel<T>, dim3(nbk_max, 1, nbatch), dim3(256), 0, st, w);
-    // MBD_SYTRD_MODE=persistent selects the cooperative panel kernel; the
-    // default issues two launches per column (measured faster on gfx950,
-    // where a grid-wide barrier costs more than a dependent launch).
-    const char* mode = getenv("MBD_SYTRD_MODE");
-    const bool want_persistent = mode && std::string(mode) == "persistent";
-    const int P = want_persistent ? sytrd_persistent_grid<T>() : 0;
-    const bool persistent = P > 0;
     // panels up to the tail of the largest matrix (smaller ones drop out of
     // the per-column kernels at their own tail start)
     const int kend = sytrd_tail_start<T>(nmax);
     for (int k0 = 0; k0 < kend && k0 + 2 <= nmax; k0 += NBP) {
         const int k1 = std::min(k0 + NBP, nmax - 1);
-        double bytes = 0;
-        if (timing)
-            for (int i = k0; i < k1; i++)
-                for (int b = 0; b < nbatch; b++) {
-                    const double m = ns_host[b] - i - 1;
-                    if (m > 0) bytes += m * (m + 1) * 0.5 * sizeof(T);
-                }
-        bool done = false;
-        if (persistent) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (timing) {
-                prof->pair(&e0, &e1, 0, bytes);
-                hipEventRecord(e0, st);
-            }
-            SytrdWs<T> wc = w;
-            int a1 = k0, a2 = k1, a3 = nbatch, a4 = 2 * P;
-            void* args[] = {&wc, &a1, &a2, &a3, &a4};
-            done = hipLaunchCooperativeKernel((const void*)sytrd_panel_kernel<T, NBP>, dim3(P), dim3(256), args, 0,
-                                              st) == hipSuccess;
-            if (!done) (void)hipGetLastError();
-            if (timing) hipEventRecord(e1, st);
-        }
-        if (!done) {
+        {
             for (int i = k0; i < k1; i++) {
                 const int j = i - k0;
                 const int b0 = (i + 1) >> 6;

@@ -21,6 +21,7 @@
 #define MBD_ST_BAD_INPUT 1u        // non-finite or non-positive per-atom input
 #define MBD_ST_COINCIDENT 2u       // two atoms closer than 1e-8 bohr
 #define MBD_ST_COLLAPSE 4u         // some eigenvalue of Q <= 0
+#define MBD_ST_NOT_CONVERGED 8u    // the FP64 refinement missed its target
 
 static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 static inline long long ceil_div_ll(long long a, long long b) { return (a + b - 1) / b; }

@@ -32,7 +32,8 @@ void mbd_prep_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, doub
 void mbd_assemble_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,
                                 const double* cc, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status);
 void mbd_energy_launch(hipStream_t st, const SysDesc* sd, int nsys, const int* ns, const double* lam,
-                       long long sL, const double* om, unsigned* status, double* lmin);
+                       long long sL, const double* om, unsigned* status, double* lmin, const int* conv);
+void mbd_errors_launch(hipStream_t st, const SysDesc* sd, int nsys, int nmat, const double* stats, const int* one);
 void mbd_invsqrt4_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const double* lam, long long sL,
                          double* sc);
 // lower triangle of M = X diag(sc)^2 X^T; the columns of X are scaled in place
@@ -47,7 +48,7 @@ void mbd_grad_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nma
 #define OA_KMAX 32  // largest window of close eigenvalues solved by Rayleigh-Ritz
 struct OaWork {
     double* colpart;  // [nbatch][nmax][6] per-column partial sums
-    unsigned* nclust; // [nbatch] unresolved close pairs of the last step
+    unsigned* nclust; // [nbatch] runs of linked columns the last step cut into windows
     int* wstart;      // [nbatch][nmax] first column of each column's window
     int* wlen;        // [nbatch][nmax] window length
     double* wv;       // [nbatch][nmax][OA_KMAX] window rotation, per column
@@ -71,7 +72,9 @@ void fill_u32_launch(hipStream_t st, unsigned* p, int n, unsigned v);
 template <typename T>
 void fill_sym_random_launch(hipStream_t st, int n, T* A, int ld, unsigned seed);
 
-// periodic (Ewald) assembly and adjoint
+// periodic (Ewald) assembly and adjoint; the adjoint keeps PER_PART doubles
+// per (q, i, j): {P, dR[3], dA[9], P0}
+#define PER_PART 14
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                                   const double* qcart, int nq, const int* img, int nimg, const int* rec,
                                   int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N);

@@ -113,11 +113,14 @@ def make_system(coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_f
 
 
 def evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_frac=None,
-             kgrid=None, param="omega", gradients=True, eigvals=False, errors=True, ewald=(0.0, 0.0, 0.0)):
-    """Energy (and gradients) of one system.  Returns a dict of torch tensors."""
+             kgrid=None, kshift=(0.0, 0.0, 0.0), param="omega", gradients=True, eigvals=False, errors=True,
+             ewald=(0.0, 0.0, 0.0)):
+    """Energy (and gradients) of one system.  Returns a dict of torch tensors.
+    Periodic systems take either q_frac or the Monkhorst-Pack mesh kgrid
+    (+ kshift) built by the library."""
     ctx.sync_stream()
     dev = ctx.device
-    s, keep = make_system(coords, alpha0, omega, rvdw, beta, a, lattice, q_frac, kgrid,
+    s, keep = make_system(coords, alpha0, omega, rvdw, beta, a, lattice, q_frac, kgrid, kshift,
                           param=param, ewald=ewald, device=dev)
     N = s.n_atoms
     periodic = lattice is not None
@@ -136,12 +139,11 @@ def evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q
             out["grad_lattice"] = torch.empty(3, 3, dtype=torch.float64, device=dev)
             r.grad_lattice = out["grad_lattice"].data_ptr()
             want |= A.MBD_WANT_GRAD_LATTICE
-        else:
-            out["grad_omega"] = torch.empty(N, dtype=torch.float64, device=dev)
-            out["grad_rvdw"] = torch.empty(N, dtype=torch.float64, device=dev)
-            r.grad_omega_or_c6 = out["grad_omega"].data_ptr()
-            r.grad_rvdw = out["grad_rvdw"].data_ptr()
-            want |= A.MBD_WANT_GRAD_OMEGA | A.MBD_WANT_GRAD_RVDW
+        out["grad_omega"] = torch.empty(N, dtype=torch.float64, device=dev)
+        out["grad_rvdw"] = torch.empty(N, dtype=torch.float64, device=dev)
+        r.grad_omega_or_c6 = out["grad_omega"].data_ptr()
+        r.grad_rvdw = out["grad_rvdw"].data_ptr()
+        want |= A.MBD_WANT_GRAD_OMEGA | A.MBD_WANT_GRAD_RVDW
     if eigvals:
         out["eigvals"] = torch.empty(nq, 3 * N, dtype=torch.float64, device=dev)
         r.eigvals = out["eigvals"].data_ptr()

@@ -104,18 +104,6 @@ def test_eigh_degenerate_cases(ctx):
     _check(A, w.cpu().numpy(), Z.cpu().numpy(), 1e-12)
 
 
-@pytest.mark.parametrize("dtype", ["float64", "float32"])
-def test_eigh_persistent_reduction_path(ctx, dtype, monkeypatch):
-    """The reduction's cooperative persistent panel kernel (grid-wide syncs)."""
-    from paper_2308_03140_amd import torch_api as T
-    _note("eigh persistent %s" % dtype)
-    monkeypatch.setenv("MBD_SYTRD_MODE", "persistent")
-    A = gen.random_symmetric(4242, 150)
-    w, Z = T.eigh(ctx, torch.tensor(A, device="cuda", dtype=getattr(torch, dtype)))
-    tol = 1e-12 if dtype == "float64" else 2e-5
-    _check(A, w.double().cpu().numpy(), Z.double().cpu().numpy(), tol)
-
-
 def test_eigh_batched(ctx):
     from paper_2308_03140_amd import torch_api as T
     _note("eigh batched 3 x 70")

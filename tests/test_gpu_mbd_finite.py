@@ -140,3 +140,7 @@ def test_config_n2000_golden(ctx):
     err = np.abs(g - np.array(ref["grad_R_sample"])).max()
     _note("  max |dE/dR - ref| = %.3e" % err)
     assert err <= TOL_G, err
+    for k, o in (("grad_alpha0_sample", "grad_alpha0"), ("grad_omega_sample", "grad_omega")):
+        e = np.abs(out[o].cpu().numpy()[ref["atoms"]] - np.array(ref[k])).max()
+        _note("  max |%s - ref| = %.3e" % (o, e))
+        assert e <= TOL_G, (k, e)
