@@ -164,6 +164,22 @@ mbd_status mbd_evaluate(mbd_ctx *ctx, const mbd_system *sys, unsigned want, mbd_
 mbd_status mbd_evaluate_batch(mbd_ctx *ctx, int32_t n_sys, const mbd_system *sys, unsigned want,
                               mbd_result *out, int32_t *status);
 
+/* No-allocation variant of mbd_evaluate, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * mbd_evaluate, for finite systems of at most MBD_NOALLOC_MAX_ATOMS atoms
+ * (larger ones: MBD_ERR_INVALID_ARGUMENT; periodic: MBD_ERR_UNSUPPORTED).
+ * Every workspace comes from one static device array of
+ * MBD_NOALLOC_SCRATCH_BYTES per device (held until the process ends; its
+ * address is resolved by mbd_create); the call makes no hipMalloc, hipFree or
+ * other allocating call.  All calls on one device share that array, which
+ * keeps the last call's contents (the kernels clear what must start at
+ * zero): calls that overlap in time on one device, from any context or
+ * stream, race and give undefined results. */
+#define MBD_NOALLOC_MAX_ATOMS 256
+#define MBD_NOALLOC_SCRATCH_BYTES (128ull << 20)
+mbd_status mbd_evaluate_noalloc(mbd_ctx *ctx, const mbd_system *sys, unsigned want, mbd_result *out);
+
 /* Dense symmetric eigensolver of the MBD path, exposed for testing and reuse:
  * the Householder reduction, divide-and-conquer tridiagonal solve and
  * back-transform used for Q.  A: [nbatch] matrices of order n, column-major

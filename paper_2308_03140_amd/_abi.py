@@ -27,6 +27,9 @@ MBD_WANT_GRAD_LATTICE = 32
 MBD_WANT_EIGVALS = 64
 MBD_WANT_ERRORS = 128
 
+MBD_NOALLOC_MAX_ATOMS = 256
+MBD_NOALLOC_SCRATCH_BYTES = 128 << 20
+
 _P = ctypes.c_void_p
 
 
@@ -79,6 +82,7 @@ def lib():
         L.mbd_destroy.argtypes = [_P]
         L.mbd_set_stream.argtypes = [_P, _P]
         L.mbd_evaluate.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_uint, ctypes.POINTER(MbdResult)]
+        L.mbd_evaluate_noalloc.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_uint, ctypes.POINTER(MbdResult)]
         L.mbd_evaluate_batch.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(MbdSystem), ctypes.c_uint,
                                          ctypes.POINTER(MbdResult), ctypes.POINTER(ctypes.c_int32)]
         L.mbd_eigh.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
@@ -89,7 +93,8 @@ def lib():
         L.mbd_get_profile.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         L.mbd_last_error.argtypes = [_P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_char_p)]
-        for f in ("mbd_create", "mbd_destroy", "mbd_set_stream", "mbd_evaluate", "mbd_evaluate_batch",
+        for f in ("mbd_create", "mbd_destroy", "mbd_set_stream", "mbd_evaluate", "mbd_evaluate_noalloc",
+                  "mbd_evaluate_batch",
                   "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error", "mbd_set_profiling",
                   "mbd_get_profile"):
             getattr(L, f).restype = ctypes.c_int
@@ -114,6 +119,10 @@ def mbd_set_stream(ctx, stream):
 
 def mbd_evaluate(ctx, system, want, result):
     return lib().mbd_evaluate(ctx, ctypes.byref(system), ctypes.c_uint(want), ctypes.byref(result))
+
+
+def mbd_evaluate_noalloc(ctx, system, want, result):
+    return lib().mbd_evaluate_noalloc(ctx, ctypes.byref(system), ctypes.c_uint(want), ctypes.byref(result))
 
 
 def mbd_evaluate_batch(ctx, systems, want, results, status):

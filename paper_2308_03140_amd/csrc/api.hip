@@ -12,8 +12,15 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
+
+// Device scratch of mbd_evaluate_noalloc: every workspace of that entry point
+// is carved from this array, so it calls no allocator.  Each device that runs
+// the library holds its own copy until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress gives on that device.
+static __device__ __align__(256) unsigned char scratch[MBD_NOALLOC_SCRATCH_BYTES];
 
 struct mbd_ctx {
     int device = 0;
@@ -40,6 +47,11 @@ struct mbd_ctx {
     std::map<std::string, Graph> graphs;
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // workspace arena (set only inside mbd_evaluate_noalloc): named workspaces
+    // are bump-allocated from [arena, arena + arena_cap) instead of hipMalloc
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    std::map<std::string, std::pair<void*, size_t>> arena_bufs;
     void drop_graphs() {
         for (auto& kv : graphs) {
             if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
@@ -80,6 +92,20 @@ mbd_status fail(mbd_ctx* c, mbd_status code, const char* origin, const std::stri
 void* ws(mbd_ctx* c, const char* name, size_t bytes) {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~size_t(255);
+    if (c->arena) {
+        // the same name returns the same memory within a call, as below
+        auto at = c->arena_bufs.find(name);
+        if (at != c->arena_bufs.end() && at->second.second >= bytes) return at->second.first;
+        if (c->arena_used + bytes > c->arena_cap) {
+            fail(c, MBD_ERR_OUT_OF_MEMORY, "workspace",
+                 std::string("the no-allocation scratch is too small for ") + name);
+            return nullptr;
+        }
+        void* p = c->arena + c->arena_used;
+        c->arena_used += bytes;
+        c->arena_bufs[name] = {p, bytes};
+        return p;
+    }
     auto it = c->bufs.find(name);
     if (it != c->bufs.end() && it->second.second >= bytes) return it->second.first;
     size_t old = it != c->bufs.end() ? it->second.second : 0;
@@ -594,6 +620,29 @@ mbd_status refine_fallback(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want,
     return MBD_OK;
 }
 
+// Per-device address of the scratch array, resolved once per device (with
+// that device current) by the library's init call, mbd_create.
+constexpr int MBD_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MBD_MAX_DEVICES] = {};
+bool g_scratch_tried[MBD_MAX_DEVICES] = {};
+
+void resolve_scratch(int device) {
+    if (device < 0 || device >= MBD_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_tried[device]) return;
+    g_scratch_tried[device] = true;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) g_scratch_ptr[device] = p;
+    else (void)hipGetLastError();
+}
+
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= MBD_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -608,6 +657,7 @@ mbd_status mbd_create(mbd_ctx** ctx, int device, mbd_precision prec, void* hip_s
         return MBD_ERR_DEVICE;
     }
     if (hipSetDevice(device) != hipSuccess) return MBD_ERR_DEVICE;
+    resolve_scratch(device);
     mbd_ctx* c = new mbd_ctx();
     c->device = device;
     c->prec = prec;
@@ -663,6 +713,37 @@ mbd_status mbd_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_resu
     }
     if (r != MBD_OK) return r;
     return code_message(c, codes[0], "mbd_evaluate");
+}
+
+mbd_status mbd_evaluate_noalloc(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_result* out) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    c->err_code = 0;
+    mbd_status r = check_system(c, s, want, out, true);
+    if (r != MBD_OK) return r;
+    if (s->lattice) return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate_noalloc", "finite systems only");
+    if (s->n_atoms > MBD_NOALLOC_MAX_ATOMS)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate_noalloc",
+                    "n_atoms exceeds MBD_NOALLOC_MAX_ATOMS (" + std::to_string(MBD_NOALLOC_MAX_ATOMS) + ")");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_evaluate_noalloc", "hipSetDevice");
+    char* base = (char*)scratch_ptr(c->device);
+    if (!base) return fail(c, MBD_ERR_DEVICE, "mbd_evaluate_noalloc", "scratch address not available on this device");
+    // no launch timing here: its events would be created on demand
+    const bool prof = c->prof.enabled;
+    c->prof.enabled = false;
+    c->arena = base;
+    c->arena_cap = MBD_NOALLOC_SCRATCH_BYTES;
+    c->arena_used = 0;
+    c->arena_bufs.clear();
+    std::vector<SysDesc> sds(1, make_desc(s, want, out));
+    std::vector<int> codes;
+    r = run_core(c, sds, want, codes, nullptr);
+    if (r == MBD_OK) r = refine_fallback(c, sds, want, codes, nullptr);
+    c->arena = nullptr;
+    c->arena_cap = c->arena_used = 0;
+    c->arena_bufs.clear();
+    c->prof.enabled = prof;
+    if (r != MBD_OK) return r;
+    return code_message(c, codes[0], "mbd_evaluate_noalloc");
 }
 
 mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, unsigned want, mbd_result* out,

@@ -114,10 +114,12 @@ def make_system(coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_f
 
 def evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_frac=None,
              kgrid=None, kshift=(0.0, 0.0, 0.0), param="omega", gradients=True, eigvals=False, errors=True,
-             ewald=(0.0, 0.0, 0.0)):
+             ewald=(0.0, 0.0, 0.0), noalloc=False):
     """Energy (and gradients) of one system.  Returns a dict of torch tensors.
     Periodic systems take either q_frac or the Monkhorst-Pack mesh kgrid
-    (+ kshift) built by the library."""
+    (+ kshift) built by the library.  noalloc=True calls
+    mbd_evaluate_noalloc (finite systems of at most MBD_NOALLOC_MAX_ATOMS;
+    the outputs are still allocated here, by torch)."""
     ctx.sync_stream()
     dev = ctx.device
     s, keep = make_system(coords, alpha0, omega, rvdw, beta, a, lattice, q_frac, kgrid, kshift,
@@ -152,7 +154,7 @@ def evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q
         out["errors"] = torch.zeros(4, dtype=torch.float64, device=dev)
         r.errors = out["errors"].data_ptr()
         want |= A.MBD_WANT_ERRORS
-    code = A.mbd_evaluate(ctx.handle, s, want, r)
+    code = (A.mbd_evaluate_noalloc if noalloc else A.mbd_evaluate)(ctx.handle, s, want, r)
     if code != A.MBD_OK:
         _raise(ctx, code)
     return out
