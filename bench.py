@@ -39,24 +39,59 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample=700):
+def _cpu_info():
+    """CPU model and physical core count of this host (from /proc/cpuinfo)."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None and core is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None and core is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return model, (len(cores) or None)
+
+
+def cpu_baseline(sizes=(500, 700), n_full=2000):
     """The oracle as it stands (Jacobi eigensolver, energy + gradients) on a
-    bounded sample: the first n_sample atoms of the N=2000 cluster, scaled to
-    N=2000 by the cubic cost law of the dense eigenproblem."""
+    bounded sample: the first n atoms of the N=2000 cluster for two sample
+    sizes.  The cost exponent p is fitted from the two times (Jacobi's sweep
+    count grows with n, so it is not exactly 3) and the larger sample is
+    extrapolated to N=2000 with it."""
+    import math
+
     import gen
     import oracle
     c = gen.cluster_n2000()
-    sl = slice(0, n_sample)
     oracle.mbd_finite(c["coords"][:20], c["alpha0"][:20], c["omega"][:20], c["rvdw"][:20])  # warm
-    t = time.perf_counter()
-    oracle.mbd_finite(c["coords"][sl], c["alpha0"][sl], c["omega"][sl], c["rvdw"][sl], c["beta"], c["a"])
-    dt = time.perf_counter() - t
+    t = {}
+    for n in sizes:
+        sl = slice(0, n)
+        t0 = time.perf_counter()
+        oracle.mbd_finite(c["coords"][sl], c["alpha0"][sl], c["omega"][sl], c["rvdw"][sl], c["beta"], c["a"])
+        t[n] = time.perf_counter() - t0
+    a, b = sizes
+    p = math.log(t[b] / t[a]) / math.log(b / a)
+    value = t[b] * (n_full / b) ** p
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    scale = (2000.0 / n_sample) ** 3
-    return {"value": dt * scale, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": "oracle energy+gradients (cyclic Jacobi) on the first %d atoms of the N=2000 "
-                      "cluster: %.2f s measured, scaled by (2000/%d)^3 = %.1f to one N=2000 evaluation"
-                      % (n_sample, dt, n_sample, scale)}
+    model, phys = _cpu_info()
+    return {"value": value, "unit": "s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "physical_cores": phys, "fitted_exponent": p,
+            "sample": "oracle energy+gradients (cyclic Jacobi) on the first %d and %d atoms of the N=2000 cluster "
+                      "(%.2f s and %.2f s measured); cost exponent fitted from the two, %.2f; the %d-atom time "
+                      "extrapolated with it to one N=%d evaluation" % (a, b, t[a], t[b], p, b, n_full)}
 
 
 def symv_traffic():
@@ -114,11 +149,18 @@ def leg_c2(args, torch, T, A):
         log("[bench] c2 %s warmup x%d, timed x%d" % (prec, args.warmup, args.steps))
         dt, out = timed(step, args.steps, args.warmup, torch)
         log("[bench] c2 %s %.4f s/step" % (prec, dt))
-        # launch-level timing of the reduction kernels (separate, profiled pass)
+        # launch-level timing of the reduction kernels and of each phase
+        # (separate, profiled pass)
         A.mbd_set_profiling(ctx.handle, 1)
         step()
         prof = {}
         for kind in (0, 1):
+            st, ms, nl, work = A.mbd_get_profile(ctx.handle, kind)
+            prof[kind] = (ms, nl, work)
+        # phases only (no per-launch events in the way)
+        A.mbd_set_profiling(ctx.handle, 2)
+        step()
+        for kind in range(2, 8):
             st, ms, nl, work = A.mbd_get_profile(ctx.handle, kind)
             prof[kind] = (ms, nl, work)
         A.mbd_set_profiling(ctx.handle, 0)
@@ -128,6 +170,39 @@ def leg_c2(args, torch, T, A):
     res["N"] = N
     res["alpha_scale"] = c["alpha_scale"]
     return res
+
+
+PHASES = {2: "assembly", 3: "reduction", 4: "divide_and_conquer", 5: "back_transform", 6: "refinement",
+          7: "energy_and_gradients"}
+
+
+def phase_rooflines(prof, n, fp32):
+    """Per-phase event time of one profiled evaluation against the time the
+    phase's algorithmic work takes at the MI355X peaks (HBM 8 TB/s; FP32 and
+    FP64 matrix cores 157.3 and 78.6 TFLOP/s): assembly writes Q (8 n^2 B, and
+    4 n^2 B for the FP32 copy); the reduction reads the lower trailing triangle
+    once per column (n^3/6 elements) and does (2/3) n^3 rank-2k flops; divide
+    and conquer at most (4/3) n^3 merge flops; the back-transform 2 n^3; one
+    refinement step 6 n^3 FP64; Q^{-1/2} n^3 FP64 plus one pass over it."""
+    es = 4 if fp32 else 8
+    peak = FP32_PEAK_TFS if fp32 else FP64_PEAK_TFS
+    tmin = {2: (8 + (4 if fp32 else 0)) * n * n / (HBM_PEAK_GBS * 1e9),
+            3: n ** 3 / 6 * es / (HBM_PEAK_GBS * 1e9) + (2.0 / 3.0) * n ** 3 / (peak * 1e12),
+            4: (4.0 / 3.0) * n ** 3 / (peak * 1e12),
+            5: 2.0 * n ** 3 / (peak * 1e12),
+            6: 6.0 * n ** 3 / (FP64_PEAK_TFS * 1e12) if fp32 else 0.0,
+            7: n ** 3 / (FP64_PEAK_TFS * 1e12) + 8 * n * n / (HBM_PEAK_GBS * 1e9)}
+    out, tot_ms, tot_min = {}, 0.0, 0.0
+    for k, name in PHASES.items():
+        ms = prof[k][0]
+        if prof[k][1] == 0:
+            continue
+        t = tmin[k] * 1e3
+        out[name] = {"ms": ms, "t_min_ms": t, "frac": t / ms if ms > 0 else None}
+        tot_ms += ms
+        tot_min += t
+    out["sum"] = {"ms": tot_ms, "t_min_ms": tot_min, "frac": tot_min / tot_ms if tot_ms > 0 else None}
+    return out
 
 
 def leg_batch(args, torch, T):
@@ -307,6 +382,86 @@ def pmc_summary(fetch_dir, write_dir):
     print("\n".join(lines))
 
 
+MFMA_PMC = os.path.join(ROOT, "profiles", "gemm_mfma_fp32_n6000_mfma.md")
+MFMA_REGEX = "gemm_mfma_kernel|gemm_f16x3_kernel|xf_small_f16_kernel"
+
+
+def _short(name):
+    name = name.replace("void ", "")
+    return name if len(name) <= 110 else name[:107] + "..."
+
+
+def mfma_summary(pmc_dir, trace_dir):
+    """Matrix-core utilisation of the GEMM kernels of one FP32+refine N=2000
+    evaluation (--pmc-pass), per kernel instantiation: MFMA flops from the
+    MfmaFlopsF16/F32/F64 counters (MOPS x 512), kernel time from a kernel-trace
+    run of the same pass, and the MfmaUtil counter (MFMA busy cycles over
+    active cycles of all SIMDs)."""
+    import csv
+    pfiles = [os.path.join(r, f) for r, _, fs in os.walk(pmc_dir) for f in fs if f.endswith("counter_collection.csv")]
+    tfiles = [os.path.join(r, f) for r, _, fs in os.walk(trace_dir) for f in fs if f.endswith("kernel_trace.csv")]
+    if not pfiles or not tfiles:
+        raise SystemExit("need counter_collection.csv under %s and kernel_trace.csv under %s" % (pmc_dir, trace_dir))
+    disp = {}
+    for fn in pfiles:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                key = int(row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                d = disp.setdefault(key, {"name": row.get("Kernel_Name", "")})
+                d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    counted = [disp[k] for k in sorted(disp)]
+    traced = []
+    for fn in tfiles:
+        with open(fn) as f:
+            traced += [r for r in csv.DictReader(f)]
+    traced.sort(key=lambda r: int(r["Start_Timestamp"]))
+    traced = [r for r in traced if any(x in r["Kernel_Name"] for x in MFMA_REGEX.split("|"))]
+    if len(traced) != len(counted):
+        raise SystemExit("%d traced vs %d counted GEMM dispatches" % (len(traced), len(counted)))
+    groups = {}
+    for c, t in zip(counted, traced):
+        if c["name"] != t["Kernel_Name"]:
+            raise SystemExit("dispatch order differs between the runs: %s / %s" % (c["name"], t["Kernel_Name"]))
+        g = groups.setdefault(c["name"], {"n": 0, "ms": 0.0, "f16": 0.0, "f32": 0.0, "f64": 0.0, "util_ms": 0.0})
+        ms = (int(t["End_Timestamp"]) - int(t["Start_Timestamp"])) * 1e-6
+        g["n"] += 1
+        g["ms"] += ms
+        g["f16"] += c.get("MfmaFlopsF16", 0.0)
+        g["f32"] += c.get("MfmaFlopsF32", 0.0)
+        g["f64"] += c.get("MfmaFlopsF64", 0.0)
+        g["util_ms"] += c.get("MfmaUtil", 0.0) * ms
+    peaks = {"f16": 2500.0, "f32": FP32_PEAK_TFS, "f64": FP64_PEAK_TFS}
+    lines = ["# Matrix-core utilisation of the GEMM kernels, one FP32+refine evaluation at N=2000 (n=6000)", "",
+             "Commands (repository root, MI355X):", "",
+             "    rocprofv3 --pmc MfmaUtil MfmaFlopsF16 MfmaFlopsF32 MfmaFlopsF64 --kernel-include-regex "
+             "'%s' --output-format csv -d gpurun_out/pmc_mfma -o m -- python3 bench.py --pmc-pass" % MFMA_REGEX,
+             "    rocprofv3 --kernel-trace --stats --kernel-include-regex '%s' --output-format csv "
+             "-d gpurun_out/trace_mfma -o t -- python3 bench.py --pmc-pass" % MFMA_REGEX,
+             "    python3 bench.py --mfma-summary gpurun_out/pmc_mfma gpurun_out/trace_mfma", "",
+             "Flops = MFMA MOPS x 512 (counter); time = traced kernel duration; TF/s and fraction of the dense "
+             "peak of the kernel's MFMA type (FP64 78.6, FP32 157.3, FP16 2500 TFLOP/s); MfmaUtil = MFMA-busy "
+             "cycles over active cycles of all SIMDs, time-weighted.", "",
+             "| kernel | dispatches | total ms | MFMA type | TFLOP/s | frac of peak | MfmaUtil % |",
+             "|---|---|---|---|---|---|---|"]
+    tot = {"f16": [0.0, 0.0], "f32": [0.0, 0.0], "f64": [0.0, 0.0]}
+    for name, g in sorted(groups.items(), key=lambda kv: -kv[1]["ms"]):
+        typ = max(("f16", "f32", "f64"), key=lambda k: g[k])
+        fl = g[typ]
+        tfs = fl / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+        tot[typ][0] += fl
+        tot[typ][1] += g["ms"]
+        lines.append("| `%s` | %d | %.3f | %s | %.1f | %.3f | %.1f |" % (
+            _short(name), g["n"], g["ms"], typ.upper(), tfs, tfs / peaks[typ], g["util_ms"] / g["ms"] if g["ms"] else 0))
+    lines += ["", "| MFMA type | total ms | TFLOP/s | frac of peak |", "|---|---|---|---|"]
+    for typ, (fl, ms) in tot.items():
+        if ms > 0:
+            tfs = fl / (ms * 1e-3) / 1e12
+            lines.append("| %s | %.3f | %.1f | %.3f |" % (typ.upper(), ms, tfs, tfs / peaks[typ]))
+    with open(MFMA_PMC, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def trace_summary(trace_dir, steps, warmup):
     """Average duration of the FP32 SYMV kernel over the evaluations of a
     `--legs c2` run traced by rocprofv3 --kernel-trace (its kernel_trace.csv
@@ -346,6 +501,9 @@ def main():
     ap.add_argument("--trace-summary", metavar="TRACE_DIR", default=None,
                     help="average SYMV kernel duration per evaluation from a rocprofv3 --kernel-trace run of "
                          "--legs c2 with the same --steps/--warmup")
+    ap.add_argument("--mfma-summary", nargs=2, metavar=("PMC_DIR", "TRACE_DIR"), default=None,
+                    help="write the matrix-core utilisation table of the GEMM kernels under profiles/ from a "
+                         "--pmc-pass counter run (MfmaUtil, MfmaFlops*) and a kernel-trace run of the same pass")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="counter-collection pass: one FP32+refine N=2000 evaluation, then a plain device copy "
                          "of 1 GiB (the calibration kernel of known traffic); prints no JSON line")
@@ -360,6 +518,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args.trace_summary, args.steps, args.warmup)
+        return
+    if args.mfma_summary:
+        mfma_summary(*args.mfma_summary)
         return
 
     import numpy as np
@@ -420,6 +581,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launches": nl, "avg_launch_us": avg_s * 1e6,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
+        "phase_rooflines": {"fp32_refined": phase_rooflines(r["fp32_refined"]["prof"], 3 * N, True),
+                            "fp64": phase_rooflines(r["fp64"]["prof"], 3 * N, False)},
         "phases": {
             "fp32_symv_GBs": achieved, "fp32_symv_total_ms": ms,
             "fp32_syr2k_TFs": fl3 / (ms3 * 1e-3) / 1e12 if ms3 > 0 else None, "fp32_syr2k_total_ms": ms3,

@@ -201,11 +201,15 @@ mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
 /* Launch timing for measurement tools.  While enabled, every per-column SYMV
  * launch of the Householder reduction (kind 0, the bandwidth-bound BLAS-2
  * phase) and every trailing SYR2K launch (kind 1, the matrix-core BLAS-3
- * phase) is bracketed by two HIP events on the context stream.  Enabling
- * clears earlier records.  mbd_get_profile synchronises the stream and
- * returns, for one kind, the summed event time (ms), the number of launches
- * and the summed algorithmic work: bytes of the lower trailing triangle read
- * (kind 0) or flops of the rank-2k update (kind 1). */
+ * phase) is bracketed by two HIP events on the context stream, and so is
+ * each phase of an evaluation: 2 input preparation and assembly, 3 Householder
+ * reduction, 4 divide and conquer, 5 back-transform, 6 refinement (FP32 path),
+ * 7 energy, Q^{-1/2} and gradients.  Enabling clears earlier records.
+ * mbd_get_profile synchronises the stream and returns, for one kind (0..7),
+ * the summed event time (ms), the number of records and the summed
+ * algorithmic work: bytes of the lower trailing triangle read (kind 0), flops
+ * of the rank-2k update (kind 1), 0 for the phases.  enable = 2 records the
+ * phases only (no per-launch events, so the phases run as unprofiled). */
 mbd_status mbd_set_profiling(mbd_ctx *ctx, int enable);
 mbd_status mbd_get_profile(mbd_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, double *work);
 

@@ -198,7 +198,10 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     const std::pair<int, int> tg = tuned_target(c, sizeof(T) == 8 ? 0 : 1, nmax);
     sw.chunk_target = tg.first;
     sw.chunk_target_lo = tg.second;
-    sytrd_launch<T>(sw, nbatch, nmax, st, ns_host, &c->prof);
+    {
+        PhaseTimer ph(&c->prof, st, 3);
+        sytrd_launch<T>(sw, nbatch, nmax, st, ns_host, &c->prof);
+    }
     HIPCHK(hipGetLastError(), "sytrd");
 
     // --- divide and conquer
@@ -241,7 +244,9 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
         if (!dw.GA0 || !dw.GA1 || !dw.GB0 || !dw.GB1) return (mbd_status)c->err_code;
     }
     dw.w_out = w_out; dw.sW = sW;
+    PhaseTimer ph_dc(&c->prof, st, 4);
     const int src = stedc_launch<T>(dw, nbatch, nmax, st);
+    ph_dc.stop();
     HIPCHK(hipGetLastError(), "stedc");
     MatBatch<T> Z = src ? dw.Z1 : dw.Z0;
 
@@ -257,6 +262,7 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
         ow.sC = (long long)(nblk / 2 + 1) * 4096; ow.Cp = wsT<T>(c, "Cpair" + t, (size_t)ow.sC * nbatch);
         ow.sVT = (long long)nblk * 64 * nmax; ow.VT = wsT<T>(c, "VT" + t, (size_t)ow.sVT * nbatch);
         if (!ow.Gpart || !ow.Tm || !ow.Ypart || !ow.Y || !ow.VT || !ow.Cp) return (mbd_status)c->err_code;
+        PhaseTimer ph(&c->prof, st, 5);
         ormtr_launch<T>(ow, nbatch, nmax, st);
         HIPCHK(hipGetLastError(), "ormtr");
     }
@@ -492,6 +498,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         HIPCHK(hipMemcpyAsync(sd_dev, sds.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nmat, hipMemcpyHostToDevice, st), "upload");
     }
+    PhaseTimer ph_asm(&c->prof, st, 2);
     fill_u32_launch(st, status, nsys, 0u);
     mbd_prep_launch(st, sd_dev, nsys, Nmax, om, cc, status);
     double* qcart = nullptr;
@@ -511,6 +518,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         mbd_assemble_finite_launch(st, sd_dev, nsys, Nmax, om, cc, A64, A32, status);
     }
     HIPCHK(hipGetLastError(), "assemble");
+    ph_asm.stop();
 
     MatBatch<double> X;
     double* stats = nullptr;
@@ -546,6 +554,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         if (!Xd.p || !Y.p || !S.p || !G.p || !ow.colpart || !ow.nclust || !ow.wstart || !ow.wlen || !ow.wv || !ow.gdiag || !ow.fexp ||
             !stats || !skip2 || !skip3)
             return (mbd_status)c->err_code;
+        PhaseTimer ph(&c->prof, st, 6);
         oa_f2d_launch(st, ns_dev, nmax, nmat, X32, Xd);
         oa_step_launch(st, ns_dev, nmax, nmat, A64, Xd, Y, S, G, lam, nmax, ow, stats, nullptr, skip2, X32);  // X1 in Y
         oa_step_launch(st, ns_dev, nmax, nmat, A64, Y, S, Xd, G, lam, nmax, ow, stats + 4 * nmat, skip2,
@@ -555,6 +564,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         HIPCHK(hipGetLastError(), "refine");
         X = S;
     }
+    PhaseTimer ph_eg(&c->prof, st, 7);
     mbd_energy_launch(st, sd_dev, nsys, ns_dev, lam, nmax, om, status, lmin, conv_dev);
     mbd_errors_launch(st, sd_dev, nsys, nmat, stats, skip_dev);
     HIPCHK(hipGetLastError(), "energy");
@@ -575,6 +585,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         }
         HIPCHK(hipGetLastError(), "gradients");
     }
+    ph_eg.stop();
     if (capturing) {
         HIPCHK(hipMemcpyAsync(mode->g->h_status, status, sizeof(unsigned) * nsys, hipMemcpyDeviceToHost, st), "status");
         return MBD_OK;
@@ -1044,12 +1055,13 @@ mbd_status mbd_set_profiling(mbd_ctx* c, int enable) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;
     hipStreamSynchronize(c->stream);
     c->prof.enabled = enable != 0;
+    c->prof.launches = enable != 2;
     c->prof.reset();
     return MBD_OK;
 }
 
 mbd_status mbd_get_profile(mbd_ctx* c, int32_t kind, double* total_ms, int64_t* launches, double* work) {
-    if (!c || !total_ms || !launches || !work || kind < 0 || kind > 1) return MBD_ERR_INVALID_ARGUMENT;
+    if (!c || !total_ms || !launches || !work || kind < 0 || kind >= PROF_KINDS) return MBD_ERR_INVALID_ARGUMENT;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_get_profile", "synchronize");
     long long n = 0;
     c->prof.summary(kind, total_ms, &n, work);

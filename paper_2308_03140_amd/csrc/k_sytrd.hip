@@ -734,7 +734,7 @@ template <typename T>
 void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, const int* ns_host,
                   LaunchProfiler* prof) {
     constexpr int NBP = SYTRD_NBP;
-    const bool timing = prof && prof->enabled && ns_host;
+    const bool timing = prof && prof->enabled && prof->launches && ns_host;
     const int nbk_max = w.nbk_max;
     hipLaunchKernelGGL(sytrd_zero_norm_kernel<T>, dim3((2 * nbatch + 255) / 256), dim3(256), 0, st, w, nbatch);
     hipLaunchKernelGGL(sytrd_init_kernel<T>, dim3(nbk_max, 1, nbatch), dim3(256), 0, st, w);

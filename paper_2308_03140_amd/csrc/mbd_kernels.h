@@ -5,12 +5,16 @@
 #include <vector>
 #include <hip/hip_ext.h>
 
-// Optional HIP-event timing of individual launches (measurement tools only).
-// kind 0: per-column SYMV of the reduction (BLAS-2), 1: trailing SYR2K
-// (BLAS-3).  `work` is the algorithmic bytes (kind 0) or flops (kind 1) of
-// the launch.
+// Optional HIP-event timing of individual launches and of whole phases
+// (measurement tools only).  kind 0: per-column SYMV of the reduction
+// (BLAS-2), 1: trailing SYR2K (BLAS-3); phases: 2 input preparation and
+// assembly, 3 Householder reduction, 4 divide and conquer, 5 back-transform,
+// 6 refinement, 7 energy, Q^{-1/2} and gradients.  `work` is the algorithmic
+// bytes (kind 0) or flops (kind 1) of the launch, 0 for phases.
+#define PROF_KINDS 8
 struct LaunchProfiler {
     bool enabled = false;
+    bool launches = true;  // per-launch records (kinds 0, 1); phases are always recorded when enabled
     std::vector<hipEvent_t> pool;
     std::vector<int> kind;
     std::vector<double> work;
@@ -45,6 +49,24 @@ struct LaunchProfiler {
         *ms = t; *n = c; *w = ww;
     }
     ~LaunchProfiler() { for (auto e : pool) hipEventDestroy(e); }
+};
+
+// Event pair around a phase on a stream (no-op unless profiling is enabled).
+struct PhaseTimer {
+    LaunchProfiler* p;
+    hipStream_t st;
+    hipEvent_t e1 = nullptr;
+    PhaseTimer(LaunchProfiler* prof, hipStream_t s, int k) : p(prof), st(s) {
+        if (!p || !p->enabled) return;
+        hipEvent_t e0;
+        p->pair(&e0, &e1, k, 0.0);
+        (void)hipEventRecord(e0, st);
+    }
+    void stop() {
+        if (e1) (void)hipEventRecord(e1, st);
+        e1 = nullptr;
+    }
+    ~PhaseTimer() { stop(); }
 };
 
 #define SYTRD_NBP 32
