@@ -229,6 +229,28 @@ def mbd_finite_freq(R, alpha0, omega, rvdw, beta=0.83, a=6.0, npts=30, sample_at
             "grad_omega_sample": gw[:ns]}
 
 
+def ts(R, alpha0, omega, rvdw, sR, a=20.0, lattice=None, gamma=None, rc=None, kc=None):
+    """Pairwise (TS) dispersion energy (eq:pairwise, Fermi damping a = 20) and
+    its gradients; periodic (energy per cell) when a lattice is given, by the
+    Ewald split of eq:ts-ewald plus the real-space damping correction."""
+    R = _arr(R, (-1, 3)); N = R.shape[0]
+    L = None
+    if lattice is not None:
+        L = _arr(lattice, (3, 3))
+        g0, rc0, kc0 = ewald_defaults(L)
+        gamma = g0 if gamma is None else gamma
+        rc = rc0 if rc is None else rc
+        kc = kc0 if kc is None else kc
+    E = np.zeros(1); gR = np.empty((N, 3)); ga = np.empty(N); gw = np.empty(N); gv = np.empty(N)
+    lib = _load()
+    lib.orc_ts.restype = ctypes.c_int
+    rcode = lib.orc_ts(N, _p(R), _p(L), ctypes.c_double(gamma or 0.0), ctypes.c_double(rc or 0.0),
+                       ctypes.c_double(kc or 0.0), _p(_arr(alpha0)), _p(_arr(omega)), _p(_arr(rvdw)),
+                       ctypes.c_double(sR), ctypes.c_double(a), _p(E), _p(gR), _p(ga), _p(gw), _p(gv))
+    _check(rcode, "ts")
+    return {"energy": float(E[0]), "grad_R": gR, "grad_alpha0": ga, "grad_omega": gw, "grad_rvdw": gv}
+
+
 def min_coupling_eig(R, alpha0, rvdw, beta=0.83, a=6.0):
     """Smallest eigenvalue of alpha0^{1/2} T^lr alpha0^{1/2} (collapse indicator)."""
     R = _arr(R, (-1, 3)); N = R.shape[0]

@@ -970,3 +970,128 @@ int orc_min_coupling_eig(int N, const double *R, const double *alpha0,
     free(om); free(Q); free(lam);
     return sw < 0 ? 3 : 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Pairwise (TS) dispersion, Sec. 2.6 eq:pairwise with the Fermi damping of    */
+/* eq:fermi-damping (TS: a = 20, s_R the damping parameter), and its lattice   */
+/* sum by the Ewald split of eq:ts-ewald                                       */
+/* ------------------------------------------------------------------------- */
+
+/* C6_ij = (3/2) alpha_i alpha_j / (1/omega_i + 1/omega_j) */
+static double c6_pair(double ai, double aj, double wi, double wj)
+{
+    return 1.5 * ai * aj / (1.0 / wi + 1.0 / wj);
+}
+
+/* sum over images of f/R^6 for one ordered pair, r = R_j - R_i, with its
+ * gradient in r and its derivative in the damping radius R0.  Finite (L ==
+ * NULL): the single term n = 0.  Periodic: the Ewald split of the undamped
+ * lattice sum of R^-6 (real-space gamma^6 phi_r(gamma R) for 0 < R < rc,
+ * reciprocal gamma^3 phi_k(G/gamma) cos(G.r)/Omega for |G| < kc with G = 0
+ * included, -gamma^6/6 for i = j) minus the real-space sum of (1-f)/R^6 over
+ * every image with (1-f) > DAMP_TAIL. */
+static void ts_pair_sum(const lattice_t *L, const double *r, int self, double R0,
+                        double a, double *S, double *dS, double *dS0)
+{
+    *S = 0.0; *dS0 = 0.0;
+    dS[0] = dS[1] = dS[2] = 0.0;
+    if (!L) {
+        double d = norm3(r);
+        double f, omf, fd, fR0;
+        fermi(d, R0, a, &f, &omf, &fd, &fR0);
+        double d6 = d * d * d * d * d * d;
+        *S = f / d6;
+        double dd = fd / d6 - 6.0 * f / (d6 * d);
+        for (int c = 0; c < 3; c++) dS[c] = dd * r[c] / d;
+        *dS0 = fR0 / d6;
+        return;
+    }
+    const double g = L->gamma;
+    for (int t = 0; t < L->nimg; t++) {
+        const int *nn = L->img + 3 * t;
+        double x[3];
+        for (int c = 0; c < 3; c++)
+            x[c] = r[c] + nn[0] * L->A[c] + nn[1] * L->A[3 + c] + nn[2] * L->A[6 + c];
+        double d = norm3(x);
+        if (d == 0.0) continue;
+        if (d < L->rc) {
+            /* gamma^6 phi_r(z), phi_r(z) = (z^-6 + z^-4 + z^-2/2) e^{-z^2} */
+            double z = g * d, z2 = z * z, ez = exp(-z2);
+            double phi = (1.0 / (z2 * z2 * z2) + 1.0 / (z2 * z2) + 0.5 / z2) * ez;
+            double dphi = -(6.0 / (z2 * z2 * z2 * z) + 6.0 / (z2 * z2 * z) + 3.0 / (z2 * z) + 1.0 / z) * ez;
+            double g6 = g * g * g * g * g * g;
+            *S += g6 * phi;
+            for (int c = 0; c < 3; c++) dS[c] += g6 * g * dphi * x[c] / d;
+        }
+        double f, omf, fd, fR0;
+        fermi(d, R0, a, &f, &omf, &fd, &fR0);
+        if (omf > DAMP_TAIL) {
+            double d6 = d * d * d * d * d * d;
+            /* -(1-f)/d^6 */
+            *S -= omf / d6;
+            double dd = fd / d6 + 6.0 * omf / (d6 * d);
+            for (int c = 0; c < 3; c++) dS[c] += dd * x[c] / d;
+            *dS0 += fR0 / d6;
+        }
+    }
+    for (int t = 0; t < L->nrec; t++) {
+        const int *mm = L->rec + 3 * t;
+        double G[3];
+        for (int c = 0; c < 3; c++) G[c] = mm[0] * L->B[c] + mm[1] * L->B[3 + c] + mm[2] * L->B[6 + c];
+        double k = norm3(G);
+        if (k >= L->kc) continue;
+        /* phi_k(k) = (pi^{3/2}/12)((4 - 2k^2) e^{-k^2/4} + k^3 sqrt(pi) erfc(k/2)), k = G/gamma */
+        double kk = k / g;
+        double phik = pow(PI, 1.5) / 12.0 *
+                      ((4.0 - 2.0 * kk * kk) * exp(-kk * kk / 4.0) + kk * kk * kk * sqrt(PI) * erfc(kk / 2.0));
+        double w = g * g * g * phik / L->vol;
+        double ph = G[0] * r[0] + G[1] * r[1] + G[2] * r[2];
+        *S += w * cos(ph);
+        for (int c = 0; c < 3; c++) dS[c] -= w * sin(ph) * G[c];
+    }
+    if (self) *S -= g * g * g * g * g * g / 6.0;
+}
+
+int orc_ts(int N, const double *R, const double *lattice, double gamma,
+           double rc, double kc, const double *alpha0, const double *omega,
+           const double *rvdw, double sR, double a, double *energy,
+           double *grad_R, double *grad_alpha0, double *grad_omega,
+           double *grad_rvdw)
+{
+    if (N < 1) return 1;
+    lattice_t Lt, *L = NULL;
+    if (lattice) {
+        if (det3(lattice) <= 0.0) return 1;
+        double maxd;
+        pair_extent(N, R, &maxd);
+        double dr = damp_range(N, rvdw, sR, a);
+        lattice_setup(&Lt, lattice, gamma, rc, kc, rc > dr ? rc : dr, maxd, 0.0);
+        L = &Lt;
+    }
+    double E = 0.0;
+#pragma omp parallel for schedule(dynamic) reduction(+:E)
+    for (int i = 0; i < N; i++) {
+        double Ei = 0.0, gi[3] = {0, 0, 0}, wi = 0.0, vi = 0.0;
+        for (int j = 0; j < N; j++) {
+            if (j == i && !L) continue;
+            double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
+            double S, dS[3], dS0;
+            ts_pair_sum(L, r, i == j, sR * (rvdw[i] + rvdw[j]), a, &S, dS, &dS0);
+            double c6 = c6_pair(alpha0[i], alpha0[j], omega[i], omega[j]);
+            /* E = -1/2 sum_ij C6_ij S_ij; each ordered pair's energy is
+             * counted at i, and i's gradient gathers both orders */
+            Ei += -0.5 * c6 * S;
+            for (int c = 0; c < 3; c++) gi[c] += c6 * dS[c];
+            wi += -c6 * S * omega[j] / (omega[i] * (omega[i] + omega[j]));
+            vi += -sR * c6 * dS0;
+        }
+        E += Ei;
+        if (grad_R) for (int c = 0; c < 3; c++) grad_R[3 * i + c] = gi[c];
+        if (grad_alpha0) grad_alpha0[i] = 2.0 * Ei / alpha0[i];
+        if (grad_omega) grad_omega[i] = wi;
+        if (grad_rvdw) grad_rvdw[i] = vi;
+    }
+    if (energy) *energy = E;
+    if (L) lattice_free(L);
+    return 0;
+}

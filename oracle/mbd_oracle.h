@@ -93,6 +93,21 @@ int orc_mbd_finite_freq(int N, const double *R, const double *alpha0,
                         const int *atoms, double *grad_R_sample,
                         double *grad_alpha0_sample, double *grad_omega_sample);
 
+/* Pairwise (TS) energy of Sec. 2.6 eq:pairwise, E = -1/2 sum_{i != j}
+ * C6_ij f(R_ij)/R_ij^6 with C6_ij = (3/2) alpha_i alpha_j/(1/omega_i +
+ * 1/omega_j) and f the Fermi damping of eq:fermi-damping (steepness a, s_R =
+ * sR; TS uses a = 20).  lattice == NULL: finite system.  Otherwise the energy
+ * per cell, sum over all images (n = 0, i = j excluded), by the Ewald split of
+ * eq:ts-ewald for the undamped R^-6 sum (read with the G = 0 term included,
+ * the self term -gamma^6/6 and cos(G.R_ij)) minus the real-space sum of
+ * (1-f)/R^6.  Gradients (each may be NULL): dE/dR [N][3], dE/dalpha0,
+ * dE/domega, dE/dRv [N]. */
+int orc_ts(int N, const double *R, const double *lattice, double gamma,
+           double rc, double kc, const double *alpha0, const double *omega,
+           const double *rvdw, double sR, double a, double *energy,
+           double *grad_R, double *grad_alpha0, double *grad_omega,
+           double *grad_rvdw);
+
 /* Smallest eigenvalue of alpha0^{1/2} T^lr alpha0^{1/2} (finite). */
 int orc_min_coupling_eig(int N, const double *R, const double *alpha0,
                          const double *rvdw, double beta, double a,

@@ -464,3 +464,78 @@ def test_periodic_large_box_limit_dimer():
     r2 = (8.0 * d[160.0] - d[80.0]) / 7.0
     assert abs(r2) < 2e-8
     assert abs((32.0 * r2 - r1) / 31.0) < 2e-9
+
+
+# --------------------------------------------------------------------------
+# pairwise (TS) dispersion, eq:pairwise and eq:ts-ewald
+# --------------------------------------------------------------------------
+
+def test_ts_equals_second_order_mbd_undamped():
+    """eq:rpa: the second order of the many-body expansion is the pairwise
+    energy.  Undamped (f = g = 1), E_MBD(s alpha0)/s^2 = E^(2) + s E^(3) +
+    s^2 E^(4) + ..., so the pairwise energy is its limit s -> 0 (two
+    Richardson steps over s, 2s, 4s)."""
+    coords, a0, om, rv = _cluster(12, 7)
+    Ets = oracle.ts(coords, a0, om, rv, sR=0.0)["energy"]
+    e = {s: oracle.mbd_finite(coords, s * a0, om, rv, beta=0.0, gradients=False)["energy"] / s ** 2
+         for s in (1e-3, 2e-3, 4e-3)}
+    r1, r2 = 2 * e[1e-3] - e[2e-3], 2 * e[2e-3] - e[4e-3]
+    lim = (4 * r1 - r2) / 3
+    assert abs(lim - Ets) < 1e-7 * abs(Ets)
+
+
+def _ts_direct(R, lat, a0, om, rv, sR, a, Rmax):
+    """Plain lattice sum of f/R^6 over images within Rmax plus the continuum
+    tail 4 pi/(3 Omega Rmax^3) per ordered pair (f = 1 there)."""
+    R = np.asarray(R); N = len(R)
+    vol = abs(np.linalg.det(lat))
+    B = 2 * np.pi * np.linalg.inv(lat).T
+    nmax = [int(np.ceil(Rmax * np.linalg.norm(B[v]) / (2 * np.pi))) + 2 for v in range(3)]
+    n = np.array([[x, y, z] for x in range(-nmax[0], nmax[0] + 1) for y in range(-nmax[1], nmax[1] + 1)
+                  for z in range(-nmax[2], nmax[2] + 1)], float) @ lat
+    E = 0.0
+    for i in range(N):
+        for j in range(N):
+            x = R[j] - R[i] + n
+            d = np.linalg.norm(x, axis=1)
+            d = d[(d > 0) & (d <= Rmax)]
+            f = 1.0 / (1.0 + np.exp(-a * (d / (sR * (rv[i] + rv[j])) - 1.0))) if sR > 0 else 1.0
+            c6 = 1.5 * a0[i] * a0[j] / (1 / om[i] + 1 / om[j])
+            E += -0.5 * c6 * (np.sum(f / d ** 6) + 4 * np.pi / (3 * vol * Rmax ** 3))
+    return E
+
+
+@pytest.mark.parametrize("sR", [0.0, 0.94])
+def test_ts_ewald_equals_direct_lattice_sum(sR):
+    """The R^-6 lattice sum converges absolutely, so the Ewald split must agree
+    with the plain sum over images (this pins the readings of eq:ts-ewald:
+    G = 0 term included, self term -gamma^6/6); and it must not depend on
+    gamma."""
+    R, lat, a0, om, rv = _cell(seed=21, N=3)
+    Ed = _ts_direct(R, lat, a0, om, rv, sR, 20.0, Rmax=120.0)
+    g, rc, kc = oracle.ewald_defaults(lat)
+    Es = [oracle.ts(R, a0, om, rv, sR=sR, lattice=lat, gamma=g * s, rc=6 / (g * s), kc=10 * g * s)["energy"]
+          for s in (0.7, 1.0, 1.4)]
+    # the sharp sphere of the plain sum leaves ~1e-7 relative (lattice points
+    # near its surface); the G = 0 term or the self term alone are ~1e-2 and ~1
+    assert abs(Es[1] - Ed) < 1e-6 * abs(Ed)
+    assert max(Es) - min(Es) < 1e-10 * abs(Ed)  # the cutoffs converge to ~1e-10 relative (Sec. 3.3)
+
+
+def test_ts_gradients_fd():
+    coords, a0, om, rv = _cluster(13, 6)
+    R, lat, pa0, pom, prv = _cell(seed=22, N=3)
+    for (X, A0, OM, RV, kw) in ((coords, a0, om, rv, {}), (R, pa0, pom, prv, {"lattice": lat})):
+        out = oracle.ts(X, A0, OM, RV, sR=0.94, **kw)
+
+        def E(x=X, a=A0, w=OM, v=RV):
+            return oracle.ts(x, a, w, v, sR=0.94, **kw)["energy"]
+
+        for idx in [(0, 0), (1, 2), (2, 1)]:
+            np.testing.assert_allclose(out["grad_R"][idx], _fd(lambda x: E(x=x), X, idx, 1e-4), atol=1e-11)
+        for i in range(2):
+            np.testing.assert_allclose(out["grad_alpha0"][i], _fd(lambda x: E(a=x), A0, i, 1e-5), rtol=1e-7)
+            np.testing.assert_allclose(out["grad_omega"][i], _fd(lambda x: E(w=x), OM, i, 1e-6), rtol=1e-7)
+            np.testing.assert_allclose(out["grad_rvdw"][i], _fd(lambda x: E(v=x), RV, i, 1e-5),
+                                       rtol=1e-6, atol=1e-12)
+        assert abs(out["grad_R"].sum(axis=0)).max() < 1e-14
