@@ -180,6 +180,20 @@ mbd_status mbd_evaluate_batch(mbd_ctx *ctx, int32_t n_sys, const mbd_system *sys
 #define MBD_NOALLOC_SCRATCH_BYTES (128ull << 20)
 mbd_status mbd_evaluate_noalloc(mbd_ctx *ctx, const mbd_system *sys, unsigned want, mbd_result *out);
 
+/* Pairwise (TS) dispersion energy and gradients (Sec. 2.6 eq:pairwise):
+ *   E = -1/2 sum_{i != j} C6_ij f(R_ij)/R_ij^6,
+ *   C6_ij = (3/2) alpha0_i alpha0_j / (1/omega_i + 1/omega_j),
+ * f the Fermi damping of eq:fermi-damping with s_R = sys->beta and steepness
+ * sys->a (the TS method uses a = 20).  Periodic (sys->lattice != NULL): the
+ * energy per cell, summed over all images with the Ewald split of
+ * eq:ts-ewald for the undamped R^-6 sum (ewald_gamma/rc/kc as for
+ * mbd_evaluate, G = 0 term included) minus the real-space sum of (1-f)/R^6;
+ * the q mesh fields are ignored.  want: MBD_WANT_ENERGY, _GRAD_COORDS,
+ * _GRAD_ALPHA0, _GRAD_OMEGA (omega or C6 per param_kind), _GRAD_RVDW,
+ * _ERRORS (all four set to 0); _GRAD_LATTICE and _EIGVALS give
+ * MBD_ERR_UNSUPPORTED.  Input validation and errors as for mbd_evaluate. */
+mbd_status mbd_ts_evaluate(mbd_ctx *ctx, const mbd_system *sys, unsigned want, mbd_result *out);
+
 /* Dense symmetric eigensolver of the MBD path, exposed for testing and reuse:
  * the Householder reduction, divide-and-conquer tridiagonal solve and
  * back-transform used for Q.  A: [nbatch] matrices of order n, column-major

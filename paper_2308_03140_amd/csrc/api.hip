@@ -757,6 +757,55 @@ mbd_status mbd_evaluate_noalloc(mbd_ctx* c, const mbd_system* s, unsigned want, 
     return code_message(c, codes[0], "mbd_evaluate_noalloc");
 }
 
+mbd_status mbd_ts_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_result* out) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    c->err_code = 0;
+    if (want & (MBD_WANT_GRAD_LATTICE | MBD_WANT_EIGVALS))
+        return fail(c, MBD_ERR_UNSUPPORTED, "mbd_ts_evaluate", "grad_lattice and eigvals are not defined here");
+    mbd_status r = check_system(c, s, want, out, true);
+    if (r != MBD_OK) return r;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_ts_evaluate", "hipSetDevice");
+    const hipStream_t st = c->stream;
+    SysDesc d = make_desc(s, want, out);
+    d.atom_off = 0;
+    d.mat0 = 0;
+    d.nmat = 0;
+    PeriodicSetup ps;
+    const bool periodic = s->lattice != nullptr;
+    if (periodic) {
+        // the pairwise lattice sum has no q mesh: one dummy point for the setup
+        mbd_system sq = *s;
+        const double q0[3] = {0.0, 0.0, 0.0};
+        sq.n_q = 1;
+        sq.q_frac = q0;
+        r = setup_periodic(c, &sq, d, ps);
+        if (r != MBD_OK) return r;
+    }
+    const int N = s->n_atoms;
+    SysDesc* sd_dev = (SysDesc*)ws(c, "sysdesc", sizeof(SysDesc));
+    unsigned* status = wsT<unsigned>(c, "status", 1);
+    double* om = wsT<double>(c, "om", N);
+    double* cc = wsT<double>(c, "cc", N);
+    double* eatom = wsT<double>(c, "ts_eatom", N);
+    int* img = wsT<int>(c, "img", std::max<size_t>(3, ps.img.size()));
+    int* rec = wsT<int>(c, "rec", std::max<size_t>(3, ps.rec.size()));
+    if (!sd_dev || !status || !om || !cc || !eatom || !img || !rec) return (mbd_status)c->err_code;
+    HIPCHK(hipMemcpyAsync(sd_dev, &d, sizeof(SysDesc), hipMemcpyHostToDevice, st), "upload");
+    if (periodic) {
+        HIPCHK(hipMemcpyAsync(img, ps.img.data(), sizeof(int) * ps.img.size(), hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(hipMemcpyAsync(rec, ps.rec.data(), sizeof(int) * ps.rec.size(), hipMemcpyHostToDevice, st), "upload");
+    }
+    fill_u32_launch(st, status, 1, 0u);
+    mbd_prep_launch(st, sd_dev, 1, N, om, cc, status);
+    mbd_ts_launch(st, sd_dev, N, om, img, (int)ps.img.size() / 3, rec, (int)ps.rec.size() / 3, periodic ? 1 : 0,
+                  eatom, status);
+    HIPCHK(hipGetLastError(), "ts");
+    unsigned sth = 0;
+    HIPCHK(hipMemcpyAsync(&sth, status, sizeof(unsigned), hipMemcpyDeviceToHost, st), "status");
+    HIPCHK(hipStreamSynchronize(st), "synchronize");
+    return code_message(c, status_code(sth), "mbd_ts_evaluate");
+}
+
 mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, unsigned want, mbd_result* out,
                               int32_t* status) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;

@@ -81,3 +81,8 @@ void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const doubl
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                               const double* qcart, int nq, const int* img, int nimg, const int* rec, int nrec,
                               MatBatch<double> M, double* partial, int N);
+
+// pairwise (TS) dispersion: per-atom energy shares into eatom, gradients into
+// the descriptor's outputs, then the energy (and errors[0..3] = 0)
+void mbd_ts_launch(hipStream_t st, const SysDesc* sd, int N, const double* om, const int* img, int nimg,
+                   const int* rec, int nrec, int periodic, double* eatom, unsigned* status);

@@ -160,6 +160,34 @@ def evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q
     return out
 
 
+def ts_evaluate(ctx, coords, alpha0, omega, rvdw, sR, a=20.0, lattice=None, param="omega", gradients=True,
+                ewald=(0.0, 0.0, 0.0)):
+    """Pairwise (TS) dispersion energy (and gradients) of one finite or
+    periodic system (mbd_ts_evaluate): s_R and the damping steepness a
+    (TS: 20) take the places of beta and a of the MBD damping."""
+    ctx.sync_stream()
+    dev = ctx.device
+    s, keep = make_system(coords, alpha0, omega, rvdw, sR, a, lattice, [[0.0, 0.0, 0.0]] if lattice is not None
+                          else None, param=param, ewald=ewald, device=dev)
+    N = s.n_atoms
+    out = {"energy": torch.empty(1, dtype=torch.float64, device=dev)}
+    r = A.MbdResult()
+    r.energy = out["energy"].data_ptr()
+    want = A.MBD_WANT_ENERGY
+    if gradients:
+        for name, field, shape, bit in (("grad_coords", "grad_coords", (N, 3), A.MBD_WANT_GRAD_COORDS),
+                                        ("grad_alpha0", "grad_alpha0", (N,), A.MBD_WANT_GRAD_ALPHA0),
+                                        ("grad_omega", "grad_omega_or_c6", (N,), A.MBD_WANT_GRAD_OMEGA),
+                                        ("grad_rvdw", "grad_rvdw", (N,), A.MBD_WANT_GRAD_RVDW)):
+            out[name] = torch.empty(*shape, dtype=torch.float64, device=dev)
+            setattr(r, field, out[name].data_ptr())
+            want |= bit
+    code = A.mbd_ts_evaluate(ctx.handle, s, want, r)
+    if code != A.MBD_OK:
+        _raise(ctx, code)
+    return out
+
+
 def evaluate_batch(ctx, systems, gradients=True, errors=True):
     """systems: list of dicts with coords, alpha0, omega, rvdw (, beta, a).  Finite only."""
     ctx.sync_stream()
