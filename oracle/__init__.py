@@ -251,6 +251,32 @@ def ts(R, alpha0, omega, rvdw, sR, a=20.0, lattice=None, gamma=None, rc=None, kc
     return {"energy": float(E[0]), "grad_R": gR, "grad_alpha0": ga, "grad_omega": gw, "grad_rvdw": gv}
 
 
+def freq_terms(R, alpha0, omega, rvdw, beta=0.83, a=6.0, nfreq=15, norder=6, lattice=None, q_frac=None,
+               gamma=None, rc=None, kc=None):
+    """Frequency-route energies (Sec. 2.5): E by eq:log-formula, the
+    renormalised energy of eq:gould-norm, min(1 + x_k), and the many-body
+    orders E^(1..norder) of eq:rpa, from the eigenvalues x_k of
+    alpha(iu)^{1/2} T^lr alpha(iu)^{1/2} on an nfreq-point frequency grid."""
+    R = _arr(R, (-1, 3)); N = R.shape[0]
+    L = None; qf = None; nq = 1
+    if lattice is not None:
+        L = _arr(lattice, (3, 3))
+        qf = _arr(q_frac, (-1, 3)); nq = qf.shape[0]
+        g0, rc0, kc0 = ewald_defaults(L)
+        gamma = g0 if gamma is None else gamma
+        rc = rc0 if rc is None else rc
+        kc = kc0 if kc is None else kc
+    t = np.empty(3 + norder)
+    lib = _load()
+    lib.orc_mbd_freq_terms.restype = ctypes.c_int
+    rcode = lib.orc_mbd_freq_terms(N, _p(R), _p(L), nq, _p(qf), ctypes.c_double(gamma or 0.0),
+                                   ctypes.c_double(rc or 0.0), ctypes.c_double(kc or 0.0), _p(_arr(alpha0)),
+                                   _p(_arr(omega)), _p(_arr(rvdw)), ctypes.c_double(beta), ctypes.c_double(a),
+                                   nfreq, norder, _p(t))
+    _check(rcode, "freq_terms")
+    return {"energy": t[0], "energy_gould": t[1], "min_one_plus_x": t[2], "orders": t[3:]}
+
+
 def min_coupling_eig(R, alpha0, rvdw, beta=0.83, a=6.0):
     """Smallest eigenvalue of alpha0^{1/2} T^lr alpha0^{1/2} (collapse indicator)."""
     R = _arr(R, (-1, 3)); N = R.shape[0]

@@ -1095,3 +1095,95 @@ int orc_ts(int N, const double *R, const double *lattice, double gamma,
     if (L) lattice_free(L);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Frequency route terms, Sec. 2.5: eq:log-formula, eq:rpa, eq:gould-norm      */
+/* ------------------------------------------------------------------------- */
+
+/* ln(1 + x~) - x~ of eq:gould-norm.  For x < 0, x~ = -erf(y)^{1/4} with
+ * y = (sqrt(pi)/2) x^4.  ln erf(y) is taken as ln(erf(y)) for small y and as
+ * ln(1 - erfc(y)) for large y, and 1 + x~ = -expm1(ln erf(y) / 4), so both
+ * stay accurate when erf(y) is tiny or close to 1. */
+static double gould_term(double x)
+{
+    if (x >= 0.0) return log1p(x) - x;
+    double y = sqrt(PI) / 2.0 * x * x * x * x;
+    double l = y < 0.5 ? log(erf(y)) : log1p(-erfc(y));   /* ln erf(y) */
+    double xt = -exp(0.25 * l);
+    double onep = -expm1(0.25 * l);      /* 1 + x~ */
+    return log(onep) - xt;
+}
+
+int orc_mbd_freq_terms(int N, const double *R, const double *lattice, int nq,
+                       const double *q_frac, double gamma, double rc, double kc,
+                       const double *alpha0, const double *omega,
+                       const double *rvdw, double beta, double a, int nfreq,
+                       int norder, double *terms)
+{
+    if (N < 1 || nfreq < 1 || norder < 1) return 1;
+    int periodic = lattice != NULL;
+    if (!periodic) nq = 1;
+    int n = 3 * N, m = periodic ? 2 * n : n;
+    double *x = (double *)malloc(sizeof(double) * nfreq);
+    double *wx = (double *)malloc(sizeof(double) * nfreq);
+    orc_gauss_legendre(nfreq, x, wx);
+    double *au = (double *)malloc(sizeof(double) * N);
+    double *one = (double *)malloc(sizeof(double) * N);
+    for (int i = 0; i < N; i++) one[i] = 1.0;
+    double *K = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *Ki = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *lam = (double *)malloc(sizeof(double) * m);
+    double B[9], Ainv[9];
+    if (periodic) {
+        inv3(lattice, Ainv);
+        for (int u = 0; u < 3; u++)
+            for (int d = 0; d < 3; d++) B[u * 3 + d] = 2.0 * PI * Ainv[d * 3 + u];
+    }
+    double Elog = 0.0, Eg = 0.0, xmin = 1e300;
+    double *En = (double *)calloc(norder, sizeof(double));
+    int rcode = 0;
+    for (int f = 0; f < nfreq && !rcode; f++) {
+        /* u = 0.6 (1+x)/(1-x) (Sec. 3.3), du = 1.2/(1-x)^2 dx */
+        double u = 0.6 * (1.0 + x[f]) / (1.0 - x[f]);
+        double du = 1.2 / ((1.0 - x[f]) * (1.0 - x[f])) * wx[f];
+        /* eq:dyn-pol */
+        for (int i = 0; i < N; i++) au[i] = alpha0[i] / (1.0 + u * u / (omega[i] * omega[i]));
+        for (int t = 0; t < nq && !rcode; t++) {
+            /* alpha(iu)^{1/2} T^lr alpha(iu)^{1/2}: Q of eq:q-matrix with omega = 1, minus I */
+            int sw;
+            if (!periodic) {
+                orc_assemble_finite(N, R, au, one, rvdw, beta, a, K);
+                for (int p = 0; p < n; p++) K[(size_t)p * n + p] -= 1.0;
+                sw = orc_jacobi(n, K, lam, NULL);
+            } else {
+                double q[3];
+                for (int d = 0; d < 3; d++)
+                    q[d] = q_frac[3 * t] * B[d] + q_frac[3 * t + 1] * B[3 + d] + q_frac[3 * t + 2] * B[6 + d];
+                orc_assemble_periodic(N, R, lattice, q, gamma, rc, kc, au, one, rvdw, beta, a, K, Ki);
+                for (int p = 0; p < n; p++) K[(size_t)p * n + p] -= 1.0;
+                sw = orc_jacobi_hermitian(n, K, Ki, lam, NULL);
+            }
+            if (sw < 0) { rcode = 3; break; }
+            /* every Hermitian eigenvalue appears twice in the real embedding */
+            double wgt = du / (2.0 * PI) / nq * (periodic ? 0.5 : 1.0);
+            for (int k = 0; k < m; k++) {
+                double xk = lam[k];
+                if (1.0 + xk < xmin) xmin = 1.0 + xk;
+                Elog += wgt * (1.0 + xk > 0.0 ? log1p(xk) : NAN);
+                Eg += wgt * gould_term(xk);
+                /* eq:rpa: E^(n) = -(1/2pi) int du ((-1)^n / n) Tr (alpha T)^n */
+                double pw = 1.0;
+                for (int o = 1; o <= norder; o++) {
+                    pw *= xk;
+                    En[o - 1] += wgt * ((o % 2) ? 1.0 : -1.0) / o * pw;
+                }
+            }
+        }
+    }
+    terms[0] = Elog;
+    terms[1] = Eg;
+    terms[2] = xmin;
+    for (int o = 0; o < norder; o++) terms[3 + o] = En[o];
+    free(x); free(wx); free(au); free(one); free(K); free(Ki); free(lam); free(En);
+    return rcode;
+}

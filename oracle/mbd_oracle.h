@@ -108,6 +108,23 @@ int orc_ts(int N, const double *R, const double *lattice, double gamma,
            double *grad_R, double *grad_alpha0, double *grad_omega,
            double *grad_rvdw);
 
+/* Frequency route of Sec. 2.5 with the eigenvalues x_k of
+ * K(u) = alpha(iu)^{1/2} T^lr alpha(iu)^{1/2} (eq:dyn-pol; periodic: K(u, q)
+ * on the q list, averaged): nfreq Gauss-Legendre points on the map of
+ * Sec. 3.3, the oracle's Jacobi for the x_k.  terms [3 + norder]:
+ *   [0] E = (1/2pi) int du sum_k ln(1 + x_k)      (eq:log-formula; NaN if
+ *                                                   some 1 + x_k <= 0)
+ *   [1] (1/2pi) int du sum_k (ln(1 + x~_k) - x~_k) (eq:gould-norm)
+ *   [2] min over u, q, k of 1 + x_k
+ *   [3 + n - 1] E^(n) = -(1/2pi) int du ((-1)^n/n) sum_k x_k^n, n = 1..norder
+ *               (eq:rpa; E^(1) vanishes for finite systems)
+ * lattice == NULL: finite (nq, q_frac, gamma, rc, kc unused). */
+int orc_mbd_freq_terms(int N, const double *R, const double *lattice, int nq,
+                       const double *q_frac, double gamma, double rc, double kc,
+                       const double *alpha0, const double *omega,
+                       const double *rvdw, double beta, double a, int nfreq,
+                       int norder, double *terms);
+
 /* Smallest eigenvalue of alpha0^{1/2} T^lr alpha0^{1/2} (finite). */
 int orc_min_coupling_eig(int N, const double *R, const double *alpha0,
                          const double *rvdw, double beta, double a,

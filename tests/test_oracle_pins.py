@@ -539,3 +539,78 @@ def test_ts_gradients_fd():
             np.testing.assert_allclose(out["grad_rvdw"][i], _fd(lambda x: E(v=x), RV, i, 1e-5),
                                        rtol=1e-6, atol=1e-12)
         assert abs(out["grad_R"].sum(axis=0)).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# frequency route: eq:log-formula, eq:rpa, eq:gould-norm
+# --------------------------------------------------------------------------
+
+def test_freq_terms_log_formula_equals_eigen_route():
+    """eq:log-formula equals eq:mbd-energy (the integral of
+    ln((lambda + u^2)/(omega^2 + u^2)) over u is pi (sqrt(lambda) - omega)),
+    for a finite cluster and for a periodic cell on a q mesh."""
+    coords, a0, om, rv = _cluster(12, 7)
+    t = oracle.freq_terms(coords, a0, om, rv, nfreq=40, norder=2)
+    e = oracle.mbd_finite(coords, a0, om, rv, gradients=False)["energy"]
+    assert abs(t["energy"] - e) < 1e-11 * abs(e)
+    R, lat, pa0, pom, prv = _cell()
+    qf = oracle.monkhorst_pack(2, 2, 1)
+    t = oracle.freq_terms(R, pa0, pom, prv, nfreq=40, norder=2, lattice=lat, q_frac=qf)
+    e = oracle.mbd_periodic(R, lat, qf, pa0, pom, prv, gradients=False)["energy"]
+    assert abs(t["energy"] - e) < 1e-10 * abs(e)
+
+
+def test_freq_terms_second_order_is_pairwise_with_g_squared():
+    """eq:pairwise: the second-order term is the pairwise energy with
+    f = R^6 Tr(T_lr^2)/6 = g^2 and C6_ij = (3/2) alpha_i alpha_j/(1/omega_i +
+    1/omega_j); the first-order term vanishes for a finite system (T_ii = 0)."""
+    coords, a0, om, rv = _cluster(14, 6)
+    t = oracle.freq_terms(coords, a0, om, rv, nfreq=40, norder=2)
+    E2 = 0.0
+    for i in range(6):
+        for j in range(6):
+            if i == j:
+                continue
+            d = np.linalg.norm(coords[j] - coords[i])
+            g = _fermi(d, 0.83 * (rv[i] + rv[j]))
+            E2 += -0.5 * 1.5 * a0[i] * a0[j] / (1 / om[i] + 1 / om[j]) * g * g / d ** 6
+    assert abs(t["orders"][1] - E2) < 1e-11 * abs(E2)
+    assert abs(t["orders"][0]) < 1e-15
+
+
+def test_freq_terms_series_sums_to_log():
+    """Weak coupling (every |x_k| < 1): the many-body expansion eq:rpa,
+    summed over orders, converges to eq:log-formula; the renormalisation of
+    eq:gould-norm changes only the negative x_k, by O(|x|^9), and its -x~ term
+    removes the first order: E_Gould = E - E^(1) to that order."""
+    coords, a0, om, rv = _cluster(15, 6)
+    t = oracle.freq_terms(coords, 0.2 * a0, om, rv, nfreq=30, norder=40)
+    assert abs(t["orders"].sum() - t["energy"]) < 1e-13 * abs(t["energy"])
+    # x~ - x = (pi/48) |x|^9 + ... for x < 0: with |x| <= 0.1 the two energies agree closely
+    t = oracle.freq_terms(coords, 0.05 * a0, om, rv, nfreq=30, norder=2)
+    assert abs(t["energy_gould"] - (t["energy"] - t["orders"][0])) < 1e-8 * abs(t["energy"])
+
+
+def test_freq_terms_first_order_lorentz():
+    """One atom per simple cubic cell at q = 0: T_ii(0) = -4 pi/(3 Omega) I
+    (Lorentz field), so E^(1) = (1/2pi) int alpha(iu) du Tr T_ii = -pi
+    alpha0 omega/Omega (using int_0^inf alpha(iu) du = pi alpha0 omega/2)."""
+    L, a0, om = 40.0, 11.0, 0.6
+    t = oracle.freq_terms(np.zeros((1, 3)), [a0], [om], [3.5], nfreq=40, norder=1, lattice=np.eye(3) * L,
+                          q_frac=[[0.0, 0.0, 0.0]])
+    assert abs(t["orders"][0] - (-np.pi * a0 * om / L ** 3)) < 1e-13
+
+
+def test_freq_terms_collapse_gould_finite():
+    """Inside the dipole collapse (some 1 + x_k <= 0) eq:log-formula has no
+    real value, while the renormalised energy of eq:gould-norm stays finite."""
+    coords = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 3.0]])
+    # x = -2 alpha(iu)/R^3 for the mode along the axis: -1.48 at u = 0
+    t = oracle.freq_terms(coords, [20.0, 20.0], [0.5, 0.5], [1.0, 1.0], beta=0.0, nfreq=15, norder=2)
+    assert t["min_one_plus_x"] <= 0.0
+    assert np.isnan(t["energy"])
+    assert np.isfinite(t["energy_gould"]) and t["energy_gould"] < 0.0
+    # a dimer just outside the collapse: renormalised and plain energies close
+    t2 = oracle.freq_terms(coords, [12.0, 12.0], [0.5, 0.5], [1.0, 1.0], beta=0.0, nfreq=40, norder=2)
+    assert t2["min_one_plus_x"] > 0.0
+    assert abs(t2["energy_gould"] - t2["energy"]) < 0.05 * abs(t2["energy"])
