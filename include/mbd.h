@@ -194,6 +194,25 @@ mbd_status mbd_evaluate_noalloc(mbd_ctx *ctx, const mbd_system *sys, unsigned wa
  * MBD_ERR_UNSUPPORTED.  Input validation and errors as for mbd_evaluate. */
 mbd_status mbd_ts_evaluate(mbd_ctx *ctx, const mbd_system *sys, unsigned want, mbd_result *out);
 
+/* Frequency route of the MBD energy (Sec. 2.5), from the eigenvalues x_k of
+ * K(u) = alpha(iu)^{1/2} T^lr alpha(iu)^{1/2}, alpha(iu) = alpha0/(1 +
+ * u^2/omega^2) (eq:dyn-pol), on n_freq Gauss-Legendre points mapped by
+ * u = 0.6 (1 + x)/(1 - x) (Sec. 3.3; the paper's default is 15), and for
+ * periodic systems on every q of the mesh (averaged).  terms (DEVICE,
+ * [3 + n_order]) receives
+ *   [0] E = (1/2pi) int du sum_k ln(1 + x_k)            (eq:log-formula;
+ *       NaN inside the dipole collapse, where some 1 + x_k <= 0)
+ *   [1] (1/2pi) int du sum_k (ln(1 + x~_k) - x~_k)       (eq:gould-norm, the
+ *       renormalised energy; finite inside the collapse)
+ *   [2] the smallest 1 + x_k over all u (and q): the collapse indicator
+ *   [2 + n] E^(n) = -(1/2pi) int du ((-1)^n/n) sum_k x_k^n, n = 1..n_order
+ *       (eq:rpa; E^(1) vanishes for finite systems)
+ * 1 <= n_freq <= 512, 1 <= n_order <= 60.  The eigenvalues are computed in
+ * FP64 whatever the context's precision (no eigenvectors are formed).
+ * Inputs, validation and Ewald parameters as for mbd_evaluate; the outputs
+ * of mbd_result are not used. */
+mbd_status mbd_freq_evaluate(mbd_ctx *ctx, const mbd_system *sys, int32_t n_freq, int32_t n_order, double *terms);
+
 /* Dense symmetric eigensolver of the MBD path, exposed for testing and reuse:
  * the Householder reduction, divide-and-conquer tridiagonal solve and
  * back-transform used for Q.  A: [nbatch] matrices of order n, column-major

@@ -84,6 +84,7 @@ def lib():
         L.mbd_evaluate.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_uint, ctypes.POINTER(MbdResult)]
         L.mbd_evaluate_noalloc.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_uint, ctypes.POINTER(MbdResult)]
         L.mbd_ts_evaluate.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_uint, ctypes.POINTER(MbdResult)]
+        L.mbd_freq_evaluate.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_int32, ctypes.c_int32, _P]
         L.mbd_evaluate_batch.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(MbdSystem), ctypes.c_uint,
                                          ctypes.POINTER(MbdResult), ctypes.POINTER(ctypes.c_int32)]
         L.mbd_eigh.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
@@ -95,6 +96,7 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         L.mbd_last_error.argtypes = [_P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_char_p)]
         for f in ("mbd_create", "mbd_destroy", "mbd_set_stream", "mbd_evaluate", "mbd_evaluate_noalloc", "mbd_ts_evaluate",
+                  "mbd_freq_evaluate",
                   "mbd_evaluate_batch",
                   "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error", "mbd_set_profiling",
                   "mbd_get_profile"):
@@ -128,6 +130,10 @@ def mbd_evaluate_noalloc(ctx, system, want, result):
 
 def mbd_ts_evaluate(ctx, system, want, result):
     return lib().mbd_ts_evaluate(ctx, ctypes.byref(system), ctypes.c_uint(want), ctypes.byref(result))
+
+
+def mbd_freq_evaluate(ctx, system, n_freq, n_order, terms):
+    return lib().mbd_freq_evaluate(ctx, ctypes.byref(system), int(n_freq), int(n_order), _P(terms))
 
 
 def mbd_evaluate_batch(ctx, systems, want, results, status):

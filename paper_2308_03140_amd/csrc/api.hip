@@ -203,6 +203,14 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
         sytrd_launch<T>(sw, nbatch, nmax, st, ns_host, &c->prof);
     }
     HIPCHK(hipGetLastError(), "sytrd");
+    if (!vectors) {
+        // eigenvalues only: Sturm-count multisection on the tridiagonal
+        PhaseTimer ph(&c->prof, st, 4);
+        stebz_launch<T>(ns, nmax, nbatch, sw.d, sw.e, sw.sD, w_out, sW, st);
+        HIPCHK(hipGetLastError(), "stebz");
+        if (Xout) *Xout = MatBatch<T>{nullptr, 0, 0};
+        return MBD_OK;
+    }
 
     // --- divide and conquer
     StedcWs<T> dw;
@@ -250,7 +258,7 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     HIPCHK(hipGetLastError(), "stedc");
     MatBatch<T> Z = src ? dw.Z1 : dw.Z0;
 
-    if (vectors) {
+    {
         OrmtrWs<T> ow;
         const int nsplit = (nmax + ORMTR_CHUNK - 1) / ORMTR_CHUNK;
         ow.A = A; ow.tau = sw.tau; ow.sD = nmax; ow.ns = ns; ow.X = Z; ow.nmax = nmax;
@@ -804,6 +812,142 @@ mbd_status mbd_ts_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_r
     HIPCHK(hipMemcpyAsync(&sth, status, sizeof(unsigned), hipMemcpyDeviceToHost, st), "status");
     HIPCHK(hipStreamSynchronize(st), "synchronize");
     return code_message(c, status_code(sth), "mbd_ts_evaluate");
+}
+
+}  // extern "C"
+
+namespace {
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_n from the
+// three-term recurrence, started at the asymptotic estimate of each root
+void gauss_legendre_nodes(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < n; k++) {
+        double t = std::cos(pi * (k + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = t;
+            for (int m = 2; m <= n; m++) {
+                const double p2 = ((2.0 * m - 1.0) * t * p1 - (m - 1.0) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = t; p0 = 1.0; }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = t;
+        for (int m = 2; m <= n; m++) {
+            const double p2 = ((2.0 * m - 1.0) * t * p1 - (m - 1.0) * p0) / m;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n == 1 ? 1.0 : n * (t * p1 - p0) / (t * t - 1.0);
+        x[k] = t;
+        w[k] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+mbd_status mbd_freq_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, int32_t n_order, double* terms) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    c->err_code = 0;
+    if (n_freq < 1 || n_freq > 512 || n_order < 1 || n_order > 60 || !terms)
+        return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_freq_evaluate", "need 1 <= n_freq <= 512, 1 <= n_order <= 60, terms");
+    mbd_result dummy;
+    std::memset(&dummy, 0, sizeof(dummy));
+    mbd_status r = check_system(c, s, 0u, &dummy, true);
+    if (r != MBD_OK) return r;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_freq_evaluate", "hipSetDevice");
+    const hipStream_t st = c->stream;
+    const int N = s->n_atoms;
+    const bool periodic = s->lattice != nullptr;
+    SysDesc base = make_desc(s, 0u, &dummy);
+    PeriodicSetup ps;
+    if (periodic) {
+        r = setup_periodic(c, s, base, ps);
+        if (r != MBD_OK) return r;
+    }
+    const int nq = periodic ? (int)ps.qcart.size() / 3 : 1;
+    const int nmat = n_freq * nq;
+    const int nmax = periodic ? 6 * N : 3 * N;
+    const int ld = round_up(nmax, 64);
+    const long long stride = (long long)ld * nmax;
+    // the frequency grid: Gauss-Legendre on [-1, 1], u = 0.6 (1+x)/(1-x)
+    std::vector<double> gx, gw, u(n_freq), wf(n_freq);
+    gauss_legendre_nodes(n_freq, gx, gw);
+    const double twopi = 6.283185307179586476925;
+    for (int f = 0; f < n_freq; f++) {
+        u[f] = 0.6 * (1.0 + gx[f]) / (1.0 - gx[f]);
+        wf[f] = 1.2 / ((1.0 - gx[f]) * (1.0 - gx[f])) * gw[f] / twopi;
+    }
+    // descriptor 0: the system; descriptor f + 1: frequency f (its c, omega
+    // entries at offset f N)
+    std::vector<SysDesc> sds(n_freq + 1, base);
+    for (int f = 0; f <= n_freq; f++) {
+        sds[f].atom_off = f == 0 ? 0 : (f - 1) * N;
+        sds[f].mat0 = f == 0 ? 0 : (f - 1) * nq;
+        sds[f].nmat = nq;
+        sds[f].embed = periodic ? 1 : 0;
+    }
+    std::vector<int> nsh(nmat, nmax);
+    SysDesc* sd_dev = (SysDesc*)ws(c, "freq_desc", sizeof(SysDesc) * (n_freq + 1));
+    int* ns_dev = wsT<int>(c, "freq_ns", nmat);
+    unsigned* status = wsT<unsigned>(c, "freq_status", n_freq + 1);
+    double* om0 = wsT<double>(c, "om", N);
+    double* cc0 = wsT<double>(c, "cc", N);
+    double* om_f = wsT<double>(c, "freq_om", (size_t)n_freq * N);
+    double* cc_f = wsT<double>(c, "freq_cc", (size_t)n_freq * N);
+    double* u_dev = wsT<double>(c, "freq_u", n_freq);
+    double* wf_dev = wsT<double>(c, "freq_w", n_freq);
+    double* lam = wsT<double>(c, "freq_lam", (size_t)nmax * nmat);
+    double* part = wsT<double>(c, "freq_part", (size_t)nmat * (3 + n_order));
+    MatBatch<double> K = {wsT<double>(c, "A64", (size_t)stride * nmat), ld, stride};
+    if (!sd_dev || !ns_dev || !status || !om0 || !cc0 || !om_f || !cc_f || !u_dev || !wf_dev || !lam || !part || !K.p)
+        return (mbd_status)c->err_code;
+    HIPCHK(hipMemcpyAsync(sd_dev, sds.data(), sizeof(SysDesc) * (n_freq + 1), hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nmat, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(hipMemcpyAsync(u_dev, u.data(), sizeof(double) * n_freq, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(hipMemcpyAsync(wf_dev, wf.data(), sizeof(double) * n_freq, hipMemcpyHostToDevice, st), "upload");
+    fill_u32_launch(st, status, n_freq + 1, 0u);
+    mbd_prep_launch(st, sd_dev, 1, N, om0, cc0, status);
+    mbd_freq_coeff_launch(st, sd_dev, om0, u_dev, n_freq, N, om_f, cc_f);
+    if (periodic) {
+        int* img = wsT<int>(c, "img", ps.img.size());
+        int* rec = wsT<int>(c, "rec", ps.rec.size());
+        double* qcart = wsT<double>(c, "qcart", ps.qcart.size());
+        if (!img || !rec || !qcart) return (mbd_status)c->err_code;
+        HIPCHK(hipMemcpyAsync(qcart, ps.qcart.data(), sizeof(double) * ps.qcart.size(), hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(hipMemcpyAsync(img, ps.img.data(), sizeof(int) * ps.img.size(), hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(hipMemcpyAsync(rec, ps.rec.data(), sizeof(int) * ps.rec.size(), hipMemcpyHostToDevice, st), "upload");
+        for (int f = 0; f < n_freq; f++) {
+            const MatBatch<double> Kf = {K.p + (long long)f * nq * stride, ld, stride};
+            mbd_assemble_periodic_launch(st, sd_dev + 1 + f, om_f, cc_f, qcart, nq, img, (int)ps.img.size() / 3, rec,
+                                         (int)ps.rec.size() / 3, Kf, MatBatch<float>{nullptr, ld, stride},
+                                         status + 1 + f, N);
+        }
+    } else {
+        mbd_assemble_finite_launch(st, sd_dev + 1, n_freq, N, om_f, cc_f, K, MatBatch<float>{nullptr, ld, stride},
+                                   status + 1);
+    }
+    HIPCHK(hipGetLastError(), "freq assemble");
+    r = run_eig<double>(c, K, ns_dev, nsh.data(), nmax, nmat, false, lam, nmax, nullptr);
+    if (r != MBD_OK) return r;
+    mbd_freq_terms_launch(st, ns_dev, nmat, lam, nmax, n_order, part, wf_dev, n_freq, nq, periodic ? 1 : 0, terms);
+    HIPCHK(hipGetLastError(), "freq terms");
+    std::vector<unsigned> sth(n_freq + 1);
+    HIPCHK(hipMemcpyAsync(sth.data(), status, sizeof(unsigned) * (n_freq + 1), hipMemcpyDeviceToHost, st), "status");
+    HIPCHK(hipStreamSynchronize(st), "synchronize");
+    unsigned all = 0;
+    for (unsigned v : sth) all |= v;
+    return code_message(c, status_code(all & (MBD_ST_BAD_INPUT | MBD_ST_COINCIDENT)), "mbd_freq_evaluate");
 }
 
 mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, unsigned want, mbd_result* out,

@@ -125,6 +125,12 @@ struct StedcWs {
 template <typename T>
 int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st);
 
+// Eigenvalues only (Sturm counts with multisection, FP64 arithmetic): d, e of
+// the reduction ([nbatch] x sD), w [nbatch] x sW ascending.
+template <typename T>
+void stebz_launch(const int* ns, int nmax, int nbatch, const T* d, const T* e, long long sD, T* w, long long sW,
+                  hipStream_t st);
+
 // --- Back-transformation ---------------------------------------------------
 template <typename T>
 struct OrmtrWs {

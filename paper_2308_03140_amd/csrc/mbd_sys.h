@@ -86,3 +86,11 @@ void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* o
 // the descriptor's outputs, then the energy (and errors[0..3] = 0)
 void mbd_ts_launch(hipStream_t st, const SysDesc* sd, int N, const double* om, const int* img, int nimg,
                    const int* rec, int nrec, int periodic, double* eatom, unsigned* status);
+
+// frequency route: per-frequency coefficients (descriptor 0 = the system,
+// 1..nfreq = one per frequency), then the per-matrix eigenvalue sums and the
+// weighted terms {E, E_Gould, min(1+x), E^(1..norder)}
+void mbd_freq_coeff_launch(hipStream_t st, const SysDesc* sd, const double* om0, const double* u, int nfreq, int N,
+                           double* om_f, double* cc_f);
+void mbd_freq_terms_launch(hipStream_t st, const int* ns, int nmat, const double* lam, long long sL, int norder,
+                           double* part, const double* wf, int nfreq, int nq, int embed, double* terms);

@@ -188,6 +188,22 @@ def ts_evaluate(ctx, coords, alpha0, omega, rvdw, sR, a=20.0, lattice=None, para
     return out
 
 
+def freq_evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_frac=None, kgrid=None,
+                  kshift=(0.0, 0.0, 0.0), n_freq=15, n_order=6, param="omega", ewald=(0.0, 0.0, 0.0)):
+    """Frequency-route energies (mbd_freq_evaluate): returns a dict with the
+    log-formula energy, the renormalised energy, min(1 + x_k) and the
+    many-body orders E^(1..n_order) (a tensor)."""
+    ctx.sync_stream()
+    dev = ctx.device
+    s, keep = make_system(coords, alpha0, omega, rvdw, beta, a, lattice, q_frac, kgrid, kshift, param=param,
+                          ewald=ewald, device=dev)
+    t = torch.empty(3 + n_order, dtype=torch.float64, device=dev)
+    code = A.mbd_freq_evaluate(ctx.handle, s, n_freq, n_order, t.data_ptr())
+    if code != A.MBD_OK:
+        _raise(ctx, code)
+    return {"energy": t[0], "energy_gould": t[1], "min_one_plus_x": t[2], "orders": t[3:]}
+
+
 def evaluate_batch(ctx, systems, gradients=True, errors=True):
     """systems: list of dicts with coords, alpha0, omega, rvdw (, beta, a).  Finite only."""
     ctx.sync_stream()

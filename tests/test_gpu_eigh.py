@@ -167,3 +167,38 @@ def test_eigh_clustered_n1100(ctx, dtype, tol):
     assert np.abs(w - np.linalg.eigvalsh(A)).max() <= tol * nrm
     assert np.abs(A @ Z - Z * w).max() <= tol * nrm
     assert np.abs(Z.T @ Z - np.eye(n)).max() <= tol * n / 100
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 150, 257, 700])
+def test_eigh_values_only(ctx, dtype, n):
+    """No eigenvectors asked for: the Householder reduction followed by the
+    Sturm-count multisection (no divide and conquer, no back-transform)."""
+    from paper_2308_03140_amd import torch_api as T
+    _note("eigh values only %s n=%d" % (dtype, n))
+    A = gen.random_symmetric(5000 + n, n)
+    w, Z = T.eigh(ctx, torch.tensor(A, device="cuda", dtype=getattr(torch, dtype)), vectors=False)
+    assert Z is None
+    tol = 1e-12 if dtype == "float64" else 2e-5
+    _check(A, w.double().cpu().numpy(), None, tol)
+
+
+def test_eigh_values_only_structured(ctx):
+    """Exact multiplicities and zero couplings (a split tridiagonal), the real
+    embedding of a Hermitian matrix (every value twice), and a batch."""
+    from paper_2308_03140_amd import torch_api as T
+    _note("eigh values only structured")
+    A = np.diag([1.0, 1.0, 2.0, 2.0, 2.0, 3.0, 0.5, 0.5])
+    w, _ = T.eigh(ctx, torch.tensor(A, device="cuda"), vectors=False)
+    _check(A, w.cpu().numpy(), None, 1e-14)
+    rng = np.random.default_rng(4)
+    n = 48
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    H = 0.5 * (X + X.conj().T)
+    E = np.block([[H.real, -H.imag], [H.imag, H.real]])
+    w, _ = T.eigh(ctx, torch.tensor(E, device="cuda"), vectors=False)
+    _check(E, w.cpu().numpy(), None, 1e-12)
+    As = np.stack([gen.random_symmetric(88 + b, 90) for b in range(3)])
+    w, _ = T.eigh(ctx, torch.tensor(As, device="cuda"), vectors=False)
+    for b in range(3):
+        _check(As[b], w[b].cpu().numpy(), None, 1e-12)

@@ -144,3 +144,29 @@ def test_config_n2000_golden(ctx):
         e = np.abs(out[o].cpu().numpy()[ref["atoms"]] - np.array(ref[k])).max()
         _note("  max |%s - ref| = %.3e" % (o, e))
         assert e <= TOL_G, (k, e)
+
+
+@pytest.mark.parametrize("N", [5, 150])
+def test_energy_only(ctx, N):
+    """Energy alone: on the FP64 path the eigenvalues come from Sturm-count
+    multisection (no eigenvectors are formed)."""
+    _note("energy only %s N=%d" % (ctx.precision, N))
+    c = _cluster(400 + N, N)
+    ref = oracle.mbd_finite(c["coords"], c["alpha0"], c["omega"], c["rvdw"], c["beta"], c["a"], gradients=False)
+    out = _run(ctx, c, gradients=False, eigvals=True)
+    assert abs(out["energy"].item() - ref["energy"]) / N <= TOL_E[ctx.precision]
+    tol = 1e-12 if ctx.precision == "fp64" else 1e-9
+    assert np.abs(out["eigvals"].cpu().numpy()[0] - ref["eigs"]).max() <= tol
+
+
+def test_energy_only_n2000_golden(ctx):
+    import json
+    import os
+    _note("energy only N=2000 golden %s" % ctx.precision)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "cluster_n2000.json")) as f:
+        ref = json.load(f)
+    c = gen.cluster_n2000()
+    out = _run(ctx, c, gradients=False)
+    dE = abs(out["energy"].item() - ref["energy"]) / 2000
+    _note("  dE/N = %.3e" % dE)
+    assert dE <= TOL_E[ctx.precision], dE
