@@ -14,9 +14,12 @@ Secondary legs, reported in the same JSON line:
             per-molecule error of FP32+refine against FP64)
   periodic  64-atom triclinic cell, 4x4x4 Monkhorst-Pack mesh (64 Hermitian
             192x192 matrices in one batch), energy + dE/dR + dE/dlattice
+  ts        pairwise (TS) energy + gradients: N=2000 cluster and the 64-atom
+            crystal (Ewald), errors against the oracle
+  freq      frequency route on the 64-atom crystal (15 frequencies x 64 q)
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--legs c2,batch,periodic] [--tuning-dir DIR]
+                    [--legs c2,batch,periodic,ts,freq] [--tuning-dir DIR]
 """
 import argparse
 import hashlib
@@ -149,18 +152,19 @@ def leg_c2(args, torch, T, A):
         log("[bench] c2 %s warmup x%d, timed x%d" % (prec, args.warmup, args.steps))
         dt, out = timed(step, args.steps, args.warmup, torch)
         log("[bench] c2 %s %.4f s/step" % (prec, dt))
-        # launch-level timing of the reduction kernels and of each phase
-        # (separate, profiled pass)
-        A.mbd_set_profiling(ctx.handle, 1)
-        step()
+        # each phase on the host clock (no timing events: once the stream has
+        # recorded timing events every later dispatch is timestamped, which
+        # slows the launch-bound reduction), then launch-level timing of the
+        # reduction kernels in a separate, profiled evaluation
         prof = {}
-        for kind in (0, 1):
-            st, ms, nl, work = A.mbd_get_profile(ctx.handle, kind)
-            prof[kind] = (ms, nl, work)
-        # phases only (no per-launch events in the way)
         A.mbd_set_profiling(ctx.handle, 2)
         step()
         for kind in range(2, 8):
+            st, ms, nl, work = A.mbd_get_profile(ctx.handle, kind)
+            prof[kind] = (ms, nl, work)
+        A.mbd_set_profiling(ctx.handle, 1)
+        step()
+        for kind in (0, 1):
             st, ms, nl, work = A.mbd_get_profile(ctx.handle, kind)
             prof[kind] = (ms, nl, work)
         A.mbd_set_profiling(ctx.handle, 0)
@@ -285,6 +289,91 @@ def leg_periodic(args, torch, T):
                 "grad_coords_Ha_per_bohr": float(np.abs(o32["grad_coords"] - o64["grad_coords"]).max()),
                 "grad_alpha0": float(np.abs(o32["grad_alpha0"] - o64["grad_alpha0"]).max()),
                 "grad_lattice_Ha_per_bohr": float(np.abs(o32["grad_lattice"] - o64["grad_lattice"]).max())}}
+
+
+TS_SR, TS_A = 0.94, 20.0
+# FP64 operations of one finite pair term of the pairwise kernel, counted from
+# its source: distance (3 sub, 3 fma, sqrt ~ 10, reciprocal ~ 10, 4 mul),
+# Fermi factor (divide ~ 10, 2, exp ~ 20, divide ~ 10, 4), C6 (2 reciprocals
+# ~ 20, 4), energy, gradient and parameter terms (~ 20)
+TS_OPS_PER_PAIR = 120
+
+
+def leg_ts(args, torch, T):
+    """Pairwise (TS) dispersion: N=2000 cluster (finite, all ordered pairs) and
+    the 64-atom crystal (periodic, Ewald split), energy + all gradients, FP64;
+    error of every result against the oracle."""
+    import numpy as np
+
+    import gen
+    import oracle
+    dev = torch.device("cuda", 0)
+    ctx = T.Context(0, "fp64")
+    out = {}
+    for name, c in (("finite_n2000", gen.cluster_n2000()), ("crystal_n64", gen.crystal_n64())):
+        lat = c["lattice"] if name.startswith("crystal") else None
+        coords = torch.tensor(c["coords"], device=dev)
+        a0 = torch.tensor(c["alpha0"], device=dev)
+        om = torch.tensor(c["omega"], device=dev)
+        rv = torch.tensor(c["rvdw"], device=dev)
+
+        def step():
+            return T.ts_evaluate(ctx, coords, a0, om, rv, TS_SR, TS_A, lattice=lat)
+
+        log("[bench] ts %s warmup x%d, timed x%d" % (name, args.warmup, 4 * args.steps))
+        dt, o = timed(step, 4 * args.steps, args.warmup, torch)
+        ref = oracle.ts(c["coords"], c["alpha0"], c["omega"], c["rvdw"], sR=TS_SR, a=TS_A, lattice=lat)
+        N = len(c["omega"])
+        res = {"s_per_eval": dt,
+               "errors_vs_oracle": {
+                   "energy_per_atom_Ha": abs(o["energy"].item() - ref["energy"]) / N,
+                   "grad_coords_Ha_per_bohr": float(np.abs(o["grad_coords"].cpu().numpy() - ref["grad_R"]).max())}}
+        if lat is None:
+            pairs = N * (N - 1)
+            res["pairs_per_s"] = pairs / dt
+            res["alu_roofline"] = {"bound": "alu", "ops_per_pair": TS_OPS_PER_PAIR,
+                                   "achieved_TFs": pairs * TS_OPS_PER_PAIR / dt / 1e12, "peak": FP64_PEAK_TFS,
+                                   "frac": pairs * TS_OPS_PER_PAIR / dt / 1e12 / FP64_PEAK_TFS}
+        out[name] = res
+    ctx.close()
+    out["workload"] = ("pairwise (TS) energy + dE/dR, dE/dalpha0, dE/domega, dE/dRv; s_R = %.2f, a = %g; N=2000 "
+                       "cluster (finite) and 64-atom crystal (periodic, Ewald defaults)" % (TS_SR, TS_A))
+    return out
+
+
+def leg_freq(args, torch, T, A):
+    """Frequency route on the 64-atom crystal: 15 frequencies x 64 q points =
+    960 embedded matrices of order 384 in one batch (eigenvalues only), with
+    the log-formula energy against the eigenvalue-route energy (their
+    difference is the 15-point quadrature error) and the renormalised energy
+    and many-body orders."""
+    import gen
+    dev = torch.device("cuda", 0)
+    c = gen.crystal_n64()
+    ctx = T.Context(0, "fp64")
+    coords = torch.tensor(c["coords"], device=dev)
+
+    def step():
+        return T.freq_evaluate(ctx, coords, c["alpha0"], c["omega"], c["rvdw"], beta=c["beta"], a=c["a"],
+                               lattice=c["lattice"], q_frac=c["q_frac"], n_freq=15, n_order=6)
+
+    log("[bench] freq warmup x%d, timed x%d" % (args.warmup, args.steps))
+    dt, o = timed(step, args.steps, args.warmup, torch)
+    e = T.evaluate(ctx, coords, c["alpha0"], c["omega"], c["rvdw"], beta=c["beta"], a=c["a"], lattice=c["lattice"],
+                   q_frac=c["q_frac"], gradients=False)["energy"].item()
+    A.mbd_set_profiling(ctx.handle, 2)
+    step()
+    ph = {k: A.mbd_get_profile(ctx.handle, k)[1] for k in (3, 4)}
+    A.mbd_set_profiling(ctx.handle, 0)
+    ctx.close()
+    n, nm = 384, 960
+    return {"workload": "64-atom crystal, 4x4x4 mesh, 15 frequencies: 960 matrices of order 384, eigenvalues only",
+            "s_per_eval": dt, "energy_log_formula": o["energy"].item(), "energy_eigen_route": e,
+            "quadrature_error_rel": abs(o["energy"].item() - e) / abs(e),
+            "energy_gould": o["energy_gould"].item(), "min_one_plus_x": o["min_one_plus_x"].item(),
+            "orders": [float(x) for x in o["orders"].cpu().numpy()],
+            "phases_ms": {"reduction": ph[3], "eigenvalues": ph[4]},
+            "reduction_t_min_ms": nm * n ** 3 / 6 * 8 / (HBM_PEAK_GBS * 1e9) * 1e3}
 
 
 def pmc_pass(torch, T):
@@ -494,7 +583,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="c2,batch,periodic")
+    ap.add_argument("--legs", default="c2,batch,periodic,ts,freq")
     ap.add_argument("--tuning-dir", default=None, help="write the autotuner tables (JSON) here")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write the SYMV HBM-traffic file under profiles/ from two --pmc-pass counter runs")
@@ -595,6 +684,10 @@ def main():
         line["batch"] = leg_batch(args, torch, T)
     if "periodic" in legs:
         line["periodic"] = leg_periodic(args, torch, T)
+    if "ts" in legs:
+        line["ts"] = leg_ts(args, torch, T)
+    if "freq" in legs:
+        line["freq"] = leg_freq(args, torch, T, A)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline()

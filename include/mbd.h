@@ -242,7 +242,8 @@ mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
  * the summed event time (ms), the number of records and the summed
  * algorithmic work: bytes of the lower trailing triangle read (kind 0), flops
  * of the rank-2k update (kind 1), 0 for the phases.  enable = 2 records the
- * phases only (no per-launch events, so the phases run as unprofiled). */
+ * phases only, without timing events (which would slow every launch): the
+ * stream is synchronised at each phase boundary and the host clock read. */
 mbd_status mbd_set_profiling(mbd_ctx *ctx, int enable);
 mbd_status mbd_get_profile(mbd_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, double *work);
 

@@ -4,13 +4,16 @@
 // multisection.  T = tridiag(e, d, e), d[0..n-1] the diagonal and e[i] the
 // element between rows i and i+1.
 //
-// One wavefront per eigenvalue index k (k-th smallest).  The wave keeps an
-// interval [lo, hi] with count(lo) <= k < count(hi), count(x) = number of
-// eigenvalues below x; each step evaluates the count at 64 interior points,
-// lane l at lo + (hi - lo)(l + 1)/65, and keeps the sub-interval where the
-// count passes k (a ballot finds it), so the interval shrinks 65-fold per
-// step and about nine steps reach rounding level.  The count is the number
-// of negative pivots of the LDL^T factorisation of T - x I,
+// A group of L lanes (L a power of two, 1..64) works on one eigenvalue index
+// k (k-th smallest).  The group keeps an interval [lo, hi] with count(lo) <=
+// k < count(hi), count(x) = number of eigenvalues below x; each step
+// evaluates the count at L interior points, lane j of the group at lo +
+// (hi - lo)(j + 1)/(L + 1), and keeps the sub-interval where the count passes
+// k (a ballot finds it), so the interval shrinks (L + 1)-fold per step.  L = 1
+// is plain bisection (least work per eigenvalue); larger L trades work for
+// fewer sequential steps and is chosen when there are too few eigenvalues to
+// fill the device.  The count is the number of negative pivots of the LDL^T
+// factorisation of T - x I,
 //   q_0 = d_0 - x,  q_i = d_i - x - e_{i-1}^2 / q_{i-1},
 // with |q| <= pivmin replaced by -pivmin, pivmin = (smallest normal) *
 // max(1, max e^2), which keeps the count monotone in x (the classical
@@ -51,12 +54,16 @@ __device__ __forceinline__ int sturm_count(const T* d, const T* e, int n, double
 
 template <typename T>
 __global__ __launch_bounds__(256) void stebz_kernel(const int* ns, const T* d, const T* e, long long sD, T* w,
-                                                      long long sW) {
+                                                      long long sW, int L) {
     const int b = blockIdx.z;
     const int n = ns[b];
     const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (k >= n) return;  // the whole wavefront
+    const int per_wave = 64 / L;
+    const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave * per_wave >= n) return;  // the whole wavefront
+    const int g = lane / L, j = lane % L;
+    const int k = wave * per_wave + g;
+    const bool active = k < n;
     const T* db = d + (long long)b * sD;
     const T* eb = e + (long long)b * sD;
     T* wb = w + (long long)b * sW;
@@ -82,25 +89,45 @@ __global__ __launch_bounds__(256) void stebz_kernel(const int* ns, const T* d, c
     const double tnorm = fmax(fabs(gl), fabs(gu));
     double lo = gl - 2.0 * eps * tnorm * n - 4.0 * pivmin;
     double hi = gu + 2.0 * eps * tnorm * n + 4.0 * pivmin;
-    for (int it = 0; it < 64; it++) {
+    const double sect = (double)(L + 1);
+    const unsigned long long gmask = L == 64 ? ~0ull : ((1ull << L) - 1ull);
+    // stop at a relative width of 2 eps, or an absolute one of eps ||T|| (the
+    // accuracy the count itself supports) for eigenvalues near zero
+    const double atol = eps * tnorm + pivmin;
+    for (int it = 0; it < 200; it++) {
         const double width = hi - lo;
-        if (width <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;  // uniform over the wave
-        const double x = lo + width * (double)(lane + 1) / 65.0;
-        const int c = sturm_count(db, eb, n, x, pivmin);
-        const unsigned long long m = __ballot(c > k);
-        const int f = m ? __ffsll((long long)m) - 1 : 64;  // first lane whose count passes k
-        const double nlo = f == 0 ? lo : lo + width * (double)f / 65.0;
-        const double nhi = f == 64 ? hi : lo + width * (double)(f + 1) / 65.0;
-        lo = nlo;
-        hi = nhi;
+        const bool done = !active || width <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + atol;
+        if (__ballot(!done) == 0ull) break;
+        const double x = lo + width * (double)(j + 1) / sect;
+        const int c = done ? 0 : sturm_count(db, eb, n, x, pivmin);
+        const unsigned long long m = (__ballot(c > k) >> (g * L)) & gmask;
+        const int f = m ? __ffsll((long long)m) - 1 : L;  // first lane of the group whose count passes k
+        if (!done) {
+            const double nlo = f == 0 ? lo : lo + width * (double)f / sect;
+            const double nhi = f == L ? hi : lo + width * (double)(f + 1) / sect;
+            lo = nlo;
+            hi = nhi;
+        }
     }
-    if (lane == 0) wb[k] = (T)(0.5 * (lo + hi));
+    if (active && j == 0) wb[k] = (T)(0.5 * (lo + hi));
+}
+
+// lanes per eigenvalue: as many as keep the launch within the lanes the
+// device holds at once (256 CUs x 4 SIMDs x 8 waves x 64 lanes), 1 to 64
+static int stebz_lanes(long long eigenvalues) {
+    const long long cap = 256LL * 4 * 8 * 64;
+    int L = 64;
+    while (L > 1 && eigenvalues * L > cap) L >>= 1;
+    return L;
 }
 
 template <typename T>
 void stebz_launch(const int* ns, int nmax, int nbatch, const T* d, const T* e, long long sD, T* w, long long sW,
                   hipStream_t st) {
-    hipLaunchKernelGGL(stebz_kernel<T>, dim3((nmax + 3) / 4, 1, nbatch), dim3(256), 0, st, ns, d, e, sD, w, sW);
+    const int L = stebz_lanes((long long)nmax * nbatch);
+    const int per_wave = 64 / L;
+    const int waves = (nmax + per_wave - 1) / per_wave;
+    hipLaunchKernelGGL(stebz_kernel<T>, dim3((waves + 3) / 4, 1, nbatch), dim3(256), 0, st, ns, d, e, sD, w, sW, L);
 }
 template void stebz_launch<double>(const int*, int, int, const double*, const double*, long long, double*, long long,
                                    hipStream_t);

@@ -15,10 +15,12 @@
 // and the cosine argument are read from the derivation of the split; the
 // printed formula omits G = 0 and has them garbled.
 //
-// One workgroup per atom i: its threads share the (j, term) pairs of row i,
-// so the atom's energy share, its gradient and its parameter derivatives come
-// out of one block reduction each (each ordered pair's energy is counted at
-// i; dE/dR_i = sum_j C6_ij grad S_ij(R_j - R_i) gathers both orders).
+// Atom i's row of (j, term) pairs is shared by one workgroup (periodic: many
+// terms per pair) or by one wavefront (finite: one term per pair, four rows
+// per workgroup), so the atom's energy share, its gradient and its parameter
+// derivatives come out of one block or wave reduction each (each ordered
+// pair's energy is counted at i; dE/dR_i = sum_j C6_ij grad S_ij(R_j - R_i)
+// gathers both orders).
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
@@ -43,14 +45,17 @@ __global__ __launch_bounds__(256) void mbd_ts_kernel(const SysDesc* sd, const do
     __shared__ double red[4];
     const SysDesc& S = sd[0];
     const int N = S.N;
-    const int i = blockIdx.x;
-    if (i >= N) return;
+    // finite: a wavefront per row; periodic: the whole workgroup per row
+    const int i = periodic ? blockIdx.x : blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int t0 = periodic ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    const int tstep = periodic ? 256 : 64;
+    if (i >= N) return;  // uniform over the workgroup (periodic) or the wavefront (finite)
     const double* R = S.coords;
     const double ai = S.alpha0[i], wi = om[S.atom_off + i], rvi = S.rvdw[i];
     const double g = S.gamma, g3 = g * g * g, g6 = g3 * g3;
     const int nterm = periodic ? nimg + nrec : 1;
     double Ei = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, dw = 0.0, dv = 0.0;
-    for (long long t = threadIdx.x; t < (long long)N * nterm; t += 256) {
+    for (long long t = t0; t < (long long)N * nterm; t += tstep) {
         const int j = (int)(t / nterm), u = (int)(t % nterm);
         if (!periodic && j == i) continue;
         const double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
@@ -122,13 +127,22 @@ __global__ __launch_bounds__(256) void mbd_ts_kernel(const SysDesc* sd, const do
         dw += -c6 * s * wj / (wi * (wi + wj));
         dv += -S.beta * c6 * ds0;
     }
-    Ei = block_sum256(Ei, red);
-    gx = block_sum256(gx, red);
-    gy = block_sum256(gy, red);
-    gz = block_sum256(gz, red);
-    dw = block_sum256(dw, red);
-    dv = block_sum256(dv, red);
-    if (threadIdx.x == 0) {
+    if (periodic) {
+        Ei = block_sum256(Ei, red);
+        gx = block_sum256(gx, red);
+        gy = block_sum256(gy, red);
+        gz = block_sum256(gz, red);
+        dw = block_sum256(dw, red);
+        dv = block_sum256(dv, red);
+    } else {
+        Ei = wave_sum(Ei);
+        gx = wave_sum(gx);
+        gy = wave_sum(gy);
+        gz = wave_sum(gz);
+        dw = wave_sum(dw);
+        dv = wave_sum(dv);
+    }
+    if (t0 == 0) {
         eatom[i] = Ei;
         if (S.grad_coords) {
             S.grad_coords[3 * i] = gx;
@@ -165,7 +179,7 @@ __global__ __launch_bounds__(256) void mbd_ts_sum_kernel(const SysDesc* sd, cons
 
 void mbd_ts_launch(hipStream_t st, const SysDesc* sd, int N, const double* om, const int* img, int nimg,
                    const int* rec, int nrec, int periodic, double* eatom, unsigned* status) {
-    hipLaunchKernelGGL(mbd_ts_kernel, dim3(N), dim3(256), 0, st, sd, om, img, nimg, rec, nrec, periodic, eatom,
-                       status);
+    hipLaunchKernelGGL(mbd_ts_kernel, dim3(periodic ? N : (N + 3) / 4), dim3(256), 0, st, sd, om, img, nimg, rec,
+                       nrec, periodic, eatom, status);
     hipLaunchKernelGGL(mbd_ts_sum_kernel, dim3(1), dim3(256), 0, st, sd, eatom, status);
 }

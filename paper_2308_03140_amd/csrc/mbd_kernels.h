@@ -2,6 +2,7 @@
 #pragma once
 #include "mbd_internal.h"
 
+#include <chrono>
 #include <vector>
 #include <hip/hip_ext.h>
 
@@ -19,11 +20,13 @@ struct LaunchProfiler {
     std::vector<int> kind;
     std::vector<double> work;
     size_t used = 0;
-    void reset() { used = 0; kind.clear(); work.clear(); }
+    std::vector<int> host_kind;     // phases timed on the host clock (phases-only mode)
+    std::vector<double> host_ms;
+    void reset() { used = 0; kind.clear(); work.clear(); host_kind.clear(); host_ms.clear(); }
     hipEvent_t next() {
         if (used == pool.size()) {
             hipEvent_t e;
-            hipEventCreate(&e);
+            (void)hipEventCreate(&e);
             pool.push_back(e);
         }
         return pool[used++];
@@ -43,28 +46,53 @@ struct LaunchProfiler {
         for (size_t i = 0; i < kind.size(); i++) {
             if (kind[i] != k) continue;
             float e = 0;
-            hipEventElapsedTime(&e, pool[2 * i], pool[2 * i + 1]);
+            (void)hipEventElapsedTime(&e, pool[2 * i], pool[2 * i + 1]);
             t += e; ww += work[i]; c++;
+        }
+        for (size_t i = 0; i < host_kind.size(); i++) {
+            if (host_kind[i] != k) continue;
+            t += host_ms[i];
+            c++;
         }
         *ms = t; *n = c; *w = ww;
     }
-    ~LaunchProfiler() { for (auto e : pool) hipEventDestroy(e); }
+    ~LaunchProfiler() { for (auto e : pool) (void)hipEventDestroy(e); }
 };
 
-// Event pair around a phase on a stream (no-op unless profiling is enabled).
+// Timing of a phase on a stream (no-op unless profiling is enabled).  With
+// per-launch records on, an event pair brackets the phase.  Phases-only mode
+// uses no timing events at all (a timing event switches the queue to
+// timestamped dispatches, which slows every later launch): the stream is
+// synchronised at both ends and the host clock taken.
 struct PhaseTimer {
     LaunchProfiler* p;
     hipStream_t st;
+    int k = 0;
     hipEvent_t e1 = nullptr;
-    PhaseTimer(LaunchProfiler* prof, hipStream_t s, int k) : p(prof), st(s) {
+    double t0 = -1.0;
+    static double now_ms() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    }
+    PhaseTimer(LaunchProfiler* prof, hipStream_t s, int kind) : p(prof), st(s), k(kind) {
         if (!p || !p->enabled) return;
-        hipEvent_t e0;
-        p->pair(&e0, &e1, k, 0.0);
-        (void)hipEventRecord(e0, st);
+        if (p->launches) {
+            hipEvent_t e0;
+            p->pair(&e0, &e1, k, 0.0);
+            (void)hipEventRecord(e0, st);
+        } else {
+            (void)hipStreamSynchronize(st);
+            t0 = now_ms();
+        }
     }
     void stop() {
         if (e1) (void)hipEventRecord(e1, st);
         e1 = nullptr;
+        if (t0 >= 0.0) {
+            (void)hipStreamSynchronize(st);
+            p->host_kind.push_back(k);
+            p->host_ms.push_back(now_ms() - t0);
+            t0 = -1.0;
+        }
     }
     ~PhaseTimer() { stop(); }
 };
