@@ -277,6 +277,48 @@ def freq_terms(R, alpha0, omega, rvdw, beta=0.83, a=6.0, nfreq=15, norder=6, lat
     return {"energy": t[0], "energy_gould": t[1], "min_one_plus_x": t[2], "orders": t[3:]}
 
 
+def dipole_gg(r, s):
+    """T^GG of eq:tgg and its r-derivative for s = sqrt(sigma_i^2 + sigma_j^2)."""
+    T = np.empty(9); dT = np.empty(27)
+    _load().orc_dipole_gg(_p(_arr(r)), ctypes.c_double(s), _p(T), _p(dT))
+    return T.reshape(3, 3), dT.reshape(3, 3, 3)
+
+
+def scs(R, alpha0, omega, rvdw, beta=0.83, a=6.0, nfreq=15):
+    """Self-consistent screening (eq:scs, eq:contraction, eq:casimir-polder,
+    eq:scale-rvdw-scs): screened alpha0, C6, omega, R_vdW and alpha_bar(iu) at
+    u = 0 and the nfreq grid points."""
+    R = _arr(R, (-1, 3)); N = R.shape[0]
+    out = {k: np.empty(N) for k in ("alpha", "c6", "omega", "rvdw")}
+    dyn = np.empty((nfreq + 1, N))
+    lib = _load()
+    lib.orc_scs.restype = ctypes.c_int
+    rc = lib.orc_scs(N, _p(R), _p(_arr(alpha0)), _p(_arr(omega)), _p(_arr(rvdw)), ctypes.c_double(beta),
+                     ctypes.c_double(a), nfreq, _p(out["alpha"]), _p(out["c6"]), _p(out["omega"]),
+                     _p(out["rvdw"]), _p(dyn))
+    _check(rc, "scs")
+    out["alpha_dyn"] = dyn
+    return out
+
+
+def mbd_rsscs(R, alpha0, omega, rvdw, beta=0.83, a=6.0, nfreq=15, gradients=True):
+    """MBD@rsSCS energy (SCS stage, then MBD with the screened parameters) and
+    dE/dR through the screened parameters."""
+    R = _arr(R, (-1, 3)); N = R.shape[0]
+    E = np.zeros(1)
+    g = np.empty((N, 3)) if gradients else None
+    sa, sw, sv = np.empty(N), np.empty(N), np.empty(N)
+    lib = _load()
+    lib.orc_mbd_rsscs.restype = ctypes.c_int
+    rc = lib.orc_mbd_rsscs(N, _p(R), _p(_arr(alpha0)), _p(_arr(omega)), _p(_arr(rvdw)), ctypes.c_double(beta),
+                           ctypes.c_double(a), nfreq, _p(E), _p(g), _p(sa), _p(sw), _p(sv))
+    _check(rc, "mbd_rsscs")
+    out = {"energy": float(E[0]), "alpha_scs": sa, "omega_scs": sw, "rvdw_scs": sv}
+    if gradients:
+        out["grad_R"] = g
+    return out
+
+
 def min_coupling_eig(R, alpha0, rvdw, beta=0.83, a=6.0):
     """Smallest eigenvalue of alpha0^{1/2} T^lr alpha0^{1/2} (collapse indicator)."""
     R = _arr(R, (-1, 3)); N = R.shape[0]

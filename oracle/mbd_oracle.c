@@ -1187,3 +1187,271 @@ int orc_mbd_freq_terms(int N, const double *R, const double *lattice, int nq,
     free(x); free(wx); free(au); free(one); free(K); free(Ki); free(lam); free(En);
     return rcode;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Self-consistent screening (MBD@rsSCS), Sec. 2.3 and 2.7                     */
+/* ------------------------------------------------------------------------- */
+
+/* T^GG of eq:tgg for widths sigma_i, sigma_j: with zeta = r/s,
+ * s = sqrt(sigma_i^2 + sigma_j^2), Theta = (2 zeta/sqrt(pi)) e^{-zeta^2},
+ *   T^GG_ab = (erf(zeta) - Theta) T_ab + 2 zeta^2 Theta r_a r_b / r^5
+ * with T the explicit dipole tensor of eq:dipole.  As C1 delta_ab + C2 r_a r_b:
+ *   C1 = (erf - Theta)/r^3,  C2 = (2 zeta^2 Theta - 3 (erf - Theta))/r^5,
+ * and (d erf/dr = Theta/r, d Theta/dr = Theta (1 - 2 zeta^2)/r)
+ *   C1' = (2 zeta^2 Theta - 3 (erf - Theta))/r^4,
+ *   C2' = (15 (erf - Theta) - 10 zeta^2 Theta - 4 zeta^4 Theta)/r^6.
+ * dT[c][a][b] = d T^GG_ab / d r_c (may be NULL). */
+void orc_dipole_gg(const double *r, double s, double *T, double *dT)
+{
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double d = sqrt(r2);
+    double z = d / s;
+    double th = 2.0 * z / sqrt(PI) * exp(-z * z);
+    double ef = erf(z);
+    double c1 = (ef - th) / (r2 * d);
+    double c2 = (2.0 * z * z * th - 3.0 * (ef - th)) / (r2 * r2 * d);
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) T[a * 3 + b] = (a == b ? c1 : 0.0) + c2 * r[a] * r[b];
+    if (!dT) return;
+    double c1p = (2.0 * z * z * th - 3.0 * (ef - th)) / (r2 * r2);
+    double c2p = (15.0 * (ef - th) - 10.0 * z * z * th - 4.0 * z * z * z * z * th) / (r2 * r2 * r2);
+    for (int c = 0; c < 3; c++)
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double v = c2p * r[c] / d * r[a] * r[b];
+                if (a == b) v += c1p * r[c] / d;
+                if (a == c) v += c2 * r[b];
+                if (b == c) v += c2 * r[a];
+                dT[c * 9 + a * 3 + b] = v;
+            }
+}
+
+/* eq:mayer */
+static double mayer_sigma(double alpha)
+{
+    return cbrt(sqrt(2.0 / PI) * alpha / 3.0);
+}
+
+/* A(u) = diag(1/alpha(iu)) + T^scs, T^scs_ij = (1 - g_ij) T^GG_ij (i != j),
+ * g the Fermi damping with a and s_R = beta on the unscaled R_vdW
+ * (eq:scs-sr-dipole); row-major n x n */
+static void scs_matrix(int N, const double *R, const double *au, const double *rvdw,
+                       double beta, double a, double *A)
+{
+    int n = 3 * N;
+    for (int i = 0; i < N; i++)
+        for (int j = 0; j < N; j++) {
+            double blk[9] = {0};
+            if (i == j) {
+                for (int c = 0; c < 3; c++) blk[c * 4] = 1.0 / au[i];
+            } else {
+                double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
+                double s = sqrt(mayer_sigma(au[i]) * mayer_sigma(au[i]) + mayer_sigma(au[j]) * mayer_sigma(au[j]));
+                double g, omg, gd, gR0;
+                fermi(norm3(r), beta * (rvdw[i] + rvdw[j]), a, &g, &omg, &gd, &gR0);
+                double T[9];
+                orc_dipole_gg(r, s, T, NULL);
+                for (int k = 0; k < 9; k++) blk[k] = omg * T[k];
+            }
+            for (int p = 0; p < 3; p++)
+                for (int q = 0; q < 3; q++) A[(size_t)(3 * i + p) * n + 3 * j + q] = blk[p * 3 + q];
+        }
+}
+
+/* inverse of a symmetric positive definite matrix (row-major, n x n) by the
+ * oracle's Cholesky and triangular solves; returns 2 if not positive definite */
+static int spd_inverse(int n, const double *A, double *Ainv)
+{
+    double *L = (double *)malloc(sizeof(double) * (size_t)n * n);
+    memcpy(L, A, sizeof(double) * (size_t)n * n);
+    if (cholesky(n, L)) { free(L); return 2; }
+#pragma omp parallel for schedule(dynamic)
+    for (int col = 0; col < n; col++) {
+        double *y = (double *)malloc(sizeof(double) * n);
+        for (int p = 0; p < n; p++) {
+            double acc = (p == col) ? 1.0 : 0.0;
+            for (int k = 0; k < p; k++) acc -= L[(size_t)p * n + k] * y[k];
+            y[p] = acc / L[(size_t)p * n + p];
+        }
+        for (int p = n - 1; p >= 0; p--) {
+            double acc = y[p];
+            for (int k = p + 1; k < n; k++) acc -= L[(size_t)k * n + p] * y[k];
+            y[p] = acc / L[(size_t)p * n + p];
+        }
+        for (int p = 0; p < n; p++) Ainv[(size_t)p * n + col] = y[p];
+        free(y);
+    }
+    free(L);
+    return 0;
+}
+
+/* the SCS stage on nfreq Gauss-Legendre points (map of Sec. 3.3) plus u = 0:
+ * alpha_bar(u) = (alpha(iu)^{-1} + T^scs)^{-1} (eq:scs), contracted
+ * (eq:contraction); C6 by eq:casimir-polder, omega = 4 C6/(3 alpha0^2), R_vdW
+ * scaled by (alpha_bar0/alpha0)^{1/3} (eq:scale-rvdw-scs).  abar
+ * [(nfreq+1) x N] (row 0: u = 0) and the inverses Abar [(nfreq+1) x n x n]
+ * are kept when non-NULL. */
+static int scs_stage(int N, const double *R, const double *alpha0, const double *omega,
+                     const double *rvdw, double beta, double a, int nfreq,
+                     double *a_scs, double *c6_scs, double *w_scs, double *rv_scs,
+                     double *abar, double *Abar, double *uw)
+{
+    int n = 3 * N;
+    double *x = (double *)malloc(sizeof(double) * nfreq), *wx = (double *)malloc(sizeof(double) * nfreq);
+    orc_gauss_legendre(nfreq, x, wx);
+    double *au = (double *)malloc(sizeof(double) * N);
+    double *A = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *Ai = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *ab = (double *)malloc(sizeof(double) * (size_t)(nfreq + 1) * N);
+    int rc = 0;
+    for (int f = 0; f <= nfreq && !rc; f++) {
+        double u = f == 0 ? 0.0 : 0.6 * (1.0 + x[f - 1]) / (1.0 - x[f - 1]);
+        if (uw && f > 0) uw[f - 1] = 1.2 / ((1.0 - x[f - 1]) * (1.0 - x[f - 1])) * wx[f - 1];
+        for (int i = 0; i < N; i++) au[i] = alpha0[i] / (1.0 + u * u / (omega[i] * omega[i]));
+        scs_matrix(N, R, au, rvdw, beta, a, A);
+        if (spd_inverse(n, A, Ai)) { rc = 2; break; }
+        for (int i = 0; i < N; i++) {
+            double s = 0.0;
+            for (int j = 0; j < N; j++)
+                for (int c = 0; c < 3; c++) s += Ai[(size_t)(3 * i + c) * n + 3 * j + c];
+            ab[(size_t)f * N + i] = s / 3.0;
+        }
+        if (Abar) memcpy(Abar + (size_t)f * n * n, Ai, sizeof(double) * (size_t)n * n);
+    }
+    if (!rc)
+        for (int i = 0; i < N; i++) {
+            double c6 = 0.0;
+            for (int f = 1; f <= nfreq; f++) {
+                double u_w = 1.2 / ((1.0 - x[f - 1]) * (1.0 - x[f - 1])) * wx[f - 1];
+                c6 += u_w * ab[(size_t)f * N + i] * ab[(size_t)f * N + i];
+            }
+            c6 *= 3.0 / PI;
+            double a0s = ab[i];
+            if (a_scs) a_scs[i] = a0s;
+            if (c6_scs) c6_scs[i] = c6;
+            if (w_scs) w_scs[i] = 4.0 * c6 / (3.0 * a0s * a0s);
+            if (rv_scs) rv_scs[i] = rvdw[i] * cbrt(a0s / alpha0[i]);
+        }
+    if (abar) memcpy(abar, ab, sizeof(double) * (size_t)(nfreq + 1) * N);
+    free(x); free(wx); free(au); free(A); free(Ai); free(ab);
+    return rc;
+}
+
+int orc_scs(int N, const double *R, const double *alpha0, const double *omega,
+            const double *rvdw, double beta, double a, int nfreq,
+            double *alpha_scs, double *c6_scs, double *omega_scs, double *rvdw_scs,
+            double *alpha_dyn)
+{
+    if (N < 1 || nfreq < 1) return 1;
+    return scs_stage(N, R, alpha0, omega, rvdw, beta, a, nfreq, alpha_scs, c6_scs, omega_scs,
+                     rvdw_scs, alpha_dyn, NULL, NULL);
+}
+
+/* MBD@rsSCS: the SCS stage, then the MBD energy of Sec. 2.1 with the screened
+ * alpha0, omega and R_vdW (T^lr = g T with the scaled radii, eq:mbd-lr-dipole).
+ * dE/dR by the chain rule through the screened parameters: for every
+ * coordinate R_mc, d alpha_bar(u)/dR_mc = -alpha_bar (dT^scs/dR_mc) alpha_bar
+ * (the derivative of eq:scs), contracted as in eq:contraction, at u = 0 and
+ * at every frequency point. */
+int orc_mbd_rsscs(int N, const double *R, const double *alpha0, const double *omega,
+                  const double *rvdw, double beta, double a, int nfreq,
+                  double *energy, double *grad_R, double *alpha_scs, double *omega_scs,
+                  double *rvdw_scs)
+{
+    if (N < 1 || nfreq < 1) return 1;
+    int n = 3 * N, nf1 = nfreq + 1;
+    double *as = (double *)malloc(sizeof(double) * N), *ws = (double *)malloc(sizeof(double) * N);
+    double *rs = (double *)malloc(sizeof(double) * N), *c6 = (double *)malloc(sizeof(double) * N);
+    double *ab = (double *)malloc(sizeof(double) * (size_t)nf1 * N);
+    double *uw = (double *)malloc(sizeof(double) * nfreq);
+    double *Ab = grad_R ? (double *)malloc(sizeof(double) * (size_t)nf1 * n * n) : NULL;
+    int rc = scs_stage(N, R, alpha0, omega, rvdw, beta, a, nfreq, as, c6, ws, rs, ab, Ab, uw);
+    double *gR = (double *)calloc((size_t)3 * N, sizeof(double));
+    double *ga = (double *)calloc(N, sizeof(double)), *gw = (double *)calloc(N, sizeof(double));
+    double *gv = (double *)calloc(N, sizeof(double));
+    if (!rc) rc = orc_mbd_finite(N, R, as, ws, rs, beta, a, energy, grad_R ? gR : NULL,
+                                 grad_R ? ga : NULL, grad_R ? gw : NULL, grad_R ? gv : NULL, NULL);
+    if (!rc && grad_R) {
+        /* weights of d alpha_bar_i(u)/dX in dE/dX: u = 0 (alpha0, and through
+         * omega and R_vdW), u_f (through C6 and omega) */
+        double *w = (double *)malloc(sizeof(double) * (size_t)nf1 * N);
+        for (int i = 0; i < N; i++) {
+            w[i] = ga[i] - 2.0 * ws[i] / as[i] * gw[i] + gv[i] * rs[i] / (3.0 * as[i]);
+            for (int f = 1; f <= nfreq; f++)
+                w[(size_t)f * N + i] = gw[i] * 4.0 / (3.0 * as[i] * as[i]) * (3.0 / PI) * uw[f - 1] * 2.0 *
+                                       ab[(size_t)f * N + i];
+        }
+        double *x = (double *)malloc(sizeof(double) * nfreq), *wx = (double *)malloc(sizeof(double) * nfreq);
+        orc_gauss_legendre(nfreq, x, wx);
+        double *au = (double *)malloc(sizeof(double) * N);
+        double *D = (double *)malloc(sizeof(double) * (size_t)N * 9);   /* dA block (m, l) per l */
+        double *cs = (double *)malloc(sizeof(double) * (size_t)n * 3);  /* sum_j Abar_{k, ja} */
+        double *Z = (double *)malloc(sizeof(double) * (size_t)n * 3);
+        for (int f = 0; f <= nfreq; f++) {
+            double u = f == 0 ? 0.0 : 0.6 * (1.0 + x[f - 1]) / (1.0 - x[f - 1]);
+            for (int i = 0; i < N; i++) au[i] = alpha0[i] / (1.0 + u * u / (omega[i] * omega[i]));
+            const double *Ai = Ab + (size_t)f * n * n;
+            for (int k = 0; k < n; k++)
+                for (int aa = 0; aa < 3; aa++) {
+                    double t = 0.0;
+                    for (int j = 0; j < N; j++) t += Ai[(size_t)k * n + 3 * j + aa];
+                    cs[3 * k + aa] = t;
+                }
+            for (int m = 0; m < N; m++)
+                for (int c = 0; c < 3; c++) {
+                    /* dA/dR_mc is nonzero in blocks (m, l) = D_l and (l, m) = D_l^T,
+                     * with D_l = d/dR_mc (1 - g) T^GG (R_l - R_m) = -d/dr_c of it */
+                    for (int l = 0; l < N; l++) {
+                        double *Dl = D + 9 * l;
+                        memset(Dl, 0, 9 * sizeof(double));
+                        if (l == m) continue;
+                        double r[3] = {R[3 * l] - R[3 * m], R[3 * l + 1] - R[3 * m + 1], R[3 * l + 2] - R[3 * m + 2]};
+                        double d = norm3(r);
+                        double sm = mayer_sigma(au[m]), sl = mayer_sigma(au[l]);
+                        double T[9], dT[27], g, omg, gd, gR0;
+                        orc_dipole_gg(r, sqrt(sm * sm + sl * sl), T, dT);
+                        fermi(d, beta * (rvdw[m] + rvdw[l]), a, &g, &omg, &gd, &gR0);
+                        for (int k = 0; k < 9; k++) Dl[k] = -(-gd * r[c] / d * T[k] + omg * dT[c * 9 + k]);
+                    }
+                    /* (Abar dA Abar)_{ia,ja} summed over j: sum_k Abar_{ia,k} (dA cs)_{k,a};
+                     * (dA cs) has rows of block m: Y[p] = sum_l D_l[p][q] cs_{lq}, and rows
+                     * (l, q): Z = sum_p D_l[p][q] cs_{mp} */
+                    double Y[9] = {0};
+                    for (int l = 0; l < N; l++)
+                        for (int pp = 0; pp < 3; pp++)
+                            for (int q = 0; q < 3; q++)
+                                for (int aa = 0; aa < 3; aa++)
+                                    Y[pp * 3 + aa] += D[9 * l + pp * 3 + q] * cs[3 * (3 * l + q) + aa];
+                    for (int l = 0; l < N; l++)
+                        for (int q = 0; q < 3; q++)
+                            for (int aa = 0; aa < 3; aa++) {
+                                double t = 0.0;
+                                for (int pp = 0; pp < 3; pp++) t += D[9 * l + pp * 3 + q] * cs[3 * (3 * m + pp) + aa];
+                                Z[3 * (3 * l + q) + aa] = t;
+                            }
+                    double acc = 0.0;
+                    for (int i = 0; i < N; i++) {
+                        double wi = w[(size_t)f * N + i];
+                        if (wi == 0.0) continue;
+                        for (int aa = 0; aa < 3; aa++) {
+                            const double *ar = Ai + (size_t)(3 * i + aa) * n;
+                            double sacc = 0.0;
+                            for (int pp = 0; pp < 3; pp++) sacc += ar[3 * m + pp] * Y[pp * 3 + aa];
+                            for (int k = 0; k < n; k++) sacc += ar[k] * Z[3 * k + aa];
+                            acc += wi * (-sacc / 3.0);
+                        }
+                    }
+                    gR[3 * m + c] += acc;
+                }
+        }
+        free(x); free(wx); free(au); free(D); free(cs); free(Z); free(w);
+    }
+    if (grad_R && !rc) memcpy(grad_R, gR, sizeof(double) * 3 * N);
+    if (alpha_scs && !rc) memcpy(alpha_scs, as, sizeof(double) * N);
+    if (omega_scs && !rc) memcpy(omega_scs, ws, sizeof(double) * N);
+    if (rvdw_scs && !rc) memcpy(rvdw_scs, rs, sizeof(double) * N);
+    if (rc && energy) *energy = NAN;
+    free(as); free(ws); free(rs); free(c6); free(ab); free(uw); free(Ab);
+    free(gR); free(ga); free(gw); free(gv);
+    return rc;
+}

@@ -125,6 +125,32 @@ int orc_mbd_freq_terms(int N, const double *R, const double *lattice, int nq,
                        const double *rvdw, double beta, double a, int nfreq,
                        int norder, double *terms);
 
+/* Gaussian-smeared dipole tensor T^GG of eq:tgg (explicit-T sign convention)
+ * for r and s = sqrt(sigma_i^2 + sigma_j^2); dT[c][a][b] = d/dr_c (may be NULL). */
+void orc_dipole_gg(const double *r, double s, double *T, double *dT);
+
+/* Self-consistent screening of Sec. 2.3 (finite systems): at u = 0 and at
+ * nfreq Gauss-Legendre points (map of Sec. 3.3), alpha_bar(u) = (alpha(iu)^-1
+ * + T^scs)^-1 (eq:scs, eq:dyn-pol), T^scs = (1 - g) T^GG with Mayer widths
+ * (eq:scs-sr-dipole, eq:tgg, eq:mayer; g with steepness a and s_R = beta on
+ * the unscaled R_vdW), contracted per atom (eq:contraction).  Outputs [N]
+ * (each may be NULL): alpha_scs = alpha_bar(0), c6_scs by eq:casimir-polder,
+ * omega_scs = 4 C6/(3 alpha_scs^2), rvdw_scs = R_vdW (alpha_scs/alpha0)^{1/3}
+ * (eq:scale-rvdw-scs); alpha_dyn [(nfreq+1) x N], row 0 at u = 0.
+ * Returns 2 if some alpha(iu)^-1 + T^scs is not positive definite. */
+int orc_scs(int N, const double *R, const double *alpha0, const double *omega,
+            const double *rvdw, double beta, double a, int nfreq,
+            double *alpha_scs, double *c6_scs, double *omega_scs, double *rvdw_scs,
+            double *alpha_dyn);
+
+/* MBD@rsSCS energy (SCS stage, then the MBD energy with the screened alpha0,
+ * omega, R_vdW and T^lr = g T) and dE/dR [N][3] through the chain rule of the
+ * screened parameters (may be NULL); screened parameters out (may be NULL). */
+int orc_mbd_rsscs(int N, const double *R, const double *alpha0, const double *omega,
+                  const double *rvdw, double beta, double a, int nfreq,
+                  double *energy, double *grad_R, double *alpha_scs, double *omega_scs,
+                  double *rvdw_scs);
+
 /* Smallest eigenvalue of alpha0^{1/2} T^lr alpha0^{1/2} (finite). */
 int orc_min_coupling_eig(int N, const double *R, const double *alpha0,
                          const double *rvdw, double beta, double a,

@@ -614,3 +614,90 @@ def test_freq_terms_collapse_gould_finite():
     t2 = oracle.freq_terms(coords, [12.0, 12.0], [0.5, 0.5], [1.0, 1.0], beta=0.0, nfreq=40, norder=2)
     assert t2["min_one_plus_x"] > 0.0
     assert abs(t2["energy_gould"] - t2["energy"]) < 0.05 * abs(t2["energy"])
+
+
+# --------------------------------------------------------------------------
+# self-consistent screening: eq:tgg, eq:mayer, eq:scs, eq:contraction,
+# eq:casimir-polder, eq:scale-rvdw-scs
+# --------------------------------------------------------------------------
+
+def _hess(f, r, h=1e-4):
+    return _num_hessian(f, np.asarray(r, float), h)
+
+
+def test_tgg_is_minus_hessian_of_erf_over_r():
+    """T^GG = -Hess(erf(r/s)/r) in the sign convention of the explicit dipole
+    tensor (reading of eq:dipole), its r-derivative matches finite
+    differences, and T^GG -> T when the widths vanish."""
+    from scipy.special import erf
+    r = np.array([1.3, -0.7, 2.1])
+    s = 1.6
+    T, dT = oracle.dipole_gg(r, s)
+    H = _hess(lambda x: erf(np.linalg.norm(x) / s) / np.linalg.norm(x), r)
+    np.testing.assert_allclose(T, -H, atol=2e-7)
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = 1e-5
+        fd = (oracle.dipole_gg(r + e, s)[0] - oracle.dipole_gg(r - e, s)[0]) / 2e-5
+        np.testing.assert_allclose(dT[c], fd, atol=1e-8)
+    T0, _ = oracle.dipole(r)
+    np.testing.assert_allclose(oracle.dipole_gg(r, 1e-3)[0], T0, atol=1e-13)
+
+
+def test_scs_isolated_atom_and_far_apart():
+    """One atom: alpha_bar = alpha, so the screened alpha0 is alpha0 and the
+    Casimir-Polder C6 is (3/pi) int alpha(iu)^2 du = (3/4) alpha0^2 omega,
+    giving back omega.  Atoms far beyond the damping radius: T^scs = (1-g) T^GG
+    vanishes and nothing is screened."""
+    o = oracle.scs(np.zeros((1, 3)), [12.0], [0.45], [3.5], nfreq=40)
+    assert abs(o["alpha"][0] - 12.0) < 1e-13
+    assert abs(o["c6"][0] - 0.75 * 12.0 ** 2 * 0.45) < 1e-11
+    assert abs(o["omega"][0] - 0.45) < 1e-12 and abs(o["rvdw"][0] - 3.5) < 1e-14
+    R = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 60.0], [0.0, 60.0, 0.0]])
+    o = oracle.scs(R, [12.0, 20.0, 8.0], [0.45, 0.6, 0.5], [3.5, 3.9, 3.0], nfreq=40)
+    np.testing.assert_allclose(o["alpha"], [12.0, 20.0, 8.0], rtol=1e-14)
+    np.testing.assert_allclose(o["omega"], [0.45, 0.6, 0.5], rtol=1e-12)
+
+
+def test_scs_dimer_closed_form():
+    """A dimer along z: alpha^-1 + T^scs splits into three 2x2 blocks (x, y, z)
+    with off-diagonal p_a = (1-g) T^GG_aa; inverting each block and contracting
+    gives alpha_bar_1 = (1/3) sum_a (1/alpha_2 - p_a) / (1/(alpha_1 alpha_2) -
+    p_a^2) at u = 0."""
+    R0 = 4.0
+    a1, a2, rv = 12.0, 20.0, (3.5, 3.9)
+    o = oracle.scs(np.array([[0.0, 0.0, 0.0], [0.0, 0.0, R0]]), [a1, a2], [0.45, 0.6], list(rv), nfreq=15)
+    sig = lambda a: (np.sqrt(2 / np.pi) * a / 3) ** (1 / 3)
+    T, _ = oracle.dipole_gg(np.array([0.0, 0.0, R0]), np.hypot(sig(a1), sig(a2)))
+    omg = 1.0 - _fermi(R0, 0.83 * (rv[0] + rv[1]))
+    p = omg * np.diag(T)
+    ab1 = np.mean([(1 / a2 - pa) / (1 / (a1 * a2) - pa * pa) for pa in p])
+    ab2 = np.mean([(1 / a1 - pa) / (1 / (a1 * a2) - pa * pa) for pa in p])
+    assert abs(o["alpha"][0] - ab1) < 1e-12 * ab1
+    assert abs(o["alpha"][1] - ab2) < 1e-12 * ab2
+    assert abs(o["rvdw"][0] - rv[0] * (ab1 / a1) ** (1 / 3)) < 1e-13
+
+
+def test_mbd_rsscs_gradient_fd():
+    """dE/dR of MBD@rsSCS (through the screened alpha0, omega and R_vdW, i.e.
+    the derivative of eq:scs contracted as in eq:contraction) against central
+    differences of the energy, Richardson-extrapolated; translation
+    invariance."""
+    coords, a0, om, rv = _cluster(12, 5)
+    out = oracle.mbd_rsscs(coords, a0, om, rv)
+
+    def E(x):
+        return oracle.mbd_rsscs(x, a0, om, rv, gradients=False)["energy"]
+
+    for idx in [(0, 0), (1, 2), (3, 1), (4, 0)]:
+        # steps large enough that the energy's rounding (~1e-15 Ha) stays out
+        f1, f2 = _fd(E, coords, idx, 1e-3), _fd(E, coords, idx, 2e-3)
+        np.testing.assert_allclose(out["grad_R"][idx], (4 * f1 - f2) / 3, rtol=1e-7, atol=1e-12)
+    assert abs(out["grad_R"].sum(axis=0)).max() < 1e-14
+
+
+def test_mbd_rsscs_is_mbd_of_screened_parameters():
+    coords, a0, om, rv = _cluster(16, 6)
+    out = oracle.mbd_rsscs(coords, a0, om, rv, gradients=False)
+    ref = oracle.mbd_finite(coords, out["alpha_scs"], out["omega_scs"], out["rvdw_scs"], gradients=False)
+    assert abs(out["energy"] - ref["energy"]) < 1e-15
