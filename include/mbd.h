@@ -213,6 +213,25 @@ mbd_status mbd_ts_evaluate(mbd_ctx *ctx, const mbd_system *sys, unsigned want, m
  * of mbd_result are not used. */
 mbd_status mbd_freq_evaluate(mbd_ctx *ctx, const mbd_system *sys, int32_t n_freq, int32_t n_order, double *terms);
 
+/* MBD@rsSCS (Secs. 2.3 and 2.7), finite systems: the self-consistent
+ * screening stage followed by the MBD energy with the screened parameters.
+ * At u = 0 and at n_freq Gauss-Legendre points (map of Sec. 3.3; the paper's
+ * default is 15), alpha_bar(u) = (alpha(iu)^-1 + T^scs)^-1 (eq:scs) with
+ * T^scs = (1 - g) T^GG (eq:scs-sr-dipole, eq:tgg, Mayer widths eq:mayer; g
+ * with steepness sys->a and s_R = sys->beta on the input R_vdW), contracted
+ * per atom (eq:contraction); C6 by eq:casimir-polder, omega = 4 C6/(3
+ * alpha_bar0^2), R_vdW scaled by (alpha_bar0/alpha0)^{1/3}
+ * (eq:scale-rvdw-scs).  The MBD energy (T^lr = g T with the scaled radii,
+ * eq:mbd-lr-dipole) runs at the context's precision; the screening stage is
+ * always FP64.  want: MBD_WANT_ENERGY, _GRAD_COORDS (dE/dR through the
+ * screened parameters: the derivative of eq:scs contracted as in
+ * eq:contraction), _EIGVALS, _ERRORS; other bits give MBD_ERR_UNSUPPORTED,
+ * as does a lattice.  scs_params (DEVICE, may be NULL): [4][N] screened
+ * alpha0, C6, omega, R_vdW.  A non-positive-definite alpha(iu)^-1 + T^scs
+ * gives MBD_ERR_NEGATIVE_EIGENVALUE. */
+mbd_status mbd_rsscs_evaluate(mbd_ctx *ctx, const mbd_system *sys, int32_t n_freq, unsigned want, mbd_result *out,
+                              double *scs_params);
+
 /* Dense symmetric eigensolver of the MBD path, exposed for testing and reuse:
  * the Householder reduction, divide-and-conquer tridiagonal solve and
  * back-transform used for Q.  A: [nbatch] matrices of order n, column-major

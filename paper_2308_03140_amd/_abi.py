@@ -85,6 +85,8 @@ def lib():
         L.mbd_evaluate_noalloc.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_uint, ctypes.POINTER(MbdResult)]
         L.mbd_ts_evaluate.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_uint, ctypes.POINTER(MbdResult)]
         L.mbd_freq_evaluate.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_int32, ctypes.c_int32, _P]
+        L.mbd_rsscs_evaluate.argtypes = [_P, ctypes.POINTER(MbdSystem), ctypes.c_int32, ctypes.c_uint,
+                                         ctypes.POINTER(MbdResult), _P]
         L.mbd_evaluate_batch.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(MbdSystem), ctypes.c_uint,
                                          ctypes.POINTER(MbdResult), ctypes.POINTER(ctypes.c_int32)]
         L.mbd_eigh.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
@@ -96,7 +98,7 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         L.mbd_last_error.argtypes = [_P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_char_p)]
         for f in ("mbd_create", "mbd_destroy", "mbd_set_stream", "mbd_evaluate", "mbd_evaluate_noalloc", "mbd_ts_evaluate",
-                  "mbd_freq_evaluate",
+                  "mbd_freq_evaluate", "mbd_rsscs_evaluate",
                   "mbd_evaluate_batch",
                   "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error", "mbd_set_profiling",
                   "mbd_get_profile"):
@@ -134,6 +136,11 @@ def mbd_ts_evaluate(ctx, system, want, result):
 
 def mbd_freq_evaluate(ctx, system, n_freq, n_order, terms):
     return lib().mbd_freq_evaluate(ctx, ctypes.byref(system), int(n_freq), int(n_order), _P(terms))
+
+
+def mbd_rsscs_evaluate(ctx, system, n_freq, want, result, scs_params):
+    return lib().mbd_rsscs_evaluate(ctx, ctypes.byref(system), int(n_freq), ctypes.c_uint(want),
+                                    ctypes.byref(result), _P(scs_params) if scs_params else None)
 
 
 def mbd_evaluate_batch(ctx, systems, want, results, status):

@@ -950,6 +950,111 @@ mbd_status mbd_freq_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, in
     return code_message(c, status_code(all & (MBD_ST_BAD_INPUT | MBD_ST_COINCIDENT)), "mbd_freq_evaluate");
 }
 
+mbd_status mbd_rsscs_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, unsigned want, mbd_result* out,
+                              double* scs_params) {
+    if (!c) return MBD_ERR_INVALID_ARGUMENT;
+    c->err_code = 0;
+    const unsigned allowed = MBD_WANT_ENERGY | MBD_WANT_GRAD_COORDS | MBD_WANT_EIGVALS | MBD_WANT_ERRORS;
+    if (want & ~allowed)
+        return fail(c, MBD_ERR_UNSUPPORTED, "mbd_rsscs_evaluate", "energy, dE/dR, eigenvalues and errors only");
+    if (n_freq < 1 || n_freq > 512) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_rsscs_evaluate", "1 <= n_freq <= 512");
+    mbd_status r = check_system(c, s, want, out, true);
+    if (r != MBD_OK) return r;
+    if (s->lattice) return fail(c, MBD_ERR_UNSUPPORTED, "mbd_rsscs_evaluate", "finite systems only");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_rsscs_evaluate", "hipSetDevice");
+    const hipStream_t st = c->stream;
+    const int N = s->n_atoms, n = 3 * N, nf = n_freq + 1;
+    const int ld = round_up(n, 64);
+    const long long stride = (long long)ld * n;
+    mbd_result none;
+    std::memset(&none, 0, sizeof(none));
+    SysDesc base = make_desc(s, 0u, &none);
+    // u = 0, then the Gauss-Legendre points; wq = (3/pi) du (Casimir-Polder)
+    std::vector<double> gx, gw, u(nf, 0.0), wq(nf, 0.0);
+    gauss_legendre_nodes(n_freq, gx, gw);
+    const double pi = 3.14159265358979323846;
+    for (int f = 1; f < nf; f++) {
+        u[f] = 0.6 * (1.0 + gx[f - 1]) / (1.0 - gx[f - 1]);
+        wq[f] = 3.0 / pi * 1.2 / ((1.0 - gx[f - 1]) * (1.0 - gx[f - 1])) * gw[f - 1];
+    }
+    std::vector<int> nsh(nf, n);
+    SysDesc* sd_dev = (SysDesc*)ws(c, "scs_desc", sizeof(SysDesc));
+    unsigned* status = wsT<unsigned>(c, "scs_status", 1);
+    int* ns_dev = wsT<int>(c, "scs_ns", nf);
+    double* om0 = wsT<double>(c, "scs_om", N);
+    double* cc0 = wsT<double>(c, "scs_cc", N);
+    double* u_dev = wsT<double>(c, "scs_u", nf);
+    double* wq_dev = wsT<double>(c, "scs_wq", nf);
+    double* lam = wsT<double>(c, "scs_lam", (size_t)n * nf);
+    double* sc = wsT<double>(c, "scs_sc", (size_t)n * nf);
+    double* abar = wsT<double>(c, "scs_abar", (size_t)nf * N);
+    double* par = wsT<double>(c, "scs_par", (size_t)4 * N);
+    MatBatch<double> A = {wsT<double>(c, "scsA", (size_t)stride * nf), ld, stride};
+    if (!sd_dev || !status || !ns_dev || !om0 || !cc0 || !u_dev || !wq_dev || !lam || !sc || !abar || !par || !A.p)
+        return (mbd_status)c->err_code;
+    HIPCHK(hipMemcpyAsync(sd_dev, &base, sizeof(SysDesc), hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(hipMemcpyAsync(u_dev, u.data(), sizeof(double) * nf, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(hipMemcpyAsync(wq_dev, wq.data(), sizeof(double) * nf, hipMemcpyHostToDevice, st), "upload");
+    fill_u32_launch(st, status, 1, 0u);
+    mbd_prep_launch(st, sd_dev, 1, N, om0, cc0, status);
+    // screening: A(u) for all u in one batch, its inverse from the eigenpairs
+    scs_assemble_launch(st, sd_dev, N, om0, u_dev, nf, A, status);
+    HIPCHK(hipGetLastError(), "scs assemble");
+    MatBatch<double> X;
+    r = run_eig<double>(c, A, ns_dev, nsh.data(), n, nf, true, lam, n, &X);
+    if (r != MBD_OK) return r;
+    scs_invhalf_launch(st, ns_dev, n, nf, lam, n, sc, status);
+    mbd_inv_sqrt_launch(st, ns_dev, n, nf, X, sc, n, A);  // A <- X diag(1/lambda) X^T (lower)
+    mbd_mirror_launch(st, ns_dev, n, nf, A);
+    scs_contract_launch(st, A, N, nf, abar);
+    scs_params_launch(st, sd_dev, N, abar, wq_dev, nf, par);
+    if (scs_params) HIPCHK(hipMemcpyAsync(scs_params, par, sizeof(double) * 4 * N, hipMemcpyDeviceToDevice, st), "copy");
+    HIPCHK(hipGetLastError(), "scs");
+    unsigned sth = 0;
+    HIPCHK(hipMemcpyAsync(&sth, status, sizeof(unsigned), hipMemcpyDeviceToHost, st), "status");
+    HIPCHK(hipStreamSynchronize(st), "synchronize");
+    if (sth & (MBD_ST_BAD_INPUT | MBD_ST_COINCIDENT)) return code_message(c, MBD_ERR_INVALID_ARGUMENT, "mbd_rsscs_evaluate");
+    if (sth & MBD_ST_COLLAPSE)
+        return fail(c, MBD_ERR_NEGATIVE_EIGENVALUE, "mbd_rsscs_evaluate",
+                    "alpha(iu)^-1 + T^scs is not positive definite (the screening collapses)");
+    // MBD with the screened alpha0, omega and R_vdW
+    mbd_system ss = *s;
+    ss.alpha0 = par;
+    ss.omega_or_c6 = par + 2 * N;
+    ss.param_kind = MBD_PARAM_OMEGA;
+    ss.rvdw = par + 3 * N;
+    const bool grads = (want & MBD_WANT_GRAD_COORDS) != 0;
+    mbd_result rs = *out;
+    unsigned w2 = want;
+    double* gpar = nullptr;
+    if (grads) {
+        gpar = wsT<double>(c, "scs_gpar", (size_t)3 * N);
+        if (!gpar) return (mbd_status)c->err_code;
+        rs.grad_alpha0 = gpar;
+        rs.grad_omega_or_c6 = gpar + N;
+        rs.grad_rvdw = gpar + 2 * N;
+        w2 |= MBD_WANT_GRAD_ALPHA0 | MBD_WANT_GRAD_OMEGA | MBD_WANT_GRAD_RVDW;
+    }
+    std::vector<SysDesc> sds(1, make_desc(&ss, w2, &rs));
+    std::vector<int> codes;
+    r = run_core(c, sds, w2, codes, nullptr);
+    if (r == MBD_OK) r = refine_fallback(c, sds, w2, codes, nullptr);
+    if (r != MBD_OK) return r;
+    if (codes[0] != MBD_OK) return code_message(c, codes[0], "mbd_rsscs_evaluate");
+    if (grads) {
+        // chain rule through the screened parameters
+        double* w = wsT<double>(c, "scs_w", (size_t)nf * N);
+        double* UV = wsT<double>(c, "scs_uv", (size_t)nf * n * 6);
+        if (!w || !UV) return (mbd_status)c->err_code;
+        scs_grad_launch(st, sd_dev, N, nf, om0, u_dev, par, abar, wq_dev, gpar, gpar + N, gpar + 2 * N, w, A, UV,
+                        out->grad_coords);
+        HIPCHK(hipGetLastError(), "scs gradient");
+        HIPCHK(hipStreamSynchronize(st), "synchronize");
+    }
+    return MBD_OK;
+}
+
 mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, unsigned want, mbd_result* out,
                               int32_t* status) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;

@@ -94,3 +94,15 @@ void mbd_freq_coeff_launch(hipStream_t st, const SysDesc* sd, const double* om0,
                            double* om_f, double* cc_f);
 void mbd_freq_terms_launch(hipStream_t st, const int* ns, int nmat, const double* lam, long long sL, int norder,
                            double* part, const double* wf, int nfreq, int nq, int embed, double* terms);
+
+// self-consistent screening (see k_scs.hip)
+void scs_assemble_launch(hipStream_t st, const SysDesc* sd, int N, const double* om, const double* u, int nf,
+                         MatBatch<double> A, unsigned* status);
+void scs_invhalf_launch(hipStream_t st, const int* ns, int nmax, int nf, const double* lam, long long sL, double* sc,
+                        unsigned* status);
+void scs_contract_launch(hipStream_t st, MatBatch<double> M, int N, int nf, double* abar);
+void scs_params_launch(hipStream_t st, const SysDesc* sd, int N, const double* abar, const double* wq, int nf,
+                       double* out);
+void scs_grad_launch(hipStream_t st, const SysDesc* sd, int N, int nf, const double* om, const double* u,
+                     const double* par, const double* abar, const double* wq, const double* ga, const double* gw,
+                     const double* gv, double* w, MatBatch<double> M, double* UV, double* grad);

@@ -204,6 +204,33 @@ def freq_evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=No
     return {"energy": t[0], "energy_gould": t[1], "min_one_plus_x": t[2], "orders": t[3:]}
 
 
+def rsscs_evaluate(ctx, coords, alpha0, omega, rvdw, beta=0.83, a=6.0, n_freq=15, param="omega", gradients=True,
+                   errors=True):
+    """MBD@rsSCS energy (and dE/dR) of a finite system (mbd_rsscs_evaluate);
+    also returns the screened parameters (alpha0, C6, omega, R_vdW)."""
+    ctx.sync_stream()
+    dev = ctx.device
+    s, keep = make_system(coords, alpha0, omega, rvdw, beta, a, param=param, device=dev)
+    N = s.n_atoms
+    out = {"energy": torch.empty(1, dtype=torch.float64, device=dev),
+           "scs": torch.empty(4, N, dtype=torch.float64, device=dev)}
+    r = A.MbdResult()
+    r.energy = out["energy"].data_ptr()
+    want = A.MBD_WANT_ENERGY
+    if gradients:
+        out["grad_coords"] = torch.empty(N, 3, dtype=torch.float64, device=dev)
+        r.grad_coords = out["grad_coords"].data_ptr()
+        want |= A.MBD_WANT_GRAD_COORDS
+    if errors:
+        out["errors"] = torch.zeros(4, dtype=torch.float64, device=dev)
+        r.errors = out["errors"].data_ptr()
+        want |= A.MBD_WANT_ERRORS
+    code = A.mbd_rsscs_evaluate(ctx.handle, s, n_freq, want, r, out["scs"].data_ptr())
+    if code != A.MBD_OK:
+        _raise(ctx, code)
+    return out
+
+
 def evaluate_batch(ctx, systems, gradients=True, errors=True):
     """systems: list of dicts with coords, alpha0, omega, rvdw (, beta, a).  Finite only."""
     ctx.sync_stream()
