@@ -17,9 +17,10 @@ Secondary legs, reported in the same JSON line:
   ts        pairwise (TS) energy + gradients: N=2000 cluster and the 64-atom
             crystal (Ewald), errors against the oracle
   freq      frequency route on the 64-atom crystal (15 frequencies x 64 q)
+  rsscs     MBD@rsSCS on the N=2000 cluster (screening + MBD energy/forces)
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--legs c2,batch,periodic,ts,freq] [--tuning-dir DIR]
+                    [--legs c2,batch,periodic,ts,freq,rsscs] [--tuning-dir DIR]
 """
 import argparse
 import hashlib
@@ -180,14 +181,18 @@ PHASES = {2: "assembly", 3: "reduction", 4: "divide_and_conquer", 5: "back_trans
           7: "energy_and_gradients"}
 
 
-def phase_rooflines(prof, n, fp32):
-    """Per-phase event time of one profiled evaluation against the time the
-    phase's algorithmic work takes at the MI355X peaks (HBM 8 TB/s; FP32 and
-    FP64 matrix cores 157.3 and 78.6 TFLOP/s): assembly writes Q (8 n^2 B, and
+def phase_rooflines(prof, n, fp32, eval_s):
+    """Per-phase time of one profiled evaluation against the time the phase's
+    algorithmic work takes at the MI355X peaks (HBM 8 TB/s; FP32 and FP64
+    matrix cores 157.3 and 78.6 TFLOP/s): assembly writes Q (8 n^2 B, and
     4 n^2 B for the FP32 copy); the reduction reads the lower trailing triangle
     once per column (n^3/6 elements) and does (2/3) n^3 rank-2k flops; divide
     and conquer at most (4/3) n^3 merge flops; the back-transform 2 n^3; one
-    refinement step 6 n^3 FP64; Q^{-1/2} n^3 FP64 plus one pass over it."""
+    refinement step 6 n^3 FP64; Q^{-1/2} n^3 FP64 plus one pass over it.
+    The phases are timed with the stream synchronised at their boundaries.
+    The reduction (11 700 launches) then runs from an idle queue and takes
+    longer than inside an unsynchronised evaluation, so it is also given as
+    the evaluation time minus the other phases ("in_evaluation")."""
     es = 4 if fp32 else 8
     peak = FP32_PEAK_TFS if fp32 else FP64_PEAK_TFS
     tmin = {2: (8 + (4 if fp32 else 0)) * n * n / (HBM_PEAK_GBS * 1e9),
@@ -206,6 +211,11 @@ def phase_rooflines(prof, n, fp32):
         tot_ms += ms
         tot_min += t
     out["sum"] = {"ms": tot_ms, "t_min_ms": tot_min, "frac": tot_min / tot_ms if tot_ms > 0 else None}
+    if "reduction" in out:
+        red = eval_s * 1e3 - sum(v["ms"] for k, v in out.items() if k not in ("reduction", "sum"))
+        out["reduction"]["ms_in_evaluation"] = red
+        out["reduction"]["frac_in_evaluation"] = out["reduction"]["t_min_ms"] / red if red > 0 else None
+    out["evaluation"] = {"ms": eval_s * 1e3, "t_min_ms": tot_min, "frac": tot_min / (eval_s * 1e3)}
     return out
 
 
@@ -374,6 +384,37 @@ def leg_freq(args, torch, T, A):
             "orders": [float(x) for x in o["orders"].cpu().numpy()],
             "phases_ms": {"reduction": ph[3], "eigenvalues": ph[4]},
             "reduction_t_min_ms": nm * n ** 3 / 6 * 8 / (HBM_PEAK_GBS * 1e9) * 1e3}
+
+
+def leg_rsscs(args, torch, T, A):
+    """MBD@rsSCS on the N=2000 cluster: the screening stage (16 FP64
+    eigendecompositions of order 6000: u = 0 and 15 frequencies) and the MBD
+    energy + forces (FP32+refine) with the screened parameters; phase times."""
+    import gen
+    dev = torch.device("cuda", 0)
+    c = gen.cluster_n2000()
+    ctx = T.Context(0, "fp32_refined")
+    coords = torch.tensor(c["coords"], device=dev)
+
+    def step():
+        return T.rsscs_evaluate(ctx, coords, c["alpha0"], c["omega"], c["rvdw"], beta=c["beta"], a=c["a"],
+                                n_freq=15)
+
+    steps = max(1, args.steps // 2)
+    log("[bench] rsscs warmup x1, timed x%d" % steps)
+    dt, o = timed(step, steps, 1, torch)
+    A.mbd_set_profiling(ctx.handle, 2)
+    step()
+    ph = {PHASES[k]: A.mbd_get_profile(ctx.handle, k)[1] for k in range(2, 8)}
+    A.mbd_set_profiling(ctx.handle, 0)
+    ctx.close()
+    n = 6000
+    return {"workload": "N=2000 cluster, 15 frequencies + u = 0 (16 FP64 eigendecompositions of order 6000), "
+                        "then MBD energy + forces FP32+refine",
+            "s_per_eval": dt, "energy": o["energy"].item(),
+            "phases_ms_summed_over_both_stages": ph,
+            "screening_t_min_ms": 16 * (n ** 3 / 6 * 8 / (HBM_PEAK_GBS * 1e9) + (2.0 / 3.0 + 4.0 / 3.0 + 2.0 + 1.0)
+                                        * n ** 3 / (FP64_PEAK_TFS * 1e12)) * 1e3}
 
 
 def pmc_pass(torch, T):
@@ -583,7 +624,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="c2,batch,periodic,ts,freq")
+    ap.add_argument("--legs", default="c2,batch,periodic,ts,freq,rsscs")
     ap.add_argument("--tuning-dir", default=None, help="write the autotuner tables (JSON) here")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write the SYMV HBM-traffic file under profiles/ from two --pmc-pass counter runs")
@@ -670,8 +711,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launches": nl, "avg_launch_us": avg_s * 1e6,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
-        "phase_rooflines": {"fp32_refined": phase_rooflines(r["fp32_refined"]["prof"], 3 * N, True),
-                            "fp64": phase_rooflines(r["fp64"]["prof"], 3 * N, False)},
+        "phase_rooflines": {"fp32_refined": phase_rooflines(r["fp32_refined"]["prof"], 3 * N, True,
+                                                            r["fp32_refined"]["s"]),
+                            "fp64": phase_rooflines(r["fp64"]["prof"], 3 * N, False, r["fp64"]["s"])},
         "phases": {
             "fp32_symv_GBs": achieved, "fp32_symv_total_ms": ms,
             "fp32_syr2k_TFs": fl3 / (ms3 * 1e-3) / 1e12 if ms3 > 0 else None, "fp32_syr2k_total_ms": ms3,
@@ -688,6 +730,8 @@ def main():
         line["ts"] = leg_ts(args, torch, T)
     if "freq" in legs:
         line["freq"] = leg_freq(args, torch, T, A)
+    if "rsscs" in legs:
+        line["rsscs"] = leg_rsscs(args, torch, T, A)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline()
