@@ -36,7 +36,14 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 SYMV_SOURCE = os.path.join(ROOT, "paper_2308_03140_amd", "csrc", "k_sytrd.hip")
-SYMV_PMC = os.path.join(ROOT, "profiles", "sytrd_symv_fp32_n6000_pmc.txt")
+# The per-column launches of the FP32 reduction: a SYMV launch (plus a finish
+# launch) per column while the trailing order exceeds FUSED_MAX_ORDER, one
+# fused launch per column below it.  Profiling kind, kernel, counter file.
+COLUMN_KERNELS = {
+    0: ("sytrd_symv_kernel<float", os.path.join(ROOT, "profiles", "sytrd_symv_fp32_n6000_pmc.txt")),
+    8: ("sytrd_col_kernel<float", os.path.join(ROOT, "profiles", "sytrd_col_fp32_n6000_pmc.txt")),
+}
+FUSED_MAX_ORDER = 4000
 
 
 def log(*a):
@@ -98,14 +105,16 @@ def cpu_baseline(sizes=(500, 700), n_full=2000):
                       "extrapolated with it to one N=%d evaluation" % (a, b, t[a], t[b], p, b, n_full)}
 
 
-def symv_traffic():
-    """HBM bytes per SYMV launch from the committed rocprofv3 counter runs
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when the kernel source has changed since the counters were taken."""
-    if not os.path.exists(SYMV_PMC):
+def column_traffic(kind):
+    """HBM bytes per launch of one per-column kernel from the committed
+    rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when the kernel source has changed since the
+    counters were taken."""
+    path = COLUMN_KERNELS[kind][1]
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(SYMV_PMC) as f:
+    with open(path) as f:
         for line in f:
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
@@ -165,7 +174,7 @@ def leg_c2(args, torch, T, A):
             prof[kind] = (ms, nl, work)
         A.mbd_set_profiling(ctx.handle, 1)
         step()
-        for kind in (0, 1):
+        for kind in (0, 1, 8):
             st, ms, nl, work = A.mbd_get_profile(ctx.handle, kind)
             prof[kind] = (ms, nl, work)
         A.mbd_set_profiling(ctx.handle, 0)
@@ -388,8 +397,9 @@ def leg_freq(args, torch, T, A):
 
 def leg_rsscs(args, torch, T, A):
     """MBD@rsSCS on the N=2000 cluster: the screening stage (16 FP64
-    eigendecompositions of order 6000: u = 0 and 15 frequencies) and the MBD
-    energy + forces (FP32+refine) with the screened parameters; phase times."""
+    Cholesky factorisations of order 6000, u = 0 and 15 frequencies, and
+    three-column solves) and the MBD energy + forces (FP32+refine) with the
+    screened parameters; phase times (screening: profiling kind 9)."""
     import gen
     dev = torch.device("cuda", 0)
     c = gen.cluster_n2000()
@@ -406,15 +416,18 @@ def leg_rsscs(args, torch, T, A):
     A.mbd_set_profiling(ctx.handle, 2)
     step()
     ph = {PHASES[k]: A.mbd_get_profile(ctx.handle, k)[1] for k in range(2, 8)}
+    scr = A.mbd_get_profile(ctx.handle, 9)[1]
     A.mbd_set_profiling(ctx.handle, 0)
     ctx.close()
     n = 6000
-    return {"workload": "N=2000 cluster, 15 frequencies + u = 0 (16 FP64 eigendecompositions of order 6000), "
-                        "then MBD energy + forces FP32+refine",
+    # screening bound: the 16 factorisations' n^3/3 flops at the FP64 matrix
+    # peak and one write and read of the 16 matrices at the HBM peak
+    t_min = (16 * n ** 3 / 3 / (FP64_PEAK_TFS * 1e12) + 2 * 16 * n * n * 8 / (HBM_PEAK_GBS * 1e9)) * 1e3
+    return {"workload": "N=2000 cluster, 15 frequencies + u = 0 (16 FP64 Cholesky factorisations of order 6000 "
+                        "and three-column solves), then MBD energy + forces FP32+refine",
             "s_per_eval": dt, "energy": o["energy"].item(),
-            "phases_ms_summed_over_both_stages": ph,
-            "screening_t_min_ms": 16 * (n ** 3 / 6 * 8 / (HBM_PEAK_GBS * 1e9) + (2.0 / 3.0 + 4.0 / 3.0 + 2.0 + 1.0)
-                                        * n ** 3 / (FP64_PEAK_TFS * 1e12)) * 1e3}
+            "screening_ms": scr, "screening_t_min_ms": t_min, "screening_frac": t_min / scr if scr > 0 else None,
+            "mbd_stage_phases_ms": ph}
 
 
 def pmc_pass(torch, T):
@@ -442,11 +455,19 @@ def pmc_pass(torch, T):
     ctx.close()
 
 
-def symv_launches(n, tail=256, panel=32):
-    """SYMV launches of one FP32 reduction of order n: one per column up to the
-    panel boundary where the last columns (at most `tail`) are reduced in LDS."""
+def column_launches(n, tail=256, panel=32, fused_max=FUSED_MAX_ORDER):
+    """Per-column launches of one FP32 reduction of a single matrix of order
+    n, as {profiling kind: count}: one per column up to the panel boundary
+    where the last columns (at most `tail`) are reduced in LDS; a panel
+    starting at column k0 runs fused launches (kind 8) when n - k0 - 1 <=
+    fused_max (and its work items are short, which holds for one matrix at
+    the default targets)."""
     start = 0 if n <= tail else -(-(n - tail) // panel) * panel
-    return min(n - 1, start)
+    start = min(n - 1, start)
+    out = {0: 0, 8: 0}
+    for k0 in range(0, start, panel):
+        out[8 if n - k0 - 1 <= fused_max else 0] += min(panel, start - k0)
+    return out
 
 
 def _pmc_dispatches(d):
@@ -472,44 +493,49 @@ def _pmc_dispatches(d):
 
 def pmc_summary(fetch_dir, write_dir):
     """Turns the FETCH_SIZE and WRITE_SIZE runs of --pmc-pass into the HBM bytes
-    per SYMV launch (profiles/sytrd_symv_fp32_n6000_pmc.txt): counters are in
-    KiB per dispatch; each is scaled by bytes/counter measured on the 1 GiB copy
-    of the same run."""
-    out = {}
-    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
-        disp = _pmc_dispatches(d)
-        symv = [v for k, v in disp if "sytrd_symv_kernel<float" in k]
-        want = symv_launches(6000)
-        if len(symv) != want:
-            raise SystemExit("%s: %d SYMV dispatches, expected the %d of one evaluation" % (name, len(symv), want))
-        copies = [v for k, v in disp if "copy" in k.lower()]
-        if not copies:
-            raise SystemExit("%s: no copy dispatch for the calibration" % name)
-        cal = float(1 << 30) / max(copies)  # bytes per counter unit on the 1 GiB copy
-        out[name] = (sum(symv) / len(symv), max(copies), cal)
+    per launch of each per-column kernel (the files named in COLUMN_KERNELS):
+    counters are in KiB per dispatch; each is scaled by bytes/counter measured
+    on the 1 GiB copy of the same run."""
     with open(SYMV_SOURCE, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    fetch, wr = out["FETCH_SIZE"], out["WRITE_SIZE"]
-    hbm = fetch[0] * fetch[2] + wr[0] * wr[2]
-    lines = [
-        "# rocprofv3 counters of sytrd_symv_kernel<float> at N=2000 (n=6000), FP32+refine path",
-        "# commands (repository root, MI355X):",
-        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- python3 bench.py --pmc-pass",
-        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- python3 bench.py --pmc-pass",
-        "#   python3 bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
-        "# averages over the %d SYMV dispatches of one evaluation; calibration on the 1 GiB copy" % symv_launches(6000),
-        "symv_fetch_counter_avg = %.3f" % fetch[0],
-        "symv_write_counter_avg = %.3f" % wr[0],
-        "copy_fetch_counter = %.3f" % fetch[1],
-        "copy_write_counter = %.3f" % wr[1],
-        "bytes_per_fetch_unit = %.6f" % fetch[2],
-        "bytes_per_write_unit = %.6f" % wr[2],
-        "hbm_bytes_per_launch = %.1f" % hbm,
-        "kernel_source_sha256_16 = %s" % sha,
-    ]
-    with open(SYMV_PMC, "w") as f:
-        f.write("\n".join(lines) + "\n")
-    print("\n".join(lines))
+    total = sum(column_launches(6000).values())
+    disp = {name: _pmc_dispatches(d) for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))}
+    for name, dl in disp.items():
+        got = sum(1 for k, _ in dl if any(kn in k for kn, _ in COLUMN_KERNELS.values()))
+        if got != total:
+            raise SystemExit("%s: %d per-column dispatches, expected the %d of one evaluation" % (name, got, total))
+    for kind, (kname, path) in COLUMN_KERNELS.items():
+        out = {}
+        for name, dl in disp.items():
+            vals = [v for k, v in dl if kname in k]
+            if not vals:
+                raise SystemExit("%s: no dispatch of %s" % (name, kname))
+            copies = [v for k, v in dl if "copy" in k.lower()]
+            if not copies:
+                raise SystemExit("%s: no copy dispatch for the calibration" % name)
+            cal = float(1 << 30) / max(copies)  # bytes per counter unit on the 1 GiB copy
+            out[name] = (sum(vals) / len(vals), max(copies), cal)
+        fetch, wr = out["FETCH_SIZE"], out["WRITE_SIZE"]
+        hbm = fetch[0] * fetch[2] + wr[0] * wr[2]
+        lines = [
+            "# rocprofv3 counters of %s> at N=2000 (n=6000), FP32+refine path" % kname,
+            "# commands (repository root, MI355X):",
+            "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- python3 bench.py --pmc-pass",
+            "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- python3 bench.py --pmc-pass",
+            "#   python3 bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
+            "# averages over the %d dispatches of one evaluation; calibration on the 1 GiB copy" % len(vals),
+            "fetch_counter_avg = %.3f" % fetch[0],
+            "write_counter_avg = %.3f" % wr[0],
+            "copy_fetch_counter = %.3f" % fetch[1],
+            "copy_write_counter = %.3f" % wr[1],
+            "bytes_per_fetch_unit = %.6f" % fetch[2],
+            "bytes_per_write_unit = %.6f" % wr[2],
+            "hbm_bytes_per_launch = %.1f" % hbm,
+            "kernel_source_sha256_16 = %s" % sha,
+        ]
+        with open(path, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
 
 
 MFMA_PMC = os.path.join(ROOT, "profiles", "gemm_mfma_fp32_n6000_mfma.md")
@@ -593,10 +619,12 @@ def mfma_summary(pmc_dir, trace_dir):
 
 
 def trace_summary(trace_dir, steps, warmup):
-    """Average duration of the FP32 SYMV kernel over the evaluations of a
-    `--legs c2` run traced by rocprofv3 --kernel-trace (its kernel_trace.csv
-    under trace_dir): the autotuner's candidate launches come first and are
-    left out."""
+    """Average duration of each FP32 per-column kernel over the evaluations of
+    a `--legs c2` run traced by rocprofv3 --kernel-trace (its kernel_trace.csv
+    under trace_dir).  Every FP32 reduction ends with one LDS tail launch, so
+    the trace is cut there: the per-column launches of the last warmup +
+    steps + 1 reductions (warm-up, timed, profiled) are kept and the
+    autotuner's candidate reductions before them left out."""
     import csv
     files = [os.path.join(r, f) for r, _, fs in os.walk(trace_dir) for f in fs if f.endswith("kernel_trace.csv")]
     if not files:
@@ -604,18 +632,36 @@ def trace_summary(trace_dir, steps, warmup):
     rows = []
     for fn in files:
         with open(fn) as f:
-            rows += [r for r in csv.DictReader(f) if r["Kernel_Name"].startswith("void sytrd_symv_kernel<float")]
-    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3 for r in rows]
-    per = symv_launches(6000)
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"]
+                if name.startswith("void sytrd_tail_kernel<float") or any(
+                        name.startswith("void " + k) for k, _ in COLUMN_KERNELS.values()):
+                    rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), name))
+    rows.sort()
+    segs, cur = [], []
+    for s0, e0, name in rows:
+        if name.startswith("void sytrd_tail_kernel"):
+            segs.append(cur)
+            cur = []
+        else:
+            cur.append((name, (e0 - s0) * 1e-3))
     n_eval = warmup + steps + 1  # warm-up, timed (captured graphs), one profiled eager evaluation
-    if len(dur) < n_eval * per:
-        raise SystemExit("%d SYMV launches, fewer than %d evaluations of %d" % (len(dur), n_eval, per))
-    ev, timed, prof = dur[-n_eval * per:], dur[-(steps + 1) * per:-per], dur[-per:]
-    print("all %d calls: %.2f us" % (len(dur), sum(dur) / len(dur)))
-    print("the %d launches of the %d evaluations: %.2f us" % (len(ev), n_eval, sum(ev) / len(ev)))
-    print("the %d launches of the %d timed (captured-graph) evaluations: %.2f us" % (len(timed), steps, sum(timed) / len(timed)))
-    print("the %d launches of the profiled evaluation: %.2f us" % (len(prof), sum(prof) / len(prof)))
+    if len(segs) < n_eval:
+        raise SystemExit("%d FP32 reductions in the trace, fewer than %d" % (len(segs), n_eval))
+    ev = segs[-n_eval:]
+    for kind, (kname, _) in sorted(COLUMN_KERNELS.items()):
+        per = [[d for nm, d in sg if nm.startswith("void " + kname)] for sg in ev]
+        if not per[-1]:
+            print("%s>: no launches" % kname)
+            continue
+        allv = [d for sg in per for d in sg]
+        timed = [d for sg in per[warmup:warmup + steps] for d in sg]
+        prof = per[-1]
+        print("%s>: %d launches per reduction" % (kname, len(prof)))
+        print("  the %d launches of the %d evaluations: %.2f us" % (len(allv), n_eval, sum(allv) / len(allv)))
+        print("  the %d launches of the %d timed (captured-graph) evaluations: %.2f us"
+              % (len(timed), steps, sum(timed) / len(timed)))
+        print("  the %d launches of the profiled evaluation: %.2f us" % (len(prof), sum(prof) / len(prof)))
 
 
 def main():
@@ -670,12 +716,23 @@ def main():
     dA = float(np.abs(e32["grad_alpha0"] - e64["grad_alpha0"]).max())
     dW = float(np.abs(e32["grad_omega"] - e64["grad_omega"]).max())
 
-    # roofline of the dominant kernel: the per-column SYMV of the FP32 reduction
-    ms, nl, byts = r["fp32_refined"]["prof"][0]
-    avg_s = ms * 1e-3 / max(nl, 1)
-    bytes_per_launch = byts / max(nl, 1)
-    achieved = bytes_per_launch / avg_s / 1e9
-    traffic = symv_traffic()
+    # roofline of the dominant kernel: the per-column kernel of the FP32
+    # reduction (SYMV or fused) with the larger total time
+    col = {}
+    for kind, (kname, _) in COLUMN_KERNELS.items():
+        kms, knl, kb = r["fp32_refined"]["prof"][kind]
+        if knl == 0:
+            continue
+        avg = kms * 1e-3 / knl
+        col[kind] = {"kernel": kname + ">", "launches": knl, "total_ms": kms, "avg_launch_us": avg * 1e6,
+                     "algorithmic_bytes_per_launch": kb / knl, "achieved_GBs": kb / knl / avg / 1e9,
+                     "traffic": column_traffic(kind)}
+    dom = max(col, key=lambda k: col[k]["total_ms"])
+    ms, nl = col[dom]["total_ms"], col[dom]["launches"]
+    avg_s = col[dom]["avg_launch_us"] * 1e-6
+    bytes_per_launch = col[dom]["algorithmic_bytes_per_launch"]
+    achieved = col[dom]["achieved_GBs"]
+    traffic = col[dom]["traffic"]
     ms3, nl3, fl3 = r["fp32_refined"]["prof"][1]
     ms64, nl64, b64 = r["fp64"]["prof"][0]
     ms364, nl364, fl364 = r["fp64"]["prof"][1]
@@ -706,16 +763,17 @@ def main():
                            "refine_steps": float(e32["errors"][2]),
                            "refine_remainder_estimate": float(e32["errors"][3]),
                            "lambda_min": float(e64["errors"][0])},
-        "roofline": {"bound": "hbm", "kernel": "sytrd_symv_kernel<float> (BLAS-2 panel SYMV)",
+        "roofline": {"bound": "hbm", "kernel": col[dom]["kernel"] + " (per-column reduction launch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launches": nl, "avg_launch_us": avg_s * 1e6,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "per_column_kernels": list(col.values())},
         "phase_rooflines": {"fp32_refined": phase_rooflines(r["fp32_refined"]["prof"], 3 * N, True,
                                                             r["fp32_refined"]["s"]),
                             "fp64": phase_rooflines(r["fp64"]["prof"], 3 * N, False, r["fp64"]["s"])},
         "phases": {
-            "fp32_symv_GBs": achieved, "fp32_symv_total_ms": ms,
+            "fp32_column_GBs": achieved, "fp32_column_total_ms": sum(v["total_ms"] for v in col.values()),
             "fp32_syr2k_TFs": fl3 / (ms3 * 1e-3) / 1e12 if ms3 > 0 else None, "fp32_syr2k_total_ms": ms3,
             "fp64_symv_GBs": (b64 / max(nl64, 1)) / (ms64 * 1e-3 / max(nl64, 1)) / 1e9 if ms64 > 0 else None,
             "fp64_symv_total_ms": ms64,

@@ -227,8 +227,11 @@ mbd_status mbd_freq_evaluate(mbd_ctx *ctx, const mbd_system *sys, int32_t n_freq
  * screened parameters: the derivative of eq:scs contracted as in
  * eq:contraction), _EIGVALS, _ERRORS; other bits give MBD_ERR_UNSUPPORTED,
  * as does a lattice.  scs_params (DEVICE, may be NULL): [4][N] screened
- * alpha0, C6, omega, R_vdW.  A non-positive-definite alpha(iu)^-1 + T^scs
- * gives MBD_ERR_NEGATIVE_EIGENVALUE. */
+ * alpha0, C6, omega, R_vdW.  alpha_bar(u) is never formed: the contraction
+ * and the gradient need it only applied to three columns, which come from a
+ * Cholesky factorisation of alpha(iu)^-1 + T^scs per frequency.  A matrix
+ * that is not positive definite (a non-positive pivot) gives
+ * MBD_ERR_NEGATIVE_EIGENVALUE. */
 mbd_status mbd_rsscs_evaluate(mbd_ctx *ctx, const mbd_system *sys, int32_t n_freq, unsigned want, mbd_result *out,
                               double *scs_params);
 
@@ -250,17 +253,22 @@ mbd_status mbd_eigh(mbd_ctx *ctx, int32_t dtype, int32_t n, int32_t nbatch, void
 mbd_status mbd_autotune(mbd_ctx *ctx, const int32_t *sizes, int32_t nsizes, const char *table_json_path);
 mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
 
-/* Launch timing for measurement tools.  While enabled, every per-column SYMV
- * launch of the Householder reduction (kind 0, the bandwidth-bound BLAS-2
- * phase) and every trailing SYR2K launch (kind 1, the matrix-core BLAS-3
- * phase) is bracketed by two HIP events on the context stream, and so is
- * each phase of an evaluation: 2 input preparation and assembly, 3 Householder
- * reduction, 4 divide and conquer, 5 back-transform, 6 refinement (FP32 path),
- * 7 energy, Q^{-1/2} and gradients.  Enabling clears earlier records.
- * mbd_get_profile synchronises the stream and returns, for one kind (0..7),
- * the summed event time (ms), the number of records and the summed
- * algorithmic work: bytes of the lower trailing triangle read (kind 0), flops
- * of the rank-2k update (kind 1), 0 for the phases.  enable = 2 records the
+/* Launch timing for measurement tools.  While enabled, every per-column
+ * launch of the Householder reduction and every trailing SYR2K launch (kind 1,
+ * the matrix-core BLAS-3 phase) is bracketed by two HIP events on the context
+ * stream, and so is each phase of an evaluation: 2 input preparation and
+ * assembly, 3 Householder reduction, 4 divide and conquer, 5 back-transform,
+ * 6 refinement (FP32 path), 7 energy, Q^{-1/2} and gradients.  The per-column
+ * launches are kind 0 where a column takes a SYMV launch and a finish launch
+ * (large trailing orders), kind 8 where one fused launch finishes the previous
+ * column and runs the column's SYMV (FP32, trailing order up to 4000).
+ * Kind 9 is the screening stage of mbd_rsscs_evaluate (assembly, Cholesky
+ * factorisation and solves, contraction; and the chain rule of its gradient).
+ * Enabling clears earlier records.  mbd_get_profile synchronises the stream
+ * and returns, for one kind (0..9), the summed event time (ms), the number of
+ * records and the summed algorithmic work: bytes of the lower trailing
+ * triangle read (kinds 0 and 8), flops of the rank-2k update (kind 1), 0 for
+ * the phases.  enable = 2 records the
  * phases only, without timing events (which would slow every launch): the
  * stream is synchronised at each phase boundary and the host clock read. */
 mbd_status mbd_set_profiling(mbd_ctx *ctx, int enable);

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libmbd_hip.so")
 ARCH = os.environ.get("MBD_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["k_sytrd.hip", "k_stedc.hip", "k_stebz.hip", "k_ormtr.hip", "k_mbd.hip", "k_refine.hip",
-           "k_periodic.hip", "k_ts.hip", "k_freq.hip", "k_scs.hip",
+           "k_periodic.hip", "k_ts.hip", "k_freq.hip", "k_scs.hip", "k_chol.hip",
            "api.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -168,11 +168,12 @@ mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int
     sw.Vp = wsT<T>(c, "Vp" + t, sw.sP * nbatch);
     sw.Wp = wsT<T>(c, "Wp" + t, sw.sP * nbatch);
     // padded to whole 64-row blocks: the SYMV phase reads it in 16-byte segments
-    sw.sC = round_up(nmax, 64); sw.colbuf = wsT<T>(c, "colbuf" + t, (size_t)sw.sC * nbatch);
-    sw.normacc = wsT<T>(c, "normacc" + t, (size_t)2 * nbatch);
-    sw.sY = 2LL * SYTRD_YCOPIES * nmax; sw.yacc = wsT<T>(c, "yacc" + t, (size_t)sw.sY * nbatch);
-    sw.sS = 2LL * SYTRD_YCOPIES * 2 * SYTRD_NBP; sw.sacc = wsT<T>(c, "sacc" + t, (size_t)sw.sS * nbatch);
-    sw.vacc = wsT<T>(c, "vacc" + t, (size_t)2 * SYTRD_VCOPIES * nbatch);
+    sw.sC = round_up(nmax, 64); sw.colbuf = wsT<T>(c, "colbuf" + t, (size_t)2 * sw.sC * nbatch);
+    sw.normacc = wsT<T>(c, "normacc" + t, (size_t)SYTRD_SLOTS * nbatch);
+    sw.sY = (long long)SYTRD_SLOTS * SYTRD_YCOPIES * nmax; sw.yacc = wsT<T>(c, "yacc" + t, (size_t)sw.sY * nbatch);
+    sw.sS = (long long)SYTRD_SLOTS * SYTRD_YCOPIES * 2 * SYTRD_NBP;
+    sw.sacc = wsT<T>(c, "sacc" + t, (size_t)sw.sS * nbatch);
+    sw.vacc = wsT<T>(c, "vacc" + t, (size_t)SYTRD_SLOTS * SYTRD_VCOPIES * nbatch);
     sw.sD = nmax;
     sw.d = wsT<T>(c, "d" + t, (size_t)nmax * nbatch);
     sw.e = wsT<T>(c, "e" + t, (size_t)nmax * nbatch);
@@ -977,38 +978,39 @@ mbd_status mbd_rsscs_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, u
         u[f] = 0.6 * (1.0 + gx[f - 1]) / (1.0 - gx[f - 1]);
         wq[f] = 3.0 / pi * 1.2 / ((1.0 - gx[f - 1]) * (1.0 - gx[f - 1])) * gw[f - 1];
     }
-    std::vector<int> nsh(nf, n);
     SysDesc* sd_dev = (SysDesc*)ws(c, "scs_desc", sizeof(SysDesc));
     unsigned* status = wsT<unsigned>(c, "scs_status", 1);
-    int* ns_dev = wsT<int>(c, "scs_ns", nf);
     double* om0 = wsT<double>(c, "scs_om", N);
     double* cc0 = wsT<double>(c, "scs_cc", N);
     double* u_dev = wsT<double>(c, "scs_u", nf);
     double* wq_dev = wsT<double>(c, "scs_wq", nf);
-    double* lam = wsT<double>(c, "scs_lam", (size_t)n * nf);
-    double* sc = wsT<double>(c, "scs_sc", (size_t)n * nf);
+    const long long sR = 3LL * n;  // three right-hand sides per matrix, row-major
+    double* linv = wsT<double>(c, "scs_linv", (size_t)chol_linv_stride(n) * nf);
+    double* rhs = wsT<double>(c, "scs_rhs", (size_t)sR * nf);
+    double* ytmp = wsT<double>(c, "scs_y", (size_t)sR * nf);
+    double* V = wsT<double>(c, "scs_v", (size_t)sR * nf);
     double* abar = wsT<double>(c, "scs_abar", (size_t)nf * N);
     double* par = wsT<double>(c, "scs_par", (size_t)4 * N);
     MatBatch<double> A = {wsT<double>(c, "scsA", (size_t)stride * nf), ld, stride};
-    if (!sd_dev || !status || !ns_dev || !om0 || !cc0 || !u_dev || !wq_dev || !lam || !sc || !abar || !par || !A.p)
+    if (!sd_dev || !status || !om0 || !cc0 || !u_dev || !wq_dev || !linv || !rhs || !ytmp || !V || !abar || !par ||
+        !A.p)
         return (mbd_status)c->err_code;
     HIPCHK(hipMemcpyAsync(sd_dev, &base, sizeof(SysDesc), hipMemcpyHostToDevice, st), "upload");
-    HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st), "upload");
     HIPCHK(hipMemcpyAsync(u_dev, u.data(), sizeof(double) * nf, hipMemcpyHostToDevice, st), "upload");
     HIPCHK(hipMemcpyAsync(wq_dev, wq.data(), sizeof(double) * nf, hipMemcpyHostToDevice, st), "upload");
     fill_u32_launch(st, status, 1, 0u);
     mbd_prep_launch(st, sd_dev, 1, N, om0, cc0, status);
-    // screening: A(u) for all u in one batch, its inverse from the eigenpairs
-    scs_assemble_launch(st, sd_dev, N, om0, u_dev, nf, A, status);
-    HIPCHK(hipGetLastError(), "scs assemble");
-    MatBatch<double> X;
-    r = run_eig<double>(c, A, ns_dev, nsh.data(), n, nf, true, lam, n, &X);
-    if (r != MBD_OK) return r;
-    scs_invhalf_launch(st, ns_dev, n, nf, lam, n, sc, status);
-    mbd_inv_sqrt_launch(st, ns_dev, n, nf, X, sc, n, A);  // A <- X diag(1/lambda) X^T (lower)
-    mbd_mirror_launch(st, ns_dev, n, nf, A);
-    scs_contract_launch(st, A, N, nf, abar);
-    scs_params_launch(st, sd_dev, N, abar, wq_dev, nf, par);
+    // screening: A(u) for all u in one batch, its Cholesky factors, and
+    // V = A(u)^-1 (1 (x) I_3) from them
+    {
+        PhaseTimer ph(&c->prof, st, 9);
+        scs_assemble_launch(st, sd_dev, N, om0, u_dev, nf, A, status);
+        chol_factor_launch(st, A, n, nf, linv, status);
+        scs_rhs_launch(st, N, nf, nullptr, rhs);
+        chol_solve_launch(st, A, n, nf, linv, rhs, ytmp, V, sR);
+        scs_contract_launch(st, N, nf, V, abar);
+        scs_params_launch(st, sd_dev, N, abar, wq_dev, nf, par);
+    }
     if (scs_params) HIPCHK(hipMemcpyAsync(scs_params, par, sizeof(double) * 4 * N, hipMemcpyDeviceToDevice, st), "copy");
     HIPCHK(hipGetLastError(), "scs");
     unsigned sth = 0;
@@ -1044,11 +1046,16 @@ mbd_status mbd_rsscs_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, u
     if (codes[0] != MBD_OK) return code_message(c, codes[0], "mbd_rsscs_evaluate");
     if (grads) {
         // chain rule through the screened parameters
+        // U^T = A(u)^-1 (w (x) I_3) with the gradient weights w_i(u)
         double* w = wsT<double>(c, "scs_w", (size_t)nf * N);
+        double* U = wsT<double>(c, "scs_u3", (size_t)sR * nf);
         double* UV = wsT<double>(c, "scs_uv", (size_t)nf * n * 6);
-        if (!w || !UV) return (mbd_status)c->err_code;
-        scs_grad_launch(st, sd_dev, N, nf, om0, u_dev, par, abar, wq_dev, gpar, gpar + N, gpar + 2 * N, w, A, UV,
-                        out->grad_coords);
+        if (!w || !U || !UV) return (mbd_status)c->err_code;
+        PhaseTimer ph(&c->prof, st, 9);
+        scs_weights_launch(st, N, nf, par, abar, wq_dev, gpar, gpar + N, gpar + 2 * N, w);
+        scs_rhs_launch(st, N, nf, w, rhs);
+        chol_solve_launch(st, A, n, nf, linv, rhs, ytmp, U, sR);
+        scs_grad_launch(st, sd_dev, N, nf, om0, u_dev, U, V, UV, out->grad_coords);
         HIPCHK(hipGetLastError(), "scs gradient");
         HIPCHK(hipStreamSynchronize(st), "synchronize");
     }
@@ -1237,7 +1244,7 @@ mbd_status autotune_size(mbd_ctx* c, int n, int* best_target, int* best_lo, doub
             double u = 0, l = 0;
             int col = 0;
             for (size_t q = 0; q < prof.kind.size(); q++) {
-                if (prof.kind[q] != 0) continue;  // SYMV launches, one per column in order
+                if (prof.kind[q] != 0 && prof.kind[q] != 8) continue;  // per-column launches, in order
                 float ms = 0;
                 hipEventElapsedTime(&ms, prof.pool[2 * q], prof.pool[2 * q + 1]);
                 const int nbt = nbk - ((col + 1) >> 6);

@@ -8,9 +8,11 @@
 //             z = r/sqrt(sigma_i^2 + sigma_j^2), Th = (2 z/sqrt(pi)) e^{-z^2}  (eq:tgg)
 //   sigma = ((1/3) sqrt(2/pi) alpha(iu))^{1/3}                              (eq:mayer)
 // (g the Fermi damping with the MBD steepness a and s_R = beta on the input
-// R_vdW; T the explicit dipole tensor).  alpha_bar(u) = A(u)^-1 (eq:scs) comes
-// from the batched eigensolver, X diag(1/lambda) X^T; contracted per atom,
-// alpha_bar_i(u) = (1/3) sum_a sum_j alpha_bar_{ia,ja} (eq:contraction).  The
+// R_vdW; T the explicit dipole tensor).  alpha_bar(u) = A(u)^-1 (eq:scs) is
+// used only through V = alpha_bar (1 (x) I_3), solved from the batched
+// Cholesky factors of A(u); contracted per atom,
+// alpha_bar_i(u) = (1/3) sum_a sum_j alpha_bar_{ia,ja} = (1/3) sum_a V_{ia,a}
+// (eq:contraction).  The
 // screened parameters are alpha_bar_i(0), C6_i = (3/pi) int alpha_bar_i(iu)^2
 // du on the grid (eq:casimir-polder), omega_i = 4 C6_i/(3 alpha_bar_i(0)^2)
 // and R_vdW,i (alpha_bar_i(0)/alpha0_i)^{1/3} (eq:scale-rvdw-scs).
@@ -22,8 +24,8 @@
 //        [d T^scs_pq / d r_c](R_l - R_m) H_ml[p][q],
 //   H_ml[p][q] = sum_a (U_{a,3m+p} V_{3l+q,a} + U_{a,3l+q} V_{3m+p,a}),
 //   U_{a,k} = sum_i w_i alpha_bar_{ia,k},  V_{k,a} = sum_j alpha_bar_{k,ja},
-// so after U and V (one pass over each alpha_bar(u)) the contraction is a
-// pair loop, like the MBD adjoint.
+// i.e. U^T = alpha_bar (w (x) I_3) (a second three-column solve) and V as
+// above, so the contraction is a pair loop, like the MBD adjoint.
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
@@ -92,31 +94,33 @@ __global__ __launch_bounds__(256) void scs_assemble_kernel(const SysDesc* sd, co
         for (int p = 0; p < 3; p++) Ab[(3 * i + p) + (long long)(3 * j + q) * A.ld] = v[p][q];
 }
 
-// sc_k = lambda_k^{-1/2}, so that X diag(sc)^2 X^T = A^-1; a non-positive
-// eigenvalue (A not positive definite: the screening collapses) sets the
-// collapse bit
-__global__ __launch_bounds__(256) void scs_invhalf_kernel(const int* ns, const double* lam, long long sL, double* sc,
-                                                            unsigned* status) {
-    const int b = blockIdx.y;
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= ns[b]) return;
-    const double x = lam[(long long)b * sL + k];
-    if (!(x > 0.0)) atomicOr(&status[0], MBD_ST_COLLAPSE);
-    sc[(long long)b * sL + k] = x > 0.0 ? 1.0 / sqrt(x) : 0.0;
+// right-hand sides R_f[3i+a][c] = x_i delta_ac, x_i = 1 (contraction) or the
+// gradient weight w_i(u_f); layout [nf][3N][3]
+__global__ __launch_bounds__(256) void scs_rhs_kernel(int N, int nf, const double* w, double* R) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long tot = (long long)nf * N * 9;
+    if (t >= tot) return;
+    const int c = (int)(t % 3), a = (int)((t / 3) % 3);
+    const long long fi = t / 9;  // f * N + i
+    R[t] = a == c ? (w ? w[fi] : 1.0) : 0.0;
 }
 
-// alpha_bar_i(u_f) = (1/3) sum_a sum_j Abar_f[3j+a, 3i+a]; one workgroup per (i, f)
-__global__ __launch_bounds__(256) void scs_contract_kernel(MatBatch<double> M, int N, double* abar) {
-    __shared__ double red[4];
-    const int i = blockIdx.x, f = blockIdx.y;
-    const double* Mb = M.at(f);
-    double s = 0.0;
-    for (int t = threadIdx.x; t < 3 * N; t += 256) {
-        const int j = t / 3, a = t % 3;
-        s += Mb[(3 * j + a) + (long long)(3 * i + a) * M.ld];
+// alpha_bar_i(u_f) = (1/3) sum_a V_f[3i+a][a]
+__global__ __launch_bounds__(256) void scs_contract_kernel(int N, int nf, const double* V, double* abar) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)nf * N) return;
+    const double* v = V + t * 9;
+    abar[t] = (v[0] + v[4] + v[8]) / 3.0;
+}
+
+// UV[f][k][6] = {U_f[k][0..2], V_f[k][0..2]} for the gradient pair loop
+__global__ __launch_bounds__(256) void scs_pack_uv_kernel(int n, int nf, const double* U, const double* V, double* UV) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)nf * n) return;
+    for (int a = 0; a < 3; a++) {
+        UV[t * 6 + a] = U[t * 3 + a];
+        UV[t * 6 + 3 + a] = V[t * 3 + a];
     }
-    s = block_sum256(s, red);
-    if (threadIdx.x == 0) abar[(long long)f * N + i] = s / 3.0;
 }
 
 // screened parameters per atom: alpha_bar(0), C6 (quadrature weights wq_f,
@@ -154,33 +158,6 @@ __global__ __launch_bounds__(256) void scs_weights_kernel(int N, int nf, const d
     if (f == 0) v = ga[i] - 2.0 * om / a * gw[i] + gv[i] * rv / (3.0 * a);
     else v = gw[i] * 4.0 / (3.0 * a * a) * wq[f] * 2.0 * abar[(long long)f * N + i];
     w[(long long)f * N + i] = v;
-}
-
-// U_{a,k} = sum_i w_i Abar[3i+a, k] and V_{k,a} = sum_j Abar[3j+a, k] (Abar
-// symmetric); one workgroup per (column k, f); UV[f][k][6] = {U_0..2, V_0..2}
-__global__ __launch_bounds__(256) void scs_uv_kernel(MatBatch<double> M, int N, const double* w, double* UV) {
-    __shared__ double red[4];
-    const int k = blockIdx.x, f = blockIdx.y;
-    const double* col = M.at(f) + (long long)k * M.ld;
-    const double* wf = w + (long long)f * N;
-    double u[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
-    for (int j = threadIdx.x; j < N; j += 256) {
-        const double wj = wf[j];
-        for (int a = 0; a < 3; a++) {
-            const double x = col[3 * j + a];
-            u[a] += wj * x;
-            v[a] += x;
-        }
-    }
-    double* out = UV + ((long long)f * 3 * N + k) * 6;
-    for (int a = 0; a < 3; a++) {
-        const double su = block_sum256(u[a], red);
-        const double sv = block_sum256(v[a], red);
-        if (threadIdx.x == 0) {
-            out[a] = su;
-            out[3 + a] = sv;
-        }
-    }
 }
 
 // dE/dR_m += sum_f (1/3) sum_{l != m} sum_pq [d T^scs_pq / d r_c] H_ml[p][q];
@@ -248,22 +225,27 @@ void scs_assemble_launch(hipStream_t st, const SysDesc* sd, int N, const double*
     const int g = (N + 15) / 16;
     hipLaunchKernelGGL(scs_assemble_kernel, dim3(g, g, nf), dim3(256), 0, st, sd, om, u, A, status);
 }
-void scs_invhalf_launch(hipStream_t st, const int* ns, int nmax, int nf, const double* lam, long long sL, double* sc,
-                        unsigned* status) {
-    hipLaunchKernelGGL(scs_invhalf_kernel, dim3((nmax + 255) / 256, nf), dim3(256), 0, st, ns, lam, sL, sc, status);
+void scs_rhs_launch(hipStream_t st, int N, int nf, const double* w, double* R) {
+    const long long tot = (long long)nf * N * 9;
+    hipLaunchKernelGGL(scs_rhs_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, N, nf, w, R);
 }
-void scs_contract_launch(hipStream_t st, MatBatch<double> M, int N, int nf, double* abar) {
-    hipLaunchKernelGGL(scs_contract_kernel, dim3(N, nf), dim3(256), 0, st, M, N, abar);
+void scs_contract_launch(hipStream_t st, int N, int nf, const double* V, double* abar) {
+    hipLaunchKernelGGL(scs_contract_kernel, dim3((unsigned)(((long long)nf * N + 255) / 256)), dim3(256), 0, st, N,
+                       nf, V, abar);
 }
 void scs_params_launch(hipStream_t st, const SysDesc* sd, int N, const double* abar, const double* wq, int nf,
                        double* out) {
     hipLaunchKernelGGL(scs_params_kernel, dim3((N + 255) / 256), dim3(256), 0, st, sd, abar, wq, nf, out);
 }
-void scs_grad_launch(hipStream_t st, const SysDesc* sd, int N, int nf, const double* om, const double* u,
-                     const double* par, const double* abar, const double* wq, const double* ga, const double* gw,
-                     const double* gv, double* w, MatBatch<double> M, double* UV, double* grad) {
+void scs_weights_launch(hipStream_t st, int N, int nf, const double* par, const double* abar, const double* wq,
+                        const double* ga, const double* gw, const double* gv, double* w) {
     hipLaunchKernelGGL(scs_weights_kernel, dim3((N + 255) / 256, nf), dim3(256), 0, st, N, nf, par, abar, wq, ga, gw,
                        gv, w);
-    hipLaunchKernelGGL(scs_uv_kernel, dim3(3 * N, nf), dim3(256), 0, st, M, N, w, UV);
+}
+void scs_grad_launch(hipStream_t st, const SysDesc* sd, int N, int nf, const double* om, const double* u,
+                     const double* U, const double* V, double* UV, double* grad) {
+    const int n = 3 * N;
+    hipLaunchKernelGGL(scs_pack_uv_kernel, dim3((unsigned)(((long long)nf * n + 255) / 256)), dim3(256), 0, st, n, nf,
+                       U, V, UV);
     hipLaunchKernelGGL(scs_grad_kernel, dim3(N), dim3(256), 0, st, sd, om, u, nf, UV, grad);
 }

@@ -19,13 +19,20 @@
 // half).  The accumulation order of the atomics varies, so results agree
 // between runs to rounding, not bitwise.
 //
-// Each phase is one launch per column: two dependent launches per column.  A
-// cooperative kernel with a grid-wide barrier after each phase and a single
-// launch that fused the phases through device-scope counters were both
-// measured slower on gfx950 (a grid barrier or a release fence per workgroup
-// costs more than a dependent launch).  Every work item carries a batch
-// index, so one launch sequence serves a single large matrix and batches of
-// uneven matrices alike.
+// While the trailing matrix is large each phase is one launch per column.
+// Below a trailing order (FP32: 4000) one launch per column does both: each
+// workgroup finishes the previous column on the rows it touches, then runs
+// this column's SYMV (the fused path below); the panel's last column gets a
+// finish launch of its own.  A dependent launch costs about 2.8 us on gfx950
+// even when empty, so the fused path saves that per column where its
+// redundant row work is cheap; for large trailing orders that row work (about
+// as many bytes as the tiles) costs more, and in FP64 its registers leave one
+// wavefront per SIMD.  A cooperative kernel with a grid-wide barrier after
+// each phase and a single launch that chained the phases through
+// device-scope counters were both measured slower (a grid barrier or a
+// release fence per workgroup costs more than a dependent launch).  Every
+// work item carries a batch index, so one launch sequence serves a single
+// large matrix and batches of uneven matrices alike.
 #include <algorithm>
 #include <cstdlib>
 #include <string>
@@ -55,11 +62,12 @@ __device__ __forceinline__ T refl_v(const T* col, int r, int s, int n, T scale) 
 // Reflector scalars from the updated column held in colbuf (LAPACK dlarfg
 // convention: beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta).  The
 // squared norm of x = col(i+2:n) was accumulated (atomically, by the phase
-// that produced the column) into parity slot (i & 1) of normacc.
+// that produced the column) into slot i % SYTRD_SLOTS of normacc; the column
+// itself is in colbuf slot i & 1.
 template <typename T>
 __device__ __forceinline__ Refl<T> refl_scalars(const SytrdWs<T>& w, int b, int i, int n) {
-    const T xn2 = w.normacc[(long long)b * 2 + (i & 1)];
-    const T alpha = w.colbuf[(long long)b * w.sC + i + 1];
+    const T xn2 = w.normacc[(long long)b * SYTRD_SLOTS + i % SYTRD_SLOTS];
+    const T alpha = w.colbuf[(long long)b * 2 * w.sC + (i & 1) * w.sC + i + 1];
     Refl<T> r;
     if (xn2 == T(0)) {
         r.tau = T(0); r.beta = alpha; r.scale = T(0);
@@ -104,7 +112,7 @@ __host__ __device__ __forceinline__ int sytrd_tail_start(int n) {
     return n <= M0 ? 0 : (n - M0 + SYTRD_NBP - 1) / SYTRD_NBP * SYTRD_NBP;
 }
 
-// Accumulators of column i live in parity slot (i & 1).  To keep atomic
+// Accumulators of column i live in slot i % SYTRD_SLOTS.  To keep atomic
 // contention low they are spread over copies: y and the panel products over
 // SYTRD_YC copies chosen by column strip, v^T A v over SYTRD_VC copies chosen
 // by workgroup; the finish phase adds the copies.
@@ -112,15 +120,15 @@ __host__ __device__ __forceinline__ int sytrd_tail_start(int n) {
 #define SYTRD_VC SYTRD_VCOPIES
 template <typename T>
 __device__ __forceinline__ T* yacc_of(const SytrdWs<T>& w, int b, int i, int copy) {
-    return w.yacc + (long long)b * w.sY + ((i & 1) * SYTRD_YC + copy) * (long long)w.nmax;
+    return w.yacc + (long long)b * w.sY + ((i % SYTRD_SLOTS) * SYTRD_YC + copy) * (long long)w.nmax;
 }
 template <typename T>
 __device__ __forceinline__ T* sacc_of(const SytrdWs<T>& w, int b, int i, int copy) {
-    return w.sacc + (long long)b * w.sS + ((i & 1) * SYTRD_YC + copy) * (2 * SYTRD_NBP);
+    return w.sacc + (long long)b * w.sS + ((i % SYTRD_SLOTS) * SYTRD_YC + copy) * (2 * SYTRD_NBP);
 }
 template <typename T>
 __device__ __forceinline__ T* vacc_of(const SytrdWs<T>& w, int b, int i) {
-    return w.vacc + (long long)b * (2 * SYTRD_VC) + (i & 1) * SYTRD_VC;
+    return w.vacc + (long long)b * (SYTRD_SLOTS * SYTRD_VC) + (i % SYTRD_SLOTS) * SYTRD_VC;
 }
 
 template <typename T>
@@ -131,15 +139,16 @@ __global__ __launch_bounds__(256) void sytrd_init_kernel(SytrdWs<T> w) {
     const int nbk = (n + 63) >> 6;
     if (R >= nbk) return;
     const T* A = w.A.at(b);
-    T* col = w.colbuf + (long long)b * w.sC;
-    // both parity slots of the accumulators start at zero
-    for (int t = threadIdx.x; t < 2 * SYTRD_YC * 64; t += 256) {
+    T* col = w.colbuf + (long long)b * 2 * w.sC;
+    // every slot of the accumulators starts at zero
+    for (int t = threadIdx.x; t < SYTRD_SLOTS * SYTRD_YC * 64; t += 256) {
         const int r = R * 64 + (t & 63);
         if (r < n) w.yacc[(long long)b * w.sY + (t >> 6) * (long long)w.nmax + r] = T(0);
     }
     if (R == 0) {
-        for (int t = threadIdx.x; t < 2 * SYTRD_YC * 2 * SYTRD_NBP; t += 256) w.sacc[(long long)b * w.sS + t] = T(0);
-        for (int t = threadIdx.x; t < 2 * SYTRD_VC; t += 256) w.vacc[(long long)b * (2 * SYTRD_VC) + t] = T(0);
+        for (int t = threadIdx.x; t < SYTRD_SLOTS * SYTRD_YC * 2 * SYTRD_NBP; t += 256) w.sacc[(long long)b * w.sS + t] = T(0);
+        for (int t = threadIdx.x; t < SYTRD_SLOTS * SYTRD_VC; t += 256)
+            w.vacc[(long long)b * (SYTRD_SLOTS * SYTRD_VC) + t] = T(0);
     }
     if (n == 1) {
         if (threadIdx.x == 0) w.d[(long long)b * w.sD] = A[0];
@@ -151,14 +160,14 @@ __global__ __launch_bounds__(256) void sytrd_init_kernel(SytrdWs<T> w) {
     if (r < n) col[r] = x;
     T q = (r >= 2 && r < n) ? x * x : T(0);
     q = wave_sum(q);
-    if (threadIdx.x == 0) unsafeAtomicAdd(&w.normacc[(long long)b * 2 + 0], q);
+    if (threadIdx.x == 0) unsafeAtomicAdd(&w.normacc[(long long)b * SYTRD_SLOTS + 0], q);
 }
 
 // both norm slots to zero before the first column
 template <typename T>
 __global__ void sytrd_zero_norm_kernel(SytrdWs<T> w, int nbatch) {
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < 2 * nbatch) w.normacc[t] = T(0);
+    if (t < SYTRD_SLOTS * nbatch) w.normacc[t] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -193,7 +202,7 @@ __device__ void symv_item(const SytrdWs<T>& w, int b, int n, int i, int j, int K
     const int nbk = (n + 63) >> 6;
     T* A = w.A.at(b);
     const long long ld = w.A.ld;
-    const T* col = w.colbuf + (long long)b * w.sC;
+    const T* col = w.colbuf + (long long)b * 2 * w.sC + (i & 1) * w.sC;
     T* Vp = w.Vp + (long long)b * w.sP;
     T* Wp = w.Wp + (long long)b * w.sP;
     T* yacc = yacc_of(w, b, i, C % SYTRD_YC);
@@ -454,8 +463,8 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
     const T vAv = wave_sum((vq[0] + vq[1]) + (vq[2] + vq[3]));
     __syncthreads();
 
-    // clear the other parity slot for column i + 1 (its SYMV runs after this
-    // kernel): rows of block R, and the scalars once per matrix
+    // clear the next column's slot for column i + 1 (its SYMV runs after
+    // this kernel): rows of block R, and the scalars once per matrix
     for (int c = part; c < SYTRD_YC; c += 4)
         if (R * 64 + lane < n) yacc_of(w, b, i + 1, c)[R * 64 + lane] = T(0);
     if (R == b0) {
@@ -501,12 +510,12 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
         T cval = T(0);
         if (rv) {
             cval = acol - u;
-            w.colbuf[(long long)b * w.sC + r] = cval;
+            w.colbuf[(long long)b * 2 * w.sC + (s & 1) * w.sC + r] = cval;
             if (s == n - 1) w.d[(long long)b * w.sD + n - 1] = cval;
         }
         T q2 = (r >= s + 2 && r < n) ? cval * cval : T(0);
         q2 = wave_sum(q2);
-        if (lane == 0) unsafeAtomicAdd(&w.normacc[(long long)b * 2 + (s & 1)], q2);
+        if (lane == 0) unsafeAtomicAdd(&w.normacc[(long long)b * SYTRD_SLOTS + s % SYTRD_SLOTS], q2);
     }
     __syncthreads();
 }
@@ -641,6 +650,486 @@ __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<
     if (threadIdx.x == 0) d[m - 1] = L[cs(m - 1)];
 }
 
+// ===========================================================================
+// Fused per-column path: one launch per column.
+//
+// The launch for column i first finishes column c = i - 1 (what the separate
+// finish phase does), in every workgroup for the rows that workgroup touches,
+// then runs the SYMV of column i on the unscaled updated column
+// x = A(i+1:n, i).  The reflector v = (x - beta e_1) / (alpha - beta) needs
+// the norm of x, which is only complete when this launch has ended; every
+// product the SYMV forms is linear in v, so the launch accumulates A x,
+// W^T x, V^T x and x^T A x, and the next launch turns them into the products
+// with v once beta is known:
+//   A v     = (A x - beta A e_1) / (alpha - beta)
+//   W^T v   = (W^T x - beta W(i+1, :)^T) / (alpha - beta)
+//   v^T A v = (x^T A x - 2 beta (A x)_1 + beta^2 A_11) / (alpha - beta)^2
+// (A the lower trailing matrix as stored, before this panel's update).  The
+// last column of a panel is finished by a launch of its own: the panel
+// update needs its w before the next column's SYMV.  Accumulators rotate
+// over three slots (a launch reads the previous column's slot, adds into its
+// own and clears the next one), the column buffer over two.
+// ===========================================================================
+template <typename T>
+__device__ __forceinline__ T* yacc_s(const SytrdWs<T>& w, int b, int slot, int copy) {
+    return w.yacc + (long long)b * w.sY + (slot * SYTRD_YC + copy) * (long long)w.nmax;
+}
+template <typename T>
+__device__ __forceinline__ T* sacc_s(const SytrdWs<T>& w, int b, int slot, int copy) {
+    return w.sacc + (long long)b * w.sS + (slot * SYTRD_YC + copy) * (2 * SYTRD_NBP);
+}
+template <typename T>
+__device__ __forceinline__ T* vacc_s(const SytrdWs<T>& w, int b, int slot) {
+    return w.vacc + (long long)b * (SYTRD_SLOTS * SYTRD_VC) + slot * SYTRD_VC;
+}
+template <typename T>
+__device__ __forceinline__ T* norm_s(const SytrdWs<T>& w, int b, int slot) {
+    return w.normacc + (long long)b * SYTRD_SLOTS + slot;
+}
+template <typename T>
+__device__ __forceinline__ T* col_s(const SytrdWs<T>& w, int b, int slot2) {
+    return w.colbuf + (long long)b * 2 * w.sC + slot2 * w.sC;
+}
+
+// Scalars of the finished column c, held by every wavefront.
+template <typename T>
+struct FinScal {
+    T beta, tau, scale, wtv, ws, us, dprev;
+    bool zero;  // x(2:) == 0: H = I, v = e_1
+};
+
+// Row r of the finish of column c: the inputs, requested together.
+template <typename T>
+struct FinRow {
+    T uc, ar, yc[SYTRD_YC], vk[SYTRD_NBP], wk[SYTRD_NBP];
+};
+
+// c: finished column (s = c + 1 its reflector's first row), J: its panel
+// column.  Rows are clamped into the matrix; the panel columns k >= J (not
+// yet written in this panel) are requested at an out-of-range offset, which
+// reads zero without a memory access.
+template <typename T>
+__device__ __forceinline__ void fin_load(const SytrdWs<T>& w, int b, int n, int c, int J, int r, FinRow<T>& f) {
+    const int s = c + 1, sl = c % SYTRD_SLOTS;
+    const int rc = r < n ? r : n - 1;
+    f.uc = col_s(w, b, c & 1)[rc];
+    f.ar = w.A.at(b)[rc + (long long)s * w.A.ld];
+#pragma unroll
+    for (int cp = 0; cp < SYTRD_YC; cp++) f.yc[cp] = yacc_s(w, b, sl, cp)[rc];
+    const unsigned pbytes = (unsigned)(w.sP * (long long)sizeof(T));
+    const __amdgpu_buffer_rsrc_t vs = make_rsrc(w.Vp + (long long)b * w.sP, pbytes);
+    const __amdgpu_buffer_rsrc_t ws = make_rsrc(w.Wp + (long long)b * w.sP, pbytes);
+#pragma unroll
+    for (int k = 0; k < SYTRD_NBP; k++) {
+        const unsigned off = k < J ? (unsigned)((rc + (long long)k * w.ldp) * sizeof(T)) : OOB_OFFSET;
+        f.vk[k] = buf_load<T>(vs, off);
+        f.wk[k] = buf_load<T>(ws, off);
+    }
+}
+
+// Column scalars of the finished column c from the accumulators of its SYMV
+// (reflector: LAPACK dlarfg convention, beta = -sign(alpha) ||x||,
+// tau = (beta - alpha) / beta), then the panel products with v, v^T A v,
+// w^T v, and w and the updated next column at row s.  Each wavefront forms
+// them on its own (no barrier); coef (wavefront-private LDS) receives
+// p_k = W(:,k)^T v, s_k = V(:,k)^T v, W(s,k), V(s,k), zero for k >= J.
+template <typename T>
+__device__ __forceinline__ FinScal<T> fin_scalars(const SytrdWs<T>& w, int b, int c, int J, T (*coef)[4]) {
+    constexpr int NBP = SYTRD_NBP;
+    static_assert(SYTRD_VC == 256 && SYTRD_YC == 4 && 2 * NBP == 64, "accumulator layout");
+    const int lane = threadIdx.x & 63;
+    const int s = c + 1, sl = c % SYTRD_SLOTS;
+    const T* A = w.A.at(b);
+    const long long ld = w.A.ld;
+    const int k = lane & (NBP - 1);
+    T sW[SYTRD_YC], sV[SYTRD_YC], va[4];
+#pragma unroll
+    for (int cp = 0; cp < SYTRD_YC; cp++) {
+        sW[cp] = sacc_s(w, b, sl, cp)[k];
+        sV[cp] = sacc_s(w, b, sl, cp)[NBP + k];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; t++) va[t] = vacc_s(w, b, sl)[lane + 64 * t];
+    const unsigned pbytes = (unsigned)(w.sP * (long long)sizeof(T));
+    const unsigned off = lane < J ? (unsigned)((s + (long long)lane * w.ldp) * sizeof(T)) : OOB_OFFSET;
+    const T Vs = buf_load<T>(make_rsrc(w.Vp + (long long)b * w.sP, pbytes), off);
+    const T Ws = buf_load<T>(make_rsrc(w.Wp + (long long)b * w.sP, pbytes), off);
+    const T yq = yacc_s(w, b, sl, lane & (SYTRD_YC - 1))[s];
+    const T xn2 = *norm_s(w, b, sl);
+    const T alpha = col_s(w, b, c & 1)[s];
+    const T dprev = col_s(w, b, c & 1)[c];
+    const T Ass = A[s + (long long)s * ld];
+
+    const T xAx = wave_sum((va[0] + va[1]) + (va[2] + va[3]));
+    const T yxs = (lane_value(yq, 0) + lane_value(yq, 1)) + (lane_value(yq, 2) + lane_value(yq, 3));
+    FinScal<T> f;
+    f.zero = xn2 == T(0);
+    if (f.zero) {
+        f.tau = T(0); f.beta = alpha; f.scale = T(0);
+    } else {
+        const T nrm = sqrt(alpha * alpha + xn2);
+        f.beta = alpha >= T(0) ? -nrm : nrm;
+        f.tau = (f.beta - alpha) / f.beta;
+        f.scale = T(1) / (alpha - f.beta);
+    }
+    const bool kv = lane < J;
+    const T Wx = (sW[0] + sW[1]) + (sW[2] + sW[3]);
+    const T Vx = (sV[0] + sV[1]) + (sV[2] + sV[3]);
+    const T pk = kv ? f.scale * (Wx - f.beta * Ws) : T(0);
+    const T sk = kv ? f.scale * (Vx - f.beta * Vs) : T(0);
+    const T pts = wave_sum(pk * sk);
+    const T corr = wave_sum(Vs * pk + Ws * sk);
+    const T vw = wave_sum(Vs * Ws);
+    const T vAv = f.scale * f.scale * ((xAx - T(2) * f.beta * yxs) + f.beta * f.beta * Ass);
+    f.wtv = f.tau * (vAv - T(2) * pts);
+    f.ws = f.tau * (f.scale * (yxs - f.beta * Ass) - corr) - T(0.5) * f.tau * f.wtv;
+    f.us = Ass - T(2) * vw - T(2) * f.ws;
+    f.dprev = dprev;
+    if (lane < NBP) {
+        coef[lane][0] = pk;
+        coef[lane][1] = sk;
+        coef[lane][2] = Ws;
+        coef[lane][3] = Vs;
+    }
+    return f;
+}
+
+// v and w of the finished column at row r, and the next column (s) updated
+// by the whole panel so far at row r:
+//   w(r) = tau (A v - V p - W s)(r) - (tau/2) (w^T v) v(r)
+//   u(r) = A(r, s) - sum_k [V(r,k) W(s,k) + W(r,k) V(s,k)]      (k <= J, V(s, J) = 1)
+// with A v, the panel products and v^T A v from those of x (above).
+template <typename T>
+__device__ __forceinline__ void fin_row(const FinScal<T>& fs, const T (*coef)[4], const FinRow<T>& f, int r, int s,
+                                        int n, T& v, T& wr, T& u) {
+    const bool rv = r >= s && r < n;
+    T corr = T(0), ucor = T(0);
+#pragma unroll
+    for (int k = 0; k < SYTRD_NBP; k++) {
+        corr += f.vk[k] * coef[k][0] + f.wk[k] * coef[k][1];
+        ucor += f.vk[k] * coef[k][2] + f.wk[k] * coef[k][3];
+    }
+    const T yx = (f.yc[0] + f.yc[1]) + (f.yc[2] + f.yc[3]);
+    T vr = r == s ? T(1) : (fs.zero ? T(0) : fs.scale * f.uc);
+    vr = rv ? vr : T(0);
+    const T yv = fs.scale * (yx - fs.beta * f.ar);
+    wr = rv ? fs.tau * (yv - corr) - T(0.5) * fs.tau * fs.wtv * vr : T(0);
+    u = f.ar - ucor - vr * fs.ws - wr;
+    v = vr;
+}
+
+// The updated next column at row r as fin_row computes it, with the panel
+// rows read eight columns at a time (for rows beyond the first block of a
+// wave, where no latency is to be hidden and registers are short).
+template <typename T>
+__device__ __forceinline__ T fin_row_stream(const SytrdWs<T>& w, const FinScal<T>& fs, const T (*coef)[4], int b, int n,
+                                            int c, int J, int r) {
+    const int s = c + 1, sl = c % SYTRD_SLOTS;
+    const int rc = r < n ? r : n - 1;
+    const T uc = col_s(w, b, c & 1)[rc];
+    const T ar = w.A.at(b)[rc + (long long)s * w.A.ld];
+    T yc[SYTRD_YC];
+#pragma unroll
+    for (int cp = 0; cp < SYTRD_YC; cp++) yc[cp] = yacc_s(w, b, sl, cp)[rc];
+    const T* Vp = w.Vp + (long long)b * w.sP + rc;
+    const T* Wp = w.Wp + (long long)b * w.sP + rc;
+    T corr = T(0), ucor = T(0);
+#pragma unroll 1
+    for (int k0 = 0; k0 < J; k0 += 8) {
+        T vk[8], wk[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int k = k0 + t < J ? k0 + t : J - 1;
+            const T a = Vp[(long long)k * w.ldp], bb = Wp[(long long)k * w.ldp];
+            vk[t] = k0 + t < J ? a : T(0);
+            wk[t] = k0 + t < J ? bb : T(0);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            corr += vk[t] * coef[k0 + t][0] + wk[t] * coef[k0 + t][1];
+            ucor += vk[t] * coef[k0 + t][2] + wk[t] * coef[k0 + t][3];
+        }
+    }
+    const bool rv = r >= s && r < n;
+    const T yx = (yc[0] + yc[1]) + (yc[2] + yc[3]);
+    T vr = r == s ? T(1) : (fs.zero ? T(0) : fs.scale * uc);
+    vr = rv ? vr : T(0);
+    const T yv = fs.scale * (yx - fs.beta * ar);
+    const T wr = rv ? fs.tau * (yv - corr) - T(0.5) * fs.tau * fs.wtv * vr : T(0);
+    return ar - ucor - vr * fs.ws - wr;
+}
+
+// ---------------------------------------------------------------------------
+// Column work item: finishes column i - 1 on the item's rows (j > 0), then
+// the SYMV of column i over tiles R in [C + q Kt, C + (q+1) Kt) of strip C,
+// as symv_item but with x in LDS.  Items q == 0 also store what the finish
+// produces on the rows of block C (v, w into the panel, v into the matrix,
+// the next column and its norm) and clear the next slot there.
+// ---------------------------------------------------------------------------
+template <typename T, int NBP>
+__device__ void col_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt, int C, int q) {
+    constexpr int RPL = 16 / (int)sizeof(T);
+    constexpr int LPC = 64 / RPL;
+    constexpr int NI = 16 / RPL;
+    typedef typename Vec16<T>::v VT;
+    static_assert(NBP == SYTRD_NBP && NBP == 32, "panel products in four groups of sixteen");
+    __shared__ T rpart[SYTRD_KTMAX][4][64];
+    __shared__ T ubuf[SYTRD_KTMAX + 1][64];  // x on the rows of the item's blocks
+    __shared__ T coefw[4][SYTRD_NBP][4];     // per-wavefront column coefficients
+    __shared__ T red[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane / LPC, rq = lane % LPC;
+    const int t1 = i + 1;  // first row of the trailing block
+    const int b0 = t1 >> 6;
+    const int nbk = (n + 63) >> 6;
+    T* A = w.A.at(b);
+    const long long ld = w.A.ld;
+    const int ldp = w.ldp;
+    const int Rb = C + q * Kt;
+    const int Re = min(Rb + Kt, nbk);
+    const int c0 = C * 64 + wv * 16;
+    // the item's row blocks: C first, then the tile rows (q == 0: they start at C)
+    const int nblk = (q == 0 ? 0 : 1) + (Re - Rb);
+    auto blk = [&](int m) { return q == 0 ? C + m : (m == 0 ? C : Rb + m - 1); };
+    auto slot_of = [&](int R) { return q == 0 ? R - C : 1 + R - Rb; };
+
+    // the first tile is requested before anything else
+    const int ncols = max(0, min(16, n - c0));
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(A + (long long)c0 * ld, (unsigned)(ncols * ld * (long long)sizeof(T)));
+    unsigned coff[NI];
+    bool cok[NI];
+#pragma unroll
+    for (int k = 0; k < NI; k++) {
+        const int c = c0 + RPL * k + g;
+        cok[k] = c >= t1 && c < n;
+        coff[k] = (unsigned)((RPL * k + g) * ld * (long long)sizeof(T));
+    }
+    VT buf[NI];
+    auto issue = [&](int R) {
+        const unsigned roff = R < Re ? (unsigned)((R * 64 + RPL * rq) * (int)sizeof(T)) : OOB_OFFSET;
+#pragma unroll
+        for (int k = 0; k < NI; k++) buf[k] = buf_load16<T>(rsrc, cok[k] ? coff[k] + roff : OOB_OFFSET);
+    };
+    issue(Rb);
+
+    const bool fin = j > 0;
+    const int cf = i - 1, J = j - 1;
+    const int sln = (i + 1) % SYTRD_SLOTS, slc = i % SYTRD_SLOTS;
+    FinScal<T> fs{};
+    if (fin && wv < nblk) {
+        // the first block of each wave: its row data is requested with the
+        // tile, the column scalars formed while it arrives
+        FinRow<T> fr;
+        const int r = blk(wv) * 64 + lane;
+        fin_load(w, b, n, cf, J, r, fr);
+        fs = fin_scalars(w, b, cf, J, coefw[wv]);
+        {
+            T v, wr, u;
+            fin_row(fs, coefw[wv], fr, r, i, n, v, wr, u);
+            const T x = (r >= t1 && r < n) ? u : T(0);
+            ubuf[wv][lane] = x;
+            if (wv == 0 && q == 0) {
+                // block C: what the finish produces, stored once
+                T* Vp = w.Vp + (long long)b * w.sP;
+                T* Wp = w.Wp + (long long)b * w.sP;
+                if (r < n) {
+                    Vp[r + (long long)J * ldp] = v;
+                    Wp[r + (long long)J * ldp] = wr;
+                    if (r >= i) {
+                        A[r + (long long)cf * ld] = v;
+                        col_s(w, b, i & 1)[r] = u;
+                    }
+                }
+                T q2 = (r >= i + 2 && r < n) ? u * u : T(0);
+                q2 = wave_sum(q2);
+                if (lane == 0) unsafeAtomicAdd(norm_s(w, b, slc), q2);
+                // panel products of column i over the rows of block C:
+                // W(:,k)^T x and V(:,k)^T x for k <= J (column J is w, v)
+                T* sacc = sacc_s(w, b, slc, C % SYTRD_YC);
+#pragma unroll
+                for (int grp = 0; grp < 4; grp++) {
+                    const int kb = (grp & 1) * 16;
+                    if (kb <= J) {
+                        T pr[16];
+#pragma unroll
+                        for (int t = 0; t < 16; t++) {
+                            const int k = kb + t;
+                            const T pv = grp < 2 ? (k == J ? wr : fr.wk[k]) : (k == J ? v : fr.vk[k]);
+                            pr[t] = pv * x;
+                        }
+                        const T ps = wave_sum16(pr);
+                        const int k = kb + (lane >> 2);
+                        if ((lane & 3) == 0 && k <= J) unsafeAtomicAdd(&sacc[(grp >> 1) * NBP + k], ps);
+                    }
+                }
+            }
+        }
+        // further blocks (long strips): one at a time, streaming the panel
+        for (int m = wv + 4; m < nblk; m += 4) {
+            const int r2 = blk(m) * 64 + lane;
+            ubuf[m][lane] = (r2 >= t1 && r2 < n) ? fin_row_stream(w, fs, coefw[wv], b, n, cf, J, r2) : T(0);
+        }
+    } else if (!fin) {
+        for (int m = wv; m < nblk; m += 4) {
+            const int r = blk(m) * 64 + lane;
+            const T uu = col_s(w, b, i & 1)[r < n ? r : n - 1];
+            ubuf[m][lane] = (r >= t1 && r < n) ? uu : T(0);
+        }
+    }
+    if (q == 0) {
+        // clear the next column's slot on the rows of block C
+        const int r = C * 64 + lane;
+        if (r < n) yacc_s(w, b, sln, wv)[r] = T(0);
+        if (C == b0) {
+            sacc_s(w, b, sln, wv)[lane] = T(0);
+            vacc_s(w, b, sln)[tid] = T(0);
+            if (tid == 0) *norm_s(w, b, sln) = T(0);
+            if (fin && tid == 0) {
+                // row i when it lies above block b0, and the finished column's outputs
+                if (i < b0 * 64) {
+                    w.Vp[(long long)b * w.sP + i + (long long)J * ldp] = T(1);
+                    w.Wp[(long long)b * w.sP + i + (long long)J * ldp] = fs.ws;
+                    A[i + (long long)cf * ld] = T(1);
+                    col_s(w, b, i & 1)[i] = fs.us;
+                }
+                w.d[(long long)b * w.sD + cf] = fs.dprev;
+                w.e[(long long)b * w.sD + cf] = fs.beta;
+                w.tau[(long long)b * w.sD + cf] = fs.tau;
+            }
+        }
+    }
+    __syncthreads();
+
+    // SYMV of column i with x
+    T vc[NI], cacc[NI];
+#pragma unroll
+    for (int k = 0; k < NI; k++) {
+        vc[k] = ubuf[0][wv * 16 + RPL * k + g];
+        cacc[k] = T(0);
+    }
+    T* yacc = yacc_s(w, b, slc, C % SYTRD_YC);
+    for (int R = Rb; R < Re; R++) {
+        const int r0 = R * 64 + RPL * rq;
+        const int sl = slot_of(R);
+        T vr[RPL], rs[RPL];
+#pragma unroll
+        for (int e = 0; e < RPL; e++) {
+            vr[e] = ubuf[sl][RPL * rq + e];
+            rs[e] = T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NI; k++) {
+            const int c = c0 + RPL * k + g;
+#pragma unroll
+            for (int e = 0; e < RPL; e++) {
+                const int r = r0 + e;
+                const T xa = (r < n && (R > C || r >= c)) ? buf[k][e] : T(0);
+                rs[e] += xa * vc[k];
+                cacc[k] += (R > C || r != c) ? xa * vr[e] : T(0);
+            }
+        }
+        issue(R + 1);
+        T rsum;
+        if constexpr (RPL == 4) {
+            rsum = pair_sum_b4(pair_sum_b5(rs[0], rs[2]), pair_sum_b5(rs[1], rs[3]));
+        } else {
+            rsum = pair_sum_b5(rs[0], rs[1]);
+        }
+        rpart[R - Rb][wv][RPL * rq + g] = rsum;
+    }
+    T vav = T(0);
+#pragma unroll
+    for (int k = 0; k < NI; k++) vav += vc[k] * cacc[k];
+    T csum;
+    if constexpr (NI == 4) {
+        csum = quad_sum(pair_sum_b2(pair_sum_b3(cacc[0], cacc[2]), pair_sum_b3(cacc[1], cacc[3])));
+    } else {
+        const T u0_ = pair_sum_b4(cacc[0], cacc[4]), u1 = pair_sum_b4(cacc[1], cacc[5]);
+        const T u2 = pair_sum_b4(cacc[2], cacc[6]), u3 = pair_sum_b4(cacc[3], cacc[7]);
+        csum = quad_sum(pair_sum_b2(pair_sum_b3(u0_, u2), pair_sum_b3(u1, u3)));
+    }
+    {
+        const int c = c0 + RPL * ((lane >> 2) % NI) + g;
+        if ((lane & 3) == 0 && c >= t1 && c < n) unsafeAtomicAdd(&yacc[c], csum);
+    }
+    __syncthreads();
+    for (int t = wv; t < Re - Rb; t += 4) {
+        const T y = (rpart[t][0][lane] + rpart[t][1][lane]) + (rpart[t][2][lane] + rpart[t][3][lane]);
+        const int r = (Rb + t) * 64 + lane;
+        if (r >= t1 && r < n) {
+            unsafeAtomicAdd(&yacc[r], y);
+            vav += ubuf[slot_of(Rb + t)][lane] * y;
+        }
+    }
+    vav = block_sum256(vav, red);
+    if (tid == 0) unsafeAtomicAdd(vacc_s(w, b, slc) + (C * 7 + q) % SYTRD_VC, vav);
+}
+
+// Trailing orders at and below which the fused path is used (measured on
+// the N=2000 cluster reduction: above it the redundant row work of the
+// fused launch costs more than the finish launch it saves; in FP64 the
+// fused launch's registers leave one wavefront per SIMD).
+#define SYTRD_FUSED_KT 3
+template <typename T> struct SytrdFused;
+template <> struct SytrdFused<float> { static constexpr int max_order = 4000; };
+template <> struct SytrdFused<double> { static constexpr int max_order = 0; };
+template <typename T> struct ColWaves;
+template <> struct ColWaves<float> { static constexpr int value = 3; };
+template <> struct ColWaves<double> { static constexpr int value = 1; };
+template <typename T, int NBP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColWaves<T>::value)))
+void sytrd_col_kernel(SytrdWs<T> w, int i, int j, int Kt) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    if (i > n - 2 || i >= sytrd_tail_start<T>(n)) return;
+    const int b0 = (i + 1) >> 6;
+    const int nbk = (n + 63) >> 6;
+    const int C = b0 + blockIdx.y;
+    const int q = blockIdx.x;
+    if (C >= nbk || q >= (nbk - C + Kt - 1) / Kt) return;
+    col_item<T, NBP>(w, b, n, i, j, Kt, C, q);
+}
+
+// Finish of the last column c of a panel (panel column J), one workgroup per
+// 64-row block from the block of s = c + 1: stores v, w, the reflector, the
+// updated column s and its norm, and the column's d, e, tau.
+template <typename T, int NBP>
+__global__ __launch_bounds__(64) void sytrd_pfinish_kernel(SytrdWs<T> w, int c, int J) {
+    const int b = blockIdx.z;
+    const int n = w.ns[b];
+    if (c > n - 2 || c >= sytrd_tail_start<T>(n)) return;
+    const int s = c + 1;
+    const int nbk = (n + 63) >> 6;
+    const int R = (s >> 6) + blockIdx.x;
+    if (R >= nbk) return;
+    __shared__ T coef[SYTRD_NBP][4];
+    const int lane = threadIdx.x;
+    const int r = R * 64 + lane;
+    FinRow<T> fr;
+    fin_load(w, b, n, c, J, r, fr);
+    const FinScal<T> fs = fin_scalars(w, b, c, J, coef);
+    T v, wr, u;
+    fin_row(fs, coef, fr, r, s, n, v, wr, u);
+    T* A = w.A.at(b);
+    if (r < n) {
+        w.Vp[(long long)b * w.sP + r + (long long)J * w.ldp] = v;
+        w.Wp[(long long)b * w.sP + r + (long long)J * w.ldp] = wr;
+        if (r >= s) {
+            A[r + (long long)c * w.A.ld] = v;
+            col_s(w, b, s & 1)[r] = u;
+        }
+    }
+    T q2 = (r >= s + 2 && r < n) ? u * u : T(0);
+    q2 = wave_sum(q2);
+    if (lane == 0) unsafeAtomicAdd(norm_s(w, b, s % SYTRD_SLOTS), q2);
+    if (R == (s >> 6) && lane == 0) {
+        w.d[(long long)b * w.sD + c] = fs.dprev;
+        w.e[(long long)b * w.sD + c] = fs.beta;
+        w.tau[(long long)b * w.sD + c] = fs.tau;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -655,7 +1144,7 @@ void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
     const int C = b0 + blockIdx.y;
     const int q = blockIdx.x;
     // the norm slot of column i + 1 is filled by this column's finish phase
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) w.normacc[(long long)b * 2 + ((i + 1) & 1)] = T(0);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) w.normacc[(long long)b * SYTRD_SLOTS + (i + 1) % SYTRD_SLOTS] = T(0);
     if (C >= nbk || q >= (nbk - C + Kt - 1) / Kt) return;
     symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, nullptr);
 }
@@ -736,13 +1225,27 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
     constexpr int NBP = SYTRD_NBP;
     const bool timing = prof && prof->enabled && prof->launches && ns_host;
     const int nbk_max = w.nbk_max;
-    hipLaunchKernelGGL(sytrd_zero_norm_kernel<T>, dim3((2 * nbatch + 255) / 256), dim3(256), 0, st, w, nbatch);
+    // panels whose trailing order is at most fused_max run one launch per
+    // column (the fused path); larger ones the SYMV and finish launches
+    static const int env_max = [] {
+        const char* e = std::getenv("MBD_SYTRD_FUSED_MAXN");
+        return e ? std::atoi(e) : -1;
+    }();
+    const int fused_max = env_max >= 0 ? env_max : SytrdFused<T>::max_order;
+    hipLaunchKernelGGL(sytrd_zero_norm_kernel<T>, dim3((SYTRD_SLOTS * nbatch + 255) / 256), dim3(256), 0, st, w, nbatch);
     hipLaunchKernelGGL(sytrd_init_kernel<T>, dim3(nbk_max, 1, nbatch), dim3(256), 0, st, w);
     // panels up to the tail of the largest matrix (smaller ones drop out of
     // the per-column kernels at their own tail start)
     const int kend = sytrd_tail_start<T>(nmax);
     for (int k0 = 0; k0 < kend && k0 + 2 <= nmax; k0 += NBP) {
         const int k1 = std::min(k0 + NBP, nmax - 1);
+        // fused only where work items can be short (at most SYTRD_FUSED_KT
+        // tiles at the default target, so at most four row blocks to finish
+        // per item, one per wavefront): in batches of small matrices an item
+        // spans a whole strip.  The choice depends on the sizes only, not on
+        // the tuned targets; inside a fused panel the item length is capped.
+        const bool fused = nmax - k0 - 1 <= fused_max &&
+                           sytrd_kt(nbk_max - ((k0 + 1) >> 6), nbatch, 1536) <= SYTRD_FUSED_KT;
         {
             for (int i = k0; i < k1; i++) {
                 const int j = i - k0;
@@ -752,8 +1255,10 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                 // workgroup already; below it fewer, longer work items measured
                 // faster, so each range has its own tuned target
                 const int tgt = 4 * nbt >= 3 * nbk_max ? w.chunk_target : w.chunk_target_lo;
-                const int Kt = sytrd_kt(nbt, nbatch, tgt > 0 ? tgt : 1536);
+                const int Kt0 = sytrd_kt(nbt, nbatch, tgt > 0 ? tgt : 1536);
+                const int Kt = fused ? std::min(Kt0, SYTRD_FUSED_KT) : Kt0;
                 const int gx = (nbt + Kt - 1) / Kt;
+                auto kern = fused ? sytrd_col_kernel<T, NBP> : sytrd_symv_kernel<T, NBP>;
                 if (timing) {
                     double bb = 0;
                     for (int b = 0; b < nbatch; b++) {
@@ -761,14 +1266,19 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                         if (m > 0) bb += m * (m + 1) * 0.5 * sizeof(T);
                     }
                     hipEvent_t e0, e1;
-                    prof->pair(&e0, &e1, 0, bb);
-                    hipExtLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, e0, e1,
-                                          0, w, i, j, Kt);
+                    prof->pair(&e0, &e1, fused ? 8 : 0, bb);
+                    hipExtLaunchKernelGGL(kern, dim3(gx, nbt, nbatch), dim3(256), 0, st, e0, e1, 0, w, i, j, Kt);
                 } else {
-                    hipLaunchKernelGGL((sytrd_symv_kernel<T, NBP>), dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j,
-                                       Kt);
+                    hipLaunchKernelGGL(kern, dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j, Kt);
                 }
-                hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j);
+                if (!fused)
+                    hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j);
+            }
+            if (fused && k1 > k0) {
+                // the panel's last column is finished before the panel update
+                const int c = k1 - 1;
+                hipLaunchKernelGGL((sytrd_pfinish_kernel<T, NBP>), dim3(nbk_max - ((c + 1) >> 6), 1, nbatch), dim3(64),
+                                   0, st, w, c, c - k0);
             }
         }
         const int t0 = k0 + NBP;

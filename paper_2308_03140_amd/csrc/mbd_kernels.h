@@ -12,7 +12,7 @@
 // assembly, 3 Householder reduction, 4 divide and conquer, 5 back-transform,
 // 6 refinement, 7 energy, Q^{-1/2} and gradients.  `work` is the algorithmic
 // bytes (kind 0) or flops (kind 1) of the launch, 0 for phases.
-#define PROF_KINDS 8
+#define PROF_KINDS 10
 struct LaunchProfiler {
     bool enabled = false;
     bool launches = true;  // per-launch records (kinds 0, 1); phases are always recorded when enabled
@@ -97,9 +97,10 @@ struct PhaseTimer {
     ~PhaseTimer() { stop(); }
 };
 
-#define SYTRD_NBP 32
+#define SYTRD_NBP 32       // Householder panel width
 #define SYTRD_YCOPIES 4    // atomic accumulator copies (y, panel products; 8 -> 4 measured faster, 2 no better)
-#define SYTRD_VCOPIES 256  // atomic accumulator copies (v^T A v)     // Householder panel width
+#define SYTRD_VCOPIES 256  // atomic accumulator copies (v^T A v)
+#define SYTRD_SLOTS 3      // accumulator slots: column i accumulates into slot i % 3
 #define ORMTR_NBB 64     // reflectors per compact-WY block in the back-transform
 #define ORMTR_CHUNK 512  // rows per split-K chunk of V^T X
 
@@ -110,11 +111,11 @@ struct SytrdWs {
     const int* ns;     // per-matrix order (device)
     int nmax, nbk_max;
     T* Vp; T* Wp; int ldp; long long sP;   // panels, column-major nmax x SYTRD_NBP
-    T* colbuf; long long sC;               // updated current column (rows padded to 64 nbk_max)
-    T* normacc;                            // ||col(i+2:n)||^2, [2 parities] per matrix
-    T* yacc; long long sY;                 // y = A v, [2 parities][SYTRD_YCOPIES][nmax] per matrix
-    T* sacc; long long sS;                 // W^T v, V^T v, [2][SYTRD_YCOPIES][2*NBP]
-    T* vacc;                               // v^T A v, [2][SYTRD_VCOPIES] per matrix
+    T* colbuf; long long sC;               // updated current column, [2 slots] of sC (rows padded to 64 nbk_max)
+    T* normacc;                            // ||col(i+2:n)||^2, [SYTRD_SLOTS] per matrix
+    T* yacc; long long sY;                 // y = A v, [SYTRD_SLOTS][SYTRD_YCOPIES][nmax] per matrix
+    T* sacc; long long sS;                 // W^T v, V^T v, [SYTRD_SLOTS][SYTRD_YCOPIES][2*NBP]
+    T* vacc;                               // v^T A v, [SYTRD_SLOTS][SYTRD_VCOPIES] per matrix
     T* d; T* e; T* tau; long long sD;      // outputs
     int chunk_target;                      // SYMV workgroups per launch, trailing sizes in the upper quarter (tuned)
     int chunk_target_lo;                   // the same below it (tuned)

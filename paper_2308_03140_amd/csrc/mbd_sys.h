@@ -98,11 +98,18 @@ void mbd_freq_terms_launch(hipStream_t st, const int* ns, int nmat, const double
 // self-consistent screening (see k_scs.hip)
 void scs_assemble_launch(hipStream_t st, const SysDesc* sd, int N, const double* om, const double* u, int nf,
                          MatBatch<double> A, unsigned* status);
-void scs_invhalf_launch(hipStream_t st, const int* ns, int nmax, int nf, const double* lam, long long sL, double* sc,
-                        unsigned* status);
-void scs_contract_launch(hipStream_t st, MatBatch<double> M, int N, int nf, double* abar);
+void scs_rhs_launch(hipStream_t st, int N, int nf, const double* w, double* R);
+void scs_contract_launch(hipStream_t st, int N, int nf, const double* V, double* abar);
 void scs_params_launch(hipStream_t st, const SysDesc* sd, int N, const double* abar, const double* wq, int nf,
                        double* out);
+void scs_weights_launch(hipStream_t st, int N, int nf, const double* par, const double* abar, const double* wq,
+                        const double* ga, const double* gw, const double* gv, double* w);
 void scs_grad_launch(hipStream_t st, const SysDesc* sd, int N, int nf, const double* om, const double* u,
-                     const double* par, const double* abar, const double* wq, const double* ga, const double* gw,
-                     const double* gv, double* w, MatBatch<double> M, double* UV, double* grad);
+                     const double* U, const double* V, double* UV, double* grad);
+// batched Cholesky (k_chol.hip): factor in place (lower), diagonal-block
+// inverses in Linv (chol_linv_stride(n) per matrix); solves with three
+// right-hand sides, layout [nbatch][n][3] with per-matrix stride sR
+long long chol_linv_stride(int n);
+void chol_factor_launch(hipStream_t st, MatBatch<double> A, int n, int nbatch, double* Linv, unsigned* status);
+void chol_solve_launch(hipStream_t st, MatBatch<double> A, int n, int nbatch, const double* Linv, double* R, double* Y,
+                       double* X, long long sR);

@@ -202,3 +202,49 @@ def test_eigh_values_only_structured(ctx):
     w, _ = T.eigh(ctx, torch.tensor(As, device="cuda"), vectors=False)
     for b in range(3):
         _check(As[b], w[b].cpu().numpy(), None, 1e-12)
+
+
+_PATH_CHILD = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import gen
+import oracle
+from paper_2308_03140_amd import torch_api as T
+out = []
+for dtype, tol in (("float64", 1e-12), ("float32", 3e-5)):
+    ctx = T.Context(0, "fp64")
+    for n in (300, 700):
+        A = gen.random_symmetric(7000 + n, n)
+        w, Z = T.eigh(ctx, torch.tensor(A, device="cuda", dtype=getattr(torch, dtype)))
+        torch.cuda.synchronize()
+        w = w.double().cpu().numpy(); Z = Z.double().cpu().numpy()
+        nrm = max(1.0, np.abs(A).sum(axis=1).max())
+        ev = np.abs(w - oracle.jacobi(A, vectors=False)).max() / nrm
+        res = np.abs(A @ Z - Z * w).max() / nrm
+        orth = np.abs(Z.T @ Z - np.eye(n)).max()
+        ok = ev <= tol and res <= tol and orth <= tol * max(1, n / 100)
+        print("%s n=%d ev=%.2e res=%.2e orth=%.2e %s" % (dtype, n, ev, res, orth, "ok" if ok else "FAIL"), flush=True)
+        out.append(ok)
+    ctx.close()
+sys.exit(0 if all(out) else 1)
+"""
+
+
+@pytest.mark.parametrize("max_order", [0, 1000000])
+def test_eigh_reduction_paths(max_order):
+    """Both per-column paths of the reduction in both precisions: the fused
+    launch everywhere (FP64 included, which the default never fuses) and the
+    SYMV + finish launches everywhere (FP32 included), chosen through the
+    library's MBD_SYTRD_FUSED_MAXN override, which is read once per process,
+    hence the child process."""
+    import os
+    import subprocess
+    _note("reduction paths, fused max order %d" % max_order)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, MBD_SYTRD_FUSED_MAXN=str(max_order))
+    r = subprocess.run([sys.executable, "-c", _PATH_CHILD, root], env=env, capture_output=True, text=True,
+                       timeout=110)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr[-2000:]
