@@ -11,7 +11,8 @@
 //                    LDS and inverts its factor, L11^-1, kept for the
 //                    panel solve and the triangular solves;
 //   panel            L21 = A21 L11^-T as a matrix-core product, in place;
-//   trailing update  A22 -= L21 L21^T on the lower tiles (matrix cores).
+//   trailing update  A22 -= L21 L21^T on the lower tiles (matrix cores),
+//                    once per superpanel of two panels (K = 128).
 // The triangular solves go block row by block row, one launch per block:
 // every workgroup forms the block's solution from the (final) residual and
 // L11^-1, the first stores it, the others update the residual of their own
@@ -29,6 +30,9 @@
 // ---------------------------------------------------------------------------
 // diagonal block: factor, invert the factor; identity padding past n
 // ---------------------------------------------------------------------------
+// One workgroup per matrix, the block in LDS; thread (i, j0) = (tid & 63,
+// tid >> 6) works on row i and columns j0, j0 + 4, ...  (A single-wavefront
+// variant without barriers, the row in LDS, measured 171 us against 100 us.)
 __global__ __launch_bounds__(256) void chol_diag_kernel(MatBatch<double> A, double* Linv, long long sLi, int n,
                                                          int k0, unsigned* status) {
     __shared__ double L[CHOL_NB][CHOL_NB + 1];
@@ -37,9 +41,21 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(MatBatch<double> A, doub
     const int w = min(CHOL_NB, n - k0);
     double* Ab = A.at(b) + k0 + (long long)k0 * A.ld;
     const long long ld = A.ld;
-    for (int t = tid; t < CHOL_NB * CHOL_NB; t += 256) {
-        const int i = t & (CHOL_NB - 1), j = t / CHOL_NB;
-        L[i][j] = (i < w && j < w) ? (i >= j ? Ab[i + j * ld] : 0.0) : (i == j ? 1.0 : 0.0);
+    constexpr int PER = CHOL_NB * CHOL_NB / 256;
+    const int ri = tid & (CHOL_NB - 1), j0 = tid >> 6;
+    {
+        // all 16 loads in flight together (rows and columns clamped, values masked)
+        double v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int j = j0 + 4 * u;
+            v[u] = Ab[min(ri, w - 1) + (long long)min(j, w - 1) * ld];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int j = j0 + 4 * u;
+            L[ri][j] = (ri < w && j < w) ? (ri >= j ? v[u] : 0.0) : (ri == j ? 1.0 : 0.0);
+        }
     }
     __syncthreads();
     bool bad = false;
@@ -50,36 +66,46 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(MatBatch<double> A, doub
         const double s = nb ? 1.0 : sqrt(d);
         __syncthreads();
         if (tid == 0) L[j][j] = s;
-        for (int i = j + 1 + tid; i < CHOL_NB; i += 256) L[i][j] /= s;
+        if (tid > j && tid < CHOL_NB) L[tid][j] /= s;
         __syncthreads();
-        for (int t = tid; t < CHOL_NB * CHOL_NB; t += 256) {
-            const int i = t & (CHOL_NB - 1), l = t / CHOL_NB;
-            if (l > j && i >= l) L[i][l] -= L[i][j] * L[l][j];
+        // trailing update L(i, l) -= L(i, j) L(l, j), j < l <= i
+        const double lij = L[ri][j];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int l = j0 + 4 * u;
+            if (l > j && ri >= l) L[ri][l] -= lij * L[l][j];
         }
         __syncthreads();
     }
     if (bad && tid == 0) atomicOr(status, MBD_ST_COLLAPSE);
-    // X = L^-1 (lower), one column per thread: X(c,c) = 1/L(c,c),
-    // X(i,c) = -(sum_{l=c}^{i-1} L(i,l) X(l,c)) / L(i,i)
-    if (tid < CHOL_NB) {
-        const int c = tid;
-        for (int i = 0; i < c; i++) X[i][c] = 0.0;
-        X[c][c] = 1.0 / L[c][c];
-        for (int i = c + 1; i < CHOL_NB; i++) {
-            double s = 0.0;
-            for (int l = c; l < i; l++) s += L[i][l] * X[l][c];
-            X[i][c] = -s / L[i][i];
+    // X = L^-1 row by row: X(r, c) = -(sum_{l=c}^{r-1} L(r,l) X(l,c)) / L(r,r)
+    // for c < r; four threads per column c split the sum over l
+    {
+        const int c = tid >> 2, part = tid & 3;
+        if (part == 0) {
+            for (int r = 0; r < CHOL_NB; r++) X[r][c] = r == c ? 1.0 / L[c][c] : 0.0;
+        }
+        __syncthreads();
+        for (int r = 1; r < CHOL_NB; r++) {
+            double sacc = 0.0;
+            if (c < r)
+                for (int l = c + part; l < r; l += 4) sacc += L[r][l] * X[l][c];
+            sacc += __shfl_xor(sacc, 1, 64);
+            sacc += __shfl_xor(sacc, 2, 64);
+            if (c < r && part == 0) X[r][c] = -sacc / L[r][r];
+            __syncthreads();
         }
     }
-    __syncthreads();
-    for (int t = tid; t < CHOL_NB * CHOL_NB; t += 256) {
-        const int i = t & (CHOL_NB - 1), j = t / CHOL_NB;
-        if (i < w && j < w && i >= j) Ab[i + j * ld] = L[i][j];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int j = j0 + 4 * u;
+        if (ri < w && j < w && ri >= j) Ab[ri + j * ld] = L[ri][j];
     }
     double* Xo = Linv + (long long)b * sLi + (long long)(k0 / CHOL_NB) * CHOL_NB * CHOL_NB;
-    for (int t = tid; t < CHOL_NB * CHOL_NB; t += 256) {
-        const int i = t & (CHOL_NB - 1), j = t / CHOL_NB;
-        Xo[i + j * CHOL_NB] = X[i][j];  // column-major, leading dimension 64
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int j = j0 + 4 * u;
+        Xo[ri + j * CHOL_NB] = X[ri][j];  // column-major, leading dimension 64
     }
 }
 
@@ -112,81 +138,98 @@ struct CholPanelProb {
 };
 
 // ---------------------------------------------------------------------------
-// trailing update: A22 -= L21 L21^T on the lower tiles (elements on and below
-// the diagonal), TS x TS tiles in the XCD-aware banded order
+// trailing update: A22 -= L21 L21^T with L21 the kw columns from k0 (64 or a
+// superpanel of 128), on the elements on and below the diagonal of the
+// block from t0 = k0 + kw: all lower tiles (XCD-aware banded order), or
+// (thin) only the first ncols columns, one tile column
 // ---------------------------------------------------------------------------
 template <int TS>
 struct CholSyrkProb {
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = true;
     MatBatch<double> A;
-    int k0, m;  // panel start, trailing order m = n - k0 - 64
-    int tiles;
+    int k0, kw, m, ncols;  // m = n - k0 - kw trailing rows
+    int tiles, thin;
     __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
         t.batch = bz;
         int ti, tj;
-        band_lower_tile(xcd_virtual(bx, gridDim.x), tiles, ti, tj);
-        t.m0 = ti * TS; t.n0 = tj * TS; t.K = CHOL_NB;
-        return t.m0 < m && t.n0 < m;
+        if (thin) { ti = bx; tj = 0; }
+        else band_lower_tile(xcd_virtual(bx, gridDim.x), tiles, ti, tj);
+        t.m0 = ti * TS; t.n0 = tj * TS; t.K = kw;
+        return t.m0 < m && t.n0 < ncols;
     }
     __device__ double a(const GemmTile& t, int r, int k) const {
-        if (r >= m) return 0.0;
-        return A.at(t.batch)[(k0 + CHOL_NB + r) + (long long)(k0 + k) * A.ld];
+        if (r >= m || k >= kw) return 0.0;
+        return A.at(t.batch)[(k0 + kw + r) + (long long)(k0 + k) * A.ld];
     }
     __device__ double b(const GemmTile& t, int k, int c) const {
-        if (c >= m) return 0.0;
-        return A.at(t.batch)[(k0 + CHOL_NB + c) + (long long)(k0 + k) * A.ld];
+        if (c >= ncols || k >= kw) return 0.0;
+        return A.at(t.batch)[(k0 + kw + c) + (long long)(k0 + k) * A.ld];
     }
     __device__ void store(const GemmTile& t, int r, int c, double v) const {
-        if (r >= m || c > r) return;
-        A.at(t.batch)[(k0 + CHOL_NB + r) + (long long)(k0 + CHOL_NB + c) * A.ld] -= v;
+        if (r >= m || c > r || c >= ncols) return;
+        A.at(t.batch)[(k0 + kw + r) + (long long)(k0 + kw + c) * A.ld] -= v;
     }
 };
 
 // ---------------------------------------------------------------------------
 // triangular solves; right-hand sides row-major [n][CHOL_NR] per matrix
 // ---------------------------------------------------------------------------
+// 64 x 64 block of a column-major matrix into LDS, all loads in flight
+// together (rows and columns clamped, values outside masked to zero)
+__device__ __forceinline__ void chol_stage(double (*S)[CHOL_NB + 1], const double* src, long long ld, int rows,
+                                           int cols) {
+    constexpr int PER = CHOL_NB * CHOL_NB / 256;
+    const int i = threadIdx.x & (CHOL_NB - 1), j0 = threadIdx.x >> 6;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int j = j0 + 4 * u;
+        v[u] = src[min(i, rows - 1) + (long long)min(j, cols - 1) * ld];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int j = j0 + 4 * u;
+        S[i][j] = (i < rows && j < cols) ? v[u] : 0.0;
+    }
+}
+
 // forward step for block kb: y_kb = X_kb r_kb; workgroup 0 stores it, workgroup
 // j >= 1 updates the residual of block kb + j: r -= L(kb + j, kb) y_kb
 __global__ __launch_bounds__(256) void chol_fwd_kernel(MatBatch<double> A, const double* Linv, long long sLi, int n,
                                                         int kb, double* R, double* Y, long long sR) {
     __shared__ double Xs[CHOL_NB][CHOL_NB + 1];
+    __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
     __shared__ double rs[CHOL_NB][CHOL_NR];
     __shared__ double ys[CHOL_NB][CHOL_NR];
     const int b = blockIdx.z, j = blockIdx.x, tid = threadIdx.x;
-    const int r0 = kb * CHOL_NB;
-    const double* Xg = Linv + (long long)b * sLi + (long long)kb * CHOL_NB * CHOL_NB;
+    const int r0 = kb * CHOL_NB, q0 = (kb + j) * CHOL_NB;
     double* Rb = R + (long long)b * sR;
-    for (int t = tid; t < CHOL_NB * CHOL_NB; t += 256) Xs[t & (CHOL_NB - 1)][t / CHOL_NB] = Xg[t];
-    for (int t = tid; t < CHOL_NB * CHOL_NR; t += 256) {
-        const int i = t / CHOL_NR, c = t % CHOL_NR;
-        rs[i][c] = r0 + i < n ? Rb[(long long)(r0 + i) * CHOL_NR + c] : 0.0;
-    }
+    const double rv = tid < CHOL_NB * CHOL_NR && r0 + tid / CHOL_NR < n
+                          ? Rb[(long long)r0 * CHOL_NR + tid] : 0.0;
+    chol_stage(Xs, Linv + (long long)b * sLi + (long long)kb * CHOL_NB * CHOL_NB, CHOL_NB, CHOL_NB, CHOL_NB);
+    if (j > 0) chol_stage(Ls, A.at(b) + q0 + (long long)r0 * A.ld, A.ld, min(CHOL_NB, n - q0), min(CHOL_NB, n - r0));
+    if (tid < CHOL_NB * CHOL_NR) rs[tid / CHOL_NR][tid % CHOL_NR] = rv;
     __syncthreads();
     if (tid < CHOL_NB * CHOL_NR) {
         const int i = tid / CHOL_NR, c = tid % CHOL_NR;
         double s = 0.0;
+#pragma unroll 8
         for (int l = 0; l <= i; l++) s += Xs[i][l] * rs[l][c];
         ys[i][c] = s;
     }
     __syncthreads();
     if (j == 0) {
-        for (int t = tid; t < CHOL_NB * CHOL_NR; t += 256) {
-            const int i = t / CHOL_NR, c = t % CHOL_NR;
-            if (r0 + i < n) Y[(long long)b * sR + (long long)(r0 + i) * CHOL_NR + c] = ys[i][c];
-        }
+        if (tid < CHOL_NB * CHOL_NR && r0 + tid / CHOL_NR < n)
+            Y[(long long)b * sR + (long long)r0 * CHOL_NR + tid] = ys[tid / CHOL_NR][tid % CHOL_NR];
         return;
     }
-    const int q0 = (kb + j) * CHOL_NB;
-    const double* Ab = A.at(b);
     if (tid < CHOL_NB * CHOL_NR) {
-        const int i = tid % CHOL_NB, c = tid / CHOL_NB;
-        const int q = q0 + i;
-        if (q < n) {
-            double s = 0.0;
-            for (int l = 0; l < CHOL_NB && r0 + l < n; l++) s += Ab[q + (long long)(r0 + l) * A.ld] * ys[l][c];
-            Rb[(long long)q * CHOL_NR + c] -= s;
-        }
+        const int i = tid / CHOL_NR, c = tid % CHOL_NR;
+        double s = 0.0;
+#pragma unroll 8
+        for (int l = 0; l < CHOL_NB; l++) s += Ls[i][l] * ys[l][c];
+        if (q0 + i < n) Rb[(long long)(q0 + i) * CHOL_NR + c] -= s;
     }
 }
 
@@ -195,40 +238,38 @@ __global__ __launch_bounds__(256) void chol_fwd_kernel(MatBatch<double> A, const
 __global__ __launch_bounds__(256) void chol_bwd_kernel(MatBatch<double> A, const double* Linv, long long sLi, int n,
                                                         int kb, double* Yr, double* Xo, long long sR) {
     __shared__ double Xs[CHOL_NB][CHOL_NB + 1];
+    __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
     __shared__ double rs[CHOL_NB][CHOL_NR];
     __shared__ double xs[CHOL_NB][CHOL_NR];
     const int b = blockIdx.z, j = blockIdx.x, tid = threadIdx.x;
-    const int r0 = kb * CHOL_NB;
-    const double* Xg = Linv + (long long)b * sLi + (long long)kb * CHOL_NB * CHOL_NB;
+    const int r0 = kb * CHOL_NB, q0 = (kb - j) * CHOL_NB;
     double* Yb = Yr + (long long)b * sR;
-    for (int t = tid; t < CHOL_NB * CHOL_NB; t += 256) Xs[t & (CHOL_NB - 1)][t / CHOL_NB] = Xg[t];
-    for (int t = tid; t < CHOL_NB * CHOL_NR; t += 256) {
-        const int i = t / CHOL_NR, c = t % CHOL_NR;
-        rs[i][c] = r0 + i < n ? Yb[(long long)(r0 + i) * CHOL_NR + c] : 0.0;
-    }
+    const double rv = tid < CHOL_NB * CHOL_NR && r0 + tid / CHOL_NR < n
+                          ? Yb[(long long)r0 * CHOL_NR + tid] : 0.0;
+    chol_stage(Xs, Linv + (long long)b * sLi + (long long)kb * CHOL_NB * CHOL_NB, CHOL_NB, CHOL_NB, CHOL_NB);
+    // L(kb, kb - j): rows r0.., columns q0.. (below the diagonal)
+    if (j > 0) chol_stage(Ls, A.at(b) + r0 + (long long)q0 * A.ld, A.ld, min(CHOL_NB, n - r0), CHOL_NB);
+    if (tid < CHOL_NB * CHOL_NR) rs[tid / CHOL_NR][tid % CHOL_NR] = rv;
     __syncthreads();
     if (tid < CHOL_NB * CHOL_NR) {
         const int i = tid / CHOL_NR, c = tid % CHOL_NR;
         double s = 0.0;
+#pragma unroll 8
         for (int l = i; l < CHOL_NB; l++) s += Xs[l][i] * rs[l][c];
         xs[i][c] = s;
     }
     __syncthreads();
     if (j == 0) {
-        for (int t = tid; t < CHOL_NB * CHOL_NR; t += 256) {
-            const int i = t / CHOL_NR, c = t % CHOL_NR;
-            if (r0 + i < n) Xo[(long long)b * sR + (long long)(r0 + i) * CHOL_NR + c] = xs[i][c];
-        }
+        if (tid < CHOL_NB * CHOL_NR && r0 + tid / CHOL_NR < n)
+            Xo[(long long)b * sR + (long long)r0 * CHOL_NR + tid] = xs[tid / CHOL_NR][tid % CHOL_NR];
         return;
     }
-    const int q0 = (kb - j) * CHOL_NB;
-    const double* Ab = A.at(b);
     if (tid < CHOL_NB * CHOL_NR) {
-        const int i = tid % CHOL_NB, c = tid / CHOL_NB;
-        const int q = q0 + i;
+        const int i = tid / CHOL_NR, c = tid % CHOL_NR;
         double s = 0.0;
-        for (int l = 0; l < CHOL_NB && r0 + l < n; l++) s += Ab[(r0 + l) + (long long)q * A.ld] * xs[l][c];
-        Yb[(long long)q * CHOL_NR + c] -= s;
+#pragma unroll 8
+        for (int l = 0; l < CHOL_NB; l++) s += Ls[l][i] * xs[l][c];
+        Yb[(long long)(q0 + i) * CHOL_NR + c] -= s;
     }
 }
 
@@ -237,28 +278,47 @@ __global__ __launch_bounds__(256) void chol_bwd_kernel(MatBatch<double> A, const
 // ---------------------------------------------------------------------------
 long long chol_linv_stride(int n) { return (long long)((n + CHOL_NB - 1) / CHOL_NB) * CHOL_NB * CHOL_NB; }
 
+static void chol_syrk(hipStream_t st, MatBatch<double> A, int nbatch, int k0, int kw, int m, bool thin) {
+    if (!thin && m >= GEMM_TS128_MIN_ORDER) {
+        typedef Gemm128Shape<double> S;
+        CholSyrkProb<128> ps;
+        ps.A = A; ps.k0 = k0; ps.kw = kw; ps.m = m; ps.ncols = m; ps.thin = 0; ps.tiles = (m + 127) / 128;
+        hipLaunchKernelGGL((gemm_mfma_kernel<double, CholSyrkProb<128>, 128, 128, S::BK, S::WM, S::WN>),
+                           dim3(ps.tiles * (ps.tiles + 1) / 2, 1, nbatch), dim3(64 * S::WM * S::WN), 0, st, ps);
+        return;
+    }
+    CholSyrkProb<64> ps;
+    ps.A = A; ps.k0 = k0; ps.kw = kw; ps.m = m; ps.thin = thin ? 1 : 0;
+    ps.ncols = thin ? std::min(m, CHOL_NB) : m;
+    ps.tiles = (m + 63) / 64;
+    const int grid = thin ? ps.tiles : ps.tiles * (ps.tiles + 1) / 2;
+    hipLaunchKernelGGL((gemm_mfma_kernel<double, CholSyrkProb<64>>), dim3(grid, 1, nbatch), dim3(256), 0, st, ps);
+}
+
+static void chol_panel(hipStream_t st, MatBatch<double> A, int n, int nbatch, double* Linv, long long sLi, int k0,
+                       unsigned* status, int& rows) {
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(nbatch), dim3(256), 0, st, A, Linv, sLi, n, k0, status);
+    rows = n - k0 - CHOL_NB;
+    if (rows <= 0) return;
+    CholPanelProb pp;
+    pp.A = A; pp.Linv = Linv; pp.sLi = sLi; pp.k0 = k0; pp.rows = rows;
+    hipLaunchKernelGGL((gemm_mfma_kernel<double, CholPanelProb>), dim3((rows + CHOL_NB - 1) / CHOL_NB, 1, nbatch),
+                       dim3(256), 0, st, pp);
+}
+
+// Superpanels of 128 columns: the first 64-column panel, its update of the
+// second panel's columns only, the second panel, then one trailing update
+// with both (K = 128: twice the flops per byte of a 64-deep update).
 void chol_factor_launch(hipStream_t st, MatBatch<double> A, int n, int nbatch, double* Linv, unsigned* status) {
     const long long sLi = chol_linv_stride(n);
-    for (int k0 = 0; k0 < n; k0 += CHOL_NB) {
-        hipLaunchKernelGGL(chol_diag_kernel, dim3(nbatch), dim3(256), 0, st, A, Linv, sLi, n, k0, status);
-        const int rows = n - k0 - CHOL_NB;
-        if (rows <= 0) break;
-        CholPanelProb pp;
-        pp.A = A; pp.Linv = Linv; pp.sLi = sLi; pp.k0 = k0; pp.rows = rows;
-        hipLaunchKernelGGL((gemm_mfma_kernel<double, CholPanelProb>), dim3((rows + CHOL_NB - 1) / CHOL_NB, 1, nbatch),
-                           dim3(256), 0, st, pp);
-        if (rows >= GEMM_TS128_MIN_ORDER) {
-            typedef Gemm128Shape<double> S;
-            CholSyrkProb<128> ps;
-            ps.A = A; ps.k0 = k0; ps.m = rows; ps.tiles = (rows + 127) / 128;
-            hipLaunchKernelGGL((gemm_mfma_kernel<double, CholSyrkProb<128>, 128, 128, S::BK, S::WM, S::WN>),
-                               dim3(ps.tiles * (ps.tiles + 1) / 2, 1, nbatch), dim3(64 * S::WM * S::WN), 0, st, ps);
-        } else {
-            CholSyrkProb<64> ps;
-            ps.A = A; ps.k0 = k0; ps.m = rows; ps.tiles = (rows + 63) / 64;
-            hipLaunchKernelGGL((gemm_mfma_kernel<double, CholSyrkProb<64>>), dim3(ps.tiles * (ps.tiles + 1) / 2, 1, nbatch),
-                               dim3(256), 0, st, ps);
-        }
+    for (int k0 = 0; k0 < n; k0 += 2 * CHOL_NB) {
+        int rows1, rows2;
+        chol_panel(st, A, n, nbatch, Linv, sLi, k0, status, rows1);
+        if (rows1 <= 0) break;
+        chol_syrk(st, A, nbatch, k0, CHOL_NB, rows1, true);
+        chol_panel(st, A, n, nbatch, Linv, sLi, k0 + CHOL_NB, status, rows2);
+        if (rows2 <= 0) break;
+        chol_syrk(st, A, nbatch, k0, 2 * CHOL_NB, rows2, false);
     }
 }
 
