@@ -272,6 +272,17 @@ mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
  * phases only, without timing events (which would slow every launch): the
  * stream is synchronised at each phase boundary and the host clock read. */
 mbd_status mbd_set_profiling(mbd_ctx *ctx, int enable);
+
+/* Host-only self-check of the divide-and-conquer workspace for matrices of
+ * order <= n_max (no device needed): FP32 merges of order 2048 and more
+ * gather their operands into buffers of ldz * n_max + 64 elements per matrix
+ * (ldz = n_max rounded up to 64).  *needed gets the furthest element, from a
+ * matrix's base, that the gather and the split product touch (0 when no such
+ * merge exists), *allocated the buffer size.  Returns MBD_OK if the one fits
+ * the other, MBD_ERR_UNSUPPORTED if not (the eigensolver refuses such an
+ * order with the same code), MBD_ERR_INVALID_ARGUMENT for n_max < 1 or NULL
+ * outputs. */
+mbd_status mbd_check_dc_buffers(int32_t n_max, int64_t *needed, int64_t *allocated);
 mbd_status mbd_get_profile(mbd_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, double *work);
 
 /* (code, origin, message) of the last error on the context; returns code.

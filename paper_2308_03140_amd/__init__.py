@@ -21,7 +21,7 @@ __all__ = [n for n in dir(_abi) if n.startswith("MBD_")] + [
     "MbdSystem", "MbdResult", "lib", "library_path",
     "mbd_create", "mbd_destroy", "mbd_set_stream", "mbd_evaluate", "mbd_evaluate_batch",
     "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error", "mbd_set_profiling",
-    "mbd_get_profile",
+    "mbd_get_profile", "mbd_check_dc_buffers",
 ]
 
 mbd_create = _abi.mbd_create
@@ -35,3 +35,4 @@ mbd_load_tuning = _abi.mbd_load_tuning
 mbd_last_error = _abi.mbd_last_error
 mbd_set_profiling = _abi.mbd_set_profiling
 mbd_get_profile = _abi.mbd_get_profile
+mbd_check_dc_buffers = _abi.mbd_check_dc_buffers

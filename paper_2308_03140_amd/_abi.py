@@ -97,11 +97,13 @@ def lib():
         L.mbd_get_profile.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         L.mbd_last_error.argtypes = [_P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_char_p)]
+        L.mbd_check_dc_buffers.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int64)]
         for f in ("mbd_create", "mbd_destroy", "mbd_set_stream", "mbd_evaluate", "mbd_evaluate_noalloc", "mbd_ts_evaluate",
                   "mbd_freq_evaluate", "mbd_rsscs_evaluate",
                   "mbd_evaluate_batch",
                   "mbd_eigh", "mbd_autotune", "mbd_load_tuning", "mbd_last_error", "mbd_set_profiling",
-                  "mbd_get_profile"):
+                  "mbd_get_profile", "mbd_check_dc_buffers"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -162,14 +164,25 @@ def mbd_load_tuning(ctx, path):
 
 
 def mbd_set_profiling(ctx, enable):
-    return lib().mbd_set_profiling(ctx, int(bool(enable)))
+    """enable: 0 off, 1 launch and phase events, 2 phases only (host clock)."""
+    return lib().mbd_set_profiling(ctx, int(enable))
 
 
 def mbd_get_profile(ctx, kind):
-    """Returns (status, total_ms, launches, work) for launch kind 0 (SYMV) or 1 (SYR2K)."""
+    """Returns (status, total_ms, launches, work) for one profiling kind: 0 SYMV
+    launches, 1 SYR2K launches, 2..7 the evaluation phases, 8 fused per-column
+    launches, 9 the screening stage of MBD@rsSCS (see include/mbd.h)."""
     ms = ctypes.c_double(); n = ctypes.c_int64(); w = ctypes.c_double()
     st = lib().mbd_get_profile(ctx, int(kind), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w))
     return st, ms.value, n.value, w.value
+
+
+def mbd_check_dc_buffers(n_max):
+    """(status, needed, allocated): host-only check of the divide-and-conquer
+    gather buffers for matrices of order <= n_max."""
+    need = ctypes.c_int64(); have = ctypes.c_int64()
+    st = lib().mbd_check_dc_buffers(int(n_max), ctypes.byref(need), ctypes.byref(have))
+    return st, need.value, have.value
 
 
 def mbd_last_error(ctx):

@@ -246,6 +246,8 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     // FP32 merges of 2048 and more (which exist once the order exceeds half
     // of that) take the split product on gathered operands
     if (sizeof(T) == 4 && 2 * nmax > GEMM_TS128_MIN_ORDER) {
+        if (stedc_split_extent(nmax, ldz) > sZ + 64)
+            return fail(c, MBD_ERR_UNSUPPORTED, "eigensolver", "split-merge operands exceed their buffers");
         dw.GA0 = wsT<T>(c, "GA0" + t, (size_t)sZ * nbatch + 64);
         dw.GA1 = wsT<T>(c, "GA1" + t, (size_t)sZ * nbatch + 64);
         dw.GB0 = wsT<T>(c, "GB0" + t, (size_t)sZ * nbatch + 64);
@@ -1354,6 +1356,14 @@ mbd_status mbd_load_tuning(mbd_ctx* c, const char* path) {
     if (!path || !read_tuning(c, path))
         return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_load_tuning", "cannot read tuning table");
     return MBD_OK;
+}
+
+mbd_status mbd_check_dc_buffers(int32_t n_max, int64_t* needed, int64_t* allocated) {
+    if (n_max < 1 || !needed || !allocated) return MBD_ERR_INVALID_ARGUMENT;
+    const long long ldz = round_up(n_max, 64);
+    *allocated = ldz * n_max + 64;
+    *needed = 2 * n_max > GEMM_TS128_MIN_ORDER ? stedc_split_extent(n_max, ldz) : 0;
+    return *needed <= *allocated ? MBD_OK : MBD_ERR_UNSUPPORTED;
 }
 
 mbd_status mbd_set_profiling(mbd_ctx* c, int enable) {

@@ -823,6 +823,33 @@ __global__ __launch_bounds__(256) void stedc_final_kernel(StedcWs<T> w) {
     w.w_out[(long long)b * w.sW + p] = (T)(w.D[(long long)b * w.sV + p] * w.scale[b]);
 }
 
+// Host check of the gathered split-merge operands (FP32 merges of order
+// GEMM_TS128_MIN_ORDER and more) against their buffers of
+// nbatch * stride + 64 elements: the furthest element, counted from a
+// matrix's base, that stedc_gather_merge_kernel writes and the split product
+// reads, over every merge of every level, with the deflation counts at their
+// bounds (K, kt, kb <= merge order k).  Writes (column o + x, row o + r):
+// x < K, r < k; reads of B: rows o + q .. o + q + 3 for q up to the 32-deep
+// slabs' end, ceil32(K) - 4, in column o + min(jj, K - 1).  Returns the
+// element count needed past the last matrix's base.
+long long stedc_split_extent(int nmax, long long ld) {
+    int L = 0;
+    while ((1 << L) < nmax) L++;
+    long long far = 0;
+    for (int lev = 1; lev <= L; lev++) {
+        if ((1 << lev) < GEMM_TS128_MIN_ORDER) continue;
+        for (int o = 0; o < nmax; o += 1 << lev) {
+            const int k = std::min(1 << lev, nmax - o), k1 = std::min(1 << (lev - 1), nmax - o);
+            if (k <= k1) continue;  // inactive merge
+            const int K = k;
+            const long long col = (long long)(o + K - 1) * ld + o;
+            far = std::max(far, col + K);                     // GB0/GB1/GA writes, GA reads
+            far = std::max(far, col + (K + 31) / 32 * 32);    // B reads, 16 bytes at a time
+        }
+    }
+    return far;
+}
+
 template <typename T>
 int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     const int gpos = (nmax + 255) / 256;

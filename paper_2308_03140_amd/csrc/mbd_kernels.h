@@ -123,6 +123,9 @@ struct SytrdWs {
 template <typename T>
 void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, const int* ns_host,
                   LaunchProfiler* prof);
+// elements past a matrix's base that the split merges of divide and conquer
+// touch in the gathered-operand buffers (host check of their sizes)
+long long stedc_split_extent(int nmax, long long ld);
 
 // --- Divide and conquer ------------------------------------------------------
 template <typename T>

@@ -70,3 +70,25 @@ def test_null_context_is_rejected_without_device_work():
     h = ctypes.c_void_p()
     # invalid precision is refused before any device query
     assert L.mbd_create(ctypes.byref(h), 0, 7, None) == A.MBD_ERR_INVALID_ARGUMENT
+
+
+def test_dc_split_buffers_fit_every_order():
+    """Host-side check (no device): for every order up to 12 000 the gathered
+    split-merge operands of divide and conquer stay inside their buffers of
+    ldz * n_max + 64 elements, ldz = n_max rounded up to 64; orders whose
+    merges stay below 2048 need none."""
+    A = _lib()
+    worst = None
+    for n in range(1, 12001):
+        st, need, have = A.mbd_check_dc_buffers(n)
+        assert st == A.MBD_OK, (n, need, have)
+        assert have == ((n + 63) // 64 * 64) * n + 64
+        if 2 * n <= 2048:
+            assert need == 0
+        else:
+            assert need > (n - 1) * ((n + 63) // 64 * 64)  # the last column is reached
+            slack = have - need
+            worst = slack if worst is None else min(worst, slack)
+    assert worst is not None and worst >= 0
+    st, _, _ = A.mbd_check_dc_buffers(0)
+    assert st == A.MBD_ERR_INVALID_ARGUMENT
