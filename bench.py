@@ -198,10 +198,10 @@ def phase_rooflines(prof, n, fp32, eval_s):
     once per column (n^3/6 elements) and does (2/3) n^3 rank-2k flops; divide
     and conquer at most (4/3) n^3 merge flops; the back-transform 2 n^3; one
     refinement step 6 n^3 FP64; Q^{-1/2} n^3 FP64 plus one pass over it.
-    The phases are timed with the stream synchronised at their boundaries.
-    The reduction (11 700 launches) then runs from an idle queue and takes
-    longer than inside an unsynchronised evaluation, so it is also given as
-    the evaluation time minus the other phases ("in_evaluation")."""
+    The phases are timed on the host clock with the stream synchronised at
+    their boundaries (no timing events); the reduction is also given as the
+    timed step minus the other phases ("in_evaluation"), a check that the
+    synchronisation does not distort it."""
     es = 4 if fp32 else 8
     peak = FP32_PEAK_TFS if fp32 else FP64_PEAK_TFS
     tmin = {2: (8 + (4 if fp32 else 0)) * n * n / (HBM_PEAK_GBS * 1e9),
