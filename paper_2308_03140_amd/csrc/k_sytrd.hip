@@ -80,6 +80,11 @@ __device__ __forceinline__ Refl<T> refl_scalars(const SytrdWs<T>& w, int b, int 
     return r;
 }
 
+// Work items of a launch are dispatched strip by strip (grid x = matrix +
+// nbatch * item, y = strip), so in a batch the longest strips of every
+// matrix (the first) start first rather than those of the last matrices
+// last.
+//
 // Tiles per work item of the SYMV phase: the fewest that keep the launch
 // within `target` workgroups.  Strip c (c = 1 .. nbt tiles long) splits into
 // ceil(c / Kt) work items, nbt = q Kt + r strips in all, so a launch has
@@ -1079,14 +1084,14 @@ template <> struct ColWaves<float> { static constexpr int value = 3; };
 template <> struct ColWaves<double> { static constexpr int value = 1; };
 template <typename T, int NBP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColWaves<T>::value)))
-void sytrd_col_kernel(SytrdWs<T> w, int i, int j, int Kt) {
-    const int b = blockIdx.z;
+void sytrd_col_kernel(SytrdWs<T> w, int i, int j, int Kt, int nbatch) {
+    const int b = blockIdx.x % nbatch;
     const int n = w.ns[b];
     if (i > n - 2 || i >= sytrd_tail_start<T>(n)) return;
     const int b0 = (i + 1) >> 6;
     const int nbk = (n + 63) >> 6;
     const int C = b0 + blockIdx.y;
-    const int q = blockIdx.x;
+    const int q = blockIdx.x / nbatch;
     if (C >= nbk || q >= (nbk - C + Kt - 1) / Kt) return;
     col_item<T, NBP>(w, b, n, i, j, Kt, C, q);
 }
@@ -1135,16 +1140,16 @@ __global__ __launch_bounds__(64) void sytrd_pfinish_kernel(SytrdWs<T> w, int c, 
 // ---------------------------------------------------------------------------
 template <typename T, int NBP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SymvWaves<T>::value)))
-void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt) {
-    const int b = blockIdx.z;
+void sytrd_symv_kernel(SytrdWs<T> w, int i, int j, int Kt, int nbatch) {
+    const int b = blockIdx.x % nbatch;
     const int n = w.ns[b];
     if (i > n - 2 || i >= sytrd_tail_start<T>(n)) return;
     const int b0 = (i + 1) >> 6;
     const int nbk = (n + 63) >> 6;
     const int C = b0 + blockIdx.y;
-    const int q = blockIdx.x;
+    const int q = blockIdx.x / nbatch;
     // the norm slot of column i + 1 is filled by this column's finish phase
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) w.normacc[(long long)b * SYTRD_SLOTS + (i + 1) % SYTRD_SLOTS] = T(0);
+    if (q == 0 && blockIdx.y == 0 && threadIdx.x == 0) w.normacc[(long long)b * SYTRD_SLOTS + (i + 1) % SYTRD_SLOTS] = T(0);
     if (C >= nbk || q >= (nbk - C + Kt - 1) / Kt) return;
     symv_item<T, NBP>(w, b, n, i, j, Kt, C, q, nullptr);
 }
@@ -1267,9 +1272,9 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
                     }
                     hipEvent_t e0, e1;
                     prof->pair(&e0, &e1, fused ? 8 : 0, bb);
-                    hipExtLaunchKernelGGL(kern, dim3(gx, nbt, nbatch), dim3(256), 0, st, e0, e1, 0, w, i, j, Kt);
+                    hipExtLaunchKernelGGL(kern, dim3(gx * nbatch, nbt), dim3(256), 0, st, e0, e1, 0, w, i, j, Kt, nbatch);
                 } else {
-                    hipLaunchKernelGGL(kern, dim3(gx, nbt, nbatch), dim3(256), 0, st, w, i, j, Kt);
+                    hipLaunchKernelGGL(kern, dim3(gx * nbatch, nbt), dim3(256), 0, st, w, i, j, Kt, nbatch);
                 }
                 if (!fused)
                     hipLaunchKernelGGL((sytrd_finish_kernel<T, NBP>), dim3(nbt, 1, nbatch), dim3(256), 0, st, w, i, j);

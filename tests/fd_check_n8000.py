@@ -23,7 +23,9 @@ sys.path.insert(0, os.path.dirname(HERE))
 import gen  # noqa: E402
 
 
-def run(n_coords=20, n_alpha=4, h=1e-4, h_rel_alpha=1e-5, seed=55, natoms=None, out=None, log=print):
+def run(n_coords=20, n_alpha=4, h=1e-4, h_rel_alpha=1e-5, seed=55, natoms=None, out=None, log=print, fp32=False):
+    """fp32: also evaluate energy and all gradients on the FP32 + refinement
+    path and report their largest differences from the FP64 results."""
     import torch
 
     from paper_2308_03140_amd import torch_api as T
@@ -35,7 +37,7 @@ def run(n_coords=20, n_alpha=4, h=1e-4, h_rel_alpha=1e-5, seed=55, natoms=None, 
     ctx = T.Context(0, "fp64")
     R = torch.tensor(c["coords"], device=dev, requires_grad=True)
     a0 = torch.tensor(c["alpha0"], device=dev, requires_grad=True)
-    om = torch.tensor(c["omega"], device=dev)
+    om = torch.tensor(c["omega"], device=dev, requires_grad=True)
     rv = torch.tensor(c["rvdw"], device=dev)
     t0 = time.perf_counter()
     E = mbd_energy(R, a0, om, rv, ctx, beta=c["beta"], a=c["a"])
@@ -44,7 +46,23 @@ def run(n_coords=20, n_alpha=4, h=1e-4, h_rel_alpha=1e-5, seed=55, natoms=None, 
     t_grad = time.perf_counter() - t0
     gR = R.grad.cpu().numpy()
     gA = a0.grad.cpu().numpy()
+    gW = om.grad.cpu().numpy()
+    om = om.detach()
     log("N=%d energy %.12f Ha, energy+gradients %.2f s" % (N, E.item(), t_grad))
+    f32 = None
+    if fp32:
+        c32 = T.Context(0, "fp32_refined")
+        t0 = time.perf_counter()
+        o = T.evaluate(c32, R.detach(), a0.detach(), om, rv, beta=c["beta"], a=c["a"], gradients=True, errors=True)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t0
+        f32 = {"energy_per_atom_diff": abs(o["energy"].item() - E.item()) / N,
+               "max_diff_grad_R": float(np.abs(o["grad_coords"].cpu().numpy() - gR).max()),
+               "max_diff_grad_alpha0": float(np.abs(o["grad_alpha0"].cpu().numpy() - gA).max()),
+               "max_diff_grad_omega": float(np.abs(o["grad_omega"].cpu().numpy() - gW).max()),
+               "refine_steps": float(o["errors"][2].item()), "s_fp32_refined": t32}
+        c32.close()
+        log("FP32+refine vs FP64: " + json.dumps(f32))
 
     def energy(coords, alpha0):
         o = T.evaluate(ctx, coords, alpha0, om, rv, beta=c["beta"], a=c["a"], gradients=False, errors=False)
@@ -79,7 +97,7 @@ def run(n_coords=20, n_alpha=4, h=1e-4, h_rel_alpha=1e-5, seed=55, natoms=None, 
            "energy": E.item(), "h_bohr": h, "h_rel_alpha0": h_rel_alpha,
            "max_err_grad_R": max([r["err"] for r in rows if r["kind"] == "R"] or [0.0]),
            "max_err_grad_alpha0": max([r["err"] for r in rows if r["kind"] == "alpha0"] or [0.0]),
-           "s_energy_gradients": t_grad, "s_energy_only": t_fd, "components": rows}
+           "s_energy_gradients": t_grad, "s_energy_only": t_fd, "fp32_refined_vs_fp64": f32, "components": rows}
     if out:
         with open(out, "w") as f:
             json.dump(res, f, indent=1)
