@@ -249,7 +249,16 @@ mbd_status mbd_eigh(mbd_ctx *ctx, int32_t dtype, int32_t n, int32_t nbatch, void
 /* Measure the launch-shape choices of the path for the problem sizes given
  * (HOST array sizes[nsizes] of matrix orders) and store the fastest in the
  * context; if table_json_path is non-NULL the table is written there.  An
- * existing table can be loaded with mbd_load_tuning. */
+ * existing table can be loaded with mbd_load_tuning.  Two choices are
+ * measured per order: the reduction's SYMV work-item target (kernel time
+ * summed separately over the upper quarter of trailing sizes and below it)
+ * and the general GEMM's output tile (64 or 128, an FP64 n x n x n product
+ * timed with both).  Table format, per precision of the context
+ * ("fp64" / "fp32"): {"<order>": [upper_target, lower_target, gemm_tile]};
+ * the loader also takes [upper, lower] or a single target (then the GEMM
+ * tile is chosen by order) and rejects tiles other than 0, 64 and 128.  An
+ * evaluation uses the row of the tuned order nearest its matrix order (on a
+ * log scale), the GEMM tile only when that order is within a factor 2. */
 mbd_status mbd_autotune(mbd_ctx *ctx, const int32_t *sizes, int32_t nsizes, const char *table_json_path);
 mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
 

@@ -22,6 +22,13 @@
 // only through the address hipGetSymbolAddress gives on that device.
 static __device__ __align__(256) unsigned char scratch[MBD_NOALLOC_SCRATCH_BYTES];
 
+// One row of the autotuner's table: SYMV work-item targets for trailing
+// sizes in the upper quarter and below it, and the general GEMM's output
+// tile (0: chosen by order).
+struct TuneEntry {
+    int hi = 1536, lo = 1536, gemm_ts = 0;
+};
+
 struct mbd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -34,7 +41,7 @@ struct mbd_ctx {
     double refine_tol = 0.0;  // second refinement step threshold (MBD_REFINE_TOL; <= 0: library default)
     bool refine_fallback = true;  // FP64 re-evaluation of unconverged systems (MBD_REFINE_FALLBACK=0: off)
     // autotuned SYMV work-item targets per matrix order, per precision (0 FP64, 1 FP32)
-    std::map<int, std::pair<int, int>> tune[2];  // order -> SYMV work-item targets (upper, lower range)
+    std::map<int, TuneEntry> tune[2];  // order -> SYMV work-item targets, GEMM tile
     // captured batch launch sequences, keyed by batch signature
     struct Graph {
         hipGraphExec_t exec = nullptr;
@@ -143,17 +150,21 @@ template <> const char* tname<float>() { return "f"; }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// SYMV work-item targets (upper and lower range of trailing sizes) for a
-// matrix order: those of the tuned order nearest to n on a log scale, 1536
-// for both ranges when nothing is tuned
-std::pair<int, int> tuned_target(const mbd_ctx* c, int prec, int n) {
+// Table row for a matrix order: that of the tuned order nearest to n on a
+// log scale; the defaults (1536 for both SYMV ranges, GEMM tile by order)
+// when nothing is tuned.  The GEMM tile is taken only from a tuned order
+// within a factor 2 of n.
+TuneEntry tuned_entry(const mbd_ctx* c, int prec, int n) {
     const auto& t = c->tune[prec];
-    std::pair<int, int> best = {1536, 1536};
+    TuneEntry best;
     double bd = 1e300;
     for (const auto& kv : t) {
         const double d = std::fabs(std::log((double)kv.first) - std::log((double)n));
         if (d < bd) { bd = d; best = kv.second; }
     }
+    // a tile timed at an order more than a factor 2 away says little about
+    // this one: leave the choice by order
+    if (bd > std::log(2.0)) best.gemm_ts = 0;
     return best;
 }
 
@@ -196,7 +207,9 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     // --- reduction
     SytrdWs<T> sw;
     if (make_sytrd_ws<T>(c, A, ns, nmax, nbatch, sw) != MBD_OK) return (mbd_status)c->err_code;
-    const std::pair<int, int> tg = tuned_target(c, sizeof(T) == 8 ? 0 : 1, nmax);
+    const TuneEntry te = tuned_entry(c, sizeof(T) == 8 ? 0 : 1, nmax);
+    const std::pair<int, int> tg = {te.hi, te.lo};
+    GemmTileScope tile_scope(te.gemm_ts);
     sw.chunk_target = tg.first;
     sw.chunk_target_lo = tg.second;
     {
@@ -486,6 +499,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     const bool grads = (want & (MBD_WANT_GRAD_COORDS | MBD_WANT_GRAD_ALPHA0 | MBD_WANT_GRAD_OMEGA |
                                 MBD_WANT_GRAD_RVDW | MBD_WANT_GRAD_LATTICE)) != 0;
     const bool fp32 = c->prec == MBD_FP32_REFINED;
+    GemmTileScope tile_scope(tuned_entry(c, fp32 ? 1 : 0, nmax).gemm_ts);
 
     SysDesc* sd_dev = (SysDesc*)ws(c, "sysdesc", sizeof(SysDesc) * nsys);
     int* ns_dev = wsT<int>(c, "ns", nmat);
@@ -1263,6 +1277,44 @@ mbd_status autotune_size(mbd_ctx* c, int n, int* best_target, int* best_lo, doub
     return MBD_OK;
 }
 
+// General-GEMM output tile for order n: C = A B (FP64, n x n x n, the shape
+// of the refinement's and the gradients' products) timed with 64 x 64 and
+// 128 x 128 tiles, the faster kept.
+mbd_status autotune_gemm_tile(mbd_ctx* c, int n, int* ts_out) {
+    const int ld = round_up(n, 64);
+    const long long stride = (long long)ld * n;
+    double* A = wsT<double>(c, "tuneGA", stride);
+    double* B = wsT<double>(c, "tuneGB", stride);
+    double* C = wsT<double>(c, "tuneGC", stride);
+    if (!A || !B || !C) return (mbd_status)c->err_code;
+    fill_sym_random_launch<double>(c->stream, n, A, ld, 4321u);
+    fill_sym_random_launch<double>(c->stream, n, B, ld, 8765u);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0), "event");
+    HIPCHK(hipEventCreate(&e1), "event");
+    double best = 1e300;
+    *ts_out = 0;
+    for (int ts : {64, 128}) {
+        GemmTileScope scope(ts);
+        float t = 1e30f;
+        for (int rep = 0; rep < 3; rep++) {
+            (void)hipEventRecord(e0, c->stream);
+            gemm_batched<double>(c->stream, false, false, nullptr, n, 1, A, ld, stride, B, ld, stride, C, ld, stride,
+                                 1.0, 0.0, false, nullptr);
+            (void)hipEventRecord(e1, c->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) t = std::min(t, ms);  // the first launch of a shape is left out
+        }
+        if (t < best) { best = t; *ts_out = ts; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError(), "autotune gemm");
+    return MBD_OK;
+}
+
 bool write_tuning(const mbd_ctx* c, const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return false;
@@ -1272,7 +1324,8 @@ bool write_tuning(const mbd_ctx* c, const char* path) {
         std::fprintf(f, "  \"%s\": {", names[p]);
         bool first = true;
         for (const auto& kv : c->tune[p]) {
-            std::fprintf(f, "%s\"%d\": [%d, %d]", first ? "" : ", ", kv.first, kv.second.first, kv.second.second);
+            std::fprintf(f, "%s\"%d\": [%d, %d, %d]", first ? "" : ", ", kv.first, kv.second.hi, kv.second.lo,
+                         kv.second.gemm_ts);
             first = false;
         }
         std::fprintf(f, "}%s\n", p == 0 ? "," : "");
@@ -1281,8 +1334,9 @@ bool write_tuning(const mbd_ctx* c, const char* path) {
     return std::fclose(f) == 0;
 }
 
-// parses {"fp64": {"n": [upper, lower], ...}, "fp32": {...}} (the format
-// written above); a single number sets both targets
+// parses {"fp64": {"n": [upper, lower, gemm_tile], ...}, "fp32": {...}} (the
+// format written above); a single number sets both targets, a missing
+// (or 0) GEMM tile leaves the choice by order
 bool read_tuning(mbd_ctx* c, const char* path) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
@@ -1299,7 +1353,7 @@ bool read_tuning(mbd_ctx* c, const char* path) {
         if (lb == std::string::npos || rb == std::string::npos || rb < lb) return false;
         const std::string body = txt.substr(lb + 1, rb - lb - 1);
         size_t pos = 0;
-        std::map<int, std::pair<int, int>> tab;
+        std::map<int, TuneEntry> tab;
         while ((pos = body.find('"', pos)) != std::string::npos) {
             const size_t q2 = body.find('"', pos + 1);
             const size_t colon = body.find(':', q2);
@@ -1307,19 +1361,23 @@ bool read_tuning(mbd_ctx* c, const char* path) {
             const int key = std::atoi(body.substr(pos + 1, q2 - pos - 1).c_str());
             size_t v = body.find_first_not_of(" \t\n", colon + 1);
             if (v == std::string::npos) return false;
-            int hi, lo;
+            int hi, lo, ts = 0;
             if (body[v] == '[') {
                 const size_t comma = body.find(',', v), rbk = body.find(']', v);
                 if (comma == std::string::npos || rbk == std::string::npos || comma > rbk) return false;
                 hi = std::atoi(body.c_str() + v + 1);
                 lo = std::atoi(body.c_str() + comma + 1);
+                const size_t comma2 = body.find(',', comma + 1);
+                if (comma2 != std::string::npos && comma2 < rbk) ts = std::atoi(body.c_str() + comma2 + 1);
                 pos = body.find(',', rbk);
             } else {
                 hi = lo = std::atoi(body.c_str() + v);
                 pos = body.find(',', v);
             }
-            if (key <= 0 || hi <= 0 || lo <= 0) return false;
-            tab[key] = {hi, lo};
+            if (key <= 0 || hi <= 0 || lo <= 0 || (ts != 0 && ts != 64 && ts != 128)) return false;
+            TuneEntry e;
+            e.hi = hi; e.lo = lo; e.gemm_ts = ts;
+            tab[key] = e;
             if (pos == std::string::npos) break;
         }
         c->tune[p] = tab;
@@ -1340,11 +1398,15 @@ mbd_status mbd_autotune(mbd_ctx* c, const int32_t* sizes, int32_t nsizes, const 
     for (int k = 0; k < nsizes; k++) {
         const int n = sizes[k];
         if (n < 2) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_autotune", "sizes must be >= 2");
-        int target = 1536, lo = 1536;
+        int target = 1536, lo = 1536, ts = 0;
         double ms = 0;
-        const mbd_status r = p ? autotune_size<float>(c, n, &target, &lo, &ms) : autotune_size<double>(c, n, &target, &lo, &ms);
+        mbd_status r = p ? autotune_size<float>(c, n, &target, &lo, &ms) : autotune_size<double>(c, n, &target, &lo, &ms);
         if (r != MBD_OK) return r;
-        c->tune[p][n] = {target, lo};
+        r = autotune_gemm_tile(c, n, &ts);
+        if (r != MBD_OK) return r;
+        TuneEntry e;
+        e.hi = target; e.lo = lo; e.gemm_ts = ts;
+        c->tune[p][n] = e;
     }
     if (path && !write_tuning(c, path)) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_autotune", "cannot write table");
     return MBD_OK;

@@ -447,14 +447,16 @@ static void gemm_gen_launch_ts(hipStream_t st, const int* ns, int nmax, int nbat
     }
 }
 
+thread_local int g_gemm_tile = 0;
+
 // 128x128 tiles for large matrices; batches of small ones keep 64x64 (less
-// padding waste at the ragged edges)
+// padding waste at the ragged edges); the autotuner's choice when set
 template <typename T, bool TA, bool TB>
 static void gemm_gen_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const T* A, int lda,
                             long long sA, const T* B, int ldb, long long sB, T* C, int ldc, long long sC,
                             T alpha, T beta, bool lower_only, const int* skip, const T* Cin, int ldcin,
                             long long sCin, const GemmSecond<T>* second = nullptr) {
-    if (nmax >= GEMM_TS128_MIN_ORDER)
+    if (g_gemm_tile == 128 || (g_gemm_tile == 0 && nmax >= GEMM_TS128_MIN_ORDER))
         gemm_gen_launch_ts<T, TA, TB, 128>(st, ns, nmax, nbatch, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta,
                                            lower_only, skip, Cin, ldcin, sCin, second);
     else

@@ -183,6 +183,15 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st);
 
 // --- generic batched GEMM (C = alpha op(A) op(B) + beta Cin, order ns[b]; Cin
 // defaults to C) ---------------------------------------------------------------
+// Output tile of the general batched GEMM (64 or 128), set per evaluation
+// from the autotuner's table (thread-local: a context is driven by one
+// thread at a time); 0 picks by order (128 from GEMM_TS128_MIN_ORDER).
+extern thread_local int g_gemm_tile;
+struct GemmTileScope {
+    int saved;
+    explicit GemmTileScope(int ts) : saved(g_gemm_tile) { g_gemm_tile = ts; }
+    ~GemmTileScope() { g_gemm_tile = saved; }
+};
 template <typename T>
 void gemm_batched(hipStream_t st, bool ta, bool tb, const int* ns, int nmax, int nbatch,
                   const T* A, int lda, long long sA, const T* B, int ldb, long long sB, T* C,

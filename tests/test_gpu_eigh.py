@@ -130,18 +130,61 @@ def test_autotune_table_roundtrip(tmp_path):
     import json
     tab = json.load(open(path))
     assert set(tab) == {"fp64", "fp32"} and "400" in tab["fp32"]
-    # each order maps to [upper-range target, lower-range target]
-    assert all(len(v) == 2 and min(v) > 0 for p in tab.values() for v in p.values())
-    # a table may also give one target for both ranges
+    # each order maps to [upper-range target, lower-range target, GEMM tile]
+    assert all(len(v) == 3 and min(v[:2]) > 0 and v[2] in (64, 128) for p in tab.values() for v in p.values())
+    # a table may also give one target for both ranges, or two targets with
+    # the GEMM tile left to the order; both tiles are usable at any order
+    for tab in ({"fp64": {"400": 768}, "fp32": {"400": [1536, 512]}},
+                {"fp64": {"400": [768, 512, 128]}, "fp32": {"400": [1536, 512, 64]}},
+                {"fp64": {"400": [768, 512, 64]}, "fp32": {"400": [1536, 512, 128]}}):
+        with open(path, "w") as f:
+            json.dump(tab, f)
+        for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32_refined", torch.float32, 2e-5)):
+            c3 = T.Context(0, prec)
+            c3.load_tuning(path)
+            A = gen.random_symmetric(98, 400)
+            w, Z = T.eigh(c3, torch.tensor(A, device="cuda", dtype=dt))
+            _check(A, w.double().cpu().numpy(), Z.double().cpu().numpy(), tol)
+            c3.close()
+    # a tile that is neither 64 nor 128 is refused
     with open(path, "w") as f:
-        json.dump({"fp64": {"400": 768}, "fp32": {"400": [1536, 512]}}, f)
-    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32_refined", torch.float32, 2e-5)):
-        c3 = T.Context(0, prec)
-        c3.load_tuning(path)
-        A = gen.random_symmetric(98, 400)
-        w, Z = T.eigh(c3, torch.tensor(A, device="cuda", dtype=dt))
-        _check(A, w.double().cpu().numpy(), Z.double().cpu().numpy(), tol)
-        c3.close()
+        json.dump({"fp64": {"400": [768, 512, 96]}, "fp32": {}}, f)
+    c4 = T.Context(0, "fp64")
+    with pytest.raises(Exception):
+        c4.load_tuning(path)
+    c4.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
+def test_gemm_tile_choice_same_results(tmp_path, prec):
+    """An evaluation (energy and every gradient) at order 3N = 600 through a
+    tuning table that sets the general GEMM's tile to 64, then to 128: the
+    two must agree to rounding (the products differ only in blocking)."""
+    import json
+    from paper_2308_03140_amd import torch_api as T
+    _note("gemm tile choice %s" % prec)
+    c = gen.finite_cluster(611, 200, 12.0 * (200 / 32.0) ** (1.0 / 3.0))
+    key = "fp64" if prec == "fp64" else "fp32"
+    out = []
+    for ts in (64, 128):
+        path = str(tmp_path / ("tile%d.json" % ts))
+        with open(path, "w") as f:
+            json.dump({key: {"600": [1536, 1536, ts]}}, f)
+        ctx = T.Context(0, prec)
+        try:
+            ctx.load_tuning(path)
+            out.append(T.evaluate(ctx, torch.tensor(c["coords"], device="cuda"), c["alpha0"], c["omega"], c["rvdw"],
+                                  beta=c["beta"], a=c["a"]))
+            torch.cuda.synchronize()
+        finally:
+            ctx.close()
+    a, b = out
+    # FP32+refine: the tile also changes the FP32 products, so the two runs
+    # agree to the refined path's own bounds, not to FP64 rounding
+    tol_e, tol_g = (1e-12, 1e-9) if prec == "fp64" else (1e-7, 1e-6)
+    assert abs(a["energy"].item() - b["energy"].item()) <= tol_e * 200
+    for k in ("grad_coords", "grad_alpha0", "grad_omega", "grad_rvdw"):
+        assert (a[k] - b[k]).abs().max().item() <= tol_g, k
 
 
 @pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 3e-5)])
