@@ -242,7 +242,11 @@ mbd_status mbd_rsscs_evaluate(mbd_ctx *ctx, const mbd_system *sys, int32_t n_fre
  * lower triangle read (copied into a library workspace first; A itself is
  * not modified).  w: [nbatch][n] eigenvalues ascending.
  * Z (may be NULL): [nbatch] n x n eigenvector matrices, leading dimension ldz,
- * stride `zstride`.  dtype: 0 = FP64, 1 = FP32 (then A, w, Z are float). */
+ * stride `zstride`.  dtype: 0 = FP64, 1 = FP32 (then A, w, Z are float).
+ * A matrix whose reduction yields a non-finite entry (NaN or Inf in A) gives
+ * MBD_ERR_INVALID_ARGUMENT; its w and Z are then not meaningful (the other
+ * matrices of the batch are solved as usual).  In mbd_evaluate and its
+ * variants the same condition fails the system with that code. */
 mbd_status mbd_eigh(mbd_ctx *ctx, int32_t dtype, int32_t n, int32_t nbatch, void *A, int32_t lda,
                     int64_t stride, void *w, void *Z, int32_t ldz, int64_t zstride);
 
@@ -273,11 +277,13 @@ mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
  * column and runs the column's SYMV (FP32, trailing order up to 4000).
  * Kind 9 is the screening stage of mbd_rsscs_evaluate (assembly, Cholesky
  * factorisation and solves, contraction; and the chain rule of its gradient).
- * Enabling clears earlier records.  mbd_get_profile synchronises the stream
- * and returns, for one kind (0..9), the summed event time (ms), the number of
- * records and the summed algorithmic work: bytes of the lower trailing
- * triangle read (kinds 0 and 8), flops of the rank-2k update (kind 1), 0 for
- * the phases.  enable = 2 records the
+ * Kind 10 is the single launch that reduces a batch of small matrices with
+ * one workgroup per matrix (FP64 batches of 8 or more matrices of order
+ * <= 1024).  Enabling clears earlier records.  mbd_get_profile synchronises
+ * the stream and returns, for one kind (0..10), the summed event time (ms),
+ * the number of records and the summed algorithmic work: bytes of the lower
+ * trailing triangle read (kinds 0, 8 and 10), flops of the rank-2k update
+ * (kind 1), 0 for the phases.  enable = 2 records the
  * phases only, without timing events (which would slow every launch): the
  * stream is synchronised at each phase boundary and the host clock read. */
 mbd_status mbd_set_profiling(mbd_ctx *ctx, int enable);

@@ -189,8 +189,9 @@ mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int
     sw.d = wsT<T>(c, "d" + t, (size_t)nmax * nbatch);
     sw.e = wsT<T>(c, "e" + t, (size_t)nmax * nbatch);
     sw.tau = wsT<T>(c, "tau" + t, (size_t)nmax * nbatch);
+    sw.order = wsT<int>(c, "sorder" + t, (size_t)nbatch);
     if (!sw.Vp || !sw.Wp || !sw.colbuf || !sw.normacc || !sw.yacc || !sw.sacc || !sw.vacc || !sw.d ||
-        !sw.e || !sw.tau)
+        !sw.e || !sw.tau || !sw.order)
         return (mbd_status)c->err_code;
     return MBD_OK;
 }
@@ -198,7 +199,7 @@ mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int
 // Full dense symmetric eigensolver on a batch: reduction, D&C, back-transform.
 template <typename T>
 mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host, int nmax, int nbatch, bool vectors,
-                   T* w_out, long long sW, MatBatch<T>* Xout) {
+                   T* w_out, long long sW, MatBatch<T>* Xout, int** bad_out = nullptr) {
     const std::string t = tname<T>();
     const hipStream_t st = c->stream;
     const int nbk = (nmax + 63) / 64;
@@ -217,6 +218,12 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
         sytrd_launch<T>(sw, nbatch, nmax, st, ns_host, &c->prof);
     }
     HIPCHK(hipGetLastError(), "sytrd");
+    // a non-finite tridiagonal (from non-finite matrix entries) is zeroed and
+    // flagged before the tridiagonal solvers see it
+    int* bad = wsT<int>(c, "eig_bad", (size_t)nbatch);
+    if (!bad) return (mbd_status)c->err_code;
+    tridiag_guard_launch<T>(ns, nbatch, sw.d, sw.e, sw.sD, bad, st);
+    if (bad_out) *bad_out = bad;
     if (!vectors) {
         // eigenvalues only: Sturm-count multisection on the tridiagonal
         PhaseTimer ph(&c->prof, st, 4);
@@ -351,6 +358,12 @@ SysDesc make_desc(const mbd_system* s, unsigned want, const mbd_result* o) {
     d.eigvals = (want & MBD_WANT_EIGVALS) ? o->eigvals : nullptr;
     d.errors = (want & MBD_WANT_ERRORS) ? o->errors : nullptr;
     return d;
+}
+
+// a matrix whose tridiagonal was not finite fails its system
+__global__ void eig_bad_status_kernel(const int* bad, int nmat, unsigned* status, int one_system) {
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    if (m < nmat && bad[m]) atomicOr(&status[one_system ? 0 : m], MBD_ST_BAD_INPUT);
 }
 
 __global__ void grad_gate_kernel(const unsigned* status, int nsys, SysDesc* sd) {
@@ -549,14 +562,15 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     double* stats = nullptr;
     int* skip_dev = nullptr;  // per matrix: refinement step one was enough
     int* conv_dev = nullptr;  // per matrix: the last step met its target
+    int* eig_bad = nullptr;  // per matrix: non-finite tridiagonal
     if (!fp32) {
-        mbd_status r = run_eig<double>(c, A64, ns_dev, nsh.data(), nmax, nmat, grads, lam, nmax, &X);
+        mbd_status r = run_eig<double>(c, A64, ns_dev, nsh.data(), nmax, nmat, grads, lam, nmax, &X, &eig_bad);
         if (r != MBD_OK) return r;
     } else {
         float* lam32 = wsT<float>(c, "lam32", (size_t)nmax * nmat);
         if (!lam32) return (mbd_status)c->err_code;
         MatBatch<float> X32;
-        mbd_status r = run_eig<float>(c, A32, ns_dev, nsh.data(), nmax, nmat, true, lam32, nmax, &X32);
+        mbd_status r = run_eig<float>(c, A32, ns_dev, nsh.data(), nmax, nmat, true, lam32, nmax, &X32, &eig_bad);
         if (r != MBD_OK) return r;
         // refinement in FP64 against the FP64 Q held in A64: step one for
         // every matrix, step two where step one's remainder estimate is large
@@ -589,6 +603,8 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         HIPCHK(hipGetLastError(), "refine");
         X = S;
     }
+    hipLaunchKernelGGL(eig_bad_status_kernel, dim3((nmat + 63) / 64), dim3(64), 0, st, eig_bad, nmat, status,
+                       per ? 1 : 0);
     PhaseTimer ph_eg(&c->prof, st, 7);
     mbd_energy_launch(st, sd_dev, nsys, ns_dev, lam, nmax, om, status, lmin, conv_dev);
     mbd_errors_launch(st, sd_dev, nsys, nmat, stats, skip_dev);
@@ -1182,6 +1198,7 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
     if (!ns_dev) return (mbd_status)c->err_code;
     HIPCHK(hipMemcpyAsync(ns_dev, nsh.data(), sizeof(int) * nbatch, hipMemcpyHostToDevice, c->stream), "upload");
     mbd_status r;
+    int* bad = nullptr;
     // the reduction reads the matrices in 16-byte segments of 64-row-aligned
     // columns: stage them into a workspace with a leading dimension that is a
     // multiple of 64 (the caller's A is left unchanged)
@@ -1196,7 +1213,7 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
                "stage");
     if (dtype == 0) {
         MatBatch<double> Ab = {(double*)As, lds, sts}, X;
-        r = run_eig<double>(c, Ab, ns_dev, nsh.data(), n, nbatch, Z != nullptr, (double*)w, n, &X);
+        r = run_eig<double>(c, Ab, ns_dev, nsh.data(), n, nbatch, Z != nullptr, (double*)w, n, &X, &bad);
         if (r == MBD_OK && Z)
             HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, X.p, sizeof(double) * X.ld, sizeof(double) * n,
                                     (size_t)n * 1, hipMemcpyDeviceToDevice, c->stream), "copy");
@@ -1207,7 +1224,7 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
                        "copy");
     } else {
         MatBatch<float> Ab = {(float*)As, lds, sts}, X;
-        r = run_eig<float>(c, Ab, ns_dev, nsh.data(), n, nbatch, Z != nullptr, (float*)w, n, &X);
+        r = run_eig<float>(c, Ab, ns_dev, nsh.data(), n, nbatch, Z != nullptr, (float*)w, n, &X, &bad);
         if (r == MBD_OK && Z)
             for (int b = 0; b < nbatch; b++)
                 HIPCHK(hipMemcpy2DAsync((float*)Z + (long long)b * zstride, sizeof(float) * ldz, X.p + (long long)b * X.stride,
@@ -1215,7 +1232,11 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
                        "copy");
     }
     if (r != MBD_OK) return r;
+    std::vector<int> badh(nbatch);
+    HIPCHK(hipMemcpyAsync(badh.data(), bad, sizeof(int) * nbatch, hipMemcpyDeviceToHost, c->stream), "read flags");
     HIPCHK(hipStreamSynchronize(c->stream), "mbd_eigh");
+    for (int b = 0; b < nbatch; b++)
+        if (badh[b]) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_eigh", "non-finite matrix entries");
     return MBD_OK;
 }
 

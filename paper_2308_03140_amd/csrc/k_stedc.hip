@@ -926,5 +926,33 @@ int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     return src;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void tridiag_guard_kernel(const int* ns, T* d, T* e, long long sD, int* bad) {
+    __shared__ int flag;
+    const int b = blockIdx.x;
+    const int n = ns[b];
+    T* db = d + (long long)b * sD;
+    T* eb = e + (long long)b * sD;
+    if (threadIdx.x == 0) flag = 0;
+    __syncthreads();
+    bool f = false;
+    for (int i = threadIdx.x; i < n; i += 256) f |= !isfinite(db[i]) || (i + 1 < n && !isfinite(eb[i]));
+    if (f) flag = 1;
+    __syncthreads();
+    if (flag)
+        for (int i = threadIdx.x; i < n; i += 256) {
+            db[i] = T(0);
+            eb[i] = T(0);
+        }
+    if (threadIdx.x == 0) bad[b] = flag;
+}
+
+template <typename T>
+void tridiag_guard_launch(const int* ns, int nbatch, T* d, T* e, long long sD, int* bad, hipStream_t st) {
+    hipLaunchKernelGGL(tridiag_guard_kernel<T>, dim3(nbatch), dim3(256), 0, st, ns, d, e, sD, bad);
+}
+template void tridiag_guard_launch<double>(const int*, int, double*, double*, long long, int*, hipStream_t);
+template void tridiag_guard_launch<float>(const int*, int, float*, float*, long long, int*, hipStream_t);
+
 template int stedc_launch<double>(const StedcWs<double>&, int, int, hipStream_t);
 template int stedc_launch<float>(const StedcWs<float>&, int, int, hipStream_t);

@@ -656,6 +656,362 @@ __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<
 }
 
 // ===========================================================================
+// One workgroup per matrix, for batches of matrices of order at most
+// SYTRD_WG_NMAX (by default FP64 only: SytrdWgMinBatch below).
+//
+// The per-column launches step every matrix of a batch through the columns
+// of the largest in lockstep, each launch a dependent round trip.  Here one
+// workgroup reduces a whole matrix, its barriers taking the place of
+// launches; per column i (s = i + 1, J its panel column):
+//   1. the thread of row r forms the column updated by the panel so far,
+//      u(r) = A(r,i) - sum_k [V(r,k) W(i,k) + W(r,k) V(i,k)], into LDS;
+//   2. the SYMV y' = A x of x = u on rows s+1.. (x(s) = 0) over the stored
+//      trailing matrix, in the tiles of the multi-workgroup kernel with
+//      WgDepth tiles in flight per wavefront, row and column sums added into
+//      LDS; with it x^T x, x^T A x and the panel products W^T x, V^T x;
+//   3. beta from ||x||, then A v = scale y' + A e_s, the panel corrections
+//      and w = tau y - (tau^2/2)(y^T v) v, with y^T v formed from the
+//      scalars of step 2 (no further reduction).
+// Every thread forms w(s), which the next column's update needs, itself;
+// the LDS column and y alternate between two buffers, so a column takes two
+// barriers.  After each panel of SYTRD_NBP columns the rank-2 NBP update of
+// the trailing matrix runs on the matrix cores.  Workgroups take the
+// matrices largest first.  The last columns are left to the LDS tail
+// kernel, as in the other path.
+// ===========================================================================
+#define SYTRD_WG_NMAX 1024
+#define SYTRD_WG_WAVES 8
+template <typename T> struct WgDepth;
+template <> struct WgDepth<float> { static constexpr int value = 6; };
+template <> struct WgDepth<double> { static constexpr int value = 3; };
+
+// order[k] = the matrix of k-th largest order (ties by index)
+__global__ __launch_bounds__(256) void sytrd_wg_order_kernel(const int* ns, int nbatch, int* order) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nbatch) return;
+    const int nb = ns[b];
+    int pos = 0;
+    for (int o = 0; o < nbatch; o++) {
+        const int no = ns[o];
+        pos += (no > nb || (no == nb && o < b)) ? 1 : 0;
+    }
+    order[pos] = b;
+}
+
+// A(t0:n, t0:n) -= V W^T + W V^T on the lower triangle, K = 2 NBP, on the
+// matrix cores: each wavefront takes block rows of 16 HR rows (longest
+// first), loads their operand rows [V W] once and sweeps the block columns
+// of 16 HC columns at and left of the diagonal.
+template <typename T, int NW>
+__device__ void wg_syr2k(T* A, long long ld, const T* Vp, const T* Wp, int ldp, int n, int t0) {
+    constexpr int NBP = SYTRD_NBP;
+    constexpr int KS = 2 * NBP / 4;  // k steps of four
+    constexpr int HR = sizeof(T) == 4 ? 2 : 1;
+    constexpr int HC = sizeof(T) == 4 ? 2 : 1;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nbr = (n - t0 + 16 * HR - 1) / (16 * HR);
+    for (int jj = wv; jj < nbr; jj += NW) {
+        const int rb = t0 + 16 * HR * (nbr - 1 - jj);
+        T af[HR][KS];
+#pragma unroll
+        for (int h = 0; h < HR; h++) {
+            const int r = min(rb + 16 * h + (lane & 15), n - 1);
+#pragma unroll
+            for (int st = 0; st < KS; st++) {
+                const int k = 4 * st + (lane >> 4);
+                af[h][st] = k < NBP ? Vp[r + (long long)k * ldp] : Wp[r + (long long)(k - NBP) * ldp];
+            }
+        }
+        for (int cc = t0; cc < rb + 16 * HR; cc += 16 * HC) {
+            T bf[HC][KS];
+#pragma unroll
+            for (int h = 0; h < HC; h++) {
+                const int c = min(cc + 16 * h + (lane & 15), n - 1);
+#pragma unroll
+                for (int st = 0; st < KS; st++) {
+                    const int k = 4 * st + (lane >> 4);
+                    bf[h][st] = k < NBP ? Wp[c + (long long)k * ldp] : Vp[c + (long long)(k - NBP) * ldp];
+                }
+            }
+            typename mfma4<T>::v acc[HR][HC];
+#pragma unroll
+            for (int hr = 0; hr < HR; hr++)
+#pragma unroll
+                for (int hc = 0; hc < HC; hc++) acc[hr][hc] = typename mfma4<T>::v{0, 0, 0, 0};
+#pragma unroll
+            for (int st = 0; st < KS; st++)
+#pragma unroll
+                for (int hr = 0; hr < HR; hr++)
+#pragma unroll
+                    for (int hc = 0; hc < HC; hc++) acc[hr][hc] = mfma16x16x4(af[hr][st], bf[hc][st], acc[hr][hc]);
+#pragma unroll
+            for (int hr = 0; hr < HR; hr++)
+#pragma unroll
+                for (int hc = 0; hc < HC; hc++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int r = rb + 16 * hr + mfma_rows<T>::row(lane, q);
+                        const int c = cc + 16 * hc + (lane & 15);
+                        if (r < n && c < n && r >= c) A[r + (long long)c * ld] -= acc[hr][hc][q];
+                    }
+        }
+    }
+}
+
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void sytrd_wg_kernel(SytrdWs<T> w) {
+    constexpr int NT = 64 * NW;
+    constexpr int NBP = SYTRD_NBP;
+    constexpr int RPT = (SYTRD_WG_NMAX + NT - 1) / NT;  // rows per thread
+    constexpr int RPL = 16 / (int)sizeof(T);
+    constexpr int LPC = 64 / RPL;
+    constexpr int NI = 16 / RPL;
+    constexpr int D = WgDepth<T>::value;
+    typedef typename Vec16<T>::v VT;
+    static_assert(NBP == 32 && NW % 4 == 0, "layout");
+    __shared__ T ucb[2][SYTRD_WG_NMAX];  // updated column, by column parity
+    __shared__ T yyb[2][SYTRD_WG_NMAX];  // y' = A x, by column parity
+    __shared__ T dots[2 * NBP + 1];      // W^T x, V^T x, x^T x
+    __shared__ T xaxw[NW];               // x^T A x per wavefront
+
+    const int b = w.order[blockIdx.x];
+    const int n = w.ns[b];
+    const int kend = sytrd_tail_start<T>(n);
+    if (kend <= 0) return;
+    T* A = w.A.at(b);
+    const long long ld = w.A.ld;
+    T* Vp = w.Vp + (long long)b * w.sP;
+    T* Wp = w.Wp + (long long)b * w.sP;
+    const int ldp = w.ldp;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane / LPC, rq = lane % LPC;
+    const int nbk = (n + 63) >> 6;
+    unsigned coff[NI];
+#pragma unroll
+    for (int k = 0; k < NI; k++) coff[k] = (unsigned)((RPL * k + g) * ld * (long long)sizeof(T));
+
+    for (int k0 = 0; k0 < kend; k0 += NBP) {
+        T ws_prev = T(0);  // w(s) of the previous column (its s is this column's i)
+        for (int J = 0; J < NBP; J++) {
+            const int i = k0 + J, s = i + 1, cb = i & 1;
+            T* uc = ucb[cb];
+            T* yy = yyb[cb];
+            // ---- 1. column i updated by the panel's previous columns
+#pragma unroll
+            for (int t = 0; t < RPT; t++) {
+                const int r = tid + t * NT;
+                if (r >= i && r < n) {
+                    T u = A[r + (long long)i * ld];
+                    for (int k = 0; k + 1 < J; k++)
+                        u -= Vp[r + (long long)k * ldp] * Wp[i + (long long)k * ldp] +
+                             Wp[r + (long long)k * ldp] * Vp[i + (long long)k * ldp];
+                    if (J > 0) u -= Vp[r + (long long)(J - 1) * ldp] * ws_prev + Wp[r + (long long)(J - 1) * ldp];
+                    uc[r] = u;
+                    yy[r] = T(0);
+                }
+            }
+            __syncthreads();
+
+            // ---- 2. panel products and norm of x, then the SYMV
+            for (int q = wv; q <= 2 * J; q += NW) {
+                const T* col = q < J ? Wp + (long long)q * ldp : Vp + (long long)(q - J) * ldp;
+                T acc = T(0);
+                for (int r = s + 1 + lane; r < n; r += 64) {
+                    const T x = uc[r];
+                    acc += (q == 2 * J ? x : col[r]) * x;
+                }
+                acc = wave_sum(acc);
+                if (lane == 0) dots[q] = acc;
+            }
+            {
+                const int b0 = s >> 6;
+                const int P = 4 * (nbk - b0);  // column pairs: strip b0 + p / 4, sixteen columns 16 (p % 4)
+                auto pair_c0 = [&](int p) { return 64 * (b0 + (p >> 2)) + 16 * (p & 3); };
+                // this wavefront's pairs, in snake order over rounds of NW
+                auto pair_of = [&](int k) { return k * NW + ((k & 1) ? NW - 1 - wv : wv); };
+                struct It { int k, p, R; };
+                auto seek = [&](It& it) {
+                    for (;; it.k++) {
+                        it.p = pair_of(it.k);
+                        if (it.p >= P) return;
+                        const int c0 = pair_c0(it.p);
+                        if (c0 < n && c0 + 16 > s) break;
+                    }
+                    it.R = b0 + (it.p >> 2);
+                };
+                auto next = [&](It& it) {
+                    if (it.p >= P) return;
+                    if (++it.R < nbk) return;
+                    it.k++;
+                    seek(it);
+                };
+                auto issue = [&](VT (&bf)[NI], const It& it) {
+                    if (it.p >= P) return;
+                    const int c0 = pair_c0(it.p);
+                    const int ncols = min(16, n - c0);
+                    const __amdgpu_buffer_rsrc_t rs =
+                        make_rsrc(A + (long long)c0 * ld, (unsigned)(ncols * ld * (long long)sizeof(T)));
+                    const unsigned roff = (unsigned)((it.R * 64 + RPL * rq) * (int)sizeof(T));
+#pragma unroll
+                    for (int k = 0; k < NI; k++) {
+                        const int c = c0 + RPL * k + g;
+                        bf[k] = buf_load16<T>(rs, (c >= s && c < n) ? coff[k] + roff : OOB_OFFSET);
+                    }
+                };
+                T vc[NI], cacc[NI];
+                T xax = T(0);
+                int cur = -1, pc0 = 0, pC = 0;
+                auto start_pair = [&](const It& it) {
+                    cur = it.p;
+                    pc0 = pair_c0(it.p);
+                    pC = b0 + (it.p >> 2);
+#pragma unroll
+                    for (int k = 0; k < NI; k++) {
+                        const int c = pc0 + RPL * k + g;
+                        vc[k] = (c > s && c < n) ? uc[c] : T(0);
+                        cacc[k] = T(0);
+                    }
+                };
+                auto flush_pair = [&]() {
+#pragma unroll
+                    for (int k = 0; k < NI; k++) xax += vc[k] * cacc[k];
+                    T csum;
+                    if constexpr (NI == 4) {
+                        csum = quad_sum(pair_sum_b2(pair_sum_b3(cacc[0], cacc[2]), pair_sum_b3(cacc[1], cacc[3])));
+                    } else {
+                        const T u0 = pair_sum_b4(cacc[0], cacc[4]), u1 = pair_sum_b4(cacc[1], cacc[5]);
+                        const T u2 = pair_sum_b4(cacc[2], cacc[6]), u3 = pair_sum_b4(cacc[3], cacc[7]);
+                        csum = quad_sum(pair_sum_b2(pair_sum_b3(u0, u2), pair_sum_b3(u1, u3)));
+                    }
+                    const int c = pc0 + RPL * ((lane >> 2) % NI) + g;
+                    if ((lane & 3) == 0 && c >= s && c < n)
+                        __hip_atomic_fetch_add(&yy[c], csum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                };
+                auto process = [&](const VT (&bf)[NI], int R) {
+                    const int r0 = R * 64 + RPL * rq;
+                    T vr[RPL], rs[RPL];
+#pragma unroll
+                    for (int e = 0; e < RPL; e++) {
+                        const int r = r0 + e;
+                        vr[e] = (r > s && r < n) ? uc[r] : T(0);
+                        rs[e] = T(0);
+                    }
+#pragma unroll
+                    for (int k = 0; k < NI; k++) {
+                        const int c = pc0 + RPL * k + g;
+#pragma unroll
+                        for (int e = 0; e < RPL; e++) {
+                            const int r = r0 + e;
+                            const T xa = (r < n && (R > pC || r >= c)) ? bf[k][e] : T(0);
+                            rs[e] += xa * vc[k];
+                            cacc[k] += (R > pC || r != c) ? xa * vr[e] : T(0);
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < RPL; e++) xax += vr[e] * rs[e];
+                    T rsum;
+                    if constexpr (RPL == 4) {
+                        rsum = pair_sum_b4(pair_sum_b5(rs[0], rs[2]), pair_sum_b5(rs[1], rs[3]));
+                    } else {
+                        rsum = pair_sum_b5(rs[0], rs[1]);
+                    }
+                    const int row = R * 64 + RPL * rq + g;
+                    if (row >= s && row < n)
+                        __hip_atomic_fetch_add(&yy[row], rsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                };
+                It ip{0, 0, 0}, iq{0, 0, 0};
+                seek(ip);
+                seek(iq);
+                VT buf[D][NI];
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    issue(buf[d], ip);
+                    next(ip);
+                }
+                while (iq.p < P) {
+#pragma unroll
+                    for (int d = 0; d < D; d++) {
+                        if (iq.p >= P) break;
+                        if (iq.p != cur) {
+                            if (cur >= 0) flush_pair();
+                            start_pair(iq);
+                        }
+                        process(buf[d], iq.R);
+                        issue(buf[d], ip);
+                        next(ip);
+                        next(iq);
+                    }
+                }
+                if (cur >= 0) flush_pair();
+                xax = wave_sum(xax);
+                if (lane == 0) xaxw[wv] = xax;
+            }
+            __syncthreads();
+
+            // ---- 3. reflector, y = A v with the panel corrections, w
+            const T xn2 = dots[2 * J];
+            const T alpha = uc[s];
+            T beta, tau, scale;
+            if (xn2 == T(0)) {
+                tau = T(0); beta = alpha; scale = T(0);
+            } else {
+                const T nrm = sqrt(alpha * alpha + xn2);
+                beta = alpha >= T(0) ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scale = T(1) / (alpha - beta);
+            }
+            T xax = T(0);
+#pragma unroll
+            for (int q = 0; q < NW; q++) xax += xaxw[q];
+            const T ys = yy[s];
+            const T Ass = A[s + (long long)s * ld];
+            T corr[RPT], pq = T(0), corr_s = T(0);
+#pragma unroll
+            for (int t = 0; t < RPT; t++) corr[t] = T(0);
+            for (int k = 0; k < J; k++) {
+                const T Wsk = Wp[s + (long long)k * ldp], Vsk = Vp[s + (long long)k * ldp];
+                const T pk = Wsk + scale * dots[k];      // W(:,k)^T v
+                const T qk = Vsk + scale * dots[J + k];  // V(:,k)^T v
+                pq += pk * qk;
+                corr_s += Vsk * pk + Wsk * qk;
+#pragma unroll
+                for (int t = 0; t < RPT; t++) {
+                    const int r = min(tid + t * NT, n - 1);
+                    corr[t] += Vp[r + (long long)k * ldp] * pk + Wp[r + (long long)k * ldp] * qk;
+                }
+            }
+            // v^T A v (A with the panel's updates) = y^T v
+            const T vav = scale * scale * xax + T(2) * scale * ys + Ass - T(2) * pq;
+            const T half = T(0.5) * tau * tau * vav;
+            const T ws = tau * (scale * ys + Ass - corr_s) - half;
+#pragma unroll
+            for (int t = 0; t < RPT; t++) {
+                const int r = tid + t * NT;
+                if (r >= s && r < n) {
+                    const T v = r == s ? T(1) : scale * uc[r];
+                    const T wr = r == s ? ws : tau * (scale * yy[r] + A[r + (long long)s * ld] - corr[t]) - half * v;
+                    Vp[r + (long long)J * ldp] = v;
+                    Wp[r + (long long)J * ldp] = wr;
+                    A[r + (long long)i * ld] = v;
+                }
+            }
+            if (tid == 0) {
+                w.d[(long long)b * w.sD + i] = uc[i];
+                w.e[(long long)b * w.sD + i] = beta;
+                w.tau[(long long)b * w.sD + i] = tau;
+            }
+            ws_prev = ws;
+        }
+        // ---- panel update of the trailing matrix
+        __syncthreads();
+        wg_syr2k<T, NW>(A, ld, Vp, Wp, ldp, n, k0 + NBP);
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
 // Fused per-column path: one launch per column.
 //
 // The launch for column i first finishes column c = i - 1 (what the separate
@@ -1076,6 +1432,15 @@ __device__ void col_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt
 // fused launch costs more than the finish launch it saves; in FP64 the
 // fused launch's registers leave one wavefront per SIMD).
 #define SYTRD_FUSED_KT 3
+// Batches of at least this many matrices, all of order <= SYTRD_WG_NMAX,
+// take the one-workgroup-per-matrix path (0: never).  Measured on 512
+// molecules of orders 30..900: FP64 54 ms against 66 ms per reduction for the
+// per-column launches; FP32 37 ms against 34 ms, so FP32 keeps the
+// per-column launches (one workgroup streams its matrix far below the
+// device's bandwidth; in FP32 the per-column launches are cheap enough).
+template <typename T> struct SytrdWgMinBatch;
+template <> struct SytrdWgMinBatch<float> { static constexpr int value = 0; };
+template <> struct SytrdWgMinBatch<double> { static constexpr int value = 8; };
 template <typename T> struct SytrdFused;
 template <> struct SytrdFused<float> { static constexpr int max_order = 4000; };
 template <> struct SytrdFused<double> { static constexpr int max_order = 0; };
@@ -1237,6 +1602,36 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
         return e ? std::atoi(e) : -1;
     }();
     const int fused_max = env_max >= 0 ? env_max : SytrdFused<T>::max_order;
+    // batches of small matrices: one workgroup per matrix
+    static const int env_wg = [] {
+        const char* e = std::getenv("MBD_SYTRD_WG_MIN_BATCH");
+        return e ? std::atoi(e) : -1;
+    }();
+    const int wg_min = env_wg >= 0 ? env_wg : SytrdWgMinBatch<T>::value;
+    if (wg_min > 0 && nbatch >= wg_min && nmax <= SYTRD_WG_NMAX) {
+        if (sytrd_tail_start<T>(nmax) > 0) {
+            hipLaunchKernelGGL(sytrd_wg_order_kernel, dim3((nbatch + 255) / 256), dim3(256), 0, st, w.ns, nbatch,
+                               w.order);
+            auto k = sytrd_wg_kernel<T, SYTRD_WG_WAVES>;
+            if (timing) {
+                double bb = 0;
+                for (int b = 0; b < nbatch; b++) {
+                    const int kt = sytrd_tail_start<T>(ns_host[b]);
+                    for (int i = 0; i < kt; i++) {
+                        const double m = ns_host[b] - i - 1;
+                        bb += m * (m + 1) * 0.5 * sizeof(T);
+                    }
+                }
+                hipEvent_t e0, e1;
+                prof->pair(&e0, &e1, 10, bb);
+                hipExtLaunchKernelGGL(k, dim3(nbatch), dim3(64 * SYTRD_WG_WAVES), 0, st, e0, e1, 0, w);
+            } else {
+                hipLaunchKernelGGL(k, dim3(nbatch), dim3(64 * SYTRD_WG_WAVES), 0, st, w);
+            }
+        }
+        hipLaunchKernelGGL(sytrd_tail_kernel<T>, dim3(nbatch), dim3(SYTRD_TAIL_THREADS), 0, st, w);
+        return;
+    }
     hipLaunchKernelGGL(sytrd_zero_norm_kernel<T>, dim3((SYTRD_SLOTS * nbatch + 255) / 256), dim3(256), 0, st, w, nbatch);
     hipLaunchKernelGGL(sytrd_init_kernel<T>, dim3(nbk_max, 1, nbatch), dim3(256), 0, st, w);
     // panels up to the tail of the largest matrix (smaller ones drop out of

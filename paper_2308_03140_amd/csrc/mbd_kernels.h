@@ -12,7 +12,7 @@
 // assembly, 3 Householder reduction, 4 divide and conquer, 5 back-transform,
 // 6 refinement, 7 energy, Q^{-1/2} and gradients.  `work` is the algorithmic
 // bytes (kind 0) or flops (kind 1) of the launch, 0 for phases.
-#define PROF_KINDS 10
+#define PROF_KINDS 11
 struct LaunchProfiler {
     bool enabled = false;
     bool launches = true;  // per-launch records (kinds 0, 1); phases are always recorded when enabled
@@ -119,6 +119,7 @@ struct SytrdWs {
     T* d; T* e; T* tau; long long sD;      // outputs
     int chunk_target;                      // SYMV workgroups per launch, trailing sizes in the upper quarter (tuned)
     int chunk_target_lo;                   // the same below it (tuned)
+    int* order;                            // [nbatch] matrices by decreasing order (one-workgroup path)
 };
 template <typename T>
 void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, const int* ns_host,
@@ -156,6 +157,15 @@ struct StedcWs {
 // Returns 0 if the eigenvectors ended in Z0, 1 if in Z1.
 template <typename T>
 int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st);
+
+// Tridiagonals with a non-finite entry are replaced by zeros and flagged in
+// bad[b] (1, else 0): the merges of divide and conquer rank each half's poles
+// by binary search in the other, which assumes ordered values (a NaN makes
+// two poles share a position and leaves another unset, whose stale index
+// would then address the eigenvector blocks), and the multisection's
+// brackets assume finite bounds.
+template <typename T>
+void tridiag_guard_launch(const int* ns, int nbatch, T* d, T* e, long long sD, int* bad, hipStream_t st);
 
 // Eigenvalues only (Sturm counts with multisection, FP64 arithmetic): d, e of
 // the reduction ([nbatch] x sD), w [nbatch] x sW ascending.

@@ -275,6 +275,111 @@ sys.exit(0 if all(out) else 1)
 """
 
 
+_WG_CHILD = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import gen
+from paper_2308_03140_amd import torch_api as T
+out = []
+for dtype, tol in (("float64", 1e-12), ("float32", 3e-5)):
+    ctx = T.Context(0, "fp64")
+    for n, nb in ((1024, 8), (450, 9), (257, 9)):
+        As = np.stack([gen.random_symmetric(6000 + 31 * n + b, n) for b in range(nb)])
+        w, Z = T.eigh(ctx, torch.tensor(As, device="cuda", dtype=getattr(torch, dtype)))
+        torch.cuda.synchronize()
+        w = w.double().cpu().numpy(); Z = Z.double().cpu().numpy()
+        for b in range(nb):
+            A = As[b].astype(np.float32).astype(np.float64) if dtype == "float32" else As[b]
+            nrm = max(1.0, np.abs(A).sum(axis=1).max())
+            ev = np.abs(w[b] - np.linalg.eigvalsh(A)).max() / nrm
+            res = np.abs(A @ Z[b] - Z[b] * w[b]).max() / nrm
+            orth = np.abs(Z[b].T @ Z[b] - np.eye(n)).max()
+            ok = ev <= tol and res <= tol and orth <= tol * max(1, n / 100)
+            out.append(ok)
+        print("%s n=%d nb=%d %s" % (dtype, n, nb, "ok" if all(out) else "FAIL"), flush=True)
+    ctx.close()
+sys.exit(0 if all(out) else 1)
+"""
+
+
+@pytest.mark.parametrize("min_batch", [0, 8])
+def test_eigh_one_workgroup_path_choice(min_batch):
+    """The batch-size threshold of the one-workgroup-per-matrix reduction
+    set through MBD_SYTRD_WG_MIN_BATCH (read once per process, hence the
+    child process): 8 sends FP32 batches through it too (by default only
+    FP64 takes it), 0 sends FP64 batches through the per-column launches."""
+    import os
+    import subprocess
+    _note("one-workgroup path, min batch %d" % min_batch)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, MBD_SYTRD_WG_MIN_BATCH=str(min_batch))
+    r = subprocess.run([sys.executable, "-c", _WG_CHILD, root], env=env, capture_output=True, text=True,
+                       timeout=110)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr[-2000:]
+
+
+@pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 3e-5)])
+@pytest.mark.parametrize("n,nb", [(1024, 8), (450, 10), (257, 9), (193, 12)])
+def test_eigh_one_workgroup_batches(dtype, tol, n, nb):
+    """Batches of eight or more matrices of order <= 1024 (FP64 takes the
+    one-workgroup-per-matrix reduction, FP32 the per-column launches): the
+    largest order it takes, orders whose last panel ends just past the LDS
+    tail's start (257 in FP32, 193 in FP64: one panel) and one in between,
+    each matrix checked by residual, orthogonality and its eigenvalues
+    against LAPACK's (numpy)."""
+    from paper_2308_03140_amd import torch_api as T
+    _note("eigh one-workgroup batch n=%d nb=%d %s" % (n, nb, dtype))
+    c = T.Context(0, "fp64" if dtype == "float64" else "fp32_refined")
+    try:
+        As = np.stack([gen.random_symmetric(5000 + 37 * n + b, n) for b in range(nb)])
+        dt = torch.float64 if dtype == "float64" else torch.float32
+        w, Z = T.eigh(c, torch.tensor(As, device="cuda", dtype=dt))
+        w = w.double().cpu().numpy()
+        Z = Z.double().cpu().numpy()
+    finally:
+        c.close()
+    for b in range(nb):
+        A = As[b].astype(np.float32).astype(np.float64) if dtype == "float32" else As[b]
+        nrm = max(1.0, np.abs(A).sum(axis=1).max())
+        assert np.abs(w[b] - np.linalg.eigvalsh(A)).max() <= tol * nrm, b
+        assert np.abs(A @ Z[b] - Z[b] * w[b]).max() <= tol * nrm, b
+        assert np.abs(Z[b].T @ Z[b] - np.eye(n)).max() <= tol * max(1, n / 100), b
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("nb", [3, 9])
+def test_eigh_nonfinite_input_reported(dtype, nb):
+    """A NaN in one matrix of a batch (per-column path: 3 matrices; one
+    workgroup per matrix: 9) is reported as an invalid argument, the
+    tridiagonal solvers having seen zeros instead of it; the same context
+    then solves a clean batch correctly."""
+    from paper_2308_03140_amd import torch_api as T
+    _note("eigh non-finite input nb=%d %s" % (nb, dtype))
+    n = 300
+    dt = torch.float64 if dtype == "float64" else torch.float32
+    tol = 1e-12 if dtype == "float64" else 3e-5
+    c = T.Context(0, "fp64" if dtype == "float64" else "fp32_refined")
+    try:
+        As = np.stack([gen.random_symmetric(7100 + b, n) for b in range(nb)])
+        bad = As.copy()
+        bad[1, 17, 5] = bad[1, 5, 17] = np.nan
+        with pytest.raises(Exception):
+            T.eigh(c, torch.tensor(bad, device="cuda", dtype=dt))
+        w, Z = T.eigh(c, torch.tensor(As, device="cuda", dtype=dt))
+        w = w.double().cpu().numpy()
+        Z = Z.double().cpu().numpy()
+    finally:
+        c.close()
+    for b in range(nb):
+        A = As[b].astype(np.float32).astype(np.float64) if dtype == "float32" else As[b]
+        nrm = max(1.0, np.abs(A).sum(axis=1).max())
+        assert np.abs(w[b] - np.linalg.eigvalsh(A)).max() <= tol * nrm, b
+        assert np.abs(A @ Z[b] - Z[b] * w[b]).max() <= tol * nrm, b
+
+
 @pytest.mark.parametrize("max_order", [0, 1000000])
 def test_eigh_reduction_paths(max_order):
     """Both per-column paths of the reduction in both precisions: the fused
