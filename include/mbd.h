@@ -278,8 +278,8 @@ mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
  * Kind 9 is the screening stage of mbd_rsscs_evaluate (assembly, Cholesky
  * factorisation and solves, contraction; and the chain rule of its gradient).
  * Kind 10 is the single launch that reduces a batch of small matrices with
- * one workgroup per matrix (FP64 batches of 8 or more matrices of order
- * <= 1024).  Enabling clears earlier records.  mbd_get_profile synchronises
+ * one workgroup per matrix (FP64 batches of 256 or more matrices of
+ * order <= 1024).  Enabling clears earlier records.  mbd_get_profile synchronises
  * the stream and returns, for one kind (0..10), the summed event time (ms),
  * the number of records and the summed algorithmic work: bytes of the lower
  * trailing triangle read (kinds 0, 8 and 10), flops of the rank-2k update

@@ -1433,14 +1433,16 @@ __device__ void col_item(const SytrdWs<T>& w, int b, int n, int i, int j, int Kt
 // fused launch's registers leave one wavefront per SIMD).
 #define SYTRD_FUSED_KT 3
 // Batches of at least this many matrices, all of order <= SYTRD_WG_NMAX,
-// take the one-workgroup-per-matrix path (0: never).  Measured on 512
-// molecules of orders 30..900: FP64 54 ms against 66 ms per reduction for the
-// per-column launches; FP32 37 ms against 34 ms, so FP32 keeps the
-// per-column launches (one workgroup streams its matrix far below the
-// device's bandwidth; in FP32 the per-column launches are cheap enough).
+// take the one-workgroup-per-matrix path (0: never).  One workgroup streams
+// its matrix far below the device's bandwidth, so the path needs a batch
+// that fills the 256 compute units.  Measured on 512 molecules of orders
+// 30..900: FP64 54 ms against 66 ms per reduction for the per-column
+// launches, FP32 37 ms against 34 ms (FP32 keeps the per-column launches);
+// on 64 matrices of order 384 (a periodic cell's q-points) FP64 4.5 ms
+// against about 3 ms.
 template <typename T> struct SytrdWgMinBatch;
 template <> struct SytrdWgMinBatch<float> { static constexpr int value = 0; };
-template <> struct SytrdWgMinBatch<double> { static constexpr int value = 8; };
+template <> struct SytrdWgMinBatch<double> { static constexpr int value = 256; };
 template <typename T> struct SytrdFused;
 template <> struct SytrdFused<float> { static constexpr int max_order = 4000; };
 template <> struct SytrdFused<double> { static constexpr int max_order = 0; };

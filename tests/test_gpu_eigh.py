@@ -308,8 +308,9 @@ sys.exit(0 if all(out) else 1)
 def test_eigh_one_workgroup_path_choice(min_batch):
     """The batch-size threshold of the one-workgroup-per-matrix reduction
     set through MBD_SYTRD_WG_MIN_BATCH (read once per process, hence the
-    child process): 8 sends FP32 batches through it too (by default only
-    FP64 takes it), 0 sends FP64 batches through the per-column launches."""
+    child process): 8 sends these batches of 8 and 9 matrices through it in
+    both precisions (by default only FP64 batches of 256 or more take it),
+    0 sends every batch through the per-column launches."""
     import os
     import subprocess
     _note("one-workgroup path, min batch %d" % min_batch)
@@ -324,12 +325,11 @@ def test_eigh_one_workgroup_path_choice(min_batch):
 @pytest.mark.parametrize("dtype,tol", [("float64", 1e-12), ("float32", 3e-5)])
 @pytest.mark.parametrize("n,nb", [(1024, 8), (450, 10), (257, 9), (193, 12)])
 def test_eigh_one_workgroup_batches(dtype, tol, n, nb):
-    """Batches of eight or more matrices of order <= 1024 (FP64 takes the
-    one-workgroup-per-matrix reduction, FP32 the per-column launches): the
-    largest order it takes, orders whose last panel ends just past the LDS
-    tail's start (257 in FP32, 193 in FP64: one panel) and one in between,
-    each matrix checked by residual, orthogonality and its eigenvalues
-    against LAPACK's (numpy)."""
+    """Batches of 8 to 12 matrices of order <= 1024 through the default
+    (per-column) reduction: the largest order the one-workgroup path would
+    take, orders whose last panel ends just past the LDS tail's start (257 in
+    FP32, 193 in FP64: one panel) and one in between, each matrix checked by
+    residual, orthogonality and its eigenvalues against LAPACK's (numpy)."""
     from paper_2308_03140_amd import torch_api as T
     _note("eigh one-workgroup batch n=%d nb=%d %s" % (n, nb, dtype))
     c = T.Context(0, "fp64" if dtype == "float64" else "fp32_refined")
