@@ -94,7 +94,12 @@ typedef struct {
     const double *lattice;        /* [3][3] bohr, rows = lattice vectors, or NULL
                                      for a finite system (HOST pointer)          */
     int32_t n_q;                  /* periodic: number of q points in q_frac, or 0
-                                     to use the Monkhorst-Pack mesh kgrid/kshift */
+                                     to use the Monkhorst-Pack mesh kgrid/kshift.
+                                     Points q, q' with q + q' an integer vector
+                                     (time-reversed partners) give the same
+                                     energy and gradient contributions; unless
+                                     eigenvalues are requested, one of each such
+                                     pair is evaluated, with weight 2 */
     const double *q_frac;         /* [n_q][3] fractional coordinates in the
                                      reciprocal basis (HOST pointer)             */
     int32_t kgrid[3];             /* periodic mesh size when n_q == 0 (each >= 1) */

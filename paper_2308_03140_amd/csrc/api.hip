@@ -379,8 +379,46 @@ __global__ void grad_gate_kernel(const unsigned* status, int nsys, SysDesc* sd) 
 // integer image list of the real-space sum and the reciprocal-vector list.
 struct PeriodicSetup {
     std::vector<double> qcart;
+    std::vector<double> qmult;  // weight of each q point (2: it stands for its time-reversed partner too)
     std::vector<int> img, rec;
+    int nq_all = 0;             // q points of the mesh before pairing
 };
+
+// Time reversal: Q(-q) is the complex conjugate of Q(q) (the lattice sums
+// are real), and Q(q + G) the similarity D Q(q) D^* with the diagonal phases
+// D = diag(exp(-i G.R_i)), whose derivative terms cancel in the gradient
+// (D^* dD is imaginary and diagonal, Q^{1/2} Hermitian).  So a mesh point
+// whose negative is also in the mesh, modulo the reciprocal lattice,
+// contributes exactly what that partner does to the energy (eq:brillouin-int)
+// and to every gradient (eq:mbd-gradient): one of each such pair is kept
+// with weight 2.  Fractions as given; a pair must sum to an integer vector
+// within 1e-10.
+void pair_time_reversal(const std::vector<double>& qf, std::vector<double>& rep, std::vector<double>& mult) {
+    const int nq = (int)qf.size() / 3;
+    std::vector<char> used(nq, 0);
+    rep.clear();
+    mult.clear();
+    for (int t = 0; t < nq; t++) {
+        if (used[t]) continue;
+        used[t] = 1;
+        double m = 1.0;
+        for (int u = t + 1; u < nq; u++) {
+            if (used[u]) continue;
+            bool match = true;
+            for (int k = 0; k < 3; k++) {
+                const double sum = qf[3 * t + k] + qf[3 * u + k];
+                if (std::fabs(sum - std::nearbyint(sum)) > 1e-10) match = false;
+            }
+            if (match) {
+                used[u] = 1;
+                m = 2.0;
+                break;
+            }
+        }
+        for (int k = 0; k < 3; k++) rep.push_back(qf[3 * t + k]);
+        mult.push_back(m);
+    }
+}
 
 void inv3(const double* A, double* Ai) {
     const double dt = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
@@ -394,7 +432,7 @@ void inv3(const double* A, double* Ai) {
 
 // Lattice, Ewald parameters (defaults of the paper's Sec. 3.3 when not
 // given), q mesh and term lists.  Reads coords and R_vdW back to the host.
-mbd_status setup_periodic(mbd_ctx* c, const mbd_system* s, SysDesc& d, PeriodicSetup& ps) {
+mbd_status setup_periodic(mbd_ctx* c, const mbd_system* s, SysDesc& d, PeriodicSetup& ps, bool pair_q = false) {
     const double* A = s->lattice;
     for (int k = 0; k < 9; k++) {
         if (!std::isfinite(A[k])) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate", "non-finite lattice");
@@ -446,6 +484,14 @@ mbd_status setup_periodic(mbd_ctx* c, const mbd_system* s, SysDesc& d, PeriodicS
                     for (int k = 0; k < 3; k++)
                         qf.push_back((2.0 * r3[k] - s->kgrid[k] - 1) / (2.0 * s->kgrid[k]) + s->kshift[k]);
                 }
+    }
+    ps.nq_all = (int)qf.size() / 3;
+    if (pair_q) {
+        std::vector<double> rep;
+        pair_time_reversal(qf, rep, ps.qmult);
+        qf.swap(rep);
+    } else {
+        ps.qmult.assign(qf.size() / 3, 1.0);
     }
     double qmax = 0.0;
     for (size_t t = 0; t < qf.size() / 3; t++) {
@@ -503,7 +549,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     for (int s = 0; s < nsys; s++) {
         sds[s].mat0 = per ? 0 : s;
         sds[s].nmat = per ? nq : 1;
-        sds[s].weight = per ? 0.25 / nq : 0.5;
+        sds[s].weight = per ? 0.25 / per->nq_all : 0.5;
         sds[s].embed = per ? 1 : 0;
     }
     const int nmax = per ? 6 * Nmax : 3 * Nmax;
@@ -540,14 +586,17 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     fill_u32_launch(st, status, nsys, 0u);
     mbd_prep_launch(st, sd_dev, nsys, Nmax, om, cc, status);
     double* qcart = nullptr;
+    double* qmult = nullptr;
     int* img = nullptr;
     int* rec = nullptr;
     if (per) {
         qcart = wsT<double>(c, "qcart", per->qcart.size());
+        qmult = wsT<double>(c, "qmult", (size_t)nq);
         img = wsT<int>(c, "img", per->img.size());
         rec = wsT<int>(c, "rec", per->rec.size());
-        if (!qcart || !img || !rec) return (mbd_status)c->err_code;
+        if (!qcart || !qmult || !img || !rec) return (mbd_status)c->err_code;
         HIPCHK(hipMemcpyAsync(qcart, per->qcart.data(), sizeof(double) * per->qcart.size(), hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(hipMemcpyAsync(qmult, per->qmult.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(img, per->img.data(), sizeof(int) * per->img.size(), hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(rec, per->rec.data(), sizeof(int) * per->rec.size(), hipMemcpyHostToDevice, st), "upload");
         mbd_assemble_periodic_launch(st, sd_dev, om, cc, qcart, nq, img, (int)per->img.size() / 3, rec,
@@ -606,7 +655,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     hipLaunchKernelGGL(eig_bad_status_kernel, dim3((nmat + 63) / 64), dim3(64), 0, st, eig_bad, nmat, status,
                        per ? 1 : 0);
     PhaseTimer ph_eg(&c->prof, st, 7);
-    mbd_energy_launch(st, sd_dev, nsys, ns_dev, lam, nmax, om, status, lmin, conv_dev);
+    mbd_energy_launch(st, sd_dev, nsys, ns_dev, lam, nmax, om, status, lmin, conv_dev, per ? qmult : nullptr);
     mbd_errors_launch(st, sd_dev, nsys, nmat, stats, skip_dev);
     HIPCHK(hipGetLastError(), "energy");
     if (grads) {
@@ -619,8 +668,8 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
             const int N = sds[0].N;
             double* part = wsT<double>(c, "gpart", (size_t)nq * N * N * PER_PART);
             if (!part) return (mbd_status)c->err_code;
-            mbd_grad_periodic_launch(st, sd_dev, om, cc, qcart, nq, img, (int)per->img.size() / 3, rec,
-                                     (int)per->rec.size() / 3, M, part, N);
+            mbd_grad_periodic_launch(st, sd_dev, om, cc, qcart, qmult, 0.25 / per->nq_all, nq, img,
+                                     (int)per->img.size() / 3, rec, (int)per->rec.size() / 3, M, part, N);
         } else {
             mbd_grad_finite_launch(st, sd_dev, nsys, Nmax, om, cc, M);
         }
@@ -755,7 +804,9 @@ mbd_status mbd_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_resu
     std::vector<int> codes;
     if (s->lattice) {
         PeriodicSetup ps;
-        r = setup_periodic(c, s, sds[0], ps);
+        // eigenvalues are returned per mesh point, so only without them are
+        // time-reversed pairs evaluated once
+        r = setup_periodic(c, s, sds[0], ps, !(want & MBD_WANT_EIGVALS));
         if (r != MBD_OK) return r;
         r = run_core(c, sds, want, codes, &ps);
         if (r == MBD_OK) r = refine_fallback(c, sds, want, codes, &ps);

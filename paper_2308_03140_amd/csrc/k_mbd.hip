@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void mbd_assemble_finite_kernel(const SysDesc*
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void mbd_energy_kernel(const SysDesc* sd, const int* ns, const double* lam,
                                                            long long sL, const double* om, unsigned* status,
-                                                           double* lmin_out, const int* conv) {
+                                                           double* lmin_out, const int* conv, const double* mmult) {
     __shared__ double red[4];
     const int s = blockIdx.x;
     const SysDesc& S = sd[s];
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void mbd_energy_kernel(const SysDesc* sd, cons
         }
         part = block_sum256(part, red);
         mn = -block_max256(-mn, red);
-        esum += S.weight * part;
+        esum += S.weight * (mmult ? mmult[b] : 1.0) * part;
         lmin = fmin(lmin, mn);
     }
     double wsum = 0.0;
@@ -334,8 +334,9 @@ void mbd_assemble_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int
 }
 
 void mbd_energy_launch(hipStream_t st, const SysDesc* sd, int nsys, const int* ns, const double* lam, long long sL,
-                       const double* om, unsigned* status, double* lmin, const int* conv) {
-    hipLaunchKernelGGL(mbd_energy_kernel, dim3(nsys), dim3(256), 0, st, sd, ns, lam, sL, om, status, lmin, conv);
+                       const double* om, unsigned* status, double* lmin, const int* conv, const double* mmult) {
+    hipLaunchKernelGGL(mbd_energy_kernel, dim3(nsys), dim3(256), 0, st, sd, ns, lam, sL, om, status, lmin, conv,
+                       mmult);
 }
 
 void mbd_errors_launch(hipStream_t st, const SysDesc* sd, int nsys, int nmat, const double* stats, const int* one) {

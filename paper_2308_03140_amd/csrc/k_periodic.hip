@@ -376,7 +376,8 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
 }
 
 // per-atom reduction in a fixed order; atom N (one extra block) sums the lattice term
-__global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const SysDesc* sd, int nq, const double* om,
+__global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const SysDesc* sd, int nq, const double* qmult,
+                                                                         double wq, const double* om,
                                                                          const double* cc, const double* part,
                                                                          MatBatch<double> M) {
     __shared__ double red[4];
@@ -384,7 +385,6 @@ __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const Sys
     const int N = S.N;
     if (N == 0) return;
     const int k = blockIdx.x;
-    const double wq = 0.25 / nq;
     if (k < N) {
         double g0 = 0, g1 = 0, g2 = 0, ga = 0, gv = 0, tr = 0;
         const long long NN = (long long)N * N;
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const Sys
             // k as j (second index), partner i = o
             const double* pj = part + ((long long)q * NN + (long long)k * N + o) * PER_PART;   // pid = i + j*N: i=o, j=k
             const double* pi = part + ((long long)q * NN + (long long)o * N + k) * PER_PART;   // i=k, j=o
-            const double cj = cc[S.atom_off + o] * cc[S.atom_off + k];
+            const double cj = qmult[q] * cc[S.atom_off + o] * cc[S.atom_off + k];
             if (o != k) {
                 g0 += cj * (pj[1] - pi[1]);
                 g1 += cj * (pj[2] - pi[2]);
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const Sys
         // Re Tr M_kk(q), summed over q
         for (int q = threadIdx.x; q < nq; q += 256) {
             const double* Mb = M.at(q);
-            for (int c = 0; c < 3; c++) tr += Mb[(3 * k + c) + (long long)(3 * k + c) * M.ld];
+            for (int c = 0; c < 3; c++) tr += qmult[q] * Mb[(3 * k + c) + (long long)(3 * k + c) * M.ld];
         }
         g0 = block_sum256(g0, red);
         g1 = block_sum256(g1, red);
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const Sys
         for (long long idx = threadIdx.x; idx < total; idx += 256) {
             const long long pid = idx % ((long long)N * N);
             const int i = (int)(pid % N), j = (int)(pid / N);
-            const double cij = cc[S.atom_off + i] * cc[S.atom_off + j];
+            const double cij = qmult[idx / ((long long)N * N)] * cc[S.atom_off + i] * cc[S.atom_off + j];
             const double* p = part + idx * PER_PART;
             for (int v = 0; v < 9; v++) la[v] += cij * p[4 + v];
         }
@@ -460,10 +460,11 @@ void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const doubl
 }
 
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
-                              const double* qcart, int nq, const int* img, int nimg, const int* rec, int nrec,
-                              MatBatch<double> M, double* partial, int N) {
+                              const double* qcart, const double* qmult, double wq, int nq, const int* img,
+                              int nimg, const int* rec, int nrec, MatBatch<double> M, double* partial, int N) {
     const long long pairs = (long long)N * N;
     hipLaunchKernelGGL(mbd_grad_periodic_kernel, dim3((unsigned)pairs, (nq + PER_LANES - 1) / PER_LANES),
                        dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, img, nimg, rec, nrec, M, partial);
-    hipLaunchKernelGGL(mbd_grad_periodic_reduce_kernel, dim3(N + 1), dim3(256), 0, st, sd, nq, om, cc, partial, M);
+    hipLaunchKernelGGL(mbd_grad_periodic_reduce_kernel, dim3(N + 1), dim3(256), 0, st, sd, nq, qmult, wq, om, cc,
+                       partial, M);
 }

@@ -31,8 +31,11 @@ void mbd_prep_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, doub
                      unsigned* status);
 void mbd_assemble_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nmax, const double* om,
                                 const double* cc, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status);
+// mmult (may be null: all 1): weight of each matrix's eigenvalue sum, a
+// multiple of the system's weight
 void mbd_energy_launch(hipStream_t st, const SysDesc* sd, int nsys, const int* ns, const double* lam,
-                       long long sL, const double* om, unsigned* status, double* lmin, const int* conv);
+                       long long sL, const double* om, unsigned* status, double* lmin, const int* conv,
+                       const double* mmult = nullptr);
 void mbd_errors_launch(hipStream_t st, const SysDesc* sd, int nsys, int nmat, const double* stats, const int* one);
 void mbd_invsqrt4_launch(hipStream_t st, const int* ns, int nmax, int nbatch, const double* lam, long long sL,
                          double* sc);
@@ -78,9 +81,11 @@ void fill_sym_random_launch(hipStream_t st, int n, T* A, int ld, unsigned seed);
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                                   const double* qcart, int nq, const int* img, int nimg, const int* rec,
                                   int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N);
+// qmult[q]: weight of q point q (2 where it stands for its time-reversed
+// partner); wq: the Brillouin-zone weight 1/4 per mesh point of all of them
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
-                              const double* qcart, int nq, const int* img, int nimg, const int* rec, int nrec,
-                              MatBatch<double> M, double* partial, int N);
+                              const double* qcart, const double* qmult, double wq, int nq, const int* img,
+                              int nimg, const int* rec, int nrec, MatBatch<double> M, double* partial, int N);
 
 // pairwise (TS) dispersion: per-atom energy shares into eatom, gradients into
 // the descriptor's outputs, then the energy (and errors[0..3] = 0)
