@@ -101,25 +101,30 @@ __device__ __forceinline__ bool image_term(const double* x, double gamma, double
     return true;
 }
 
-// one thread per (q, i, j): assemble the embedded Q(q)
-// One workgroup per ordered atom pair (i, j), one lane per q-point (grid y
-// covers q-points in groups of 64).  The real-space image terms depend on the
-// pair and the image only: each is formed once, by one lane, into LDS (in
-// groups of 64 images), and every lane adds it with its own phase e^{-i q.x}.
+// Assembly of the embedded Q(q).  A wavefront holds 64 / lpp ordered atom
+// pairs (i, j), lpp lanes each, one lane per q-point (lpp: the q count
+// rounded up to a power of two, at most 64; grid y covers further groups of
+// q-points).  The real-space image terms depend on the pair and the image
+// only: each is formed once, by one lane of its pair, into LDS (lpp images
+// per round), and every lane of the pair adds it with its own phase
+// e^{-i q.x}.  Lanes of a pair index past N^2 follow the barriers and store
+// nothing.
 #define PER_LANES 64
 __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const SysDesc* sd, const double* om,
                                                                           const double* cc, const double* qcart,
-                                                                          int nq, const int* img, int nimg,
+                                                                          int nq, int lpp, const int* img, int nimg,
                                                                           const int* rec, int nrec, MatBatch<double> Q,
                                                                           MatBatch<float> Q32, unsigned* status) {
     __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9];
     __shared__ int oks[PER_LANES];
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
-    const int q = blockIdx.y * PER_LANES + threadIdx.x;
-    const bool qv_ok = q < nq;
-    const long long pid = blockIdx.x;
-    if (pid >= (long long)N * N) return;
+    const int slot = threadIdx.x / lpp, ql = threadIdx.x % lpp;
+    const long long pid0 = (long long)blockIdx.x * (PER_LANES / lpp) + slot;
+    const bool pv = pid0 < (long long)N * N;
+    const long long pid = pv ? pid0 : 0;
+    const int q = blockIdx.y * lpp + ql;
+    const bool qv_ok = pv && q < nq;
     const int i = (int)(pid % N), j = (int)(pid / N);
     const double* R = S.coords;
     const double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
@@ -128,9 +133,9 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
     const double R0 = S.beta * (S.rvdw[i] + S.rvdw[j]);
     double Tre[9], Tim[9];
     for (int k = 0; k < 9; k++) { Tre[k] = 0.0; Tim[k] = 0.0; }
-    for (int t0 = 0; t0 < nimg; t0 += PER_LANES) {
+    for (int t0 = 0; t0 < nimg; t0 += lpp) {
         {
-            const int t = t0 + (int)threadIdx.x;
+            const int t = t0 + ql;
             int ok = 0;
             if (t < nimg) {
                 const double n0 = img[3 * t], n1 = img[3 * t + 1], n2 = img[3 * t + 2];
@@ -138,7 +143,7 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
                 for (int c = 0; c < 3; c++) x[c] = r[c] + n0 * S.lat[c] + n1 * S.lat[3 + c] + n2 * S.lat[6 + c];
                 const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
                 if (d2 != 0.0) {
-                    if (i != j && d2 < 1e-16 && blockIdx.y == 0) atomicOr(&status[0], MBD_ST_COINCIDENT);
+                    if (pv && i != j && d2 < 1e-16 && blockIdx.y == 0) atomicOr(&status[0], MBD_ST_COINCIDENT);
                     double F[9];
                     if (image_term(x, S.gamma, S.rc, R0, S.a, F, nullptr)) {
                         ok = 1;
@@ -150,8 +155,9 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
             oks[threadIdx.x] = ok;
         }
         __syncthreads();
-        const int tn = min(PER_LANES, nimg - t0);
-        for (int u = 0; u < tn; u++) {
+        const int tn = min(lpp, nimg - t0);
+        for (int u0 = 0; u0 < tn; u0++) {
+            const int u = slot * lpp + u0;
             if (!oks[u]) continue;
             double sph, cph;
             sincos(-(qv[0] * xs[u][0] + qv[1] * xs[u][1] + qv[2] * xs[u][2]), &sph, &cph);
@@ -228,17 +234,20 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
 // into LDS and added by every lane with its own phase and M(q).
 __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysDesc* sd, const double* om,
                                                                       const double* cc, const double* qcart, int nq,
-                                                                      const int* img, int nimg, const int* rec,
-                                                                      int nrec, MatBatch<double> M, double* part) {
+                                                                      int lpp, const int* img, int nimg,
+                                                                      const int* rec, int nrec, MatBatch<double> M,
+                                                                      double* part) {
     __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9], dFs[PER_LANES][27], F0s[PER_LANES][9];
     __shared__ int ns_[PER_LANES][3], oks[PER_LANES];
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
-    const int q0 = blockIdx.y * PER_LANES + threadIdx.x;
-    const bool qv_ok = q0 < nq;
-    const int q = qv_ok ? q0 : 0;
-    const long long pid = blockIdx.x;
-    if (pid >= (long long)N * N) return;
+    const int slot = threadIdx.x / lpp, ql = threadIdx.x % lpp;
+    const long long pid0 = (long long)blockIdx.x * (PER_LANES / lpp) + slot;
+    const bool pv = pid0 < (long long)N * N;
+    const long long pid = pv ? pid0 : 0;
+    const int q0 = blockIdx.y * lpp + ql;
+    const bool qv_ok = pv && q0 < nq;
+    const int q = q0 < nq ? q0 : 0;
     const int i = (int)(pid % N), j = (int)(pid / N);
     double* out = part + ((long long)q * N * N + pid) * PER_PART;
     if (S.N == 0) return;
@@ -259,9 +268,9 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
     for (int v = 0; v < 3; v++) rho[v] = S.linv[v] * r[0] + S.linv[3 + v] * r[1] + S.linv[6 + v] * r[2];
     double P = 0.0, P0 = 0.0, dR[3] = {0, 0, 0}, dA[9];
     for (int k = 0; k < 9; k++) dA[k] = 0.0;
-    for (int t0 = 0; t0 < nimg; t0 += PER_LANES) {
+    for (int t0 = 0; t0 < nimg; t0 += lpp) {
         {
-            const int t = t0 + (int)threadIdx.x;
+            const int t = t0 + ql;
             int ok = 0;
             if (t < nimg) {
                 const int nn[3] = {img[3 * t], img[3 * t + 1], img[3 * t + 2]};
@@ -280,8 +289,9 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
             oks[threadIdx.x] = ok;
         }
         __syncthreads();
-        const int tn = min(PER_LANES, nimg - t0);
-        for (int u = 0; u < tn; u++) {
+        const int tn = min(lpp, nimg - t0);
+        for (int u0 = 0; u0 < tn; u0++) {
+        const int u = slot * lpp + u0;
         if (!oks[u]) continue;
         const double* x = xs[u];
         const double* F = Fs[u];
@@ -451,20 +461,29 @@ __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const Sys
     }
 }
 
+// lanes per atom pair: the q count rounded up to a power of two, at most 64
+static int per_lanes_per_pair(int nq) {
+    int l = 1;
+    while (l < nq && l < PER_LANES) l *= 2;
+    return l;
+}
+
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                                   const double* qcart, int nq, const int* img, int nimg, const int* rec,
                                   int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N) {
     const long long pairs = (long long)N * N;
-    hipLaunchKernelGGL(mbd_assemble_periodic_kernel, dim3((unsigned)pairs, (nq + PER_LANES - 1) / PER_LANES),
-                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, img, nimg, rec, nrec, Q, Q32, status);
+    const int lpp = per_lanes_per_pair(nq), ppw = PER_LANES / lpp;
+    hipLaunchKernelGGL(mbd_assemble_periodic_kernel, dim3((unsigned)((pairs + ppw - 1) / ppw), (nq + lpp - 1) / lpp),
+                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, rec, nrec, Q, Q32, status);
 }
 
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                               const double* qcart, const double* qmult, double wq, int nq, const int* img,
                               int nimg, const int* rec, int nrec, MatBatch<double> M, double* partial, int N) {
     const long long pairs = (long long)N * N;
-    hipLaunchKernelGGL(mbd_grad_periodic_kernel, dim3((unsigned)pairs, (nq + PER_LANES - 1) / PER_LANES),
-                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, img, nimg, rec, nrec, M, partial);
+    const int lpp = per_lanes_per_pair(nq), ppw = PER_LANES / lpp;
+    hipLaunchKernelGGL(mbd_grad_periodic_kernel, dim3((unsigned)((pairs + ppw - 1) / ppw), (nq + lpp - 1) / lpp),
+                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, rec, nrec, M, partial);
     hipLaunchKernelGGL(mbd_grad_periodic_reduce_kernel, dim3(N + 1), dim3(256), 0, st, sd, nq, qmult, wq, om, cc,
                        partial, M);
 }
