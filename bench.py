@@ -670,7 +670,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="c2,batch,periodic,ts,freq,rsscs")
+    ap.add_argument("--legs", default="c2,batch,periodic,ts,freq,rsscs",
+                    help="legs to run; without c2 the named legs run alone and print their results only")
     ap.add_argument("--tuning-dir", default=None, help="write the autotuner tables (JSON) here")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write the SYMV HBM-traffic file under profiles/ from two --pmc-pass counter runs")
@@ -707,6 +708,17 @@ def main():
 
     if args.pmc_pass:
         pmc_pass(torch, T)
+        return
+    if "c2" not in legs:
+        # secondary legs on their own (profiling runs): their results only,
+        # not the benchmark line
+        out = {}
+        for name, fn in (("batch", lambda: leg_batch(args, torch, T)), ("periodic", lambda: leg_periodic(args, torch, T)),
+                         ("ts", lambda: leg_ts(args, torch, T)), ("freq", lambda: leg_freq(args, torch, T, A)),
+                         ("rsscs", lambda: leg_rsscs(args, torch, T, A))):
+            if name in legs:
+                out[name] = fn()
+        print(json.dumps(out), flush=True)
         return
     r = leg_c2(args, torch, T, A)
     e64, e32 = r["fp64"]["out"], r["fp32_refined"]["out"]
