@@ -685,17 +685,38 @@ template <typename T> struct WgDepth;
 template <> struct WgDepth<float> { static constexpr int value = 6; };
 template <> struct WgDepth<double> { static constexpr int value = 3; };
 
-// order[k] = the matrix of k-th largest order (ties by index)
-__global__ __launch_bounds__(256) void sytrd_wg_order_kernel(const int* ns, int nbatch, int* order) {
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= nbatch) return;
-    const int nb = ns[b];
-    int pos = 0;
-    for (int o = 0; o < nbatch; o++) {
-        const int no = ns[o];
-        pos += (no > nb || (no == nb && o < b)) ? 1 : 0;
+// order: the matrices by decreasing order (counting sort over the orders
+// 0..SYTRD_WG_NMAX in one workgroup; the order among equal sizes is that of
+// the atomics)
+__global__ __launch_bounds__(1024) void sytrd_wg_order_kernel(const int* ns, int nbatch, int* order) {
+    constexpr int NB = SYTRD_WG_NMAX + 1;
+    __shared__ int cnt[NB];
+    __shared__ int wsum[16];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < NB; k += 1024) cnt[k] = 0;
+    __syncthreads();
+    for (int b = tid; b < nbatch; b += 1024) atomicAdd(&cnt[SYTRD_WG_NMAX - min(ns[b], SYTRD_WG_NMAX)], 1);
+    __syncthreads();
+    // exclusive prefix sum of the bin counts: two bins per thread (NB <= 2048)
+    static_assert(NB <= 2048, "two bins per thread");
+    const int k0 = 2 * tid;
+    const int c0 = k0 < NB ? cnt[k0] : 0, c1 = k0 + 1 < NB ? cnt[k0 + 1] : 0;
+    int v = c0 + c1;
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
     }
-    order[pos] = b;
+    if (lane == 63) wsum[wv] = v;
+    __syncthreads();
+    int base = 0;
+    for (int q = 0; q < wv; q++) base += wsum[q];
+    const int excl = base + v - (c0 + c1);
+    __syncthreads();
+    if (k0 < NB) cnt[k0] = excl;
+    if (k0 + 1 < NB) cnt[k0 + 1] = excl + c0;
+    __syncthreads();
+    for (int b = tid; b < nbatch; b += 1024) order[atomicAdd(&cnt[SYTRD_WG_NMAX - min(ns[b], SYTRD_WG_NMAX)], 1)] = b;
 }
 
 // A(t0:n, t0:n) -= V W^T + W V^T on the lower triangle, K = 2 NBP, on the
@@ -1612,8 +1633,7 @@ void sytrd_launch(const SytrdWs<T>& w, int nbatch, int nmax, hipStream_t st, con
     const int wg_min = env_wg >= 0 ? env_wg : SytrdWgMinBatch<T>::value;
     if (wg_min > 0 && nbatch >= wg_min && nmax <= SYTRD_WG_NMAX) {
         if (sytrd_tail_start<T>(nmax) > 0) {
-            hipLaunchKernelGGL(sytrd_wg_order_kernel, dim3((nbatch + 255) / 256), dim3(256), 0, st, w.ns, nbatch,
-                               w.order);
+            hipLaunchKernelGGL(sytrd_wg_order_kernel, dim3(1), dim3(1024), 0, st, w.ns, nbatch, w.order);
             auto k = sytrd_wg_kernel<T, SYTRD_WG_WAVES>;
             if (timing) {
                 double bb = 0;

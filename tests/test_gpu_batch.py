@@ -75,8 +75,9 @@ def test_batch_repeat_and_status(ctx):
 
 def test_molecule_batch_512():
     """The 512-molecule workload (N ~ U{10..300}) in one batched call with
-    FP32 + refinement: every molecule against the FP64 GPU path, and a seeded
-    sample (plus the largest molecule) against the oracle."""
+    FP32 + refinement: every molecule against the FP64 GPU path (which
+    reduces this batch with one workgroup per matrix, largest first), and a
+    seeded sample (plus the largest molecule) against the oracle in both."""
     from paper_2308_03140_amd import torch_api as T
     _note("molecule batch 512")
     mols = gen.molecule_batch()
