@@ -285,7 +285,7 @@ from paper_2308_03140_amd import torch_api as T
 out = []
 for dtype, tol in (("float64", 1e-12), ("float32", 3e-5)):
     ctx = T.Context(0, "fp64")
-    for n, nb in ((1024, 8), (450, 9), (257, 9)):
+    for n, nb in ((1024, 8), (450, 9), (257, 9), (193, 9)):
         As = np.stack([gen.random_symmetric(6000 + 31 * n + b, n) for b in range(nb)])
         w, Z = T.eigh(ctx, torch.tensor(As, device="cuda", dtype=getattr(torch, dtype)))
         torch.cuda.synchronize()
