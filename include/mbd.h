@@ -73,6 +73,19 @@ typedef enum {
  * remainder threshold, default 3e-5. */
 typedef enum { MBD_FP64 = 0, MBD_FP32_REFINED = 1 } mbd_precision;
 
+/* Environment variables read by the library (once per process unless noted):
+ *   MBD_REFINE_TOL, MBD_REFINE_FALLBACK   see mbd_precision (at mbd_create)
+ *   MBD_WORKSPACE_LIMIT    cap on a context's device workspace, bytes
+ *   MBD_NO_GRAPH=1         mbd_evaluate_batch runs eagerly instead of
+ *                          replaying a captured graph (read per call)
+ *   MBD_SYTRD_FUSED_MAXN   largest trailing order reduced by one fused launch
+ *                          per column (default 4000 in FP32, 0 in FP64)
+ *   MBD_SYTRD_WG_MIN_BATCH smallest batch of matrices of order <= 1024 that
+ *                          is reduced with one workgroup per matrix (default
+ *                          256 in FP64; FP32 only when set; 0: never)
+ * The last two choose between reduction paths of equal results (to
+ * rounding); they exist for measurement and tests. */
+
 /* Second oscillator parameter: omega (Ha) or C6 (Ha bohr^6), related by
  * 4 C6 = 3 omega alpha0^2 (Sec. 2.1, eq:osc-param). */
 typedef enum { MBD_PARAM_OMEGA = 0, MBD_PARAM_C6 = 1 } mbd_param_kind;
