@@ -75,7 +75,8 @@ typedef enum { MBD_FP64 = 0, MBD_FP32_REFINED = 1 } mbd_precision;
 
 /* Environment variables read by the library (once per process unless noted):
  *   MBD_REFINE_TOL, MBD_REFINE_FALLBACK   see mbd_precision (at mbd_create)
- *   MBD_WORKSPACE_LIMIT    cap on a context's device workspace, bytes
+ *   MBD_WORKSPACE_LIMIT    cap on a context's device workspace, bytes (at
+ *                          mbd_create)
  *   MBD_NO_GRAPH=1         mbd_evaluate_batch runs eagerly instead of
  *                          replaying a captured graph (read per call)
  *   MBD_SYTRD_FUSED_MAXN   largest trailing order reduced by one fused launch
