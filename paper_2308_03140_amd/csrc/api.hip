@@ -61,10 +61,10 @@ struct mbd_ctx {
     std::map<std::string, std::pair<void*, size_t>> arena_bufs;
     void drop_graphs() {
         for (auto& kv : graphs) {
-            if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-            hipHostFree(kv.second.h_desc);
-            hipHostFree(kv.second.h_ns);
-            hipHostFree(kv.second.h_status);
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            (void)hipHostFree(kv.second.h_desc);
+            (void)hipHostFree(kv.second.h_ns);
+            (void)hipHostFree(kv.second.h_status);
         }
         graphs.clear();
     }
@@ -121,10 +121,10 @@ void* ws(mbd_ctx* c, const char* name, size_t bytes) {
         return nullptr;
     }
     if (it != c->bufs.end()) {
-        hipStreamSynchronize(c->stream);
-        if (c->gstream) hipStreamSynchronize(c->gstream);
+        (void)hipStreamSynchronize(c->stream);
+        if (c->gstream) (void)hipStreamSynchronize(c->gstream);
         c->drop_graphs();  // captured sequences hold the old address
-        hipFree(it->second.first);
+        (void)hipFree(it->second.first);
         c->total -= old;
         c->bufs.erase(it);
     }
@@ -775,21 +775,21 @@ mbd_status mbd_create(mbd_ctx** ctx, int device, mbd_precision prec, void* hip_s
 
 mbd_status mbd_destroy(mbd_ctx* c) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
-    if (c->gstream) hipStreamSynchronize(c->gstream);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->gstream) (void)hipStreamSynchronize(c->gstream);
     c->drop_graphs();
-    if (c->gstream) hipStreamDestroy(c->gstream);
-    if (c->ev_in) hipEventDestroy(c->ev_in);
-    if (c->ev_out) hipEventDestroy(c->ev_out);
-    for (auto& kv : c->bufs) hipFree(kv.second.first);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    for (auto& kv : c->bufs) (void)hipFree(kv.second.first);
     delete c;
     return MBD_OK;
 }
 
 mbd_status mbd_set_stream(mbd_ctx* c, void* hip_stream) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     c->stream = (hipStream_t)hip_stream;
     return MBD_OK;
 }
@@ -1214,7 +1214,7 @@ mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, 
                     const bool end_ok = hipStreamEndCapture(c->gstream, &graph) == hipSuccess;
                     ok = rc == MBD_OK && end_ok && graph &&
                          hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess;
-                    if (graph) hipGraphDestroy(graph);
+                    if (graph) (void)hipGraphDestroy(graph);
                 }
                 c->stream = user;
                 (void)hipGetLastError();
@@ -1334,7 +1334,7 @@ mbd_status autotune_size(mbd_ctx* c, int n, int* best_target, int* best_lo, doub
             for (size_t q = 0; q < prof.kind.size(); q++) {
                 if (prof.kind[q] != 0 && prof.kind[q] != 8) continue;  // per-column launches, in order
                 float ms = 0;
-                hipEventElapsedTime(&ms, prof.pool[2 * q], prof.pool[2 * q + 1]);
+                (void)hipEventElapsedTime(&ms, prof.pool[2 * q], prof.pool[2 * q + 1]);
                 const int nbt = nbk - ((col + 1) >> 6);
                 (4 * nbt >= 3 * nbk ? u : l) += ms;
                 col++;
@@ -1502,7 +1502,7 @@ mbd_status mbd_check_dc_buffers(int32_t n_max, int64_t* needed, int64_t* allocat
 
 mbd_status mbd_set_profiling(mbd_ctx* c, int enable) {
     if (!c) return MBD_ERR_INVALID_ARGUMENT;
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     c->prof.enabled = enable != 0;
     c->prof.launches = enable != 2;
     c->prof.reset();
