@@ -297,12 +297,21 @@ def leg_periodic(args, torch, T):
         log("[bench] periodic %s warmup x%d, timed x%d" % (prec, args.warmup, args.steps))
         dt, out = timed(step, args.steps, args.warmup, torch)
         log("[bench] periodic %s %.4f s/step" % (prec, dt))
-        res[prec] = {"s": dt, "out": {k: v.detach().cpu().numpy() for k, v in out.items()}}
+        # the same with time-reversed q points folded (32 of the 64 matrices)
+        os.environ["MBD_Q_PAIRS"] = "1"
+        try:
+            dtp, _ = timed(step, args.steps, args.warmup, torch)
+        finally:
+            del os.environ["MBD_Q_PAIRS"]
+        log("[bench] periodic %s, q pairs folded: %.4f s/step" % (prec, dtp))
+        res[prec] = {"s": dt, "s_pairs": dtp, "out": {k: v.detach().cpu().numpy() for k, v in out.items()}}
         ctx.close()
     o32, o64 = res["fp32_refined"]["out"], res["fp64"]["out"]
     return {"workload": "64-atom triclinic cell, 4x4x4 Monkhorst-Pack (64 Hermitian 192x192 = real 384x384), "
                         "Ewald defaults, seed 3, alpha0 x %.4f" % c["alpha_scale"],
             "s_per_eval": res["fp32_refined"]["s"], "fp64_s_per_eval": res["fp64"]["s"],
+            "q_pairs_folded": {"s_per_eval": res["fp32_refined"]["s_pairs"],
+                               "fp64_s_per_eval": res["fp64"]["s_pairs"]},
             "errors_vs_fp64": {
                 "energy_per_atom_Ha": abs(float(o32["energy"][0]) - float(o64["energy"][0])) / 64,
                 "grad_coords_Ha_per_bohr": float(np.abs(o32["grad_coords"] - o64["grad_coords"]).max()),

@@ -79,6 +79,8 @@ typedef enum { MBD_FP64 = 0, MBD_FP32_REFINED = 1 } mbd_precision;
  *                          mbd_create)
  *   MBD_NO_GRAPH=1         mbd_evaluate_batch runs eagerly instead of
  *                          replaying a captured graph (read per call)
+ *   MBD_Q_PAIRS=1          periodic evaluations fold time-reversed q points
+ *                          (see mbd_system.n_q; read per call)
  *   MBD_SYTRD_FUSED_MAXN   largest trailing order reduced by one fused launch
  *                          per column (default 4000 in FP32, 0 in FP64)
  *   MBD_SYTRD_WG_MIN_BATCH smallest batch of matrices of order <= 1024 that
@@ -109,10 +111,11 @@ typedef struct {
                                      for a finite system (HOST pointer)          */
     int32_t n_q;                  /* periodic: number of q points in q_frac, or 0
                                      to use the Monkhorst-Pack mesh kgrid/kshift.
-                                     Points q, q' with q + q' an integer vector
-                                     (time-reversed partners) give the same
-                                     energy and gradient contributions; unless
-                                     eigenvalues are requested, one of each such
+                                     Every point is evaluated.  Points q, q'
+                                     with q + q' an integer vector (time-
+                                     reversed partners) give the same energy and
+                                     gradient contributions: with MBD_Q_PAIRS=1
+                                     (and no eigenvalue output) one of each
                                      pair is evaluated, with weight 2 */
     const double *q_frac;         /* [n_q][3] fractional coordinates in the
                                      reciprocal basis (HOST pointer)             */

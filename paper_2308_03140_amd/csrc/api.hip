@@ -804,9 +804,11 @@ mbd_status mbd_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_resu
     std::vector<int> codes;
     if (s->lattice) {
         PeriodicSetup ps;
-        // eigenvalues are returned per mesh point, so only without them are
-        // time-reversed pairs evaluated once
-        r = setup_periodic(c, s, sds[0], ps, !(want & MBD_WANT_EIGVALS));
+        // time-reversed pairs evaluated once: on request (MBD_Q_PAIRS=1),
+        // and never with eigenvalue output, which is per mesh point
+        const char* qp = std::getenv("MBD_Q_PAIRS");
+        const bool pair_q = qp && qp[0] == '1' && !(want & MBD_WANT_EIGVALS);
+        r = setup_periodic(c, s, sds[0], ps, pair_q);
         if (r != MBD_OK) return r;
         r = run_core(c, sds, want, codes, &ps);
         if (r == MBD_OK) r = refine_fallback(c, sds, want, codes, &ps);

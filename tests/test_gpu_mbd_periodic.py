@@ -140,11 +140,11 @@ def test_periodic_c6_input(ctx):
 
 
 @pytest.mark.parametrize("kgrid,kshift", [((3, 3, 2), (0.0, 0.0, 0.0)), ((4, 2, 2), (0.125, 0.0, 0.0))])
-def test_time_reversal_pairs_match_full_mesh(ctx, kgrid, kshift):
-    """Without eigenvalue output the library evaluates one q point of each
+def test_time_reversal_pairs_match_full_mesh(ctx, kgrid, kshift, monkeypatch):
+    """With MBD_Q_PAIRS=1 the library evaluates one q point of each
     time-reversed pair (q, -q modulo the reciprocal lattice) with weight 2;
-    with it, every mesh point.  Energy and every gradient agree between the
-    two (FP64 to rounding), and with the oracle on the full mesh.  The
+    by default, every mesh point.  Energy and every gradient agree between
+    the two (FP64 to rounding), and with the oracle on the full mesh.  The
     shifted mesh pairs only some of its points."""
     from paper_2308_03140_amd import torch_api as T
     _note("periodic time reversal %s k=%s shift=%s" % (ctx.precision, kgrid, kshift))
@@ -152,8 +152,11 @@ def test_time_reversal_pairs_match_full_mesh(ctx, kgrid, kshift):
     qf = oracle.monkhorst_pack(*kgrid) + np.array(kshift)
     ref = oracle.mbd_periodic(c["coords"], c["lattice"], qf, c["alpha0"], c["omega"], c["rvdw"],
                               c["beta"], c["a"])
-    runs = [T.evaluate(ctx, torch.tensor(c["coords"], device="cuda"), c["alpha0"], c["omega"], c["rvdw"],
-                       beta=c["beta"], a=c["a"], lattice=c["lattice"], q_frac=qf, eigvals=ev) for ev in (False, True)]
+    runs = []
+    for pairs in ("1", "0"):
+        monkeypatch.setenv("MBD_Q_PAIRS", pairs)
+        runs.append(T.evaluate(ctx, torch.tensor(c["coords"], device="cuda"), c["alpha0"], c["omega"], c["rvdw"],
+                               beta=c["beta"], a=c["a"], lattice=c["lattice"], q_frac=qf))
     torch.cuda.synchronize()
     for out in runs:
         _compare(ctx, 5, out, ref)
