@@ -382,7 +382,52 @@ struct PeriodicSetup {
     std::vector<double> qmult;  // weight of each q point (2: it stands for its time-reversed partner too)
     std::vector<int> img, rec;
     int nq_all = 0;             // q points of the mesh before pairing
+    std::vector<int> rcol;      // [nq][ncol]: reciprocal vectors of each q point's sphere, -1 padded
+    int ncol = 0;
 };
+
+// Per q point, the reciprocal vectors G of the list with 0 < |G + q| < kc:
+// the columns of its reciprocal-space basis.
+static void recip_columns(const SysDesc& d, PeriodicSetup& ps) {
+    const int nq = (int)ps.qcart.size() / 3, nr = (int)ps.rec.size() / 3;
+    std::vector<std::vector<int>> lists(nq);
+    size_t ncol = 0;
+    for (int q = 0; q < nq; q++) {
+        for (int t = 0; t < nr; t++) {
+            double k[3];
+            for (int c = 0; c < 3; c++)
+                k[c] = ps.rec[3 * t] * d.recip[c] + ps.rec[3 * t + 1] * d.recip[3 + c] + ps.rec[3 * t + 2] * d.recip[6 + c] +
+                       ps.qcart[3 * q + c];
+            const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            if (k2 == 0.0 || k2 >= d.kc * d.kc) continue;
+            lists[q].push_back(t);
+        }
+        ncol = std::max(ncol, lists[q].size());
+    }
+    ps.ncol = (int)ncol;
+    ps.rcol.assign((size_t)nq * ncol, -1);
+    for (int q = 0; q < nq; q++)
+        std::copy(lists[q].begin(), lists[q].end(), ps.rcol.begin() + (size_t)q * ncol);
+}
+
+// Device column lists and basis workspaces of the reciprocal-space product
+// (W, the adjoint's, only when gradients are wanted).
+static mbd_status make_per_recip(mbd_ctx* c, const PeriodicSetup& ps, int N, int nq, const int* rec_dev, bool with_w,
+                                 PerRecip& pr) {
+    pr.rec = rec_dev;
+    pr.ncol = ps.ncol;
+    pr.ldz = round_up(6 * N, 64);
+    pr.sZ = (long long)pr.ldz * std::max(ps.ncol, 1);
+    int* col = wsT<int>(c, "rcol", std::max<size_t>(1, ps.rcol.size()));
+    pr.Z = wsT<double>(c, "rZ", (size_t)pr.sZ * nq);
+    pr.W = with_w ? wsT<double>(c, "rW", (size_t)pr.sZ * nq) : nullptr;
+    if (!col || !pr.Z || (with_w && !pr.W)) return (mbd_status)c->err_code;
+    if (!ps.rcol.empty())
+        HIPCHK(hipMemcpyAsync(col, ps.rcol.data(), sizeof(int) * ps.rcol.size(), hipMemcpyHostToDevice, c->stream),
+               "upload");
+    pr.col = col;
+    return MBD_OK;
+}
 
 // Time reversal: Q(-q) is the complex conjugate of Q(q) (the lattice sums
 // are real), and Q(q + G) the similarity D Q(q) D^* with the diagonal phases
@@ -528,6 +573,7 @@ mbd_status setup_periodic(mbd_ctx* c, const mbd_system* s, SysDesc& d, PeriodicS
                 if (std::sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]) > d.kc + qmax + 1e-9) continue;
                 ps.rec.push_back(x); ps.rec.push_back(y); ps.rec.push_back(z);
             }
+    recip_columns(d, ps);
     return MBD_OK;
 }
 
@@ -589,6 +635,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     double* qmult = nullptr;
     int* img = nullptr;
     int* rec = nullptr;
+    PerRecip prc = {};
     if (per) {
         qcart = wsT<double>(c, "qcart", per->qcart.size());
         qmult = wsT<double>(c, "qmult", (size_t)nq);
@@ -599,8 +646,11 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         HIPCHK(hipMemcpyAsync(qmult, per->qmult.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(img, per->img.data(), sizeof(int) * per->img.size(), hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(rec, per->rec.data(), sizeof(int) * per->rec.size(), hipMemcpyHostToDevice, st), "upload");
-        mbd_assemble_periodic_launch(st, sd_dev, om, cc, qcart, nq, img, (int)per->img.size() / 3, rec,
-                                     (int)per->rec.size() / 3, A64, A32, status, sds[0].N);
+        const mbd_status rr = make_per_recip(c, *per, sds[0].N, nq, rec, grads, prc);
+        if (rr != MBD_OK) return rr;
+        per_recip_basis_launch(st, sd_dev, qcart, nq, prc);
+        mbd_assemble_periodic_launch(st, sd_dev, om, cc, qcart, nq, img, (int)per->img.size() / 3, prc, A64, A32,
+                                     status, sds[0].N);
     } else {
         mbd_assemble_finite_launch(st, sd_dev, nsys, Nmax, om, cc, A64, A32, status);
     }
@@ -666,10 +716,14 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         mbd_mirror_launch(st, ns_dev, nmax, nmat, M);
         if (per) {
             const int N = sds[0].N;
+            const int nch = per_recip_chunks(prc.ncol);
             double* part = wsT<double>(c, "gpart", (size_t)nq * N * N * PER_PART);
-            if (!part) return (mbd_status)c->err_code;
+            double* rq = wsT<double>(c, "grq", std::max<size_t>(1, (size_t)nq * nch * N * 4));
+            double* rl = wsT<double>(c, "grl", std::max<size_t>(1, (size_t)nq * nch * 10));
+            double* latpart = wsT<double>(c, "glat", (size_t)N * 9);
+            if (!part || !rq || !rl || !latpart) return (mbd_status)c->err_code;
             mbd_grad_periodic_launch(st, sd_dev, om, cc, qcart, qmult, 0.25 / per->nq_all, nq, img,
-                                     (int)per->img.size() / 3, rec, (int)per->rec.size() / 3, M, part, N);
+                                     (int)per->img.size() / 3, prc, M, part, rq, rl, latpart, N);
         } else {
             mbd_grad_finite_launch(st, sd_dev, nsys, Nmax, om, cc, M);
         }
@@ -1013,11 +1067,15 @@ mbd_status mbd_freq_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, in
         HIPCHK(hipMemcpyAsync(qcart, ps.qcart.data(), sizeof(double) * ps.qcart.size(), hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(img, ps.img.data(), sizeof(int) * ps.img.size(), hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(rec, ps.rec.data(), sizeof(int) * ps.rec.size(), hipMemcpyHostToDevice, st), "upload");
+        PerRecip prc = {};
+        r = make_per_recip(c, ps, N, nq, rec, false, prc);
+        if (r != MBD_OK) return r;
+        // the basis depends on the geometry only: one for every frequency
+        per_recip_basis_launch(st, sd_dev + 1, qcart, nq, prc);
         for (int f = 0; f < n_freq; f++) {
             const MatBatch<double> Kf = {K.p + (long long)f * nq * stride, ld, stride};
-            mbd_assemble_periodic_launch(st, sd_dev + 1 + f, om_f, cc_f, qcart, nq, img, (int)ps.img.size() / 3, rec,
-                                         (int)ps.rec.size() / 3, Kf, MatBatch<float>{nullptr, ld, stride},
-                                         status + 1 + f, N);
+            mbd_assemble_periodic_launch(st, sd_dev + 1 + f, om_f, cc_f, qcart, nq, img, (int)ps.img.size() / 3, prc,
+                                         Kf, MatBatch<float>{nullptr, ld, stride}, status + 1 + f, N);
         }
     } else {
         mbd_assemble_finite_launch(st, sd_dev + 1, n_freq, N, om_f, cc_f, K, MatBatch<float>{nullptr, ld, stride},

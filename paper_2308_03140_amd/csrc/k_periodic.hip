@@ -1,7 +1,7 @@
 // Periodic systems: Q(q) of eq:q-matrix with T^lr(q) the Bloch sum of g T
 // (paper Sec. 2.2), evaluated with the Ewald split of eq:ewald/eq:terfc plus
-// a real-space damping correction, for every q of the mesh in one launch, and
-// the matching adjoint contraction for dE/dR, dE/dalpha0 and dE/dA (lattice).
+// a real-space damping correction, for every q of the mesh, and the matching
+// adjoint contraction for dE/dR, dE/dalpha0 and dE/dA (lattice).
 //
 // For the pair (i, j), r = R_j - R_i and x_n = r + R_n:
 //   T_ij(q) = sum_n [T^erfc(x_n) (|x_n| < Rc) - (1 - g(x_n)) T(x_n)] e^{-i q.x_n}
@@ -12,9 +12,18 @@
 // T^erfc_ab = (delta_ab r^2 B - r_a r_b C)/r^5 with B, C of eq:terfc (the
 // factor 3 of the printed r_a r_b term is part of C).
 //
+// The reciprocal-space term is a sum of rank-one 3x3 blocks k k^T times a
+// pair phase, so over all pairs it is the low-rank product U U^H with
+// U_{ia,g} = sqrt(w_g) k_a e^{-i G_g.R_i}, w = (4 pi/Omega) e^{-k^2/(4 gamma^2)}/k^2,
+// one column per reciprocal vector of the q point's sphere.  It is formed on
+// the matrix cores (a product over the ~265 columns instead of that many
+// exponentials and phases per pair and q), and the adjoint contracts M with U
+// the same way: W = M C U, then per atom and column a few products of U and W.
+//
 // The Hermitian Q(q) is stored as its real embedding [[Re, -Im], [Im, Re]]
 // (order 2n) so the batched real eigensolver serves it; every eigenvalue of
 // Q(q) appears twice.  The reciprocal sums are evaluated in FP64.
+#include "gemm_mfma.h"
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
@@ -108,13 +117,14 @@ __device__ __forceinline__ bool image_term(const double* x, double gamma, double
 // only: each is formed once, by one lane of its pair, into LDS (lpp images
 // per round), and every lane of the pair adds it with its own phase
 // e^{-i q.x}.  Lanes of a pair index past N^2 follow the barriers and store
-// nothing.
+// nothing.  Writes the real-space and self terms and omega^2 into the left
+// block column [Re; Im] of the embedding; the reciprocal-space product then
+// adds its term and fills the right block column.
 #define PER_LANES 64
 __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const SysDesc* sd, const double* om,
                                                                           const double* cc, const double* qcart,
                                                                           int nq, int lpp, const int* img, int nimg,
-                                                                          const int* rec, int nrec, MatBatch<double> Q,
-                                                                          MatBatch<float> Q32, unsigned* status) {
+                                                                          MatBatch<double> Q, unsigned* status) {
     __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9];
     __shared__ int oks[PER_LANES];
     const SysDesc& S = sd[0];
@@ -166,52 +176,108 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
         __syncthreads();
     }
     if (!qv_ok) return;
-    const double pref = 4.0 * M_PI / S.vol;
-    const double g4 = 1.0 / (4.0 * S.gamma * S.gamma);
-    for (int t = 0; t < nrec; t++) {
-        const double m0 = rec[3 * t], m1 = rec[3 * t + 1], m2 = rec[3 * t + 2];
-        double G[3], k[3];
-        for (int c = 0; c < 3; c++) {
-            G[c] = m0 * S.recip[c] + m1 * S.recip[3 + c] + m2 * S.recip[6 + c];
-            k[c] = G[c] + qv[c];
-        }
-        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-        if (k2 == 0.0 || k2 >= S.kc * S.kc) continue;
-        const double E = pref * exp(-k2 * g4) / k2;
-        double sph, cph;
-        sincos(G[0] * r[0] + G[1] * r[1] + G[2] * r[2], &sph, &cph);
-        for (int p = 0; p < 3; p++)
-            for (int s = 0; s < 3; s++) {
-                const double h = k[p] * k[s] * E;
-                Tre[p * 3 + s] += h * cph;
-                Tim[p * 3 + s] += h * sph;
-            }
-    }
     if (i == j) {
         const double self = 4.0 * S.gamma * S.gamma * S.gamma / (3.0 * SQRT_PI);
         Tre[0] -= self; Tre[4] -= self; Tre[8] -= self;
     }
     const double pc = cc[S.atom_off + i] * cc[S.atom_off + j];
     double* Qb = Q.at(q);
-    float* Qf = Q32.p ? Q32.at(q) : nullptr;
-    const long long ld = Q.ld, ldf = Q32.ld;
+    const long long ld = Q.ld;
     for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) {
             const double re = pc * Tre[a * 3 + b] + ((i == j && a == b) ? om[S.atom_off + i] * om[S.atom_off + i] : 0.0);
-            const double im = pc * Tim[a * 3 + b];
             const long long r0 = 3 * i + a, c0 = 3 * j + b;
             Qb[r0 + c0 * ld] = re;
-            Qb[(r0 + n) + (c0 + n) * ld] = re;
-            Qb[r0 + (c0 + n) * ld] = -im;
-            Qb[(r0 + n) + c0 * ld] = im;
-            if (Qf) {
-                Qf[r0 + c0 * ldf] = (float)re;
-                Qf[(r0 + n) + (c0 + n) * ldf] = (float)re;
-                Qf[r0 + (c0 + n) * ldf] = (float)-im;
-                Qf[(r0 + n) + c0 * ldf] = (float)im;
-            }
+            Qb[(r0 + n) + c0 * ld] = pc * Tim[a * 3 + b];
         }
 }
+
+// Reciprocal vector and weights of column g of q point q's list (t >= 0):
+// G, k = G + q, sw = sqrt(w), w = (4 pi/Omega) e^{-k^2/(4 gamma^2)}/k^2, and
+// f = (dw/dk_d)/(w k_d) = -1/(2 gamma^2) - 2/k^2.
+__device__ __forceinline__ void recip_column(const SysDesc& S, const int* rec, int t, const double* qv, double* G,
+                                             double* k, double& sw, double& f) {
+    const double m0 = rec[3 * t], m1 = rec[3 * t + 1], m2 = rec[3 * t + 2];
+    for (int c = 0; c < 3; c++) {
+        G[c] = m0 * S.recip[c] + m1 * S.recip[3 + c] + m2 * S.recip[6 + c];
+        k[c] = G[c] + qv[c];
+    }
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    const double g4 = 1.0 / (4.0 * S.gamma * S.gamma);
+    sw = sqrt(4.0 * M_PI / S.vol * exp(-k2 * g4) / k2);
+    f = -2.0 * g4 - 2.0 / k2;
+}
+
+// Columns of U(q), embedded: rows 0 .. n-1 Re U, rows n .. 2n-1 Im U; the
+// columns past the q point's count are zero.  Grid (ncol, nq), 64 threads
+// over the atoms.
+__global__ __launch_bounds__(64) void per_recip_basis_kernel(const SysDesc* sd, const double* qcart, PerRecip pr) {
+    const SysDesc& S = sd[0];
+    const int N = S.N, n = 3 * N;
+    const int g = blockIdx.x, q = blockIdx.y;
+    double* Zc = pr.Z + (long long)q * pr.sZ + (long long)g * pr.ldz;
+    const int t = pr.col[(long long)q * pr.ncol + g];
+    double G[3] = {0.0, 0.0, 0.0}, k[3] = {0.0, 0.0, 0.0}, sw = 0.0, f;
+    if (t >= 0) recip_column(S, pr.rec, t, qcart + 3 * q, G, k, sw, f);
+    const double* R = S.coords;
+    for (int i = threadIdx.x; i < N; i += 64) {
+        double sn = 0.0, cs = 1.0;
+        if (t >= 0) sincos(G[0] * R[3 * i] + G[1] * R[3 * i + 1] + G[2] * R[3 * i + 2], &sn, &cs);
+        for (int a = 0; a < 3; a++) {
+            Zc[3 * i + a] = sw * k[a] * cs;      // e^{-i G.R} = cos - i sin
+            Zc[n + 3 * i + a] = -sw * k[a] * sn;
+        }
+    }
+}
+
+// Reciprocal term of the embedding: [Re; Im] of C U U^H C is [U_r, -U_i;
+// U_i, U_r] times the first n rows of the same, transposed (K = 2 ncol), so
+// one product per q over the left block column.  The epilogue adds it to the
+// real-space part there, mirrors it into the right block column (Re to the
+// bottom right, -Im to the top right) and writes the FP32 copy.
+struct PerRecAsmProb {
+    static constexpr bool A_M_CONTIG = true;
+    static constexpr bool B_N_CONTIG = true;
+    const SysDesc* sd;
+    const double* cc;
+    const double* Z; int ldz; long long sZ; int ncol; int n;
+    MatBatch<double> Q; MatBatch<float> Q32;
+    int tiles_m, tiles_n;
+    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
+        int ti, tj;
+        band_tile(xcd_virtual(bx, gridDim.x), tiles_m, tiles_n, ti, tj);
+        t.batch = bz;
+        t.m0 = ti * GEMM_BM; t.n0 = tj * GEMM_BN; t.K = 2 * ncol;
+        return t.m0 < 2 * n && t.n0 < n;
+    }
+    // row m, column k of [U_r, -U_i; U_i, U_r]
+    __device__ double zf(const GemmTile& t, int m, int k) const {
+        const double* Zb = Z + (long long)t.batch * sZ;
+        if (k < ncol) return Zb[m + (long long)k * ldz];
+        const long long o = (long long)(k - ncol) * ldz;
+        return m < n ? -Zb[m + n + o] : Zb[m - n + o];
+    }
+    __device__ double a(const GemmTile& t, int m, int k) const { return (m < 2 * n && k < t.K) ? zf(t, m, k) : 0.0; }
+    __device__ double b(const GemmTile& t, int k, int c) const { return (c < n && k < t.K) ? zf(t, c, k) : 0.0; }
+    __device__ void store(const GemmTile& t, int m, int c, double v) const {
+        if (m >= 2 * n || c >= n) return;
+        const bool top = m < n;
+        const int off = sd->atom_off;
+        const int i = (top ? m : m - n) / 3, j = c / 3;
+        double* Qb = Q.at(t.batch);
+        const long long ld = Q.ld;
+        const double val = Qb[m + (long long)c * ld] + cc[off + i] * cc[off + j] * v;
+        const int mm = top ? m + n : m - n;
+        const double mv = top ? val : -val;
+        Qb[m + (long long)c * ld] = val;
+        Qb[mm + (long long)(c + n) * ld] = mv;
+        if (Q32.p) {
+            float* Qf = Q32.at(t.batch);
+            Qf[m + (long long)c * Q32.ld] = (float)val;
+            Qf[mm + (long long)(c + n) * Q32.ld] = (float)mv;
+        }
+    }
+};
 
 // Adjoint contraction.  With M(q) = Q(q)^{-1/2} read from the embedded
 // inverse square root (Re in the top-left block, Im in the bottom-left), the
@@ -228,15 +294,15 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
 //                                      (1/2) omega_i Re Tr M_ii(q) per q)
 //   to dE/dRv_i, dE/dRv_j              X = beta dT_ij(q)/dR0 (damping radius
 //                                      R0 = beta (Rv_i + Rv_j))
-// Partial results per (q, i, j): {P, dR[3], dA[9], P0}.
+// Partial results per (q, i, j) of the real-space and self terms: {P, dR[3],
+// dA[9], P0}; the reciprocal-space term is contracted through U below.
 // Same layout as the assembly: one workgroup per ordered pair, one lane per
 // q-point, each real-space image term (F and its derivatives) formed once
 // into LDS and added by every lane with its own phase and M(q).
 __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysDesc* sd, const double* om,
                                                                       const double* cc, const double* qcart, int nq,
                                                                       int lpp, const int* img, int nimg,
-                                                                      const int* rec, int nrec, MatBatch<double> M,
-                                                                      double* part) {
+                                                                      MatBatch<double> M, double* part) {
     __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9], dFs[PER_LANES][27], F0s[PER_LANES][9];
     __shared__ int ns_[PER_LANES][3], oks[PER_LANES];
     const SysDesc& S = sd[0];
@@ -325,55 +391,6 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
         }
         __syncthreads();
     }
-    const double pref = 4.0 * M_PI / S.vol;
-    const double g4 = 1.0 / (4.0 * S.gamma * S.gamma);
-    for (int t = 0; t < nrec; t++) {
-        const double m0 = rec[3 * t], m1 = rec[3 * t + 1], m2 = rec[3 * t + 2];
-        double G[3], k[3];
-        for (int c = 0; c < 3; c++) {
-            G[c] = m0 * S.recip[c] + m1 * S.recip[3 + c] + m2 * S.recip[6 + c];
-            k[c] = G[c] + qv[c];
-        }
-        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-        if (k2 == 0.0 || k2 >= S.kc * S.kc) continue;
-        const double E = exp(-k2 * g4);
-        double sph, cph;
-        sincos(G[0] * r[0] + G[1] * r[1] + G[2] * r[2], &sph, &cph);
-        // S_h = sum_ab M h_ab with h = k_a k_b E / k^2
-        double Sh = 0.0, Shi = 0.0, Sdh[3] = {0, 0, 0}, Sdhi[3] = {0, 0, 0};
-        for (int p = 0; p < 3; p++)
-            for (int s = 0; s < 3; s++) {
-                const double h = k[p] * k[s] * E / k2;
-                Sh += Mr[p * 3 + s] * h;
-                Shi += Mi[p * 3 + s] * h;
-                for (int dd = 0; dd < 3; dd++) {
-                    double dh = -2.0 * k[p] * k[s] * k[dd] / (k2 * k2) * E - h * k[dd] * 2.0 * g4;
-                    if (p == dd) dh += k[s] / k2 * E;
-                    if (s == dd) dh += k[p] / k2 * E;
-                    Sdh[dd] += Mr[p * 3 + s] * dh;
-                    Sdhi[dd] += Mi[p * 3 + s] * dh;
-                }
-            }
-        P += pref * (Sh * cph - Shi * sph);
-        for (int c = 0; c < 3; c++) {
-            // pref h (i G_c) e^{i ph}
-            dR[c] += -pref * G[c] * (Sh * sph + Shi * cph);
-            for (int v = 0; v < 3; v++) {
-                double ure = 0.0, uim = 0.0;  // sum_ab M (u_ab) with u = -Ainv_cv h - k_c dh.Ainv[:, v]
-                const double aiv = S.linv[c * 3 + v];
-                double dv = 0.0, dvi = 0.0;
-                for (int dd = 0; dd < 3; dd++) {
-                    dv += Sdh[dd] * S.linv[dd * 3 + v];
-                    dvi += Sdhi[dd] * S.linv[dd * 3 + v];
-                }
-                ure = -aiv * Sh - k[c] * dv;
-                uim = -aiv * Shi - k[c] * dvi;
-                // im part of the bracket: -h G_c rho_v
-                const double wv = -G[c] * rho[v];
-                dA[v * 3 + c] += pref * ((ure * cph - uim * sph) - wv * (Sh * sph + Shi * cph));
-            }
-        }
-    }
     if (i == j) {
         const double self = 4.0 * S.gamma * S.gamma * S.gamma / (3.0 * SQRT_PI);
         P -= self * (Mr[0] + Mr[4] + Mr[8]);
@@ -385,80 +402,205 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
     out[13] = P0;
 }
 
-// per-atom reduction in a fixed order; atom N (one extra block) sums the lattice term
+// Reciprocal term of the adjoint, W = M C U: M(q) the full embedded inverse
+// square root (2n x 2n), C U the basis with row (i, a) scaled by c_i;
+// W (2n x ncol) is [Re; Im] of the complex product.
+struct PerRecMZProb {
+    static constexpr bool A_M_CONTIG = true;
+    static constexpr bool B_N_CONTIG = false;
+    const SysDesc* sd;
+    const double* cc;
+    MatBatch<double> M;
+    const double* Z; double* W; int ldz; long long sZ; int ncol; int n;
+    int tiles_m, tiles_n;
+    __device__ bool tile(int bx, int, int bz, GemmTile& t) const {
+        int ti, tj;
+        band_tile(xcd_virtual(bx, gridDim.x), tiles_m, tiles_n, ti, tj);
+        t.batch = bz;
+        t.m0 = ti * GEMM_BM; t.n0 = tj * GEMM_BN; t.K = 2 * n;
+        return t.m0 < 2 * n && t.n0 < ncol;
+    }
+    __device__ double a(const GemmTile& t, int m, int k) const {
+        return (m < 2 * n && k < 2 * n) ? M.at(t.batch)[m + (long long)k * M.ld] : 0.0;
+    }
+    __device__ double b(const GemmTile& t, int k, int g) const {
+        if (k >= 2 * n || g >= ncol) return 0.0;
+        return cc[sd->atom_off + (k < n ? k : k - n) / 3] * Z[(long long)t.batch * sZ + k + (long long)g * ldz];
+    }
+    __device__ void store(const GemmTile& t, int m, int g, double v) const {
+        if (m < 2 * n && g < ncol) W[(long long)t.batch * sZ + m + (long long)g * ldz] = v;
+    }
+};
+
+// Reciprocal term of the adjoint, per atom k and column g (k = G + q,
+// u = U_{k., g}, z = c_k sum_a conj(u_a) W_{ka, g}):
+//   dE/dalpha, dE/domega partial  2 Re z (the pair sum over both orders)
+//   dE/dR_k                        -2 G Im z
+//   dE/dA_vc  -Ainv_cv s - sum_d Ainv_dv [k_c k_d f s + 2 sw k_c b_d
+//             + G_c sum_k R_kd e_k], s = sum_k Re z, e_k = -2 Im z,
+//             b_d = sum_k c_k Re(conj(W_{kd,g}) e^{-i G.R_k})
+// (derivatives of the weight w, of k and of the pair phase through G with
+// the fractional q fixed, and of the prefactor through Omega).  Grid (nq,
+// chunks of PER_RCOLS columns); writes per (q, chunk, atom) {2 Re z, dR[3]}
+// and per (q, chunk) {s, L[c][d]}, L the bracket's matrix without Ainv.
+#define PER_RCOLS 16
+__global__ __launch_bounds__(64) void per_recip_grad_kernel(const SysDesc* sd, const double* cc, const double* qcart,
+                                                            PerRecip pr, int nchunk, double* rq, double* rl) {
+    const SysDesc& S = sd[0];
+    const int N = S.N, n = 3 * N;
+    const int q = blockIdx.x, ch = blockIdx.y;
+    const double* Wq = pr.W + (long long)q * pr.sZ;
+    const int* cols = pr.col + (long long)q * pr.ncol;
+    const double* qv = qcart + 3 * q;
+    const double* R = S.coords;
+    const int g0 = ch * PER_RCOLS, g1 = min(pr.ncol, g0 + PER_RCOLS);
+    double sre = 0.0, L[9];
+    for (int v = 0; v < 9; v++) L[v] = 0.0;
+    for (int k = threadIdx.x; k < N; k += 64) {
+        const double ck = cc[S.atom_off + k];
+        const double Rk[3] = {R[3 * k], R[3 * k + 1], R[3 * k + 2]};
+        double ga = 0.0, gr[3] = {0.0, 0.0, 0.0};
+        for (int g = g0; g < g1; g++) {
+            const int t = cols[g];
+            if (t < 0) break;
+            double G[3], kv[3], sw, f;
+            recip_column(S, pr.rec, t, qv, G, kv, sw, f);
+            double sn, cs;
+            sincos(G[0] * Rk[0] + G[1] * Rk[1] + G[2] * Rk[2], &sn, &cs);
+            const double pr_ = cs, pi_ = -sn;  // e^{-i G.R_k}
+            double zr = 0.0, zi = 0.0, bd[3];
+            for (int a = 0; a < 3; a++) {
+                const double wr = Wq[3 * k + a + (long long)g * pr.ldz];
+                const double wi = Wq[n + 3 * k + a + (long long)g * pr.ldz];
+                const double ur = sw * kv[a] * pr_, ui = sw * kv[a] * pi_;
+                zr += ur * wr + ui * wi;
+                zi += ur * wi - ui * wr;
+                bd[a] = ck * (wr * pr_ + wi * pi_);
+            }
+            zr *= ck;
+            zi *= ck;
+            const double e = -2.0 * zi;
+            ga += 2.0 * zr;
+            for (int c = 0; c < 3; c++) gr[c] += G[c] * e;
+            sre += zr;
+            for (int c = 0; c < 3; c++)
+                for (int d = 0; d < 3; d++)
+                    L[c * 3 + d] += f * zr * kv[c] * kv[d] + 2.0 * sw * kv[c] * bd[d] + e * G[c] * Rk[d];
+        }
+        double* o = rq + (((long long)q * nchunk + ch) * N + k) * 4;
+        o[0] = ga;
+        for (int c = 0; c < 3; c++) o[1 + c] = gr[c];
+    }
+    sre = wave_sum(sre);
+    for (int v = 0; v < 9; v++) L[v] = wave_sum(L[v]);
+    if (threadIdx.x == 0) {
+        double* o = rl + ((long long)q * nchunk + ch) * 10;
+        o[0] = sre;
+        for (int v = 0; v < 9; v++) o[1 + v] = L[v];
+    }
+}
+
+// Per-atom reduction in a fixed order: the pair partials (k as either atom)
+// over all q, the reciprocal partials of every (q, chunk), and the lattice
+// partials of the pairs with k as second atom, to latpart[k].
 __global__ __launch_bounds__(256) void mbd_grad_periodic_reduce_kernel(const SysDesc* sd, int nq, const double* qmult,
                                                                          double wq, const double* om,
                                                                          const double* cc, const double* part,
-                                                                         MatBatch<double> M) {
+                                                                         MatBatch<double> M, const double* rq,
+                                                                         int nchunk, double* latpart) {
     __shared__ double red[4];
     const SysDesc& S = sd[0];
     const int N = S.N;
     if (N == 0) return;
     const int k = blockIdx.x;
-    if (k < N) {
-        double g0 = 0, g1 = 0, g2 = 0, ga = 0, gv = 0, tr = 0;
-        const long long NN = (long long)N * N;
-        for (long long idx = threadIdx.x; idx < (long long)nq * N; idx += 256) {
-            const int q = (int)(idx / N), o = (int)(idx % N);
-            // k as j (second index), partner i = o
-            const double* pj = part + ((long long)q * NN + (long long)k * N + o) * PER_PART;   // pid = i + j*N: i=o, j=k
-            const double* pi = part + ((long long)q * NN + (long long)o * N + k) * PER_PART;   // i=k, j=o
-            const double cj = qmult[q] * cc[S.atom_off + o] * cc[S.atom_off + k];
-            if (o != k) {
-                g0 += cj * (pj[1] - pi[1]);
-                g1 += cj * (pj[2] - pi[2]);
-                g2 += cj * (pj[3] - pi[3]);
-            }
-            ga += cj * (pj[0] + pi[0]);
-            gv += cj * (pj[13] + pi[13]);
+    double g0 = 0, g1 = 0, g2 = 0, ga = 0, gv = 0, tr = 0, la[9];
+    for (int v = 0; v < 9; v++) la[v] = 0.0;
+    const long long NN = (long long)N * N;
+    for (long long idx = threadIdx.x; idx < (long long)nq * N; idx += 256) {
+        const int q = (int)(idx / N), o = (int)(idx % N);
+        // k as j (second index), partner i = o
+        const double* pj = part + ((long long)q * NN + (long long)k * N + o) * PER_PART;   // pid = i + j*N: i=o, j=k
+        const double* pi = part + ((long long)q * NN + (long long)o * N + k) * PER_PART;   // i=k, j=o
+        const double cj = qmult[q] * cc[S.atom_off + o] * cc[S.atom_off + k];
+        if (o != k) {
+            g0 += cj * (pj[1] - pi[1]);
+            g1 += cj * (pj[2] - pi[2]);
+            g2 += cj * (pj[3] - pi[3]);
         }
-        // Re Tr M_kk(q), summed over q
-        for (int q = threadIdx.x; q < nq; q += 256) {
-            const double* Mb = M.at(q);
-            for (int c = 0; c < 3; c++) tr += qmult[q] * Mb[(3 * k + c) + (long long)(3 * k + c) * M.ld];
-        }
-        g0 = block_sum256(g0, red);
-        g1 = block_sum256(g1, red);
-        g2 = block_sum256(g2, red);
-        ga = block_sum256(ga, red);
-        gv = block_sum256(gv, red);
-        tr = block_sum256(tr, red);
-        if (threadIdx.x == 0) {
-            if (S.grad_coords) {
-                S.grad_coords[3 * k] = wq * g0;
-                S.grad_coords[3 * k + 1] = wq * g1;
-                S.grad_coords[3 * k + 2] = wq * g2;
-            }
-            const double a0 = S.alpha0[k];
-            const double w = om[S.atom_off + k];
-            const double dEda = wq * ga / (2.0 * a0);
-            const double dEdw = wq * ga / w + wq * 2.0 * w * tr - 1.5;
-            if (S.param_kind == 1) {
-                // omega = 4 C6/(3 alpha0^2)
-                if (S.grad_alpha0) S.grad_alpha0[k] = dEda - 2.0 * w / a0 * dEdw;
-                if (S.grad_omega) S.grad_omega[k] = dEdw * w / S.omega_or_c6[k];
-            } else {
-                if (S.grad_alpha0) S.grad_alpha0[k] = dEda;
-                if (S.grad_omega) S.grad_omega[k] = dEdw;
-            }
-            if (S.grad_rvdw) S.grad_rvdw[k] = wq * S.beta * gv;
-        }
-    } else {
-        double la[9];
-        for (int v = 0; v < 9; v++) la[v] = 0.0;
-        const long long total = (long long)nq * N * N;
-        for (long long idx = threadIdx.x; idx < total; idx += 256) {
-            const long long pid = idx % ((long long)N * N);
-            const int i = (int)(pid % N), j = (int)(pid / N);
-            const double cij = qmult[idx / ((long long)N * N)] * cc[S.atom_off + i] * cc[S.atom_off + j];
-            const double* p = part + idx * PER_PART;
-            for (int v = 0; v < 9; v++) la[v] += cij * p[4 + v];
-        }
-        for (int v = 0; v < 9; v++) {
-            const double s = block_sum256(la[v], red);
-            if (threadIdx.x == 0 && S.grad_lattice) S.grad_lattice[v] = wq * s;
-        }
+        ga += cj * (pj[0] + pi[0]);
+        gv += cj * (pj[13] + pi[13]);
+        for (int v = 0; v < 9; v++) la[v] += cj * pj[4 + v];
     }
+    for (long long idx = threadIdx.x; idx < (long long)nq * nchunk; idx += 256) {
+        const double w = qmult[idx / nchunk];
+        const double* r = rq + (idx * N + k) * 4;
+        ga += w * r[0];
+        g0 += w * r[1];
+        g1 += w * r[2];
+        g2 += w * r[3];
+    }
+    // Re Tr M_kk(q), summed over q
+    for (int q = threadIdx.x; q < nq; q += 256) {
+        const double* Mb = M.at(q);
+        for (int c = 0; c < 3; c++) tr += qmult[q] * Mb[(3 * k + c) + (long long)(3 * k + c) * M.ld];
+    }
+    g0 = block_sum256(g0, red);
+    g1 = block_sum256(g1, red);
+    g2 = block_sum256(g2, red);
+    ga = block_sum256(ga, red);
+    gv = block_sum256(gv, red);
+    tr = block_sum256(tr, red);
+    for (int v = 0; v < 9; v++) la[v] = block_sum256(la[v], red);
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < 9; v++) latpart[9 * k + v] = la[v];
+        if (S.grad_coords) {
+            S.grad_coords[3 * k] = wq * g0;
+            S.grad_coords[3 * k + 1] = wq * g1;
+            S.grad_coords[3 * k + 2] = wq * g2;
+        }
+        const double a0 = S.alpha0[k];
+        const double w = om[S.atom_off + k];
+        const double dEda = wq * ga / (2.0 * a0);
+        const double dEdw = wq * ga / w + wq * 2.0 * w * tr - 1.5;
+        if (S.param_kind == 1) {
+            // omega = 4 C6/(3 alpha0^2)
+            if (S.grad_alpha0) S.grad_alpha0[k] = dEda - 2.0 * w / a0 * dEdw;
+            if (S.grad_omega) S.grad_omega[k] = dEdw * w / S.omega_or_c6[k];
+        } else {
+            if (S.grad_alpha0) S.grad_alpha0[k] = dEda;
+            if (S.grad_omega) S.grad_omega[k] = dEdw;
+        }
+        if (S.grad_rvdw) S.grad_rvdw[k] = wq * S.beta * gv;
+    }
+}
+
+// dE/dA: the per-atom pair partials and the reciprocal (q, chunk) partials,
+// each summed in a fixed order, the latter contracted with Ainv once.
+__global__ __launch_bounds__(256) void mbd_grad_periodic_lattice_kernel(const SysDesc* sd, int nq, int nchunk,
+                                                                          const double* qmult, double wq,
+                                                                          const double* latpart, const double* rl) {
+    __shared__ double red[4];
+    const SysDesc& S = sd[0];
+    const int N = S.N;
+    double la[9], r[10];
+    for (int v = 0; v < 9; v++) la[v] = 0.0;
+    for (int v = 0; v < 10; v++) r[v] = 0.0;
+    for (int k = threadIdx.x; k < N; k += 256)
+        for (int v = 0; v < 9; v++) la[v] += latpart[9 * k + v];
+    for (long long idx = threadIdx.x; idx < (long long)nq * nchunk; idx += 256) {
+        const double w = qmult[idx / nchunk];
+        for (int v = 0; v < 10; v++) r[v] += w * rl[idx * 10 + v];
+    }
+    for (int v = 0; v < 9; v++) la[v] = block_sum256(la[v], red);
+    for (int v = 0; v < 10; v++) r[v] = block_sum256(r[v], red);
+    if (threadIdx.x != 0 || !S.grad_lattice) return;
+    // linv[d * 3 + v] = Ainv[d][v]
+    for (int v = 0; v < 3; v++)
+        for (int c = 0; c < 3; c++) {
+            double t = -S.linv[c * 3 + v] * r[0];
+            for (int d = 0; d < 3; d++) t -= S.linv[d * 3 + v] * r[1 + c * 3 + d];
+            S.grad_lattice[v * 3 + c] = wq * (la[v * 3 + c] + t);
+        }
 }
 
 // lanes per atom pair: the q count rounded up to a power of two, at most 64
@@ -468,22 +610,53 @@ static int per_lanes_per_pair(int nq) {
     return l;
 }
 
+void per_recip_basis_launch(hipStream_t st, const SysDesc* sd, const double* qcart, int nq, const PerRecip& pr) {
+    if (pr.ncol == 0 || nq == 0) return;
+    hipLaunchKernelGGL(per_recip_basis_kernel, dim3(pr.ncol, nq), dim3(64), 0, st, sd, qcart, pr);
+}
+
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
-                                  const double* qcart, int nq, const int* img, int nimg, const int* rec,
-                                  int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N) {
+                                  const double* qcart, int nq, const int* img, int nimg, const PerRecip& pr,
+                                  MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N) {
     const long long pairs = (long long)N * N;
     const int lpp = per_lanes_per_pair(nq), ppw = PER_LANES / lpp;
     hipLaunchKernelGGL(mbd_assemble_periodic_kernel, dim3((unsigned)((pairs + ppw - 1) / ppw), (nq + lpp - 1) / lpp),
-                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, rec, nrec, Q, Q32, status);
+                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, Q, status);
+    // always launched: besides the reciprocal term, the epilogue fills the
+    // right block column and the FP32 copy
+    PerRecAsmProb p;
+    p.sd = sd; p.cc = cc; p.Z = pr.Z; p.ldz = pr.ldz; p.sZ = pr.sZ; p.ncol = pr.ncol; p.n = 3 * N;
+    p.Q = Q; p.Q32 = Q32;
+    p.tiles_m = (6 * N + GEMM_BM - 1) / GEMM_BM;
+    p.tiles_n = (3 * N + GEMM_BN - 1) / GEMM_BN;
+    hipLaunchKernelGGL((gemm_mfma_kernel<double, PerRecAsmProb>), dim3(p.tiles_m * p.tiles_n, 1, nq), dim3(256), 0,
+                       st, p);
 }
+
+int per_recip_chunks(int ncol) { return (ncol + PER_RCOLS - 1) / PER_RCOLS; }
 
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                               const double* qcart, const double* qmult, double wq, int nq, const int* img,
-                              int nimg, const int* rec, int nrec, MatBatch<double> M, double* partial, int N) {
+                              int nimg, const PerRecip& pr, MatBatch<double> M, double* partial, double* rq,
+                              double* rl, double* latpart, int N) {
     const long long pairs = (long long)N * N;
     const int lpp = per_lanes_per_pair(nq), ppw = PER_LANES / lpp;
     hipLaunchKernelGGL(mbd_grad_periodic_kernel, dim3((unsigned)((pairs + ppw - 1) / ppw), (nq + lpp - 1) / lpp),
-                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, rec, nrec, M, partial);
-    hipLaunchKernelGGL(mbd_grad_periodic_reduce_kernel, dim3(N + 1), dim3(256), 0, st, sd, nq, qmult, wq, om, cc,
-                       partial, M);
+                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, M, partial);
+    const int nchunk = per_recip_chunks(pr.ncol);
+    if (nchunk > 0) {
+        PerRecMZProb p;
+        p.sd = sd; p.cc = cc; p.M = M; p.Z = pr.Z; p.W = pr.W; p.ldz = pr.ldz; p.sZ = pr.sZ; p.ncol = pr.ncol;
+        p.n = 3 * N;
+        p.tiles_m = (6 * N + GEMM_BM - 1) / GEMM_BM;
+        p.tiles_n = (pr.ncol + GEMM_BN - 1) / GEMM_BN;
+        hipLaunchKernelGGL((gemm_mfma_kernel<double, PerRecMZProb>), dim3(p.tiles_m * p.tiles_n, 1, nq), dim3(256),
+                           0, st, p);
+        hipLaunchKernelGGL(per_recip_grad_kernel, dim3(nq, nchunk), dim3(64), 0, st, sd, cc, qcart, pr, nchunk, rq,
+                           rl);
+    }
+    hipLaunchKernelGGL(mbd_grad_periodic_reduce_kernel, dim3(N), dim3(256), 0, st, sd, nq, qmult, wq, om, cc,
+                       partial, M, rq, nchunk, latpart);
+    hipLaunchKernelGGL(mbd_grad_periodic_lattice_kernel, dim3(1), dim3(256), 0, st, sd, nq, nchunk, qmult, wq,
+                       latpart, rl);
 }

@@ -76,16 +76,36 @@ template <typename T>
 void fill_sym_random_launch(hipStream_t st, int n, T* A, int ld, unsigned seed);
 
 // periodic (Ewald) assembly and adjoint; the adjoint keeps PER_PART doubles
-// per (q, i, j): {P, dR[3], dA[9], P0}
+// per (q, i, j): {P, dR[3], dA[9], P0} of the real-space and self terms
 #define PER_PART 14
+// Reciprocal-space term as a product of the basis U(q) (one column per
+// reciprocal vector G with 0 < |G + q| < kc, embedded [Re; Im], 2n x ncol per
+// q, ld ldz, stride sZ; columns past a q point's count are zero) with itself
+// (assembly) or with M(q) C (adjoint, into W, same layout).
+struct PerRecip {
+    const int* rec;    // reciprocal lattice vectors, integer triplets
+    const int* col;    // [nq][ncol]: index into rec of each column, -1 past the q point's count
+    int ncol;          // columns per q point (the largest count)
+    double* Z;         // basis U(q)
+    double* W;         // M C U (adjoint only)
+    int ldz;
+    long long sZ;
+};
+// U(q) for every q (before the assembly; the adjoint reuses it)
+void per_recip_basis_launch(hipStream_t st, const SysDesc* sd, const double* qcart, int nq, const PerRecip& pr);
+// Writes the whole embedded Q(q) (and its FP32 copy when Q32.p is set)
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
-                                  const double* qcart, int nq, const int* img, int nimg, const int* rec,
-                                  int nrec, MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N);
+                                  const double* qcart, int nq, const int* img, int nimg, const PerRecip& pr,
+                                  MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N);
+// column chunks of the reciprocal adjoint: rq holds 4 N doubles and rl 10 per
+// (q, chunk); latpart 9 N doubles
+int per_recip_chunks(int ncol);
 // qmult[q]: weight of q point q (2 where it stands for its time-reversed
 // partner); wq: the Brillouin-zone weight 1/4 per mesh point of all of them
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                               const double* qcart, const double* qmult, double wq, int nq, const int* img,
-                              int nimg, const int* rec, int nrec, MatBatch<double> M, double* partial, int N);
+                              int nimg, const PerRecip& pr, MatBatch<double> M, double* partial, double* rq,
+                              double* rl, double* latpart, int N);
 
 // pairwise (TS) dispersion: per-atom energy shares into eatom, gradients into
 // the descriptor's outputs, then the energy (and errors[0..3] = 0)
