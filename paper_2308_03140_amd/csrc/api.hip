@@ -1070,13 +1070,14 @@ mbd_status mbd_freq_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, in
         PerRecip prc = {};
         r = make_per_recip(c, ps, N, nq, rec, false, prc);
         if (r != MBD_OK) return r;
-        // the basis depends on the geometry only: one for every frequency
+        // the lattice sums T(q) depend on the geometry only: assembled once,
+        // then scaled by c_i c_j per frequency
+        const MatBatch<double> Tq = {wsT<double>(c, "freq_T", (size_t)stride * nq), ld, stride};
+        if (!Tq.p) return (mbd_status)c->err_code;
         per_recip_basis_launch(st, sd_dev + 1, qcart, nq, prc);
-        for (int f = 0; f < n_freq; f++) {
-            const MatBatch<double> Kf = {K.p + (long long)f * nq * stride, ld, stride};
-            mbd_assemble_periodic_launch(st, sd_dev + 1 + f, om_f, cc_f, qcart, nq, img, (int)ps.img.size() / 3, prc,
-                                         Kf, MatBatch<float>{nullptr, ld, stride}, status + 1 + f, N);
-        }
+        mbd_assemble_periodic_launch(st, sd_dev + 1, nullptr, nullptr, qcart, nq, img, (int)ps.img.size() / 3, prc, Tq,
+                                     MatBatch<float>{nullptr, ld, stride}, status + 1, N);
+        mbd_freq_scale_launch(st, cc_f, N, n_freq, nq, Tq, K);
     } else {
         mbd_assemble_finite_launch(st, sd_dev + 1, n_freq, N, om_f, cc_f, K, MatBatch<float>{nullptr, ld, stride},
                                    status + 1);

@@ -7,8 +7,9 @@
 //   E_G    = (1/2pi) int du sum_k (ln(1 + x~_k) - x~_k)       (eq:gould-norm)
 //   E^(n)  = -(1/2pi) int du ((-1)^n / n) sum_k x_k^n        (eq:rpa)
 // K(u) is assembled by the MBD assembly kernels with omega -> 0 on the
-// diagonal and c_i -> alpha_i(iu)^{1/2}; every (u, q) matrix is one member of
-// a batch for the eigenvalue-only solver.  Periodic matrices are real
+// diagonal and c_i -> alpha_i(iu)^{1/2} (periodic: the lattice sums T(q) once,
+// then scaled per frequency); every (u, q) matrix is one member of a batch
+// for the eigenvalue-only solver.  Periodic matrices are real
 // embeddings of order 2n, so each x_k appears twice and carries half weight.
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
@@ -27,6 +28,23 @@ __global__ __launch_bounds__(256) void mbd_freq_coeff_kernel(const SysDesc* sd, 
     const double a = sd[0].alpha0[i] / (1.0 + u[f] * u[f] / (w * w));
     om_f[(long long)f * N + i] = 0.0;
     cc_f[(long long)f * N + i] = sqrt(a);
+}
+
+// Periodic K(u_f, q) = C_f T(q) C_f from the embedded lattice sum T(q),
+// assembled once (it does not depend on the frequency): element (m, c) of
+// the order-2n embedding belongs to atoms (m mod n)/3 and (c mod n)/3.
+// Grid (elements / 256, nq, nfreq).
+__global__ __launch_bounds__(256) void mbd_freq_scale_kernel(const double* cc_f, int N, int nq, MatBatch<double> T,
+                                                               MatBatch<double> K) {
+    const int n = 3 * N, n2 = 2 * n;
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long long)n2 * n2) return;
+    const int q = blockIdx.y, f = blockIdx.z;
+    const int m = (int)(e % n2), c = (int)(e / n2);
+    const double* cf = cc_f + (long long)f * N;
+    const double s = cf[(m < n ? m : m - n) / 3] * cf[(c < n ? c : c - n) / 3];
+    const long long o = m + (long long)c * T.ld;
+    K.at(f * nq + q)[m + (long long)c * K.ld] = s * T.at(q)[o];
 }
 
 // ln(1 + x~) - x~ (eq:gould-norm); x~ = -erf(y)^{1/4} for x < 0, y =
@@ -109,6 +127,13 @@ void mbd_freq_coeff_launch(hipStream_t st, const SysDesc* sd, const double* om0,
                            double* om_f, double* cc_f) {
     hipLaunchKernelGGL(mbd_freq_coeff_kernel, dim3((N + 255) / 256, nfreq), dim3(256), 0, st, sd, om0, u, N, om_f,
                        cc_f);
+}
+
+void mbd_freq_scale_launch(hipStream_t st, const double* cc_f, int N, int nfreq, int nq, MatBatch<double> T,
+                           MatBatch<double> K) {
+    const long long el = 36LL * N * N;
+    hipLaunchKernelGGL(mbd_freq_scale_kernel, dim3((unsigned)((el + 255) / 256), nq, nfreq), dim3(256), 0, st, cc_f, N,
+                       nq, T, K);
 }
 
 void mbd_freq_terms_launch(hipStream_t st, const int* ns, int nmat, const double* lam, long long sL, int norder,

@@ -180,12 +180,14 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
         const double self = 4.0 * S.gamma * S.gamma * S.gamma / (3.0 * SQRT_PI);
         Tre[0] -= self; Tre[4] -= self; Tre[8] -= self;
     }
-    const double pc = cc[S.atom_off + i] * cc[S.atom_off + j];
+    // without cc and om: the lattice sum T(q) itself (c = 1, no omega^2)
+    const double pc = cc ? cc[S.atom_off + i] * cc[S.atom_off + j] : 1.0;
     double* Qb = Q.at(q);
     const long long ld = Q.ld;
     for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) {
-            const double re = pc * Tre[a * 3 + b] + ((i == j && a == b) ? om[S.atom_off + i] * om[S.atom_off + i] : 0.0);
+            const double re = pc * Tre[a * 3 + b] +
+                              ((om && i == j && a == b) ? om[S.atom_off + i] * om[S.atom_off + i] : 0.0);
             const long long r0 = 3 * i + a, c0 = 3 * j + b;
             Qb[r0 + c0 * ld] = re;
             Qb[(r0 + n) + c0 * ld] = pc * Tim[a * 3 + b];
@@ -266,7 +268,7 @@ struct PerRecAsmProb {
         const int i = (top ? m : m - n) / 3, j = c / 3;
         double* Qb = Q.at(t.batch);
         const long long ld = Q.ld;
-        const double val = Qb[m + (long long)c * ld] + cc[off + i] * cc[off + j] * v;
+        const double val = Qb[m + (long long)c * ld] + (cc ? cc[off + i] * cc[off + j] : 1.0) * v;
         const int mm = top ? m + n : m - n;
         const double mv = top ? val : -val;
         Qb[m + (long long)c * ld] = val;

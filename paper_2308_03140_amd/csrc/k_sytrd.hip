@@ -625,14 +625,36 @@ __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<
         __syncthreads();
         if (tau != T(0)) {
             // y(r) = tau sum_c A(r, c) v(c) over the trailing block, quarter q
-            // taking c = i + 1 + q, i + 1 + q + 4, ...
+            // taking c = i + 1 + q, i + 1 + q + 4, ...: A(r, c) from column c
+            // while c <= r, then from column r.  Four columns per step with
+            // their loads issued together (the loop is LDS-latency bound).
             T ys = T(0);
             if (r > i && rv) {
                 int c = i + 1 + q, csc = cs(c);
-                for (; c < m; c += Q) {
-                    ys += L[r >= c ? csc + r - c : csr + c - r] * vv[c];
-                    csc += Q * m - Q * c - Q * (Q - 1) / 2;  // cs(c + Q) - cs(c)
+                T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+                for (; c + 3 * Q <= r; c += 4 * Q) {
+                    // cs(c + Q) - cs(c) = Q m - Q c - Q (Q - 1) / 2, falling by Q^2 per step
+                    const int d0 = Q * m - Q * c - Q * (Q - 1) / 2, d1 = d0 - Q * Q, d2 = d1 - Q * Q;
+                    const int a0 = csc + r - c, a1 = a0 + d0 - Q, a2 = a1 + d1 - Q, a3 = a2 + d2 - Q;
+                    s0 += L[a0] * vv[c];
+                    s1 += L[a1] * vv[c + Q];
+                    s2 += L[a2] * vv[c + 2 * Q];
+                    s3 += L[a3] * vv[c + 3 * Q];
+                    csc += 4 * d0 - 6 * Q * Q;
                 }
+                for (; c <= r; c += Q) {
+                    s0 += L[csc + r - c] * vv[c];
+                    csc += Q * m - Q * c - Q * (Q - 1) / 2;
+                }
+                for (; c + 3 * Q < m; c += 4 * Q) {
+                    const int a0 = csr + c - r;
+                    s0 += L[a0] * vv[c];
+                    s1 += L[a0 + Q] * vv[c + Q];
+                    s2 += L[a0 + 2 * Q] * vv[c + 2 * Q];
+                    s3 += L[a0 + 3 * Q] * vv[c + 3 * Q];
+                }
+                for (; c < m; c += Q) s0 += L[csr + c - r] * vv[c];
+                ys = (s0 + s1) + (s2 + s3);
             }
             if (rv) yp[q][r] = ys;
             __syncthreads();
@@ -641,9 +663,20 @@ __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<
             const T wr = yr - T(0.5) * tau * ytv * vr;
             if (q == 0 && rv) ww[r] = wr;
             __syncthreads();
-            // A(r, c) -= v(r) w(c) + w(r) v(c), c = i + 1 + q, ... <= r
+            // A(r, c) -= v(r) w(c) + w(r) v(c), c = i + 1 + q, ... <= r; four
+            // columns per step, all loads before the stores
             if (r > i && rv) {
                 int c = i + 1 + q, csc = cs(c);
+                for (; c + 3 * Q <= r; c += 4 * Q) {
+                    const int d0 = Q * m - Q * c - Q * (Q - 1) / 2, d1 = d0 - Q * Q, d2 = d1 - Q * Q;
+                    const int a0 = csc + r - c, a1 = a0 + d0 - Q, a2 = a1 + d1 - Q, a3 = a2 + d2 - Q;
+                    const T t0 = L[a0], t1 = L[a1], t2 = L[a2], t3 = L[a3];
+                    L[a0] = t0 - (vr * ww[c] + wr * vv[c]);
+                    L[a1] = t1 - (vr * ww[c + Q] + wr * vv[c + Q]);
+                    L[a2] = t2 - (vr * ww[c + 2 * Q] + wr * vv[c + 2 * Q]);
+                    L[a3] = t3 - (vr * ww[c + 3 * Q] + wr * vv[c + 3 * Q]);
+                    csc += 4 * d0 - 6 * Q * Q;
+                }
                 for (; c <= r; c += Q) {
                     L[csc + r - c] -= vr * ww[c] + wr * vv[c];
                     csc += Q * m - Q * c - Q * (Q - 1) / 2;

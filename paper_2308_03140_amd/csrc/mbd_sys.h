@@ -93,7 +93,8 @@ struct PerRecip {
 };
 // U(q) for every q (before the assembly; the adjoint reuses it)
 void per_recip_basis_launch(hipStream_t st, const SysDesc* sd, const double* qcart, int nq, const PerRecip& pr);
-// Writes the whole embedded Q(q) (and its FP32 copy when Q32.p is set)
+// Writes the whole embedded Q(q) (and its FP32 copy when Q32.p is set); with
+// cc and om null, the lattice sum T(q) itself (c = 1, no omega^2 diagonal)
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                                   const double* qcart, int nq, const int* img, int nimg, const PerRecip& pr,
                                   MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N);
@@ -117,6 +118,10 @@ void mbd_ts_launch(hipStream_t st, const SysDesc* sd, int N, const double* om, c
 // weighted terms {E, E_Gould, min(1+x), E^(1..norder)}
 void mbd_freq_coeff_launch(hipStream_t st, const SysDesc* sd, const double* om0, const double* u, int nfreq, int N,
                            double* om_f, double* cc_f);
+// periodic K(u_f, q) = C_f T(q) C_f for every frequency f and q (T: the
+// embedded lattice sums, as the periodic assembly writes them without c, omega)
+void mbd_freq_scale_launch(hipStream_t st, const double* cc_f, int N, int nfreq, int nq, MatBatch<double> T,
+                           MatBatch<double> K);
 void mbd_freq_terms_launch(hipStream_t st, const int* ns, int nmat, const double* lam, long long sL, int norder,
                            double* part, const double* wf, int nfreq, int nq, int embed, double* terms);
 
