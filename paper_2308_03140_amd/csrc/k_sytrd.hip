@@ -530,37 +530,34 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
 // <= M0, one workgroup of 1024 threads per matrix: thread (q, r) = tid / 256,
 // tid % 256 works on row r and on the columns c = q (mod 4), so that each
 // SIMD holds four waves.  The lower triangle is held packed by columns in
-// LDS (column c holds rows c .. m-1).  Per column i: the reflector of
-// x = A(i+1:m, i) with the panel path's convention (beta = -sign(alpha) ||x||,
-// tau = (beta - alpha) / beta, v(i+1) = 1, v(r) = x(r) / (alpha - beta)),
-// y = tau A v over the trailing block, w = y - (tau / 2)(y^T v) v, and the
-// rank-2 update A -= v w^T + w v^T of its lower triangle.  d, e, tau and the
+// LDS (column c holds rows c .. m-1).  Per column i, s = i + 1, with the
+// panel path's reflector convention (beta = -sign(alpha) ||x||, tau =
+// (beta - alpha) / beta, v(s) = 1, v(r) = x(r) / (alpha - beta)) for x =
+// A(s:m-1, i), alpha = x(s):
+//   1. y' = A x' over the trailing block for x' = x with x'(s) = 0, which
+//      needs no reflector scalars, and with it the partial sums of x^T x
+//      (r > s), x'^T A x' and x'^T A e_s;                        barrier
+//   2. every thread forms beta, tau and scale = 1/(alpha - beta) from the
+//      same sums; A v = scale y' + A e_s, v^T A v = scale^2 x'^T A x' +
+//      2 scale x'^T A e_s + A(s,s), y = tau A v, w = y - (tau/2)(y^T v) v;
+//                                                                 barrier
+//   3. the rank-2 update A -= v w^T + w v^T of the lower triangle; barrier.
+// Three barriers per column (none when tau = 0).  d, e, tau and the
 // reflectors (stored in A below the diagonal) are written as the panel path
 // writes them.
 // ---------------------------------------------------------------------------
 #define SYTRD_TAIL_THREADS 1024
-template <typename T>
-__device__ __forceinline__ T block_sum1024(T v, T* red) {
-    v = wave_sum(v);
-    const int wv = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[wv] = v;
-    __syncthreads();
-    T s = T(0);
-#pragma unroll
-    for (int k = 0; k < 16; k++) s += red[k];
-    return s;
-}
 
 template <typename T>
 __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<T> w) {
     constexpr int M0 = SytrdTail<T>::M0;
     constexpr int Q = SYTRD_TAIL_THREADS / 256;
+    constexpr int NW = SYTRD_TAIL_THREADS / 64;
     static_assert(M0 <= 256, "one row per thread of a quarter");
     __shared__ T L[M0 * (M0 + 1) / 2];
     __shared__ T vv[M0], ww[M0];
-    __shared__ T yp[Q][M0];
-    __shared__ T red[SYTRD_TAIL_THREADS / 64];
+    __shared__ T yp[Q - 1][M0];   // SYMV partials of quarters 1 .. Q-1 (quarter 0 keeps its own)
+    __shared__ T red[2][3][NW];   // per-wave partial sums, by column parity
     const int b = blockIdx.x;
     const int n = w.ns[b];
     const int k0 = sytrd_tail_start<T>(n);
@@ -570,6 +567,7 @@ __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<
     const long long ld = w.A.ld;
     const int r = threadIdx.x & 255;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+    const int wv = threadIdx.x >> 6;
     const bool rv = r < m;
     // start of packed column c
     auto cs = [m](int c) { return c * m - c * (c - 1) / 2; };
@@ -599,10 +597,63 @@ __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<
     T* e = w.e + (long long)b * w.sD + k0;
     T* tau_o = w.tau + (long long)b * w.sD + k0;
     for (int i = 0; i + 1 < m; i++) {
-        const int ci = cs(i);
-        const T xr = (r > i && rv) ? L[ci + r - i] : T(0);
+        const int s = i + 1, ci = cs(i), css = cs(s);
+        const bool row = rv && r >= s;       // rows of the trailing block
+        const T xr = (rv && r > s) ? L[ci + r - i] : T(0);   // x'(r)
+        // 1. y'(r) partial over c = s + q, s + q + Q, ... (c > s: x'(s) = 0),
+        // A(r, c) from column c while c <= r, then from column r; four
+        // columns per step with their loads issued together
+        T ys = T(0);
+        if (row) {
+            int c = s + q + (q == 0 ? Q : 0), csc = cs(c);
+            const T* xc = L + ci - i;   // x'(c) = xc[c]
+            T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+            for (; c + 3 * Q <= r; c += 4 * Q) {
+                // cs(c + Q) - cs(c) = Q m - Q c - Q (Q - 1) / 2, falling by Q^2 per step
+                const int d0 = Q * m - Q * c - Q * (Q - 1) / 2, d1 = d0 - Q * Q, d2 = d1 - Q * Q;
+                const int a0 = csc + r - c, a1 = a0 + d0 - Q, a2 = a1 + d1 - Q, a3 = a2 + d2 - Q;
+                s0 += L[a0] * xc[c];
+                s1 += L[a1] * xc[c + Q];
+                s2 += L[a2] * xc[c + 2 * Q];
+                s3 += L[a3] * xc[c + 3 * Q];
+                csc += 4 * d0 - 6 * Q * Q;
+            }
+            for (; c <= r; c += Q) {
+                s0 += L[csc + r - c] * xc[c];
+                csc += Q * m - Q * c - Q * (Q - 1) / 2;
+            }
+            for (; c + 3 * Q < m; c += 4 * Q) {
+                const int a0 = csr + c - r;
+                s0 += L[a0] * xc[c];
+                s1 += L[a0 + Q] * xc[c + Q];
+                s2 += L[a0 + 2 * Q] * xc[c + 2 * Q];
+                s3 += L[a0 + 3 * Q] * xc[c + 3 * Q];
+            }
+            for (; c < m; c += Q) s0 += L[csr + c - r] * xc[c];
+            ys = (s0 + s1) + (s2 + s3);
+        }
+        const T ars = row ? L[css + r - s] : T(0);   // A(r, s)
+        {
+            const T p0 = wave_sum(q == 0 ? xr * xr : T(0));
+            const T p1 = wave_sum(xr * ys);
+            const T p2 = wave_sum(q == 0 ? xr * ars : T(0));
+            if ((threadIdx.x & 63) == 0) {
+                red[i & 1][0][wv] = p0;
+                red[i & 1][1][wv] = p1;
+                red[i & 1][2][wv] = p2;
+            }
+        }
+        if (q > 0 && rv) yp[q - 1][r] = ys;
+        __syncthreads();
+        // 2. reflector and w from the sums (the same order in every thread)
+        T xn2 = T(0), xax = T(0), xae = T(0);
+#pragma unroll
+        for (int k = 0; k < NW; k++) {
+            xn2 += red[i & 1][0][k];
+            xax += red[i & 1][1][k];
+            xae += red[i & 1][2][k];
+        }
         const T alpha = L[ci + 1];
-        const T xn2 = block_sum1024(q == 0 && r > i + 1 ? xr * xr : T(0), red);
         T beta, tau, scale;
         if (xn2 == T(0)) {
             tau = T(0); beta = alpha; scale = T(0);
@@ -612,61 +663,29 @@ __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<
             tau = (beta - alpha) / beta;
             scale = T(1) / (alpha - beta);
         }
-        const T vr = (r == i + 1) ? T(1) : (r > i + 1 && rv ? xr * scale : T(0));
         if (q == 0) {
-            if (rv) vv[r] = vr;
-            if (r > i && rv) A[r + (long long)i * ld] = vr;
+            const T vr = (r == s) ? T(1) : xr * scale;
+            if (row) A[r + (long long)i * ld] = vr;
             if (r == 0) {
                 d[i] = L[ci];
                 e[i] = beta;
                 tau_o[i] = tau;
             }
-        }
-        __syncthreads();
-        if (tau != T(0)) {
-            // y(r) = tau sum_c A(r, c) v(c) over the trailing block, quarter q
-            // taking c = i + 1 + q, i + 1 + q + 4, ...: A(r, c) from column c
-            // while c <= r, then from column r.  Four columns per step with
-            // their loads issued together (the loop is LDS-latency bound).
-            T ys = T(0);
-            if (r > i && rv) {
-                int c = i + 1 + q, csc = cs(c);
-                T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-                for (; c + 3 * Q <= r; c += 4 * Q) {
-                    // cs(c + Q) - cs(c) = Q m - Q c - Q (Q - 1) / 2, falling by Q^2 per step
-                    const int d0 = Q * m - Q * c - Q * (Q - 1) / 2, d1 = d0 - Q * Q, d2 = d1 - Q * Q;
-                    const int a0 = csc + r - c, a1 = a0 + d0 - Q, a2 = a1 + d1 - Q, a3 = a2 + d2 - Q;
-                    s0 += L[a0] * vv[c];
-                    s1 += L[a1] * vv[c + Q];
-                    s2 += L[a2] * vv[c + 2 * Q];
-                    s3 += L[a3] * vv[c + 3 * Q];
-                    csc += 4 * d0 - 6 * Q * Q;
-                }
-                for (; c <= r; c += Q) {
-                    s0 += L[csc + r - c] * vv[c];
-                    csc += Q * m - Q * c - Q * (Q - 1) / 2;
-                }
-                for (; c + 3 * Q < m; c += 4 * Q) {
-                    const int a0 = csr + c - r;
-                    s0 += L[a0] * vv[c];
-                    s1 += L[a0 + Q] * vv[c + Q];
-                    s2 += L[a0 + 2 * Q] * vv[c + 2 * Q];
-                    s3 += L[a0 + 3 * Q] * vv[c + 3 * Q];
-                }
-                for (; c < m; c += Q) s0 += L[csr + c - r] * vv[c];
-                ys = (s0 + s1) + (s2 + s3);
+            if (tau != T(0) && row) {
+                const T yr = tau * (scale * (((ys + yp[0][r]) + yp[1][r]) + yp[2][r]) + ars);
+                const T vav = scale * scale * xax + T(2) * scale * xae + L[css];
+                const T ytv = tau * vav;
+                vv[r] = vr;
+                ww[r] = yr - T(0.5) * tau * ytv * vr;
             }
-            if (rv) yp[q][r] = ys;
+        }
+        if (tau != T(0)) {
             __syncthreads();
-            const T yr = rv ? tau * ((yp[0][r] + yp[1][r]) + (yp[2][r] + yp[3][r])) : T(0);
-            const T ytv = block_sum1024(q == 0 ? yr * vr : T(0), red);
-            const T wr = yr - T(0.5) * tau * ytv * vr;
-            if (q == 0 && rv) ww[r] = wr;
-            __syncthreads();
-            // A(r, c) -= v(r) w(c) + w(r) v(c), c = i + 1 + q, ... <= r; four
+            // 3. A(r, c) -= v(r) w(c) + w(r) v(c), c = s + q, ... <= r; four
             // columns per step, all loads before the stores
-            if (r > i && rv) {
-                int c = i + 1 + q, csc = cs(c);
+            if (row) {
+                const T vr = vv[r], wr = ww[r];
+                int c = s + q, csc = cs(c);
                 for (; c + 3 * Q <= r; c += 4 * Q) {
                     const int d0 = Q * m - Q * c - Q * (Q - 1) / 2, d1 = d0 - Q * Q, d2 = d1 - Q * Q;
                     const int a0 = csc + r - c, a1 = a0 + d0 - Q, a2 = a1 + d1 - Q, a3 = a2 + d2 - Q;
