@@ -695,7 +695,10 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         PhaseTimer ph(&c->prof, st, 6);
         oa_f2d_launch(st, ns_dev, nmax, nmat, X32, Xd);
         oa_step_launch(st, ns_dev, nmax, nmat, A64, Xd, Y, S, G, lam, nmax, ow, stats, nullptr, skip2, X32);  // X1 in Y
-        oa_step_launch(st, ns_dev, nmax, nmat, A64, Y, S, Xd, G, lam, nmax, ow, stats + 4 * nmat, skip2,
+        // the second step is accepted only far below the threshold
+        OaWork ow2 = ow;
+        ow2.rho_next = (ow.rho_next > 0.0 ? ow.rho_next : OA_RHO_NEXT) / OA_RHO_FINAL_DIV;
+        oa_step_launch(st, ns_dev, nmax, nmat, A64, Y, S, Xd, G, lam, nmax, ow2, stats + 4 * nmat, skip2,
                        skip3, MatBatch<float>{nullptr, 0, 0});                                                                   // X2 in S
         skip_dev = skip2;
         conv_dev = skip3;

@@ -36,20 +36,24 @@
 // when the step cut a run of linked columns into windows of OA_KMAX (a cut
 // between columns whose lam agree to rounding is harmless and not counted):
 // the second step's runs then form around the old cut, where the pairs left
-// over sit.  If the second step again ends with rho above the threshold or
-// with a cut, the matrix is reported as not converged.  The decisions stay on
+// over sit.  The second step starts from the first one's remainder, so on a
+// matrix it can treat it ends near rounding level; if it ends with rho above
+// OA_RHO_FINAL_DIV times less than the threshold, or with a cut, pairs are
+// left that the windows could not resolve (a wide band of near-degenerate
+// columns: there rho stayed at 2e-6 and the dE/domega error reached 3e-6),
+// and the matrix is reported as not converged.  The decisions stay on
 // the device (per-matrix flags), so captured launch graphs remain valid.
 #include "mbd_internal.h"
 #include "gemm_mfma.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
 
-// Default second-step threshold (OaWork::rho_next overrides when > 0).  rho
-// estimates the remainder before the column rescaling, which removes most of
-// it (measured factor 3-6 on FP32 eigenvectors of n = 100..6000); at 3e-5 the
-// element error left in Q^{-1/2} stays near 6e-6 or below, which keeps the
-// gradients within 1e-6 and the energy within 1e-12 Ha/atom of FP64.
-#define OA_RHO_NEXT 3e-5
+// The default threshold OA_RHO_NEXT = 3e-5 (OaWork::rho_next overrides when
+// > 0): rho estimates the remainder before the column rescaling, which
+// removes most of it (measured factor 3-6 on FP32 eigenvectors of n =
+// 100..6000); at 3e-5 the element error left in Q^{-1/2} stays near 6e-6 or
+// below, which keeps the gradients within 1e-6 and the energy within 1e-12
+// Ha/atom of FP64.
 #define OA_TAU 1e-4
 #define OA_LINK 4
 #define OA_CP 6  // per-column partials: s2 (then eta), r2, max|R|, |lam|, max|x|, spare

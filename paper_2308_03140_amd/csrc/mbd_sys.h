@@ -49,6 +49,11 @@ void mbd_grad_finite_launch(hipStream_t st, const SysDesc* sd, int nsys, int Nma
 
 // Ogita-Aishima refinement (one step per call; see k_refine.hip)
 #define OA_KMAX 32  // largest window of close eigenvalues solved by Rayleigh-Ritz
+// Default remainder threshold of the first refinement step (rho_next
+// overrides when > 0) and the factor by which the second step must end below
+// the threshold in force
+#define OA_RHO_NEXT 3e-5
+#define OA_RHO_FINAL_DIV 300.0
 struct OaWork {
     double* colpart;  // [nbatch][nmax][6] per-column partial sums
     unsigned* nclust; // [nbatch] runs of linked columns the last step cut into windows
@@ -57,7 +62,7 @@ struct OaWork {
     double* wv;       // [nbatch][nmax][OA_KMAX] window rotation, per column
     double* gdiag;    // [nbatch][nmax] diagonal of X^T X
     int* fexp;        // [nbatch][nmax] power-of-two scale of each F_small column (first step)
-    double rho_next;  // second-step threshold on the remainder estimate (<= 0: default)
+    double rho_next;  // threshold on the step's remainder estimate (<= 0: default OA_RHO_NEXT)
 };
 size_t oa_colpart_doubles(int nmax, int nbatch);
 void oa_f2d_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<float> X32, MatBatch<double> Xd);
