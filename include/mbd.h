@@ -64,7 +64,7 @@ typedef enum {
  * back-transform in FP32 on matrix cores with FP32 accumulation, then one
  * Ogita-Aishima refinement step of the eigenpairs in FP64 against the FP64 Q
  * (a second one where the first leaves a large remainder estimate or cuts a
- * run of linked near-degenerate columns into windows, which must end 300
+ * run of linked near-degenerate columns into windows, which must end 20
  * times below the threshold); the sqrt(lambda)
  * energy sum, the gradients and the Ewald sums stay FP64.  A system whose
  * refinement still misses its target after the second step is re-evaluated

@@ -36,12 +36,10 @@
 // when the step cut a run of linked columns into windows of OA_KMAX (a cut
 // between columns whose lam agree to rounding is harmless and not counted):
 // the second step's runs then form around the old cut, where the pairs left
-// over sit.  The second step starts from the first one's remainder, so on a
-// matrix it can treat it ends near rounding level; if it ends with rho above
-// OA_RHO_FINAL_DIV times less than the threshold, or with a cut, pairs are
-// left that the windows could not resolve (a wide band of near-degenerate
-// columns: there rho stayed at 2e-6 and the dE/domega error reached 3e-6),
-// and the matrix is reported as not converged.  The decisions stay on
+// over sit.  If the second step ends with rho above the threshold divided by
+// OA_RHO_FINAL_DIV (there rho measures the error left, where after the first
+// step it overstates it), or with a cut, the matrix is reported as not
+// converged.  The decisions stay on
 // the device (per-matrix flags), so captured launch graphs remain valid.
 #include "mbd_internal.h"
 #include "gemm_mfma.h"
