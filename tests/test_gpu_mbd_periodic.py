@@ -124,6 +124,46 @@ def test_explicit_ewald_parameters(ctx):
             assert abs(out["energy"].item() - base) <= 1e-10
 
 
+def _recip_counts(lattice, q_frac, kc):
+    """Reciprocal vectors G with 0 < |G + q| < kc, per q point (geometry only)."""
+    B = 2.0 * np.pi * np.linalg.inv(np.asarray(lattice)).T
+    m = np.array([[x, y, z] for x in range(-8, 9) for y in range(-8, 9) for z in range(-8, 9)], float)
+    G = m @ B
+    out = []
+    for qf in np.asarray(q_frac):
+        k2 = np.sum((G + qf @ B) ** 2, axis=1)
+        out.append(int(np.sum((k2 > 0.0) & (k2 < kc * kc))))
+    return out
+
+
+@pytest.mark.parametrize("kc_scale", [1e-4, 0.4])
+def test_reciprocal_sphere_empty_and_ragged(ctx, kc_scale):
+    """The reciprocal-space term runs as a product over one column per
+    reciprocal vector of each q point's sphere.  k_c far below the shortest
+    G + q leaves no column at any q (the embedding's product has no depth,
+    the adjoint's reciprocal kernels are skipped); 0.4 times the default
+    leaves the q points of a shifted mesh with different counts (padded
+    columns).  Both against the oracle with the same explicit parameters
+    (alpha0 scaled by 0.3, so that Q stays positive definite without most of
+    the reciprocal sum)."""
+    _note("periodic reciprocal sphere kc x %g %s" % (kc_scale, ctx.precision))
+    c = gen.small_crystal(64, 4, kgrid=(2, 2, 2))
+    c["q_frac"] = c["q_frac"] + np.array([0.1, 0.05, 0.0])
+    c["alpha0"] = 0.3 * c["alpha0"]
+    g0, rc0, kc0 = oracle.ewald_defaults(c["lattice"])
+    kc = kc_scale * kc0
+    counts = _recip_counts(c["lattice"], c["q_frac"], kc)
+    if kc_scale < 1e-2:
+        assert max(counts) == 0, counts
+    else:
+        assert 0 < min(counts) < max(counts), counts
+    ref = oracle.mbd_periodic(c["coords"], c["lattice"], c["q_frac"], c["alpha0"], c["omega"], c["rvdw"],
+                              c["beta"], c["a"], gamma=g0, rc=rc0, kc=kc)
+    out = _run(ctx, c, ewald=(g0, rc0, kc))
+    torch.cuda.synchronize()
+    _compare(ctx, 4, out, ref)
+
+
 def test_periodic_c6_input(ctx):
     from paper_2308_03140_amd import torch_api as T
     _note("periodic c6 input %s" % ctx.precision)
