@@ -76,6 +76,8 @@ class Context:
 
 
 def _dev(x, device):
+    if isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.device == device and x.is_contiguous():
+        return x
     return torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
 
 
@@ -85,7 +87,9 @@ def make_system(coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_f
     (or array-likes copied to `device`); lattice and q_frac stay on the host."""
     keep = []
     dev = device if device is not None else coords.device
-    c = _dev(coords, dev).reshape(-1, 3)
+    c = _dev(coords, dev)
+    if c.dim() != 2 or c.shape[1] != 3:
+        c = c.reshape(-1, 3)
     a0 = _dev(alpha0, dev); w = _dev(omega, dev); rv = _dev(rvdw, dev)
     keep += [c, a0, w, rv]
     s = A.MbdSystem()
@@ -93,7 +97,8 @@ def make_system(coords, alpha0, omega, rvdw, beta=0.83, a=6.0, lattice=None, q_f
     s.coords = c.data_ptr(); s.alpha0 = a0.data_ptr(); s.omega_or_c6 = w.data_ptr(); s.rvdw = rv.data_ptr()
     s.param_kind = A.MBD_PARAM_C6 if param == "c6" else A.MBD_PARAM_OMEGA
     s.beta = float(beta); s.a = float(a)
-    s.ewald_gamma, s.ewald_rc, s.ewald_kc = [float(x) for x in ewald]
+    if lattice is not None:
+        s.ewald_gamma, s.ewald_rc, s.ewald_kc = [float(x) for x in ewald]
     if lattice is not None:
         lat = (ctypes.c_double * 9)(*[float(x) for x in torch.as_tensor(lattice, dtype=torch.float64).reshape(-1).tolist()])
         keep.append(lat)
@@ -250,20 +255,33 @@ def evaluate_batch(ctx, systems, gradients=True, errors=True):
                            sy.get("a", 6.0), device=dev)
         keep.append(k)
         sarr[i] = s
-        N = s.n_atoms
-        o = {"energy": torch.empty(1, dtype=torch.float64, device=dev)}
+    # one allocation per output kind for the whole batch; each system gets views
+    sizes = [sarr[i].n_atoms for i in range(n)]
+    tot = sum(sizes)
+    energy_all = torch.empty(n, dtype=torch.float64, device=dev)
+    if gradients:
+        gc_all = torch.empty(tot, 3, dtype=torch.float64, device=dev)
+        ga_all = torch.empty(tot, dtype=torch.float64, device=dev)
+        gw_all = torch.empty(tot, dtype=torch.float64, device=dev)
+    if errors:
+        err_all = torch.zeros(n, 4, dtype=torch.float64, device=dev)
+    off = 0
+    for i in range(n):
+        N = sizes[i]
+        o = {"energy": energy_all[i:i + 1]}
         rarr[i].energy = o["energy"].data_ptr()
         if gradients:
-            o["grad_coords"] = torch.empty(N, 3, dtype=torch.float64, device=dev)
-            o["grad_alpha0"] = torch.empty(N, dtype=torch.float64, device=dev)
-            o["grad_omega"] = torch.empty(N, dtype=torch.float64, device=dev)
+            o["grad_coords"] = gc_all[off:off + N]
+            o["grad_alpha0"] = ga_all[off:off + N]
+            o["grad_omega"] = gw_all[off:off + N]
             rarr[i].grad_coords = o["grad_coords"].data_ptr()
             rarr[i].grad_alpha0 = o["grad_alpha0"].data_ptr()
             rarr[i].grad_omega_or_c6 = o["grad_omega"].data_ptr()
         if errors:
-            o["errors"] = torch.zeros(4, dtype=torch.float64, device=dev)
+            o["errors"] = err_all[i]
             rarr[i].errors = o["errors"].data_ptr()
         outs.append(o)
+        off += N
     code = A.mbd_evaluate_batch(ctx.handle, sarr, want, rarr, stat)
     for i in range(n):
         outs[i]["status"] = int(stat[i])
