@@ -188,22 +188,23 @@ __global__ __launch_bounds__(256) void mbd_invsqrt4_kernel(const int* ns, const 
     sc[(long long)b * sL + k] = x > 0.0 ? 1.0 / sqrt(sqrt(x)) : 0.0;
 }
 
-// X(:, c) *= sc_c (X is not needed afterwards)
+// X(:, c) *= sc_c (X is not needed afterwards); one workgroup per column
 __global__ __launch_bounds__(256) void mbd_scale_cols_kernel(const int* ns, MatBatch<double> X, const double* sc,
                                                                long long sL) {
     const int b = blockIdx.z;
     const int n = ns[b];
-    const int c = blockIdx.y;
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (c >= n || r >= n) return;
-    X.at(b)[r + (long long)c * X.ld] *= sc[(long long)b * sL + c];
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    const double f = sc[(long long)b * sL + c];
+    double* x = X.at(b) + (long long)c * X.ld;
+    for (int r = threadIdx.x; r < n; r += 256) x[r] *= f;
 }
 
 // M = (X sc)(X sc)^T, lower triangle: the columns of X are scaled in place,
 // then the symmetric product runs as a plain lower-triangle GEMM
 void mbd_inv_sqrt_launch(hipStream_t st, const int* ns, int nmax, int nbatch, MatBatch<double> X,
                          const double* sc, long long sL, MatBatch<double> M) {
-    hipLaunchKernelGGL(mbd_scale_cols_kernel, dim3((nmax + 255) / 256, nmax, nbatch), dim3(256), 0, st, ns, X, sc, sL);
+    hipLaunchKernelGGL(mbd_scale_cols_kernel, dim3(nmax, 1, nbatch), dim3(256), 0, st, ns, X, sc, sL);
     gemm_batched<double>(st, false, true, ns, nmax, nbatch, X.p, X.ld, X.stride, X.p, X.ld, X.stride, M.p, M.ld,
                          M.stride, 1.0, 0.0, true);
 }

@@ -62,16 +62,21 @@ __global__ __launch_bounds__(256) void stedc_init_kernel(StedcWs<T> w) {
     if (threadIdx.x == 0) w.scale[b] = mx;
 }
 
-// Z0 = I, Z1 = 0 on the n x n block
+// Z0 = I, Z1 = 0 on the n x n block; one workgroup per column (a grid of
+// row chunks per column left most workgroups of a batch of small matrices
+// with nothing to do)
 template <typename T>
 __global__ __launch_bounds__(256) void stedc_fill_kernel(StedcWs<T> w) {
     const int b = blockIdx.z;
     const int n = w.ns[b];
-    const int c = blockIdx.y;
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (c >= n || r >= n) return;
-    w.Z0.at(b)[r + (long long)c * w.Z0.ld] = (r == c) ? T(1) : T(0);
-    w.Z1.at(b)[r + (long long)c * w.Z1.ld] = T(0);
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    T* z0 = w.Z0.at(b) + (long long)c * w.Z0.ld;
+    T* z1 = w.Z1.at(b) + (long long)c * w.Z1.ld;
+    for (int r = threadIdx.x; r < n; r += 256) {
+        z0[r] = (r == c) ? T(1) : T(0);
+        z1[r] = T(0);
+    }
 }
 
 // merge inputs: z vector, sorted poles, permutation
@@ -854,7 +859,7 @@ template <typename T>
 int stedc_launch(const StedcWs<T>& w, int nbatch, int nmax, hipStream_t st) {
     const int gpos = (nmax + 255) / 256;
     hipLaunchKernelGGL(stedc_init_kernel<T>, dim3(1, 1, nbatch), dim3(256), 0, st, w);
-    hipLaunchKernelGGL(stedc_fill_kernel<T>, dim3(gpos, nmax, nbatch), dim3(256), 0, st, w);
+    hipLaunchKernelGGL(stedc_fill_kernel<T>, dim3(nmax, 1, nbatch), dim3(256), 0, st, w);
     int L = 0;
     while ((1 << L) < nmax) L++;
     int src = 0;
