@@ -199,7 +199,7 @@ mbd_status make_sytrd_ws(mbd_ctx* c, MatBatch<T> A, const int* ns, int nmax, int
 // Full dense symmetric eigensolver on a batch: reduction, D&C, back-transform.
 template <typename T>
 mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host, int nmax, int nbatch, bool vectors,
-                   T* w_out, long long sW, MatBatch<T>* Xout, int** bad_out = nullptr) {
+                   T* w_out, long long sW, MatBatch<T>* Xout, int** bad_out = nullptr, bool embed_pairs = false) {
     const std::string t = tname<T>();
     const hipStream_t st = c->stream;
     const int nbk = (nmax + 63) / 64;
@@ -227,7 +227,7 @@ mbd_status run_eig(mbd_ctx* c, MatBatch<T> A, const int* ns, const int* ns_host,
     if (!vectors) {
         // eigenvalues only: Sturm-count multisection on the tridiagonal
         PhaseTimer ph(&c->prof, st, 4);
-        stebz_launch<T>(ns, nmax, nbatch, sw.d, sw.e, sw.sD, w_out, sW, st);
+        stebz_launch<T>(ns, nmax, nbatch, sw.d, sw.e, sw.sD, w_out, sW, st, embed_pairs);
         HIPCHK(hipGetLastError(), "stebz");
         if (Xout) *Xout = MatBatch<T>{nullptr, 0, 0};
         return MBD_OK;
@@ -663,7 +663,10 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     int* conv_dev = nullptr;  // per matrix: the last step met its target
     int* eig_bad = nullptr;  // per matrix: non-finite tridiagonal
     if (!fp32) {
-        mbd_status r = run_eig<double>(c, A64, ns_dev, nsh.data(), nmax, nmat, grads, lam, nmax, &X, &eig_bad);
+        // periodic matrices are real embeddings: without vectors each
+        // eigenvalue pair is found once
+        mbd_status r = run_eig<double>(c, A64, ns_dev, nsh.data(), nmax, nmat, grads, lam, nmax, &X, &eig_bad,
+                                       per != nullptr);
         if (r != MBD_OK) return r;
     } else {
         float* lam32 = wsT<float>(c, "lam32", (size_t)nmax * nmat);
@@ -1086,7 +1089,7 @@ mbd_status mbd_freq_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, in
                                    status + 1);
     }
     HIPCHK(hipGetLastError(), "freq assemble");
-    r = run_eig<double>(c, K, ns_dev, nsh.data(), nmax, nmat, false, lam, nmax, nullptr);
+    r = run_eig<double>(c, K, ns_dev, nsh.data(), nmax, nmat, false, lam, nmax, nullptr, nullptr, periodic);
     if (r != MBD_OK) return r;
     mbd_freq_terms_launch(st, ns_dev, nmat, lam, nmax, n_order, part, wf_dev, n_freq, nq, periodic ? 1 : 0, terms);
     HIPCHK(hipGetLastError(), "freq terms");

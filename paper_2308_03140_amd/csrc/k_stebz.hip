@@ -52,18 +52,25 @@ __device__ __forceinline__ int sturm_count(const T* d, const T* e, int n, double
     return c;
 }
 
+// pairs != 0: T is the tridiagonal of the real embedding [[A, -B], [B, A]]
+// of a Hermitian A + iB, whose eigenvalues all come in equal pairs
+// (lambda_{2m} = lambda_{2m+1}): only the odd indices are found and each is
+// written to both of its pair's slots (an odd order takes every index).
 template <typename T>
 __global__ __launch_bounds__(256) void stebz_kernel(const int* ns, const T* d, const T* e, long long sD, T* w,
-                                                      long long sW, int L) {
+                                                      long long sW, int L, int pairs) {
     const int b = blockIdx.z;
     const int n = ns[b];
+    const bool pr = pairs && !(n & 1);
+    const int nk = pr ? n / 2 : n;   // eigenvalue indices to find
     const int lane = threadIdx.x & 63;
     const int per_wave = 64 / L;
     const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave * per_wave >= n) return;  // the whole wavefront
+    if (wave * per_wave >= nk) return;  // the whole wavefront
     const int g = lane / L, j = lane % L;
-    const int k = wave * per_wave + g;
-    const bool active = k < n;
+    const int kq = wave * per_wave + g;
+    const bool active = kq < nk;
+    const int k = pr ? 2 * kq + 1 : kq;
     const T* db = d + (long long)b * sD;
     const T* eb = e + (long long)b * sD;
     T* wb = w + (long long)b * sW;
@@ -109,7 +116,10 @@ __global__ __launch_bounds__(256) void stebz_kernel(const int* ns, const T* d, c
             hi = nhi;
         }
     }
-    if (active && j == 0) wb[k] = (T)(0.5 * (lo + hi));
+    if (active && j == 0) {
+        wb[k] = (T)(0.5 * (lo + hi));
+        if (pr) wb[k - 1] = wb[k];
+    }
 }
 
 // lanes per eigenvalue: as many as keep the launch within the lanes the
@@ -123,13 +133,17 @@ static int stebz_lanes(long long eigenvalues) {
 
 template <typename T>
 void stebz_launch(const int* ns, int nmax, int nbatch, const T* d, const T* e, long long sD, T* w, long long sW,
-                  hipStream_t st) {
-    const int L = stebz_lanes((long long)nmax * nbatch);
+                  hipStream_t st, bool pairs) {
+    // lanes per eigenvalue from the indices actually found; the grid still
+    // covers every index of the largest order (waves past a matrix's count exit)
+    const int nk = pairs ? (nmax + 1) / 2 : nmax;
+    const int L = stebz_lanes((long long)nk * nbatch);
     const int per_wave = 64 / L;
     const int waves = (nmax + per_wave - 1) / per_wave;
-    hipLaunchKernelGGL(stebz_kernel<T>, dim3((waves + 3) / 4, 1, nbatch), dim3(256), 0, st, ns, d, e, sD, w, sW, L);
+    hipLaunchKernelGGL(stebz_kernel<T>, dim3((waves + 3) / 4, 1, nbatch), dim3(256), 0, st, ns, d, e, sD, w, sW, L,
+                       pairs ? 1 : 0);
 }
 template void stebz_launch<double>(const int*, int, int, const double*, const double*, long long, double*, long long,
-                                   hipStream_t);
+                                   hipStream_t, bool);
 template void stebz_launch<float>(const int*, int, int, const float*, const float*, long long, float*, long long,
-                                  hipStream_t);
+                                  hipStream_t, bool);

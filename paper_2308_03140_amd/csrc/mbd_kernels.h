@@ -168,10 +168,12 @@ template <typename T>
 void tridiag_guard_launch(const int* ns, int nbatch, T* d, T* e, long long sD, int* bad, hipStream_t st);
 
 // Eigenvalues only (Sturm counts with multisection, FP64 arithmetic): d, e of
-// the reduction ([nbatch] x sD), w [nbatch] x sW ascending.
+// the reduction ([nbatch] x sD), w [nbatch] x sW ascending.  pairs: the
+// matrices are real embeddings of Hermitian ones (every eigenvalue twice),
+// and each pair is found once.
 template <typename T>
 void stebz_launch(const int* ns, int nmax, int nbatch, const T* d, const T* e, long long sD, T* w, long long sW,
-                  hipStream_t st);
+                  hipStream_t st, bool pairs = false);
 
 // --- Back-transformation ---------------------------------------------------
 template <typename T>

@@ -124,6 +124,23 @@ def test_explicit_ewald_parameters(ctx):
             assert abs(out["energy"].item() - base) <= 1e-10
 
 
+@pytest.mark.parametrize("kgrid", [(2, 2, 1), (3, 1, 1)])
+def test_energy_only_eigenvalues(ctx, kgrid):
+    """Energy without gradients: on the FP64 path the eigenvalues come from
+    the Sturm-count solver, which finds each pair of the real embedding once
+    and writes it to both slots.  Energy and every eigenvalue of every q
+    against the oracle."""
+    _note("periodic energy only %s k=%s" % (ctx.precision, kgrid))
+    c = gen.small_crystal(65, 5, kgrid=kgrid)
+    ref = oracle.mbd_periodic(c["coords"], c["lattice"], c["q_frac"], c["alpha0"], c["omega"], c["rvdw"],
+                              c["beta"], c["a"], gradients=False)
+    out = _run(ctx, c, gradients=False, eigvals=True)
+    torch.cuda.synchronize()
+    assert abs(out["energy"].item() - ref["energy"]) / 5 <= TOL_E[ctx.precision]
+    tol = 1e-12 if ctx.precision == "fp64" else 1e-9
+    assert np.abs(out["eigvals"].cpu().numpy() - ref["eigs"]).max() <= tol
+
+
 def _recip_counts(lattice, q_frac, kc):
     """Reciprocal vectors G with 0 < |G + q| < kc, per q point (geometry only)."""
     B = 2.0 * np.pi * np.linalg.inv(np.asarray(lattice)).T
