@@ -285,7 +285,9 @@ mbd_status mbd_eigh(mbd_ctx *ctx, int32_t dtype, int32_t n, int32_t nbatch, void
  * the loader also takes [upper, lower] or a single target (then the GEMM
  * tile is chosen by order) and rejects tiles other than 0, 64 and 128.  An
  * evaluation uses the row of the tuned order nearest its matrix order (on a
- * log scale), the GEMM tile only when that order is within a factor 2. */
+ * log scale), the GEMM tile only when that order is within a factor 2.
+ * Both calls retire the batch launch graphs the context has captured (they
+ * hold the previous shapes); the next mbd_evaluate_batch captures anew. */
 mbd_status mbd_autotune(mbd_ctx *ctx, const int32_t *sizes, int32_t nsizes, const char *table_json_path);
 mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
 

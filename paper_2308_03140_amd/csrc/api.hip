@@ -1454,6 +1454,14 @@ mbd_status autotune_gemm_tile(mbd_ctx* c, int n, int* ts_out) {
     return MBD_OK;
 }
 
+// Captured batch sequences replay the launch shapes they were recorded with;
+// a changed tuning table retires them (after the work queued on both streams)
+void drop_graphs_synced(mbd_ctx* c) {
+    (void)hipStreamSynchronize(c->stream);
+    if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+    c->drop_graphs();
+}
+
 bool write_tuning(const mbd_ctx* c, const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return false;
@@ -1547,6 +1555,7 @@ mbd_status mbd_autotune(mbd_ctx* c, const int32_t* sizes, int32_t nsizes, const 
         e.hi = target; e.lo = lo; e.gemm_ts = ts;
         c->tune[p][n] = e;
     }
+    drop_graphs_synced(c);  // captured batches were recorded with the old launch shapes
     if (path && !write_tuning(c, path)) return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_autotune", "cannot write table");
     return MBD_OK;
 }
@@ -1556,6 +1565,7 @@ mbd_status mbd_load_tuning(mbd_ctx* c, const char* path) {
     c->err_code = 0;
     if (!path || !read_tuning(c, path))
         return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_load_tuning", "cannot read tuning table");
+    drop_graphs_synced(c);  // captured batches were recorded with the old launch shapes
     return MBD_OK;
 }
 
