@@ -265,27 +265,30 @@ __global__ __launch_bounds__(256) void ormtr_ysum_kernel(OrmtrWs<T> w, int b0, i
 }
 
 // Y_k = P_k - C_k P_h for pair p (blocks k = b0k / 64 and k + 1): Y holds
-// P_k in rows 0..63 and P_h in rows 64..127 of each column; 64 columns per
-// workgroup, so that C_k is staged once for all of them
+// P_k in rows 0..63 and P_h in rows 64..127 of each column; ORMTR_FIX_COLS
+// columns per workgroup, each staging C_k (64 columns per workgroup left
+// most compute units idle on one large matrix: 94 workgroups at order 6000)
+#define ORMTR_FIX_COLS 16
 template <typename T>
 __global__ __launch_bounds__(256) void ormtr_pair_fix_kernel(OrmtrWs<T> w, int b0k, int p) {
+    constexpr int CW = ORMTR_FIX_COLS;
     __shared__ T C[64][65];
-    __shared__ T Ph[64][65];
+    __shared__ T Ph[CW][65];
     const int b = blockIdx.z;
     const int n = w.ns[b];
     if (b0k >= n - 1) return;
-    const int c0 = blockIdx.x * 64;
+    const int c0 = blockIdx.x * CW;
     if (c0 >= n) return;
     const T* Cg = w.Cp + (long long)b * w.sC + (long long)p * 4096;
     T* Y = w.Y + (long long)b * w.sY;
-    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) C[idx & 63][idx >> 6] = Cg[idx];
+    for (int idx = threadIdx.x; idx < 64 * CW; idx += 256) {
         const int i = idx & 63, q = idx >> 6;
-        C[i][q] = Cg[idx];
         Ph[q][i] = c0 + q < n ? Y[64 + i + (long long)(c0 + q) * 128] : T(0);
     }
     __syncthreads();
     const int i = threadIdx.x & 63;
-    for (int q = threadIdx.x >> 6; q < 64; q += 4) {
+    for (int q = threadIdx.x >> 6; q < CW; q += 4) {
         const int c = c0 + q;
         if (c >= n) break;
         T s = T(0);
@@ -391,7 +394,8 @@ void ormtr_launch(const OrmtrWs<T>& w, int nbatch, int nmax, hipStream_t st) {
                            st, px);
         hipLaunchKernelGGL(ormtr_ysum_kernel<T>, dim3((128 * nmax + 255) / 256, 1, nbatch), dim3(256), 0, st, w, b0,
                            128);
-        hipLaunchKernelGGL(ormtr_pair_fix_kernel<T>, dim3((nmax + 63) / 64, 1, nbatch), dim3(256), 0, st, w, b0, p);
+        hipLaunchKernelGGL(ormtr_pair_fix_kernel<T>, dim3((nmax + ORMTR_FIX_COLS - 1) / ORMTR_FIX_COLS, 1, nbatch),
+                           dim3(256), 0, st, w, b0, p);
         VyProb<T, 64, 128> py;
         py.X = w.X; py.ns = w.ns; py.b0 = b0; py.VT = w.VT; py.sVT = w.sVT; py.nmax = w.nmax; py.Y = w.Y; py.sY = w.sY;
         py.tiles_n = tiles;
