@@ -412,8 +412,8 @@ static void recip_columns(const SysDesc& d, PeriodicSetup& ps) {
 
 // Device column lists and basis workspaces of the reciprocal-space product
 // (W, the adjoint's, only when gradients are wanted).
-static mbd_status make_per_recip(mbd_ctx* c, const PeriodicSetup& ps, int N, int nq, const int* rec_dev, bool with_w,
-                                 PerRecip& pr) {
+static mbd_status make_per_ewald(mbd_ctx* c, const PeriodicSetup& ps, int N, int nq, const int* rec_dev, bool with_w,
+                                 PerEwald& pr) {
     pr.rec = rec_dev;
     pr.ncol = ps.ncol;
     pr.ldz = round_up(6 * N, 64);
@@ -421,7 +421,8 @@ static mbd_status make_per_recip(mbd_ctx* c, const PeriodicSetup& ps, int N, int
     int* col = wsT<int>(c, "rcol", std::max<size_t>(1, ps.rcol.size()));
     pr.Z = wsT<double>(c, "rZ", (size_t)pr.sZ * nq);
     pr.W = with_w ? wsT<double>(c, "rW", (size_t)pr.sZ * nq) : nullptr;
-    if (!col || !pr.Z || (with_w && !pr.W)) return (mbd_status)c->err_code;
+    pr.phase = wsT<double>(c, "rphase", std::max<size_t>(2, ps.img.size() / 3 * 2 * (size_t)nq));
+    if (!col || !pr.Z || (with_w && !pr.W) || !pr.phase) return (mbd_status)c->err_code;
     if (!ps.rcol.empty())
         HIPCHK(hipMemcpyAsync(col, ps.rcol.data(), sizeof(int) * ps.rcol.size(), hipMemcpyHostToDevice, c->stream),
                "upload");
@@ -635,7 +636,7 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
     double* qmult = nullptr;
     int* img = nullptr;
     int* rec = nullptr;
-    PerRecip prc = {};
+    PerEwald prc = {};
     if (per) {
         qcart = wsT<double>(c, "qcart", per->qcart.size());
         qmult = wsT<double>(c, "qmult", (size_t)nq);
@@ -646,9 +647,9 @@ mbd_status run_core(mbd_ctx* c, std::vector<SysDesc>& sds, unsigned want, std::v
         HIPCHK(hipMemcpyAsync(qmult, per->qmult.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(img, per->img.data(), sizeof(int) * per->img.size(), hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(rec, per->rec.data(), sizeof(int) * per->rec.size(), hipMemcpyHostToDevice, st), "upload");
-        const mbd_status rr = make_per_recip(c, *per, sds[0].N, nq, rec, grads, prc);
+        const mbd_status rr = make_per_ewald(c, *per, sds[0].N, nq, rec, grads, prc);
         if (rr != MBD_OK) return rr;
-        per_recip_basis_launch(st, sd_dev, qcart, nq, prc);
+        per_recip_basis_launch(st, sd_dev, qcart, nq, img, (int)per->img.size() / 3, prc);
         mbd_assemble_periodic_launch(st, sd_dev, om, cc, qcart, nq, img, (int)per->img.size() / 3, prc, A64, A32,
                                      status, sds[0].N);
     } else {
@@ -1073,14 +1074,14 @@ mbd_status mbd_freq_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, in
         HIPCHK(hipMemcpyAsync(qcart, ps.qcart.data(), sizeof(double) * ps.qcart.size(), hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(img, ps.img.data(), sizeof(int) * ps.img.size(), hipMemcpyHostToDevice, st), "upload");
         HIPCHK(hipMemcpyAsync(rec, ps.rec.data(), sizeof(int) * ps.rec.size(), hipMemcpyHostToDevice, st), "upload");
-        PerRecip prc = {};
-        r = make_per_recip(c, ps, N, nq, rec, false, prc);
+        PerEwald prc = {};
+        r = make_per_ewald(c, ps, N, nq, rec, false, prc);
         if (r != MBD_OK) return r;
         // the lattice sums T(q) depend on the geometry only: assembled once,
         // then scaled by c_i c_j per frequency
         const MatBatch<double> Tq = {wsT<double>(c, "freq_T", (size_t)stride * nq), ld, stride};
         if (!Tq.p) return (mbd_status)c->err_code;
-        per_recip_basis_launch(st, sd_dev + 1, qcart, nq, prc);
+        per_recip_basis_launch(st, sd_dev + 1, qcart, nq, img, (int)ps.img.size() / 3, prc);
         mbd_assemble_periodic_launch(st, sd_dev + 1, nullptr, nullptr, qcart, nq, img, (int)ps.img.size() / 3, prc, Tq,
                                      MatBatch<float>{nullptr, ld, stride}, status + 1, N);
         mbd_freq_scale_launch(st, cc_f, N, n_freq, nq, Tq, K);

@@ -124,9 +124,10 @@ __device__ __forceinline__ bool image_term(const double* x, double gamma, double
 __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const SysDesc* sd, const double* om,
                                                                           const double* cc, const double* qcart,
                                                                           int nq, int lpp, const int* img, int nimg,
-                                                                          MatBatch<double> Q, unsigned* status) {
-    __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9];
-    __shared__ int oks[PER_LANES];
+                                                                          const double* phase, MatBatch<double> Q,
+                                                                          unsigned* status) {
+    __shared__ double Fs[PER_LANES][9];
+    __shared__ int oks[PER_LANES];   // image index + 1 of the slot's term, 0 if empty
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
     const int slot = threadIdx.x / lpp, ql = threadIdx.x % lpp;
@@ -141,6 +142,9 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
     const int qc = qv_ok ? q : 0;
     const double qv[3] = {qcart[3 * qc], qcart[3 * qc + 1], qcart[3 * qc + 2]};
     const double R0 = S.beta * (S.rvdw[i] + S.rvdw[j]);
+    // e^{-i q.x} = e^{-i q.r} e^{-i q.R_n}, the second factor from the table
+    double sb, cb;
+    sincos(-(qv[0] * r[0] + qv[1] * r[1] + qv[2] * r[2]), &sb, &cb);
     double Tre[9], Tim[9];
     for (int k = 0; k < 9; k++) { Tre[k] = 0.0; Tim[k] = 0.0; }
     for (int t0 = 0; t0 < nimg; t0 += lpp) {
@@ -156,8 +160,7 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
                     if (pv && i != j && d2 < 1e-16 && blockIdx.y == 0) atomicOr(&status[0], MBD_ST_COINCIDENT);
                     double F[9];
                     if (image_term(x, S.gamma, S.rc, R0, S.a, F, nullptr)) {
-                        ok = 1;
-                        for (int c = 0; c < 3; c++) xs[threadIdx.x][c] = x[c];
+                        ok = t + 1;
                         for (int k = 0; k < 9; k++) Fs[threadIdx.x][k] = F[k];
                     }
                 }
@@ -169,8 +172,8 @@ __global__ __launch_bounds__(PER_LANES) void mbd_assemble_periodic_kernel(const 
         for (int u0 = 0; u0 < tn; u0++) {
             const int u = slot * lpp + u0;
             if (!oks[u]) continue;
-            double sph, cph;
-            sincos(-(qv[0] * xs[u][0] + qv[1] * xs[u][1] + qv[2] * xs[u][2]), &sph, &cph);
+            const double* pt = phase + 2 * ((long long)(oks[u] - 1) * nq + qc);
+            const double cph = cb * pt[0] - sb * pt[1], sph = cb * pt[1] + sb * pt[0];
             for (int k = 0; k < 9; k++) { Tre[k] += Fs[u][k] * cph; Tim[k] += Fs[u][k] * sph; }
         }
         __syncthreads();
@@ -213,7 +216,7 @@ __device__ __forceinline__ void recip_column(const SysDesc& S, const int* rec, i
 // Columns of U(q), embedded: rows 0 .. n-1 Re U, rows n .. 2n-1 Im U; the
 // columns past the q point's count are zero.  Grid (ncol, nq), 64 threads
 // over the atoms.
-__global__ __launch_bounds__(64) void per_recip_basis_kernel(const SysDesc* sd, const double* qcart, PerRecip pr) {
+__global__ __launch_bounds__(64) void per_recip_basis_kernel(const SysDesc* sd, const double* qcart, PerEwald pr) {
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
     const int g = blockIdx.x, q = blockIdx.y;
@@ -230,6 +233,22 @@ __global__ __launch_bounds__(64) void per_recip_basis_kernel(const SysDesc* sd, 
             Zc[n + 3 * i + a] = -sw * k[a] * sn;
         }
     }
+}
+
+// Real-space phases: phase[t][q] = (cos, sin) of -q.R_n for image t, so that
+// the lanes of a pair (one q each) read consecutive entries.
+__global__ __launch_bounds__(256) void per_phase_kernel(const SysDesc* sd, const double* qcart, int nq,
+                                                        const int* img, int nimg, double* phase) {
+    const SysDesc& S = sd[0];
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long long)nimg * nq) return;
+    const int t = (int)(e / nq), q = (int)(e % nq);
+    double Rn[3];
+    for (int c = 0; c < 3; c++) Rn[c] = img[3 * t] * S.lat[c] + img[3 * t + 1] * S.lat[3 + c] + img[3 * t + 2] * S.lat[6 + c];
+    double sn, cs;
+    sincos(-(qcart[3 * q] * Rn[0] + qcart[3 * q + 1] * Rn[1] + qcart[3 * q + 2] * Rn[2]), &sn, &cs);
+    phase[2 * e] = cs;
+    phase[2 * e + 1] = sn;
 }
 
 // Reciprocal term of the embedding: [Re; Im] of C U U^H C is [U_r, -U_i;
@@ -304,9 +323,10 @@ struct PerRecAsmProb {
 __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysDesc* sd, const double* om,
                                                                       const double* cc, const double* qcart, int nq,
                                                                       int lpp, const int* img, int nimg,
-                                                                      MatBatch<double> M, double* part) {
-    __shared__ double xs[PER_LANES][3], Fs[PER_LANES][9], dFs[PER_LANES][27], F0s[PER_LANES][9];
-    __shared__ int ns_[PER_LANES][3], oks[PER_LANES];
+                                                                      const double* phase, MatBatch<double> M,
+                                                                      double* part) {
+    __shared__ double Fs[PER_LANES][9], dFs[PER_LANES][27], F0s[PER_LANES][9];
+    __shared__ int ns_[PER_LANES][3], oks[PER_LANES];   // oks: image index + 1 of the slot's term, 0 if empty
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
     const int slot = threadIdx.x / lpp, ql = threadIdx.x % lpp;
@@ -323,6 +343,9 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
     const double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
     const double qv[3] = {qcart[3 * q], qcart[3 * q + 1], qcart[3 * q + 2]};
     const double R0 = S.beta * (S.rvdw[i] + S.rvdw[j]);
+    // e^{-i q.x} = e^{-i q.r} e^{-i q.R_n}, the second factor from the table
+    double sb, cb;
+    sincos(-(qv[0] * r[0] + qv[1] * r[1] + qv[2] * r[2]), &sb, &cb);
     // M_{jb,ia}
     double Mr[9], Mi[9];
     const double* Mb = M.at(q);
@@ -347,8 +370,8 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
                 const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
                 double F[9], dF[27], F0[9];
                 if (d2 != 0.0 && image_term(x, S.gamma, S.rc, R0, S.a, F, dF, F0)) {
-                    ok = 1;
-                    for (int c = 0; c < 3; c++) { xs[threadIdx.x][c] = x[c]; ns_[threadIdx.x][c] = nn[c]; }
+                    ok = t + 1;
+                    for (int c = 0; c < 3; c++) ns_[threadIdx.x][c] = nn[c];
                     for (int k = 0; k < 9; k++) Fs[threadIdx.x][k] = F[k];
                     for (int k = 0; k < 27; k++) dFs[threadIdx.x][k] = dF[k];
                     for (int k = 0; k < 9; k++) F0s[threadIdx.x][k] = F0[k];
@@ -361,12 +384,11 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
         for (int u0 = 0; u0 < tn; u0++) {
         const int u = slot * lpp + u0;
         if (!oks[u]) continue;
-        const double* x = xs[u];
         const double* F = Fs[u];
         const double* dF = dFs[u];
         const int* nn = ns_[u];
-        double sph, cph;
-        sincos(-(qv[0] * x[0] + qv[1] * x[1] + qv[2] * x[2]), &sph, &cph);
+        const double* pt = phase + 2 * ((long long)(oks[u] - 1) * nq + q);
+        const double cph = cb * pt[0] - sb * pt[1], sph = cb * pt[1] + sb * pt[0];
         double SF = 0.0, SFi = 0.0, SdF[3] = {0, 0, 0}, SdFi[3] = {0, 0, 0}, SF0 = 0.0, SF0i = 0.0;
         for (int k = 0; k < 9; k++) {
             SF += Mr[k] * F[k];
@@ -447,7 +469,7 @@ struct PerRecMZProb {
 // and per (q, chunk) {s, L[c][d]}, L the bracket's matrix without Ainv.
 #define PER_RCOLS 16
 __global__ __launch_bounds__(64) void per_recip_grad_kernel(const SysDesc* sd, const double* cc, const double* qcart,
-                                                            PerRecip pr, int nchunk, double* rq, double* rl) {
+                                                            PerEwald pr, int nchunk, double* rq, double* rl) {
     const SysDesc& S = sd[0];
     const int N = S.N, n = 3 * N;
     const int q = blockIdx.x, ch = blockIdx.y;
@@ -612,18 +634,23 @@ static int per_lanes_per_pair(int nq) {
     return l;
 }
 
-void per_recip_basis_launch(hipStream_t st, const SysDesc* sd, const double* qcart, int nq, const PerRecip& pr) {
-    if (pr.ncol == 0 || nq == 0) return;
+void per_recip_basis_launch(hipStream_t st, const SysDesc* sd, const double* qcart, int nq, const int* img,
+                            int nimg, const PerEwald& pr) {
+    if (nq == 0) return;
+    if (nimg > 0)
+        hipLaunchKernelGGL(per_phase_kernel, dim3((unsigned)(((long long)nimg * nq + 255) / 256)), dim3(256), 0, st,
+                           sd, qcart, nq, img, nimg, pr.phase);
+    if (pr.ncol == 0) return;
     hipLaunchKernelGGL(per_recip_basis_kernel, dim3(pr.ncol, nq), dim3(64), 0, st, sd, qcart, pr);
 }
 
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
-                                  const double* qcart, int nq, const int* img, int nimg, const PerRecip& pr,
+                                  const double* qcart, int nq, const int* img, int nimg, const PerEwald& pr,
                                   MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N) {
     const long long pairs = (long long)N * N;
     const int lpp = per_lanes_per_pair(nq), ppw = PER_LANES / lpp;
     hipLaunchKernelGGL(mbd_assemble_periodic_kernel, dim3((unsigned)((pairs + ppw - 1) / ppw), (nq + lpp - 1) / lpp),
-                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, Q, status);
+                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, pr.phase, Q, status);
     // always launched: besides the reciprocal term, the epilogue fills the
     // right block column and the FP32 copy
     PerRecAsmProb p;
@@ -639,12 +666,12 @@ int per_recip_chunks(int ncol) { return (ncol + PER_RCOLS - 1) / PER_RCOLS; }
 
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                               const double* qcart, const double* qmult, double wq, int nq, const int* img,
-                              int nimg, const PerRecip& pr, MatBatch<double> M, double* partial, double* rq,
+                              int nimg, const PerEwald& pr, MatBatch<double> M, double* partial, double* rq,
                               double* rl, double* latpart, int N) {
     const long long pairs = (long long)N * N;
     const int lpp = per_lanes_per_pair(nq), ppw = PER_LANES / lpp;
     hipLaunchKernelGGL(mbd_grad_periodic_kernel, dim3((unsigned)((pairs + ppw - 1) / ppw), (nq + lpp - 1) / lpp),
-                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, M, partial);
+                       dim3(PER_LANES), 0, st, sd, om, cc, qcart, nq, lpp, img, nimg, pr.phase, M, partial);
     const int nchunk = per_recip_chunks(pr.ncol);
     if (nchunk > 0) {
         PerRecMZProb p;

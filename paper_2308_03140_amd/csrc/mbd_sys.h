@@ -87,11 +87,12 @@ void fill_sym_random_launch(hipStream_t st, int n, T* A, int ld, unsigned seed);
 // periodic (Ewald) assembly and adjoint; the adjoint keeps PER_PART doubles
 // per (q, i, j): {P, dR[3], dA[9], P0} of the real-space and self terms
 #define PER_PART 14
-// Reciprocal-space term as a product of the basis U(q) (one column per
-// reciprocal vector G with 0 < |G + q| < kc, embedded [Re; Im], 2n x ncol per
-// q, ld ldz, stride sZ; columns past a q point's count are zero) with itself
-// (assembly) or with M(q) C (adjoint, into W, same layout).
-struct PerRecip {
+// Work of the Ewald sums.  Reciprocal-space term as a product of the basis
+// U(q) (one column per reciprocal vector G with 0 < |G + q| < kc, embedded
+// [Re; Im], 2n x ncol per q, ld ldz, stride sZ; columns past a q point's
+// count are zero) with itself (assembly) or with M(q) C (adjoint, into W,
+// same layout); real-space phases e^{-i q.R_n} per image n and q.
+struct PerEwald {
     const int* rec;    // reciprocal lattice vectors, integer triplets
     const int* col;    // [nq][ncol]: index into rec of each column, -1 past the q point's count
     int ncol;          // columns per q point (the largest count)
@@ -99,13 +100,16 @@ struct PerRecip {
     double* W;         // M C U (adjoint only)
     int ldz;
     long long sZ;
+    double* phase;     // [nimg][nq] (cos, sin) of -q.R_n
 };
-// U(q) for every q (before the assembly; the adjoint reuses it)
-void per_recip_basis_launch(hipStream_t st, const SysDesc* sd, const double* qcart, int nq, const PerRecip& pr);
+// U(q) for every q and the real-space phase table (before the assembly; the
+// adjoint reuses both)
+void per_recip_basis_launch(hipStream_t st, const SysDesc* sd, const double* qcart, int nq, const int* img,
+                            int nimg, const PerEwald& pr);
 // Writes the whole embedded Q(q) (and its FP32 copy when Q32.p is set); with
 // cc and om null, the lattice sum T(q) itself (c = 1, no omega^2 diagonal)
 void mbd_assemble_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
-                                  const double* qcart, int nq, const int* img, int nimg, const PerRecip& pr,
+                                  const double* qcart, int nq, const int* img, int nimg, const PerEwald& pr,
                                   MatBatch<double> Q, MatBatch<float> Q32, unsigned* status, int N);
 // column chunks of the reciprocal adjoint: rq holds 4 N doubles and rl 10 per
 // (q, chunk); latpart 9 N doubles
@@ -114,7 +118,7 @@ int per_recip_chunks(int ncol);
 // partner); wq: the Brillouin-zone weight 1/4 per mesh point of all of them
 void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* om, const double* cc,
                               const double* qcart, const double* qmult, double wq, int nq, const int* img,
-                              int nimg, const PerRecip& pr, MatBatch<double> M, double* partial, double* rq,
+                              int nimg, const PerEwald& pr, MatBatch<double> M, double* partial, double* rq,
                               double* rl, double* latpart, int N);
 
 // pairwise (TS) dispersion: per-atom energy shares into eatom, gradients into
