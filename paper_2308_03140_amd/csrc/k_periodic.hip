@@ -319,8 +319,10 @@ struct PerRecAsmProb {
 // dA[9], P0}; the reciprocal-space term is contracted through U below.
 // Same layout as the assembly: one workgroup per ordered pair, one lane per
 // q-point, each real-space image term (F and its derivatives) formed once
-// into LDS and added by every lane with its own phase and M(q).
-__global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysDesc* sd, const double* om,
+// into LDS and added by every lane with its own phase and M(q).  Two
+// wavefronts per SIMD (at most 256 registers, a few spilled: 587 -> 519 us
+// for the 64-atom cell's 64 q against one wavefront at 268 registers).
+__global__ __launch_bounds__(PER_LANES, 2) void mbd_grad_periodic_kernel(const SysDesc* sd, const double* om,
                                                                       const double* cc, const double* qcart, int nq,
                                                                       int lpp, const int* img, int nimg,
                                                                       const double* phase, MatBatch<double> M,
@@ -368,13 +370,10 @@ __global__ __launch_bounds__(PER_LANES) void mbd_grad_periodic_kernel(const SysD
                 double x[3];
                 for (int c = 0; c < 3; c++) x[c] = r[c] + nn[0] * S.lat[c] + nn[1] * S.lat[3 + c] + nn[2] * S.lat[6 + c];
                 const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-                double F[9], dF[27], F0[9];
-                if (d2 != 0.0 && image_term(x, S.gamma, S.rc, R0, S.a, F, dF, F0)) {
+                // the term is written straight into this lane's slot
+                if (d2 != 0.0 && image_term(x, S.gamma, S.rc, R0, S.a, Fs[threadIdx.x], dFs[threadIdx.x], F0s[threadIdx.x])) {
                     ok = t + 1;
                     for (int c = 0; c < 3; c++) ns_[threadIdx.x][c] = nn[c];
-                    for (int k = 0; k < 9; k++) Fs[threadIdx.x][k] = F[k];
-                    for (int k = 0; k < 27; k++) dFs[threadIdx.x][k] = dF[k];
-                    for (int k = 0; k < 9; k++) F0s[threadIdx.x][k] = F0[k];
                 }
             }
             oks[threadIdx.x] = ok;
