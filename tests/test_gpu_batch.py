@@ -73,6 +73,37 @@ def test_batch_repeat_and_status(ctx):
     assert abs(outs[2]["energy"].item() - ref["energy"]) / len(mols[1]["omega"]) <= TOL_E[ctx.precision]
 
 
+def test_tuning_change_retires_captured_batches(ctx, tmp_path):
+    """A batch is captured on its first call and replayed after; loading a
+    tuning table (here with each GEMM output tile in turn) retires the
+    captured sequences, and the replays after it still match the oracle."""
+    import json
+    from paper_2308_03140_amd import torch_api as T
+    _note("batch tuning change %s" % ctx.precision)
+    mols = _mols(9, 5, 20, 60)
+    systems = [dict(m, coords=torch.tensor(m["coords"], device="cuda")) for m in mols]
+    refs = [oracle.mbd_finite(m["coords"], m["alpha0"], m["omega"], m["rvdw"], m["beta"], m["a"]) for m in mols]
+    nmax = max(3 * len(m["omega"]) for m in mols)
+    key = "fp32" if ctx.precision == "fp32_refined" else "fp64"
+    try:
+        for ts in (64, 128, 64):
+            path = tmp_path / ("tune_%d.json" % ts)
+            path.write_text(json.dumps({"fp64": {}, "fp32": {}, key: {str(nmax): [1536, 1536, ts]}}))
+            ctx.load_tuning(str(path))
+            for rep in range(2):   # capture, then replay
+                outs = T.evaluate_batch(ctx, systems)
+                for m, o, ref in zip(mols, outs, refs):
+                    assert o["status"] == 0
+                    N = len(m["omega"])
+                    assert abs(o["energy"].item() - ref["energy"]) / N <= TOL_E[ctx.precision], (ts, rep)
+                    assert np.abs(o["grad_coords"].cpu().numpy() - ref["grad_R"]).max() <= 1e-6, (ts, rep)
+    finally:
+        # back to the untuned defaults for the module's later tests
+        empty = tmp_path / "tune_empty.json"
+        empty.write_text(json.dumps({"fp64": {}, "fp32": {}}))
+        ctx.load_tuning(str(empty))
+
+
 def test_molecule_batch_512():
     """The 512-molecule workload (N ~ U{10..300}) in one batched call with
     FP32 + refinement: every molecule against the FP64 GPU path (which
