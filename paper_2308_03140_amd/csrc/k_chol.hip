@@ -147,6 +147,12 @@ template <int TS>
 struct CholSyrkProb {
     static constexpr bool A_M_CONTIG = true;
     static constexpr bool B_N_CONTIG = true;
+    // read-modify-write of the tile in 16-byte column segments (the tile is
+    // requested before the K loop); rows k0 + kw + r are even for even r, so
+    // the segments are aligned
+    static constexpr bool EPI_VEC = true;
+    typedef typename Vec16<double>::v Vec;
+    static constexpr int RPL = 2;
     MatBatch<double> A;
     int k0, kw, m, ncols;  // m = n - k0 - kw trailing rows
     int tiles, thin;
@@ -166,10 +172,22 @@ struct CholSyrkProb {
         if (c >= ncols || k >= kw) return 0.0;
         return A.at(t.batch)[(k0 + kw + c) + (long long)(k0 + k) * A.ld];
     }
-    __device__ void store(const GemmTile& t, int r, int c, double v) const {
-        if (r >= m || c > r || c >= ncols) return;
-        A.at(t.batch)[(k0 + kw + r) + (long long)(k0 + kw + c) * A.ld] -= v;
+    __device__ Vec epi_load(const GemmTile& t, int r, int c) const {
+        if (r >= m || c >= ncols || r + RPL <= c) return Vec{};
+        return *reinterpret_cast<const Vec*>(A.at(t.batch) + (k0 + kw + r) + (long long)(k0 + kw + c) * A.ld);
     }
+    __device__ void epi_store(const GemmTile& t, int r, int c, Vec acc, Vec cin) const {
+        if (r >= m || c >= ncols || r + RPL <= c) return;
+        double* a = A.at(t.batch) + (k0 + kw + r) + (long long)(k0 + kw + c) * A.ld;
+        if (r >= c && r + RPL <= m) {
+            *reinterpret_cast<Vec*>(a) = cin - acc;
+        } else {
+#pragma unroll
+            for (int e = 0; e < RPL; e++)
+                if (r + e >= c && r + e < m) a[e] = cin[e] - acc[e];
+        }
+    }
+    __device__ void store(const GemmTile&, int, int, double) const {}
 };
 
 // ---------------------------------------------------------------------------
