@@ -112,7 +112,8 @@ typedef struct {
                                      for a finite system (HOST pointer)          */
     int32_t n_q;                  /* periodic: number of q points in q_frac, or 0
                                      to use the Monkhorst-Pack mesh kgrid/kshift.
-                                     Every point is evaluated.  Points q, q'
+                                     Every point is evaluated (at most 65535,
+                                     else MBD_ERR_UNSUPPORTED).  Points q, q'
                                      with q + q' an integer vector (time-
                                      reversed partners) give the same energy and
                                      gradient contributions: with MBD_Q_PAIRS=1
@@ -183,7 +184,7 @@ mbd_status mbd_evaluate(mbd_ctx *ctx, const mbd_system *sys, unsigned want, mbd_
  * The launch sequence is captured once per batch signature (sizes, want,
  * precision) in a HIP graph and replayed on later calls with the same
  * signature.  Returns MBD_OK if every system succeeded, else the first
- * failing code. */
+ * failing code.  At most 65535 systems per call (MBD_ERR_UNSUPPORTED). */
 mbd_status mbd_evaluate_batch(mbd_ctx *ctx, int32_t n_sys, const mbd_system *sys, unsigned want,
                               mbd_result *out, int32_t *status);
 
@@ -230,7 +231,8 @@ mbd_status mbd_ts_evaluate(mbd_ctx *ctx, const mbd_system *sys, unsigned want, m
  *   [2] the smallest 1 + x_k over all u (and q): the collapse indicator
  *   [2 + n] E^(n) = -(1/2pi) int du ((-1)^n/n) sum_k x_k^n, n = 1..n_order
  *       (eq:rpa; E^(1) vanishes for finite systems)
- * 1 <= n_freq <= 512, 1 <= n_order <= 60.  The eigenvalues are computed in
+ * 1 <= n_freq <= 512, 1 <= n_order <= 60, and n_freq times the number of q
+ * points at most 65535 (MBD_ERR_UNSUPPORTED).  The eigenvalues are computed in
  * FP64 whatever the context's precision (no eigenvectors are formed).
  * Inputs, validation and Ewald parameters as for mbd_evaluate; the outputs
  * of mbd_result are not used. */
@@ -269,7 +271,8 @@ mbd_status mbd_rsscs_evaluate(mbd_ctx *ctx, const mbd_system *sys, int32_t n_fre
  * A matrix whose reduction yields a non-finite entry (NaN or Inf in A) gives
  * MBD_ERR_INVALID_ARGUMENT; its w and Z are then not meaningful (the other
  * matrices of the batch are solved as usual).  In mbd_evaluate and its
- * variants the same condition fails the system with that code. */
+ * variants the same condition fails the system with that code.  At most
+ * 65535 matrices per call (MBD_ERR_UNSUPPORTED). */
 mbd_status mbd_eigh(mbd_ctx *ctx, int32_t dtype, int32_t n, int32_t nbatch, void *A, int32_t lda,
                     int64_t stride, void *w, void *Z, int32_t ldz, int64_t zstride);
 

@@ -532,6 +532,9 @@ mbd_status setup_periodic(mbd_ctx* c, const mbd_system* s, SysDesc& d, PeriodicS
                 }
     }
     ps.nq_all = (int)qf.size() / 3;
+    // every q point is one matrix of a batch (grid z of the batched products)
+    if (ps.nq_all > MBD_MAX_BATCH)
+        return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate", "at most 65535 q points per evaluation");
     if (pair_q) {
         std::vector<double> rep;
         pair_time_reversal(qf, rep, ps.qmult);
@@ -1023,6 +1026,8 @@ mbd_status mbd_freq_evaluate(mbd_ctx* c, const mbd_system* s, int32_t n_freq, in
         if (r != MBD_OK) return r;
     }
     const int nq = periodic ? (int)ps.qcart.size() / 3 : 1;
+    if ((long long)n_freq * nq > MBD_MAX_BATCH)
+        return fail(c, MBD_ERR_UNSUPPORTED, "mbd_freq_evaluate", "at most 65535 matrices (frequencies x q points)");
     const int nmat = n_freq * nq;
     const int nmax = periodic ? 6 * N : 3 * N;
     const int ld = round_up(nmax, 64);
@@ -1219,6 +1224,8 @@ mbd_status mbd_evaluate_batch(mbd_ctx* c, int32_t n_sys, const mbd_system* sys, 
     c->err_code = 0;
     if (n_sys < 1 || !sys || !out || !status)
         return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_evaluate_batch", "bad batch arguments");
+    if (n_sys > MBD_MAX_BATCH)
+        return fail(c, MBD_ERR_UNSUPPORTED, "mbd_evaluate_batch", "at most 65535 systems per batch");
     std::vector<SysDesc> sds(n_sys);
     std::string sig = std::to_string((int)c->prec) + ":" + std::to_string(want) + ":";
     for (int i = 0; i < n_sys; i++) {
@@ -1311,6 +1318,7 @@ mbd_status mbd_eigh(mbd_ctx* c, int32_t dtype, int32_t n, int32_t nbatch, void* 
     if (n < 1 || nbatch < 1 || !A || !w || lda < n || stride < (int64_t)lda * n || (dtype != 0 && dtype != 1) ||
         (Z && (ldz < n || zstride < (int64_t)ldz * n)))
         return fail(c, MBD_ERR_INVALID_ARGUMENT, "mbd_eigh", "bad sizes or pointers");
+    if (nbatch > MBD_MAX_BATCH) return fail(c, MBD_ERR_UNSUPPORTED, "mbd_eigh", "at most 65535 matrices per call");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MBD_ERR_DEVICE, "mbd_eigh", "hipSetDevice");
     std::vector<int> nsh(nbatch, n);
     int* ns_dev = wsT<int>(c, "eigh_ns", nbatch);

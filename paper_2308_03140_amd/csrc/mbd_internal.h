@@ -7,6 +7,7 @@
 
 #define MBD_TILE 64          // SYMV / assembly tile edge (rows of one wavefront)
 #define MBD_THREADS 256      // 4 wavefronts of 64 lanes
+#define MBD_MAX_BATCH 65535  // matrices of one batched launch sequence (grid z)
 
 // Error codes mirrored from include/mbd.h
 #define MBD_OK_ 0
