@@ -529,9 +529,9 @@ def pmc_summary(fetch_dir, write_dir):
         lines = [
             "# rocprofv3 counters of %s> at N=2000 (n=6000), FP32+refine path" % kname,
             "# commands (repository root, MI355X):",
-            "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- python3 bench.py --pmc-pass",
-            "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- python3 bench.py --pmc-pass",
-            "#   python3 bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
+            "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s -o f -- python3 bench.py --pmc-pass" % fetch_dir,
+            "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o w -- python3 bench.py --pmc-pass" % write_dir,
+            "#   python3 bench.py --pmc-summary %s %s" % (fetch_dir, write_dir),
             "# averages over the %d dispatches of one evaluation; calibration on the 1 GiB copy" % len(vals),
             "fetch_counter_avg = %.3f" % fetch[0],
             "write_counter_avg = %.3f" % wr[0],
@@ -599,10 +599,10 @@ def mfma_summary(pmc_dir, trace_dir):
     lines = ["# Matrix-core utilisation of the GEMM kernels, one FP32+refine evaluation at N=2000 (n=6000)", "",
              "Commands (repository root, MI355X):", "",
              "    rocprofv3 --pmc MfmaUtil MfmaFlopsF16 MfmaFlopsF32 MfmaFlopsF64 --kernel-include-regex "
-             "'%s' --output-format csv -d gpurun_out/pmc_mfma -o m -- python3 bench.py --pmc-pass" % MFMA_REGEX,
+             "'%s' --output-format csv -d %s -o m -- python3 bench.py --pmc-pass" % (MFMA_REGEX, pmc_dir),
              "    rocprofv3 --kernel-trace --stats --kernel-include-regex '%s' --output-format csv "
-             "-d gpurun_out/trace_mfma -o t -- python3 bench.py --pmc-pass" % MFMA_REGEX,
-             "    python3 bench.py --mfma-summary gpurun_out/pmc_mfma gpurun_out/trace_mfma", "",
+             "-d %s -o t -- python3 bench.py --pmc-pass" % (MFMA_REGEX, trace_dir),
+             "    python3 bench.py --mfma-summary %s %s" % (pmc_dir, trace_dir), "",
              "Flops = MFMA MOPS x 512 (counter); time = traced kernel duration; TF/s and fraction of the dense "
              "peak of the kernel's MFMA type (FP64 78.6, FP32 157.3, FP16 2500 TFLOP/s); MfmaUtil = MFMA-busy "
              "cycles over active cycles of all SIMDs, time-weighted.", "",
