@@ -307,11 +307,14 @@ mbd_status mbd_load_tuning(mbd_ctx *ctx, const char *table_json_path);
  * factorisation and solves, contraction; and the chain rule of its gradient).
  * Kind 10 is the single launch that reduces a batch of small matrices with
  * one workgroup per matrix (FP64 batches of 256 or more matrices of
- * order <= 1024).  Enabling clears earlier records.  mbd_get_profile synchronises
- * the stream and returns, for one kind (0..10), the summed event time (ms),
+ * order <= 1024).  Kind 11 is the pair kernel of mbd_ts_evaluate.  Enabling
+ * clears earlier records.  mbd_get_profile synchronises
+ * the stream and returns, for one kind (0..11), the summed event time (ms),
  * the number of records and the summed algorithmic work: bytes of the lower
  * trailing triangle read (kinds 0, 8 and 10), flops of the rank-2k update
- * (kind 1), 0 for the phases.  enable = 2 records the
+ * (kind 1), pair terms (kind 11: N (N - 1) ordered pairs for a finite system,
+ * N^2 times the image and reciprocal terms for a cell), 0 for the phases.
+ * enable = 2 records the
  * phases only, without timing events (which would slow every launch): the
  * stream is synchronised at each phase boundary and the host clock read. */
 mbd_status mbd_set_profiling(mbd_ctx *ctx, int enable);

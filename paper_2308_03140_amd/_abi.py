@@ -172,7 +172,7 @@ def mbd_get_profile(ctx, kind):
     """Returns (status, total_ms, launches, work) for one profiling kind: 0 SYMV
     launches, 1 SYR2K launches, 2..7 the evaluation phases, 8 fused per-column
     launches, 9 the screening stage of MBD@rsSCS, 10 the one-workgroup-per-matrix
-    reduction of a batch (see include/mbd.h)."""
+    reduction of a batch, 11 the pairwise (TS) kernel (see include/mbd.h)."""
     ms = ctypes.c_double(); n = ctypes.c_int64(); w = ctypes.c_double()
     st = lib().mbd_get_profile(ctx, int(kind), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w))
     return st, ms.value, n.value, w.value

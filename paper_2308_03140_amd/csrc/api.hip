@@ -956,7 +956,7 @@ mbd_status mbd_ts_evaluate(mbd_ctx* c, const mbd_system* s, unsigned want, mbd_r
     fill_u32_launch(st, status, 1, 0u);
     mbd_prep_launch(st, sd_dev, 1, N, om, cc, status);
     mbd_ts_launch(st, sd_dev, N, om, img, (int)ps.img.size() / 3, rec, (int)ps.rec.size() / 3, periodic ? 1 : 0,
-                  eatom, status);
+                  eatom, status, &c->prof);
     HIPCHK(hipGetLastError(), "ts");
     unsigned sth = 0;
     HIPCHK(hipMemcpyAsync(&sth, status, sizeof(unsigned), hipMemcpyDeviceToHost, st), "status");

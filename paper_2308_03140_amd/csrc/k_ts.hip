@@ -15,12 +15,15 @@
 // and the cosine argument are read from the derivation of the split; the
 // printed formula omits G = 0 and has them garbled.
 //
-// Atom i's row of (j, term) pairs is shared by one workgroup (periodic: many
-// terms per pair) or by one wavefront (finite: one term per pair, four rows
-// per workgroup), so the atom's energy share, its gradient and its parameter
-// derivatives come out of one block or wave reduction each (each ordered
-// pair's energy is counted at i; dE/dR_i = sum_j C6_ij grad S_ij(R_j - R_i)
-// gathers both orders).
+// Atom i's row of (j, term) pairs is shared by one workgroup, so the atom's
+// energy share, its gradient and its parameter derivatives come out of one
+// block reduction each (each ordered pair's energy is counted at i; dE/dR_i =
+// sum_j C6_ij grad S_ij(R_j - R_i) gathers both orders).  A finite row has
+// one term per pair, so its 256 lanes take about N/256 pairs each and the
+// N workgroups keep several wavefronts on every SIMD to hide the neighbour
+// loads.  Per pair the divisions are shared: C6 and its omega derivative
+// through 1/(omega_i + omega_j), the Fermi factor through 1/R0 and
+// 1/(1 + e^{-|x|}), and 1/R.
 #include "mbd_internal.h"
 #include "mbd_kernels.h"
 #include "mbd_sys.h"
@@ -28,44 +31,60 @@
 #define TS_DAMP_TAIL 1e-18
 #define TS_SQRT_PI 1.7724538509055160273
 
+// f = 1/(1 + e^{-x}), x = a (d/R0 - 1), with 1 - f and the derivatives in d
+// and R0, from e = e^{-|x|} (no overflow on either side)
 __device__ __forceinline__ void ts_fermi(double d, double R0, double a, double& f, double& omf, double& df_dd,
                                          double& df_dR0) {
     if (R0 <= 0.0) { f = 1.0; omf = 0.0; df_dd = 0.0; df_dR0 = 0.0; return; }
-    const double x = a * (d / R0 - 1.0);
-    if (x >= 0.0) { const double e = exp(-x); f = 1.0 / (1.0 + e); omf = e / (1.0 + e); }
-    else { const double e = exp(x); f = e / (1.0 + e); omf = 1.0 / (1.0 + e); }
-    const double ff = f * omf;
-    df_dd = a / R0 * ff;
-    df_dR0 = -a * d / (R0 * R0) * ff;
+    const double iR0 = 1.0 / R0;
+    const double x = a * (d * iR0 - 1.0);
+    const double e = exp(-fabs(x));
+    const double p = 1.0 / (1.0 + e);
+    if (x >= 0.0) { f = p; omf = e * p; }
+    else { f = e * p; omf = p; }
+    const double ff = a * iR0 * (f * omf);
+    df_dd = ff;
+    df_dR0 = -d * iR0 * ff;
 }
 
+// one instance per case, so the finite kernel carries none of the lattice
+// code's registers
+template <bool periodic>
 __global__ __launch_bounds__(256) void mbd_ts_kernel(const SysDesc* sd, const double* om, const int* img, int nimg,
-                                                       const int* rec, int nrec, int periodic, double* eatom,
-                                                       unsigned* status) {
+                                                       const int* rec, int nrec, double* eatom, unsigned* status) {
     __shared__ double red[4];
     const SysDesc& S = sd[0];
     const int N = S.N;
-    // finite: a wavefront per row; periodic: the whole workgroup per row
-    const int i = periodic ? blockIdx.x : blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    const int t0 = periodic ? (int)threadIdx.x : (int)(threadIdx.x & 63);
-    const int tstep = periodic ? 256 : 64;
-    if (i >= N) return;  // uniform over the workgroup (periodic) or the wavefront (finite)
+    const int i = blockIdx.x;
+    const int t0 = (int)threadIdx.x;
+    if (i >= N) return;
     const double* R = S.coords;
     const double ai = S.alpha0[i], wi = om[S.atom_off + i], rvi = S.rvdw[i];
+    const double iwi = 1.0 / wi;
     const double g = S.gamma, g3 = g * g * g, g6 = g3 * g3;
     const int nterm = periodic ? nimg + nrec : 1;
     double Ei = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, dw = 0.0, dv = 0.0;
-    for (long long t = t0; t < (long long)N * nterm; t += tstep) {
-        const int j = (int)(t / nterm), u = (int)(t % nterm);
+    // lane steps of 256 over the flat (j, term) index, carried into j
+    // without an integer division per step (finite: one term per pair)
+    int j = periodic ? t0 / nterm : t0, u = periodic ? t0 % nterm : 0;
+    auto advance = [&]() {
+        if (!periodic) { j += 256; return; }
+        u += 256;
+        while (u >= nterm) { u -= nterm; j++; }
+    };
+    for (; j < N; advance()) {
         if (!periodic && j == i) continue;
         const double r[3] = {R[3 * j] - R[3 * i], R[3 * j + 1] - R[3 * i + 1], R[3 * j + 2] - R[3 * i + 2]};
         const double aj = S.alpha0[j], wj = om[S.atom_off + j];
-        const double c6 = 1.5 * ai * aj / (1.0 / wi + 1.0 / wj);
+        // C6 = (3/2) ai aj wi wj/(wi + wj); dC6/dwi = C6 wj/(wi (wi + wj))
+        const double h = 1.0 / (wi + wj);
+        const double c6 = 1.5 * ai * aj * wi * wj * h;
+        const double c6w = c6 * wj * h * iwi;
         const double R0 = S.beta * (rvi + S.rvdw[j]);
         if (periodic && j == i && u == 0) {
             // self term -gamma^6/6 of the reciprocal sum, once per atom
             Ei += -0.5 * c6 * (-g6 / 6.0);
-            dw += -c6 * (-g6 / 6.0) * wj / (wi * (wi + wj));
+            dw += -c6w * (-g6 / 6.0);
         }
         double s = 0.0, ds[3] = {0.0, 0.0, 0.0}, ds0 = 0.0;
         if (!periodic || u < nimg) {
@@ -124,24 +143,15 @@ __global__ __launch_bounds__(256) void mbd_ts_kernel(const SysDesc* sd, const do
         gx += c6 * ds[0];
         gy += c6 * ds[1];
         gz += c6 * ds[2];
-        dw += -c6 * s * wj / (wi * (wi + wj));
+        dw += -c6w * s;
         dv += -S.beta * c6 * ds0;
     }
-    if (periodic) {
-        Ei = block_sum256(Ei, red);
-        gx = block_sum256(gx, red);
-        gy = block_sum256(gy, red);
-        gz = block_sum256(gz, red);
-        dw = block_sum256(dw, red);
-        dv = block_sum256(dv, red);
-    } else {
-        Ei = wave_sum(Ei);
-        gx = wave_sum(gx);
-        gy = wave_sum(gy);
-        gz = wave_sum(gz);
-        dw = wave_sum(dw);
-        dv = wave_sum(dv);
-    }
+    Ei = block_sum256(Ei, red);
+    gx = block_sum256(gx, red);
+    gy = block_sum256(gy, red);
+    gz = block_sum256(gz, red);
+    dw = block_sum256(dw, red);
+    dv = block_sum256(dv, red);
     if (t0 == 0) {
         eatom[i] = Ei;
         if (S.grad_coords) {
@@ -178,8 +188,17 @@ __global__ __launch_bounds__(256) void mbd_ts_sum_kernel(const SysDesc* sd, cons
 }
 
 void mbd_ts_launch(hipStream_t st, const SysDesc* sd, int N, const double* om, const int* img, int nimg,
-                   const int* rec, int nrec, int periodic, double* eatom, unsigned* status) {
-    hipLaunchKernelGGL(mbd_ts_kernel, dim3(periodic ? N : (N + 3) / 4), dim3(256), 0, st, sd, om, img, nimg, rec,
-                       nrec, periodic, eatom, status);
+                   const int* rec, int nrec, int periodic, double* eatom, unsigned* status, LaunchProfiler* prof) {
+    auto kern = periodic ? mbd_ts_kernel<true> : mbd_ts_kernel<false>;
+    if (prof && prof->enabled && prof->launches) {
+        // work: the pair terms of the launch
+        const double terms = periodic ? (double)N * N * (nimg + nrec) : (double)N * (N - 1);
+        hipEvent_t e0, e1;
+        prof->pair(&e0, &e1, 11, terms);
+        hipExtLaunchKernelGGL(kern, dim3(N), dim3(256), 0, st, e0, e1, 0, sd, om, img, nimg, rec, nrec, eatom,
+                              status);
+    } else {
+        hipLaunchKernelGGL(kern, dim3(N), dim3(256), 0, st, sd, om, img, nimg, rec, nrec, eatom, status);
+    }
     hipLaunchKernelGGL(mbd_ts_sum_kernel, dim3(1), dim3(256), 0, st, sd, eatom, status);
 }

@@ -10,9 +10,11 @@
 // (measurement tools only).  kind 0: per-column SYMV of the reduction
 // (BLAS-2), 1: trailing SYR2K (BLAS-3); phases: 2 input preparation and
 // assembly, 3 Householder reduction, 4 divide and conquer, 5 back-transform,
-// 6 refinement, 7 energy, Q^{-1/2} and gradients.  `work` is the algorithmic
-// bytes (kind 0) or flops (kind 1) of the launch, 0 for phases.
-#define PROF_KINDS 11
+// 6 refinement, 7 energy, Q^{-1/2} and gradients; 8 fused per-column
+// launch, 9 screening stage, 10 one-workgroup-per-matrix reduction, 11 the
+// pairwise (TS) kernel.  `work` is the algorithmic bytes (kinds 0, 8, 10),
+// flops (kind 1) or pair terms (kind 11) of the launch, 0 for phases.
+#define PROF_KINDS 12
 struct LaunchProfiler {
     bool enabled = false;
     bool launches = true;  // per-launch records (kinds 0, 1); phases are always recorded when enabled

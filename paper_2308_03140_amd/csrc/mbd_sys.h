@@ -122,9 +122,12 @@ void mbd_grad_periodic_launch(hipStream_t st, const SysDesc* sd, const double* o
                               double* rl, double* latpart, int N);
 
 // pairwise (TS) dispersion: per-atom energy shares into eatom, gradients into
-// the descriptor's outputs, then the energy (and errors[0..3] = 0)
+// the descriptor's outputs, then the energy (and errors[0..3] = 0); with
+// launch profiling on, the pair kernel is timed as kind 11
+struct LaunchProfiler;
 void mbd_ts_launch(hipStream_t st, const SysDesc* sd, int N, const double* om, const int* img, int nimg,
-                   const int* rec, int nrec, int periodic, double* eatom, unsigned* status);
+                   const int* rec, int nrec, int periodic, double* eatom, unsigned* status,
+                   LaunchProfiler* prof = nullptr);
 
 // frequency route: per-frequency coefficients (descriptor 0 = the system,
 // 1..nfreq = one per frequency), then the per-matrix eigenvalue sums and the

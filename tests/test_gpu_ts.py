@@ -112,3 +112,31 @@ def test_ts_invalid_and_unsupported(ctx):
         T.ts_evaluate(ctx, torch.tensor(coords, device="cuda"), c["alpha0"], c["omega"], c["rvdw"], SR,
                       lattice=c["lattice"])
     assert e.value.code == A.MBD_ERR_INVALID_ARGUMENT
+
+
+def test_ts_kernel_profile(ctx):
+    """Launch timing of the pair kernel (profiling kind 11): one record per
+    call, its work the pair terms of the launch; results unchanged by the
+    timed launch; kinds past the last are refused."""
+    from paper_2308_03140_amd import _abi as A
+    _note("ts kernel profile")
+    N = 150
+    c = gen.finite_cluster(450, N, 12.0 * (N / 32.0) ** (1 / 3))
+    plain = _run(ctx, c)
+    A.mbd_set_profiling(ctx.handle, 1)
+    try:
+        timed = _run(ctx, c)
+        st, ms, n, work = A.mbd_get_profile(ctx.handle, 11)
+        assert st == A.MBD_OK and n == 1 and ms > 0.0
+        assert work == N * (N - 1)
+        p = gen.small_crystal(73, 3)
+        _run(ctx, p, lattice=p["lattice"])
+        st, ms2, n2, work2 = A.mbd_get_profile(ctx.handle, 11)
+        assert st == A.MBD_OK and n2 == 2 and work2 > work + 9
+        assert (work2 - work) % 9 == 0   # N^2 times the image and reciprocal terms
+        st, _, _, _ = A.mbd_get_profile(ctx.handle, 12)
+        assert st == A.MBD_ERR_INVALID_ARGUMENT
+    finally:
+        A.mbd_set_profiling(ctx.handle, 0)
+    assert timed["energy"].item() == plain["energy"].item()
+    assert torch.equal(timed["grad_coords"], plain["grad_coords"])
