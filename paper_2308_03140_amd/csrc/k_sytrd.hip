@@ -527,9 +527,10 @@ __device__ void finish_item(const SytrdWs<T>& w, int b, int n, int i, int j, int
 
 // ---------------------------------------------------------------------------
 // tail: unblocked reduction of the trailing block A(k0:n, k0:n), m = n - k0
-// <= M0, one workgroup of 1024 threads per matrix: thread (q, r) = tid / 256,
-// tid % 256 works on row r and on the columns c = q (mod 4), so that each
-// SIMD holds four waves.  The lower triangle is held packed by columns in
+// <= M0, one workgroup of 1024 threads per matrix: thread tid of quarter q =
+// tid / 256 works on one row r and on the columns c = q (mod 4), so that
+// each SIMD holds four waves (the quarter's four wavefronts take the four
+// 64-row blocks, in an order rotated by q).  The lower triangle is held packed by columns in
 // LDS (column c holds rows c .. m-1).  Per column i, s = i + 1, with the
 // panel path's reflector convention (beta = -sign(alpha) ||x||, tau =
 // (beta - alpha) / beta, v(s) = 1, v(r) = x(r) / (alpha - beta)) for x =
@@ -565,8 +566,13 @@ __global__ __launch_bounds__(SYTRD_TAIL_THREADS) void sytrd_tail_kernel(SytrdWs<
     if (m <= 0) return;
     T* A = w.A.at(b) + k0 + (long long)k0 * w.A.ld;
     const long long ld = w.A.ld;
-    const int r = threadIdx.x & 255;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+    // row of this thread: the four wavefronts of quarter q take the 64-row
+    // blocks rotated by q, so that each SIMD (wavefront k of a workgroup
+    // runs on SIMD k mod 4) holds one wavefront of every row block and the
+    // triangular update (row r: about r/4 columns per quarter) is spread
+    // evenly over the SIMDs
+    const int r = ((((int)threadIdx.x >> 6) + q) & 3) * 64 + (int)(threadIdx.x & 63);
     const int wv = threadIdx.x >> 6;
     const bool rv = r < m;
     // start of packed column c
