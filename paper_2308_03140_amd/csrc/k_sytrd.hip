@@ -1534,6 +1534,8 @@ template <> struct SytrdWgMinBatch<double> { static constexpr int value = 256; }
 template <typename T> struct SytrdFused;
 template <> struct SytrdFused<float> { static constexpr int max_order = 4000; };
 template <> struct SytrdFused<double> { static constexpr int max_order = 0; };
+// occupancy target of the fused kernel (waves per SIMD): in FP32 three is the
+// most without spills (168 registers; a target of four spills 45)
 template <typename T> struct ColWaves;
 template <> struct ColWaves<float> { static constexpr int value = 3; };
 template <> struct ColWaves<double> { static constexpr int value = 1; };
